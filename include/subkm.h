@@ -1,0 +1,230 @@
+/*
+ * subkm.h -- C ABI of libsubkm, subclustered k-means on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The method is the two-level clustering of "A parallel sampling based
+ * clustering" (arXiv 1412.1947):
+ *   1. feature scaling of every attribute (Sec. II, Algorithm 1 step 1),
+ *      here min-max scaling to [0,1];
+ *   2. equal sized subclustering (Sec. II, Algorithm 1 steps 2, 3 and 5):
+ *      repeatedly gather the N remaining points closest to the landmark L,
+ *      the point made of the attribute-wise minima of the remaining points;
+ *   3. Lloyd's k-means inside every subcluster (Algorithm 1 step 4; Sec. I
+ *      names Lloyd's algorithm), giving the local centers;
+ *   4. Lloyd's k-means on the local centers to obtain the required number of
+ *      centers (Sec. I, Sec. V).
+ *
+ * Conventions shared by every call:
+ *  - Points are row-major n x d float32 arrays ("row major flattening",
+ *    Sec. V): the d attributes of a point are contiguous.
+ *  - Every array argument is a DEVICE pointer (memory of the context's GPU,
+ *    e.g. a torch CUDA tensor) unless the comment says "host".  The caller
+ *    owns every input and output buffer; the library owns only its context
+ *    and the scratch memory the context keeps between calls.
+ *  - Calls are asynchronous on the context's stream unless stated otherwise:
+ *    outputs are valid once that stream has been synchronised.  Inputs must
+ *    stay valid until then.
+ *  - Every call returns a status and never aborts or throws.  Arguments are
+ *    validated before any device work; on an error status the outputs are
+ *    unspecified and subkm_last_error() describes the problem.
+ *  - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef SUBKM_H
+#define SUBKM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SUBKM_OK = 0,
+    SUBKM_EINVAL = 1,      /* invalid argument (or non-finite input data)      */
+    SUBKM_ENOMEM = 2,      /* device scratch memory could not be allocated     */
+    SUBKM_EDEVICE = 3,     /* a HIP runtime call failed                         */
+    SUBKM_EBUSY = 4,       /* serving engine full or over its memory budget    */
+    SUBKM_EUNSUPPORTED = 5 /* combination of arguments not supported            */
+} subkm_status;
+
+typedef struct subkm_ctx subkm_ctx;
+
+/* Create a context on HIP device `device`, issuing work on `stream` (a
+ * hipStream_t; NULL selects the device's null stream).  *out receives the
+ * context.  The stream must outlive the context or be replaced first.      */
+subkm_status subkm_create(int device, void *stream, subkm_ctx **out);
+
+/* Destroy a context and free its scratch memory (synchronises its stream). */
+void subkm_destroy(subkm_ctx *ctx);
+
+/* Text of the last error on this context ("" if none).  Valid until the
+ * next call on the same context.  NULL ctx gives the last create error.     */
+const char *subkm_last_error(const subkm_ctx *ctx);
+
+/* Replace the stream of a context (hipStream_t, NULL = null stream).        */
+subkm_status subkm_set_stream(subkm_ctx *ctx, void *stream);
+
+/* Block the host until all work issued on the context's stream is done.    */
+subkm_status subkm_synchronize(subkm_ctx *ctx);
+
+/* ---------------------------------------------------------------------- */
+/* Min-max feature scaling (Sec. II, Algorithm 1 step 1; Sec. III,
+ * Algorithm 2 step 1).
+ *
+ * For every attribute j: mins[j] = min_i X[i][j], maxs[j] = max_i X[i][j]
+ * (exact float32), and S[i][j] = (float)(((double)X[i][j] - mins[j]) /
+ * ((double)maxs[j] - mins[j])) with binary64 subtraction and division,
+ * rounded once to float32; an attribute with maxs[j] == mins[j] maps to 0.
+ *
+ * X: n x d input.  S: n x d output, may alias X.  mins, maxs: d outputs.
+ * Requires n >= 1, 1 <= d.  A NaN or infinite input value gives
+ * SUBKM_EINVAL; this check needs the results of the min/max pass, so the
+ * call synchronises the stream once.                                      */
+subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
+                         float *S, float *mins, float *maxs);
+
+/* ---------------------------------------------------------------------- */
+/* Equal sized subclustering (Sec. II, Algorithm 1 steps 2, 3 and 5, applied
+ * round after round to the points left over).
+ *
+ * Round t (t = 0 .. T-1, T = ceil(n / N)):
+ *   L_t[j] = min over the remaining points of S[i][j]   (landmark_mode 0),
+ *            or the first landmark L_0 in every round     (landmark_mode 1);
+ *   key_i  = sum_j ((double)S[i][j] - (double)L_t[j])^2, binary64, j
+ *            ascending, no fused multiply-add;
+ *   G_t    = the min(N, remaining) remaining points with the smallest
+ *            (key_i, i) in lexicographic order (ties to the lower index);
+ *   G_t is written in ascending index to perm[t*N ..] and its rows to P.
+ *
+ * S: n x d input (normally the output of subkm_scale).
+ * P: n x d output, P[r] = S[perm[r]] (subcluster t occupies rows
+ *    offsets[t] .. offsets[t+1]-1).
+ * perm: n int32 output.  offsets: T+1 int64 output; offsets[t] = t*N for
+ * t < T and offsets[T] = n.  landmarks: nullable, T x d float32 output of
+ * the landmarks L_t.
+ * Requires 1 <= n < 2^31, 1 <= d <= 4096, N >= 1.  The selection is exact:
+ * perm and P equal those of a sort by (key, index) bit for bit.          */
+subkm_status subkm_subcluster(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
+                              int64_t N, int32_t landmark_mode, float *P,
+                              int32_t *perm, int64_t *offsets, float *landmarks);
+
+/* ---------------------------------------------------------------------- */
+/* Many independent Lloyd runs in one call (Sec. II Algorithm 1 step 4 for
+ * every subcluster; Sec. V runs every subcluster on its own block of
+ * threads).
+ *
+ * Run r clusters runs[r].n points of runs[r].d attributes, stored row-major
+ * at P + runs[r].x_off, into runs[r].k centers stored at C + runs[r].c_off;
+ * C holds the starting centers on entry and the result on return.  Every
+ * run repeats { assign every point to its nearest center (ties to the lower
+ * center index); move every center to the mean of its points (a center with
+ * no point stays) } until max_iter moves were made or the largest Euclidean
+ * center move of the run is strictly below tol; a last assignment against
+ * the returned centers gives labels[runs[r].lab_off + i] (center index
+ * within the run) and sse[r] = sum_i min_c ||x_i - C_c||^2 (binary64).
+ * iters[r] receives the number of moves made.
+ *
+ * runs: HOST array of R descriptors.  P, C, labels: device buffers holding
+ * every run at the given offsets (runs must not overlap in C or labels).
+ * iters (R int32) and sse (R double): device outputs.
+ *
+ * precision: SUBKM_PREC_FP32 computes distances in float32;
+ *            SUBKM_PREC_BF16 computes them with bfloat16 matrix cores and
+ *            float32 accumulation.  In both, every point whose two nearest
+ *            centers are closer than the error bound of that arithmetic is
+ *            re-assigned with binary64 distances, so the labels are those of
+ *            exact arithmetic on the float32 inputs.  Center sums are exact
+ *            (64-bit fixed point), so results do not depend on the order of
+ *            the work.
+ * form:      SUBKM_FORM_BATCHED runs every run together (one launch per
+ *            phase for all runs); SUBKM_FORM_PLAIN runs one run at a time
+ *            with one launch per phase and run (the reference form).  Both
+ *            give identical results.
+ * Requires R >= 1, n >= 1, 1 <= d <= 4096, 1 <= k <= n per run,
+ * max_iter >= 0, tol >= 0.                                               */
+typedef struct {
+    int64_t x_off;   /* offset of the run's first point in P, in floats      */
+    int64_t n;       /* number of points                                     */
+    int64_t c_off;   /* offset of the run's first center in C, in floats     */
+    int64_t lab_off; /* offset of the run's first label in labels           */
+    int32_t d;       /* attributes                                           */
+    int32_t k;       /* centers                                              */
+} subkm_run;
+
+#define SUBKM_PREC_FP32 0
+#define SUBKM_PREC_BF16 1
+#define SUBKM_FORM_BATCHED 0
+#define SUBKM_FORM_PLAIN 1
+
+subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run *runs,
+                                 int32_t R, float *C, int32_t *labels, int32_t max_iter,
+                                 double tol, int32_t precision, int32_t form,
+                                 int32_t *iters, double *sse);
+
+/* ---------------------------------------------------------------------- */
+/* The whole two-level method (Sec. II Algorithm 1 and Sec. V): scale X,
+ * subcluster it with subclusters of N points, run Lloyd in every subcluster
+ * with k_r = ceil(n_r * k_local / N) centers started from the subcluster's
+ * first k_r points (the compression value of Sec. VI is N / k_local), then
+ * run Lloyd on the M = sum_r k_r local centers with k_final centers started
+ * from local center q * floor(M / k_final) for q = 0 .. k_final-1, and label
+ * every point.
+ *
+ * X: n x d input (not modified).  centers: k_final x d output, in scaled
+ * space (unscale with the mins/maxs of subkm_scale).  labels: n int32
+ * output, the final center of every point in input order.  sse: 1 double
+ * output, sum over all points of the squared distance to its final center,
+ * in scaled space.  opts: nullable.  stats: nullable HOST output; when given
+ * the call synchronises and reports phase times.
+ * Requires k_local <= N and k_final <= M, besides the requirements of the
+ * calls above.                                                            */
+typedef struct {
+    int32_t landmark_mode; /* 0: landmark recomputed each round (default)   */
+    int32_t precision;     /* SUBKM_PREC_*                                   */
+    int32_t form;          /* SUBKM_FORM_* of the local runs                 */
+    int32_t reserved;
+    /* optional device outputs of intermediates (NULL = not wanted) */
+    float *S;              /* n x d scaled points                            */
+    int32_t *perm;         /* n, subcluster order                            */
+    float *local_centers;  /* M x d                                          */
+    int32_t *local_iters;  /* T                                              */
+    double *local_sse;     /* T                                              */
+} subkm_opts;
+
+typedef struct {
+    int64_t T;               /* subclusters                                   */
+    int64_t M;               /* local centers                                 */
+    int32_t final_iters;     /* moves of the final run                        */
+    int32_t reserved;
+    int64_t local_point_iters; /* sum over local runs of n_r * iters_r        */
+    int64_t final_point_iters; /* M * final_iters                             */
+    double us_scale;         /* phase times, microseconds (device events)     */
+    double us_subcluster;
+    double us_local;
+    double us_final;
+    double us_label;
+    double us_total;
+} subkm_stats;
+
+subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t N,
+                           int32_t k_local, int32_t k_final, int32_t max_iter, double tol,
+                           const subkm_opts *opts, float *centers, int32_t *labels,
+                           double *sse, subkm_stats *stats);
+
+/* Sizes of the two-level problem: T = ceil(n / N) subclusters and
+ * M = sum_r ceil(n_r * k_local / N) local centers (host only, no device
+ * work).  Returns SUBKM_EINVAL on invalid sizes.                          */
+subkm_status subkm_cluster_sizes(int64_t n, int64_t N, int32_t k_local,
+                                 int64_t *T, int64_t *M);
+
+/* Device memory a subkm_cluster call of these sizes needs besides its
+ * inputs and outputs, in bytes (host only).  Used for admission control.  */
+size_t subkm_cluster_footprint(int64_t n, int32_t d, int64_t N, int32_t k_local,
+                               int32_t k_final);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SUBKM_H */

@@ -1,0 +1,272 @@
+"""Python binding of libsubkm (include/subkm.h): subclustered k-means on
+AMD Instinct MI355X.
+
+Argument marshalling only.  Every step of the method runs in the HIP
+library; PyTorch supplies device memory and the stream.  There is no CPU
+fallback: without the built library (``__graft_entry__.build()``) or without
+a GPU every call raises.
+
+The method (arXiv 1412.1947): min-max feature scaling, equal sized
+subclustering (Sec. II, Algorithm 1), Lloyd's k-means inside every
+subcluster and on the local centers (Sec. I, Sec. V).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsubkm.so")
+
+PREC_FP32 = 0
+PREC_BF16 = 1
+FORM_BATCHED = 0
+FORM_PLAIN = 1
+
+
+class SubkmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libsubkm status {status}: {msg}")
+        self.status = status
+
+
+class Run(ctypes.Structure):
+    _fields_ = [("x_off", ctypes.c_int64), ("n", ctypes.c_int64), ("c_off", ctypes.c_int64),
+                ("lab_off", ctypes.c_int64), ("d", ctypes.c_int32), ("k", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("landmark_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("S", ctypes.c_void_p), ("perm", ctypes.c_void_p),
+                ("local_centers", ctypes.c_void_p), ("local_iters", ctypes.c_void_p),
+                ("local_sse", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int64), ("M", ctypes.c_int64), ("final_iters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("local_point_iters", ctypes.c_int64),
+                ("final_point_iters", ctypes.c_int64), ("us_scale", ctypes.c_double),
+                ("us_subcluster", ctypes.c_double), ("us_local", ctypes.c_double),
+                ("us_final", ctypes.c_double), ("us_label", ctypes.c_double),
+                ("us_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+EXPORTS = ("subkm_create", "subkm_destroy", "subkm_last_error", "subkm_set_stream",
+           "subkm_synchronize", "subkm_scale", "subkm_subcluster", "subkm_lloyd_batched",
+           "subkm_cluster", "subkm_cluster_sizes", "subkm_cluster_footprint")
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def lib():
+    """The loaded libsubkm (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+            L = ctypes.CDLL(LIB_PATH)
+            P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+            st = ctypes.c_int
+            L.subkm_create.argtypes = [ctypes.c_int, P, ctypes.POINTER(P)]
+            L.subkm_create.restype = st
+            L.subkm_destroy.argtypes = [P]
+            L.subkm_destroy.restype = None
+            L.subkm_last_error.argtypes = [P]
+            L.subkm_last_error.restype = ctypes.c_char_p
+            L.subkm_set_stream.argtypes = [P, P]
+            L.subkm_set_stream.restype = st
+            L.subkm_synchronize.argtypes = [P]
+            L.subkm_synchronize.restype = st
+            L.subkm_scale.argtypes = [P, P, i64, i32, P, P, P]
+            L.subkm_scale.restype = st
+            L.subkm_subcluster.argtypes = [P, P, i64, i32, i64, i32, P, P, P, P]
+            L.subkm_subcluster.restype = st
+            L.subkm_lloyd_batched.argtypes = [P, P, ctypes.POINTER(Run), i32, P, P, i32, f64, i32,
+                                              i32, P, P]
+            L.subkm_lloyd_batched.restype = st
+            L.subkm_cluster.argtypes = [P, P, i64, i32, i64, i32, i32, i32, f64,
+                                        ctypes.POINTER(Opts), P, P, P, ctypes.POINTER(Stats)]
+            L.subkm_cluster.restype = st
+            L.subkm_cluster_sizes.argtypes = [i64, i64, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+            L.subkm_cluster_sizes.restype = st
+            L.subkm_cluster_footprint.argtypes = [i64, i32, i64, i32, i32]
+            L.subkm_cluster_footprint.restype = ctypes.c_size_t
+            _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def cluster_sizes(n: int, N: int, k_local: int):
+    T, M = ctypes.c_int64(), ctypes.c_int64()
+    st = lib().subkm_cluster_sizes(n, N, k_local, ctypes.byref(T), ctypes.byref(M))
+    if st != 0:
+        raise SubkmError(st, "invalid sizes")
+    return T.value, M.value
+
+
+def cluster_footprint(n: int, d: int, N: int, k_local: int, k_final: int) -> int:
+    return int(lib().subkm_cluster_footprint(n, d, N, k_local, k_final))
+
+
+class Context:
+    """A libsubkm context on one GPU; calls run on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libsubkm needs a ROCm GPU; none is visible")
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        st = lib().subkm_create(self.device, None, ctypes.byref(h))
+        if st != 0:
+            raise SubkmError(st, lib().subkm_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().subkm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            raise SubkmError(st, lib().subkm_last_error(self._h).decode())
+
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._check(lib().subkm_set_stream(self._h, ctypes.c_void_p(s)))
+
+    def _dev(self, t, dtype, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.device.index != self.device:
+            raise ValueError(f"{name} must be a tensor on cuda:{self.device}")
+        if t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} tensor")
+        return t
+
+    def _empty(self, shape, dtype):
+        return torch.empty(shape, dtype=dtype, device=f"cuda:{self.device}")
+
+    def synchronize(self):
+        self._check(lib().subkm_synchronize(self._h))
+
+    # -- the C ABI -------------------------------------------------------------
+    def scale(self, X, out=None):
+        """Min-max scaling. Returns (S, mins, maxs)."""
+        X = self._dev(X, torch.float32, "X")
+        n, d = X.shape
+        S = self._empty((n, d), torch.float32) if out is None else self._dev(out, torch.float32, "out")
+        mins = self._empty((d,), torch.float32)
+        maxs = self._empty((d,), torch.float32)
+        self._bind_stream()
+        self._check(lib().subkm_scale(self._h, _ptr(X), n, d, _ptr(S), _ptr(mins), _ptr(maxs)))
+        return S, mins, maxs
+
+    def subcluster(self, S, N: int, landmark_mode: int = 0, landmarks: bool = False):
+        """Algorithm 1. Returns (P, perm, offsets[, landmarks])."""
+        S = self._dev(S, torch.float32, "S")
+        n, d = S.shape
+        T = -(-n // int(N)) if N >= 1 else 0
+        P = self._empty((n, d), torch.float32)
+        perm = self._empty((n,), torch.int32)
+        offs = self._empty((T + 1,), torch.int64)
+        lm = self._empty((T, d), torch.float32) if landmarks else None
+        self._bind_stream()
+        self._check(lib().subkm_subcluster(self._h, _ptr(S), n, d, int(N), int(landmark_mode),
+                                           _ptr(P), _ptr(perm), _ptr(offs), _ptr(lm)))
+        return (P, perm, offs, lm) if landmarks else (P, perm, offs)
+
+    def lloyd_batched(self, P, runs, C, labels, max_iter: int, tol: float,
+                      precision: int = PREC_FP32, form: int = FORM_BATCHED):
+        """Lloyd runs described by `runs` (tuples x_off, n, c_off, lab_off, d, k).
+        C holds the starting centers and receives the result.  Returns (iters, sse)."""
+        P = self._dev(P, torch.float32, "P")
+        C = self._dev(C, torch.float32, "C")
+        labels = self._dev(labels, torch.int32, "labels")
+        R = len(runs)
+        arr = (Run * max(R, 1))(*[Run(*map(int, r)) for r in runs])
+        iters = self._empty((max(R, 1),), torch.int32)
+        sse = self._empty((max(R, 1),), torch.float64)
+        self._bind_stream()
+        self._check(lib().subkm_lloyd_batched(self._h, _ptr(P), arr, R, _ptr(C), _ptr(labels),
+                                              int(max_iter), float(tol), int(precision), int(form),
+                                              _ptr(iters), _ptr(sse)))
+        return iters[:R], sse[:R]
+
+    def cluster(self, X, N: int, k_local: int, k_final: int, max_iter: int, tol: float,
+                landmark_mode: int = 0, precision: int = PREC_FP32, form: int = FORM_BATCHED,
+                intermediates: bool = False, stats: bool = False):
+        """The whole two-level method.  Returns a dict with centers (scaled
+        space), labels, sse and, on request, intermediates and phase stats."""
+        X = self._dev(X, torch.float32, "X")
+        n, d = X.shape
+        out = {}
+        o = Opts(landmark_mode=int(landmark_mode), precision=int(precision), form=int(form))
+        if intermediates:
+            T, M = cluster_sizes(n, int(N), int(k_local))
+            out["S"] = self._empty((n, d), torch.float32)
+            out["perm"] = self._empty((n,), torch.int32)
+            out["local_centers"] = self._empty((M, d), torch.float32)
+            out["local_iters"] = self._empty((T,), torch.int32)
+            out["local_sse"] = self._empty((T,), torch.float64)
+            o.S, o.perm = out["S"].data_ptr(), out["perm"].data_ptr()
+            o.local_centers = out["local_centers"].data_ptr()
+            o.local_iters = out["local_iters"].data_ptr()
+            o.local_sse = out["local_sse"].data_ptr()
+        centers = self._empty((k_final, d), torch.float32)
+        labels = self._empty((n,), torch.int32)
+        sse = self._empty((1,), torch.float64)
+        st = Stats() if stats else None
+        self._bind_stream()
+        self._check(lib().subkm_cluster(self._h, _ptr(X), n, d, int(N), int(k_local), int(k_final),
+                                        int(max_iter), float(tol), ctypes.byref(o), _ptr(centers),
+                                        _ptr(labels), _ptr(sse),
+                                        ctypes.byref(st) if st is not None else None))
+        out.update(centers=centers, labels=labels, sse=sse)
+        if st is not None:
+            out["stats"] = st.as_dict()
+        return out
+
+
+_contexts: dict = {}
+
+
+def context(device: int = 0) -> Context:
+    """The shared context of a device (created on first use)."""
+    c = _contexts.get(device)
+    if c is None:
+        c = _contexts[device] = Context(device)
+    return c
+
+
+def scale(X):
+    return context(X.device.index or 0).scale(X)
+
+
+def subcluster(S, N, landmark_mode=0, landmarks=False):
+    return context(S.device.index or 0).subcluster(S, N, landmark_mode, landmarks)
+
+
+def lloyd_batched(P, runs, C, labels, max_iter, tol, precision=PREC_FP32, form=FORM_BATCHED):
+    return context(P.device.index or 0).lloyd_batched(P, runs, C, labels, max_iter, tol,
+                                                      precision, form)
+
+
+def cluster(X, N, k_local, k_final, max_iter, tol, **kw):
+    return context(X.device.index or 0).cluster(X, N, k_local, k_final, max_iter, tol, **kw)

@@ -1,0 +1,330 @@
+// C ABI of libsubkm: argument validation, context and scratch memory, and
+// the two-level method built from the stage implementations.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+
+static std::mutex g_create_mu;
+static std::string g_create_err;
+
+subkm_status set_err(subkm_ctx *ctx, subkm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else {
+        std::lock_guard<std::mutex> g(g_create_mu);
+        g_create_err = buf;
+    }
+    return st;
+}
+
+void *ctx_scratch(subkm_ctx *ctx, int slot, size_t bytes) {
+    ScratchBuf &b = ctx->scratch[slot];
+    if (bytes == 0) bytes = 1;
+    if (b.bytes >= bytes) return b.ptr;
+    if (b.ptr) {
+        // earlier work on the stream may still use the old buffer
+        hipStreamSynchronize(ctx->stream);
+        hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8 + 4096;
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        hipGetLastError();
+        b.ptr = nullptr;
+        set_err(ctx, SUBKM_ENOMEM, "device allocation of %zu bytes failed", want);
+        return nullptr;
+    }
+    b.bytes = want;
+    return b.ptr;
+}
+
+void *ctx_pinned(subkm_ctx *ctx, size_t bytes) {
+    if (ctx->pinned_bytes >= bytes) return ctx->pinned;
+    if (ctx->pinned) {
+        hipStreamSynchronize(ctx->stream);
+        hipHostFree(ctx->pinned);
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault) != hipSuccess) {
+        hipGetLastError();
+        ctx->pinned = nullptr;
+        set_err(ctx, SUBKM_ENOMEM, "pinned host allocation of %zu bytes failed", want);
+        return nullptr;
+    }
+    ctx->pinned_bytes = want;
+    return ctx->pinned;
+}
+
+// RAII: make the context's device current for the duration of a call
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+#define CHECK_CTX(ctx)                                                                    \
+    do {                                                                                  \
+        if (!(ctx)) return SUBKM_EINVAL;                                                  \
+        (ctx)->err.clear();                                                               \
+    } while (0)
+
+#define REQUIRE(ctx, cond, ...)                                                           \
+    do {                                                                                  \
+        if (!(cond)) return set_err((ctx), SUBKM_EINVAL, __VA_ARGS__);                    \
+    } while (0)
+
+extern "C" {
+
+subkm_status subkm_create(int device, void *stream, subkm_ctx **out) {
+    if (!out) return set_err(nullptr, SUBKM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        hipGetLastError();
+        return set_err(nullptr, SUBKM_EDEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= ndev)
+        return set_err(nullptr, SUBKM_EINVAL, "device %d out of range [0,%d)", device, ndev);
+    subkm_ctx *c = new (std::nothrow) subkm_ctx();
+    if (!c) return set_err(nullptr, SUBKM_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+    for (auto &e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            hipGetLastError();
+            delete c;
+            return set_err(nullptr, SUBKM_EDEVICE, "hipEventCreate failed");
+        }
+    }
+    *out = c;
+    return SUBKM_OK;
+}
+
+void subkm_destroy(subkm_ctx *ctx) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    for (auto &b : ctx->scratch)
+        if (b.ptr) hipFree(b.ptr);
+    if (ctx->pinned) hipHostFree(ctx->pinned);
+    for (auto &e : ctx->ev)
+        if (e) hipEventDestroy(e);
+    delete ctx;
+}
+
+const char *subkm_last_error(const subkm_ctx *ctx) {
+    if (!ctx) {
+        std::lock_guard<std::mutex> g(g_create_mu);
+        return g_create_err.c_str();
+    }
+    return ctx->err.c_str();
+}
+
+subkm_status subkm_set_stream(subkm_ctx *ctx, void *stream) {
+    CHECK_CTX(ctx);
+    ctx->stream = (hipStream_t)stream;
+    return SUBKM_OK;
+}
+
+subkm_status subkm_synchronize(subkm_ctx *ctx) {
+    CHECK_CTX(ctx);
+    DeviceGuard g(ctx->device);
+    SUBKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return SUBKM_OK;
+}
+
+subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
+                         float *mins, float *maxs) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
+    REQUIRE(ctx, d >= 1 && d <= 4096, "d must be in [1, 4096]");
+    REQUIRE(ctx, X && S && mins && maxs, "NULL array argument");
+    DeviceGuard g(ctx->device);
+    return scale_impl(ctx, X, n, d, S, mins, maxs, true);
+}
+
+subkm_status subkm_subcluster(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
+                              int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
+                              float *landmarks) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
+    REQUIRE(ctx, d >= 1 && d <= 4096, "d must be in [1, 4096]");
+    REQUIRE(ctx, N >= 1, "N must be >= 1");
+    REQUIRE(ctx, landmark_mode == 0 || landmark_mode == 1, "landmark_mode must be 0 or 1");
+    REQUIRE(ctx, S && P && perm && offsets, "NULL array argument");
+    REQUIRE(ctx, (const void *)S != (const void *)P, "P must not alias S");
+    DeviceGuard g(ctx->device);
+    return subcluster_impl(ctx, S, n, d, N, landmark_mode, P, perm, offsets, landmarks);
+}
+
+subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run *runs,
+                                 int32_t R, float *C, int32_t *labels, int32_t max_iter,
+                                 double tol, int32_t precision, int32_t form, int32_t *iters,
+                                 double *sse) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, R >= 1, "R must be >= 1");
+    REQUIRE(ctx, P && runs && C && labels && iters && sse, "NULL array argument");
+    REQUIRE(ctx, max_iter >= 0, "max_iter must be >= 0");
+    REQUIRE(ctx, tol >= 0 && std::isfinite(tol), "tol must be finite and >= 0");
+    REQUIRE(ctx, precision == SUBKM_PREC_FP32 || precision == SUBKM_PREC_BF16,
+            "unknown precision %d", precision);
+    REQUIRE(ctx, form == SUBKM_FORM_BATCHED || form == SUBKM_FORM_PLAIN, "unknown form %d", form);
+    for (int32_t r = 0; r < R; ++r) {
+        const subkm_run &u = runs[r];
+        REQUIRE(ctx, u.n >= 1 && u.n < (1ll << 31), "run %d: n must be in [1, 2^31)", r);
+        REQUIRE(ctx, u.d >= 1 && u.d <= 4096, "run %d: d must be in [1, 4096]", r);
+        REQUIRE(ctx, u.k >= 1 && u.k <= u.n, "run %d: k must be in [1, n]", r);
+        REQUIRE(ctx, u.x_off >= 0 && u.c_off >= 0 && u.lab_off >= 0, "run %d: negative offset", r);
+    }
+    DeviceGuard g(ctx->device);
+    return lloyd_impl(ctx, P, runs, R, C, labels, max_iter, tol, precision, form, iters, sse, 0);
+}
+
+subkm_status subkm_cluster_sizes(int64_t n, int64_t N, int32_t k_local, int64_t *T, int64_t *M) {
+    if (n < 1 || N < 1 || k_local < 1 || k_local > N || !T || !M) return SUBKM_EINVAL;
+    int64_t t = ceil_div(n, N);
+    int64_t full = n / N, rest = n - full * N;
+    int64_t m = full * (int64_t)k_local + (rest ? ceil_div(rest * (int64_t)k_local, N) : 0);
+    *T = t;
+    *M = m;
+    return SUBKM_OK;
+}
+
+size_t subkm_cluster_footprint(int64_t n, int32_t d, int64_t N, int32_t k_local,
+                               int32_t k_final) {
+    int64_t T = 0, M = 0;
+    if (subkm_cluster_sizes(n, N, k_local, &T, &M) != SUBKM_OK || d < 1) return 0;
+    size_t pts = (size_t)n * d * sizeof(float);
+    size_t b = 0;
+    b += 2 * pts;                                  // S and P
+    b += (size_t)n * (4 + 4 + 4 + 8 + 12 + 4);     // perm, rem x2, keys, candidates, labels
+    b += (size_t)M * d * sizeof(float) + (size_t)M * 4;  // local centers + their labels
+    b += (size_t)(T + 1) * 8 + (size_t)T * 16;
+    b += (size_t)(n / 256 + M / 256 + T + 8) * 64;      // Lloyd work items and partials
+    b += (size_t)k_final * d * 4 + (size_t)d * 64 + (1 << 20);
+    return b;
+}
+
+subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t N,
+                           int32_t k_local, int32_t k_final, int32_t max_iter, double tol,
+                           const subkm_opts *opts, float *centers, int32_t *labels, double *sse,
+                           subkm_stats *stats) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
+    REQUIRE(ctx, d >= 1 && d <= 4096, "d must be in [1, 4096]");
+    REQUIRE(ctx, N >= 1, "N must be >= 1");
+    REQUIRE(ctx, k_local >= 1 && k_local <= N, "k_local must be in [1, N]");
+    REQUIRE(ctx, max_iter >= 0, "max_iter must be >= 0");
+    REQUIRE(ctx, tol >= 0 && std::isfinite(tol), "tol must be finite and >= 0");
+    REQUIRE(ctx, X && centers && labels && sse, "NULL array argument");
+    subkm_opts o{};
+    if (opts) o = *opts;
+    REQUIRE(ctx, o.landmark_mode == 0 || o.landmark_mode == 1, "landmark_mode must be 0 or 1");
+    REQUIRE(ctx, o.precision == SUBKM_PREC_FP32 || o.precision == SUBKM_PREC_BF16,
+            "unknown precision");
+    REQUIRE(ctx, o.form == SUBKM_FORM_BATCHED || o.form == SUBKM_FORM_PLAIN, "unknown form");
+    int64_t T = 0, M = 0;
+    subkm_cluster_sizes(n, N, k_local, &T, &M);
+    REQUIRE(ctx, k_final >= 1 && k_final <= M, "k_final must be in [1, M=%lld]", (long long)M);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->stream;
+
+    const size_t pts = (size_t)n * d;
+    float *S = o.S ? o.S : (float *)ctx_scratch(ctx, SC_CL_S, pts * sizeof(float));
+    float *P = (float *)ctx_scratch(ctx, SC_CL_P, pts * sizeof(float));
+    int32_t *perm = o.perm ? o.perm : (int32_t *)ctx_scratch(ctx, SC_CL_PERM, n * sizeof(int32_t));
+    int64_t *offs = (int64_t *)ctx_scratch(ctx, SC_CL_OFFS, (T + 1) * sizeof(int64_t));
+    float *loc = o.local_centers ? o.local_centers
+                                 : (float *)ctx_scratch(ctx, SC_CL_LOCAL, (size_t)M * d * 4);
+    int32_t *llab = (int32_t *)ctx_scratch(ctx, SC_CL_LLAB, (size_t)n * sizeof(int32_t));
+    int32_t *lit = o.local_iters ? o.local_iters
+                                 : (int32_t *)ctx_scratch(ctx, SC_CL_LIT, T * sizeof(int32_t));
+    double *lsse = o.local_sse ? o.local_sse
+                               : (double *)ctx_scratch(ctx, SC_CL_LSSE, T * sizeof(double));
+    float *mm = (float *)ctx_scratch(ctx, SC_CL_MINMAX, 2 * (size_t)d * sizeof(float));
+    char *fin = (char *)ctx_scratch(ctx, SC_CL_FINAL, (size_t)M * 4 + 64);
+    if (!S || !P || !perm || !offs || !loc || !llab || !lit || !lsse || !mm || !fin)
+        return SUBKM_ENOMEM;
+    int32_t *fit = (int32_t *)fin;
+    double *fsse = (double *)(fin + 16);
+    int32_t *flab = (int32_t *)(fin + 64);
+
+    hipEvent_t *ev = ctx->ev;
+    if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[0], s));
+    SUBKM_TRY(scale_impl(ctx, X, n, d, S, mm, mm + d, true));
+    if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[1], s));
+    SUBKM_TRY(subcluster_impl(ctx, S, n, d, N, o.landmark_mode, P, perm, offs, nullptr));
+    if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
+
+    // local runs: subcluster t holds rows t*N .. of P
+    std::vector<subkm_run> runs((size_t)T);
+    int64_t m = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        int64_t nr = std::min<int64_t>(N, n - t * N);
+        subkm_run &u = runs[t];
+        u.x_off = t * N * d;
+        u.n = nr;
+        u.c_off = m * d;
+        u.lab_off = t * N;
+        u.d = d;
+        u.k = (int32_t)ceil_div(nr * (int64_t)k_local, N);
+        m += u.k;
+    }
+    SUBKM_TRY(lloyd_impl(ctx, P, runs.data(), (int32_t)T, loc, llab, max_iter, tol, o.precision,
+                         o.form, lit, lsse, 1));
+    if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[3], s));
+    // final run on the local centers, strided start
+    subkm_run fr{0, M, 0, 0, d, k_final};
+    SUBKM_TRY(lloyd_impl(ctx, loc, &fr, 1, centers, flab, max_iter, tol, o.precision,
+                         SUBKM_FORM_BATCHED, fit, fsse, 2));
+    if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[4], s));
+    // labels of all points against the final centers (an assignment only)
+    subkm_run lr{0, n, 0, 0, d, k_final};
+    SUBKM_TRY(lloyd_impl(ctx, S, &lr, 1, centers, labels, 0, 0.0, o.precision,
+                         SUBKM_FORM_BATCHED, fit + 1, sse, 0));
+    if (stats) {
+        SUBKM_HIP(ctx, hipEventRecord(ev[5], s));
+        SUBKM_HIP(ctx, hipEventSynchronize(ev[5]));
+        float ms[5];
+        for (int q = 0; q < 5; ++q) SUBKM_HIP(ctx, hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
+        std::vector<int32_t> hit((size_t)T + 1);
+        SUBKM_HIP(ctx, hipMemcpy(hit.data(), lit, T * sizeof(int32_t), hipMemcpyDeviceToHost));
+        SUBKM_HIP(ctx, hipMemcpy(&hit[T], fit, sizeof(int32_t), hipMemcpyDeviceToHost));
+        stats->T = T;
+        stats->M = M;
+        stats->final_iters = hit[T];
+        int64_t lpi = 0;
+        for (int64_t t = 0; t < T; ++t) lpi += runs[t].n * (int64_t)hit[t];
+        stats->local_point_iters = lpi;
+        stats->final_point_iters = M * (int64_t)hit[T];
+        stats->us_scale = ms[0] * 1e3;
+        stats->us_subcluster = ms[1] * 1e3;
+        stats->us_local = ms[2] * 1e3;
+        stats->us_final = ms[3] * 1e3;
+        stats->us_label = ms[4] * 1e3;
+        stats->us_total = (ms[0] + ms[1] + ms[2] + ms[3] + ms[4]) * 1e3;
+    }
+    return SUBKM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Internal declarations of libsubkm (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/subkm.h"
+
+// ---------------------------------------------------------------------------
+// Context: device, stream, scratch slots that persist between calls.
+enum ScratchSlot {
+    SC_MM_PART = 0,  // min/max partials
+    SC_MM_FLAG,      // non-finite flag + small host-visible words
+    SC_KEYS,         // landmark keys, double per remaining point
+    SC_REM0,         // remaining positions -> original index (ping)
+    SC_REM1,         // (pong)
+    SC_CAND,         // selection candidates (key, position)
+    SC_SEL,          // selection state + histograms + block counts
+    SC_LAND,         // landmark (float) + running minima (ordered uint)
+    SC_COLMAX,       // column maxima of S for the key bound
+    SC_RUNS,         // device copy of run descriptors
+    SC_ITEMS,        // work items of the Lloyd kernels
+    SC_RSTATE,       // per-run Lloyd state
+    SC_SSEPART,      // per-item objective partials
+    SC_FIXSCALE,     // per-run fixed-point exponents
+    SC_RECHECK,      // recheck counters
+    SC_CL_S,         // cluster(): scaled points
+    SC_CL_P,         // cluster(): grouped points
+    SC_CL_PERM,      // cluster(): permutation
+    SC_CL_OFFS,      // cluster(): offsets
+    SC_CL_LOCAL,     // cluster(): local centers
+    SC_CL_LLAB,      // cluster(): local labels
+    SC_CL_LIT,       // cluster(): local iterations
+    SC_CL_LSSE,      // cluster(): local objective
+    SC_CL_MINMAX,    // cluster(): mins / maxs
+    SC_CL_FINAL,     // cluster(): final-run labels, iters, sse
+    SC_COUNT
+};
+
+struct ScratchBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct subkm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 256;
+    std::string err;
+    ScratchBuf scratch[SC_COUNT];
+    void *pinned = nullptr;  // small pinned host staging area
+    size_t pinned_bytes = 0;
+    hipEvent_t ev[8] = {};
+};
+
+// Scratch memory of a slot with at least `bytes` bytes (grows on demand).
+// Returns nullptr and sets ctx->err when allocation fails.
+void *ctx_scratch(subkm_ctx *ctx, int slot, size_t bytes);
+void *ctx_pinned(subkm_ctx *ctx, size_t bytes);
+
+subkm_status set_err(subkm_ctx *ctx, subkm_status st, const char *fmt, ...);
+
+#define SUBKM_HIP(ctx, expr)                                                              \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return set_err((ctx), SUBKM_EDEVICE, "%s failed: %s (%s:%d)", #expr,          \
+                           hipGetErrorString(e_), __FILE__, __LINE__);                    \
+    } while (0)
+
+#define SUBKM_LAUNCHED(ctx)                                                               \
+    do {                                                                                  \
+        hipError_t e_ = hipGetLastError();                                                \
+        if (e_ != hipSuccess)                                                             \
+            return set_err((ctx), SUBKM_EDEVICE, "kernel launch failed: %s (%s:%d)",      \
+                           hipGetErrorString(e_), __FILE__, __LINE__);                    \
+    } while (0)
+
+#define SUBKM_TRY(expr)                                                                   \
+    do {                                                                                  \
+        subkm_status s_ = (expr);                                                         \
+        if (s_ != SUBKM_OK) return s_;                                                    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Stage entry points used by subkm_cluster (already validated arguments).
+subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
+                        float *mins, float *maxs, bool check_finite);
+subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
+                             int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
+                             float *landmarks);
+
+// Lloyd runs.  `runs` is a host array; `init_mode` 0 = centers already in C,
+// 1 = copy the first k points of every run into C first, 2 = strided start
+// C[q] = X[q * floor(n / k)] (single-run final stage).
+subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, int32_t R,
+                        float *C, int32_t *labels, int32_t max_iter, double tol,
+                        int32_t precision, int32_t form, int32_t *iters, double *sse,
+                        int init_mode);
+
+// ---------------------------------------------------------------------------
+// Small device helpers shared by the kernels.
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+    // monotone map of float to uint32 (total order of non-NaN floats)
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ordered_float(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

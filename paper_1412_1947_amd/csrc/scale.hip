@@ -1,0 +1,197 @@
+// Min-max feature scaling (Sec. II, Algorithm 1 step 1; Sec. III, Algorithm 2
+// step 1).  Two HBM-bound passes: column minima/maxima (exact, so the
+// reduction order is free), then the binary64 transform rounded once to
+// float32.
+//
+// Thread -> element mapping.  Narrow rows (d < 64): a flat grid-stride loop
+// whose stride is a multiple of d, so every thread keeps one fixed column and
+// consecutive lanes read consecutive floats.  Wide rows (d >= 64): a block
+// owns a range of rows and its lanes sweep the columns of each row, again
+// contiguous across lanes.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#pragma clang fp contract(off)
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ __launch_bounds__(kThreads) void k_minmax_narrow(const float *__restrict__ X,
+                                                            int64_t total, int d, int64_t stride,
+                                                            float *__restrict__ pmin,
+                                                            float *__restrict__ pmax,
+                                                            int *__restrict__ flag) {
+    __shared__ float smin[kThreads], smax[kThreads];
+    const int t = threadIdx.x;
+    const int64_t e0 = (int64_t)blockIdx.x * kThreads + t;
+    float mn = INFINITY, mx = -INFINITY;
+    bool bad = false;
+    for (int64_t e = e0; e < total; e += stride) {
+        float v = __builtin_nontemporal_load(X + e);
+        bad |= !isfinite(v);
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+    }
+    if (bad) atomicOr(flag, 1);
+    smin[t] = mn;
+    smax[t] = mx;
+    __syncthreads();
+    // column c collects the threads t' with (blockIdx*256 + t') % d == c
+    const int base = (int)(((int64_t)blockIdx.x * kThreads) % d);
+    for (int c = t; c < d; c += kThreads) {
+        int t0 = (c - base) % d;
+        if (t0 < 0) t0 += d;
+        float a = INFINITY, b = -INFINITY;
+        for (int q = t0; q < kThreads; q += d) {
+            a = fminf(a, smin[q]);
+            b = fmaxf(b, smax[q]);
+        }
+        pmin[(int64_t)blockIdx.x * d + c] = a;
+        pmax[(int64_t)blockIdx.x * d + c] = b;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_minmax_wide(const float *__restrict__ X, int64_t n,
+                                                          int d, int64_t rows_per_block,
+                                                          float *__restrict__ pmin,
+                                                          float *__restrict__ pmax,
+                                                          int *__restrict__ flag) {
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(n, r0 + rows_per_block);
+    bool bad = false;
+    for (int c = threadIdx.x; c < d; c += kThreads) {
+        float mn = INFINITY, mx = -INFINITY;
+        for (int64_t r = r0; r < r1; ++r) {
+            float v = __builtin_nontemporal_load(X + r * d + c);
+            bad |= !isfinite(v);
+            mn = fminf(mn, v);
+            mx = fmaxf(mx, v);
+        }
+        pmin[(int64_t)blockIdx.x * d + c] = mn;
+        pmax[(int64_t)blockIdx.x * d + c] = mx;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+// second stage: one thread per column over the block partials
+__global__ void k_minmax_final(const float *__restrict__ pmin, const float *__restrict__ pmax,
+                               int parts, int d, float *__restrict__ mins,
+                               float *__restrict__ maxs) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d) return;
+    float a = INFINITY, b = -INFINITY;
+    for (int p = 0; p < parts; ++p) {
+        a = fminf(a, pmin[(int64_t)p * d + c]);
+        b = fmaxf(b, pmax[(int64_t)p * d + c]);
+    }
+    if (mins) mins[c] = a;
+    if (maxs) maxs[c] = b;
+}
+
+__device__ __forceinline__ float scale_one(float x, float mn, float mx) {
+    double range = (double)mx - (double)mn;
+    if (!(range > 0.0)) return 0.0f;
+    double num = (double)x - (double)mn;
+    return (float)(num / range);
+}
+
+__global__ __launch_bounds__(kThreads) void k_apply_narrow(const float *X, int64_t total, int d,
+                                                           int64_t stride,
+                                                           const float *__restrict__ mins,
+                                                           const float *__restrict__ maxs,
+                                                           float *S) {
+    const int64_t e0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e0 >= total) return;
+    const int c = (int)(e0 % d);
+    const float mn = mins[c], mx = maxs[c];
+    for (int64_t e = e0; e < total; e += stride) S[e] = scale_one(X[e], mn, mx);
+}
+
+__global__ __launch_bounds__(kThreads) void k_apply_wide(const float *X, int64_t n, int d,
+                                                         int64_t rows_per_block,
+                                                         const float *__restrict__ mins,
+                                                         const float *__restrict__ maxs,
+                                                         float *S) {
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(n, r0 + rows_per_block);
+    for (int c = threadIdx.x; c < d; c += kThreads) {
+        const float mn = mins[c], mx = maxs[c];
+        for (int64_t r = r0; r < r1; ++r) S[r * d + c] = scale_one(X[r * d + c], mn, mx);
+    }
+}
+
+struct Plan {
+    bool narrow;
+    int64_t blocks;
+    int64_t stride;          // narrow: elements
+    int64_t rows_per_block;  // wide
+};
+
+Plan plan_for(int64_t n, int d) {
+    Plan p{};
+    const int64_t total = n * d;
+    if (d < 64) {
+        p.narrow = true;
+        const int64_t unit = d / std::gcd(d, kThreads);  // blocks per column period
+        int64_t want = std::min<int64_t>(ceil_div(total, kThreads), 2048);
+        p.blocks = std::max<int64_t>(unit, ceil_div(want, unit) * unit);
+        p.stride = p.blocks * kThreads;
+    } else {
+        p.narrow = false;
+        p.rows_per_block = std::max<int64_t>(8, ceil_div(n, 2048));
+        p.blocks = ceil_div(n, p.rows_per_block);
+    }
+    return p;
+}
+
+}  // namespace
+
+// Column minima and maxima of an n x d array into mins/maxs (either may be
+// null).  flag (device int, zeroed by the caller) is set when a value is NaN
+// or infinite.
+subkm_status minmax_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *mins,
+                         float *maxs, int *flag) {
+    Plan p = plan_for(n, d);
+    float *part = (float *)ctx_scratch(ctx, SC_MM_PART, sizeof(float) * 2 * p.blocks * d);
+    if (!part) return SUBKM_ENOMEM;
+    float *pmin = part, *pmax = part + p.blocks * d;
+    if (p.narrow)
+        hipLaunchKernelGGL(k_minmax_narrow, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X,
+                           n * d, d, p.stride, pmin, pmax, flag);
+    else
+        hipLaunchKernelGGL(k_minmax_wide, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n,
+                           d, p.rows_per_block, pmin, pmax, flag);
+    SUBKM_LAUNCHED(ctx);
+    hipLaunchKernelGGL(k_minmax_final, dim3(ceil_div(d, 256)), dim3(256), 0, ctx->stream, pmin,
+                       pmax, (int)p.blocks, d, mins, maxs);
+    SUBKM_LAUNCHED(ctx);
+    return SUBKM_OK;
+}
+
+subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
+                        float *mins, float *maxs, bool check_finite) {
+    int *flag = (int *)ctx_scratch(ctx, SC_MM_FLAG, 256);
+    if (!flag) return SUBKM_ENOMEM;
+    SUBKM_HIP(ctx, hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+    SUBKM_TRY(minmax_impl(ctx, X, n, d, mins, maxs, flag));
+    if (check_finite) {
+        int *h = (int *)ctx_pinned(ctx, sizeof(int));
+        if (!h) return SUBKM_ENOMEM;
+        SUBKM_HIP(ctx, hipMemcpyAsync(h, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        SUBKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (*h) return set_err(ctx, SUBKM_EINVAL, "input contains NaN or infinite values");
+    }
+    Plan p = plan_for(n, d);
+    if (p.narrow)
+        hipLaunchKernelGGL(k_apply_narrow, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X,
+                           n * d, d, p.stride, mins, maxs, S);
+    else
+        hipLaunchKernelGGL(k_apply_wide, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n, d,
+                           p.rows_per_block, mins, maxs, S);
+    SUBKM_LAUNCHED(ctx);
+    return SUBKM_OK;
+}

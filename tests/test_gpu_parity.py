@@ -1,0 +1,271 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Scaling and subclustering must match bit for bit.  Lloyd is checked step by
+step ("shadow" parity: the oracle takes the GPU's float32 centers as its
+input), where labels must match exactly -- the library re-assigns every
+point whose two nearest centers are within its float32 error bound with
+binary64 distances -- and centers and objective within 1e-5 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def km():
+    import paper_1412_1947_amd as pkg
+    return pkg.context(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_err(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b)))) if a.size else 0.0
+
+
+# ----------------------------------------------------------------------------- scale
+@pytest.mark.parametrize("n,d", [(1, 1), (7, 3), (4096, 4), (5000, 7), (3001, 64), (1000, 100),
+                                 (257, 300)])
+def test_scale_bit_exact(km, oracle, n, d):
+    rng = np.random.default_rng(n * 31 + d)
+    X = (rng.standard_normal((n, d)) * rng.uniform(0.01, 100, d) + rng.uniform(-9, 9, d)).astype(np.float32)
+    if d > 2:
+        X[:, 1] = 0.625  # constant attribute
+    S, mn, mx = km.scale(dev(X))
+    Sr, mnr, mxr = oracle.scale(X)
+    assert np.array_equal(host(mn), mnr) and np.array_equal(host(mx), mxr)
+    assert np.array_equal(host(S), Sr)
+
+
+def test_scale_mid_workload(km, oracle):
+    X = synth.mid(n=1 << 18).X
+    S, _, _ = km.scale(dev(X))
+    assert np.array_equal(host(S), oracle.scale(X)[0])
+
+
+def test_scale_rejects_nan(km):
+    import paper_1412_1947_amd as pkg
+    X = np.ones((100, 4), np.float32)
+    X[50, 2] = np.nan
+    with pytest.raises(pkg.SubkmError) as e:
+        km.scale(dev(X))
+    assert e.value.status == 1
+
+
+# ------------------------------------------------------------------------ subcluster
+def check_subcluster(km, oracle, S, N, mode=0):
+    P, perm, offs, lm = km.subcluster(dev(S), N, landmark_mode=mode, landmarks=True)
+    permr, offr, lmr = oracle.subcluster(S, N, fixed_landmark=bool(mode))
+    perm = host(perm)
+    assert np.array_equal(host(offs), offr)
+    assert np.array_equal(host(lm), lmr)
+    assert np.array_equal(perm, permr)
+    assert np.array_equal(host(P), S[perm])
+
+
+@pytest.mark.parametrize("N", [1, 7, 100, 512, 1000, 4095, 4096, 10 ** 6])
+def test_subcluster_tiny(km, oracle, N):
+    S, _, _ = oracle.scale(synth.tiny().X)
+    check_subcluster(km, oracle, S, N)
+
+
+@pytest.mark.parametrize("n,d,N", [(1, 1, 1), (2, 1, 1), (10, 3, 4), (3000, 1, 200), (6000, 3, 777),
+                                   (5000, 16, 2048), (4000, 100, 999), (2100, 600, 700),
+                                   (20000, 2, 2500)])
+def test_subcluster_shapes(km, oracle, n, d, N):
+    rng = np.random.default_rng(n + d + N)
+    X = rng.standard_normal((n, d)).astype(np.float32) + rng.integers(0, 4, (n, 1)).astype(np.float32)
+    S, _, _ = oracle.scale(X)
+    check_subcluster(km, oracle, S, N)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_subcluster_ties_and_duplicates(km, oracle, mode):
+    rng = np.random.default_rng(3)
+    S = (rng.integers(0, 3, (9000, 2)) / 2).astype(np.float32)  # 9 distinct points only
+    check_subcluster(km, oracle, S, 1000, mode)
+    S2 = np.repeat(rng.uniform(0, 1, (40, 4)).astype(np.float32), 100, axis=0)
+    check_subcluster(km, oracle, S2, 333, mode)
+
+
+def test_subcluster_fixed_landmark(km, oracle):
+    S, _, _ = oracle.scale(synth.tiny().X)
+    check_subcluster(km, oracle, S, 300, mode=1)
+
+
+def test_subcluster_mid_workload(km, oracle):
+    job = synth.mid(n=1 << 18)
+    S, _, _ = oracle.scale(job.X)
+    check_subcluster(km, oracle, S, job.N)
+
+
+# ----------------------------------------------------------------------------- Lloyd
+def shadow_steps(km, oracle, X, C0, steps, precision=0):
+    """Run `steps` single GPU iterations, each checked against one oracle
+    iteration from the same float32 centers."""
+    n, d = X.shape
+    k = C0.shape[0]
+    Xd = dev(X)
+    X64 = X.astype(np.float64)
+    C = C0.astype(np.float32).copy()
+    lab_d = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    # max_iter = 0: a pure assignment
+    Cd = dev(C)
+    _, sse = km.lloyd_batched(Xd, [(0, n, 0, 0, d, k)], Cd, lab_d, 0, 0.0, precision)
+    lab_r, sse_r, _, _ = oracle.assign(X64, C)
+    assert np.array_equal(host(lab_d), lab_r)
+    assert abs(host(sse)[0] - sse_r) <= TOL * sse_r + 1e-300
+    for _ in range(steps):
+        Cd = dev(C)
+        it, sse = km.lloyd_batched(Xd, [(0, n, 0, 0, d, k)], Cd, lab_d, 1, 0.0, precision)
+        Cg = host(Cd)
+        lab0, _, _, _ = oracle.assign(X64, C)
+        Cref, _, _ = oracle.update(X64, lab0, C.astype(np.float64))
+        assert rel_err(Cg, Cref) <= TOL
+        lab1, sse1, _, _ = oracle.assign(X64, Cg)
+        assert np.array_equal(host(lab_d), lab1)
+        assert abs(host(sse)[0] - sse1) <= TOL * sse1
+        assert host(it)[0] == 1
+        C = Cg
+
+
+@pytest.mark.parametrize("n,d,k", [(512, 4, 32), (1000, 2, 10), (3000, 16, 256), (2000, 7, 50),
+                                   (777, 32, 77), (1500, 64, 100), (900, 128, 300), (300, 3, 300)])
+def test_lloyd_shadow(km, oracle, n, d, k):
+    rng = np.random.default_rng(n * 7 + d)
+    X, _ = synth.gaussian_blobs(n, d, max(2, k // 8), seed=n + d, sigma=0.7)
+    S, _, _ = oracle.scale(X)
+    shadow_steps(km, oracle, S, S[:k], steps=3)
+
+
+def test_lloyd_ties_and_empty_clusters(km, oracle):
+    # duplicated points and duplicated centers: exact ties everywhere; the
+    # second copy of every center ends up empty and must stay in place
+    rng = np.random.default_rng(11)
+    base = rng.uniform(0, 1, (20, 3)).astype(np.float32)
+    X = np.repeat(base, 30, axis=0)
+    C0 = np.concatenate([base[:10], base[:10]])
+    shadow_steps(km, oracle, X, C0, steps=2)
+
+
+def test_lloyd_k1_and_k_equals_n(km, oracle):
+    X, _ = synth.gaussian_blobs(200, 5, 3, seed=5)
+    S, _, _ = oracle.scale(X)
+    shadow_steps(km, oracle, S, S[:1], steps=1)
+    shadow_steps(km, oracle, S[:50], S[:50], steps=1)
+
+
+def run_batch(km, runs_np, ks, max_iter, tol, form=0, precision=0):
+    """Many runs in one call; returns per-run centers, labels, iters, sse."""
+    xs, specs, x_off, c_off, l_off = [], [], 0, 0, 0
+    for X, k in zip(runs_np, ks):
+        n, d = X.shape
+        specs.append((x_off, n, c_off, l_off, d, k))
+        xs.append(X.reshape(-1))
+        x_off += n * d
+        c_off += k * d
+        l_off += n
+    P = dev(np.concatenate(xs))
+    C = torch.cat([dev(X[:k].reshape(-1)) for X, k in zip(runs_np, ks)])
+    lab = torch.empty(l_off, dtype=torch.int32, device="cuda:0")
+    it, sse = km.lloyd_batched(P, specs, C, lab, max_iter, tol, precision, form)
+    Ch, labh, ith, sseh = host(C), host(lab), host(it), host(sse)
+    out = []
+    for (xo, n, co, lo, d, k) in specs:
+        out.append((Ch[co:co + k * d].reshape(k, d), labh[lo:lo + n]))
+    return out, ith, sseh
+
+
+def test_lloyd_batched_matches_oracle_trajectory(km, oracle):
+    rng = np.random.default_rng(21)
+    runs, ks = [], []
+    for j in range(12):
+        n = int(rng.integers(300, 3000))
+        d = int(rng.choice([2, 4, 8, 16, 5]))
+        X, _ = synth.gaussian_blobs(n, d, int(rng.integers(3, 12)), seed=j, sigma=0.4)
+        runs.append(oracle.scale(X)[0])
+        ks.append(int(rng.integers(1, 40)))
+    out, iters, sse = run_batch(km, runs, ks, 15, 1e-6)
+    for r, (X, k) in enumerate(zip(runs, ks)):
+        ref = oracle.lloyd(X.astype(np.float64), X[:k], 15, 1e-6)
+        # with no near tie on the oracle's path the trajectories coincide
+        C, lab = out[r]
+        lab_ref, _, _, margin = oracle.assign(X.astype(np.float64), ref["centers"])
+        if np.all(margin[np.isfinite(margin)] > 1e-6) and abs(iters[r] - ref["iters"]) == 0:
+            assert rel_err(C, ref["centers"]) <= TOL, r
+            assert abs(sse[r] - ref["sse"]) <= TOL * ref["sse"], r
+            assert np.array_equal(lab, ref["labels"]), r
+
+
+def test_plain_equals_batched_and_deterministic(km, oracle):
+    rng = np.random.default_rng(5)
+    runs, ks = [], []
+    for j in range(9):
+        n = int(rng.integers(100, 5000))
+        X, _ = synth.gaussian_blobs(n, 16, 10, seed=100 + j, sigma=0.5)
+        runs.append(oracle.scale(X)[0])
+        ks.append(int(min(n, rng.integers(1, 300))))
+    a, ia, sa = run_batch(km, runs, ks, 10, 1e-6, form=0)
+    b, ib, sb = run_batch(km, runs, ks, 10, 1e-6, form=1)
+    c, ic, sc = run_batch(km, runs, ks, 10, 1e-6, form=0)
+    assert np.array_equal(ia, ib) and np.array_equal(sa, sb) and np.array_equal(sa, sc)
+    for (ca, la), (cb, lb), (cc, lc) in zip(a, b, c):
+        assert np.array_equal(ca, cb) and np.array_equal(la, lb)
+        assert np.array_equal(ca, cc) and np.array_equal(la, lc)
+
+
+# --------------------------------------------------------------------------- cluster
+def check_cluster(km, oracle, job, fixed=False):
+    X = dev(job.X)
+    out = km.cluster(X, job.N, job.k_local, job.k_final, job.max_iter, job.tol,
+                     landmark_mode=int(fixed), intermediates=True, stats=True)
+    ref = oracle.cluster(job.X, job.N, job.k_local, job.k_final, job.max_iter, job.tol,
+                         fixed_landmark=fixed)
+    assert np.array_equal(host(out["S"]), ref["S"])
+    assert np.array_equal(host(out["perm"]), ref["perm"])
+    st = out["stats"]
+    assert st["T"] == ref["T"] and st["M"] == ref["M"]
+    loc = host(out["local_centers"])
+    return out, ref, loc
+
+
+def test_cluster_tiny_end_to_end(km, oracle):
+    job = synth.tiny()
+    out, ref, loc = check_cluster(km, oracle, job)
+    assert rel_err(loc, ref["local_centers"]) <= TOL
+    assert np.array_equal(host(out["local_iters"]), ref["local_iters"])
+    assert rel_err(host(out["local_sse"]), ref["local_sse"]) <= TOL
+    assert rel_err(host(out["centers"]), ref["centers"]) <= TOL
+    assert np.array_equal(host(out["labels"]), ref["labels"])
+    assert abs(host(out["sse"])[0] - ref["sse"]) <= TOL * ref["sse"]
+
+
+@pytest.mark.parametrize("which,N,k_local", [("iris", 25, 5), ("seeds", 35, 6)])
+def test_cluster_table1_shapes(km, oracle, which, N, k_local):
+    job = synth.ClusterJob(synth.table1(which), N, k_local, 3, 20, 0.0)
+    out, ref, loc = check_cluster(km, oracle, job)
+    assert rel_err(loc, ref["local_centers"]) <= TOL
+    assert abs(host(out["sse"])[0] - ref["sse"]) <= TOL * ref["sse"]
+
+
+def test_cluster_ragged_tail_and_fixed_landmark(km, oracle):
+    X = synth.tiny().X[:3333]
+    job = synth.ClusterJob(X, 500, 20, 6, 12, 0.0)
+    check_cluster(km, oracle, job, fixed=True)
+    out, ref, loc = check_cluster(km, oracle, job)
+    assert rel_err(loc, ref["local_centers"]) <= TOL
