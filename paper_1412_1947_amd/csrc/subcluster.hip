@@ -321,8 +321,10 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
             double k = ckey[c];
             if (vmap(k, base) == vstar) {
                 uint32_t s = atomicAdd(&s_n, 1u);
-                rk[s] = k;
-                rp[s] = cpos[c];
+                if (s < (uint32_t)kRankCap) {
+                    rk[s] = k;
+                    rp[s] = cpos[c];
+                }
             }
         }
         __syncthreads();
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
                                                 int32_t *__restrict__ perm, int64_t off_t,
                                                 int32_t *__restrict__ rem_next, uint32_t *Lmin,
                                                 float *L, float *landmarks_next,
-                                                uint32_t *done3) {
+                                                uint32_t *done3, uint32_t need) {
     __shared__ int32_t s_src[kBS];
     __shared__ int32_t s_dst[kBS];  // >= 0: P row; < 0: -(1 + slot) in rem_next
     __shared__ uint32_t tmp[kT / 64], s_last;
@@ -420,14 +422,17 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
         if (lp < cnt) {
             int32_t idx = rem ? rem[p0 + lp] : (int32_t)(p0 + lp);
             s_src[lp] = idx;
+            // the guards only matter if the selection counts were inconsistent
             if (sel[q]) {
                 uint32_t row = sel_base + si++;
-                s_dst[lp] = (int32_t)row;
-                perm[off_t + row] = idx;
+                bool ok = row < need;
+                s_dst[lp] = ok ? (int32_t)row : INT32_MIN;
+                if (ok) perm[off_t + row] = idx;
             } else {
                 uint32_t slot = stay_base + ti++;
-                s_dst[lp] = -1 - (int32_t)slot;
-                rem_next[slot] = idx;
+                bool ok = slot < nrem - need;
+                s_dst[lp] = ok ? -1 - (int32_t)slot : INT32_MIN;
+                if (ok) rem_next[slot] = idx;
             }
         }
     }
@@ -444,6 +449,7 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
             uint32_t r = (uint32_t)(e / d);
             uint32_t j = (uint32_t)(e - (int64_t)r * d);
             int32_t dst = s_dst[r];
+            if (dst == INT32_MIN) continue;
             if (dst >= 0) {
                 P[((int64_t)off_t + dst) * d + j] = S[(int64_t)s_src[r] * d + j];
             } else if (track_min) {
@@ -574,7 +580,7 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
         float *lm_next = nullptr;
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kT), dyn_scatter, s, S, d, cur, keys, nrem, st,
                            blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt, Lmin, L,
-                           lm_next, &st->done3);
+                           lm_next, &st->done3, need);
         SUBKM_LAUNCHED(ctx);
         nrem -= need;
         // the list just written becomes the current one
