@@ -223,6 +223,19 @@ subkm_status subkm_cluster_sizes(int64_t n, int64_t N, int32_t k_local,
 size_t subkm_cluster_footprint(int64_t n, int32_t d, int64_t N, int32_t k_local,
                                int32_t k_final);
 
+/* ---------------------------------------------------------------------- */
+/* Per-launch kernel timing (diagnostics; not part of the method).
+ * When enabled, the library records a pair of HIP events on the context's
+ * stream around every launch of each kernel class below and accumulates
+ * the elapsed device time.  Enabling (or disabling) resets the counters.
+ * subkm_profile_query synchronises the stream and returns the number of
+ * launches and their total milliseconds for one class.
+ * Classes: 0 assign, 1 update, 2 keys, 3 cand, 4 scatter, 5 scale,
+ * 6 lloyd_fused (see subkm_profile_name).                                  */
+subkm_status subkm_profile_enable(subkm_ctx *ctx, int32_t on);
+subkm_status subkm_profile_query(subkm_ctx *ctx, int32_t cls, int64_t *launches, double *ms);
+const char *subkm_profile_name(int32_t cls);
+
 #ifdef __cplusplus
 }
 #endif

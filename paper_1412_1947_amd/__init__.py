@@ -60,7 +60,10 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ("subkm_create", "subkm_destroy", "subkm_last_error", "subkm_set_stream",
            "subkm_synchronize", "subkm_scale", "subkm_subcluster", "subkm_lloyd_batched",
-           "subkm_cluster", "subkm_cluster_sizes", "subkm_cluster_footprint")
+           "subkm_cluster", "subkm_cluster_sizes", "subkm_cluster_footprint",
+           "subkm_profile_enable", "subkm_profile_query", "subkm_profile_name")
+
+KERNEL_CLASSES = ("assign", "update", "keys", "cand", "scatter", "scale", "lloyd_fused")
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -100,6 +103,12 @@ def lib():
             L.subkm_cluster_sizes.restype = st
             L.subkm_cluster_footprint.argtypes = [i64, i32, i64, i32, i32]
             L.subkm_cluster_footprint.restype = ctypes.c_size_t
+            L.subkm_profile_enable.argtypes = [P, i32]
+            L.subkm_profile_enable.restype = st
+            L.subkm_profile_query.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64)]
+            L.subkm_profile_query.restype = st
+            L.subkm_profile_name.argtypes = [i32]
+            L.subkm_profile_name.restype = ctypes.c_char_p
             _lib = L
     return _lib
 
@@ -165,6 +174,19 @@ class Context:
 
     def synchronize(self):
         self._check(lib().subkm_synchronize(self._h))
+
+    def profile(self, on: bool = True):
+        """Start (or stop) per-launch kernel timing; resets the counters."""
+        self._check(lib().subkm_profile_enable(self._h, int(bool(on))))
+
+    def profile_read(self):
+        """{class: (launches, total ms)} of the launches timed so far."""
+        out = {}
+        for c, name in enumerate(KERNEL_CLASSES):
+            n, ms = ctypes.c_int64(), ctypes.c_double()
+            self._check(lib().subkm_profile_query(self._h, c, ctypes.byref(n), ctypes.byref(ms)))
+            out[name] = (n.value, ms.value)
+        return out
 
     # -- the C ABI -------------------------------------------------------------
     def scale(self, X, out=None):

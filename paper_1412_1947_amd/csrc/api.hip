@@ -66,6 +66,47 @@ void *ctx_pinned(subkm_ctx *ctx, size_t bytes) {
     return ctx->pinned;
 }
 
+static hipEvent_t prof_event(subkm_ctx *ctx) {
+    if (!ctx->prof_free.empty()) {
+        hipEvent_t e = ctx->prof_free.back();
+        ctx->prof_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+ProfScope::ProfScope(subkm_ctx *c, int k) : ctx(c), cls(k) {
+    if (!ctx->prof_on) return;
+    a = prof_event(ctx);
+    if (a) hipEventRecord(a, ctx->stream);
+}
+
+ProfScope::~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = prof_event(ctx);
+    if (!b) return;
+    hipEventRecord(b, ctx->stream);
+    ctx->prof_pending.push_back(ProfRec{cls, a, b});
+}
+
+static void prof_resolve(subkm_ctx *ctx) {
+    for (auto &r : ctx->prof_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            ctx->prof_ms[r.cls] += ms;
+            ctx->prof_n[r.cls] += 1;
+        }
+        ctx->prof_free.push_back(r.a);
+        ctx->prof_free.push_back(r.b);
+    }
+    ctx->prof_pending.clear();
+}
+
 // RAII: make the context's device current for the duration of a call
 struct DeviceGuard {
     int prev = -1;
@@ -129,6 +170,8 @@ void subkm_destroy(subkm_ctx *ctx) {
     if (ctx->pinned) hipHostFree(ctx->pinned);
     for (auto &e : ctx->ev)
         if (e) hipEventDestroy(e);
+    prof_resolve(ctx);
+    for (auto &e : ctx->prof_free) hipEventDestroy(e);
     delete ctx;
 }
 
@@ -151,6 +194,35 @@ subkm_status subkm_synchronize(subkm_ctx *ctx) {
     DeviceGuard g(ctx->device);
     SUBKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return SUBKM_OK;
+}
+
+subkm_status subkm_profile_enable(subkm_ctx *ctx, int32_t on) {
+    CHECK_CTX(ctx);
+    DeviceGuard g(ctx->device);
+    prof_resolve(ctx);
+    for (int q = 0; q < PK_COUNT; ++q) {
+        ctx->prof_ms[q] = 0.0;
+        ctx->prof_n[q] = 0;
+    }
+    ctx->prof_on = on != 0;
+    return SUBKM_OK;
+}
+
+subkm_status subkm_profile_query(subkm_ctx *ctx, int32_t cls, int64_t *launches, double *ms) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, cls >= 0 && cls < PK_COUNT, "unknown kernel class %d", cls);
+    REQUIRE(ctx, launches && ms, "NULL output");
+    DeviceGuard g(ctx->device);
+    prof_resolve(ctx);
+    *launches = ctx->prof_n[cls];
+    *ms = ctx->prof_ms[cls];
+    return SUBKM_OK;
+}
+
+const char *subkm_profile_name(int32_t cls) {
+    static const char *names[PK_COUNT] = {"assign", "update", "keys", "cand",
+                                          "scatter", "scale", "lloyd_fused"};
+    return (cls >= 0 && cls < PK_COUNT) ? names[cls] : "";
 }
 
 subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,

@@ -41,6 +41,17 @@ enum ScratchSlot {
     SC_COUNT
 };
 
+// Kernel classes timed by the optional per-launch profiler (device events on
+// the context's stream around every launch of the class).
+enum ProfClass {
+    PK_ASSIGN = 0, PK_UPDATE, PK_KEYS, PK_CAND, PK_SCATTER, PK_SCALE, PK_LLOYD_FUSED, PK_COUNT
+};
+
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+};
+
 struct ScratchBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -55,6 +66,20 @@ struct subkm_ctx {
     void *pinned = nullptr;  // small pinned host staging area
     size_t pinned_bytes = 0;
     hipEvent_t ev[8] = {};
+    bool prof_on = false;
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_free;
+    double prof_ms[PK_COUNT] = {};
+    long long prof_n[PK_COUNT] = {};
+};
+
+// RAII timer of the launches issued inside its scope (no-op when off).
+struct ProfScope {
+    subkm_ctx *ctx;
+    int cls;
+    hipEvent_t a = nullptr;
+    ProfScope(subkm_ctx *c, int k);
+    ~ProfScope();
 };
 
 // Scratch memory of a slot with at least `bytes` bytes (grows on demand).

@@ -368,6 +368,7 @@ template <int D>
 subkm_status launch_assign(subkm_ctx *ctx, int nitems, int item_base, const float *P,
                            const DevRun *runs, const Item *items, const float *C, int32_t *labels,
                            RunState *rs, double *ssepart) {
+    ProfScope ps(ctx, PK_ASSIGN);
     hipLaunchKernelGGL(k_assign<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
                        item_base, C, labels, rs, ssepart);
     SUBKM_LAUNCHED(ctx);
@@ -461,6 +462,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                 SUBKM_TRY(assign_dispatch(ctx, D.d, D.nitems, D.item0, P, d_runs, d_items, C,
                                           labels, d_rs, d_sse));
                 if (a < max_iter) {
+                    ProfScope ps(ctx, PK_UPDATE);
                     hipLaunchKernelGGL(k_update, dim3(D.nuitems), dim3(kUT), 0, s, P, d_runs,
                                        d_items, D.uitem0, C, labels, d_rs, tol);
                     SUBKM_LAUNCHED(ctx);
@@ -474,6 +476,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                 SUBKM_TRY(assign_dispatch(ctx, g.first, g.second.second, g.second.first, P,
                                           d_runs, d_items, C, labels, d_rs, d_sse));
             if (a < max_iter) {
+                ProfScope ps(ctx, PK_UPDATE);
                 hipLaunchKernelGGL(k_update, dim3(nu), dim3(kUT), 0, s, P, d_runs, d_items, u0, C,
                                    labels, d_rs, tol);
                 SUBKM_LAUNCHED(ctx);

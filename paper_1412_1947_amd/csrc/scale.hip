@@ -155,6 +155,7 @@ Plan plan_for(int64_t n, int d) {
 // or infinite.
 subkm_status minmax_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *mins,
                          float *maxs, int *flag) {
+    ProfScope ps(ctx, PK_SCALE);
     Plan p = plan_for(n, d);
     float *part = (float *)ctx_scratch(ctx, SC_MM_PART, sizeof(float) * 2 * p.blocks * d);
     if (!part) return SUBKM_ENOMEM;
@@ -186,6 +187,7 @@ subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, fl
         if (*h) return set_err(ctx, SUBKM_EINVAL, "input contains NaN or infinite values");
     }
     Plan p = plan_for(n, d);
+    ProfScope ps(ctx, PK_SCALE);
     if (p.narrow)
         hipLaunchKernelGGL(k_apply_narrow, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X,
                            n * d, d, p.stride, mins, maxs, S);

@@ -566,9 +566,11 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
                 SUBKM_LAUNCHED(ctx);
                 cur = rem1;
             }
+            ProfScope pk(ctx, PK_KEYS);
             hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kT), dyn_keys, s, S, d, cur, nrem, need, L,
                                colmax, keys, hist1, st, lm_t, vec4 ? 1 : 0);
             SUBKM_LAUNCHED(ctx);
+            ProfScope pc(ctx, PK_CAND);
             hipLaunchKernelGGL(k_cand, dim3(nb), dim3(kT), 0, s, keys, nrem, need, st, ckey, cpos,
                                hist2, blockcnt, blockoff, nb);
             SUBKM_LAUNCHED(ctx);
@@ -578,6 +580,7 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
         const bool track = !all && !fixed;
         // L_{t+1} reaches `landmarks` through k_keys (or the copy above) of the next round
         float *lm_next = nullptr;
+        ProfScope psc(ctx, PK_SCATTER);
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kT), dyn_scatter, s, S, d, cur, keys, nrem, st,
                            blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt, Lmin, L,
                            lm_next, &st->done3, need);
