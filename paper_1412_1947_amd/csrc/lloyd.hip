@@ -1,67 +1,85 @@
-// Lloyd's k-means for many independent runs at once (Sec. II Algorithm 1
-// step 4 inside every subcluster; Sec. I, Sec. V for the final run on the
-// local centers).
+// Lloyd's k-means for many independent runs (Sec. II Algorithm 1 step 4 in
+// every subcluster; Sec. I and Sec. V for the final run on the local
+// centers).
 //
-// One iteration is two launches over all runs that are still active:
+// Assignment (every form).  A tile of 256 points, one per thread, against the
+// run's centers staged in LDS.  Every thread tracks its two smallest float32
+// distances; when their gap is not larger than the rounding-error bound of
+// the float32 arithmetic, the point is re-assigned with binary64 distances
+// (attributes left to right, lowest center index on ties), one wavefront per
+// such point.  Labels are therefore those of exact arithmetic on the float32
+// inputs.  The objective uses the binary64 distance to the chosen center.
 //
-//   assign  work item = (run, tile of 256 points).  The run's centers are
-//           staged in LDS; every thread keeps one point in registers and
-//           tracks its two smallest float32 distances.  If their gap is not
-//           larger than the rounding-error bound of the float32 arithmetic,
-//           the point is re-assigned with binary64 distances, attributes left
-//           to right, lowest center index on ties -- so every label is the
-//           label of exact arithmetic on the float32 inputs.  The objective
-//           of the tile (binary64 distance to the chosen center) goes to a
-//           per-item slot.
-//   update  work item = (run, chunk of centers).  The block scans the run's
-//           labels, sums the points of its centers as 64-bit fixed point in
-//           LDS (exact, so the result does not depend on the order of the
-//           atomics), writes the new float32 centers (a center without
-//           points stays) and its largest center move; the run's last block
-//           decides convergence (largest move strictly below tol).
+// Update.  Every point adds its coordinates, as 64-bit fixed point scaled by
+// a per-run power of two, to its center's sum in LDS.  Integer sums are exact,
+// so the new centers do not depend on the order in which threads, blocks or
+// forms add them; a center without points stays.  The largest center move
+// (binary64) decides convergence (strictly below tol).
 //
-// A run's state moves ITER -> FINAL (converged: one more assignment gives
-// labels and objective for the returned centers) -> DONE.
+// Forms.
+//   batched  one cooperative persistent launch for all runs and all
+//            iterations.  Run r is split over G_r blocks (chosen by a
+//            largest-work-first schedule on the host); after every
+//            assignment the G_r blocks exchange their partial sums through
+//            global memory behind a per-run arrival counter, and each block
+//            forms the same new centers from them in the same order.
+//   plain    one run at a time: per iteration one assign+accumulate launch
+//            over the run's tiles and one finalize launch.
+// Runs whose k*d exceeds the LDS budget use launch-per-phase kernels for all
+// runs together (the update scans the labels per chunk of centers).
 #include "internal.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <map>
+#include <queue>
 #include <vector>
 
 #pragma clang fp contract(off)
 
 namespace {
 
-constexpr int kAT = 256;        // assign threads = points per work item
-constexpr int kUT = 256;        // update threads
-constexpr int kLdsFloats = 8192;  // centers staged per assign pass (32 KB)
-constexpr int kUpdLdsWords = 6144;  // int64 sums per update block (48 KB)
+constexpr int kAT = 256;            // threads per block = points per tile
+constexpr int kCF = 4096;           // floats of centers held in LDS (fused path)
+constexpr int kMaxK = 1024;         // centers per run in the fused path
+constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path)
+constexpr int kUpdLdsWords = 6144;  // int64 sums per block (scan-update path)
+constexpr long long kSpinLimit = 1ll << 24;
 
 enum : int32_t { PH_ITER = 0, PH_FINAL = 1, PH_DONE = 2 };
 
 struct DevRun {
     int64_t x_off, n, c_off, lab_off;
     int32_t d, k;
-    int32_t item0, nitems;    // assign items
-    int32_t uitem0, nuitems;  // update items
+    int32_t item0, nitems;    // objective slots (tiles or blocks of the run)
+    int32_t uitem0, nuitems;  // update items (center chunks)
     int32_t kcu;              // centers per update item
-    int32_t fix_shift;        // fixed-point exponent (set on the device)
+    int32_t fused;            // k*d fits the LDS sums
+    int64_t sum_off;          // offset of the run's int64 sums (k*d) + counts (k)
+    int64_t part_off;         // batched: offset of the run's exchange slots
+    int32_t G;                // batched: blocks of the run
+    int32_t pad;
 };
 
 struct RunState {
     int32_t phase;
     int32_t iters;
     uint32_t ucount;
-    uint32_t pad;
+    uint32_t arrive;
     unsigned long long shift_bits;
     unsigned long long rechecks;
+    uint32_t absmax_bits;
+    uint32_t pad;
 };
 
 struct Item {
     int32_t run;
     int32_t first;  // first point (assign) or first center (update)
+};
+
+struct Task {
+    int32_t run;
+    int32_t g;  // part g of the run's G blocks
 };
 
 // ---------------------------------------------------------------------------
@@ -78,7 +96,7 @@ __device__ __forceinline__ double dist64(const float *x, const float *c, int d) 
 
 // Binary64 argmin over all k centers of one point, by one wavefront: lanes
 // take centers lane, lane+64, ...; ties go to the lowest index.
-__device__ int32_t wave_argmin64(const float *x, const float *C, int d, int k, double *best_out) {
+__device__ int32_t wave_argmin64(const float *x, const float *C, int d, int k) {
     const int lane = threadIdx.x & 63;
     double best = INFINITY;
     int32_t bi = 0x7fffffff;
@@ -97,17 +115,15 @@ __device__ int32_t wave_argmin64(const float *x, const float *C, int d, int k, d
             bi = oi;
         }
     }
-    *best_out = best;
     return bi;
 }
 
 // Deterministic sum of one double per thread (fixed pairing tree).
-template <int NT>
 __device__ double block_sum_det(double v, double *sh) {
     sh[threadIdx.x] = v;
     __syncthreads();
 #pragma unroll
-    for (int s = NT / 2; s > 0; s >>= 1) {
+    for (int s = kAT / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
         __syncthreads();
     }
@@ -116,33 +132,362 @@ __device__ double block_sum_det(double v, double *sh) {
     return r;
 }
 
+__device__ double block_max(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = kAT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Fixed-point exponent s of a run: n * max|x| * 2^s stays below 2^61, so no
+// sum of the run can overflow int64.
+__device__ __forceinline__ int fix_shift_of(uint32_t absmax_bits, int64_t n) {
+    float m = __uint_as_float(absmax_bits);
+    int e = 0;
+    if (m > 0.0f) frexpf(m, &e);  // m < 2^e
+    int lg = 0;
+    while ((1ll << lg) < n + 1) ++lg;
+    return 61 - e - lg;
+}
+
+__device__ __forceinline__ long long to_fixed(float x, int s) {
+    return (long long)rint(ldexp((double)x, s));
+}
+
+// Float32 squared distances of this thread's point against centers sC[0..nc)
+// (row-major, d per row); keeps the two smallest values and the first index
+// of the smallest (strict <, centers in ascending order).
+template <int D>
+__device__ __forceinline__ void scan_centers(const float *x, const float *xg, const float *sC,
+                                             int c0, int nc, int d, float &b1, float &b2,
+                                             int32_t &i1) {
+    for (int c = 0; c < nc; ++c) {
+        const float *cc = sC + c * d;
+        float acc = 0.0f;
+        if (D > 0) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                float t = x[j] - cc[j];
+                acc = __builtin_fmaf(t, t, acc);
+            }
+        } else {
+            for (int j = 0; j < d; ++j) {
+                float t = xg[j] - cc[j];
+                acc = __builtin_fmaf(t, t, acc);
+            }
+        }
+        b2 = fminf(b2, fmaxf(acc, b1));
+        bool lt = acc < b1;
+        b1 = lt ? acc : b1;
+        i1 = lt ? c0 + c : i1;
+    }
+}
+
+// The gap between the two smallest float32 distances is certain iff it is
+// larger than the error bound of both: |D^ - D| <= gamma_{d+2} D (one
+// rounding per subtraction, one per FMA), with a safety factor of 2 and an
+// absolute term for results in the subnormal range.
+__device__ __forceinline__ bool certain_gap(float b1, float b2, int d, int k) {
+    const float gam = 2.0f * (float)(d + 2) * 5.9604645e-8f;
+    const float slack = (float)(2 * d + 2) * 2.8025969e-45f;
+    return k == 1 || (b2 - b1) > gam * (b1 + b2) + slack;
+}
+
+// Binary64 re-assignment of the uncertain points of a tile (listed in
+// s_list), one wavefront per point; results land in s_newlab[thread].
+__device__ void recheck_tile(const float *X, int64_t first, const float *Csrc, int d, int k,
+                             const int32_t *s_list, uint32_t nl, int32_t *s_newlab) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (uint32_t q = wave; q < nl; q += kAT / 64) {
+        const int t = s_list[q];
+        const int32_t w = wave_argmin64(X + (first + t) * d, Csrc, d, k);
+        if (lane == 0) s_newlab[t] = w;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Assignment.  D > 0: compile-time attribute count (point in registers);
-// D == 0: any d (point read from global memory).
+// LDS of the fused kernels.
+struct FusedLds {
+    float sC[kCF];
+    long long s_sum[kCF];
+    unsigned int s_cnt[kMaxK];
+    int32_t s_list[kAT];
+    int32_t s_newlab[kAT];
+    double s_red[kAT];
+    uint32_t s_nlist;
+    uint32_t s_flag;
+};
+
+// Assign one tile of up to 256 points of a run against all k centers held in
+// L.sC; optionally add the points to the fixed-point sums.  Returns the
+// binary64 objective contribution of this thread's point (0 if none).
+template <int D>
+__device__ double fused_tile(FusedLds &L, const float *X, int64_t first, int64_t n, int d, int k,
+                             int32_t *lab_out, bool accumulate, int shift,
+                             unsigned long long *rechecks) {
+    const int64_t i = first + threadIdx.x;
+    const bool valid = i < n;
+    const float *xg = X + (valid ? i : 0) * d;
+    float x[D > 0 ? D : 1];
+    if (D > 0) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[j] = xg[j];
+    }
+    __syncthreads();  // the previous tile is done with the recheck list
+    if (threadIdx.x == 0) L.s_nlist = 0;
+    __syncthreads();
+    float b1 = INFINITY, b2 = INFINITY;
+    int32_t i1 = 0;
+    scan_centers<D>(x, xg, L.sC, 0, k, d, b1, b2, i1);
+    const bool certain = certain_gap(b1, b2, d, k);
+    if (valid && !certain) L.s_list[atomicAdd(&L.s_nlist, 1u)] = threadIdx.x;
+    __syncthreads();
+    const uint32_t nl = L.s_nlist;
+    if (nl) {
+        recheck_tile(X, first, L.sC, d, k, L.s_list, nl, L.s_newlab);
+        __syncthreads();
+        if (valid && !certain) i1 = L.s_newlab[threadIdx.x];
+        if (threadIdx.x == 0) atomicAdd(rechecks, (unsigned long long)nl);
+    }
+    double obj = 0.0;
+    if (valid) {
+        lab_out[i] = i1;
+        obj = dist64(xg, L.sC + i1 * d, d);
+        if (accumulate) {
+            atomicAdd(&L.s_cnt[i1], 1u);
+            long long *row = L.s_sum + i1 * d;
+            if (D > 0) {
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    atomicAdd((unsigned long long *)&row[j], (unsigned long long)to_fixed(x[j], shift));
+            } else {
+                for (int j = 0; j < d; ++j)
+                    atomicAdd((unsigned long long *)&row[j], (unsigned long long)to_fixed(xg[j], shift));
+            }
+        }
+    }
+    return obj;
+}
+
+// New centers from the sums in L.s_sum / L.s_cnt: writes L.sC (and Cglob if
+// non-null) and returns the largest binary64 center move.
+__device__ double centers_from_sums(FusedLds &L, int d, int k, int shift, float *Cglob) {
+    double mx = 0.0;
+    for (int c = threadIdx.x; c < k; c += kAT) {
+        const unsigned int cnt = L.s_cnt[c];
+        double mv2 = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const float old = L.sC[c * d + j];
+            const double nv = cnt ? ldexp((double)L.s_sum[c * d + j], -shift) / (double)cnt : (double)old;
+            const double q = nv - (double)old;
+            mv2 = mv2 + q * q;
+            const float f = (float)nv;
+            L.sC[c * d + j] = f;
+            if (Cglob) Cglob[c * d + j] = f;
+        }
+        mx = fmax(mx, sqrt(mv2));
+    }
+    return block_max(mx, L.s_red);
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: persistent, cooperative.  Block b works through its tasks
+// task_off[b] .. task_off[b+1]-1 in order; every task is one part of a run.
+template <int D>
+__global__ __launch_bounds__(kAT) void k_lloyd_persist(
+    const float *__restrict__ P, const DevRun *__restrict__ runs, const Task *__restrict__ tasks,
+    const int32_t *__restrict__ task_off, float *C, int32_t *labels, RunState *rstate,
+    long long *parts, double *objpart, int max_iter, double tol, int *err) {
+    __shared__ FusedLds L;
+    for (int ti = task_off[blockIdx.x]; ti < task_off[blockIdx.x + 1]; ++ti) {
+        const Task tk = tasks[ti];
+        const DevRun R = runs[tk.run];
+        RunState *rs = rstate + tk.run;
+        const int d = D > 0 ? D : R.d;
+        const int k = R.k;
+        const int kd = k * d;
+        const int G = R.G;
+        const int shift = fix_shift_of(rs->absmax_bits, R.n);
+        // the run's points are split over its G blocks in whole tiles
+        const int64_t tiles = (R.n + kAT - 1) / kAT;
+        const int64_t t0 = tiles * tk.g / G, t1 = tiles * (tk.g + 1) / G;
+        const float *X = P + R.x_off;
+        int32_t *lab = labels + R.lab_off;
+        float *Cr = C + R.c_off;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kd; e += kAT) L.sC[e] = Cr[e];
+        int it = 0;
+        bool converged = false;
+        for (;;) {
+            const bool last = it == max_iter || converged;
+            for (int e = threadIdx.x; e < kd; e += kAT) L.s_sum[e] = 0;
+            for (int c = threadIdx.x; c < k; c += kAT) L.s_cnt[c] = 0;
+            __syncthreads();
+            for (int64_t t = t0; t < t1; ++t) {
+                const double obj = fused_tile<D>(L, X, t * kAT, R.n, d, k, lab, !last, shift, &rs->rechecks);
+                if (last) {
+                    // objective per tile, summed over tiles in order by the
+                    // finalize kernel: the same rounding as the plain form
+                    const double tot = block_sum_det(obj, L.s_red);
+                    if (threadIdx.x == 0) objpart[R.item0 + t] = tot;
+                }
+            }
+            if (last) {
+                if (threadIdx.x == 0 && tk.g == 0) rs->iters = it;
+                break;
+            }
+            __syncthreads();
+            if (G > 1) {
+                // publish this block's sums, wait for the run's other blocks,
+                // then add all parts in block order (exact integer sums)
+                long long *slot = parts + R.part_off + ((int64_t)(it & 1) * G + tk.g) * (kd + k);
+                for (int e = threadIdx.x; e < kd; e += kAT) slot[e] = L.s_sum[e];
+                for (int c = threadIdx.x; c < k; c += kAT) slot[kd + c] = (long long)L.s_cnt[c];
+                __threadfence();
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    atomicAdd(&rs->arrive, 1u);
+                    const uint32_t target = (uint32_t)G * (uint32_t)(it + 1);
+                    long long spins = 0;
+                    while (__hip_atomic_load(&rs->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > kSpinLimit) {
+                            atomicOr(err, 1);
+                            break;
+                        }
+                    }
+                    __threadfence();
+                }
+                __syncthreads();
+                const long long *base = parts + R.part_off + (int64_t)(it & 1) * G * (kd + k);
+                for (int e = threadIdx.x; e < kd; e += kAT) {
+                    long long a = 0;
+                    for (int q = 0; q < G; ++q) a += base[(int64_t)q * (kd + k) + e];
+                    L.s_sum[e] = a;
+                }
+                for (int c = threadIdx.x; c < k; c += kAT) {
+                    long long a = 0;
+                    for (int q = 0; q < G; ++q) a += base[(int64_t)q * (kd + k) + kd + c];
+                    L.s_cnt[c] = (unsigned int)a;
+                }
+                __syncthreads();
+            }
+            const double shift_max = centers_from_sums(L, d, k, shift, tk.g == 0 ? Cr : nullptr);
+            ++it;
+            converged = shift_max < tol;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain form, fused path: assign + accumulate over a run's tiles (one item
+// per tile), sums flushed to the run's global accumulators with integer
+// atomics.
+template <int D>
+__global__ __launch_bounds__(kAT) void k_assign_acc(const float *__restrict__ P,
+                                                    const DevRun *__restrict__ runs,
+                                                    const Item *__restrict__ items, int item_base,
+                                                    const float *__restrict__ C, int32_t *labels,
+                                                    RunState *rstate, double *objpart,
+                                                    long long *gsum, int accumulate) {
+    __shared__ FusedLds L;
+    const Item itm = items[item_base + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    RunState *rs = rstate + itm.run;
+    const int32_t ph = rs->phase;
+    if (ph == PH_DONE) return;
+    const bool acc = accumulate && ph == PH_ITER;
+    const int d = D > 0 ? D : R.d;
+    const int k = R.k, kd = k * d;
+    const int shift = fix_shift_of(rs->absmax_bits, R.n);
+    for (int e = threadIdx.x; e < kd; e += kAT) {
+        L.sC[e] = C[R.c_off + e];
+        L.s_sum[e] = 0;
+    }
+    for (int c = threadIdx.x; c < k; c += kAT) L.s_cnt[c] = 0;
+    __syncthreads();
+    const double obj = fused_tile<D>(L, P + R.x_off, itm.first, R.n, d, k, labels + R.lab_off, acc,
+                                     shift, &rs->rechecks);
+    const double tot = block_sum_det(obj, L.s_red);
+    if (threadIdx.x == 0) objpart[item_base + blockIdx.x] = tot;
+    if (!acc) return;
+    long long *gs = gsum + R.sum_off;
+    for (int c = threadIdx.x; c < k; c += kAT)
+        if (L.s_cnt[c]) atomicAdd((unsigned long long *)&gs[kd + c], (unsigned long long)L.s_cnt[c]);
+    for (int e = threadIdx.x; e < kd; e += kAT)
+        if (L.s_cnt[e / d]) atomicAdd((unsigned long long *)&gs[e], (unsigned long long)L.s_sum[e]);
+}
+
+// Fused path, per iteration: new centers of run run0 + blockIdx.x from its
+// global sums, which the block zeroes for the next iteration.
+__global__ __launch_bounds__(kAT) void k_update_fin(const DevRun *__restrict__ runs, int run0,
+                                                    float *C, RunState *rstate, long long *gsum,
+                                                    double tol) {
+    __shared__ FusedLds L;
+    const int r = run0 + blockIdx.x;
+    const DevRun R = runs[r];
+    RunState *rs = rstate + r;
+    const int32_t ph = rs->phase;
+    if (ph == PH_DONE) return;
+    if (ph == PH_FINAL) {
+        // the assignment that just ran was the last one of this run
+        if (threadIdx.x == 0) rs->phase = PH_DONE;
+        return;
+    }
+    const int d = R.d, k = R.k, kd = k * d;
+    const int shift = fix_shift_of(rs->absmax_bits, R.n);
+    long long *gs = gsum + R.sum_off;
+    for (int e = threadIdx.x; e < kd; e += kAT) {
+        L.sC[e] = C[R.c_off + e];
+        L.s_sum[e] = gs[e];
+        gs[e] = 0;
+    }
+    for (int c = threadIdx.x; c < k; c += kAT) {
+        L.s_cnt[c] = (unsigned int)gs[kd + c];
+        gs[kd + c] = 0;
+    }
+    __syncthreads();
+    const double mx = centers_from_sums(L, d, k, shift, C + R.c_off);
+    if (threadIdx.x == 0) {
+        rs->iters += 1;
+        rs->phase = mx < tol ? PH_FINAL : PH_ITER;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scan-update path (k*d beyond the LDS budget): assign without accumulation,
+// centers staged through LDS in chunks, rechecks against global memory.
 template <int D>
 __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
                                                 const DevRun *__restrict__ runs,
                                                 const Item *__restrict__ items, int item_base,
                                                 const float *__restrict__ C, int32_t *labels,
-                                                RunState *rstate, double *ssepart) {
+                                                RunState *rstate, double *objpart) {
     __shared__ float sC[kLdsFloats];
     __shared__ int32_t s_list[kAT];
+    __shared__ int32_t s_newlab[kAT];
     __shared__ uint32_t s_nlist;
     __shared__ double s_red[kAT];
-    __shared__ int32_t s_newlab[kAT];
-    const Item it = items[item_base + blockIdx.x];
-    const DevRun R = runs[it.run];
-    if (rstate[it.run].phase == PH_DONE) return;
+    const Item itm = items[item_base + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    if (rstate[itm.run].phase == PH_DONE) return;
     const int d = D > 0 ? D : R.d;
     const int k = R.k;
-    const int64_t i = it.first + threadIdx.x;
+    const int64_t i = itm.first + threadIdx.x;
     const bool valid = i < R.n;
-    const float *xg = P + R.x_off + (valid ? i : 0) * d;
+    const float *X = P + R.x_off;
+    const float *xg = X + (valid ? i : 0) * d;
     const float *Cr = C + R.c_off;
     float x[D > 0 ? D : 1];
     if (D > 0) {
 #pragma unroll
-        for (int j = 0; j < D; ++j) x[j] = valid ? xg[j] : 0.0f;
+        for (int j = 0; j < D; ++j) x[j] = xg[j];
     }
     if (threadIdx.x == 0) s_nlist = 0;
     float b1 = INFINITY, b2 = INFINITY;
@@ -153,48 +498,13 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
         __syncthreads();
         for (int e = threadIdx.x; e < nc * d; e += kAT) sC[e] = Cr[(int64_t)c0 * d + e];
         __syncthreads();
-        for (int c = 0; c < nc; ++c) {
-            const float *cc = sC + c * d;
-            float acc = 0.0f;
-            if (D > 0) {
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    float t = x[j] - cc[j];
-                    acc = __builtin_fmaf(t, t, acc);
-                }
-            } else {
-                for (int j = 0; j < d; ++j) {
-                    float t = xg[j] - cc[j];
-                    acc = __builtin_fmaf(t, t, acc);
-                }
-            }
-            // keep the two smallest; strict < keeps the lowest index first
-            b2 = fminf(b2, fmaxf(acc, b1));
-            bool lt = acc < b1;
-            b1 = lt ? acc : b1;
-            i1 = lt ? c0 + c : i1;
-        }
+        scan_centers<D>(x, xg, sC, c0, nc, d, b1, b2, i1);
     }
-    // certain iff the gap exceeds the float32 error bound of both distances:
-    // |D^ - D| <= gamma_{d+2} D (one rounding per subtraction, per FMA)
-    const float gam = 2.0f * (float)(d + 2) * 5.9604645e-8f;
-    const float slack = (float)(2 * d + 2) * 1.4012985e-45f * 2.0f;
-    bool certain = (k == 1) || ((b2 - b1) > gam * (b1 + b2) + slack);
-    if (valid && !certain) {
-        uint32_t s = atomicAdd(&s_nlist, 1u);
-        s_list[s] = threadIdx.x;
-    }
+    const bool certain = certain_gap(b1, b2, d, k);
+    if (valid && !certain) s_list[atomicAdd(&s_nlist, 1u)] = threadIdx.x;
     __syncthreads();
-    // binary64 re-assignment of the uncertain points, one wavefront per point
     const uint32_t nl = s_nlist;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (uint32_t q = wave; q < nl; q += kAT / 64) {
-        const int t = s_list[q];
-        const float *xq = P + R.x_off + (it.first + t) * d;
-        double bv;
-        int32_t w = wave_argmin64(xq, Cr, d, k, &bv);
-        if (lane == 0) s_newlab[t] = w;
-    }
+    recheck_tile(X, itm.first, Cr, d, k, s_list, nl, s_newlab);
     __syncthreads();
     if (valid && !certain) i1 = s_newlab[threadIdx.x];
     double obj = 0.0;
@@ -202,56 +512,51 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
         labels[R.lab_off + i] = i1;
         obj = dist64(xg, Cr + (int64_t)i1 * d, d);
     }
-    double tot = block_sum_det<kAT>(obj, s_red);
+    const double tot = block_sum_det(obj, s_red);
     if (threadIdx.x == 0) {
-        ssepart[item_base + blockIdx.x] = tot;
-        if (nl) atomicAdd(&rstate[it.run].rechecks, (unsigned long long)nl);
+        objpart[item_base + blockIdx.x] = tot;
+        if (nl) atomicAdd(&rstate[itm.run].rechecks, (unsigned long long)nl);
     }
 }
 
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ long long to_fixed(float x, int s) {
-    return (long long)rint(ldexp((double)x, s));
-}
-
-// Update of one chunk of centers of one run.
-__global__ __launch_bounds__(kUT) void k_update(const float *__restrict__ P,
-                                                const DevRun *__restrict__ runs,
-                                                const Item *__restrict__ items, int item_base,
-                                                float *C, const int32_t *__restrict__ labels,
-                                                RunState *rstate, double tol) {
+// Scan-update path: the block owns a chunk of centers of one run, scans the
+// run's labels and adds the points of its centers.
+__global__ __launch_bounds__(kAT) void k_update_scan(const float *__restrict__ P,
+                                                     const DevRun *__restrict__ runs,
+                                                     const Item *__restrict__ items, int item_base,
+                                                     float *C, const int32_t *__restrict__ labels,
+                                                     RunState *rstate, double tol) {
     __shared__ long long s_sum[kUpdLdsWords];
     __shared__ unsigned int s_cnt[1024];
-    __shared__ int32_t s_pts[kUT];
-    __shared__ int32_t s_lab[kUT];
+    __shared__ int32_t s_pts[kAT];
+    __shared__ int32_t s_lab[kAT];
     __shared__ uint32_t s_np, s_last;
-    __shared__ double s_red[kUT];
-    const Item it = items[item_base + blockIdx.x];
-    const DevRun R = runs[it.run];
-    RunState *rs = rstate + it.run;
+    __shared__ double s_red[kAT];
+    const Item itm = items[item_base + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    RunState *rs = rstate + itm.run;
     const int32_t ph = rs->phase;
     if (ph == PH_DONE) return;
     if (ph == PH_FINAL) {
-        // the assignment that just ran was the last one of this run
-        if (it.first == 0 && threadIdx.x == 0) rs->phase = PH_DONE;
+        if (itm.first == 0 && threadIdx.x == 0) rs->phase = PH_DONE;
         return;
     }
     const int d = R.d;
-    const int c0 = it.first;
+    const int c0 = itm.first;
     const int nc = R.kcu < R.k - c0 ? R.kcu : R.k - c0;
-    const int s = R.fix_shift;
-    for (int e = threadIdx.x; e < nc * d; e += kUT) s_sum[e] = 0;
-    for (int c = threadIdx.x; c < nc; c += kUT) s_cnt[c] = 0;
+    const int s = fix_shift_of(rs->absmax_bits, R.n);
+    for (int e = threadIdx.x; e < nc * d; e += kAT) s_sum[e] = 0;
+    for (int c = threadIdx.x; c < nc; c += kAT) s_cnt[c] = 0;
     const float *X = P + R.x_off;
     const int32_t *lab = labels + R.lab_off;
-    for (int64_t b = 0; b < R.n; b += kUT) {
+    for (int64_t b = 0; b < R.n; b += kAT) {
         if (threadIdx.x == 0) s_np = 0;
         __syncthreads();
-        int64_t i = b + threadIdx.x;
+        const int64_t i = b + threadIdx.x;
         if (i < R.n) {
-            int32_t l = lab[i] - c0;
+            const int32_t l = lab[i] - c0;
             if (l >= 0 && l < nc) {
-                uint32_t q = atomicAdd(&s_np, 1u);
+                const uint32_t q = atomicAdd(&s_np, 1u);
                 s_pts[q] = (int32_t)threadIdx.x;
                 s_lab[q] = l;
                 atomicAdd(&s_cnt[l], 1u);
@@ -259,51 +564,41 @@ __global__ __launch_bounds__(kUT) void k_update(const float *__restrict__ P,
         }
         __syncthreads();
         const int np = (int)s_np;
-        for (int e = threadIdx.x; e < np * d; e += kUT) {
-            int m = e / d, j = e - m * d;
-            float v = X[(b + s_pts[m]) * d + j];
-            atomicAdd((unsigned long long *)&s_sum[s_lab[m] * d + j],
-                      (unsigned long long)to_fixed(v, s));
+        for (int e = threadIdx.x; e < np * d; e += kAT) {
+            const int m = e / d, j = e - m * d;
+            const float v = X[(b + s_pts[m]) * d + j];
+            atomicAdd((unsigned long long *)&s_sum[s_lab[m] * d + j], (unsigned long long)to_fixed(v, s));
         }
         __syncthreads();
     }
-    // new centers; squared moves go back into the sum slots as doubles
     float *Cr = C + R.c_off + (int64_t)c0 * d;
-    for (int e = threadIdx.x; e < nc * d; e += kUT) {
-        int c = e / d;
-        unsigned int cnt = s_cnt[c];
-        float old = Cr[e];
-        double nv = cnt ? ldexp((double)s_sum[e], -s) / (double)cnt : (double)old;
-        double mv = nv - (double)old;
+    for (int e = threadIdx.x; e < nc * d; e += kAT) {
+        const int c = e / d;
+        const unsigned int cnt = s_cnt[c];
+        const float old = Cr[e];
+        const double nv = cnt ? ldexp((double)s_sum[e], -s) / (double)cnt : (double)old;
+        const double mv = nv - (double)old;
         Cr[e] = (float)nv;
         s_sum[e] = __double_as_longlong(mv * mv);
     }
     __syncthreads();
     double mx = 0.0;
-    for (int c = threadIdx.x; c < nc; c += kUT) {
+    for (int c = threadIdx.x; c < nc; c += kAT) {
         double a = 0.0;
         for (int j = 0; j < d; ++j) a = a + __longlong_as_double(s_sum[c * d + j]);
         mx = fmax(mx, sqrt(a));
     }
-    // max over the block, then over the run (non-negative doubles order as
-    // their bit patterns)
-    s_red[threadIdx.x] = mx;
-    __syncthreads();
-    for (int st = kUT / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) s_red[threadIdx.x] = fmax(s_red[threadIdx.x], s_red[threadIdx.x + st]);
-        __syncthreads();
-    }
+    mx = block_max(mx, s_red);
     if (threadIdx.x == 0) {
-        atomicMax(&rs->shift_bits, (unsigned long long)__double_as_longlong(s_red[0]));
+        atomicMax(&rs->shift_bits, (unsigned long long)__double_as_longlong(mx));
         __threadfence();
         s_last = atomicAdd(&rs->ucount, 1u) == (uint32_t)R.nuitems - 1;
         if (s_last) {
             __threadfence();
-            unsigned long long sb = __hip_atomic_load(&rs->shift_bits, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-            double shift = __longlong_as_double((long long)sb);
+            const unsigned long long sb =
+                __hip_atomic_load(&rs->shift_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             rs->iters += 1;
-            rs->phase = shift < tol ? PH_FINAL : PH_ITER;
+            rs->phase = __longlong_as_double((long long)sb) < tol ? PH_FINAL : PH_ITER;
             rs->shift_bits = 0;
             rs->ucount = 0;
         }
@@ -311,36 +606,42 @@ __global__ __launch_bounds__(kUT) void k_update(const float *__restrict__ P,
 }
 
 // ---------------------------------------------------------------------------
-// Per-run setup: fixed-point exponent from the largest |x| of the run, state.
-__global__ __launch_bounds__(256) void k_setup(const float *__restrict__ P, DevRun *runs,
-                                               RunState *rstate) {
+__global__ void k_state_init(RunState *rstate, int R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    RunState z{};
+    z.phase = PH_ITER;
+    rstate[r] = z;
+}
+
+// largest |x| of every run (grid: chunks x runs)
+__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ P,
+                                                const DevRun *__restrict__ runs, RunState *rstate) {
     __shared__ float s_m[256];
-    DevRun &R = runs[blockIdx.x];
+    const DevRun R = runs[blockIdx.y];
     const float *X = P + R.x_off;
     const int64_t tot = R.n * R.d;
     float m = 0.0f;
-    for (int64_t e = threadIdx.x; e < tot; e += 256) m = fmaxf(m, fabsf(X[e]));
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+        m = fmaxf(m, fabsf(X[e]));
     s_m[threadIdx.x] = m;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
         if (threadIdx.x < st) s_m[threadIdx.x] = fmaxf(s_m[threadIdx.x], s_m[threadIdx.x + st]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        int e = 0;
-        if (s_m[0] > 0.0f) frexpf(s_m[0], &e);  // max|x| < 2^e
-        int lg = 0;
-        while ((1ll << lg) < R.n + 1) ++lg;
-        // n * 2^(e + s) <= 2^62 keeps every sum inside int64
-        R.fix_shift = 61 - e - lg;
-        RunState z{};
-        z.phase = PH_ITER;
-        rstate[blockIdx.x] = z;
-    }
+    if (threadIdx.x == 0 && s_m[0] > 0.0f)
+        atomicMax(&rstate[blockIdx.y].absmax_bits, __float_as_uint(s_m[0]));
 }
 
-// first k points of every run as its starting centers (init 1), or the
-// strided start C[q] = X[q * floor(n / k)] (init 2)
+__global__ void k_fill_i64(long long *a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
+}
+
+// first k points of every run as its starting centers (mode 1), or the
+// strided start C[q] = X[q * floor(n / k)] (mode 2)
 __global__ void k_init(const float *__restrict__ P, const DevRun *__restrict__ runs, float *C,
                        int mode) {
     const DevRun R = runs[blockIdx.y];
@@ -348,47 +649,148 @@ __global__ void k_init(const float *__restrict__ P, const DevRun *__restrict__ r
     const int64_t stride = mode == 2 ? R.n / R.k : 1;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t q = e / R.d, j = e - q * R.d;
+        const int64_t q = e / R.d, j = e - q * R.d;
         C[R.c_off + e] = P[R.x_off + q * stride * R.d + j];
     }
 }
 
 __global__ void k_finalize(const DevRun *__restrict__ runs, const RunState *__restrict__ rstate,
-                           const double *__restrict__ ssepart, int R, int32_t *iters, double *sse) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
+                           const double *__restrict__ objpart, int R, int32_t *iters, double *sse,
+                           unsigned long long *rechecks) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
     const DevRun D = runs[r];
     double s = 0.0;
-    for (int q = 0; q < D.nitems; ++q) s = s + ssepart[D.item0 + q];
+    for (int q = 0; q < D.nitems; ++q) s = s + objpart[D.item0 + q];
     sse[r] = s;
     if (iters) iters[r] = rstate[r].iters;
+    if (rechecks) atomicAdd(rechecks, rstate[r].rechecks);
+}
+
+// ---------------------------------------------------------------------------
+#define SUBKM_DISPATCH_D(d, FN, ...)                                                      \
+    switch (d) {                                                                          \
+        case 1: return FN<1>(__VA_ARGS__);                                                \
+        case 2: return FN<2>(__VA_ARGS__);                                                \
+        case 4: return FN<4>(__VA_ARGS__);                                                \
+        case 8: return FN<8>(__VA_ARGS__);                                                \
+        case 16: return FN<16>(__VA_ARGS__);                                              \
+        case 32: return FN<32>(__VA_ARGS__);                                              \
+        case 64: return FN<64>(__VA_ARGS__);                                              \
+        case 128: return FN<128>(__VA_ARGS__);                                            \
+        default: return FN<0>(__VA_ARGS__);                                               \
+    }
+
+template <int D>
+subkm_status launch_assign_acc(subkm_ctx *ctx, int nitems, int item_base, const float *P,
+                               const DevRun *runs, const Item *items, const float *C,
+                               int32_t *labels, RunState *rs, double *objpart, long long *gsum,
+                               int accumulate) {
+    ProfScope ps(ctx, PK_ASSIGN);
+    hipLaunchKernelGGL(k_assign_acc<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
+                       item_base, C, labels, rs, objpart, gsum, accumulate);
+    SUBKM_LAUNCHED(ctx);
+    return SUBKM_OK;
 }
 
 template <int D>
 subkm_status launch_assign(subkm_ctx *ctx, int nitems, int item_base, const float *P,
                            const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                           RunState *rs, double *ssepart) {
+                           RunState *rs, double *objpart) {
     ProfScope ps(ctx, PK_ASSIGN);
     hipLaunchKernelGGL(k_assign<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
-                       item_base, C, labels, rs, ssepart);
+                       item_base, C, labels, rs, objpart);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
 
-subkm_status assign_dispatch(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
-                             const DevRun *runs, const Item *items, const float *C,
-                             int32_t *labels, RunState *rs, double *ssepart) {
+template <int D>
+subkm_status launch_persist(subkm_ctx *ctx, int blocks, const float *P, const DevRun *runs,
+                            const Task *tasks, const int32_t *task_off, float *C, int32_t *labels,
+                            RunState *rs, long long *parts, double *objpart, int max_iter,
+                            double tol, int *err) {
+    ProfScope ps(ctx, PK_LLOYD_FUSED);
+    void *args[] = {(void *)&P,      (void *)&runs,  (void *)&tasks,   (void *)&task_off,
+                    (void *)&C,      (void *)&labels, (void *)&rs,     (void *)&parts,
+                    (void *)&objpart, (void *)&max_iter, (void *)&tol, (void *)&err};
+    SUBKM_HIP(ctx, hipLaunchCooperativeKernel((const void *)k_lloyd_persist<D>, dim3(blocks),
+                                              dim3(kAT), args, 0, ctx->stream));
+    return SUBKM_OK;
+}
+
+template <int D>
+int persist_occupancy() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lloyd_persist<D>, kAT, 0) != hipSuccess) {
+        hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+
+int persist_occupancy_d(int d) { SUBKM_DISPATCH_D(d, persist_occupancy); }
+
+subkm_status assign_acc_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
+                          const DevRun *runs, const Item *items, const float *C, int32_t *labels,
+                          RunState *rs, double *objpart, long long *gsum, int accumulate) {
     if (nitems <= 0) return SUBKM_OK;
-    switch (d) {
-        case 1: return launch_assign<1>(ctx, nitems, item_base, P, runs, items, C, labels, rs, ssepart);
-        case 2: return launch_assign<2>(ctx, nitems, item_base, P, runs, items, C, labels, rs, ssepart);
-        case 4: return launch_assign<4>(ctx, nitems, item_base, P, runs, items, C, labels, rs, ssepart);
-        case 8: return launch_assign<8>(ctx, nitems, item_base, P, runs, items, C, labels, rs, ssepart);
-        case 16: return launch_assign<16>(ctx, nitems, item_base, P, runs, items, C, labels, rs, ssepart);
-        case 32: return launch_assign<32>(ctx, nitems, item_base, P, runs, items, C, labels, rs, ssepart);
-        case 64: return launch_assign<64>(ctx, nitems, item_base, P, runs, items, C, labels, rs, ssepart);
-        case 128: return launch_assign<128>(ctx, nitems, item_base, P, runs, items, C, labels, rs, ssepart);
-        default: return launch_assign<0>(ctx, nitems, item_base, P, runs, items, C, labels, rs, ssepart);
+    SUBKM_DISPATCH_D(d, launch_assign_acc, ctx, nitems, item_base, P, runs, items, C, labels, rs,
+                     objpart, gsum, accumulate);
+}
+
+subkm_status assign_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
+                      const DevRun *runs, const Item *items, const float *C, int32_t *labels,
+                      RunState *rs, double *objpart) {
+    if (nitems <= 0) return SUBKM_OK;
+    SUBKM_DISPATCH_D(d, launch_assign, ctx, nitems, item_base, P, runs, items, C, labels, rs,
+                     objpart);
+}
+
+subkm_status persist_d(subkm_ctx *ctx, int d, int blocks, const float *P, const DevRun *runs,
+                       const Task *tasks, const int32_t *task_off, float *C, int32_t *labels,
+                       RunState *rs, long long *parts, double *objpart, int max_iter, double tol,
+                       int *err) {
+    SUBKM_DISPATCH_D(d, launch_persist, ctx, blocks, P, runs, tasks, task_off, C, labels, rs, parts,
+                     objpart, max_iter, tol, err);
+}
+
+// Largest-work-first schedule of the runs of one attribute count over
+// `blocks` persistent blocks.  Run r gets G_r blocks (about its share of the
+// total work, at most one per tile) and starts when its G_r least-loaded
+// blocks are free.  Every block's task list follows the global assignment
+// order, so the per-run barriers cannot wait on each other in a cycle.
+void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blocks,
+              bool exchange, std::vector<int32_t> &G, std::vector<std::vector<Task>> &per_block) {
+    std::vector<int> order(rr);
+    auto work = [&](int r) { return (double)dr[r].n * dr[r].k * dr[r].d; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    double total = 0;
+    for (int r : order) total += work(r);
+    const double target = total / blocks;
+    using Slot = std::pair<double, int>;  // (finish time, block)
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> pq;
+    for (int b = 0; b < blocks; ++b) pq.push({0.0, b});
+    per_block.assign(blocks, {});
+    for (int r : order) {
+        const int64_t tiles = (dr[r].n + kAT - 1) / kAT;
+        int64_t g = std::llround(work(r) / std::max(target, 1.0));
+        // with a per-iteration exchange, every block reads the G partial sums:
+        // keep G small and at least two tiles per block
+        const int64_t gmax = exchange ? std::min<int64_t>(16, std::max<int64_t>(1, tiles / 2)) : tiles;
+        g = std::max<int64_t>(1, std::min<int64_t>({g, gmax, (int64_t)blocks}));
+        G[r] = (int32_t)g;
+        std::vector<Slot> take;
+        double start = 0;
+        for (int64_t q = 0; q < g; ++q) {
+            take.push_back(pq.top());
+            pq.pop();
+            start = std::max(start, take.back().first);
+        }
+        const double fin = start + work(r) / g;
+        for (int64_t q = 0; q < g; ++q) {
+            per_block[take[q].second].push_back(Task{r, (int32_t)q});
+            pq.push({fin, take[q].second});
+        }
     }
 }
 
@@ -400,53 +802,129 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                         int init_mode) {
     (void)precision;
     hipStream_t s = ctx->stream;
-    // host plan: order the assign items by attribute count so that one launch
-    // covers all runs of one d; update items follow the run order
     std::vector<DevRun> dr(R);
-    std::map<int, std::vector<int>> by_d;
-    for (int r = 0; r < R; ++r) by_d[runs[r].d].push_back(r);
+    bool all_fused = true;
+    int64_t sum_words = 0;
+    for (int r = 0; r < R; ++r) {
+        const subkm_run &u = runs[r];
+        DevRun &D = dr[r];
+        std::memset(&D, 0, sizeof D);
+        D.x_off = u.x_off;
+        D.n = u.n;
+        D.c_off = u.c_off;
+        D.lab_off = u.lab_off;
+        D.d = u.d;
+        D.k = u.k;
+        D.fused = ((int64_t)u.k * u.d <= kCF && u.k <= kMaxK) ? 1 : 0;
+        all_fused = all_fused && D.fused;
+        D.sum_off = sum_words;
+        if (D.fused) sum_words += (int64_t)u.k * u.d + u.k;
+    }
+    std::vector<int> ds;  // distinct attribute counts
+    for (int r = 0; r < R; ++r) ds.push_back(dr[r].d);
+    std::sort(ds.begin(), ds.end());
+    ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
+
+    const bool batched = form == SUBKM_FORM_BATCHED && all_fused;
     std::vector<Item> items;
-    std::vector<std::pair<int, std::pair<int, int>>> groups;  // d -> (item0, count)
-    for (auto &g : by_d) {
-        int g0 = (int)items.size();
-        for (int r : g.second) {
-            const subkm_run &u = runs[r];
+    std::vector<Task> tasks;
+    std::vector<int32_t> task_off;
+    std::vector<std::pair<int, std::pair<int, int>>> groups;  // d -> (first block, blocks)
+    int64_t part_words = 0;
+    int n_obj = 0;
+    if (batched) {
+        // one persistent launch per attribute count, at most the co-resident capacity
+        int block_base = 0;
+        task_off.push_back(0);
+        for (int dv : ds) {
+            std::vector<int> rr;
+            int64_t tiles = 0;
+            for (int r = 0; r < R; ++r)
+                if (dr[r].d == dv) {
+                    rr.push_back(r);
+                    tiles += (dr[r].n + kAT - 1) / kAT;
+                }
+            const int occ = std::max(1, persist_occupancy_d(dv));
+            const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->cu_count * occ, tiles));
+            std::vector<int32_t> G(R, 1);
+            std::vector<std::vector<Task>> pb;
+            schedule(rr, dr, blocks, max_iter > 0, G, pb);
+            for (int r : rr) {
+                DevRun &D = dr[r];
+                D.G = G[r];
+                D.nitems = (int32_t)((D.n + kAT - 1) / kAT);
+                D.part_off = part_words;
+                if (G[r] > 1) part_words += 2ll * G[r] * ((int64_t)D.k * D.d + D.k);
+            }
+            for (int b = 0; b < blocks; ++b) {
+                for (const Task &t : pb[b]) tasks.push_back(t);
+                task_off.push_back((int32_t)tasks.size());
+            }
+            groups.push_back({dv, {block_base, blocks}});
+            block_base += blocks;
+        }
+        for (int r = 0; r < R; ++r) {
+            dr[r].item0 = n_obj;
+            n_obj += dr[r].nitems;
+        }
+    } else {
+        for (int r = 0; r < R; ++r) {
             DevRun &D = dr[r];
-            D.x_off = u.x_off;
-            D.n = u.n;
-            D.c_off = u.c_off;
-            D.lab_off = u.lab_off;
-            D.d = u.d;
-            D.k = u.k;
             D.item0 = (int)items.size();
-            for (int64_t f = 0; f < u.n; f += kAT) items.push_back(Item{r, (int32_t)f});
+            for (int64_t f = 0; f < D.n; f += kAT) items.push_back(Item{r, (int32_t)f});
             D.nitems = (int)items.size() - D.item0;
         }
-        groups.push_back({g.first, {g0, (int)items.size() - g0}});
-    }
-    const int n_assign = (int)items.size();
-    for (int r = 0; r < R; ++r) {
-        DevRun &D = dr[r];
-        D.kcu = std::max(1, std::min({D.k, kUpdLdsWords / D.d, 1024}));
-        D.uitem0 = (int)items.size();
-        for (int c = 0; c < D.k; c += D.kcu) items.push_back(Item{r, c});
-        D.nuitems = (int)items.size() - D.uitem0;
+        n_obj = (int)items.size();
+        for (int r = 0; r < R; ++r) {
+            DevRun &D = dr[r];
+            D.kcu = std::max(1, std::min({D.k, kUpdLdsWords / D.d, 1024}));
+            D.uitem0 = (int)items.size();
+            if (!D.fused)
+                for (int c = 0; c < D.k; c += D.kcu) items.push_back(Item{r, c});
+            D.nuitems = (int)items.size() - D.uitem0;
+        }
     }
     const int n_items = (int)items.size();
+
+    // device copies of the plan: runs | items | tasks | task_off
     const size_t b_runs = sizeof(DevRun) * R, b_items = sizeof(Item) * n_items;
-    DevRun *d_runs = (DevRun *)ctx_scratch(ctx, SC_RUNS, b_runs + b_items);
-    RunState *d_rs = (RunState *)ctx_scratch(ctx, SC_RSTATE, sizeof(RunState) * R);
-    double *d_sse = (double *)ctx_scratch(ctx, SC_SSEPART, sizeof(double) * n_assign);
-    char *h = (char *)ctx_pinned(ctx, b_runs + b_items);
-    if (!d_runs || !d_rs || !d_sse || !h) return SUBKM_ENOMEM;
-    Item *d_items = (Item *)((char *)d_runs + b_runs);
-    // the pinned staging area is reused by the next call: wait for its copy
+    const size_t b_tasks = sizeof(Task) * tasks.size(), b_toff = sizeof(int32_t) * task_off.size();
+    const size_t b_plan = b_runs + b_items + b_tasks + b_toff;
+    char *d_plan = (char *)ctx_scratch(ctx, SC_RUNS, b_plan + 64);
+    RunState *d_rs = (RunState *)ctx_scratch(ctx, SC_RSTATE, sizeof(RunState) * R + 64);
+    double *d_obj = (double *)ctx_scratch(ctx, SC_SSEPART, sizeof(double) * (n_obj + 1));
+    long long *d_sum =
+        (long long *)ctx_scratch(ctx, SC_FIXSCALE, sizeof(long long) * (sum_words + part_words + 1));
+    int *d_err = (int *)ctx_scratch(ctx, SC_RECHECK, 128);
+    if (!d_plan || !d_rs || !d_obj || !d_sum || !d_err) return SUBKM_ENOMEM;
+    char *h = (char *)ctx_pinned(ctx, b_plan + 64);
+    if (!h) return SUBKM_ENOMEM;
+    DevRun *d_runs = (DevRun *)d_plan;
+    Item *d_items = (Item *)(d_plan + b_runs);
+    Task *d_tasks = (Task *)(d_plan + b_runs + b_items);
+    int32_t *d_toff = (int32_t *)(d_plan + b_runs + b_items + b_tasks);
+    // the pinned staging area is shared by calls: wait for its previous copy
     SUBKM_HIP(ctx, hipStreamSynchronize(s));
     std::memcpy(h, dr.data(), b_runs);
-    std::memcpy(h + b_runs, items.data(), b_items);
-    SUBKM_HIP(ctx, hipMemcpyAsync(d_runs, h, b_runs + b_items, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_setup, dim3(R), dim3(256), 0, s, P, d_runs, d_rs);
+    if (b_items) std::memcpy(h + b_runs, items.data(), b_items);
+    if (b_tasks) std::memcpy(h + b_runs + b_items, tasks.data(), b_tasks);
+    if (b_toff) std::memcpy(h + b_runs + b_items + b_tasks, task_off.data(), b_toff);
+    SUBKM_HIP(ctx, hipMemcpyAsync(d_plan, h, b_plan, hipMemcpyHostToDevice, s));
+
+    hipLaunchKernelGGL(k_state_init, dim3(ceil_div(R, 256)), dim3(256), 0, s, d_rs, R);
     SUBKM_LAUNCHED(ctx);
+    hipLaunchKernelGGL(k_fill_i64, dim3(std::min<int64_t>(ceil_div(sum_words + 1, 256), 2048)),
+                       dim3(256), 0, s, d_sum, sum_words + 1);
+    SUBKM_LAUNCHED(ctx);
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, (long long *)d_err, 16);
+    SUBKM_LAUNCHED(ctx);
+    if (max_iter > 0) {
+        int64_t maxtot = 0;
+        for (int r = 0; r < R; ++r) maxtot = std::max<int64_t>(maxtot, dr[r].n * dr[r].d);
+        hipLaunchKernelGGL(k_absmax, dim3(std::min<int64_t>(ceil_div(maxtot, 4096), 256), R),
+                           dim3(256), 0, s, P, d_runs, d_rs);
+        SUBKM_LAUNCHED(ctx);
+    }
     if (init_mode) {
         int64_t kmax = 0;
         for (int r = 0; r < R; ++r) kmax = std::max<int64_t>(kmax, (int64_t)runs[r].k * runs[r].d);
@@ -454,37 +932,80 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                            0, s, P, d_runs, C, init_mode);
         SUBKM_LAUNCHED(ctx);
     }
-    if (form == SUBKM_FORM_PLAIN) {
+    long long *gsum = d_sum;
+    long long *parts = d_sum + sum_words;
+    unsigned long long *d_rechecks = (unsigned long long *)(d_err + 16);
+
+    if (batched) {
+        for (auto &g : groups) {
+            const int dv = g.first, b0 = g.second.first, nbk = g.second.second;
+            SUBKM_TRY(persist_d(ctx, dv, nbk, P, d_runs, d_tasks, d_toff + b0, C, labels, d_rs,
+                                parts, d_obj, max_iter, tol, d_err));
+        }
+    } else if (form == SUBKM_FORM_PLAIN) {
         // one run at a time, one launch per phase
         for (int r = 0; r < R; ++r) {
             const DevRun &D = dr[r];
             for (int a = 0; a <= max_iter; ++a) {
-                SUBKM_TRY(assign_dispatch(ctx, D.d, D.nitems, D.item0, P, d_runs, d_items, C,
-                                          labels, d_rs, d_sse));
-                if (a < max_iter) {
-                    ProfScope ps(ctx, PK_UPDATE);
-                    hipLaunchKernelGGL(k_update, dim3(D.nuitems), dim3(kUT), 0, s, P, d_runs,
-                                       d_items, D.uitem0, C, labels, d_rs, tol);
-                    SUBKM_LAUNCHED(ctx);
+                if (D.fused) {
+                    SUBKM_TRY(assign_acc_d(ctx, D.d, D.nitems, D.item0, P, d_runs, d_items, C,
+                                           labels, d_rs, d_obj, gsum, a < max_iter ? 1 : 0));
+                } else {
+                    SUBKM_TRY(assign_d(ctx, D.d, D.nitems, D.item0, P, d_runs, d_items, C, labels,
+                                       d_rs, d_obj));
                 }
-            }
-        }
-    } else {
-        const int u0 = n_assign, nu = n_items - n_assign;
-        for (int a = 0; a <= max_iter; ++a) {
-            for (auto &g : groups)
-                SUBKM_TRY(assign_dispatch(ctx, g.first, g.second.second, g.second.first, P,
-                                          d_runs, d_items, C, labels, d_rs, d_sse));
-            if (a < max_iter) {
+                if (a == max_iter) break;
                 ProfScope ps(ctx, PK_UPDATE);
-                hipLaunchKernelGGL(k_update, dim3(nu), dim3(kUT), 0, s, P, d_runs, d_items, u0, C,
-                                   labels, d_rs, tol);
+                if (D.fused)
+                    hipLaunchKernelGGL(k_update_fin, dim3(1), dim3(kAT), 0, s, d_runs, r, C, d_rs, gsum, tol);
+                else
+                    hipLaunchKernelGGL(k_update_scan, dim3(D.nuitems), dim3(kAT), 0, s, P, d_runs,
+                                       d_items, D.uitem0, C, labels, d_rs, tol);
                 SUBKM_LAUNCHED(ctx);
             }
         }
+    } else {
+        // batched request with runs beyond the LDS budget: all runs per launch
+        for (int a = 0; a <= max_iter; ++a) {
+            for (int r0 = 0; r0 < R;) {
+                int r1 = r0 + 1;
+                while (r1 < R && dr[r1].d == dr[r0].d && dr[r1].fused == dr[r0].fused) ++r1;
+                const int i0 = dr[r0].item0, ni = dr[r1 - 1].item0 + dr[r1 - 1].nitems - i0;
+                if (dr[r0].fused)
+                    SUBKM_TRY(assign_acc_d(ctx, dr[r0].d, ni, i0, P, d_runs, d_items, C, labels,
+                                           d_rs, d_obj, gsum, a < max_iter ? 1 : 0));
+                else
+                    SUBKM_TRY(assign_d(ctx, dr[r0].d, ni, i0, P, d_runs, d_items, C, labels, d_rs,
+                                       d_obj));
+                r0 = r1;
+            }
+            if (a == max_iter) break;
+            ProfScope ps(ctx, PK_UPDATE);
+            for (int r0 = 0; r0 < R;) {
+                int r1 = r0 + 1;
+                while (r1 < R && dr[r1].fused == dr[r0].fused) ++r1;
+                if (dr[r0].fused) {
+                    hipLaunchKernelGGL(k_update_fin, dim3(r1 - r0), dim3(kAT), 0, s, d_runs, r0, C,
+                                       d_rs, gsum, tol);
+                } else {
+                    const int u0 = dr[r0].uitem0, nu = dr[r1 - 1].uitem0 + dr[r1 - 1].nuitems - u0;
+                    hipLaunchKernelGGL(k_update_scan, dim3(nu), dim3(kAT), 0, s, P, d_runs, d_items,
+                                       u0, C, labels, d_rs, tol);
+                }
+                SUBKM_LAUNCHED(ctx);
+                r0 = r1;
+            }
+        }
     }
-    hipLaunchKernelGGL(k_finalize, dim3(ceil_div(R, 256)), dim3(256), 0, s, d_runs, d_rs, d_sse, R,
-                       iters, sse);
+    hipLaunchKernelGGL(k_finalize, dim3(ceil_div(R, 256)), dim3(256), 0, s, d_runs, d_rs, d_obj, R,
+                       iters, sse, d_rechecks);
     SUBKM_LAUNCHED(ctx);
+    if (batched) {
+        // a barrier that gave up would leave wrong results: report it
+        int *hflag = (int *)h;
+        SUBKM_HIP(ctx, hipMemcpyAsync(hflag, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+        SUBKM_HIP(ctx, hipStreamSynchronize(s));
+        if (*hflag) return set_err(ctx, SUBKM_EDEVICE, "persistent Lloyd barrier timed out");
+    }
     return SUBKM_OK;
 }
