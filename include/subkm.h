@@ -231,7 +231,9 @@ size_t subkm_cluster_footprint(int64_t n, int32_t d, int64_t N, int32_t k_local,
  * subkm_profile_query synchronises the stream and returns the number of
  * launches and their total milliseconds for one class.
  * Classes: 0 assign, 1 update, 2 keys, 3 cand, 4 scatter, 5 scale,
- * 6 lloyd_fused (see subkm_profile_name).                                  */
+ * 6 lloyd_fused, 7 subcluster (see subkm_profile_name).  The subclustering
+ * rounds run as one replayed HIP graph, timed as a whole under class 7;
+ * classes 2-4 then stay empty.                                            */
 subkm_status subkm_profile_enable(subkm_ctx *ctx, int32_t on);
 subkm_status subkm_profile_query(subkm_ctx *ctx, int32_t cls, int64_t *launches, double *ms);
 const char *subkm_profile_name(int32_t cls);

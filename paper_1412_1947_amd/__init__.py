@@ -63,7 +63,8 @@ EXPORTS = ("subkm_create", "subkm_destroy", "subkm_last_error", "subkm_set_strea
            "subkm_cluster", "subkm_cluster_sizes", "subkm_cluster_footprint",
            "subkm_profile_enable", "subkm_profile_query", "subkm_profile_name")
 
-KERNEL_CLASSES = ("assign", "update", "keys", "cand", "scatter", "scale", "lloyd_fused")
+KERNEL_CLASSES = ("assign", "update", "keys", "cand", "scatter", "scale", "lloyd_fused",
+                  "subcluster")
 
 _lib = None
 _lib_lock = threading.Lock()

@@ -44,6 +44,7 @@ void *ctx_scratch(subkm_ctx *ctx, int slot, size_t bytes) {
         return nullptr;
     }
     b.bytes = want;
+    ctx->scratch_epoch += 1;
     return b.ptr;
 }
 
@@ -172,6 +173,8 @@ void subkm_destroy(subkm_ctx *ctx) {
         if (e) hipEventDestroy(e);
     prof_resolve(ctx);
     for (auto &e : ctx->prof_free) hipEventDestroy(e);
+    if (ctx->subg.exec) hipGraphExecDestroy(ctx->subg.exec);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
@@ -221,7 +224,7 @@ subkm_status subkm_profile_query(subkm_ctx *ctx, int32_t cls, int64_t *launches,
 
 const char *subkm_profile_name(int32_t cls) {
     static const char *names[PK_COUNT] = {"assign", "update", "keys", "cand",
-                                          "scatter", "scale", "lloyd_fused"};
+                                          "scatter", "scale", "lloyd_fused", "subcluster"};
     return (cls >= 0 && cls < PK_COUNT) ? names[cls] : "";
 }
 

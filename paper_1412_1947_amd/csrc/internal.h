@@ -38,13 +38,15 @@ enum ScratchSlot {
     SC_CL_LSSE,      // cluster(): local objective
     SC_CL_MINMAX,    // cluster(): mins / maxs
     SC_CL_FINAL,     // cluster(): final-run labels, iters, sse
+    SC_BOX,          // per-run attribute bounds
     SC_COUNT
 };
 
 // Kernel classes timed by the optional per-launch profiler (device events on
 // the context's stream around every launch of the class).
 enum ProfClass {
-    PK_ASSIGN = 0, PK_UPDATE, PK_KEYS, PK_CAND, PK_SCATTER, PK_SCALE, PK_LLOYD_FUSED, PK_COUNT
+    PK_ASSIGN = 0, PK_UPDATE, PK_KEYS, PK_CAND, PK_SCATTER, PK_SCALE, PK_LLOYD_FUSED,
+    PK_SUBCLUSTER, PK_COUNT
 };
 
 struct ProfRec {
@@ -71,6 +73,13 @@ struct subkm_ctx {
     std::vector<hipEvent_t> prof_free;
     double prof_ms[PK_COUNT] = {};
     long long prof_n[PK_COUNT] = {};
+    uint64_t scratch_epoch = 0;       // bumped whenever a scratch buffer moves
+    hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    struct GraphCache {
+        bool valid = false;
+        uint64_t key[12] = {};
+        hipGraphExec_t exec = nullptr;
+    } subg;                            // captured subclustering sequence
 };
 
 // RAII timer of the launches issued inside its scope (no-op when off).

@@ -40,7 +40,8 @@
 namespace {
 
 constexpr int kAT = 256;            // threads per block = points per tile
-constexpr int kCF = 4096;           // floats of centers held in LDS (fused path)
+constexpr int kCF = 4608;           // floats of centers held in LDS (fused path)
+constexpr int kSumW = 4096;         // int64 center sums held in LDS (fused path)
 constexpr int kMaxK = 1024;         // centers per run in the fused path
 constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path)
 constexpr int kUpdLdsWords = 6144;  // int64 sums per block (scan-update path)
@@ -58,7 +59,8 @@ struct DevRun {
     int64_t sum_off;          // offset of the run's int64 sums (k*d) + counts (k)
     int64_t part_off;         // batched: offset of the run's exchange slots
     int32_t G;                // batched: blocks of the run
-    int32_t pad;
+    int32_t mf;               // assignment on matrix cores
+    int64_t box_off;          // offset of the run's attribute minima and maxima
 };
 
 struct RunState {
@@ -212,45 +214,224 @@ __device__ void recheck_tile(const float *X, int64_t first, const float *Csrc, i
 }
 
 // ---------------------------------------------------------------------------
-// LDS of the fused kernels.
+// LDS of the fused kernels.  Centers are held row-major (c * d + j) for the
+// vector path and dim-major with a padded pitch (j * (k + 16) + c) for the
+// matrix-core path, whose operand reads are then free of bank conflicts.
 struct FusedLds {
     float sC[kCF];
-    long long s_sum[kCF];
+    float cn[kMaxK + 16];  // matrix-core path: ||c - m||^2, +inf past k
+    long long s_sum[kSumW];
     unsigned int s_cnt[kMaxK];
     int32_t s_list[kAT];
     int32_t s_newlab[kAT];
+    int32_t s_lab[kAT];    // stage-1 label, bit 31 set when uncertain
     double s_red[kAT];
+    float s_R;             // matrix-core path: max_c ||c - m||
     uint32_t s_nlist;
-    uint32_t s_flag;
 };
 
-// Assign one tile of up to 256 points of a run against all k centers held in
-// L.sC; optionally add the points to the fixed-point sums.  Returns the
-// binary64 objective contribution of this thread's point (0 if none).
+template <bool MF>
+__device__ __forceinline__ int cidx(int c, int j, int d, int ldk) {
+    return MF ? j * ldk + c : c * d + j;
+}
+
+// binary64 distance of a point (global memory) to center c held in LDS
+template <bool MF>
+__device__ __forceinline__ double dist64_lds(const float *x, const float *sC, int c, int d, int ldk) {
+    double acc = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double q = (double)x[j] - (double)sC[cidx<MF>(c, j, d, ldk)];
+        acc = acc + q * q;
+    }
+    return acc;
+}
+
+template <bool MF>
+__device__ int32_t wave_argmin64_lds(const float *x, const float *sC, int d, int k, int ldk) {
+    const int lane = threadIdx.x & 63;
+    double best = INFINITY;
+    int32_t bi = 0x7fffffff;
+    for (int c = lane; c < k; c += 64) {
+        double v = dist64_lds<MF>(x, sC, c, d, ldk);
+        if (v < best) {
+            best = v;
+            bi = c;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        double ob = __shfl_xor(best, o, 64);
+        int32_t oi = __shfl_xor(bi, o, 64);
+        if (ob < best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    return bi;
+}
+
+// Reference point m of a run for the matrix-core path: the midpoint of its
+// bounding box (box = ordered bits of the attribute minima, then maxima).
+__device__ __forceinline__ float box_mid(const uint32_t *box, int d, int j) {
+    return 0.5f * (ordered_float(box[j]) + ordered_float(box[d + j]));
+}
+
+// Matrix-core path: squared norms of the centered centers and their maximum.
 template <int D>
+__device__ void center_norms(FusedLds &L, const uint32_t *box, int k, int ldk) {
+    float mx = 0.0f;
+    for (int c = threadIdx.x; c < kMaxK + 16 && c < ((k + 15) & ~15); c += kAT) {
+        float a = INFINITY;
+        if (c < k) {
+            a = 0.0f;
+#pragma unroll 4
+            for (int j = 0; j < D; ++j) {
+                const float t = L.sC[j * ldk + c] - box_mid(box, D, j);
+                a = __builtin_fmaf(t, t, a);
+            }
+            mx = fmaxf(mx, a);
+        }
+        L.cn[c] = a;
+    }
+    const double r = block_max((double)mx, L.s_red);
+    if (threadIdx.x == 0) L.s_R = sqrtf((float)r);
+    __syncthreads();
+}
+
+// Stage 1 on matrix cores (v_mfma_f32_16x16x4_f32).  A wavefront takes 64
+// points as four groups of 16; a 16x16 output tile holds the dot products of
+// 16 centers (rows) with 16 points (columns): lane l sees point l % 16 of a
+// group and centers 4 * (l / 16) + r, r = 0..3, of the tile.  Both sides are
+// centered on m; v = ||c - m||^2 - 2 (x - m).(c - m) ranks the centers like
+// ||x - c||^2.  Every lane keeps the two smallest v of its centers; four
+// lanes share a point and merge at the end.  The gap of the two smallest is
+// certain when it exceeds twice the error bound
+//     E = 2 (d + 5) u (||x - m|| + max_c ||c - m||)^2,   u = 2^-24,
+// which covers the rounding of the centering, the products, the sums and the
+// final combination (with a factor 2 of margin).  Results go to L.s_lab.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int D>
+__device__ void stage1_mfma(FusedLds &L, const float *X, int64_t first, int64_t n, int k, int ldk,
+                            const uint32_t *box) {
+    constexpr int KQ = D / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kk = lane >> 4;
+    float mq[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) mq[q] = box_mid(box, D, kk + 4 * q);
+    float xb[4][KQ];
+    float xn[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int64_t p = first + wave * 64 + g * 16 + col;
+        const bool ok = p < n;
+        float s2 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const float v = ok ? X[p * D + kk + 4 * q] - mq[q] : 0.0f;
+            xb[g][q] = v;
+            s2 = __builtin_fmaf(v, v, s2);
+        }
+        s2 += __shfl_xor(s2, 16, 64);
+        s2 += __shfl_xor(s2, 32, 64);
+        xn[g] = sqrtf(s2);
+    }
+    float b1[4], b2[4];
+    int32_t i1[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        b1[g] = INFINITY;
+        b2[g] = INFINITY;
+        i1[g] = 0;
+    }
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        const int cA = c0 + col;
+        float ca[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) ca[q] = cA < k ? L.sC[(kk + 4 * q) * ldk + cA] - mq[q] : 0.0f;
+        const floatx4 cnv = *(const floatx4 *)&L.cn[c0 + 4 * kk];
+        const int cbase = c0 + 4 * kk;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[q], xb[g][q], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float v = __builtin_fmaf(-2.0f, acc[r], cnv[r]);
+                b2[g] = fminf(b2[g], fmaxf(v, b1[g]));
+                const bool lt = v < b1[g];
+                b1[g] = lt ? v : b1[g];
+                i1[g] = lt ? cbase + r : i1[g];
+            }
+        }
+    }
+    const float Rc = L.s_R;
+    const float Ku = 2.0f * (float)(D + 5) * 5.9604645e-8f;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            const float ob1 = __shfl_xor(b1[g], o, 64);
+            const float ob2 = __shfl_xor(b2[g], o, 64);
+            const int32_t oi = __shfl_xor(i1[g], o, 64);
+            const float nb2 = fminf(fminf(b2[g], ob2), fmaxf(b1[g], ob1));
+            const bool take = ob1 < b1[g] || (ob1 == b1[g] && oi < i1[g]);
+            b1[g] = take ? ob1 : b1[g];
+            i1[g] = take ? oi : i1[g];
+            b2[g] = nb2;
+        }
+        if (kk == 0) {
+            const float s = xn[g] + Rc;
+            const float E = Ku * s * s + 1e-30f;
+            const bool certain = k == 1 || (b2[g] - b1[g]) > 2.0f * E;
+            L.s_lab[wave * 64 + g * 16 + col] = i1[g] | (certain ? 0 : (int32_t)0x80000000);
+        }
+    }
+}
+
+// Assign one tile of up to 256 points of a run against all k centers held in
+// LDS; optionally add the points to the fixed-point sums.  Returns the
+// binary64 objective contribution of this thread's point (0 if none).
+template <int D, bool MF>
 __device__ double fused_tile(FusedLds &L, const float *X, int64_t first, int64_t n, int d, int k,
-                             int32_t *lab_out, bool accumulate, int shift,
-                             unsigned long long *rechecks) {
+                             int ldk, const uint32_t *box, int32_t *lab_out, bool accumulate,
+                             int shift, unsigned long long *rechecks) {
     const int64_t i = first + threadIdx.x;
     const bool valid = i < n;
     const float *xg = X + (valid ? i : 0) * d;
-    float x[D > 0 ? D : 1];
-    if (D > 0) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) x[j] = xg[j];
-    }
-    __syncthreads();  // the previous tile is done with the recheck list
+    __syncthreads();  // the previous tile is done with the LDS lists
     if (threadIdx.x == 0) L.s_nlist = 0;
-    __syncthreads();
-    float b1 = INFINITY, b2 = INFINITY;
-    int32_t i1 = 0;
-    scan_centers<D>(x, xg, L.sC, 0, k, d, b1, b2, i1);
-    const bool certain = certain_gap(b1, b2, d, k);
+    int32_t i1;
+    bool certain;
+    if constexpr (MF) {
+        stage1_mfma<D>(L, X, first, n, k, ldk, box);
+        __syncthreads();
+        const int32_t sl = L.s_lab[threadIdx.x];
+        i1 = sl & 0x7fffffff;
+        certain = sl >= 0;
+    } else {
+        float x[D > 0 ? D : 1];
+        if (D > 0) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) x[j] = xg[j];
+        }
+        __syncthreads();
+        float b1 = INFINITY, b2 = INFINITY;
+        i1 = 0;
+        scan_centers<D>(x, xg, L.sC, 0, k, d, b1, b2, i1);
+        certain = certain_gap(b1, b2, d, k);
+    }
     if (valid && !certain) L.s_list[atomicAdd(&L.s_nlist, 1u)] = threadIdx.x;
     __syncthreads();
     const uint32_t nl = L.s_nlist;
     if (nl) {
-        recheck_tile(X, first, L.sC, d, k, L.s_list, nl, L.s_newlab);
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (uint32_t q = wave; q < nl; q += kAT / 64) {
+            const int t = L.s_list[q];
+            const int32_t w = wave_argmin64_lds<MF>(X + (first + t) * d, L.sC, d, k, ldk);
+            if (lane == 0) L.s_newlab[t] = w;
+        }
         __syncthreads();
         if (valid && !certain) i1 = L.s_newlab[threadIdx.x];
         if (threadIdx.x == 0) atomicAdd(rechecks, (unsigned long long)nl);
@@ -258,37 +439,39 @@ __device__ double fused_tile(FusedLds &L, const float *X, int64_t first, int64_t
     double obj = 0.0;
     if (valid) {
         lab_out[i] = i1;
-        obj = dist64(xg, L.sC + i1 * d, d);
+        obj = dist64_lds<MF>(xg, L.sC, i1, d, ldk);
         if (accumulate) {
             atomicAdd(&L.s_cnt[i1], 1u);
             long long *row = L.s_sum + i1 * d;
-            if (D > 0) {
-#pragma unroll
-                for (int j = 0; j < D; ++j)
-                    atomicAdd((unsigned long long *)&row[j], (unsigned long long)to_fixed(x[j], shift));
-            } else {
-                for (int j = 0; j < d; ++j)
-                    atomicAdd((unsigned long long *)&row[j], (unsigned long long)to_fixed(xg[j], shift));
+            // lanes start at different attributes, so that one LDS atomic
+            // instruction does not send all lanes to the same bank
+            int j = threadIdx.x % d;
+            for (int q = 0; q < d; ++q) {
+                atomicAdd((unsigned long long *)&row[j], (unsigned long long)to_fixed(xg[j], shift));
+                j = j + 1 == d ? 0 : j + 1;
             }
         }
     }
     return obj;
 }
 
-// New centers from the sums in L.s_sum / L.s_cnt: writes L.sC (and Cglob if
-// non-null) and returns the largest binary64 center move.
-__device__ double centers_from_sums(FusedLds &L, int d, int k, int shift, float *Cglob) {
+// New centers from the sums in L.s_sum / L.s_cnt: writes L.sC (and Cglob,
+// row-major, if non-null) and returns the largest binary64 center move.
+template <bool MF>
+__device__ double centers_from_sums(FusedLds &L, int d, int k, int ldk, int shift, float *Cglob) {
     double mx = 0.0;
     for (int c = threadIdx.x; c < k; c += kAT) {
         const unsigned int cnt = L.s_cnt[c];
         double mv2 = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const float old = L.sC[c * d + j];
+        int j = c % d;  // rotated start: neighbouring lanes read different banks
+        for (int q = 0; q < d; ++q, j = j + 1 == d ? 0 : j + 1) {
+            const int e = cidx<MF>(c, j, d, ldk);
+            const float old = L.sC[e];
             const double nv = cnt ? ldexp((double)L.s_sum[c * d + j], -shift) / (double)cnt : (double)old;
-            const double q = nv - (double)old;
-            mv2 = mv2 + q * q;
+            const double dv = nv - (double)old;
+            mv2 = mv2 + dv * dv;
             const float f = (float)nv;
-            L.sC[c * d + j] = f;
+            L.sC[e] = f;
             if (Cglob) Cglob[c * d + j] = f;
         }
         mx = fmax(mx, sqrt(mv2));
@@ -296,14 +479,24 @@ __device__ double centers_from_sums(FusedLds &L, int d, int k, int shift, float 
     return block_max(mx, L.s_red);
 }
 
+// load the run's centers (row-major in global memory) into LDS
+template <bool MF>
+__device__ void load_centers(FusedLds &L, const float *Cr, int d, int k, int ldk) {
+    for (int e = threadIdx.x; e < k * d; e += kAT) {
+        const int c = e / d, j = e - c * d;
+        L.sC[cidx<MF>(c, j, d, ldk)] = Cr[e];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Batched form: persistent, cooperative.  Block b works through its tasks
 // task_off[b] .. task_off[b+1]-1 in order; every task is one part of a run.
-template <int D>
+template <int D, bool MF>
 __global__ __launch_bounds__(kAT) void k_lloyd_persist(
     const float *__restrict__ P, const DevRun *__restrict__ runs, const Task *__restrict__ tasks,
     const int32_t *__restrict__ task_off, float *C, int32_t *labels, RunState *rstate,
-    long long *parts, double *objpart, int max_iter, double tol, int *err) {
+    long long *parts, double *objpart, const uint32_t *__restrict__ boxes, int max_iter,
+    double tol, int *err) {
     __shared__ FusedLds L;
     for (int ti = task_off[blockIdx.x]; ti < task_off[blockIdx.x + 1]; ++ti) {
         const Task tk = tasks[ti];
@@ -312,8 +505,10 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
         const int d = D > 0 ? D : R.d;
         const int k = R.k;
         const int kd = k * d;
+        const int ldk = k + 16;
         const int G = R.G;
         const int shift = fix_shift_of(rs->absmax_bits, R.n);
+        const uint32_t *box = boxes + R.box_off;
         // the run's points are split over its G blocks in whole tiles
         const int64_t tiles = (R.n + kAT - 1) / kAT;
         const int64_t t0 = tiles * tk.g / G, t1 = tiles * (tk.g + 1) / G;
@@ -321,16 +516,18 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
         int32_t *lab = labels + R.lab_off;
         float *Cr = C + R.c_off;
         __syncthreads();
-        for (int e = threadIdx.x; e < kd; e += kAT) L.sC[e] = Cr[e];
+        load_centers<MF>(L, Cr, d, k, ldk);
+        __syncthreads();
+        if constexpr (MF) center_norms<D>(L, box, k, ldk);
         int it = 0;
         bool converged = false;
         for (;;) {
             const bool last = it == max_iter || converged;
             for (int e = threadIdx.x; e < kd; e += kAT) L.s_sum[e] = 0;
             for (int c = threadIdx.x; c < k; c += kAT) L.s_cnt[c] = 0;
-            __syncthreads();
             for (int64_t t = t0; t < t1; ++t) {
-                const double obj = fused_tile<D>(L, X, t * kAT, R.n, d, k, lab, !last, shift, &rs->rechecks);
+                const double obj = fused_tile<D, MF>(L, X, t * kAT, R.n, d, k, ldk, box, lab, !last,
+                                                     shift, &rs->rechecks);
                 if (last) {
                     // objective per tile, summed over tiles in order by the
                     // finalize kernel: the same rounding as the plain form
@@ -378,7 +575,8 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
                 }
                 __syncthreads();
             }
-            const double shift_max = centers_from_sums(L, d, k, shift, tk.g == 0 ? Cr : nullptr);
+            const double shift_max = centers_from_sums<MF>(L, d, k, ldk, shift, tk.g == 0 ? Cr : nullptr);
+            if constexpr (MF) center_norms<D>(L, box, k, ldk);
             ++it;
             converged = shift_max < tol;
         }
@@ -389,13 +587,14 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
 // Plain form, fused path: assign + accumulate over a run's tiles (one item
 // per tile), sums flushed to the run's global accumulators with integer
 // atomics.
-template <int D>
+template <int D, bool MF>
 __global__ __launch_bounds__(kAT) void k_assign_acc(const float *__restrict__ P,
                                                     const DevRun *__restrict__ runs,
                                                     const Item *__restrict__ items, int item_base,
                                                     const float *__restrict__ C, int32_t *labels,
                                                     RunState *rstate, double *objpart,
-                                                    long long *gsum, int accumulate) {
+                                                    long long *gsum, const uint32_t *__restrict__ boxes,
+                                                    int accumulate) {
     __shared__ FusedLds L;
     const Item itm = items[item_base + blockIdx.x];
     const DevRun R = runs[itm.run];
@@ -404,16 +603,16 @@ __global__ __launch_bounds__(kAT) void k_assign_acc(const float *__restrict__ P,
     if (ph == PH_DONE) return;
     const bool acc = accumulate && ph == PH_ITER;
     const int d = D > 0 ? D : R.d;
-    const int k = R.k, kd = k * d;
+    const int k = R.k, kd = k * d, ldk = k + 16;
     const int shift = fix_shift_of(rs->absmax_bits, R.n);
-    for (int e = threadIdx.x; e < kd; e += kAT) {
-        L.sC[e] = C[R.c_off + e];
-        L.s_sum[e] = 0;
-    }
+    const uint32_t *box = boxes + R.box_off;
+    load_centers<MF>(L, C + R.c_off, d, k, ldk);
+    for (int e = threadIdx.x; e < kd; e += kAT) L.s_sum[e] = 0;
     for (int c = threadIdx.x; c < k; c += kAT) L.s_cnt[c] = 0;
     __syncthreads();
-    const double obj = fused_tile<D>(L, P + R.x_off, itm.first, R.n, d, k, labels + R.lab_off, acc,
-                                     shift, &rs->rechecks);
+    if constexpr (MF) center_norms<D>(L, box, k, ldk);
+    const double obj = fused_tile<D, MF>(L, P + R.x_off, itm.first, R.n, d, k, ldk, box,
+                                         labels + R.lab_off, acc, shift, &rs->rechecks);
     const double tot = block_sum_det(obj, L.s_red);
     if (threadIdx.x == 0) objpart[item_base + blockIdx.x] = tot;
     if (!acc) return;
@@ -453,7 +652,7 @@ __global__ __launch_bounds__(kAT) void k_update_fin(const DevRun *__restrict__ r
         gs[kd + c] = 0;
     }
     __syncthreads();
-    const double mx = centers_from_sums(L, d, k, shift, C + R.c_off);
+    const double mx = centers_from_sums<false>(L, d, k, 0, shift, C + R.c_off);
     if (threadIdx.x == 0) {
         rs->iters += 1;
         rs->phase = mx < tol ? PH_FINAL : PH_ITER;
@@ -614,16 +813,58 @@ __global__ void k_state_init(RunState *rstate, int R) {
     rstate[r] = z;
 }
 
-// largest |x| of every run (grid: chunks x runs)
-__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ P,
-                                                const DevRun *__restrict__ runs, RunState *rstate) {
+// Attribute-wise minimum and maximum of every run as ordered bits (box[j],
+// box[d + j]) and the largest |x| of the run (grid: chunks x runs).
+__global__ void k_box_init(const DevRun *__restrict__ runs, uint32_t *boxes) {
+    const DevRun R = runs[blockIdx.x];
+    for (int j = threadIdx.x; j < 2 * R.d; j += blockDim.x)
+        boxes[R.box_off + j] = j < R.d ? 0xFFFFFFFFu : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_runbox(const float *__restrict__ P,
+                                                const DevRun *__restrict__ runs, uint32_t *boxes,
+                                                RunState *rstate) {
+    extern __shared__ uint32_t s_box[];  // 2 d words
     __shared__ float s_m[256];
     const DevRun R = runs[blockIdx.y];
+    const int d = R.d;
+    for (int j = threadIdx.x; j < d; j += 256) {
+        s_box[j] = 0xFFFFFFFFu;
+        s_box[d + j] = 0u;
+    }
+    __syncthreads();
     const float *X = P + R.x_off;
-    const int64_t tot = R.n * R.d;
+    const int64_t per = (R.n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(R.n, r0 + per);
+    if (256 % d == 0) {
+        // every thread keeps one attribute
+        const int col = threadIdx.x % d, rstep = 256 / d;
+        uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+        for (int64_t row = r0 + threadIdx.x / d; row < r1; row += rstep) {
+            const uint32_t o = ordered_bits(X[row * d + col]);
+            lo = min(lo, o);
+            hi = max(hi, o);
+        }
+        atomicMin(&s_box[col], lo);
+        atomicMax(&s_box[d + col], hi);
+    } else {
+        for (int64_t row = r0; row < r1; ++row)
+            for (int col = threadIdx.x; col < d; col += 256) {
+                const uint32_t o = ordered_bits(X[row * d + col]);
+                atomicMin(&s_box[col], o);
+                atomicMax(&s_box[d + col], o);
+            }
+    }
+    __syncthreads();
+    uint32_t *gb = boxes + R.box_off;
     float m = 0.0f;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
-        m = fmaxf(m, fabsf(X[e]));
+    for (int j = threadIdx.x; j < d; j += 256) {
+        if (s_box[j] != 0xFFFFFFFFu) {
+            atomicMin(&gb[j], s_box[j]);
+            atomicMax(&gb[d + j], s_box[d + j]);
+            m = fmaxf(m, fmaxf(fabsf(ordered_float(s_box[j])), fabsf(ordered_float(s_box[d + j]))));
+        }
+    }
     s_m[threadIdx.x] = m;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
@@ -681,14 +922,26 @@ __global__ void k_finalize(const DevRun *__restrict__ runs, const RunState *__re
         default: return FN<0>(__VA_ARGS__);                                               \
     }
 
+// matrix-core variants exist for attribute counts that are multiples of 4
 template <int D>
-subkm_status launch_assign_acc(subkm_ctx *ctx, int nitems, int item_base, const float *P,
+constexpr bool kHasMF = D >= 4 && D <= 128 && D % 4 == 0;
+
+template <int D>
+subkm_status launch_assign_acc(subkm_ctx *ctx, bool mf, int nitems, int item_base, const float *P,
                                const DevRun *runs, const Item *items, const float *C,
                                int32_t *labels, RunState *rs, double *objpart, long long *gsum,
-                               int accumulate) {
+                               const uint32_t *boxes, int accumulate) {
     ProfScope ps(ctx, PK_ASSIGN);
-    hipLaunchKernelGGL(k_assign_acc<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
-                       item_base, C, labels, rs, objpart, gsum, accumulate);
+    if constexpr (kHasMF<D>) {
+        if (mf) {
+            hipLaunchKernelGGL((k_assign_acc<D, true>), dim3(nitems), dim3(kAT), 0, ctx->stream, P,
+                               runs, items, item_base, C, labels, rs, objpart, gsum, boxes, accumulate);
+            SUBKM_LAUNCHED(ctx);
+            return SUBKM_OK;
+        }
+    }
+    hipLaunchKernelGGL((k_assign_acc<D, false>), dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs,
+                       items, item_base, C, labels, rs, objpart, gsum, boxes, accumulate);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
@@ -704,38 +957,62 @@ subkm_status launch_assign(subkm_ctx *ctx, int nitems, int item_base, const floa
     return SUBKM_OK;
 }
 
-template <int D>
-subkm_status launch_persist(subkm_ctx *ctx, int blocks, const float *P, const DevRun *runs,
-                            const Task *tasks, const int32_t *task_off, float *C, int32_t *labels,
-                            RunState *rs, long long *parts, double *objpart, int max_iter,
-                            double tol, int *err) {
+template <int D, bool MF>
+subkm_status launch_persist_k(subkm_ctx *ctx, int blocks, const float *P, const DevRun *runs,
+                              const Task *tasks, const int32_t *task_off, float *C,
+                              int32_t *labels, RunState *rs, long long *parts, double *objpart,
+                              const uint32_t *boxes, int max_iter, double tol, int *err) {
     ProfScope ps(ctx, PK_LLOYD_FUSED);
-    void *args[] = {(void *)&P,      (void *)&runs,  (void *)&tasks,   (void *)&task_off,
-                    (void *)&C,      (void *)&labels, (void *)&rs,     (void *)&parts,
-                    (void *)&objpart, (void *)&max_iter, (void *)&tol, (void *)&err};
-    SUBKM_HIP(ctx, hipLaunchCooperativeKernel((const void *)k_lloyd_persist<D>, dim3(blocks),
+    void *args[] = {(void *)&P,       (void *)&runs,   (void *)&tasks, (void *)&task_off,
+                    (void *)&C,       (void *)&labels, (void *)&rs,    (void *)&parts,
+                    (void *)&objpart, (void *)&boxes,  (void *)&max_iter, (void *)&tol,
+                    (void *)&err};
+    SUBKM_HIP(ctx, hipLaunchCooperativeKernel((const void *)k_lloyd_persist<D, MF>, dim3(blocks),
                                               dim3(kAT), args, 0, ctx->stream));
     return SUBKM_OK;
 }
 
 template <int D>
-int persist_occupancy() {
+subkm_status launch_persist(subkm_ctx *ctx, bool mf, int blocks, const float *P,
+                            const DevRun *runs, const Task *tasks, const int32_t *task_off,
+                            float *C, int32_t *labels, RunState *rs, long long *parts,
+                            double *objpart, const uint32_t *boxes, int max_iter, double tol,
+                            int *err) {
+    if constexpr (kHasMF<D>) {
+        if (mf)
+            return launch_persist_k<D, true>(ctx, blocks, P, runs, tasks, task_off, C, labels, rs,
+                                             parts, objpart, boxes, max_iter, tol, err);
+    }
+    return launch_persist_k<D, false>(ctx, blocks, P, runs, tasks, task_off, C, labels, rs, parts,
+                                      objpart, boxes, max_iter, tol, err);
+}
+
+template <int D>
+int persist_occupancy(bool mf) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lloyd_persist<D>, kAT, 0) != hipSuccess) {
+    hipError_t e;
+    if constexpr (kHasMF<D>) {
+        if (mf) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lloyd_persist<D, true>, kAT, 0);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lloyd_persist<D, false>, kAT, 0);
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lloyd_persist<D, false>, kAT, 0);
+    }
+    if (e != hipSuccess) {
         hipGetLastError();
         return 0;
     }
     return nb;
 }
 
-int persist_occupancy_d(int d) { SUBKM_DISPATCH_D(d, persist_occupancy); }
+int persist_occupancy_d(int d, bool mf) { SUBKM_DISPATCH_D(d, persist_occupancy, mf); }
 
-subkm_status assign_acc_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
-                          const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                          RunState *rs, double *objpart, long long *gsum, int accumulate) {
+subkm_status assign_acc_d(subkm_ctx *ctx, int d, bool mf, int nitems, int item_base,
+                          const float *P, const DevRun *runs, const Item *items, const float *C,
+                          int32_t *labels, RunState *rs, double *objpart, long long *gsum,
+                          const uint32_t *boxes, int accumulate) {
     if (nitems <= 0) return SUBKM_OK;
-    SUBKM_DISPATCH_D(d, launch_assign_acc, ctx, nitems, item_base, P, runs, items, C, labels, rs,
-                     objpart, gsum, accumulate);
+    SUBKM_DISPATCH_D(d, launch_assign_acc, ctx, mf, nitems, item_base, P, runs, items, C, labels,
+                     rs, objpart, gsum, boxes, accumulate);
 }
 
 subkm_status assign_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
@@ -746,12 +1023,12 @@ subkm_status assign_d(subkm_ctx *ctx, int d, int nitems, int item_base, const fl
                      objpart);
 }
 
-subkm_status persist_d(subkm_ctx *ctx, int d, int blocks, const float *P, const DevRun *runs,
-                       const Task *tasks, const int32_t *task_off, float *C, int32_t *labels,
-                       RunState *rs, long long *parts, double *objpart, int max_iter, double tol,
-                       int *err) {
-    SUBKM_DISPATCH_D(d, launch_persist, ctx, blocks, P, runs, tasks, task_off, C, labels, rs, parts,
-                     objpart, max_iter, tol, err);
+subkm_status persist_d(subkm_ctx *ctx, int d, bool mf, int blocks, const float *P,
+                       const DevRun *runs, const Task *tasks, const int32_t *task_off, float *C,
+                       int32_t *labels, RunState *rs, long long *parts, double *objpart,
+                       const uint32_t *boxes, int max_iter, double tol, int *err) {
+    SUBKM_DISPATCH_D(d, launch_persist, ctx, mf, blocks, P, runs, tasks, task_off, C, labels, rs,
+                     parts, objpart, boxes, max_iter, tol, err);
 }
 
 // Largest-work-first schedule of the runs of one attribute count over
@@ -804,7 +1081,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     hipStream_t s = ctx->stream;
     std::vector<DevRun> dr(R);
     bool all_fused = true;
-    int64_t sum_words = 0;
+    int64_t sum_words = 0, box_words = 0;
     for (int r = 0; r < R; ++r) {
         const subkm_run &u = runs[r];
         DevRun &D = dr[r];
@@ -815,13 +1092,18 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         D.lab_off = u.lab_off;
         D.d = u.d;
         D.k = u.k;
-        D.fused = ((int64_t)u.k * u.d <= kCF && u.k <= kMaxK) ? 1 : 0;
+        const int64_t kd = (int64_t)u.k * u.d;
+        const bool mf_shape = (u.d == 4 || u.d == 8 || u.d == 16 || u.d == 32 || u.d == 64 || u.d == 128);
+        D.mf = (mf_shape && (int64_t)u.d * (u.k + 16) <= kCF) ? 1 : 0;
+        D.fused = (kd <= kSumW && kd <= kCF && u.k <= kMaxK) ? 1 : 0;
         all_fused = all_fused && D.fused;
         D.sum_off = sum_words;
-        if (D.fused) sum_words += (int64_t)u.k * u.d + u.k;
+        if (D.fused) sum_words += kd + u.k;
+        D.box_off = box_words;
+        box_words += 2 * (int64_t)u.d;
     }
-    std::vector<int> ds;  // distinct attribute counts
-    for (int r = 0; r < R; ++r) ds.push_back(dr[r].d);
+    std::vector<std::pair<int, int>> ds;  // distinct (attribute count, matrix-core path)
+    for (int r = 0; r < R; ++r) ds.push_back({dr[r].d, dr[r].mf});
     std::sort(ds.begin(), ds.end());
     ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
 
@@ -829,22 +1111,26 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     std::vector<Item> items;
     std::vector<Task> tasks;
     std::vector<int32_t> task_off;
-    std::vector<std::pair<int, std::pair<int, int>>> groups;  // d -> (first block, blocks)
+    struct Group {
+        int d, mf, block0, blocks;
+    };
+    std::vector<Group> groups;
     int64_t part_words = 0;
     int n_obj = 0;
     if (batched) {
         // one persistent launch per attribute count, at most the co-resident capacity
         int block_base = 0;
         task_off.push_back(0);
-        for (int dv : ds) {
+        for (auto dm : ds) {
+            const int dv = dm.first, mv = dm.second;
             std::vector<int> rr;
             int64_t tiles = 0;
             for (int r = 0; r < R; ++r)
-                if (dr[r].d == dv) {
+                if (dr[r].d == dv && dr[r].mf == mv) {
                     rr.push_back(r);
                     tiles += (dr[r].n + kAT - 1) / kAT;
                 }
-            const int occ = std::max(1, persist_occupancy_d(dv));
+            const int occ = std::max(1, persist_occupancy_d(dv, mv != 0));
             const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->cu_count * occ, tiles));
             std::vector<int32_t> G(R, 1);
             std::vector<std::vector<Task>> pb;
@@ -860,7 +1146,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                 for (const Task &t : pb[b]) tasks.push_back(t);
                 task_off.push_back((int32_t)tasks.size());
             }
-            groups.push_back({dv, {block_base, blocks}});
+            groups.push_back(Group{dv, mv, block_base, blocks});
             block_base += blocks;
         }
         for (int r = 0; r < R; ++r) {
@@ -896,7 +1182,8 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     long long *d_sum =
         (long long *)ctx_scratch(ctx, SC_FIXSCALE, sizeof(long long) * (sum_words + part_words + 1));
     int *d_err = (int *)ctx_scratch(ctx, SC_RECHECK, 128);
-    if (!d_plan || !d_rs || !d_obj || !d_sum || !d_err) return SUBKM_ENOMEM;
+    uint32_t *d_box = (uint32_t *)ctx_scratch(ctx, SC_BOX, sizeof(uint32_t) * (box_words + 1));
+    if (!d_plan || !d_rs || !d_obj || !d_sum || !d_err || !d_box) return SUBKM_ENOMEM;
     char *h = (char *)ctx_pinned(ctx, b_plan + 64);
     if (!h) return SUBKM_ENOMEM;
     DevRun *d_runs = (DevRun *)d_plan;
@@ -918,11 +1205,19 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     SUBKM_LAUNCHED(ctx);
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, (long long *)d_err, 16);
     SUBKM_LAUNCHED(ctx);
-    if (max_iter > 0) {
-        int64_t maxtot = 0;
-        for (int r = 0; r < R; ++r) maxtot = std::max<int64_t>(maxtot, dr[r].n * dr[r].d);
-        hipLaunchKernelGGL(k_absmax, dim3(std::min<int64_t>(ceil_div(maxtot, 4096), 256), R),
-                           dim3(256), 0, s, P, d_runs, d_rs);
+    {
+        // attribute-wise bounds of every run: reference point of the
+        // matrix-core path and fixed-point scale of the sums
+        int64_t nmax = 0;
+        int dmax = 1;
+        for (int r = 0; r < R; ++r) {
+            nmax = std::max<int64_t>(nmax, dr[r].n);
+            dmax = std::max(dmax, dr[r].d);
+        }
+        hipLaunchKernelGGL(k_box_init, dim3(R), dim3(256), 0, s, d_runs, d_box);
+        SUBKM_LAUNCHED(ctx);
+        hipLaunchKernelGGL(k_runbox, dim3(std::min<int64_t>(ceil_div(nmax, 2048), 128), R), dim3(256),
+                           2 * sizeof(uint32_t) * dmax, s, P, d_runs, d_box, d_rs);
         SUBKM_LAUNCHED(ctx);
     }
     if (init_mode) {
@@ -937,19 +1232,17 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     unsigned long long *d_rechecks = (unsigned long long *)(d_err + 16);
 
     if (batched) {
-        for (auto &g : groups) {
-            const int dv = g.first, b0 = g.second.first, nbk = g.second.second;
-            SUBKM_TRY(persist_d(ctx, dv, nbk, P, d_runs, d_tasks, d_toff + b0, C, labels, d_rs,
-                                parts, d_obj, max_iter, tol, d_err));
-        }
+        for (const Group &g : groups)
+            SUBKM_TRY(persist_d(ctx, g.d, g.mf != 0, g.blocks, P, d_runs, d_tasks, d_toff + g.block0,
+                                C, labels, d_rs, parts, d_obj, d_box, max_iter, tol, d_err));
     } else if (form == SUBKM_FORM_PLAIN) {
         // one run at a time, one launch per phase
         for (int r = 0; r < R; ++r) {
             const DevRun &D = dr[r];
             for (int a = 0; a <= max_iter; ++a) {
                 if (D.fused) {
-                    SUBKM_TRY(assign_acc_d(ctx, D.d, D.nitems, D.item0, P, d_runs, d_items, C,
-                                           labels, d_rs, d_obj, gsum, a < max_iter ? 1 : 0));
+                    SUBKM_TRY(assign_acc_d(ctx, D.d, D.mf != 0, D.nitems, D.item0, P, d_runs, d_items,
+                                           C, labels, d_rs, d_obj, gsum, d_box, a < max_iter ? 1 : 0));
                 } else {
                     SUBKM_TRY(assign_d(ctx, D.d, D.nitems, D.item0, P, d_runs, d_items, C, labels,
                                        d_rs, d_obj));
@@ -969,11 +1262,13 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         for (int a = 0; a <= max_iter; ++a) {
             for (int r0 = 0; r0 < R;) {
                 int r1 = r0 + 1;
-                while (r1 < R && dr[r1].d == dr[r0].d && dr[r1].fused == dr[r0].fused) ++r1;
+                while (r1 < R && dr[r1].d == dr[r0].d && dr[r1].fused == dr[r0].fused &&
+                       dr[r1].mf == dr[r0].mf)
+                    ++r1;
                 const int i0 = dr[r0].item0, ni = dr[r1 - 1].item0 + dr[r1 - 1].nitems - i0;
                 if (dr[r0].fused)
-                    SUBKM_TRY(assign_acc_d(ctx, dr[r0].d, ni, i0, P, d_runs, d_items, C, labels,
-                                           d_rs, d_obj, gsum, a < max_iter ? 1 : 0));
+                    SUBKM_TRY(assign_acc_d(ctx, dr[r0].d, dr[r0].mf != 0, ni, i0, P, d_runs, d_items, C,
+                                           labels, d_rs, d_obj, gsum, d_box, a < max_iter ? 1 : 0));
                 else
                     SUBKM_TRY(assign_d(ctx, dr[r0].d, ni, i0, P, d_runs, d_items, C, labels, d_rs,
                                        d_obj));

@@ -150,6 +150,12 @@ Plan plan_for(int64_t n, int d) {
 
 }  // namespace
 
+// scratch bytes minmax_impl asks for (callers that capture graphs allocate first)
+size_t minmax_scratch_bytes(int64_t n, int32_t d) {
+    Plan p = plan_for(n, d);
+    return sizeof(float) * 2 * p.blocks * d;
+}
+
 // Column minima and maxima of an n x d array into mins/maxs (either may be
 // null).  flag (device int, zeroed by the caller) is set when a value is NaN
 // or infinite.

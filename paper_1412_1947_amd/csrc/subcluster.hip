@@ -29,6 +29,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <cstring>
 
 #pragma clang fp contract(off)
 
@@ -382,6 +383,88 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
     }
 }
 
+template <int W>
+struct VecT;
+template <>
+struct VecT<1> {
+    typedef float type;
+};
+template <>
+struct VecT<4> {
+    typedef float4 type;
+};
+
+__device__ __forceinline__ float vget(const float &v, int) { return v; }
+__device__ __forceinline__ float vget(const float4 &v, int c) {
+    return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+}
+
+template <int W>
+__device__ void scatter_rows(const float *__restrict__ S, int d, uint32_t cnt, const int32_t *s_src,
+                             const int32_t *s_dst, int track_min, float *__restrict__ P,
+                             int64_t off_t, uint32_t *s_cmin) {
+    typedef typename VecT<W>::type V;
+    constexpr int U = 4;
+    const uint32_t dq = (uint32_t)d / W;
+    const uint32_t total = cnt * dq;
+    const uint32_t dr = kT / dq, dj = kT % dq;
+    // a thread keeps its attribute group when kT is a multiple of dq
+    const bool fixed = (kT % dq) == 0;
+    uint32_t mymin[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) mymin[c] = 0xFFFFFFFFu;
+    uint32_t r = threadIdx.x / dq, j = threadIdx.x % dq;
+    const uint32_t j_fixed = j;
+    for (uint32_t e = threadIdx.x; e < total; e += U * kT) {
+        V v[U];
+        int kind[U];  // 0: nothing to do, 1: copy to P row prow[u], 2: stays (minimum)
+        int32_t prow[U];
+        uint32_t jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            kind[u] = 0;
+            prow[u] = 0;
+            jj[u] = j;
+            if (e + u * kT < total) {
+                const int32_t dst = s_dst[r];
+                if (dst != INT32_MIN) {
+                    v[u] = ((const V *)(S + (int64_t)s_src[r] * d))[j];
+                    if (dst >= 0) {
+                        kind[u] = 1;
+                        prow[u] = dst;
+                    } else {
+                        kind[u] = 2;
+                    }
+                }
+            }
+            r += dr;
+            j += dj;
+            if (j >= dq) {
+                j -= dq;
+                ++r;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (kind[u] == 1) {
+                ((V *)(P + ((int64_t)off_t + prow[u]) * d))[jj[u]] = v[u];
+            } else if (kind[u] == 2 && track_min) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) {
+                    const uint32_t o = ordered_bits(vget(v[u], c));
+                    if (fixed) mymin[c] = min(mymin[c], o);
+                    else atomicMin(&s_cmin[jj[u] * W + c], o);
+                }
+            }
+        }
+    }
+    if (track_min && fixed && j_fixed < dq) {
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+            if (mymin[c] != 0xFFFFFFFFu) atomicMin(&s_cmin[j_fixed * W + c], mymin[c]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Stable compaction of one block of kBS positions.  all_sel: every remaining
 // point is selected (last round).  track_min: write the attribute-wise
@@ -394,7 +477,7 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
                                                 int all_sel, int track_min, float *__restrict__ P,
                                                 int32_t *__restrict__ perm, int64_t off_t,
                                                 int32_t *__restrict__ rem_next,
-                                                uint32_t *__restrict__ Lpart) {
+                                                uint32_t *__restrict__ Lpart, int vec4) {
     __shared__ int32_t s_src[kBS];
     __shared__ int32_t s_dst[kBS];  // >= 0: P row; < 0: -(1 + slot) in rem_next
     __shared__ uint32_t tmp[kT / 64];
@@ -445,41 +528,20 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
             }
         }
     }
-    const bool fixed_col = (kT % d) == 0;
-    if (track_min && !fixed_col)
+    if (track_min)
         for (int j = threadIdx.x; j < d; j += kT) s_cmin[j] = 0xFFFFFFFFu;
     __syncthreads();
-    // rows: copy the selected ones, reduce the minimum of the others
-    uint32_t my_min = 0xFFFFFFFFu;
-    const int64_t total = (int64_t)cnt * d;
+    // Rows: copy the selected ones, reduce the minimum of the others.  The
+    // block's rows are walked as a flat array of W-float vectors (W = 4 when
+    // d % 4 == 0), stepped by kT with no division in the loop; U vectors are
+    // loaded before any is used so that several loads are in flight.
     if (track_min || tot > 0) {
-        for (int64_t e = threadIdx.x; e < total; e += kT) {
-            const uint32_t r = (uint32_t)(e / d);
-            const uint32_t j = (uint32_t)(e - (int64_t)r * d);
-            const int32_t dst = s_dst[r];
-            if (dst == INT32_MIN) continue;
-            if (dst >= 0) {
-                P[((int64_t)off_t + dst) * d + j] = S[(int64_t)s_src[r] * d + j];
-            } else if (track_min) {
-                const uint32_t o = ordered_bits(S[(int64_t)s_src[r] * d + j]);
-                if (fixed_col) my_min = min(my_min, o);
-                else atomicMin(&s_cmin[j], o);
-            }
-        }
+        if (vec4) scatter_rows<4>(S, d, cnt, s_src, s_dst, track_min, P, off_t, s_cmin);
+        else scatter_rows<1>(S, d, cnt, s_src, s_dst, track_min, P, off_t, s_cmin);
     }
     if (track_min) {
-        if (fixed_col) {
-            s_min[threadIdx.x] = my_min;
-            __syncthreads();
-            for (int j = threadIdx.x; j < d; j += kT) {
-                uint32_t m = 0xFFFFFFFFu;
-                for (int t = j; t < kT; t += d) m = min(m, s_min[t]);
-                Lpart[(int64_t)blockIdx.x * d + j] = m;
-            }
-        } else {
-            __syncthreads();
-            for (int j = threadIdx.x; j < d; j += kT) Lpart[(int64_t)blockIdx.x * d + j] = s_cmin[j];
-        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < d; j += kT) Lpart[(int64_t)blockIdx.x * d + j] = s_cmin[j];
     }
 }
 
@@ -489,10 +551,14 @@ __global__ __launch_bounds__(kST) void k_lfin(const uint32_t *__restrict__ Lpart
     extern __shared__ uint32_t s_m[];  // d words
     for (int j = threadIdx.x; j < d; j += kST) s_m[j] = 0xFFFFFFFFu;
     __syncthreads();
-    const int64_t total = (int64_t)nb * d;
-    for (int64_t e = threadIdx.x; e < total; e += kST) {
+    const uint32_t total = nb * (uint32_t)d;
+    const uint32_t dj = kST % d;
+    uint32_t j = threadIdx.x % d;
+    for (uint32_t e = threadIdx.x; e < total; e += kST) {
         const uint32_t v = Lpart[e];
-        if (v != 0xFFFFFFFFu) atomicMin(&s_m[e % d], v);
+        if (v != 0xFFFFFFFFu) atomicMin(&s_m[j], v);
+        j += dj;
+        if (j >= (uint32_t)d) j -= d;
     }
     __syncthreads();
     for (int j = threadIdx.x; j < d; j += kST) L[j] = ordered_float(s_m[j]);
@@ -508,6 +574,11 @@ __global__ void k_fill_u32(uint32_t *a, uint32_t n, uint32_t v) {
     if (i < n) a[i] = v;
 }
 
+__global__ void k_copy_f32(float *dst, const float *src, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 __global__ void k_offsets(int64_t *off, int64_t T, int64_t N, int64_t n) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t <= T) off[t] = t < T ? t * N : n;
@@ -517,46 +588,69 @@ __global__ void k_offsets(int64_t *off, int64_t T, int64_t N, int64_t n) {
 
 subkm_status minmax_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *mins,
                          float *maxs, int *flag);
+size_t minmax_scratch_bytes(int64_t n, int32_t d);
 
-subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
-                             int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
-                             float *landmarks) {
+namespace {
+
+struct SubBufs {
+    double *keys;
+    int32_t *rem0, *rem1;
+    char *cand, *sel;
+    float *land, *colmax;
+    int *flag;
+};
+
+// Scratch of one subclustering call (allocated before any capture).
+subkm_status sub_alloc(subkm_ctx *ctx, int64_t n, int32_t d, SubBufs &b) {
+    const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
+    b.keys = (double *)ctx_scratch(ctx, SC_KEYS, sizeof(double) * n);
+    b.rem0 = (int32_t *)ctx_scratch(ctx, SC_REM0, sizeof(int32_t) * n);
+    b.rem1 = (int32_t *)ctx_scratch(ctx, SC_REM1, sizeof(int32_t) * n);
+    b.cand = (char *)ctx_scratch(ctx, SC_CAND, (sizeof(double) + sizeof(uint32_t)) * n + 64);
+    const size_t sel_words = 2 * (size_t)kRep * kBins + 3 * (size_t)nb_max + 64;
+    b.sel = (char *)ctx_scratch(ctx, SC_SEL, 256 + sizeof(uint32_t) * sel_words);
+    b.land = (float *)ctx_scratch(ctx, SC_LAND, sizeof(float) * ((size_t)d * (nb_max + 1) + 64));
+    b.colmax = (float *)ctx_scratch(ctx, SC_COLMAX, sizeof(float) * d + 64);
+    b.flag = (int *)ctx_scratch(ctx, SC_MM_FLAG, 256);
+    void *mm = ctx_scratch(ctx, SC_MM_PART, minmax_scratch_bytes(n, d));
+    if (!b.keys || !b.rem0 || !b.rem1 || !b.cand || !b.sel || !b.land || !b.colmax || !b.flag || !mm)
+        return SUBKM_ENOMEM;
+    return SUBKM_OK;
+}
+
+// Every launch of one subclustering call, in order, on ctx->stream.
+subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64_t n, int32_t d,
+                         int64_t N, int32_t landmark_mode, float *P, int32_t *perm,
+                         int64_t *offsets, float *landmarks) {
     const int64_t T = ceil_div(n, N);
     hipStream_t s = ctx->stream;
     const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
-    double *keys = (double *)ctx_scratch(ctx, SC_KEYS, sizeof(double) * n);
-    int32_t *rem0 = (int32_t *)ctx_scratch(ctx, SC_REM0, sizeof(int32_t) * n);
-    int32_t *rem1 = (int32_t *)ctx_scratch(ctx, SC_REM1, sizeof(int32_t) * n);
-    char *cand = (char *)ctx_scratch(ctx, SC_CAND, (sizeof(double) + sizeof(uint32_t)) * n + 64);
-    const size_t sel_words = 2 * (size_t)kRep * kBins + 3 * (size_t)nb_max + 64;
-    char *sel = (char *)ctx_scratch(ctx, SC_SEL, 256 + sizeof(uint32_t) * sel_words);
-    float *land = (float *)ctx_scratch(ctx, SC_LAND, sizeof(float) * ((size_t)d * (nb_max + 1) + 64));
-    float *colmax = (float *)ctx_scratch(ctx, SC_COLMAX, sizeof(float) * d + 64);
-    int *flag = (int *)ctx_scratch(ctx, SC_MM_FLAG, 256);
-    if (!keys || !rem0 || !rem1 || !cand || !sel || !land || !colmax || !flag)
-        return SUBKM_ENOMEM;
-    SelState *st = (SelState *)sel;
-    uint32_t *hist1 = (uint32_t *)(sel + 256);
+    SelState *st = (SelState *)b.sel;
+    uint32_t *hist1 = (uint32_t *)(b.sel + 256);
     uint32_t *hist2 = hist1 + kRep * kBins;
     uint32_t *blockcnt = hist2 + kRep * kBins;
     uint32_t *blockoff = blockcnt + nb_max;
     uint32_t *ccount = blockoff + nb_max;
-    double *ckey = (double *)cand;
-    uint32_t *cpos = (uint32_t *)(cand + sizeof(double) * n);
-    float *L = land;
-    uint32_t *Lpart = (uint32_t *)(land + d);
+    double *ckey = (double *)b.cand;
+    uint32_t *cpos = (uint32_t *)(b.cand + sizeof(double) * n);
+    float *L = b.land;
+    uint32_t *Lpart = (uint32_t *)(b.land + d);
+    double *keys = b.keys;
+    int32_t *rem0 = b.rem0, *rem1 = b.rem1;
+    const float *colmax = b.colmax;
 
     // histogram replicas start at zero (the select kernels re-zero them)
     const uint32_t nzero = (uint32_t)(2 * kRep * kBins);
     hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(nzero, 256)), dim3(256), 0, s, hist1, nzero, 0u);
     SUBKM_LAUNCHED(ctx);
     // first landmark: attribute-wise minimum of all points; column maxima bound the keys
-    SUBKM_TRY(minmax_impl(ctx, S, n, d, L, colmax, flag));
+    SUBKM_TRY(minmax_impl(ctx, S, n, d, L, b.colmax, b.flag));
     hipLaunchKernelGGL(k_offsets, dim3(ceil_div(T + 1, 256)), dim3(256), 0, s, offsets, T, N, n);
     SUBKM_LAUNCHED(ctx);
 
     const bool fixed = landmark_mode == 1;
     const bool vec4 = (d % 4) == 0 && ((uintptr_t)S % 16) == 0;
+    const bool vec4p = vec4 && ((uintptr_t)P % 16) == 0;
     int32_t *cur = nullptr;  // round 0 reads the points through the identity
     int32_t *nxt = rem0;
     uint32_t nrem = (uint32_t)n;
@@ -591,13 +685,15 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
                                hist2, blockcnt, blockoff);
             SUBKM_LAUNCHED(ctx);
         } else if (lm_t) {
-            SUBKM_HIP(ctx, hipMemcpyAsync(lm_t, L, sizeof(float) * d, hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_copy_f32, dim3(ceil_div(d, 256)), dim3(256), 0, s, lm_t, L, d);
+            SUBKM_LAUNCHED(ctx);
         }
         const bool track = !all && !fixed;
         {
             ProfScope psc(ctx, PK_SCATTER);
             hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kT), dyn_d, s, S, d, cur, keys, nrem, need,
-                               st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt, Lpart);
+                               st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt, Lpart,
+                               vec4p ? 1 : 0);
             SUBKM_LAUNCHED(ctx);
         }
         if (track) {
@@ -609,5 +705,62 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
         nxt = (written == rem0) ? rem1 : rem0;
         cur = written;
     }
+    return SUBKM_OK;
+}
+
+}  // namespace
+
+// The whole sequence (3 + about 6 T launches) is captured once into a HIP
+// graph per (inputs, outputs, sizes, scratch buffers) and replayed, which
+// removes the launch gaps between the many short kernels.  The graph holds
+// kernel nodes only.
+subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
+                             int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
+                             float *landmarks) {
+    SubBufs b;
+    SUBKM_TRY(sub_alloc(ctx, n, d, b));
+    const uint64_t key[12] = {(uint64_t)(uintptr_t)S, (uint64_t)n, (uint64_t)d, (uint64_t)N,
+                              (uint64_t)landmark_mode, (uint64_t)(uintptr_t)P,
+                              (uint64_t)(uintptr_t)perm, (uint64_t)(uintptr_t)offsets,
+                              (uint64_t)(uintptr_t)landmarks, ctx->scratch_epoch,
+                              (uint64_t)(uintptr_t)ctx, 0x5c1ull};
+    auto &g = ctx->subg;
+    if (!(g.valid && std::memcmp(g.key, key, sizeof key) == 0)) {
+        if (g.exec) {
+            hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+        g.valid = false;
+        if (!ctx->cap_stream)
+            SUBKM_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = ctx->stream;
+        const bool prof = ctx->prof_on;
+        ctx->stream = ctx->cap_stream;
+        ctx->prof_on = false;
+        hipGraph_t graph = nullptr;
+        subkm_status st = SUBKM_OK;
+        hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            st = sub_enqueue(ctx, b, S, n, d, N, landmark_mode, P, perm, offsets, landmarks);
+            e = hipStreamEndCapture(ctx->cap_stream, &graph);
+        }
+        ctx->stream = user;
+        ctx->prof_on = prof;
+        if (st != SUBKM_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return set_err(ctx, SUBKM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g.exec = nullptr;
+            return set_err(ctx, SUBKM_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        std::memcpy(g.key, key, sizeof key);
+        g.valid = true;
+    }
+    ProfScope ps(ctx, PK_SUBCLUSTER);
+    SUBKM_HIP(ctx, hipGraphLaunch(g.exec, ctx->stream));
     return SUBKM_OK;
 }
