@@ -895,17 +895,26 @@ __global__ void k_init(const float *__restrict__ P, const DevRun *__restrict__ r
     }
 }
 
-__global__ void k_finalize(const DevRun *__restrict__ runs, const RunState *__restrict__ rstate,
-                           const double *__restrict__ objpart, int R, int32_t *iters, double *sse,
-                           unsigned long long *rechecks) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
+// Objective of every run: the per-tile partials summed in a fixed order (each
+// thread a contiguous range, then a fixed tree), one block per run.
+__global__ __launch_bounds__(kAT) void k_finalize(const DevRun *__restrict__ runs,
+                                                  const RunState *__restrict__ rstate,
+                                                  const double *__restrict__ objpart,
+                                                  int32_t *iters, double *sse,
+                                                  unsigned long long *rechecks) {
+    __shared__ double s_red[kAT];
+    const int r = blockIdx.x;
     const DevRun D = runs[r];
+    const int per = (D.nitems + kAT - 1) / kAT;
+    const int q0 = threadIdx.x * per, q1 = min(D.nitems, q0 + per);
     double s = 0.0;
-    for (int q = 0; q < D.nitems; ++q) s = s + objpart[D.item0 + q];
-    sse[r] = s;
-    if (iters) iters[r] = rstate[r].iters;
-    if (rechecks) atomicAdd(rechecks, rstate[r].rechecks);
+    for (int q = q0; q < q1; ++q) s = s + objpart[D.item0 + q];
+    const double tot = block_sum_det(s, s_red);
+    if (threadIdx.x == 0) {
+        sse[r] = tot;
+        if (iters) iters[r] = rstate[r].iters;
+        if (rechecks) atomicAdd(rechecks, rstate[r].rechecks);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1216,7 +1225,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         }
         hipLaunchKernelGGL(k_box_init, dim3(R), dim3(256), 0, s, d_runs, d_box);
         SUBKM_LAUNCHED(ctx);
-        hipLaunchKernelGGL(k_runbox, dim3(std::min<int64_t>(ceil_div(nmax, 2048), 128), R), dim3(256),
+        hipLaunchKernelGGL(k_runbox, dim3(std::min<int64_t>(ceil_div(nmax, 2048), 1024), R), dim3(256),
                            2 * sizeof(uint32_t) * dmax, s, P, d_runs, d_box, d_rs);
         SUBKM_LAUNCHED(ctx);
     }
@@ -1292,8 +1301,8 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
             }
         }
     }
-    hipLaunchKernelGGL(k_finalize, dim3(ceil_div(R, 256)), dim3(256), 0, s, d_runs, d_rs, d_obj, R,
-                       iters, sse, d_rechecks);
+    hipLaunchKernelGGL(k_finalize, dim3(R), dim3(kAT), 0, s, d_runs, d_rs, d_obj, iters, sse,
+                       d_rechecks);
     SUBKM_LAUNCHED(ctx);
     if (batched) {
         // a barrier that gave up would leave wrong results: report it

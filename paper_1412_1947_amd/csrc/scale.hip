@@ -77,19 +77,33 @@ __global__ __launch_bounds__(kThreads) void k_minmax_wide(const float *__restric
     if (bad) atomicOr(flag, 1);
 }
 
-// second stage: one thread per column over the block partials
-__global__ void k_minmax_final(const float *__restrict__ pmin, const float *__restrict__ pmax,
-                               int parts, int d, float *__restrict__ mins,
-                               float *__restrict__ maxs) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d) return;
+// second stage: one block per column, a strided pass over the block
+// partials and a tree in LDS (min and max are exact in any order)
+__global__ __launch_bounds__(256) void k_minmax_final(const float *__restrict__ pmin,
+                                                      const float *__restrict__ pmax, int parts,
+                                                      int d, float *__restrict__ mins,
+                                                      float *__restrict__ maxs) {
+    __shared__ float sa[256], sb[256];
+    const int c = blockIdx.x;
     float a = INFINITY, b = -INFINITY;
-    for (int p = 0; p < parts; ++p) {
+    for (int p = threadIdx.x; p < parts; p += 256) {
         a = fminf(a, pmin[(int64_t)p * d + c]);
         b = fmaxf(b, pmax[(int64_t)p * d + c]);
     }
-    if (mins) mins[c] = a;
-    if (maxs) maxs[c] = b;
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sa[threadIdx.x] = fminf(sa[threadIdx.x], sa[threadIdx.x + s]);
+            sb[threadIdx.x] = fmaxf(sb[threadIdx.x], sb[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (mins) mins[c] = sa[0];
+        if (maxs) maxs[c] = sb[0];
+    }
 }
 
 __device__ __forceinline__ float scale_one(float x, float mn, float mx) {
@@ -173,7 +187,7 @@ subkm_status minmax_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, f
         hipLaunchKernelGGL(k_minmax_wide, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n,
                            d, p.rows_per_block, pmin, pmax, flag);
     SUBKM_LAUNCHED(ctx);
-    hipLaunchKernelGGL(k_minmax_final, dim3(ceil_div(d, 256)), dim3(256), 0, ctx->stream, pmin,
+    hipLaunchKernelGGL(k_minmax_final, dim3(d), dim3(256), 0, ctx->stream, pmin,
                        pmax, (int)p.blocks, d, mins, maxs);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;

@@ -308,6 +308,20 @@ __device__ void slow_select(const double *ckey, const uint32_t *cpos, const uint
     *thr_pos = ppre;
 }
 
+// Flat view of the candidate segments: candidate i (0 <= i < total) lives in
+// segment seg with cstart[seg] <= i < cstart[seg + 1].
+__device__ __forceinline__ uint32_t seg_of(const uint32_t *cstart, uint32_t nb, uint32_t i) {
+    uint32_t lo = 0, hi = nb;  // largest seg with cstart[seg] <= i
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (cstart[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+constexpr uint32_t kSegCap = 4096;  // segments handled in LDS by k_sel2
+
 __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
                                               const double *__restrict__ ckey,
                                               const uint32_t *__restrict__ cpos,
@@ -318,19 +332,43 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
     __shared__ double rk[kRankCap];
     __shared__ uint32_t rp[kRankCap];
     __shared__ uint32_t h256[256];
+    __shared__ uint32_t cstart[kSegCap + 1];
+    __shared__ uint32_t csel[kSegCap];
     const uint32_t astar = st->astar, base = st->base;
     const uint32_t need1 = need - st->below1;
     uint32_t b, below2, cnt2;
     merge_find_bin(hist2, need1, sh, tmp, &b, &below2, &cnt2);
     const uint32_t need2 = need1 - below2;
     const uint32_t vstar = (astar << 12) | b;
+    const bool flat = nb <= kSegCap;
+    uint32_t total = 0;
+    if (flat) {
+        // start of every segment in the flat candidate order
+        uint32_t carry = 0;
+        for (uint32_t c0 = 0; c0 < nb; c0 += kST) {
+            const uint32_t sgi = c0 + threadIdx.x;
+            const uint32_t v = sgi < nb ? ccount[sgi] : 0u;
+            uint32_t tot;
+            const uint32_t pre = block_scan<kST>(v, tmp, &tot);
+            if (sgi < nb) {
+                cstart[sgi] = carry + pre;
+                csel[sgi] = 0;
+            }
+            carry += tot;
+        }
+        total = carry;
+        if (threadIdx.x == 0) cstart[nb] = total;
+        __syncthreads();
+    }
     double thr_key;
     uint32_t thr_pos;
     if (cnt2 <= (uint32_t)kRankCap) {
         if (threadIdx.x == 0) s_n = 0;
         __syncthreads();
-        for (uint32_t s = threadIdx.x; s < nb; s += kST) {
-            for (uint32_t c = s * kBS; c < s * kBS + ccount[s]; ++c) {
+        if (flat) {
+            for (uint32_t i = threadIdx.x; i < total; i += kST) {
+                const uint32_t sg = seg_of(cstart, nb, i);
+                const uint32_t c = sg * kBS + (i - cstart[sg]);
                 const double k = ckey[c];
                 if (vmap(k, base) == vstar) {
                     const uint32_t q = atomicAdd(&s_n, 1u);
@@ -340,6 +378,18 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
                     }
                 }
             }
+        } else {
+            for (uint32_t sg = threadIdx.x; sg < nb; sg += kST)
+                for (uint32_t c = sg * kBS; c < sg * kBS + ccount[sg]; ++c) {
+                    const double k = ckey[c];
+                    if (vmap(k, base) == vstar) {
+                        const uint32_t q = atomicAdd(&s_n, 1u);
+                        if (q < (uint32_t)kRankCap) {
+                            rk[q] = k;
+                            rp[q] = cpos[c];
+                        }
+                    }
+                }
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt2; i += kST) {
@@ -359,18 +409,30 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
     }
     // the candidates at or below the threshold join their block's count;
     // then block counts become block offsets of the selected rows
+    if (flat) {
+        for (uint32_t i = threadIdx.x; i < total; i += kST) {
+            const uint32_t sg = seg_of(cstart, nb, i);
+            const uint32_t c = sg * kBS + (i - cstart[sg]);
+            if (pair_le(ckey[c], cpos[c], thr_key, thr_pos)) atomicAdd(&csel[sg], 1u);
+        }
+        __syncthreads();
+    }
     uint32_t carry = 0;
     for (uint32_t c0 = 0; c0 < nb; c0 += kST) {
-        const uint32_t s = c0 + threadIdx.x;
+        const uint32_t sg = c0 + threadIdx.x;
         uint32_t v = 0;
-        if (s < nb) {
-            v = blockcnt[s];
-            for (uint32_t c = s * kBS; c < s * kBS + ccount[s]; ++c)
-                v += pair_le(ckey[c], cpos[c], thr_key, thr_pos) ? 1u : 0u;
+        if (sg < nb) {
+            v = blockcnt[sg];
+            if (flat) {
+                v += csel[sg];
+            } else {
+                for (uint32_t c = sg * kBS; c < sg * kBS + ccount[sg]; ++c)
+                    v += pair_le(ckey[c], cpos[c], thr_key, thr_pos) ? 1u : 0u;
+            }
         }
         uint32_t tot;
         const uint32_t pre = block_scan<kST>(v, tmp, &tot);
-        if (s < nb) blockoff[s] = carry + pre;
+        if (sg < nb) blockoff[sg] = carry + pre;
         carry += tot;
     }
     if (threadIdx.x == 0) {
