@@ -182,6 +182,7 @@ def main():
         "point_iters_per_step": point_iters,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phases_us": {k: st[k] for k in ("us_scale", "us_subcluster", "us_local", "us_final", "us_label")},
+        "rechecked_assignments_per_step": st["rechecked"],
         "kernels_ms_per_step": {c: v[1] / a.steps for c, v in prof.items() if v[0]},
         "roofline": roof, "roofline_other": {c: v for c, v in roofs.items() if c != dom},
         "plain": plain, "cpu_baseline": cpu,

@@ -205,6 +205,8 @@ typedef struct {
     double us_final;
     double us_label;
     double us_total;
+    int64_t rechecked;       /* point assignments redone in binary64 (local +
+                                final + labelling passes)                     */
 } subkm_stats;
 
 subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t N,

@@ -52,7 +52,7 @@ class Stats(ctypes.Structure):
                 ("final_point_iters", ctypes.c_int64), ("us_scale", ctypes.c_double),
                 ("us_subcluster", ctypes.c_double), ("us_local", ctypes.c_double),
                 ("us_final", ctypes.c_double), ("us_label", ctypes.c_double),
-                ("us_total", ctypes.c_double)]
+                ("us_total", ctypes.c_double), ("rechecked", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}

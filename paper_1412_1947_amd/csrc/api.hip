@@ -337,12 +337,14 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
     double *lsse = o.local_sse ? o.local_sse
                                : (double *)ctx_scratch(ctx, SC_CL_LSSE, T * sizeof(double));
     float *mm = (float *)ctx_scratch(ctx, SC_CL_MINMAX, 2 * (size_t)d * sizeof(float));
-    char *fin = (char *)ctx_scratch(ctx, SC_CL_FINAL, (size_t)M * 4 + 64);
+    char *fin = (char *)ctx_scratch(ctx, SC_CL_FINAL, (size_t)M * 4 + 128);
     if (!S || !P || !perm || !offs || !loc || !llab || !lit || !lsse || !mm || !fin)
         return SUBKM_ENOMEM;
     int32_t *fit = (int32_t *)fin;
     double *fsse = (double *)(fin + 16);
-    int32_t *flab = (int32_t *)(fin + 64);
+    unsigned long long *nrecheck = (unsigned long long *)(fin + 32);
+    int32_t *flab = (int32_t *)(fin + 128);
+    SUBKM_HIP(ctx, hipMemsetAsync(nrecheck, 0, sizeof(unsigned long long), s));
 
     hipEvent_t *ev = ctx->ev;
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[0], s));
@@ -366,17 +368,17 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
         m += u.k;
     }
     SUBKM_TRY(lloyd_impl(ctx, P, runs.data(), (int32_t)T, loc, llab, max_iter, tol, o.precision,
-                         o.form, lit, lsse, 1));
+                         o.form, lit, lsse, 1, nrecheck));
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[3], s));
     // final run on the local centers, strided start
     subkm_run fr{0, M, 0, 0, d, k_final};
     SUBKM_TRY(lloyd_impl(ctx, loc, &fr, 1, centers, flab, max_iter, tol, o.precision,
-                         SUBKM_FORM_BATCHED, fit, fsse, 2));
+                         SUBKM_FORM_BATCHED, fit, fsse, 2, nrecheck));
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[4], s));
     // labels of all points against the final centers (an assignment only)
     subkm_run lr{0, n, 0, 0, d, k_final};
     SUBKM_TRY(lloyd_impl(ctx, S, &lr, 1, centers, labels, 0, 0.0, o.precision,
-                         SUBKM_FORM_BATCHED, fit + 1, sse, 0));
+                         SUBKM_FORM_BATCHED, fit + 1, sse, 0, nrecheck));
     if (stats) {
         SUBKM_HIP(ctx, hipEventRecord(ev[5], s));
         SUBKM_HIP(ctx, hipEventSynchronize(ev[5]));
@@ -385,6 +387,9 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
         std::vector<int32_t> hit((size_t)T + 1);
         SUBKM_HIP(ctx, hipMemcpy(hit.data(), lit, T * sizeof(int32_t), hipMemcpyDeviceToHost));
         SUBKM_HIP(ctx, hipMemcpy(&hit[T], fit, sizeof(int32_t), hipMemcpyDeviceToHost));
+        unsigned long long nr = 0;
+        SUBKM_HIP(ctx, hipMemcpy(&nr, nrecheck, sizeof nr, hipMemcpyDeviceToHost));
+        stats->rechecked = (int64_t)nr;
         stats->T = T;
         stats->M = M;
         stats->final_iters = hit[T];

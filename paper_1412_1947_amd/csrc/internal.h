@@ -134,7 +134,7 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
 subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, int32_t R,
                         float *C, int32_t *labels, int32_t max_iter, double tol,
                         int32_t precision, int32_t form, int32_t *iters, double *sse,
-                        int init_mode);
+                        int init_mode, unsigned long long *rechecks_acc = nullptr);
 
 // ---------------------------------------------------------------------------
 // Small device helpers shared by the kernels.

@@ -46,6 +46,7 @@ constexpr int kMaxK = 1024;         // centers per run in the fused path
 constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path)
 constexpr int kUpdLdsWords = 6144;  // int64 sums per block (scan-update path)
 constexpr long long kSpinLimit = 1ll << 24;
+constexpr int kMaxG = 16;          // blocks per run in the batched form
 
 enum : int32_t { PH_ITER = 0, PH_FINAL = 1, PH_DONE = 2 };
 
@@ -147,19 +148,22 @@ __device__ double block_max(double v, double *sh) {
     return r;
 }
 
-// Fixed-point exponent s of a run: n * max|x| * 2^s stays below 2^61, so no
-// sum of the run can overflow int64.
+// Fixed point of the center sums.  Every coordinate is quantised to an
+// integer q = rint(x * 2^s) with s chosen per run so that |q| < 2^31
+// (|x| <= max|x| < 2^e, s = 31 - e); the error of one coordinate is at most
+// 2^-32 * 2^e <= 2^-31 max|x|, far below a float32 ulp of the mean.  The
+// integers are summed exactly in int64 (no overflow below 2^32 points), so a
+// sum does not depend on the order of the additions.
 __device__ __forceinline__ int fix_shift_of(uint32_t absmax_bits, int64_t n) {
-    float m = __uint_as_float(absmax_bits);
+    (void)n;
+    const float m = __uint_as_float(absmax_bits);
     int e = 0;
     if (m > 0.0f) frexpf(m, &e);  // m < 2^e
-    int lg = 0;
-    while ((1ll << lg) < n + 1) ++lg;
-    return 61 - e - lg;
+    return 31 - e;
 }
 
 __device__ __forceinline__ long long to_fixed(float x, int s) {
-    return (long long)rint(ldexp((double)x, s));
+    return (long long)(int)rintf(ldexpf(x, s));
 }
 
 // Float32 squared distances of this thread's point against centers sC[0..nc)
@@ -310,11 +314,31 @@ __device__ void center_norms(FusedLds &L, const uint32_t *box, int k, int ldk) {
 // final combination (with a factor 2 of margin).  Results go to L.s_lab.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Raw coordinates of a tile as the matrix-core lanes hold them: lane
+// (col = l % 16, kk = l / 16) of a wavefront holds attributes kk + 4 q of
+// point col of each of its four 16-point groups.  Loads are unconditional
+// (rows past n are clamped to the last row; their values are never used),
+// so all of them are in flight together.
 template <int D>
-__device__ void stage1_mfma(FusedLds &L, const float *X, int64_t first, int64_t n, int k, int ldk,
-                            const uint32_t *box) {
+__device__ __forceinline__ void load_tile(const float *X, int64_t first_w, int64_t n,
+                                          float (&xr)[4][D / 4]) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        int64_t p = first_w + g * 16 + col;
+        p = p < n ? p : n - 1;
+#pragma unroll
+        for (int q = 0; q < D / 4; ++q) xr[g][q] = X[p * D + kk + 4 * q];
+    }
+}
+
+template <int D>
+__device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t first_w, int64_t n,
+                            int k, int ldk, const uint32_t *box, int32_t *lab_out, bool accumulate,
+                            int shift, int32_t *wlab) {
     constexpr int KQ = D / 4;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int col = lane & 15, kk = lane >> 4;
     float mq[KQ];
 #pragma unroll
@@ -323,12 +347,11 @@ __device__ void stage1_mfma(FusedLds &L, const float *X, int64_t first, int64_t 
     float xn[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        const int64_t p = first + wave * 64 + g * 16 + col;
-        const bool ok = p < n;
+        const bool ok = first_w + g * 16 + col < n;
         float s2 = 0.0f;
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
-            const float v = ok ? X[p * D + kk + 4 * q] - mq[q] : 0.0f;
+            const float v = ok ? xr[g][q] - mq[q] : 0.0f;
             xb[g][q] = v;
             s2 = __builtin_fmaf(v, v, s2);
         }
@@ -344,25 +367,40 @@ __device__ void stage1_mfma(FusedLds &L, const float *X, int64_t first, int64_t 
         b2[g] = INFINITY;
         i1[g] = 0;
     }
+    // the bias ||c - m||^2 enters the product as one more K-step: lanes of
+    // K-slot 0 carry (||c - m||^2, 1), the others (0, 0); the centers are
+    // scaled by -2 (exact), so the accumulator is v itself
+    const float bb = kk == 0 ? 1.0f : 0.0f;
     for (int c0 = 0; c0 < k; c0 += 16) {
         const int cA = c0 + col;
+        // rows of sC are padded to k + 16 and cn holds +inf up to the next
+        // multiple of 16, so these reads stay inside the arrays; values of
+        // centers past k are discarded by the selects
         float ca[KQ];
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) ca[q] = cA < k ? L.sC[(kk + 4 * q) * ldk + cA] - mq[q] : 0.0f;
-        const floatx4 cnv = *(const floatx4 *)&L.cn[c0 + 4 * kk];
-        const int cbase = c0 + 4 * kk;
+        for (int q = 0; q < KQ; ++q) {
+            const float cv = L.sC[(kk + 4 * q) * ldk + cA];
+            ca[q] = cA < k ? -2.0f * (cv - mq[q]) : 0.0f;
+        }
+        const float cnv = L.cn[cA];
+        const float cb = kk == 0 ? cnv : 0.0f;
+        int32_t ci[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ci[r] = c0 + 4 * kk + r;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cb, bb, acc, 0, 0, 0);
 #pragma unroll
             for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[q], xb[g][q], acc, 0, 0, 0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float v = __builtin_fmaf(-2.0f, acc[r], cnv[r]);
-                b2[g] = fminf(b2[g], fmaxf(v, b1[g]));
+                const float v = acc[r];
+                // b1 <= b2 always holds, so the new second-smallest is the median
+                b2[g] = __builtin_amdgcn_fmed3f(v, b1[g], b2[g]);
                 const bool lt = v < b1[g];
                 b1[g] = lt ? v : b1[g];
-                i1[g] = lt ? cbase + r : i1[g];
+                i1[g] = lt ? ci[r] : i1[g];
             }
         }
     }
@@ -381,13 +419,71 @@ __device__ void stage1_mfma(FusedLds &L, const float *X, int64_t first, int64_t 
             i1[g] = take ? oi : i1[g];
             b2[g] = nb2;
         }
-        if (kk == 0) {
-            const float s = xn[g] + Rc;
-            const float E = Ku * s * s + 1e-30f;
-            const bool certain = k == 1 || (b2[g] - b1[g]) > 2.0f * E;
-            L.s_lab[wave * 64 + g * 16 + col] = i1[g] | (certain ? 0 : (int32_t)0x80000000);
+        // the four lanes of a point now agree on (b1, b2, i1)
+        const int64_t p = first_w + g * 16 + col;
+        const float s = xn[g] + Rc;
+        const float E = Ku * s * s + 1e-30f;
+        const bool certain = k == 1 || (b2[g] - b1[g]) > 2.0f * E;
+        if (p < n && certain) {
+            // a certain point is labelled and added to its center right here,
+            // from the registers that hold it (each lane its KQ attributes)
+            if (kk == 0) lab_out[p] = i1[g];
+            if (accumulate) {
+                if (kk == 0) atomicAdd(&L.s_cnt[i1[g]], 1u);
+                long long *row = L.s_sum + i1[g] * D;
+#pragma unroll
+                for (int q = 0; q < KQ; ++q)
+                    atomicAdd((unsigned long long *)&row[kk + 4 * q],
+                              (unsigned long long)to_fixed(xr[g][q], shift));
+            }
+        }
+        if (kk == 0) wlab[g * 16 + col] = i1[g] | (certain ? 0 : (int32_t)0x80000000);
+    }
+}
+
+// Matrix-core tile of one wavefront (64 points, first_w .. first_w + 63):
+// stage 1 labels (and, if asked, accumulates) every point whose nearest center
+// is certain; the uncertain ones are re-assigned in binary64 by the whole
+// wavefront, one after the other, then labelled and accumulated by their own
+// lane.  No block barrier: only the wavefront's own LDS slice is exchanged.
+// On the final pass (no accumulation) every lane returns the binary64
+// objective of its point.
+template <int D>
+__device__ double wave_tile_mf(FusedLds &L, const float (&xr)[4][D / 4], const float *X,
+                               int64_t first_w, int64_t n, int k, int ldk, const uint32_t *box,
+                               int32_t *lab_out, bool accumulate, int shift,
+                               unsigned long long &nrecheck) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t *wlab = L.s_lab + wave * 64;
+    const int64_t i = first_w + lane;
+    const bool valid = i < n;
+    const float *xg = X + (valid ? i : 0) * D;
+    stage1_mfma<D>(L, xr, first_w, n, k, ldk, box, lab_out, accumulate, shift, wlab);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int32_t sl = wlab[lane];
+    int32_t i1 = sl & 0x7fffffff;
+    unsigned long long todo = __ballot(valid && sl < 0);
+    nrecheck += (unsigned long long)__popcll(todo);
+    while (todo) {
+        const int t = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int32_t w = wave_argmin64_lds<true>(X + (first_w + t) * D, L.sC, D, k, ldk);
+        if (lane == t) {
+            i1 = w;
+            lab_out[i] = w;
+            if (accumulate) {
+                atomicAdd(&L.s_cnt[w], 1u);
+                long long *row = L.s_sum + w * D;
+                for (int j = 0; j < D; ++j)
+                    atomicAdd((unsigned long long *)&row[j], (unsigned long long)to_fixed(xg[j], shift));
+            }
         }
     }
+    double obj = 0.0;
+    if (valid && !accumulate) obj = dist64_lds<true>(xg, L.sC, i1, D, ldk);
+    return obj;
 }
 
 // Assign one tile of up to 256 points of a run against all k centers held in
@@ -404,13 +500,7 @@ __device__ double fused_tile(FusedLds &L, const float *X, int64_t first, int64_t
     if (threadIdx.x == 0) L.s_nlist = 0;
     int32_t i1;
     bool certain;
-    if constexpr (MF) {
-        stage1_mfma<D>(L, X, first, n, k, ldk, box);
-        __syncthreads();
-        const int32_t sl = L.s_lab[threadIdx.x];
-        i1 = sl & 0x7fffffff;
-        certain = sl >= 0;
-    } else {
+    {
         float x[D > 0 ? D : 1];
         if (D > 0) {
 #pragma unroll
@@ -439,7 +529,7 @@ __device__ double fused_tile(FusedLds &L, const float *X, int64_t first, int64_t
     double obj = 0.0;
     if (valid) {
         lab_out[i] = i1;
-        obj = dist64_lds<MF>(xg, L.sC, i1, d, ldk);
+        if (!accumulate) obj = dist64_lds<MF>(xg, L.sC, i1, d, ldk);
         if (accumulate) {
             atomicAdd(&L.s_cnt[i1], 1u);
             long long *row = L.s_sum + i1 * d;
@@ -525,14 +615,45 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
             const bool last = it == max_iter || converged;
             for (int e = threadIdx.x; e < kd; e += kAT) L.s_sum[e] = 0;
             for (int c = threadIdx.x; c < k; c += kAT) L.s_cnt[c] = 0;
-            for (int64_t t = t0; t < t1; ++t) {
-                const double obj = fused_tile<D, MF>(L, X, t * kAT, R.n, d, k, ldk, box, lab, !last,
-                                                     shift, &rs->rechecks);
-                if (last) {
-                    // objective per tile, summed over tiles in order by the
-                    // finalize kernel: the same rounding as the plain form
-                    const double tot = block_sum_det(obj, L.s_red);
-                    if (threadIdx.x == 0) objpart[R.item0 + t] = tot;
+            if constexpr (MF) {
+                // the next tile's points are loaded while this one computes
+                // (for narrow points; wide ones would need too many registers)
+                constexpr bool kPrefetch = D <= 32;
+                const int64_t wofs = (threadIdx.x >> 6) * 64;
+                float xr[4][D / 4], xq[4][D / 4];
+                unsigned long long nre = 0;
+                if (t0 < t1) load_tile<D>(X, t0 * kAT + wofs, R.n, xr);
+                __syncthreads();  // sums and counts are zeroed
+                for (int64_t t = t0; t < t1; ++t) {
+                    if constexpr (kPrefetch) {
+                        if (t + 1 < t1) load_tile<D>(X, (t + 1) * kAT + wofs, R.n, xq);
+                    } else {
+                        if (t > t0) load_tile<D>(X, t * kAT + wofs, R.n, xr);
+                    }
+                    const double obj = wave_tile_mf<D>(L, xr, X, t * kAT + wofs, R.n, k, ldk, box, lab,
+                                                       !last, shift, nre);
+                    if (last) {
+                        // objective per tile, summed over tiles in order by the
+                        // finalize kernel: the same rounding as the plain form
+                        const double tot = block_sum_det(obj, L.s_red);
+                        if (threadIdx.x == 0) objpart[R.item0 + t] = tot;
+                    }
+                    if constexpr (kPrefetch) {
+#pragma unroll
+                        for (int g = 0; g < 4; ++g)
+#pragma unroll
+                            for (int q = 0; q < D / 4; ++q) xr[g][q] = xq[g][q];
+                    }
+                }
+                if ((threadIdx.x & 63) == 0 && nre) atomicAdd(&rs->rechecks, nre);
+            } else {
+                for (int64_t t = t0; t < t1; ++t) {
+                    const double obj = fused_tile<D, MF>(L, X, t * kAT, R.n, d, k, ldk, box, lab,
+                                                         !last, shift, &rs->rechecks);
+                    if (last) {
+                        const double tot = block_sum_det(obj, L.s_red);
+                        if (threadIdx.x == 0) objpart[R.item0 + t] = tot;
+                    }
                 }
             }
             if (last) {
@@ -541,37 +662,48 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
             }
             __syncthreads();
             if (G > 1) {
-                // publish this block's sums, wait for the run's other blocks,
-                // then add all parts in block order (exact integer sums)
+                // Publish this block's sums, wait for the run's other blocks,
+                // then add all parts in block order (exact integer sums).  The
+                // parts are written and read with agent-scope atomic stores
+                // and loads, which the hardware performs at the device's
+                // coherence point; every thread waits for its own stores to
+                // complete before the block arrives, so a block that sees
+                // all arrivals also sees all parts.  No cache-wide fence.
                 long long *slot = parts + R.part_off + ((int64_t)(it & 1) * G + tk.g) * (kd + k);
-                for (int e = threadIdx.x; e < kd; e += kAT) slot[e] = L.s_sum[e];
-                for (int c = threadIdx.x; c < k; c += kAT) slot[kd + c] = (long long)L.s_cnt[c];
-                __threadfence();
+                for (int e = threadIdx.x; e < kd; e += kAT)
+                    __hip_atomic_store(&slot[e], L.s_sum[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int c = threadIdx.x; c < k; c += kAT)
+                    __hip_atomic_store(&slot[kd + c], (long long)L.s_cnt[c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
                 if (threadIdx.x == 0) {
-                    atomicAdd(&rs->arrive, 1u);
+                    __hip_atomic_fetch_add(&rs->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     const uint32_t target = (uint32_t)G * (uint32_t)(it + 1);
                     long long spins = 0;
                     while (__hip_atomic_load(&rs->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                        __builtin_amdgcn_s_sleep(2);
+                        __builtin_amdgcn_s_sleep(1);
                         if (++spins > kSpinLimit) {
                             atomicOr(err, 1);
                             break;
                         }
                     }
-                    __threadfence();
                 }
                 __syncthreads();
                 const long long *base = parts + R.part_off + (int64_t)(it & 1) * G * (kd + k);
-                for (int e = threadIdx.x; e < kd; e += kAT) {
+                // all G loads of an element are issued before any is used
+                for (int e = threadIdx.x; e < kd + k; e += kAT) {
+                    long long v[kMaxG];
+#pragma unroll
+                    for (int q = 0; q < kMaxG; ++q)
+                        v[q] = q < G ? __hip_atomic_load(&base[(int64_t)q * (kd + k) + e], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                     : 0ll;
                     long long a = 0;
-                    for (int q = 0; q < G; ++q) a += base[(int64_t)q * (kd + k) + e];
-                    L.s_sum[e] = a;
-                }
-                for (int c = threadIdx.x; c < k; c += kAT) {
-                    long long a = 0;
-                    for (int q = 0; q < G; ++q) a += base[(int64_t)q * (kd + k) + kd + c];
-                    L.s_cnt[c] = (unsigned int)a;
+#pragma unroll
+                    for (int q = 0; q < kMaxG; ++q) a += v[q];
+                    if (e < kd) L.s_sum[e] = a;
+                    else L.s_cnt[e - kd] = (unsigned int)a;
                 }
                 __syncthreads();
             }
@@ -611,8 +743,19 @@ __global__ __launch_bounds__(kAT) void k_assign_acc(const float *__restrict__ P,
     for (int c = threadIdx.x; c < k; c += kAT) L.s_cnt[c] = 0;
     __syncthreads();
     if constexpr (MF) center_norms<D>(L, box, k, ldk);
-    const double obj = fused_tile<D, MF>(L, P + R.x_off, itm.first, R.n, d, k, ldk, box,
-                                         labels + R.lab_off, acc, shift, &rs->rechecks);
+    double obj;
+    if constexpr (MF) {
+        const int64_t first_w = itm.first + (threadIdx.x >> 6) * 64;
+        float xr[4][D / 4];
+        unsigned long long nre = 0;
+        load_tile<D>(P + R.x_off, first_w, R.n, xr);
+        obj = wave_tile_mf<D>(L, xr, P + R.x_off, first_w, R.n, k, ldk, box, labels + R.lab_off, acc,
+                              shift, nre);
+        if ((threadIdx.x & 63) == 0 && nre) atomicAdd(&rs->rechecks, nre);
+    } else {
+        obj = fused_tile<D, MF>(L, P + R.x_off, itm.first, R.n, d, k, ldk, box, labels + R.lab_off,
+                                acc, shift, &rs->rechecks);
+    }
     const double tot = block_sum_det(obj, L.s_red);
     if (threadIdx.x == 0) objpart[item_base + blockIdx.x] = tot;
     if (!acc) return;
@@ -1062,7 +1205,7 @@ void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blo
         int64_t g = std::llround(work(r) / std::max(target, 1.0));
         // with a per-iteration exchange, every block reads the G partial sums:
         // keep G small and at least two tiles per block
-        const int64_t gmax = exchange ? std::min<int64_t>(16, std::max<int64_t>(1, tiles / 2)) : tiles;
+        const int64_t gmax = exchange ? std::min<int64_t>(kMaxG, std::max<int64_t>(1, tiles / 2)) : tiles;
         g = std::max<int64_t>(1, std::min<int64_t>({g, gmax, (int64_t)blocks}));
         G[r] = (int32_t)g;
         std::vector<Slot> take;
@@ -1085,7 +1228,7 @@ void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blo
 subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, int32_t R,
                         float *C, int32_t *labels, int32_t max_iter, double tol,
                         int32_t precision, int32_t form, int32_t *iters, double *sse,
-                        int init_mode) {
+                        int init_mode, unsigned long long *rechecks_acc) {
     (void)precision;
     hipStream_t s = ctx->stream;
     std::vector<DevRun> dr(R);
@@ -1302,7 +1445,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         }
     }
     hipLaunchKernelGGL(k_finalize, dim3(R), dim3(kAT), 0, s, d_runs, d_rs, d_obj, iters, sse,
-                       d_rechecks);
+                       rechecks_acc ? rechecks_acc : d_rechecks);
     SUBKM_LAUNCHED(ctx);
     if (batched) {
         // a barrier that gave up would leave wrong results: report it
