@@ -49,7 +49,8 @@ struct SelState {
     uint32_t bstar, below2, cnt2, need2;
     uint32_t thr_pos;
     uint32_t fallback;  // rounds that needed the slow exact path
-    uint32_t pad[2];
+    uint32_t ncand;     // length of the flat candidate list
+    uint32_t pad;
     double thr_key;
 };
 
@@ -197,17 +198,18 @@ __global__ __launch_bounds__(kST) void k_sel1(uint32_t *hist1, uint32_t need, Se
         st->astar = a;
         st->below1 = below;
         st->cnt1 = cnt;
+        st->ncand = 0;
     }
 }
 
 __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, uint32_t nrem,
-                                             const SelState *__restrict__ st,
-                                             double *__restrict__ ckey,
-                                             uint32_t *__restrict__ cpos,
-                                             uint32_t *__restrict__ ccount, uint32_t *hist2,
+                                             SelState *st, double *__restrict__ ckey,
+                                             uint32_t *__restrict__ cpos, uint32_t *hist2,
                                              uint32_t *__restrict__ blockcnt) {
     __shared__ uint32_t h[kBins];
-    __shared__ uint32_t s_red[kT / 64], s_nc;
+    __shared__ double s_ck[kBS];
+    __shared__ uint32_t s_cp[kBS];
+    __shared__ uint32_t s_red[kT / 64], s_nc, s_base;
     for (int i = threadIdx.x; i < kBins; i += kT) h[i] = 0;
     if (threadIdx.x == 0) s_nc = 0;
     __syncthreads();
@@ -231,9 +233,9 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
             if (lane == (int)first) slot0 = atomicAdd(&s_nc, cnt);
             slot0 = __shfl(slot0, first, 64);
             if (c) {
-                const uint32_t slot = p0 + slot0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                ckey[slot] = k;
-                cpos[slot] = p;
+                const uint32_t slot = slot0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                s_ck[slot] = k;
+                s_cp[slot] = p;
                 atomicAdd(&h[v & 0xFFFu], 1u);
             }
         }
@@ -241,13 +243,21 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
     for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o, 64);
     if (lane == 0) s_red[threadIdx.x >> 6] = below;
     __syncthreads();
+    const uint32_t nc = s_nc;
     if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int w = 0; w < kT / 64; ++w) s += s_red[w];
-        blockcnt[blockIdx.x] = s;
-        ccount[blockIdx.x] = s_nc;
+        uint32_t sum = 0;
+        for (int w = 0; w < kT / 64; ++w) sum += s_red[w];
+        blockcnt[blockIdx.x] = sum;
+        // the block's candidates go to one contiguous stretch of the list
+        s_base = nc ? atomicAdd(&st->ncand, nc) : 0u;
     }
-    if (s_nc) {
+    __syncthreads();
+    if (nc) {
+        const uint32_t b0 = s_base;
+        for (uint32_t i = threadIdx.x; i < nc; i += kT) {
+            ckey[b0 + i] = s_ck[i];
+            cpos[b0 + i] = s_cp[i];
+        }
         uint32_t *rep = hist2 + (blockIdx.x % kRep) * kBins;
         for (int i = threadIdx.x; i < kBins; i += kT)
             if (h[i]) atomicAdd(&rep[i], h[i]);
@@ -257,16 +267,16 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
 // Exact selection of the need2-th smallest (key, pos) among the candidates
 // whose v equals vstar, when there are too many to rank in LDS: a
 // most-significant-digit radix select over the 96-bit pair, 8 bits a pass.
-__device__ void slow_select(const double *ckey, const uint32_t *cpos, const uint32_t *ccount,
-                            uint32_t nb, uint32_t vstar, uint32_t base, uint32_t need,
+__device__ void slow_select(const double *ckey, const uint32_t *cpos, uint32_t ncand,
+                            uint32_t vstar, uint32_t base, uint32_t need,
                             uint32_t *hist256, uint32_t *sh, double *thr_key, uint32_t *thr_pos) {
     uint64_t kpre = 0;
     uint32_t ppre = 0;
     for (int pass = 0; pass < 12; ++pass) {
         for (int i = threadIdx.x; i < 256; i += kST) hist256[i] = 0;
         __syncthreads();
-        for (uint32_t b = threadIdx.x; b < nb; b += kST) {
-            for (uint32_t c = b * kBS; c < b * kBS + ccount[b]; ++c) {
+        {
+            for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
                 const double k = ckey[c];
                 if (vmap(k, base) != vstar) continue;
                 const uint64_t kb = (uint64_t)__double_as_longlong(k);
@@ -308,88 +318,41 @@ __device__ void slow_select(const double *ckey, const uint32_t *cpos, const uint
     *thr_pos = ppre;
 }
 
-// Flat view of the candidate segments: candidate i (0 <= i < total) lives in
-// segment seg with cstart[seg] <= i < cstart[seg + 1].
-__device__ __forceinline__ uint32_t seg_of(const uint32_t *cstart, uint32_t nb, uint32_t i) {
-    uint32_t lo = 0, hi = nb;  // largest seg with cstart[seg] <= i
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (cstart[mid] <= i) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-constexpr uint32_t kSegCap = 4096;  // segments handled in LDS by k_sel2
+constexpr uint32_t kSegCap = 4096;  // compaction blocks counted in LDS by k_sel2
 
 __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
                                               const double *__restrict__ ckey,
-                                              const uint32_t *__restrict__ cpos,
-                                              const uint32_t *__restrict__ ccount, uint32_t nb,
+                                              const uint32_t *__restrict__ cpos, uint32_t nb,
                                               uint32_t *hist2, uint32_t *blockcnt,
                                               uint32_t *blockoff) {
     __shared__ uint32_t sh[4], tmp[kST / 64], s_n;
     __shared__ double rk[kRankCap];
     __shared__ uint32_t rp[kRankCap];
     __shared__ uint32_t h256[256];
-    __shared__ uint32_t cstart[kSegCap + 1];
     __shared__ uint32_t csel[kSegCap];
     const uint32_t astar = st->astar, base = st->base;
     const uint32_t need1 = need - st->below1;
+    const uint32_t ncand = st->ncand;
+    const bool lds_counts = nb <= kSegCap;
+    for (uint32_t i = threadIdx.x; i < kSegCap; i += kST) csel[i] = 0;
     uint32_t b, below2, cnt2;
     merge_find_bin(hist2, need1, sh, tmp, &b, &below2, &cnt2);
     const uint32_t need2 = need1 - below2;
     const uint32_t vstar = (astar << 12) | b;
-    const bool flat = nb <= kSegCap;
-    uint32_t total = 0;
-    if (flat) {
-        // start of every segment in the flat candidate order
-        uint32_t carry = 0;
-        for (uint32_t c0 = 0; c0 < nb; c0 += kST) {
-            const uint32_t sgi = c0 + threadIdx.x;
-            const uint32_t v = sgi < nb ? ccount[sgi] : 0u;
-            uint32_t tot;
-            const uint32_t pre = block_scan<kST>(v, tmp, &tot);
-            if (sgi < nb) {
-                cstart[sgi] = carry + pre;
-                csel[sgi] = 0;
-            }
-            carry += tot;
-        }
-        total = carry;
-        if (threadIdx.x == 0) cstart[nb] = total;
-        __syncthreads();
-    }
     double thr_key;
     uint32_t thr_pos;
     if (cnt2 <= (uint32_t)kRankCap) {
         if (threadIdx.x == 0) s_n = 0;
         __syncthreads();
-        if (flat) {
-            for (uint32_t i = threadIdx.x; i < total; i += kST) {
-                const uint32_t sg = seg_of(cstart, nb, i);
-                const uint32_t c = sg * kBS + (i - cstart[sg]);
-                const double k = ckey[c];
-                if (vmap(k, base) == vstar) {
-                    const uint32_t q = atomicAdd(&s_n, 1u);
-                    if (q < (uint32_t)kRankCap) {
-                        rk[q] = k;
-                        rp[q] = cpos[c];
-                    }
+        for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
+            const double k = ckey[c];
+            if (vmap(k, base) == vstar) {
+                const uint32_t q = atomicAdd(&s_n, 1u);
+                if (q < (uint32_t)kRankCap) {
+                    rk[q] = k;
+                    rp[q] = cpos[c];
                 }
             }
-        } else {
-            for (uint32_t sg = threadIdx.x; sg < nb; sg += kST)
-                for (uint32_t c = sg * kBS; c < sg * kBS + ccount[sg]; ++c) {
-                    const double k = ckey[c];
-                    if (vmap(k, base) == vstar) {
-                        const uint32_t q = atomicAdd(&s_n, 1u);
-                        if (q < (uint32_t)kRankCap) {
-                            rk[q] = k;
-                            rp[q] = cpos[c];
-                        }
-                    }
-                }
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt2; i += kST) {
@@ -404,32 +367,25 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
         thr_pos = rp[sh[3]];
         __syncthreads();
     } else {
-        slow_select(ckey, cpos, ccount, nb, vstar, base, need2, h256, sh, &thr_key, &thr_pos);
+        slow_select(ckey, cpos, ncand, vstar, base, need2, h256, sh, &thr_key, &thr_pos);
         if (threadIdx.x == 0) st->fallback += 1;
     }
     // the candidates at or below the threshold join their block's count;
     // then block counts become block offsets of the selected rows
-    if (flat) {
-        for (uint32_t i = threadIdx.x; i < total; i += kST) {
-            const uint32_t sg = seg_of(cstart, nb, i);
-            const uint32_t c = sg * kBS + (i - cstart[sg]);
-            if (pair_le(ckey[c], cpos[c], thr_key, thr_pos)) atomicAdd(&csel[sg], 1u);
+    for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
+        const uint32_t pc = cpos[c];
+        if (pair_le(ckey[c], pc, thr_key, thr_pos)) {
+            if (lds_counts) atomicAdd(&csel[pc / kBS], 1u);
+            else atomicAdd(&blockcnt[pc / kBS], 1u);
         }
-        __syncthreads();
     }
+    if (!lds_counts) __threadfence_block();
+    __syncthreads();
     uint32_t carry = 0;
     for (uint32_t c0 = 0; c0 < nb; c0 += kST) {
         const uint32_t sg = c0 + threadIdx.x;
         uint32_t v = 0;
-        if (sg < nb) {
-            v = blockcnt[sg];
-            if (flat) {
-                v += csel[sg];
-            } else {
-                for (uint32_t c = sg * kBS; c < sg * kBS + ccount[sg]; ++c)
-                    v += pair_le(ckey[c], cpos[c], thr_key, thr_pos) ? 1u : 0u;
-            }
-        }
+        if (sg < nb) v = (lds_counts ? csel[sg] : 0u) + __hip_atomic_load(&blockcnt[sg], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t tot;
         const uint32_t pre = block_scan<kST>(v, tmp, &tot);
         if (sg < nb) blockoff[sg] = carry + pre;
@@ -692,7 +648,6 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     uint32_t *hist2 = hist1 + kRep * kBins;
     uint32_t *blockcnt = hist2 + kRep * kBins;
     uint32_t *blockoff = blockcnt + nb_max;
-    uint32_t *ccount = blockoff + nb_max;
     double *ckey = (double *)b.cand;
     uint32_t *cpos = (uint32_t *)(b.cand + sizeof(double) * n);
     float *L = b.land;
@@ -740,11 +695,11 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
             {
                 ProfScope pc(ctx, PK_CAND);
                 hipLaunchKernelGGL(k_cand, dim3(nb), dim3(kT), 0, s, keys, nrem, st, ckey, cpos,
-                                   ccount, hist2, blockcnt);
+                                   hist2, blockcnt);
                 SUBKM_LAUNCHED(ctx);
             }
-            hipLaunchKernelGGL(k_sel2, dim3(1), dim3(kST), 0, s, need, st, ckey, cpos, ccount, nb,
-                               hist2, blockcnt, blockoff);
+            hipLaunchKernelGGL(k_sel2, dim3(1), dim3(kST), 0, s, need, st, ckey, cpos, nb, hist2,
+                               blockcnt, blockoff);
             SUBKM_LAUNCHED(ctx);
         } else if (lm_t) {
             hipLaunchKernelGGL(k_copy_f32, dim3(ceil_div(d, 256)), dim3(256), 0, s, lm_t, L, d);
