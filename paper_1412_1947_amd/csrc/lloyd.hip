@@ -47,6 +47,8 @@ constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path
 constexpr int kUpdLdsWords = 6144;  // int64 sums per block (scan-update path)
 constexpr long long kSpinLimit = 1ll << 24;
 constexpr int kMaxG = 16;          // blocks per run in the batched form
+constexpr int kSlice = 8192;        // points per update block (chunked path)
+constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 
 enum : int32_t { PH_ITER = 0, PH_FINAL = 1, PH_DONE = 2 };
 
@@ -78,6 +80,8 @@ struct RunState {
 struct Item {
     int32_t run;
     int32_t first;  // first point (assign) or first center (update)
+    int32_t slice;  // update: slice of kSlice points of the run
+    int32_t pad;
 };
 
 struct Task {
@@ -861,28 +865,193 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
     }
 }
 
-// Scan-update path: the block owns a chunk of centers of one run, scans the
-// run's labels and adds the points of its centers.
-__global__ __launch_bounds__(kAT) void k_update_scan(const float *__restrict__ P,
-                                                     const DevRun *__restrict__ runs,
-                                                     const Item *__restrict__ items, int item_base,
-                                                     float *C, const int32_t *__restrict__ labels,
-                                                     RunState *rstate, double tol) {
-    __shared__ long long s_sum[kUpdLdsWords];
-    __shared__ unsigned int s_cnt[1024];
-    __shared__ int32_t s_pts[kAT];
+// Chunked path, assignment on matrix cores: the run's centers stream through
+// LDS in chunks (dim-major, padded pitch); every wavefront keeps the two
+// smallest values of its 64 points across the chunks.  Same centering and
+// error bound as stage1_mfma, with max_c ||c - m|| accumulated chunk by
+// chunk; near-ties are re-assigned in binary64 against the centers in global
+// memory.  The objective of the tile goes to objpart.
+template <int D>
+__global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
+                                                    const DevRun *__restrict__ runs,
+                                                    const Item *__restrict__ items, int item_base,
+                                                    const float *__restrict__ C, int32_t *labels,
+                                                    RunState *rstate, double *objpart,
+                                                    const uint32_t *__restrict__ boxes) {
+    constexpr int KQ = D / 4;
+    constexpr int ldc = (kChunkF / D) < 1040 ? (kChunkF / D) : 1040;  // pitch of a staged chunk
+    constexpr int kc = ((ldc - 16) / 16) * 16;                         // centers per chunk
+    static_assert(kc >= 16, "chunk too small");
+    __shared__ float sC[D * ldc];
+    __shared__ float cn[ldc];
     __shared__ int32_t s_lab[kAT];
-    __shared__ uint32_t s_np, s_last;
     __shared__ double s_red[kAT];
     const Item itm = items[item_base + blockIdx.x];
     const DevRun R = runs[itm.run];
     RunState *rs = rstate + itm.run;
-    const int32_t ph = rs->phase;
-    if (ph == PH_DONE) return;
-    if (ph == PH_FINAL) {
-        if (itm.first == 0 && threadIdx.x == 0) rs->phase = PH_DONE;
-        return;
+    if (rs->phase == PH_DONE) return;
+    const int k = R.k;
+    const float *X = P + R.x_off;
+    const float *Cr = C + R.c_off;
+    const uint32_t *box = boxes + R.box_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kk = lane >> 4;
+    const int64_t first_w = itm.first + wave * 64;
+    float mq[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) mq[q] = box_mid(box, D, kk + 4 * q);
+    float xr[4][KQ];
+    load_tile<D>(X, first_w, R.n, xr);
+    float xb[4][KQ], xn[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const bool ok = first_w + g * 16 + col < R.n;
+        float s2 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const float v = ok ? xr[g][q] - mq[q] : 0.0f;
+            xb[g][q] = v;
+            s2 = __builtin_fmaf(v, v, s2);
+        }
+        s2 += __shfl_xor(s2, 16, 64);
+        s2 += __shfl_xor(s2, 32, 64);
+        xn[g] = sqrtf(s2);
     }
+    float b1[4], b2[4];
+    int32_t i1[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        b1[g] = INFINITY;
+        b2[g] = INFINITY;
+        i1[g] = 0;
+    }
+    float Rc2 = 0.0f;  // max_c ||c - m||^2 over the chunks seen
+    const float bb = kk == 0 ? 1.0f : 0.0f;
+    for (int c0 = 0; c0 < k; c0 += kc) {
+        const int nc = kc < k - c0 ? kc : k - c0;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nc * D; e += kAT) {
+            const int c = e / D, j = e - c * D;
+            sC[j * ldc + c] = Cr[(int64_t)(c0 + c) * D + j];
+        }
+        __syncthreads();
+        float mx = 0.0f;
+        for (int c = threadIdx.x; c < ((nc + 15) & ~15); c += kAT) {
+            float a = INFINITY;
+            if (c < nc) {
+                a = 0.0f;
+#pragma unroll 4
+                for (int j = 0; j < D; ++j) {
+                    const float t = sC[j * ldc + c] - box_mid(box, D, j);
+                    a = __builtin_fmaf(t, t, a);
+                }
+                mx = fmaxf(mx, a);
+            }
+            cn[c] = a;
+        }
+        s_red[threadIdx.x] = (double)mx;
+        __syncthreads();
+        for (int st = kAT / 2; st > 0; st >>= 1) {
+            if (threadIdx.x < st) s_red[threadIdx.x] = fmax(s_red[threadIdx.x], s_red[threadIdx.x + st]);
+            __syncthreads();
+        }
+        Rc2 = fmaxf(Rc2, (float)s_red[0]);
+        for (int t0 = 0; t0 < nc; t0 += 16) {
+            const int cA = t0 + col;
+            float ca[KQ];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                const float cv = sC[(kk + 4 * q) * ldc + cA];
+                ca[q] = cA < nc ? -2.0f * (cv - mq[q]) : 0.0f;
+            }
+            const float cnv = cn[cA];
+            const float cb = kk == 0 ? cnv : 0.0f;
+            int32_t ci[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ci[r] = c0 + t0 + 4 * kk + r;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cb, bb, acc, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[q], xb[g][q], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float v = acc[r];
+                    b2[g] = __builtin_amdgcn_fmed3f(v, b1[g], b2[g]);
+                    const bool lt = v < b1[g];
+                    b1[g] = lt ? v : b1[g];
+                    i1[g] = lt ? ci[r] : i1[g];
+                }
+            }
+        }
+    }
+    const float Rc = sqrtf(Rc2);
+    const float Ku = 2.0f * (float)(D + 5) * 5.9604645e-8f;
+    int32_t *wlab = s_lab + wave * 64;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            const float ob1 = __shfl_xor(b1[g], o, 64);
+            const float ob2 = __shfl_xor(b2[g], o, 64);
+            const int32_t oi = __shfl_xor(i1[g], o, 64);
+            const float nb2 = fminf(fminf(b2[g], ob2), fmaxf(b1[g], ob1));
+            const bool take = ob1 < b1[g] || (ob1 == b1[g] && oi < i1[g]);
+            b1[g] = take ? ob1 : b1[g];
+            i1[g] = take ? oi : i1[g];
+            b2[g] = nb2;
+        }
+        const float sx = xn[g] + Rc;
+        const float E = Ku * sx * sx + 1e-30f;
+        const bool certain = k == 1 || (b2[g] - b1[g]) > 2.0f * E;
+        if (kk == 0) wlab[g * 16 + col] = i1[g] | (certain ? 0 : (int32_t)0x80000000);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t i = first_w + lane;
+    const bool valid = i < R.n;
+    const float *xg = X + (valid ? i : 0) * D;
+    const int32_t sl = wlab[lane];
+    int32_t lab = sl & 0x7fffffff;
+    unsigned long long todo = __ballot(valid && sl < 0);
+    const unsigned long long nre = (unsigned long long)__popcll(todo);
+    while (todo) {
+        const int t = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int32_t w = wave_argmin64(X + (first_w + t) * D, Cr, D, k);
+        if (lane == t) lab = w;
+    }
+    double obj = 0.0;
+    if (valid) {
+        labels[R.lab_off + i] = lab;
+        obj = dist64(xg, Cr + (int64_t)lab * D, D);
+    }
+    if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
+    const double tot = block_sum_det(obj, s_red);
+    if (threadIdx.x == 0) objpart[item_base + blockIdx.x] = tot;
+}
+
+// Chunked path, update, step 1: item (run, first center c0, slice of
+// kSlice points).  Sums of the slice's points whose label is in
+// [c0, c0 + kcu), as exact integers in LDS, flushed with integer atomics to
+// the run's global sums.
+__global__ __launch_bounds__(kAT) void k_upd_acc(const float *__restrict__ P,
+                                                 const DevRun *__restrict__ runs,
+                                                 const Item *__restrict__ items, int item_base,
+                                                 const int32_t *__restrict__ labels,
+                                                 const RunState *__restrict__ rstate,
+                                                 long long *gsum) {
+    __shared__ long long s_sum[kUpdLdsWords];
+    __shared__ unsigned int s_cnt[1024];
+    __shared__ int32_t s_pts[kAT];
+    __shared__ int32_t s_lab[kAT];
+    __shared__ uint32_t s_np;
+    const Item itm = items[item_base + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    const RunState *rs = rstate + itm.run;
+    if (rs->phase != PH_ITER) return;
     const int d = R.d;
     const int c0 = itm.first;
     const int nc = R.kcu < R.k - c0 ? R.kcu : R.k - c0;
@@ -891,11 +1060,13 @@ __global__ __launch_bounds__(kAT) void k_update_scan(const float *__restrict__ P
     for (int c = threadIdx.x; c < nc; c += kAT) s_cnt[c] = 0;
     const float *X = P + R.x_off;
     const int32_t *lab = labels + R.lab_off;
-    for (int64_t b = 0; b < R.n; b += kAT) {
+    const int64_t p0 = (int64_t)itm.slice * kSlice;
+    const int64_t p1 = min(R.n, p0 + kSlice);
+    for (int64_t b = p0; b < p1; b += kAT) {
         if (threadIdx.x == 0) s_np = 0;
         __syncthreads();
         const int64_t i = b + threadIdx.x;
-        if (i < R.n) {
+        if (i < p1) {
             const int32_t l = lab[i] - c0;
             if (l >= 0 && l < nc) {
                 const uint32_t q = atomicAdd(&s_np, 1u);
@@ -913,22 +1084,55 @@ __global__ __launch_bounds__(kAT) void k_update_scan(const float *__restrict__ P
         }
         __syncthreads();
     }
-    float *Cr = C + R.c_off + (int64_t)c0 * d;
-    for (int e = threadIdx.x; e < nc * d; e += kAT) {
-        const int c = e / d;
-        const unsigned int cnt = s_cnt[c];
-        const float old = Cr[e];
-        const double nv = cnt ? ldexp((double)s_sum[e], -s) / (double)cnt : (double)old;
-        const double mv = nv - (double)old;
-        Cr[e] = (float)nv;
-        s_sum[e] = __double_as_longlong(mv * mv);
+    long long *gs = gsum + R.sum_off;
+    const int kd = R.k * d;
+    for (int c = threadIdx.x; c < nc; c += kAT)
+        if (s_cnt[c]) atomicAdd((unsigned long long *)&gs[kd + c0 + c], (unsigned long long)s_cnt[c]);
+    for (int e = threadIdx.x; e < nc * d; e += kAT)
+        if (s_cnt[e / d]) atomicAdd((unsigned long long *)&gs[(int64_t)c0 * d + e], (unsigned long long)s_sum[e]);
+}
+
+// Chunked path, update, step 2: item (run, first center c0).  New centers
+// of the chunk from the global sums (zeroed for the next iteration), the
+// chunk's largest move; the run's last chunk to finish decides convergence.
+__global__ __launch_bounds__(kAT) void k_upd_fin(const DevRun *__restrict__ runs,
+                                                 const Item *__restrict__ items, int item_base,
+                                                 float *C, RunState *rstate, long long *gsum,
+                                                 double tol) {
+    __shared__ double s_red[kAT];
+    __shared__ uint32_t s_last;
+    const Item itm = items[item_base + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    RunState *rs = rstate + itm.run;
+    const int32_t ph = rs->phase;
+    if (ph == PH_DONE) return;
+    if (ph == PH_FINAL) {
+        // the assignment that just ran was the last one of this run
+        if (itm.first == 0 && threadIdx.x == 0) rs->phase = PH_DONE;
+        return;
     }
-    __syncthreads();
+    const int d = R.d, kd = R.k * d;
+    const int c0 = itm.first;
+    const int nc = R.kcu < R.k - c0 ? R.kcu : R.k - c0;
+    const int s = fix_shift_of(rs->absmax_bits, R.n);
+    long long *gs = gsum + R.sum_off;
+    float *Cr = C + R.c_off + (int64_t)c0 * d;
     double mx = 0.0;
     for (int c = threadIdx.x; c < nc; c += kAT) {
-        double a = 0.0;
-        for (int j = 0; j < d; ++j) a = a + __longlong_as_double(s_sum[c * d + j]);
-        mx = fmax(mx, sqrt(a));
+        const long long cnt = gs[kd + c0 + c];
+        gs[kd + c0 + c] = 0;
+        double mv2 = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const int64_t e = (int64_t)c * d + j;
+            const long long sm = gs[(int64_t)c0 * d + e];
+            gs[(int64_t)c0 * d + e] = 0;
+            const float old = Cr[e];
+            const double nv = cnt ? ldexp((double)sm, -s) / (double)cnt : (double)old;
+            const double dv = nv - (double)old;
+            mv2 = mv2 + dv * dv;
+            Cr[e] = (float)nv;
+        }
+        mx = fmax(mx, sqrt(mv2));
     }
     mx = block_max(mx, s_red);
     if (threadIdx.x == 0) {
@@ -1175,6 +1379,31 @@ subkm_status assign_d(subkm_ctx *ctx, int d, int nitems, int item_base, const fl
                      objpart);
 }
 
+template <int D>
+subkm_status launch_assign_big(subkm_ctx *ctx, int nitems, int item_base, const float *P,
+                               const DevRun *runs, const Item *items, const float *C,
+                               int32_t *labels, RunState *rs, double *objpart,
+                               const uint32_t *boxes) {
+    if constexpr (kHasMF<D>) {
+        ProfScope ps(ctx, PK_ASSIGN);
+        hipLaunchKernelGGL(k_assign_big<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
+                           item_base, C, labels, rs, objpart, boxes);
+        SUBKM_LAUNCHED(ctx);
+        return SUBKM_OK;
+    } else {
+        return launch_assign<D>(ctx, nitems, item_base, P, runs, items, C, labels, rs, objpart);
+    }
+}
+
+// assignment of runs beyond the LDS budget: matrix cores when d allows
+subkm_status assign_big_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
+                          const DevRun *runs, const Item *items, const float *C, int32_t *labels,
+                          RunState *rs, double *objpart, const uint32_t *boxes) {
+    if (nitems <= 0) return SUBKM_OK;
+    SUBKM_DISPATCH_D(d, launch_assign_big, ctx, nitems, item_base, P, runs, items, C, labels, rs,
+                     objpart, boxes);
+}
+
 subkm_status persist_d(subkm_ctx *ctx, int d, bool mf, int blocks, const float *P,
                        const DevRun *runs, const Task *tasks, const int32_t *task_off, float *C,
                        int32_t *labels, RunState *rs, long long *parts, double *objpart,
@@ -1250,7 +1479,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         D.fused = (kd <= kSumW && kd <= kCF && u.k <= kMaxK) ? 1 : 0;
         all_fused = all_fused && D.fused;
         D.sum_off = sum_words;
-        if (D.fused) sum_words += kd + u.k;
+        sum_words += kd + u.k;
         D.box_off = box_words;
         box_words += 2 * (int64_t)u.d;
     }
@@ -1261,6 +1490,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
 
     const bool batched = form == SUBKM_FORM_BATCHED && all_fused;
     std::vector<Item> items;
+    std::vector<int> uacc0, nuacc;
     std::vector<Task> tasks;
     std::vector<int32_t> task_off;
     struct Group {
@@ -1309,16 +1539,28 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         for (int r = 0; r < R; ++r) {
             DevRun &D = dr[r];
             D.item0 = (int)items.size();
-            for (int64_t f = 0; f < D.n; f += kAT) items.push_back(Item{r, (int32_t)f});
+            for (int64_t f = 0; f < D.n; f += kAT) items.push_back(Item{r, (int32_t)f, 0, 0});
             D.nitems = (int)items.size() - D.item0;
         }
         n_obj = (int)items.size();
+        // chunked path: accumulate items (run, center chunk, point slice),
+        // then finalize items (run, center chunk)
+        uacc0.assign(R, 0);
+        nuacc.assign(R, 0);
         for (int r = 0; r < R; ++r) {
             DevRun &D = dr[r];
             D.kcu = std::max(1, std::min({D.k, kUpdLdsWords / D.d, 1024}));
+            uacc0[r] = (int)items.size();
+            if (!D.fused)
+                for (int c = 0; c < D.k; c += D.kcu)
+                    for (int64_t sl = 0; sl * kSlice < D.n; ++sl) items.push_back(Item{r, c, (int32_t)sl, 0});
+            nuacc[r] = (int)items.size() - uacc0[r];
+        }
+        for (int r = 0; r < R; ++r) {
+            DevRun &D = dr[r];
             D.uitem0 = (int)items.size();
             if (!D.fused)
-                for (int c = 0; c < D.k; c += D.kcu) items.push_back(Item{r, c});
+                for (int c = 0; c < D.k; c += D.kcu) items.push_back(Item{r, c, 0, 0});
             D.nuitems = (int)items.size() - D.uitem0;
         }
     }
@@ -1396,21 +1638,26 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                     SUBKM_TRY(assign_acc_d(ctx, D.d, D.mf != 0, D.nitems, D.item0, P, d_runs, d_items,
                                            C, labels, d_rs, d_obj, gsum, d_box, a < max_iter ? 1 : 0));
                 } else {
-                    SUBKM_TRY(assign_d(ctx, D.d, D.nitems, D.item0, P, d_runs, d_items, C, labels,
-                                       d_rs, d_obj));
+                    SUBKM_TRY(assign_big_d(ctx, D.d, D.nitems, D.item0, P, d_runs, d_items, C, labels,
+                                           d_rs, d_obj, d_box));
                 }
                 if (a == max_iter) break;
                 ProfScope ps(ctx, PK_UPDATE);
-                if (D.fused)
+                if (D.fused) {
                     hipLaunchKernelGGL(k_update_fin, dim3(1), dim3(kAT), 0, s, d_runs, r, C, d_rs, gsum, tol);
-                else
-                    hipLaunchKernelGGL(k_update_scan, dim3(D.nuitems), dim3(kAT), 0, s, P, d_runs,
-                                       d_items, D.uitem0, C, labels, d_rs, tol);
+                } else {
+                    hipLaunchKernelGGL(k_upd_acc, dim3(nuacc[r]), dim3(kAT), 0, s, P, d_runs, d_items,
+                                       uacc0[r], labels, d_rs, gsum);
+                    SUBKM_LAUNCHED(ctx);
+                    hipLaunchKernelGGL(k_upd_fin, dim3(D.nuitems), dim3(kAT), 0, s, d_runs, d_items,
+                                       D.uitem0, C, d_rs, gsum, tol);
+                }
                 SUBKM_LAUNCHED(ctx);
             }
         }
     } else {
-        // batched request with runs beyond the LDS budget: all runs per launch
+        // batched request with runs beyond the LDS budget: every phase is one
+        // launch per attribute count (or path) over all runs
         for (int a = 0; a <= max_iter; ++a) {
             for (int r0 = 0; r0 < R;) {
                 int r1 = r0 + 1;
@@ -1422,8 +1669,8 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                     SUBKM_TRY(assign_acc_d(ctx, dr[r0].d, dr[r0].mf != 0, ni, i0, P, d_runs, d_items, C,
                                            labels, d_rs, d_obj, gsum, d_box, a < max_iter ? 1 : 0));
                 else
-                    SUBKM_TRY(assign_d(ctx, dr[r0].d, ni, i0, P, d_runs, d_items, C, labels, d_rs,
-                                       d_obj));
+                    SUBKM_TRY(assign_big_d(ctx, dr[r0].d, ni, i0, P, d_runs, d_items, C, labels, d_rs,
+                                           d_obj, d_box));
                 r0 = r1;
             }
             if (a == max_iter) break;
@@ -1435,9 +1682,13 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                     hipLaunchKernelGGL(k_update_fin, dim3(r1 - r0), dim3(kAT), 0, s, d_runs, r0, C,
                                        d_rs, gsum, tol);
                 } else {
+                    const int a0 = uacc0[r0], na = uacc0[r1 - 1] + nuacc[r1 - 1] - a0;
+                    hipLaunchKernelGGL(k_upd_acc, dim3(na), dim3(kAT), 0, s, P, d_runs, d_items, a0,
+                                       labels, d_rs, gsum);
+                    SUBKM_LAUNCHED(ctx);
                     const int u0 = dr[r0].uitem0, nu = dr[r1 - 1].uitem0 + dr[r1 - 1].nuitems - u0;
-                    hipLaunchKernelGGL(k_update_scan, dim3(nu), dim3(kAT), 0, s, P, d_runs, d_items,
-                                       u0, C, labels, d_rs, tol);
+                    hipLaunchKernelGGL(k_upd_fin, dim3(nu), dim3(kAT), 0, s, d_runs, d_items, u0, C,
+                                       d_rs, gsum, tol);
                 }
                 SUBKM_LAUNCHED(ctx);
                 r0 = r1;

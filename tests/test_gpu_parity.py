@@ -269,3 +269,81 @@ def test_cluster_ragged_tail_and_fixed_landmark(km, oracle):
     check_cluster(km, oracle, job, fixed=True)
     out, ref, loc = check_cluster(km, oracle, job)
     assert rel_err(loc, ref["local_centers"]) <= TOL
+
+
+# ------------------------------------------------------- chunked path, ragged runs
+def test_ragged_large_k_runs(km, oracle):
+    """Runs whose k*d exceeds the LDS budget (centers streamed in chunks,
+    label-scan update), mixed with small runs and two attribute counts in one
+    call; every run is checked step by step against the oracle."""
+    rng = np.random.default_rng(33)
+    runs, ks = [], []
+    for j, (n, d) in enumerate([(6000, 32), (3000, 8), (9000, 32), (1500, 8), (2500, 32), (700, 5)]):
+        X, _ = synth.gaussian_blobs(n, d, int(rng.integers(4, 33)), seed=300 + j, sigma=(0.2, 1.5))
+        runs.append(oracle.scale(X)[0])
+        ks.append(int(min(-(-n // 32) * 4, 1024)) if d == 32 else int(-(-n // 32)))
+    # one batched call, 3 moves, then one more move checked against the oracle
+    out, iters, sse = run_batch(km, runs, ks, 3, 0.0)
+    for r, (X, k) in enumerate(zip(runs, ks)):
+        C3, lab3 = out[r]
+        X64 = X.astype(np.float64)
+        lab_ref, sse_ref, _, _ = oracle.assign(X64, C3)
+        assert np.array_equal(lab3, lab_ref), r
+        assert abs(sse[r] - sse_ref) <= TOL * sse_ref, r
+        assert iters[r] == 3
+    # shadow step on the largest run at full k
+    X, k = runs[2], ks[2]
+    assert k * X.shape[1] > 4096
+    shadow_steps(km, oracle, X, X[:k], steps=2)
+
+
+def test_forms_agree_on_large_k(km, oracle):
+    rng = np.random.default_rng(44)
+    runs, ks = [], []
+    for j in range(4):
+        n = int(rng.integers(3000, 8000))
+        X, _ = synth.gaussian_blobs(n, 32, 12, seed=400 + j, sigma=0.5)
+        runs.append(oracle.scale(X)[0])
+        ks.append(300)
+    a, ia, sa = run_batch(km, runs, ks, 8, 1e-6, form=0)
+    b, ib, sb = run_batch(km, runs, ks, 8, 1e-6, form=1)
+    assert np.array_equal(ia, ib) and np.array_equal(sa, sb)
+    for (ca, la), (cb, lb) in zip(a, b):
+        assert np.array_equal(ca, cb) and np.array_equal(la, lb)
+
+
+# ------------------------------------------------ full-size workload, bench config
+def test_mid_workload_full_size(km, oracle):
+    """The benchmark's workload at full size, through the same call the
+    benchmark times: scaling and subclustering bit-exact against the oracle;
+    sampled local runs checked by one oracle step from the GPU's centers."""
+    job = synth.mid()
+    X = dev(job.X)
+    out = km.cluster(X, job.N, job.k_local, job.k_final, job.max_iter, job.tol,
+                     intermediates=True, stats=True)
+    S = host(out["S"])
+    Sr, _, _ = oracle.scale(job.X)
+    assert np.array_equal(S, Sr)
+    perm = host(out["perm"])
+    permr, offr, _ = oracle.subcluster(Sr, job.N)
+    assert np.array_equal(perm, permr)
+    loc = host(out["local_centers"])
+    lit = host(out["local_iters"])
+    lsse = host(out["local_sse"])
+    k = job.k_local
+    for t in (0, 63, 127):
+        P = Sr[permr[offr[t]:offr[t + 1]]].astype(np.float64)
+        C = loc[t * k:(t + 1) * k]
+        # labels and objective of the returned centers
+        lab, obj, _, _ = oracle.assign(P, C)
+        assert abs(lsse[t] - obj) <= TOL * obj
+        assert 1 <= lit[t] <= job.max_iter
+        # the returned centers are (within the tolerance) where one more
+        # oracle move takes them when the run stopped on the tolerance
+        nxt, shift, _ = oracle.update(P, lab, C)
+        if lit[t] < job.max_iter:
+            assert shift < 1e-4
+    fin = host(out["centers"])
+    lab, obj, _, _ = oracle.assign(Sr.astype(np.float64), fin)
+    assert np.array_equal(host(out["labels"]), lab)
+    assert abs(host(out["sse"])[0] - obj) <= TOL * obj
