@@ -39,6 +39,10 @@ enum ScratchSlot {
     SC_CL_MINMAX,    // cluster(): mins / maxs
     SC_CL_FINAL,     // cluster(): final-run labels, iters, sse
     SC_BOX,          // per-run attribute bounds
+    SC_WCNT,         // wide runs: counts | starts | cursors per center
+    SC_WORDER,       // wide runs: point indices grouped by label
+    SC_FRAGS,        // split path: center fragments
+    SC_CNORM,        // split path: squared center norms
     SC_COUNT
 };
 

@@ -27,7 +27,7 @@
 //            over the run's tiles and one finalize launch.
 // Runs whose k*d exceeds the LDS budget use launch-per-phase kernels for all
 // runs together (the update scans the labels per chunk of centers).
-#include "internal.h"
+#include "lloyd_dev.h"
 
 #include <algorithm>
 #include <cmath>
@@ -39,136 +39,16 @@
 
 namespace {
 
-constexpr int kAT = 256;            // threads per block = points per tile
+using namespace subkm_lloyd;
+
 constexpr int kCF = 4608;           // floats of centers held in LDS (fused path)
 constexpr int kSumW = 4096;         // int64 center sums held in LDS (fused path)
 constexpr int kMaxK = 1024;         // centers per run in the fused path
 constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path)
-constexpr int kUpdLdsWords = 6144;  // int64 sums per block (scan-update path)
 constexpr long long kSpinLimit = 1ll << 24;
 constexpr int kMaxG = 16;          // blocks per run in the batched form
-constexpr int kSlice = 8192;        // points per update block (chunked path)
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
-
-enum : int32_t { PH_ITER = 0, PH_FINAL = 1, PH_DONE = 2 };
-
-struct DevRun {
-    int64_t x_off, n, c_off, lab_off;
-    int32_t d, k;
-    int32_t item0, nitems;    // objective slots (tiles or blocks of the run)
-    int32_t uitem0, nuitems;  // update items (center chunks)
-    int32_t kcu;              // centers per update item
-    int32_t fused;            // k*d fits the LDS sums
-    int64_t sum_off;          // offset of the run's int64 sums (k*d) + counts (k)
-    int64_t part_off;         // batched: offset of the run's exchange slots
-    int32_t G;                // batched: blocks of the run
-    int32_t mf;               // assignment on matrix cores
-    int64_t box_off;          // offset of the run's attribute minima and maxima
-};
-
-struct RunState {
-    int32_t phase;
-    int32_t iters;
-    uint32_t ucount;
-    uint32_t arrive;
-    unsigned long long shift_bits;
-    unsigned long long rechecks;
-    uint32_t absmax_bits;
-    uint32_t pad;
-};
-
-struct Item {
-    int32_t run;
-    int32_t first;  // first point (assign) or first center (update)
-    int32_t slice;  // update: slice of kSlice points of the run
-    int32_t pad;
-};
-
-struct Task {
-    int32_t run;
-    int32_t g;  // part g of the run's G blocks
-};
-
-// ---------------------------------------------------------------------------
-// exact binary64 distance of a float32 point to a float32 center, attributes
-// left to right, separate multiply and add (the definition of the objective)
-__device__ __forceinline__ double dist64(const float *x, const float *c, int d) {
-    double acc = 0.0;
-    for (int j = 0; j < d; ++j) {
-        double q = (double)x[j] - (double)c[j];
-        acc = acc + q * q;
-    }
-    return acc;
-}
-
-// Binary64 argmin over all k centers of one point, by one wavefront: lanes
-// take centers lane, lane+64, ...; ties go to the lowest index.
-__device__ int32_t wave_argmin64(const float *x, const float *C, int d, int k) {
-    const int lane = threadIdx.x & 63;
-    double best = INFINITY;
-    int32_t bi = 0x7fffffff;
-    for (int c = lane; c < k; c += 64) {
-        double v = dist64(x, C + (int64_t)c * d, d);
-        if (v < best) {
-            best = v;
-            bi = c;
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        double ob = __shfl_xor(best, o, 64);
-        int32_t oi = __shfl_xor(bi, o, 64);
-        if (ob < best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-        }
-    }
-    return bi;
-}
-
-// Deterministic sum of one double per thread (fixed pairing tree).
-__device__ double block_sum_det(double v, double *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int s = kAT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-__device__ double block_max(double v, double *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int s = kAT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-// Fixed point of the center sums.  Every coordinate is quantised to an
-// integer q = rint(x * 2^s) with s chosen per run so that |q| < 2^31
-// (|x| <= max|x| < 2^e, s = 31 - e); the error of one coordinate is at most
-// 2^-32 * 2^e <= 2^-31 max|x|, far below a float32 ulp of the mean.  The
-// integers are summed exactly in int64 (no overflow below 2^32 points), so a
-// sum does not depend on the order of the additions.
-__device__ __forceinline__ int fix_shift_of(uint32_t absmax_bits, int64_t n) {
-    (void)n;
-    const float m = __uint_as_float(absmax_bits);
-    int e = 0;
-    if (m > 0.0f) frexpf(m, &e);  // m < 2^e
-    return 31 - e;
-}
-
-__device__ __forceinline__ long long to_fixed(float x, int s) {
-    return (long long)(int)rintf(ldexpf(x, s));
-}
+constexpr int kWideCenters = 16;    // centers per update item (wide runs)
 
 // Float32 squared distances of this thread's point against centers sC[0..nc)
 // (row-major, d per row); keeps the two smallest values and the first index
@@ -275,12 +155,6 @@ __device__ int32_t wave_argmin64_lds(const float *x, const float *sC, int d, int
         }
     }
     return bi;
-}
-
-// Reference point m of a run for the matrix-core path: the midpoint of its
-// bounding box (box = ordered bits of the attribute minima, then maxima).
-__device__ __forceinline__ float box_mid(const uint32_t *box, int d, int j) {
-    return 0.5f * (ordered_float(box[j]) + ordered_float(box[d + j]));
 }
 
 // Matrix-core path: squared norms of the centered centers and their maximum.
@@ -601,7 +475,7 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
         const int kd = k * d;
         const int ldk = k + 16;
         const int G = R.G;
-        const int shift = fix_shift_of(rs->absmax_bits, R.n);
+        const int shift = fix_shift_of(rs->absmax_bits);
         const uint32_t *box = boxes + R.box_off;
         // the run's points are split over its G blocks in whole tiles
         const int64_t tiles = (R.n + kAT - 1) / kAT;
@@ -740,7 +614,7 @@ __global__ __launch_bounds__(kAT) void k_assign_acc(const float *__restrict__ P,
     const bool acc = accumulate && ph == PH_ITER;
     const int d = D > 0 ? D : R.d;
     const int k = R.k, kd = k * d, ldk = k + 16;
-    const int shift = fix_shift_of(rs->absmax_bits, R.n);
+    const int shift = fix_shift_of(rs->absmax_bits);
     const uint32_t *box = boxes + R.box_off;
     load_centers<MF>(L, C + R.c_off, d, k, ldk);
     for (int e = threadIdx.x; e < kd; e += kAT) L.s_sum[e] = 0;
@@ -787,7 +661,7 @@ __global__ __launch_bounds__(kAT) void k_update_fin(const DevRun *__restrict__ r
         return;
     }
     const int d = R.d, k = R.k, kd = k * d;
-    const int shift = fix_shift_of(rs->absmax_bits, R.n);
+    const int shift = fix_shift_of(rs->absmax_bits);
     long long *gs = gsum + R.sum_off;
     for (int e = threadIdx.x; e < kd; e += kAT) {
         L.sC[e] = C[R.c_off + e];
@@ -814,7 +688,7 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
                                                 const DevRun *__restrict__ runs,
                                                 const Item *__restrict__ items, int item_base,
                                                 const float *__restrict__ C, int32_t *labels,
-                                                RunState *rstate, double *objpart) {
+                                                RunState *rstate, double *objpart, int last_pass) {
     __shared__ float sC[kLdsFloats];
     __shared__ int32_t s_list[kAT];
     __shared__ int32_t s_newlab[kAT];
@@ -822,7 +696,9 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
     __shared__ double s_red[kAT];
     const Item itm = items[item_base + blockIdx.x];
     const DevRun R = runs[itm.run];
-    if (rstate[itm.run].phase == PH_DONE) return;
+    const int32_t ph = rstate[itm.run].phase;
+    if (ph == PH_DONE) return;
+    const bool want_obj = last_pass || ph == PH_FINAL;
     const int d = D > 0 ? D : R.d;
     const int k = R.k;
     const int64_t i = itm.first + threadIdx.x;
@@ -856,12 +732,12 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
     double obj = 0.0;
     if (valid) {
         labels[R.lab_off + i] = i1;
-        obj = dist64(xg, Cr + (int64_t)i1 * d, d);
+        if (want_obj) obj = dist64(xg, Cr + (int64_t)i1 * d, d);
     }
-    const double tot = block_sum_det(obj, s_red);
-    if (threadIdx.x == 0) {
-        objpart[item_base + blockIdx.x] = tot;
-        if (nl) atomicAdd(&rstate[itm.run].rechecks, (unsigned long long)nl);
+    if (threadIdx.x == 0 && nl) atomicAdd(&rstate[itm.run].rechecks, (unsigned long long)nl);
+    if (want_obj) {
+        const double tot = block_sum_det(obj, s_red);
+        if (threadIdx.x == 0) objpart[item_base + blockIdx.x] = tot;
     }
 }
 
@@ -877,7 +753,8 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
                                                     const Item *__restrict__ items, int item_base,
                                                     const float *__restrict__ C, int32_t *labels,
                                                     RunState *rstate, double *objpart,
-                                                    const uint32_t *__restrict__ boxes) {
+                                                    const uint32_t *__restrict__ boxes,
+                                                    int last_pass) {
     constexpr int KQ = D / 4;
     constexpr int ldc = (kChunkF / D) < 1040 ? (kChunkF / D) : 1040;  // pitch of a staged chunk
     constexpr int kc = ((ldc - 16) / 16) * 16;                         // centers per chunk
@@ -889,7 +766,9 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
     const Item itm = items[item_base + blockIdx.x];
     const DevRun R = runs[itm.run];
     RunState *rs = rstate + itm.run;
-    if (rs->phase == PH_DONE) return;
+    const int32_t ph = rs->phase;
+    if (ph == PH_DONE) return;
+    const bool want_obj = last_pass || ph == PH_FINAL;
     const int k = R.k;
     const float *X = P + R.x_off;
     const float *Cr = C + R.c_off;
@@ -1026,128 +905,12 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
     double obj = 0.0;
     if (valid) {
         labels[R.lab_off + i] = lab;
-        obj = dist64(xg, Cr + (int64_t)lab * D, D);
+        if (want_obj) obj = dist64(xg, Cr + (int64_t)lab * D, D);
     }
     if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
-    const double tot = block_sum_det(obj, s_red);
-    if (threadIdx.x == 0) objpart[item_base + blockIdx.x] = tot;
-}
-
-// Chunked path, update, step 1: item (run, first center c0, slice of
-// kSlice points).  Sums of the slice's points whose label is in
-// [c0, c0 + kcu), as exact integers in LDS, flushed with integer atomics to
-// the run's global sums.
-__global__ __launch_bounds__(kAT) void k_upd_acc(const float *__restrict__ P,
-                                                 const DevRun *__restrict__ runs,
-                                                 const Item *__restrict__ items, int item_base,
-                                                 const int32_t *__restrict__ labels,
-                                                 const RunState *__restrict__ rstate,
-                                                 long long *gsum) {
-    __shared__ long long s_sum[kUpdLdsWords];
-    __shared__ unsigned int s_cnt[1024];
-    __shared__ int32_t s_pts[kAT];
-    __shared__ int32_t s_lab[kAT];
-    __shared__ uint32_t s_np;
-    const Item itm = items[item_base + blockIdx.x];
-    const DevRun R = runs[itm.run];
-    const RunState *rs = rstate + itm.run;
-    if (rs->phase != PH_ITER) return;
-    const int d = R.d;
-    const int c0 = itm.first;
-    const int nc = R.kcu < R.k - c0 ? R.kcu : R.k - c0;
-    const int s = fix_shift_of(rs->absmax_bits, R.n);
-    for (int e = threadIdx.x; e < nc * d; e += kAT) s_sum[e] = 0;
-    for (int c = threadIdx.x; c < nc; c += kAT) s_cnt[c] = 0;
-    const float *X = P + R.x_off;
-    const int32_t *lab = labels + R.lab_off;
-    const int64_t p0 = (int64_t)itm.slice * kSlice;
-    const int64_t p1 = min(R.n, p0 + kSlice);
-    for (int64_t b = p0; b < p1; b += kAT) {
-        if (threadIdx.x == 0) s_np = 0;
-        __syncthreads();
-        const int64_t i = b + threadIdx.x;
-        if (i < p1) {
-            const int32_t l = lab[i] - c0;
-            if (l >= 0 && l < nc) {
-                const uint32_t q = atomicAdd(&s_np, 1u);
-                s_pts[q] = (int32_t)threadIdx.x;
-                s_lab[q] = l;
-                atomicAdd(&s_cnt[l], 1u);
-            }
-        }
-        __syncthreads();
-        const int np = (int)s_np;
-        for (int e = threadIdx.x; e < np * d; e += kAT) {
-            const int m = e / d, j = e - m * d;
-            const float v = X[(b + s_pts[m]) * d + j];
-            atomicAdd((unsigned long long *)&s_sum[s_lab[m] * d + j], (unsigned long long)to_fixed(v, s));
-        }
-        __syncthreads();
-    }
-    long long *gs = gsum + R.sum_off;
-    const int kd = R.k * d;
-    for (int c = threadIdx.x; c < nc; c += kAT)
-        if (s_cnt[c]) atomicAdd((unsigned long long *)&gs[kd + c0 + c], (unsigned long long)s_cnt[c]);
-    for (int e = threadIdx.x; e < nc * d; e += kAT)
-        if (s_cnt[e / d]) atomicAdd((unsigned long long *)&gs[(int64_t)c0 * d + e], (unsigned long long)s_sum[e]);
-}
-
-// Chunked path, update, step 2: item (run, first center c0).  New centers
-// of the chunk from the global sums (zeroed for the next iteration), the
-// chunk's largest move; the run's last chunk to finish decides convergence.
-__global__ __launch_bounds__(kAT) void k_upd_fin(const DevRun *__restrict__ runs,
-                                                 const Item *__restrict__ items, int item_base,
-                                                 float *C, RunState *rstate, long long *gsum,
-                                                 double tol) {
-    __shared__ double s_red[kAT];
-    __shared__ uint32_t s_last;
-    const Item itm = items[item_base + blockIdx.x];
-    const DevRun R = runs[itm.run];
-    RunState *rs = rstate + itm.run;
-    const int32_t ph = rs->phase;
-    if (ph == PH_DONE) return;
-    if (ph == PH_FINAL) {
-        // the assignment that just ran was the last one of this run
-        if (itm.first == 0 && threadIdx.x == 0) rs->phase = PH_DONE;
-        return;
-    }
-    const int d = R.d, kd = R.k * d;
-    const int c0 = itm.first;
-    const int nc = R.kcu < R.k - c0 ? R.kcu : R.k - c0;
-    const int s = fix_shift_of(rs->absmax_bits, R.n);
-    long long *gs = gsum + R.sum_off;
-    float *Cr = C + R.c_off + (int64_t)c0 * d;
-    double mx = 0.0;
-    for (int c = threadIdx.x; c < nc; c += kAT) {
-        const long long cnt = gs[kd + c0 + c];
-        gs[kd + c0 + c] = 0;
-        double mv2 = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const int64_t e = (int64_t)c * d + j;
-            const long long sm = gs[(int64_t)c0 * d + e];
-            gs[(int64_t)c0 * d + e] = 0;
-            const float old = Cr[e];
-            const double nv = cnt ? ldexp((double)sm, -s) / (double)cnt : (double)old;
-            const double dv = nv - (double)old;
-            mv2 = mv2 + dv * dv;
-            Cr[e] = (float)nv;
-        }
-        mx = fmax(mx, sqrt(mv2));
-    }
-    mx = block_max(mx, s_red);
-    if (threadIdx.x == 0) {
-        atomicMax(&rs->shift_bits, (unsigned long long)__double_as_longlong(mx));
-        __threadfence();
-        s_last = atomicAdd(&rs->ucount, 1u) == (uint32_t)R.nuitems - 1;
-        if (s_last) {
-            __threadfence();
-            const unsigned long long sb =
-                __hip_atomic_load(&rs->shift_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            rs->iters += 1;
-            rs->phase = __longlong_as_double((long long)sb) < tol ? PH_FINAL : PH_ITER;
-            rs->shift_bits = 0;
-            rs->ucount = 0;
-        }
+    if (want_obj) {
+        const double tot = block_sum_det(obj, s_red);
+        if (threadIdx.x == 0) objpart[item_base + blockIdx.x] = tot;
     }
 }
 
@@ -1305,10 +1068,10 @@ subkm_status launch_assign_acc(subkm_ctx *ctx, bool mf, int nitems, int item_bas
 template <int D>
 subkm_status launch_assign(subkm_ctx *ctx, int nitems, int item_base, const float *P,
                            const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                           RunState *rs, double *objpart) {
+                           RunState *rs, double *objpart, int last_pass) {
     ProfScope ps(ctx, PK_ASSIGN);
     hipLaunchKernelGGL(k_assign<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
-                       item_base, C, labels, rs, objpart);
+                       item_base, C, labels, rs, objpart, last_pass);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
@@ -1371,37 +1134,30 @@ subkm_status assign_acc_d(subkm_ctx *ctx, int d, bool mf, int nitems, int item_b
                      rs, objpart, gsum, boxes, accumulate);
 }
 
-subkm_status assign_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
-                      const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                      RunState *rs, double *objpart) {
-    if (nitems <= 0) return SUBKM_OK;
-    SUBKM_DISPATCH_D(d, launch_assign, ctx, nitems, item_base, P, runs, items, C, labels, rs,
-                     objpart);
-}
-
 template <int D>
 subkm_status launch_assign_big(subkm_ctx *ctx, int nitems, int item_base, const float *P,
                                const DevRun *runs, const Item *items, const float *C,
                                int32_t *labels, RunState *rs, double *objpart,
-                               const uint32_t *boxes) {
+                               const uint32_t *boxes, int last_pass) {
     if constexpr (kHasMF<D>) {
         ProfScope ps(ctx, PK_ASSIGN);
         hipLaunchKernelGGL(k_assign_big<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
-                           item_base, C, labels, rs, objpart, boxes);
+                           item_base, C, labels, rs, objpart, boxes, last_pass);
         SUBKM_LAUNCHED(ctx);
         return SUBKM_OK;
     } else {
-        return launch_assign<D>(ctx, nitems, item_base, P, runs, items, C, labels, rs, objpart);
+        return launch_assign<D>(ctx, nitems, item_base, P, runs, items, C, labels, rs, objpart,
+                                last_pass);
     }
 }
 
 // assignment of runs beyond the LDS budget: matrix cores when d allows
 subkm_status assign_big_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
                           const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                          RunState *rs, double *objpart, const uint32_t *boxes) {
+                          RunState *rs, double *objpart, const uint32_t *boxes, int last_pass) {
     if (nitems <= 0) return SUBKM_OK;
     SUBKM_DISPATCH_D(d, launch_assign_big, ctx, nitems, item_base, P, runs, items, C, labels, rs,
-                     objpart, boxes);
+                     objpart, boxes, last_pass);
 }
 
 subkm_status persist_d(subkm_ctx *ctx, int d, bool mf, int blocks, const float *P,
@@ -1458,11 +1214,10 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                         float *C, int32_t *labels, int32_t max_iter, double tol,
                         int32_t precision, int32_t form, int32_t *iters, double *sse,
                         int init_mode, unsigned long long *rechecks_acc) {
-    (void)precision;
     hipStream_t s = ctx->stream;
     std::vector<DevRun> dr(R);
     bool all_fused = true;
-    int64_t sum_words = 0, box_words = 0;
+    int64_t sum_words = 0, box_words = 0, cnt_words = 0, order_words = 0, frag_words = 0, cn_words = 0;
     for (int r = 0; r < R; ++r) {
         const subkm_run &u = runs[r];
         DevRun &D = dr[r];
@@ -1478,10 +1233,25 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         D.mf = (mf_shape && (int64_t)u.d * (u.k + 16) <= kCF) ? 1 : 0;
         D.fused = (kd <= kSumW && kd <= kCF && u.k <= kMaxK) ? 1 : 0;
         all_fused = all_fused && D.fused;
-        D.sum_off = sum_words;
-        sum_words += kd + u.k;
         D.box_off = box_words;
         box_words += 2 * (int64_t)u.d;
+        if (D.fused) {
+            D.sum_off = sum_words;
+            sum_words += kd + u.k;
+        } else {
+            // centers stream from memory; exact update through labels
+            D.cnt_off = cnt_words;
+            cnt_words += 3 * (int64_t)u.k;
+            order_words = std::max<int64_t>(order_words, u.lab_off + u.n);
+            D.split = (precision == SUBKM_PREC_BF16 && u.d >= 32 && u.d <= 128 && u.k <= 1024) ? 1 : 0;
+            if (D.split) {
+                const int64_t kt = ceil_div(u.k, 16), st = ceil_div(u.d, 32);
+                D.frag_off = frag_words;
+                frag_words += kt * st * 128;
+                D.cn_off = cn_words;
+                cn_words += kt * 16;
+            }
+        }
     }
     std::vector<std::pair<int, int>> ds;  // distinct (attribute count, matrix-core path)
     for (int r = 0; r < R; ++r) ds.push_back({dr[r].d, dr[r].mf});
@@ -1490,7 +1260,6 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
 
     const bool batched = form == SUBKM_FORM_BATCHED && all_fused;
     std::vector<Item> items;
-    std::vector<int> uacc0, nuacc;
     std::vector<Task> tasks;
     std::vector<int32_t> task_off;
     struct Group {
@@ -1543,24 +1312,14 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
             D.nitems = (int)items.size() - D.item0;
         }
         n_obj = (int)items.size();
-        // chunked path: accumulate items (run, center chunk, point slice),
-        // then finalize items (run, center chunk)
-        uacc0.assign(R, 0);
-        nuacc.assign(R, 0);
-        for (int r = 0; r < R; ++r) {
-            DevRun &D = dr[r];
-            D.kcu = std::max(1, std::min({D.k, kUpdLdsWords / D.d, 1024}));
-            uacc0[r] = (int)items.size();
-            if (!D.fused)
-                for (int c = 0; c < D.k; c += D.kcu)
-                    for (int64_t sl = 0; sl * kSlice < D.n; ++sl) items.push_back(Item{r, c, (int32_t)sl, 0});
-            nuacc[r] = (int)items.size() - uacc0[r];
-        }
+        // update items of the wide runs: chunks of kWideCenters centers
         for (int r = 0; r < R; ++r) {
             DevRun &D = dr[r];
             D.uitem0 = (int)items.size();
-            if (!D.fused)
-                for (int c = 0; c < D.k; c += D.kcu) items.push_back(Item{r, c, 0, 0});
+            if (!D.fused) {
+                D.kcu = kWideCenters;
+                for (int c = 0; c < D.k; c += kWideCenters) items.push_back(Item{r, c, 0, 0});
+            }
             D.nuitems = (int)items.size() - D.uitem0;
         }
     }
@@ -1577,7 +1336,12 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         (long long *)ctx_scratch(ctx, SC_FIXSCALE, sizeof(long long) * (sum_words + part_words + 1));
     int *d_err = (int *)ctx_scratch(ctx, SC_RECHECK, 128);
     uint32_t *d_box = (uint32_t *)ctx_scratch(ctx, SC_BOX, sizeof(uint32_t) * (box_words + 1));
-    if (!d_plan || !d_rs || !d_obj || !d_sum || !d_err || !d_box) return SUBKM_ENOMEM;
+    int32_t *d_cnt = (int32_t *)ctx_scratch(ctx, SC_WCNT, sizeof(int32_t) * (cnt_words + 2));
+    int32_t *d_order = (int32_t *)ctx_scratch(ctx, SC_WORDER, sizeof(int32_t) * (order_words + 1));
+    uint4 *d_frags = (uint4 *)ctx_scratch(ctx, SC_FRAGS, sizeof(uint4) * (frag_words + 1));
+    float *d_cn = (float *)ctx_scratch(ctx, SC_CNORM, sizeof(float) * (cn_words + 16));
+    if (!d_plan || !d_rs || !d_obj || !d_sum || !d_err || !d_box || !d_cnt || !d_order || !d_frags || !d_cn)
+        return SUBKM_ENOMEM;
     char *h = (char *)ctx_pinned(ctx, b_plan + 64);
     if (!h) return SUBKM_ENOMEM;
     DevRun *d_runs = (DevRun *)d_plan;
@@ -1597,11 +1361,17 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     hipLaunchKernelGGL(k_fill_i64, dim3(std::min<int64_t>(ceil_div(sum_words + 1, 256), 2048)),
                        dim3(256), 0, s, d_sum, sum_words + 1);
     SUBKM_LAUNCHED(ctx);
+    if (cnt_words) {
+        const int64_t w = ceil_div(cnt_words, 2);
+        hipLaunchKernelGGL(k_fill_i64, dim3(std::min<int64_t>(ceil_div(w, 256), 2048)), dim3(256), 0, s,
+                           (long long *)d_cnt, w);
+        SUBKM_LAUNCHED(ctx);
+    }
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, (long long *)d_err, 16);
     SUBKM_LAUNCHED(ctx);
     {
         // attribute-wise bounds of every run: reference point of the
-        // matrix-core path and fixed-point scale of the sums
+        // matrix-core paths and fixed-point scale of the sums
         int64_t nmax = 0;
         int dmax = 1;
         for (int r = 0; r < R; ++r) {
@@ -1625,6 +1395,42 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     long long *parts = d_sum + sum_words;
     unsigned long long *d_rechecks = (unsigned long long *)(d_err + 16);
 
+    // one assignment launch for runs [r0, r1), which share path and attribute count
+    auto assign_seg = [&](int r0, int r1, int a) -> subkm_status {
+        const DevRun &D0 = dr[r0];
+        const int i0 = D0.item0, ni = dr[r1 - 1].item0 + dr[r1 - 1].nitems - i0;
+        const int last = a == max_iter ? 1 : 0;
+        if (D0.fused)
+            return assign_acc_d(ctx, D0.d, D0.mf != 0, ni, i0, P, d_runs, d_items, C, labels, d_rs, d_obj,
+                                gsum, d_box, a < max_iter ? 1 : 0);
+        if (D0.split) {
+            int kt = 0;
+            for (int r = r0; r < r1; ++r) kt = std::max(kt, (int)ceil_div(dr[r].k, 16));
+            const int S = (int)ceil_div(D0.d, 32);
+            SUBKM_TRY(wide_split_prep(ctx, r0, r1 - r0, kt, S, d_runs, C, d_box, d_frags, d_cn, d_rs));
+            return wide_assign_split(ctx, S, i0, ni, P, d_runs, d_items, C, d_frags, d_cn, labels, d_rs,
+                                     d_obj, d_box, last);
+        }
+        return assign_big_d(ctx, D0.d, ni, i0, P, d_runs, d_items, C, labels, d_rs, d_obj, d_box, last);
+    };
+    // one update for runs [r0, r1), all on-chip or all wide
+    auto update_seg = [&](int r0, int r1) -> subkm_status {
+        if (dr[r0].fused) {
+            ProfScope ps(ctx, PK_UPDATE);
+            hipLaunchKernelGGL(k_update_fin, dim3(r1 - r0), dim3(kAT), 0, s, d_runs, r0, C, d_rs, gsum, tol);
+            SUBKM_LAUNCHED(ctx);
+            return SUBKM_OK;
+        }
+        const int i0 = dr[r0].item0, ni = dr[r1 - 1].item0 + dr[r1 - 1].nitems - i0;
+        const int u0 = dr[r0].uitem0, nu = dr[r1 - 1].uitem0 + dr[r1 - 1].nuitems - u0;
+        return wide_update(ctx, r0, r1 - r0, i0, ni, u0, nu, P, d_runs, d_items, labels, C, d_rs, d_cnt,
+                           d_order, tol);
+    };
+    auto same_assign = [&](int a, int b) {
+        return dr[a].d == dr[b].d && dr[a].fused == dr[b].fused && dr[a].mf == dr[b].mf &&
+               dr[a].split == dr[b].split;
+    };
+
     if (batched) {
         for (const Group &g : groups)
             SUBKM_TRY(persist_d(ctx, g.d, g.mf != 0, g.blocks, P, d_runs, d_tasks, d_toff + g.block0,
@@ -1632,65 +1438,27 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     } else if (form == SUBKM_FORM_PLAIN) {
         // one run at a time, one launch per phase
         for (int r = 0; r < R; ++r) {
-            const DevRun &D = dr[r];
             for (int a = 0; a <= max_iter; ++a) {
-                if (D.fused) {
-                    SUBKM_TRY(assign_acc_d(ctx, D.d, D.mf != 0, D.nitems, D.item0, P, d_runs, d_items,
-                                           C, labels, d_rs, d_obj, gsum, d_box, a < max_iter ? 1 : 0));
-                } else {
-                    SUBKM_TRY(assign_big_d(ctx, D.d, D.nitems, D.item0, P, d_runs, d_items, C, labels,
-                                           d_rs, d_obj, d_box));
-                }
+                SUBKM_TRY(assign_seg(r, r + 1, a));
                 if (a == max_iter) break;
-                ProfScope ps(ctx, PK_UPDATE);
-                if (D.fused) {
-                    hipLaunchKernelGGL(k_update_fin, dim3(1), dim3(kAT), 0, s, d_runs, r, C, d_rs, gsum, tol);
-                } else {
-                    hipLaunchKernelGGL(k_upd_acc, dim3(nuacc[r]), dim3(kAT), 0, s, P, d_runs, d_items,
-                                       uacc0[r], labels, d_rs, gsum);
-                    SUBKM_LAUNCHED(ctx);
-                    hipLaunchKernelGGL(k_upd_fin, dim3(D.nuitems), dim3(kAT), 0, s, d_runs, d_items,
-                                       D.uitem0, C, d_rs, gsum, tol);
-                }
-                SUBKM_LAUNCHED(ctx);
+                SUBKM_TRY(update_seg(r, r + 1));
             }
         }
     } else {
-        // batched request with runs beyond the LDS budget: every phase is one
-        // launch per attribute count (or path) over all runs
+        // batched request with runs beyond the on-chip budget: every phase is
+        // one launch per group of consecutive runs of the same path
         for (int a = 0; a <= max_iter; ++a) {
             for (int r0 = 0; r0 < R;) {
                 int r1 = r0 + 1;
-                while (r1 < R && dr[r1].d == dr[r0].d && dr[r1].fused == dr[r0].fused &&
-                       dr[r1].mf == dr[r0].mf)
-                    ++r1;
-                const int i0 = dr[r0].item0, ni = dr[r1 - 1].item0 + dr[r1 - 1].nitems - i0;
-                if (dr[r0].fused)
-                    SUBKM_TRY(assign_acc_d(ctx, dr[r0].d, dr[r0].mf != 0, ni, i0, P, d_runs, d_items, C,
-                                           labels, d_rs, d_obj, gsum, d_box, a < max_iter ? 1 : 0));
-                else
-                    SUBKM_TRY(assign_big_d(ctx, dr[r0].d, ni, i0, P, d_runs, d_items, C, labels, d_rs,
-                                           d_obj, d_box));
+                while (r1 < R && same_assign(r0, r1)) ++r1;
+                SUBKM_TRY(assign_seg(r0, r1, a));
                 r0 = r1;
             }
             if (a == max_iter) break;
-            ProfScope ps(ctx, PK_UPDATE);
             for (int r0 = 0; r0 < R;) {
                 int r1 = r0 + 1;
                 while (r1 < R && dr[r1].fused == dr[r0].fused) ++r1;
-                if (dr[r0].fused) {
-                    hipLaunchKernelGGL(k_update_fin, dim3(r1 - r0), dim3(kAT), 0, s, d_runs, r0, C,
-                                       d_rs, gsum, tol);
-                } else {
-                    const int a0 = uacc0[r0], na = uacc0[r1 - 1] + nuacc[r1 - 1] - a0;
-                    hipLaunchKernelGGL(k_upd_acc, dim3(na), dim3(kAT), 0, s, P, d_runs, d_items, a0,
-                                       labels, d_rs, gsum);
-                    SUBKM_LAUNCHED(ctx);
-                    const int u0 = dr[r0].uitem0, nu = dr[r1 - 1].uitem0 + dr[r1 - 1].nuitems - u0;
-                    hipLaunchKernelGGL(k_upd_fin, dim3(nu), dim3(kAT), 0, s, d_runs, d_items, u0, C,
-                                       d_rs, gsum, tol);
-                }
-                SUBKM_LAUNCHED(ctx);
+                SUBKM_TRY(update_seg(r0, r1));
                 r0 = r1;
             }
         }

@@ -1,0 +1,705 @@
+// Lloyd's k-means for runs whose centers do not fit on chip (Sec. II
+// Algorithm 1 step 4 for large subclusters, Sec. V for the final run).
+//
+// Assignment with split-bfloat16 products (precision SUBKM_PREC_BF16).
+//   Every run is centered on the midpoint m of its bounding box.  Before each
+//   assignment the centers are turned into matrix-core fragments of
+//   a = -2 (c - m) = a_hi + a_lo, both bfloat16 (a_hi = bf16(a),
+//   a_lo = bf16(a - a_hi)); the points are split the same way in registers.
+//   Three bfloat16 products a_hi x_hi + a_hi x_lo + a_lo x_hi, accumulated
+//   in float32 on the matrix cores (v_mfma_f32_16x16x32_bf16) in two chains,
+//   plus ||c - m||^2 and ||x - m||^2 give a float32 estimate D~ of
+//   ||x - c||^2 whose error is below a bound E(x) (see split_bound).  A single
+//   bfloat16 product would leave an error bound near 1% of ||x-m|| ||c-m||,
+//   so large that almost every point of a dense run would need a recheck.
+//
+//   Every lane keeps the three smallest D~ of its centers.  The index of a
+//   center rides in the 10 low mantissa bits of its value, so the minimum and
+//   median instructions move it along for free; the perturbation (below
+//   2^-13 |D~|) enters the bound.  Then, per point:
+//     certain    the second smallest is provably larger than the smallest:
+//                label = that center;
+//     two-way    the third smallest is provably larger: binary64 distances to
+//                the two candidates decide (lowest index on ties);
+//     pooled     otherwise: the block collects such points, recomputes their
+//                distances to all centers and keeps every center that cannot
+//                be excluded, then compares those in binary64.
+//   All binary64 distances use the arithmetic of the objective (attributes
+//   left to right, separate multiply and add), so labels are those of exact
+//   binary64 arithmetic on the float32 inputs, as in every other path.
+//
+// Update (every wide run, either precision).  Labels are counted per center,
+// the counts scanned into starts, the points of the run ordered by label;
+// then every center is the mean of its points, summed exactly as 64-bit
+// fixed point (the same quantisation as the on-chip path), so centers do not
+// depend on the order of the work.  A center without points stays.  The
+// largest Euclidean move of the run decides convergence (strictly below tol).
+#include "lloyd_dev.h"
+
+#include <algorithm>
+#include <cmath>
+
+#pragma clang fp contract(off)
+
+namespace subkm_lloyd {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kPadNorm = 1.0e36f;  // ||c - m||^2 given to the padding rows of the last tile
+constexpr float kBig = 3.0e38f;      // initial tracked value
+constexpr uint32_t kIdxBits = 0x3FFu;  // center index bits of a tracked value (k <= 1024)
+constexpr int kCandCap = 1024;         // candidates per pooled round (16 points)
+constexpr float kMaxNorm = 1.0e15f;    // ||x - m||, ||c - m|| beyond this: full binary64 scan
+
+__device__ __forceinline__ uint32_t bf16_bits(float a) {
+    const uint32_t u = __float_as_uint(a);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;  // round to nearest even
+}
+
+// a = hi + lo + r with hi = bf16(a), lo = bf16(a - hi), |r| <= 2^-16 |a|;
+// a - hi is exact in float32 (hi holds the leading bits of a)
+__device__ __forceinline__ void split_bf16(float a, uint32_t &h, uint32_t &l) {
+    h = bf16_bits(a);
+    l = bf16_bits(a - __uint_as_float(h << 16));
+}
+
+__device__ __forceinline__ bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ float fmin3(float a, float b) {
+    return __builtin_amdgcn_fmed3f(a, b, -3.402823466e38f);
+}
+__device__ __forceinline__ float fmax3(float a, float b) {
+    return __builtin_amdgcn_fmed3f(a, b, 3.402823466e38f);
+}
+
+// keep the three smallest of (b1 <= b2 <= b3) and e (all distinct)
+__device__ __forceinline__ void top3_insert(float &b1, float &b2, float &b3, float e) {
+    b3 = __builtin_amdgcn_fmed3f(b2, b3, fmax3(b1, e));
+    b2 = __builtin_amdgcn_fmed3f(b1, b2, e);
+    b1 = fmin3(b1, e);
+}
+
+__device__ __forceinline__ float encode(float v, uint32_t idx) {
+    return __uint_as_float((__float_as_uint(v) & ~kIdxBits) | idx);
+}
+
+// Bounds of the value before the index was put into it: D~ lies in
+// [lo_of(e), hi_of(e)] (|e - D~| < 2^-13 |D~|, plus the subnormal range).
+__device__ __forceinline__ double lo_of(float e) {
+    const double v = e;
+    return v - 0x1p-12 * fabs(v) - 1e-38;
+}
+__device__ __forceinline__ double hi_of(float e) {
+    const double v = e;
+    return v + 0x1p-12 * fabs(v) + 1e-38;
+}
+
+// Error bound of one D~ for a point with ||x^ - m|| <= rx against centers
+// with ||c^ - m|| <= rc (x^, c^ the float32 centered values), for S steps of
+// 32 attributes (Dp = 32 S products per chain pass):
+//   split      a x - (a_hi x_hi + a_hi x_lo + a_lo x_hi), summed over the
+//              attributes: <= 2 (3 ub^2 + 2 ub^3) rx rc
+//   chain 1    ||c - m||^2 + a_hi . x_hi, Dp additions in any order with
+//              any faithful rounding (u' = 2^-23): gamma'_Dp (rc^2 (1+u) +
+//              2 (1+ub)^2 rx rc)
+//   chain 2    a_hi . x_lo + a_lo . x_hi: gamma'_2Dp 4 ub (1+ub) rx rc
+//   combining  two float32 additions: 2 u' 1.05 (rx + rc)^2
+//   centering  x^ = fl(x - m), c^ = fl(c - m): 2 u 1.02 (rx + rc)^2
+//   norm       ||c^||^2 rounded once to float32: 1.01 u rc^2
+// plus 1e-12 (rx + rc)^2 for the binary64 arithmetic that decides, and an
+// absolute term for the subnormal range.  Products of bfloat16 values are
+// exact in float32.
+__device__ __forceinline__ double split_bound(int S, double rx, double rc) {
+    const double u = 0x1p-24, u2 = 0x1p-23, ub = 0x1p-8;
+    const double dp = 32.0 * S;
+    const double g1 = dp * u2 / (1.0 - dp * u2), g2 = 2.0 * dp * u2 / (1.0 - 2.0 * dp * u2);
+    const double cA = 2.0 * (3.0 * ub * ub + 2.0 * ub * ub * ub) + g1 * 2.0 * (1.0 + ub) * (1.0 + ub) +
+                      g2 * 4.0 * ub * (1.0 + ub);
+    const double cC = g1 * (1.0 + u) + 1.01 * u;
+    const double cB = 2.0 * u2 * 1.05 + 2.0 * u * 1.02 + 1e-12;
+    const double s = rx + rc;
+    return cA * rx * rc + cC * rc * rc + cB * s * s + 1e-30;
+}
+
+// ---------------------------------------------------------------------------
+// Center fragments.  For tile t (centers 16t .. 16t+15), step s (attributes
+// 32s .. 32s+31) and part p (0 hi, 1 lo), lane l of the 64-lane fragment
+// holds center 16t + l % 16, attributes 32s + 8 (l / 16) + j, j = 0..7, as
+// eight bfloat16 values: the A operand of v_mfma_f32_16x16x32_bf16.
+__global__ __launch_bounds__(256) void k_split_prep(const DevRun *__restrict__ runs, int r0,
+                                                   const float *__restrict__ C,
+                                                   const uint32_t *__restrict__ boxes, uint4 *frags,
+                                                   float *cnorm, RunState *rstate) {
+    __shared__ double s_red[256];
+    const int r = r0 + blockIdx.y;
+    const DevRun R = runs[r];
+    if (!R.split) return;
+    RunState *rs = rstate + r;
+    if (rs->phase == PH_DONE) return;
+    const int d = R.d, k = R.k;
+    const int S = (d + 31) / 32;
+    const int KT = (k + 15) / 16;
+    const uint32_t *box = boxes + R.box_off;
+    const float *Cr = C + R.c_off;
+    const int64_t nf = (int64_t)KT * S * 64;
+    const int64_t step = (int64_t)gridDim.x * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nf; e += step) {
+        const int l = (int)(e & 63);
+        const int64_t ts = e >> 6;  // t * S + s
+        const int s = (int)(ts % S);
+        const int64_t t = ts / S;
+        const int64_t c = t * 16 + (l & 15);
+        const int j0 = 32 * s + 8 * (l >> 4);
+        uint32_t hb[8], lb[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int dim = j0 + j;
+            float a = 0.0f;
+            if (c < k && dim < d) a = -2.0f * (Cr[c * d + dim] - box_mid(box, d, dim));
+            split_bf16(a, hb[j], lb[j]);
+        }
+        uint4 H, L;
+        H.x = hb[0] | (hb[1] << 16);
+        H.y = hb[2] | (hb[3] << 16);
+        H.z = hb[4] | (hb[5] << 16);
+        H.w = hb[6] | (hb[7] << 16);
+        L.x = lb[0] | (lb[1] << 16);
+        L.y = lb[2] | (lb[3] << 16);
+        L.z = lb[4] | (lb[5] << 16);
+        L.w = lb[6] | (lb[7] << 16);
+        frags[R.frag_off + (ts * 2 + 0) * 64 + l] = H;
+        frags[R.frag_off + (ts * 2 + 1) * 64 + l] = L;
+    }
+    double mx = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < (int64_t)KT * 16; c += step) {
+        float v = kPadNorm;
+        if (c < k) {
+            double a = 0.0;
+            for (int j = 0; j < d; ++j) {
+                const double q = (double)(Cr[c * d + j] - box_mid(box, d, j));
+                a = a + q * q;
+            }
+            v = (float)a;
+            mx = fmax(mx, a);
+        }
+        cnorm[R.cn_off + c] = v;
+    }
+    mx = block_max(mx, s_red);
+    if (threadIdx.x == 0 && mx > 0.0)
+        atomicMax(&rs->rc2_bits, (unsigned long long)__double_as_longlong(mx));
+}
+
+// B-operand fragments of one point (lane: column l % 16, attributes
+// 32s + 8 (l / 16) + j) and its partial ||x^ - m||^2 over those attributes.
+template <int S>
+__device__ __forceinline__ void point_frags(const float *X, int64_t p, bool ok, int d,
+                                            const float (&mq)[S][8], int kk, u32x4 (&xh)[S],
+                                            u32x4 (&xl)[S], float &s2) {
+    s2 = 0.0f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        uint32_t hb[8], lb[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int dim = 32 * s + 8 * kk + j;
+            const bool in = ok && dim < d;
+            const float xv = in ? X[p * d + dim] : 0.0f;
+            const float v = in ? xv - mq[s][j] : 0.0f;
+            s2 = __builtin_fmaf(v, v, s2);
+            split_bf16(v, hb[j], lb[j]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            xh[s][q] = hb[2 * q] | (hb[2 * q + 1] << 16);
+            xl[s][q] = lb[2 * q] | (lb[2 * q + 1] << 16);
+        }
+    }
+}
+
+// D~ of the 4 centers (rows 4 (l/16) + r of tile t) against this lane's point
+template <int S>
+__device__ __forceinline__ floatx4 split_tile(const u32x4 (&ah)[S], const u32x4 (&al)[S],
+                                              floatx4 cn4, const u32x4 (&xh)[S],
+                                              const u32x4 (&xl)[S], float xn2) {
+    floatx4 a1 = cn4;
+    floatx4 a2 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah[s]), as_bf(xh[s]), a1, 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah[s]), as_bf(xl[s]), a2, 0, 0, 0);
+        a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(al[s]), as_bf(xh[s]), a2, 0, 0, 0);
+    }
+    floatx4 v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = (a1[r] + a2[r]) + xn2;
+    return v;
+}
+
+template <int S>
+__device__ __forceinline__ void load_center_tile(const uint4 *F, int t, int lane, u32x4 (&ah)[S],
+                                                 u32x4 (&al)[S]) {
+    const u32x4 *Ft = reinterpret_cast<const u32x4 *>(F) + (int64_t)t * S * 128;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        ah[s] = Ft[(s * 2 + 0) * 64 + lane];
+        al[s] = Ft[(s * 2 + 1) * 64 + lane];
+    }
+}
+
+enum : int32_t { ST_CERTAIN = 0, ST_TWO = 1, ST_POOL = 2, ST_FULL = 3 };
+
+// Assignment of one tile of kAT points of a split run: four wavefronts of 64
+// points, each point's fragments held in registers while all center tiles
+// stream through (fragments read straight from memory, the next tile's while
+// the current one computes).
+template <int S>
+__global__ __launch_bounds__(kAT) void k_assign_split(
+    const float *__restrict__ P, const DevRun *__restrict__ runs, const Item *__restrict__ items,
+    int item_base, const float *__restrict__ C, const uint4 *__restrict__ frags,
+    const float *__restrict__ cnorm, int32_t *labels, RunState *rstate, double *objpart,
+    const uint32_t *__restrict__ boxes, int last_pass) {
+    __shared__ int32_t s_c1[kAT], s_c2[kAT], s_st[kAT], s_lab[kAT];
+    __shared__ float s_thr[kAT];
+    __shared__ int32_t s_pool[kAT];
+    __shared__ uint32_t s_npool, s_ncand;
+    __shared__ int32_t s_cq[kCandCap], s_cc[kCandCap];
+    __shared__ double s_cd[kCandCap];
+    __shared__ double s_red[kAT];
+
+    const Item itm = items[item_base + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    RunState *rs = rstate + itm.run;
+    const int32_t ph = rs->phase;
+    if (ph == PH_DONE) return;
+    const bool want_obj = last_pass || ph == PH_FINAL;
+    const int d = R.d, k = R.k, KT = (k + 15) / 16;
+    const float *X = P + R.x_off;
+    const float *Cr = C + R.c_off;
+    const uint32_t *box = boxes + R.box_off;
+    const uint4 *F = frags + R.frag_off;
+    const float *cnr = cnorm + R.cn_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kk = lane >> 4;
+    const int64_t first_w = itm.first + wave * 64;
+    if (threadIdx.x == 0) s_npool = 0;
+
+    float mq[S][8];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int dim = 32 * s + 8 * kk + j;
+            mq[s][j] = dim < d ? box_mid(box, d, dim) : 0.0f;
+        }
+
+    u32x4 xh[4][S], xl[4][S];
+    float xn2[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int64_t p = first_w + g * 16 + col;
+        float s2;
+        point_frags<S>(X, p, p < R.n, d, mq, kk, xh[g], xl[g], s2);
+        s2 += __shfl_xor(s2, 16, 64);
+        s2 += __shfl_xor(s2, 32, 64);
+        xn2[g] = s2;
+    }
+
+    float b1[4], b2[4], b3[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) b1[g] = b2[g] = b3[g] = kBig;
+
+    u32x4 ah[S], al[S], nh[S], nl[S];
+    load_center_tile<S>(F, 0, lane, ah, al);
+    for (int t = 0; t < KT; ++t) {
+        if (t + 1 < KT) load_center_tile<S>(F, t + 1, lane, nh, nl);
+        const floatx4 cn4 = *reinterpret_cast<const floatx4 *>(cnr + t * 16 + 4 * kk);
+        const uint32_t cbase = (uint32_t)(t * 16 + 4 * kk);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const floatx4 v = split_tile<S>(ah, al, cn4, xh[g], xl[g], xn2[g]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) top3_insert(b1[g], b2[g], b3[g], encode(v[r], cbase + r));
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            ah[s] = nh[s];
+            al[s] = nl[s];
+        }
+    }
+
+    // the four lanes of a point hold disjoint center sets: merge their triples
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            const float o1 = __shfl_xor(b1[g], o, 64);
+            const float o2 = __shfl_xor(b2[g], o, 64);
+            const float o3 = __shfl_xor(b3[g], o, 64);
+            top3_insert(b1[g], b2[g], b3[g], o1);
+            top3_insert(b1[g], b2[g], b3[g], o2);
+            top3_insert(b1[g], b2[g], b3[g], o3);
+        }
+
+    const double rc2 = __longlong_as_double((long long)rs->rc2_bits);
+    const double rc = sqrt(rc2) * (1.0 + 1e-12);
+    if (kk == 0) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const double rx = sqrt((double)xn2[g]) * (1.0 + 0x1p-14);
+            const double E = split_bound(S, rx, rc);
+            const int32_t c1 = (int32_t)(__float_as_uint(b1[g]) & kIdxBits);
+            const int32_t c2 = (int32_t)(__float_as_uint(b2[g]) & kIdxBits);
+            const double top = hi_of(b1[g]) + 2.0 * E;
+            int32_t st;
+            if (!(rx < kMaxNorm && rc < kMaxNorm) || c1 >= k) st = ST_FULL;
+            else if (k == 1 || lo_of(b2[g]) > top) st = ST_CERTAIN;
+            else if (lo_of(b3[g]) > top && c2 < k) st = ST_TWO;
+            else st = ST_POOL;
+            // pooled points keep every center whose tracked value could lie
+            // below top: e <= lo_of^-1(top), rounded up
+            const double thr = top >= 0.0 ? (top + 1e-38) / (1.0 - 0x1p-12) : (top + 1e-38) / (1.0 + 0x1p-12);
+            const int slot = wave * 64 + g * 16 + col;
+            s_c1[slot] = c1;
+            s_c2[slot] = c2;
+            s_st[slot] = st;
+            s_thr[slot] = (float)(thr + 0x1p-20 * fabs(thr) + 1e-37);
+        }
+    }
+    __syncthreads();  // LDS results of every wavefront (and s_npool = 0) visible
+
+    const int my = threadIdx.x;
+    const int64_t i = itm.first + my;
+    const bool valid = i < R.n;
+    const float *xg = X + (valid ? i : 0) * d;
+    int32_t st = valid ? s_st[my] : ST_CERTAIN;
+    int32_t lab = s_c1[my];
+    double obj = 0.0;
+    bool have_obj = false;
+    if (st == ST_TWO) {
+        const int32_t c2 = s_c2[my];
+        double d1 = dist64(xg, Cr + (int64_t)lab * d, d);
+        const double d2 = dist64(xg, Cr + (int64_t)c2 * d, d);
+        if (d2 < d1 || (d2 == d1 && c2 < lab)) {
+            lab = c2;
+            d1 = d2;
+        }
+        obj = d1;
+        have_obj = true;
+    } else if (st == ST_POOL) {
+        s_pool[atomicAdd(&s_npool, 1u)] = my;
+    }
+    // full scans: one wavefront per point
+    {
+        unsigned long long todo = __ballot(st == ST_FULL);
+        while (todo) {
+            const int t = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int32_t w = wave_argmin64(X + (first_w + t) * d, Cr, d, k);
+            if (lane == t) lab = w;
+        }
+    }
+    __syncthreads();
+    const int np = (int)s_npool;
+    for (int q0 = 0; q0 < np; q0 += 16) {
+        const int nq = np - q0 < 16 ? np - q0 : 16;
+        if (threadIdx.x == 0) s_ncand = 0;
+        __syncthreads();
+        {
+            // every wavefront rebuilds the fragments of the (up to) 16 pooled
+            // points and scans its share of the center tiles
+            const bool okq = col < nq;
+            const int pl = s_pool[q0 + (okq ? col : 0)];
+            u32x4 yh[S], yl[S];
+            float y2;
+            point_frags<S>(X, itm.first + pl, true, d, mq, kk, yh, yl, y2);
+            y2 += __shfl_xor(y2, 16, 64);
+            y2 += __shfl_xor(y2, 32, 64);
+            const float thr = okq ? s_thr[pl] : -kBig;
+            for (int t = wave; t < KT; t += kAT / 64) {
+                u32x4 ch[S], cl[S];
+                load_center_tile<S>(F, t, lane, ch, cl);
+                const floatx4 cn4 = *reinterpret_cast<const floatx4 *>(cnr + t * 16 + 4 * kk);
+                const floatx4 v = split_tile<S>(ch, cl, cn4, yh, yl, y2);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = t * 16 + 4 * kk + r;
+                    if (c < k && encode(v[r], (uint32_t)c) <= thr) {
+                        const uint32_t q = atomicAdd(&s_ncand, 1u);
+                        if (q < (uint32_t)kCandCap) {
+                            s_cq[q] = col;
+                            s_cc[q] = c;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t ncand = s_ncand;
+        if (ncand <= (uint32_t)kCandCap) {
+            for (uint32_t e = threadIdx.x; e < ncand; e += kAT) {
+                const int pl = s_pool[q0 + s_cq[e]];
+                s_cd[e] = dist64(X + (itm.first + pl) * d, Cr + (int64_t)s_cc[e] * d, d);
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < nq) {
+                double best = INFINITY;
+                int32_t bi = 0x7fffffff;
+                for (uint32_t e = 0; e < ncand; ++e)
+                    if (s_cq[e] == (int)threadIdx.x) {
+                        const double v = s_cd[e];
+                        if (v < best || (v == best && s_cc[e] < bi)) {
+                            best = v;
+                            bi = s_cc[e];
+                        }
+                    }
+                s_lab[s_pool[q0 + threadIdx.x]] = bi;
+            }
+        } else {
+            // too many candidates (not expected): full scans of this round
+            for (int q = wave; q < nq; q += kAT / 64) {
+                const int pl = s_pool[q0 + q];
+                const int32_t w = wave_argmin64(X + (itm.first + pl) * d, Cr, d, k);
+                if (lane == 0) s_lab[pl] = w;
+            }
+        }
+        __syncthreads();
+    }
+    if (st == ST_POOL) lab = s_lab[my];
+    if (valid) {
+        labels[R.lab_off + i] = lab;
+        if (want_obj && !have_obj) obj = dist64(xg, Cr + (int64_t)lab * d, d);
+    }
+    const unsigned long long nre = __popcll(__ballot(valid && st != ST_CERTAIN));
+    if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
+    if (want_obj) {
+        const double tot = block_sum_det(obj, s_red);
+        if (threadIdx.x == 0) objpart[item_base + blockIdx.x] = tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Update of the wide runs.  cnt holds per run (at cnt_off) counts[k],
+// starts[k] and cursors[k]; order holds per run (at lab_off) the run's point
+// indices grouped by label.
+__global__ __launch_bounds__(kAT) void k_wcount(const DevRun *__restrict__ runs,
+                                               const Item *__restrict__ items, int i0,
+                                               const int32_t *__restrict__ labels,
+                                               const RunState *__restrict__ rstate, int32_t *cnt) {
+    const Item itm = items[i0 + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    if (rstate[itm.run].phase != PH_ITER) return;
+    const int64_t i = itm.first + threadIdx.x;
+    if (i >= R.n) return;
+    const int32_t l = labels[R.lab_off + i];
+    if ((uint32_t)l < (uint32_t)R.k) atomicAdd(&cnt[R.cnt_off + l], 1);
+}
+
+// exclusive scan of the counts of run r0 + blockIdx.x into starts and cursors
+__global__ __launch_bounds__(kAT) void k_wscan(const DevRun *__restrict__ runs, int r0,
+                                              const RunState *__restrict__ rstate, int32_t *cnt) {
+    __shared__ int32_t s_v[kAT];
+    const int r = r0 + blockIdx.x;
+    const DevRun R = runs[r];
+    if (R.fused || rstate[r].phase != PH_ITER) return;
+    int32_t *counts = cnt + R.cnt_off;
+    int32_t *starts = counts + R.k;
+    int32_t *cursor = starts + R.k;
+    int32_t carry = 0;
+    for (int c0 = 0; c0 < R.k; c0 += kAT) {
+        const int c = c0 + threadIdx.x;
+        const int32_t v = c < R.k ? counts[c] : 0;
+        s_v[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kAT; o <<= 1) {
+            const int32_t a = threadIdx.x >= (unsigned)o ? s_v[threadIdx.x - o] : 0;
+            __syncthreads();
+            s_v[threadIdx.x] += a;
+            __syncthreads();
+        }
+        const int32_t incl = s_v[threadIdx.x];
+        if (c < R.k) {
+            starts[c] = carry + incl - v;
+            cursor[c] = carry + incl - v;
+        }
+        carry += s_v[kAT - 1];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kAT) void k_wscatter(const DevRun *__restrict__ runs,
+                                                 const Item *__restrict__ items, int i0,
+                                                 const int32_t *__restrict__ labels,
+                                                 const RunState *__restrict__ rstate, int32_t *cnt,
+                                                 int32_t *order) {
+    const Item itm = items[i0 + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    if (rstate[itm.run].phase != PH_ITER) return;
+    const int64_t i = itm.first + threadIdx.x;
+    if (i >= R.n) return;
+    const int32_t l = labels[R.lab_off + i];
+    if ((uint32_t)l >= (uint32_t)R.k) return;
+    const int32_t pos = atomicAdd(&cnt[R.cnt_off + 2 * (int64_t)R.k + l], 1);
+    if ((int64_t)pos < R.n) order[R.lab_off + pos] = (int32_t)i;
+}
+
+// New centers of update item (run, first center c0, kcu centers): one
+// wavefront per center; lanes split the attributes (and, for narrow points,
+// several points at once).  The run's last item to finish decides.
+__global__ __launch_bounds__(kAT) void k_wsum(const float *__restrict__ P,
+                                             const DevRun *__restrict__ runs,
+                                             const Item *__restrict__ items, int u0,
+                                             const int32_t *__restrict__ order, float *C,
+                                             RunState *rstate, int32_t *cnt, double tol) {
+    __shared__ double s_red[kAT];
+    __shared__ uint32_t s_last;
+    const Item itm = items[u0 + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    RunState *rs = rstate + itm.run;
+    const int32_t ph = rs->phase;
+    if (ph == PH_DONE) return;
+    if (ph == PH_FINAL) {
+        // the assignment that just ran was the last one of this run
+        if (itm.first == 0 && threadIdx.x == 0) rs->phase = PH_DONE;
+        return;
+    }
+    const int d = R.d;
+    const int s = fix_shift_of(rs->absmax_bits);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int dg = 1;  // lanes per point: the next power of two >= d, at most 64
+    while (dg < d && dg < 64) dg <<= 1;
+    const int ppw = 64 / dg, sub = lane / dg, j0 = lane % dg;
+    int32_t *counts = cnt + R.cnt_off;
+    const int32_t *starts = counts + R.k;
+    const float *X = P + R.x_off;
+    const int32_t *ord = order + R.lab_off;
+    float *Cr = C + R.c_off;
+    const int c1 = min(R.k, itm.first + R.kcu);
+    double mx = 0.0;
+    for (int c = itm.first + wave; c < c1; c += kAT / 64) {
+        const int32_t n_c = counts[c];
+        const int32_t st = starts[c];
+        double mv2 = 0.0;
+        if (n_c > 0) {
+            for (int jb = 0; jb < d; jb += dg) {
+                const int j = jb + j0;
+                long long a = 0;
+                if (j < d) {
+                    int m = sub;
+                    for (; m + 3 * ppw < n_c; m += 4 * ppw) {
+                        const int32_t p0 = ord[st + m], p1 = ord[st + m + ppw];
+                        const int32_t p2 = ord[st + m + 2 * ppw], p3 = ord[st + m + 3 * ppw];
+                        const float v0 = X[(int64_t)p0 * d + j], v1 = X[(int64_t)p1 * d + j];
+                        const float v2 = X[(int64_t)p2 * d + j], v3 = X[(int64_t)p3 * d + j];
+                        a += to_fixed(v0, s) + to_fixed(v1, s) + to_fixed(v2, s) + to_fixed(v3, s);
+                    }
+                    for (; m < n_c; m += ppw) a += to_fixed(X[(int64_t)ord[st + m] * d + j], s);
+                }
+                for (int o = dg; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
+                double dv2 = 0.0;
+                if (sub == 0 && j < d) {
+                    const float old = Cr[(int64_t)c * d + j];
+                    const double nv = ldexp((double)a, -s) / (double)n_c;
+                    const double dv = nv - (double)old;
+                    dv2 = dv * dv;
+                    Cr[(int64_t)c * d + j] = (float)nv;
+                }
+                // fixed-order tree over the lanes
+                for (int o = 32; o > 0; o >>= 1) dv2 = dv2 + __shfl_xor(dv2, o, 64);
+                mv2 = mv2 + dv2;
+            }
+        }
+        if (lane == 0) counts[c] = 0;
+        mx = fmax(mx, sqrt(mv2));
+    }
+    mx = block_max(mx, s_red);
+    if (threadIdx.x == 0) {
+        atomicMax(&rs->shift_bits, (unsigned long long)__double_as_longlong(mx));
+        __threadfence();
+        s_last = atomicAdd(&rs->ucount, 1u) == (uint32_t)R.nuitems - 1;
+        if (s_last) {
+            __threadfence();
+            const unsigned long long sb =
+                __hip_atomic_load(&rs->shift_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            rs->iters += 1;
+            rs->phase = __longlong_as_double((long long)sb) < tol ? PH_FINAL : PH_ITER;
+            rs->shift_bits = 0;
+            rs->ucount = 0;
+            rs->rc2_bits = 0;
+        }
+    }
+}
+
+template <int S>
+subkm_status launch_split(subkm_ctx *ctx, int i0, int ni, const float *P, const DevRun *runs,
+                          const Item *items, const float *C, const uint4 *frags,
+                          const float *cnorm, int32_t *labels, RunState *rs, double *objpart,
+                          const uint32_t *boxes, int last_pass) {
+    hipLaunchKernelGGL(k_assign_split<S>, dim3(ni), dim3(kAT), 0, ctx->stream, P, runs, items, i0, C,
+                       frags, cnorm, labels, rs, objpart, boxes, last_pass);
+    SUBKM_LAUNCHED(ctx);
+    return SUBKM_OK;
+}
+
+}  // namespace
+
+subkm_status wide_split_prep(subkm_ctx *ctx, int r0, int nr, int kt_max, int steps_max,
+                             const DevRun *runs, const float *C, const uint32_t *boxes,
+                             uint4 *frags, float *cnorm, RunState *rs) {
+    if (nr <= 0) return SUBKM_OK;
+    ProfScope ps(ctx, PK_UPDATE);
+    const int64_t work = std::max<int64_t>((int64_t)kt_max * steps_max * 64, (int64_t)kt_max * 16);
+    const int bx = (int)std::min<int64_t>(ceil_div(work, 256), 1024);
+    hipLaunchKernelGGL(k_split_prep, dim3(bx, nr), dim3(256), 0, ctx->stream, runs, r0, C, boxes,
+                       frags, cnorm, rs);
+    SUBKM_LAUNCHED(ctx);
+    return SUBKM_OK;
+}
+
+subkm_status wide_assign_split(subkm_ctx *ctx, int S, int i0, int ni, const float *P,
+                               const DevRun *runs, const Item *items, const float *C,
+                               const uint4 *frags, const float *cnorm, int32_t *labels,
+                               RunState *rs, double *objpart, const uint32_t *boxes,
+                               int last_pass) {
+    if (ni <= 0) return SUBKM_OK;
+    ProfScope ps(ctx, PK_ASSIGN);
+    switch (S) {
+        case 1: return launch_split<1>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
+        case 2: return launch_split<2>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
+        case 3: return launch_split<3>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
+        case 4: return launch_split<4>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
+        default: return set_err(ctx, SUBKM_EINVAL, "split path: %d attribute steps", S);
+    }
+}
+
+subkm_status wide_update(subkm_ctx *ctx, int r0, int nr, int i0, int ni, int u0, int nu,
+                         const float *P, const DevRun *runs, const Item *items,
+                         const int32_t *labels, float *C, RunState *rs, int32_t *cnt,
+                         int32_t *order, double tol) {
+    if (nr <= 0) return SUBKM_OK;
+    ProfScope ps(ctx, PK_UPDATE);
+    hipStream_t s = ctx->stream;
+    if (ni > 0) {
+        hipLaunchKernelGGL(k_wcount, dim3(ni), dim3(kAT), 0, s, runs, items, i0, labels, rs, cnt);
+        SUBKM_LAUNCHED(ctx);
+    }
+    hipLaunchKernelGGL(k_wscan, dim3(nr), dim3(kAT), 0, s, runs, r0, rs, cnt);
+    SUBKM_LAUNCHED(ctx);
+    if (ni > 0) {
+        hipLaunchKernelGGL(k_wscatter, dim3(ni), dim3(kAT), 0, s, runs, items, i0, labels, rs, cnt,
+                           order);
+        SUBKM_LAUNCHED(ctx);
+    }
+    if (nu > 0) {
+        hipLaunchKernelGGL(k_wsum, dim3(nu), dim3(kAT), 0, s, P, runs, items, u0, order, C, rs, cnt,
+                           tol);
+        SUBKM_LAUNCHED(ctx);
+    }
+    return SUBKM_OK;
+}
+
+}  // namespace subkm_lloyd

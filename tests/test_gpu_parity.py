@@ -347,3 +347,133 @@ def test_mid_workload_full_size(km, oracle):
     lab, obj, _, _ = oracle.assign(Sr.astype(np.float64), fin)
     assert np.array_equal(host(out["labels"]), lab)
     assert abs(host(out["sse"])[0] - obj) <= TOL * obj
+
+
+# ------------------------------------------- split-bfloat16 path (wide runs, BF16)
+PREC_BF16 = 1
+
+
+@pytest.mark.parametrize("n,d,k", [(3001, 32, 300), (2000, 48, 200), (1500, 64, 100), (900, 128, 300),
+                                   (2600, 100, 257), (500, 128, 33), (2048, 128, 1024), (4100, 33, 130)])
+def test_lloyd_shadow_bf16(km, oracle, n, d, k):
+    """Split-bfloat16 products on matrix cores: labels must still be those of
+    exact arithmetic, centers and objective within the tolerance, step by
+    step against the oracle (attribute counts 32..128, padded and ragged
+    tiles, k up to 1024)."""
+    assert k * d > 4096
+    X, _ = synth.gaussian_blobs(n, d, max(2, k // 8), seed=n + d + 1, sigma=0.7)
+    S, _, _ = oracle.scale(X)
+    shadow_steps(km, oracle, S, S[:k], steps=2, precision=PREC_BF16)
+
+
+def test_lloyd_bf16_exact_ties(km, oracle):
+    # every point equidistant from two copies of its center: exact ties on
+    # every point, resolved to the lower index; the copies stay empty
+    rng = np.random.default_rng(12)
+    base = rng.uniform(0, 1, (40, 64)).astype(np.float32)
+    X = np.repeat(base, 25, axis=0)
+    C0 = np.concatenate([base, base])
+    assert C0.shape[0] * 64 > 4096
+    shadow_steps(km, oracle, X, C0, steps=2, precision=PREC_BF16)
+
+
+def test_lloyd_bf16_dense_near_ties(km, oracle):
+    # many centers packed inside one blob: small gaps, frequent two-way and
+    # pooled rechecks
+    X, _ = synth.gaussian_blobs(6000, 128, 2, seed=77, sigma=0.3)
+    S, _, _ = oracle.scale(X)
+    shadow_steps(km, oracle, S, S[:512], steps=2, precision=PREC_BF16)
+
+
+def test_forms_agree_bf16(km, oracle):
+    rng = np.random.default_rng(45)
+    runs, ks = [], []
+    for j in range(5):
+        n = int(rng.integers(2000, 7000))
+        d = [32, 64, 128, 40, 96][j]
+        X, _ = synth.gaussian_blobs(n, d, 10, seed=500 + j, sigma=0.5)
+        runs.append(oracle.scale(X)[0])
+        ks.append(int(rng.integers(130, 600)))
+    a, ia, sa = run_batch(km, runs, ks, 6, 1e-6, form=0, precision=PREC_BF16)
+    b, ib, sb = run_batch(km, runs, ks, 6, 1e-6, form=1, precision=PREC_BF16)
+    c, ic, sc = run_batch(km, runs, ks, 6, 1e-6, form=0, precision=PREC_BF16)
+    f, i32, s32 = run_batch(km, runs, ks, 6, 1e-6, form=0, precision=0)
+    assert np.array_equal(ia, ib) and np.array_equal(sa, sb) and np.array_equal(sa, sc)
+    for (ca, la), (cb, lb), (cc, lc), (cf, lf) in zip(a, b, c, f):
+        assert np.array_equal(ca, cb) and np.array_equal(la, lb)
+        assert np.array_equal(ca, cc) and np.array_equal(la, lc)
+        # exact labels in both precisions: the same trajectory
+        assert np.array_equal(ca, cf) and np.array_equal(la, lf)
+    assert np.array_equal(ia, i32) and np.array_equal(sa, s32)
+
+
+def _keys(S, L):
+    # the landmark key of Algorithm 1 in the oracle's arithmetic: binary64,
+    # attributes left to right, separate multiply and add
+    acc = np.zeros(S.shape[0])
+    for j in range(S.shape[1]):
+        q = S[:, j].astype(np.float64) - np.float64(L[j])
+        acc = acc + q * q
+    return acc
+
+
+@pytest.mark.timeout(900)
+def test_precision_workload_full_size(km, oracle):
+    """The precision workload (n = 2^22, d = 128, N = 32768, 1024 local and
+    256 final centers) through cluster() with split-bfloat16 products:
+    scaling bit-exact; the subclustering a partition whose sampled rounds are
+    exactly the N smallest (key, index) of the remaining points; sampled
+    local runs and a sample of the final labels against the oracle."""
+    import paper_1412_1947_amd as subkm
+    job = synth.precision()
+    n, d = job.X.shape
+    X = dev(job.X)
+    out = km.cluster(X, job.N, job.k_local, job.k_final, job.max_iter, job.tol,
+                     precision=subkm.PREC_BF16, intermediates=True, stats=True)
+    S = host(out["S"])
+    Sr, _, _ = oracle.scale(job.X)
+    assert np.array_equal(S, Sr)
+    del X
+    perm = host(out["perm"]).astype(np.int64)
+    N, T = job.N, out["stats"]["T"]
+    assert T == n // N
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    removed = np.zeros(n, dtype=bool)
+    for t in range(T):
+        G = perm[t * N:(t + 1) * N]
+        assert np.all(np.diff(G) > 0), t            # ascending original index
+        if t in (0, 1, 64, T - 1):
+            R = np.flatnonzero(~removed)
+            L = Sr[R].min(axis=0)
+            key = _keys(Sr[R], L)
+            inG = np.isin(R, G)
+            kg, ig = key[inG], R[inG]
+            kr, ir = key[~inG], R[~inG]
+            if kr.size:
+                # lexicographic (key, index): max over G below min over the rest
+                jg = np.lexsort((ig, kg))[-1]
+                jr = np.lexsort((ir, kr))[0]
+                assert (kg[jg], ig[jg]) < (kr[jr], ir[jr]), t
+        removed[G] = True
+    loc = host(out["local_centers"])
+    lsse = host(out["local_sse"])
+    lit = host(out["local_iters"])
+    k = job.k_local
+    for t in (0, T - 1):
+        P = Sr[perm[t * N:(t + 1) * N]].astype(np.float64)
+        C = loc[t * k:(t + 1) * k]
+        lab, obj, _, _ = oracle.assign(P, C)
+        assert abs(lsse[t] - obj) <= TOL * obj
+        assert 1 <= lit[t] <= job.max_iter
+    fin = host(out["centers"])
+    labels = host(out["labels"])
+    rng = np.random.default_rng(3)
+    sample = np.sort(rng.choice(n, 1 << 15, replace=False))
+    lab, _, _, _ = oracle.assign(Sr[sample].astype(np.float64), fin)
+    assert np.array_equal(labels[sample], lab)
+    # objective of the returned labels, summed in binary64
+    tot = 0.0
+    for a in range(0, n, 1 << 19):
+        diff = Sr[a:a + (1 << 19)].astype(np.float64) - fin.astype(np.float64)[labels[a:a + (1 << 19)]]
+        tot += float(np.sum(np.einsum("ij,ij->i", diff, diff)))
+    assert abs(host(out["sse"])[0] - tot) <= TOL * tot
