@@ -688,7 +688,8 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
                                                 const DevRun *__restrict__ runs,
                                                 const Item *__restrict__ items, int item_base,
                                                 const float *__restrict__ C, int32_t *labels,
-                                                RunState *rstate, double *objpart, int last_pass) {
+                                                RunState *rstate, double *objpart, int last_pass,
+                                                int32_t *cnt) {
     __shared__ float sC[kLdsFloats];
     __shared__ int32_t s_list[kAT];
     __shared__ int32_t s_newlab[kAT];
@@ -733,6 +734,8 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
     if (valid) {
         labels[R.lab_off + i] = i1;
         if (want_obj) obj = dist64(xg, Cr + (int64_t)i1 * d, d);
+        // an update follows: count the point for its center
+        if (!last_pass && ph == PH_ITER) atomicAdd(&cnt[R.cnt_off + i1], 1);
     }
     if (threadIdx.x == 0 && nl) atomicAdd(&rstate[itm.run].rechecks, (unsigned long long)nl);
     if (want_obj) {
@@ -754,7 +757,7 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
                                                     const float *__restrict__ C, int32_t *labels,
                                                     RunState *rstate, double *objpart,
                                                     const uint32_t *__restrict__ boxes,
-                                                    int last_pass) {
+                                                    int last_pass, int32_t *cnt) {
     constexpr int KQ = D / 4;
     constexpr int ldc = (kChunkF / D) < 1040 ? (kChunkF / D) : 1040;  // pitch of a staged chunk
     constexpr int kc = ((ldc - 16) / 16) * 16;                         // centers per chunk
@@ -906,6 +909,7 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
     if (valid) {
         labels[R.lab_off + i] = lab;
         if (want_obj) obj = dist64(xg, Cr + (int64_t)lab * D, D);
+        if (!last_pass && ph == PH_ITER) atomicAdd(&cnt[R.cnt_off + lab], 1);
     }
     if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
     if (want_obj) {
@@ -1068,10 +1072,10 @@ subkm_status launch_assign_acc(subkm_ctx *ctx, bool mf, int nitems, int item_bas
 template <int D>
 subkm_status launch_assign(subkm_ctx *ctx, int nitems, int item_base, const float *P,
                            const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                           RunState *rs, double *objpart, int last_pass) {
+                           RunState *rs, double *objpart, int last_pass, int32_t *cnt) {
     ProfScope ps(ctx, PK_ASSIGN);
     hipLaunchKernelGGL(k_assign<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
-                       item_base, C, labels, rs, objpart, last_pass);
+                       item_base, C, labels, rs, objpart, last_pass, cnt);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
@@ -1138,26 +1142,27 @@ template <int D>
 subkm_status launch_assign_big(subkm_ctx *ctx, int nitems, int item_base, const float *P,
                                const DevRun *runs, const Item *items, const float *C,
                                int32_t *labels, RunState *rs, double *objpart,
-                               const uint32_t *boxes, int last_pass) {
+                               const uint32_t *boxes, int last_pass, int32_t *cnt) {
     if constexpr (kHasMF<D>) {
         ProfScope ps(ctx, PK_ASSIGN);
         hipLaunchKernelGGL(k_assign_big<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
-                           item_base, C, labels, rs, objpart, boxes, last_pass);
+                           item_base, C, labels, rs, objpart, boxes, last_pass, cnt);
         SUBKM_LAUNCHED(ctx);
         return SUBKM_OK;
     } else {
         return launch_assign<D>(ctx, nitems, item_base, P, runs, items, C, labels, rs, objpart,
-                                last_pass);
+                                last_pass, cnt);
     }
 }
 
 // assignment of runs beyond the LDS budget: matrix cores when d allows
 subkm_status assign_big_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
                           const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                          RunState *rs, double *objpart, const uint32_t *boxes, int last_pass) {
+                          RunState *rs, double *objpart, const uint32_t *boxes, int last_pass,
+                          int32_t *cnt) {
     if (nitems <= 0) return SUBKM_OK;
     SUBKM_DISPATCH_D(d, launch_assign_big, ctx, nitems, item_base, P, runs, items, C, labels, rs,
-                     objpart, boxes, last_pass);
+                     objpart, boxes, last_pass, cnt);
 }
 
 subkm_status persist_d(subkm_ctx *ctx, int d, bool mf, int blocks, const float *P,
@@ -1239,6 +1244,11 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
             D.sum_off = sum_words;
             sum_words += kd + u.k;
         } else {
+            if (u.d <= kWalkD) {
+                // sums of the centers that cross a walk window
+                D.sum_off = sum_words;
+                sum_words += kd;
+            }
             // centers stream from memory; exact update through labels
             D.cnt_off = cnt_words;
             cnt_words += 3 * (int64_t)u.k;
@@ -1260,6 +1270,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
 
     const bool batched = form == SUBKM_FORM_BATCHED && all_fused;
     std::vector<Item> items;
+    std::vector<int> walk0, nwalk;
     std::vector<Task> tasks;
     std::vector<int32_t> task_off;
     struct Group {
@@ -1322,6 +1333,15 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
             }
             D.nuitems = (int)items.size() - D.uitem0;
         }
+        // walk items of the wide runs: kWalkB label-sorted positions each
+        walk0.assign(R, 0);
+        nwalk.assign(R, 0);
+        for (int r = 0; r < R; ++r) {
+            walk0[r] = (int)items.size();
+            if (!dr[r].fused && dr[r].d <= kWalkD)
+                for (int64_t f = 0; f < dr[r].n; f += kWalkB) items.push_back(Item{r, (int32_t)f, 0, 0});
+            nwalk[r] = (int)items.size() - walk0[r];
+        }
     }
     const int n_items = (int)items.size();
 
@@ -1337,7 +1357,8 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     int *d_err = (int *)ctx_scratch(ctx, SC_RECHECK, 128);
     uint32_t *d_box = (uint32_t *)ctx_scratch(ctx, SC_BOX, sizeof(uint32_t) * (box_words + 1));
     int32_t *d_cnt = (int32_t *)ctx_scratch(ctx, SC_WCNT, sizeof(int32_t) * (cnt_words + 2));
-    int32_t *d_order = (int32_t *)ctx_scratch(ctx, SC_WORDER, sizeof(int32_t) * (order_words + 1));
+    // point indices grouped by label, then their labels
+    int32_t *d_order = (int32_t *)ctx_scratch(ctx, SC_WORDER, sizeof(int32_t) * (2 * order_words + 1));
     uint4 *d_frags = (uint4 *)ctx_scratch(ctx, SC_FRAGS, sizeof(uint4) * (frag_words + 1));
     float *d_cn = (float *)ctx_scratch(ctx, SC_CNORM, sizeof(float) * (cn_words + 16));
     if (!d_plan || !d_rs || !d_obj || !d_sum || !d_err || !d_box || !d_cnt || !d_order || !d_frags || !d_cn)
@@ -1409,9 +1430,10 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
             const int S = (int)ceil_div(D0.d, 32);
             SUBKM_TRY(wide_split_prep(ctx, r0, r1 - r0, kt, S, d_runs, C, d_box, d_frags, d_cn, d_rs));
             return wide_assign_split(ctx, S, i0, ni, P, d_runs, d_items, C, d_frags, d_cn, labels, d_rs,
-                                     d_obj, d_box, last);
+                                     d_obj, d_box, last, d_cnt);
         }
-        return assign_big_d(ctx, D0.d, ni, i0, P, d_runs, d_items, C, labels, d_rs, d_obj, d_box, last);
+        return assign_big_d(ctx, D0.d, ni, i0, P, d_runs, d_items, C, labels, d_rs, d_obj, d_box, last,
+                            d_cnt);
     };
     // one update for runs [r0, r1), all on-chip or all wide
     auto update_seg = [&](int r0, int r1) -> subkm_status {
@@ -1423,8 +1445,9 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         }
         const int i0 = dr[r0].item0, ni = dr[r1 - 1].item0 + dr[r1 - 1].nitems - i0;
         const int u0 = dr[r0].uitem0, nu = dr[r1 - 1].uitem0 + dr[r1 - 1].nuitems - u0;
-        return wide_update(ctx, r0, r1 - r0, i0, ni, u0, nu, P, d_runs, d_items, labels, C, d_rs, d_cnt,
-                           d_order, tol);
+        const int w0 = walk0[r0], nw = walk0[r1 - 1] + nwalk[r1 - 1] - w0;
+        return wide_update(ctx, r0, r1 - r0, i0, ni, w0, nw, u0, nu, P, d_runs, d_items, labels, C, d_rs,
+                           d_cnt, d_order, order_words, gsum, tol);
     };
     auto same_assign = [&](int a, int b) {
         return dr[a].d == dr[b].d && dr[a].fused == dr[b].fused && dr[a].mf == dr[b].mf &&

@@ -10,6 +10,9 @@
 namespace subkm_lloyd {
 
 constexpr int kAT = 256;  // threads per block = points per assignment tile
+constexpr int kWalkD = 128;            // widest points of the balanced update walk
+constexpr int kWalkW = 256;            // positions per wavefront in the walk
+constexpr int kWalkB = 4 * kWalkW;     // positions per walk item (block)
 
 enum : int32_t { PH_ITER = 0, PH_FINAL = 1, PH_DONE = 2 };
 
@@ -163,14 +166,18 @@ subkm_status wide_assign_split(subkm_ctx *ctx, int S, int i0, int ni, const floa
                                const DevRun *runs, const Item *items, const float *C,
                                const uint4 *frags, const float *cnorm, int32_t *labels,
                                RunState *rs, double *objpart, const uint32_t *boxes,
-                               int last_pass);
+                               int last_pass, int32_t *cnt);
 
-// Exact center update of the wide runs from their labels: counts, starts,
-// points ordered by label, then per-center fixed-point sums and the run's
-// convergence decision.
-subkm_status wide_update(subkm_ctx *ctx, int r0, int nr, int i0, int ni, int u0, int nu,
-                         const float *P, const DevRun *runs, const Item *items,
+// Exact center update of the wide runs from their labels (counted per
+// center by the assignment): starts, points ordered by label, then
+// per-center fixed-point sums and the run's convergence decision.
+// order holds the point indices grouped by label at lab_off and their
+// labels at olab_off + lab_off; gsum the int64 sums of the wide runs with
+// d <= kWalkD (at sum_off, zero between calls).  Walk items [w0, w0 + nw)
+// cover kWalkB positions each.
+subkm_status wide_update(subkm_ctx *ctx, int r0, int nr, int i0, int ni, int w0, int nw, int u0,
+                         int nu, const float *P, const DevRun *runs, const Item *items,
                          const int32_t *labels, float *C, RunState *rs, int32_t *cnt,
-                         int32_t *order, double tol);
+                         int32_t *order, int64_t olab_off, long long *gsum, double tol);
 
 }  // namespace subkm_lloyd

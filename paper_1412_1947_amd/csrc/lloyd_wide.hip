@@ -51,7 +51,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr float kPadNorm = 1.0e36f;  // ||c - m||^2 given to the padding rows of the last tile
 constexpr float kBig = 3.0e38f;      // initial tracked value
 constexpr uint32_t kIdxBits = 0x3FFu;  // center index bits of a tracked value (k <= 1024)
-constexpr int kCandCap = 1024;         // candidates per pooled round (16 points)
+constexpr int kCandCap = 512;          // candidates per pooled round (16 points)
 constexpr float kMaxNorm = 1.0e15f;    // ||x - m||, ||c - m|| beyond this: full binary64 scan
 
 __device__ __forceinline__ uint32_t bf16_bits(float a) {
@@ -144,48 +144,50 @@ __global__ __launch_bounds__(256) void k_split_prep(const DevRun *__restrict__ r
     const int KT = (k + 15) / 16;
     const uint32_t *box = boxes + R.box_off;
     const float *Cr = C + R.c_off;
-    const int64_t nf = (int64_t)KT * S * 64;
-    const int64_t step = (int64_t)gridDim.x * 256;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nf; e += step) {
-        const int l = (int)(e & 63);
-        const int64_t ts = e >> 6;  // t * S + s
-        const int s = (int)(ts % S);
-        const int64_t t = ts / S;
-        const int64_t c = t * 16 + (l & 15);
-        const int j0 = 32 * s + 8 * (l >> 4);
-        uint32_t hb[8], lb[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int dim = j0 + j;
-            float a = 0.0f;
-            if (c < k && dim < d) a = -2.0f * (Cr[c * d + dim] - box_mid(box, d, dim));
-            split_bf16(a, hb[j], lb[j]);
-        }
-        uint4 H, L;
-        H.x = hb[0] | (hb[1] << 16);
-        H.y = hb[2] | (hb[3] << 16);
-        H.z = hb[4] | (hb[5] << 16);
-        H.w = hb[6] | (hb[7] << 16);
-        L.x = lb[0] | (lb[1] << 16);
-        L.y = lb[2] | (lb[3] << 16);
-        L.z = lb[4] | (lb[5] << 16);
-        L.w = lb[6] | (lb[7] << 16);
-        frags[R.frag_off + (ts * 2 + 0) * 64 + l] = H;
-        frags[R.frag_off + (ts * 2 + 1) * 64 + l] = L;
-    }
     double mx = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < (int64_t)KT * 16; c += step) {
-        float v = kPadNorm;
-        if (c < k) {
-            double a = 0.0;
-            for (int j = 0; j < d; ++j) {
-                const double q = (double)(Cr[c * d + j] - box_mid(box, d, j));
-                a = a + q * q;
+    // one thread per (tile t, lane l): center 16t + l % 16, attributes
+    // 32s + 8 (l / 16) + j of every step s; a wavefront covers one tile, so
+    // the four lanes of a center finish its squared norm with two exchanges
+    // (a fixed order: the result does not depend on the launch)
+    const int64_t step = (int64_t)gridDim.x * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)KT * 64; e += step) {
+        const int l = (int)(e & 63);
+        const int64_t t = e >> 6;
+        const int64_t c = t * 16 + (l & 15);
+        double a2 = 0.0;
+        for (int s = 0; s < S; ++s) {
+            const int j0 = 32 * s + 8 * (l >> 4);
+            uint32_t hb[8], lb[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int dim = j0 + j;
+                float a = 0.0f;
+                if (c < k && dim < d) {
+                    const float cp = Cr[c * d + dim] - box_mid(box, d, dim);
+                    a2 = a2 + (double)cp * (double)cp;
+                    a = -2.0f * cp;
+                }
+                split_bf16(a, hb[j], lb[j]);
             }
-            v = (float)a;
-            mx = fmax(mx, a);
+            uint4 H, L;
+            H.x = hb[0] | (hb[1] << 16);
+            H.y = hb[2] | (hb[3] << 16);
+            H.z = hb[4] | (hb[5] << 16);
+            H.w = hb[6] | (hb[7] << 16);
+            L.x = lb[0] | (lb[1] << 16);
+            L.y = lb[2] | (lb[3] << 16);
+            L.z = lb[4] | (lb[5] << 16);
+            L.w = lb[6] | (lb[7] << 16);
+            const int64_t ts = t * S + s;
+            frags[R.frag_off + (ts * 2 + 0) * 64 + l] = H;
+            frags[R.frag_off + (ts * 2 + 1) * 64 + l] = L;
         }
-        cnorm[R.cn_off + c] = v;
+        a2 = a2 + __shfl_xor(a2, 16, 64);
+        a2 = a2 + __shfl_xor(a2, 32, 64);
+        if (l < 16) {
+            cnorm[R.cn_off + c] = c < k ? (float)a2 : kPadNorm;
+            if (c < k) mx = fmax(mx, a2);
+        }
     }
     mx = block_max(mx, s_red);
     if (threadIdx.x == 0 && mx > 0.0)
@@ -241,14 +243,78 @@ __device__ __forceinline__ floatx4 split_tile(const u32x4 (&ah)[S], const u32x4 
 }
 
 template <int S>
-__device__ __forceinline__ void load_center_tile(const uint4 *F, int t, int lane, u32x4 (&ah)[S],
-                                                 u32x4 (&al)[S]) {
+__device__ __forceinline__ void load_center_tile(const uint4 *F, const float *cnr, int t, int lane,
+                                                 int kk, u32x4 (&ah)[S], u32x4 (&al)[S],
+                                                 floatx4 &cn4) {
     const u32x4 *Ft = reinterpret_cast<const u32x4 *>(F) + (int64_t)t * S * 128;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         ah[s] = Ft[(s * 2 + 0) * 64 + lane];
         al[s] = Ft[(s * 2 + 1) * 64 + lane];
     }
+    cn4 = *reinterpret_cast<const floatx4 *>(cnr + t * 16 + 4 * kk);
+}
+
+// one center tile against the wavefront's four 16-point groups: every lane
+// inserts its four tagged values per group into the group's top three
+template <int S>
+__device__ __forceinline__ void track_tile(const u32x4 (&ah)[S], const u32x4 (&al)[S], floatx4 cn4,
+                                           uint32_t cbase, const u32x4 (&xh)[4][S],
+                                           const u32x4 (&xl)[4][S], const float (&xn2)[4],
+                                           float (&b1)[4], float (&b2)[4], float (&b3)[4]) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const floatx4 v = split_tile<S>(ah, al, cn4, xh[g], xl[g], xn2[g]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) top3_insert(b1[g], b2[g], b3[g], encode(v[r], cbase + r));
+    }
+}
+
+constexpr int kChunkTiles = 2;  // center tiles per staged chunk
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Copy the fragments of center tiles [t0, t0 + nt) (contiguous in memory)
+// into LDS with direct global-to-LDS loads: one 1 KiB fragment per
+// instruction and wavefront, no registers involved.
+template <int S>
+__device__ __forceinline__ void stage_chunk(const uint4 *F, int t0, int nt, uint4 *buf, int wave,
+                                            int lane) {
+    const uint4 *src = F + (int64_t)t0 * S * 128;
+    for (int f = wave; f < nt * S * 2; f += kAT / 64)
+        __builtin_amdgcn_global_load_lds((const void *)(src + f * 64 + lane), (lds_void *)(buf + f * 64), 16, 0, 0);
+}
+
+// One staged center tile against the wavefront's four 16-point groups; the
+// products are accumulated in the same order as split_tile.
+template <int S>
+__device__ __forceinline__ void track_tile_lds(const uint4 *tb, int lane, floatx4 cn4, uint32_t cbase,
+                                               const u32x4 (&xh)[4][S], const u32x4 (&xl)[4][S],
+                                               const float (&xn2)[4], float (&b1)[4], float (&b2)[4],
+                                               float (&b3)[4]) {
+    floatx4 a1[4], a2[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        a1[g] = cn4;
+        a2[g] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    const u32x4 *t4 = reinterpret_cast<const u32x4 *>(tb);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const u32x4 ah = t4[(s * 2 + 0) * 64 + lane];
+        const u32x4 al = t4[(s * 2 + 1) * 64 + lane];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            a1[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(xh[g][s]), a1[g], 0, 0, 0);
+            a2[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(xl[g][s]), a2[g], 0, 0, 0);
+            a2[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(al), as_bf(xh[g][s]), a2[g], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            top3_insert(b1[g], b2[g], b3[g], encode((a1[g][r] + a2[g][r]) + xn2[g], cbase + r));
 }
 
 enum : int32_t { ST_CERTAIN = 0, ST_TWO = 1, ST_POOL = 2, ST_FULL = 3 };
@@ -258,11 +324,11 @@ enum : int32_t { ST_CERTAIN = 0, ST_TWO = 1, ST_POOL = 2, ST_FULL = 3 };
 // stream through (fragments read straight from memory, the next tile's while
 // the current one computes).
 template <int S>
-__global__ __launch_bounds__(kAT) void k_assign_split(
+__global__ __launch_bounds__(kAT, 2) void k_assign_split(
     const float *__restrict__ P, const DevRun *__restrict__ runs, const Item *__restrict__ items,
     int item_base, const float *__restrict__ C, const uint4 *__restrict__ frags,
     const float *__restrict__ cnorm, int32_t *labels, RunState *rstate, double *objpart,
-    const uint32_t *__restrict__ boxes, int last_pass) {
+    const uint32_t *__restrict__ boxes, int last_pass, int32_t *cnt) {
     __shared__ int32_t s_c1[kAT], s_c2[kAT], s_st[kAT], s_lab[kAT];
     __shared__ float s_thr[kAT];
     __shared__ int32_t s_pool[kAT];
@@ -270,6 +336,7 @@ __global__ __launch_bounds__(kAT) void k_assign_split(
     __shared__ int32_t s_cq[kCandCap], s_cc[kCandCap];
     __shared__ double s_cd[kCandCap];
     __shared__ double s_red[kAT];
+    __shared__ uint4 s_fa[kChunkTiles * S * 128], s_fb[kChunkTiles * S * 128];
 
     const Item itm = items[item_base + blockIdx.x];
     const DevRun R = runs[itm.run];
@@ -313,22 +380,24 @@ __global__ __launch_bounds__(kAT) void k_assign_split(
 #pragma unroll
     for (int g = 0; g < 4; ++g) b1[g] = b2[g] = b3[g] = kBig;
 
-    u32x4 ah[S], al[S], nh[S], nl[S];
-    load_center_tile<S>(F, 0, lane, ah, al);
-    for (int t = 0; t < KT; ++t) {
-        if (t + 1 < KT) load_center_tile<S>(F, t + 1, lane, nh, nl);
-        const floatx4 cn4 = *reinterpret_cast<const floatx4 *>(cnr + t * 16 + 4 * kk);
-        const uint32_t cbase = (uint32_t)(t * 16 + 4 * kk);
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const floatx4 v = split_tile<S>(ah, al, cn4, xh[g], xl[g], xn2[g]);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) top3_insert(b1[g], b2[g], b3[g], encode(v[r], cbase + r));
-        }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            ah[s] = nh[s];
-            al[s] = nl[s];
+    // center fragments stream through two LDS buffers of kChunkTiles tiles:
+    // the next chunk is copied in while the current one computes
+    const int nch = (KT + kChunkTiles - 1) / kChunkTiles;
+    stage_chunk<S>(F, 0, min(kChunkTiles, KT), s_fa, wave, lane);
+    floatx4 cn4 = *reinterpret_cast<const floatx4 *>(cnr + 4 * kk);
+    for (int ch = 0; ch < nch; ++ch) {
+        uint4 *cur = (ch & 1) ? s_fb : s_fa;
+        uint4 *nxt = (ch & 1) ? s_fa : s_fb;
+        __builtin_amdgcn_s_waitcnt(0);  // this wavefront's copies of chunk ch are done
+        __syncthreads();                // everyone's; and nobody still reads nxt
+        const int t0 = ch * kChunkTiles;
+        const int nt = min(kChunkTiles, KT - t0);
+        if (ch + 1 < nch) stage_chunk<S>(F, t0 + kChunkTiles, min(kChunkTiles, KT - t0 - kChunkTiles), nxt, wave, lane);
+        for (int tt = 0; tt < nt; ++tt) {
+            const int t = t0 + tt;
+            const floatx4 cnn = t + 1 < KT ? *reinterpret_cast<const floatx4 *>(cnr + (t + 1) * 16 + 4 * kk) : cn4;
+            track_tile_lds<S>(cur + tt * S * 128, lane, cn4, (uint32_t)(t * 16 + 4 * kk), xh, xl, xn2, b1, b2, b3);
+            cn4 = cnn;
         }
     }
 
@@ -422,8 +491,8 @@ __global__ __launch_bounds__(kAT) void k_assign_split(
             const float thr = okq ? s_thr[pl] : -kBig;
             for (int t = wave; t < KT; t += kAT / 64) {
                 u32x4 ch[S], cl[S];
-                load_center_tile<S>(F, t, lane, ch, cl);
-                const floatx4 cn4 = *reinterpret_cast<const floatx4 *>(cnr + t * 16 + 4 * kk);
+                floatx4 cn4;
+                load_center_tile<S>(F, cnr, t, lane, kk, ch, cl, cn4);
                 const floatx4 v = split_tile<S>(ch, cl, cn4, yh, yl, y2);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -473,6 +542,8 @@ __global__ __launch_bounds__(kAT) void k_assign_split(
     if (valid) {
         labels[R.lab_off + i] = lab;
         if (want_obj && !have_obj) obj = dist64(xg, Cr + (int64_t)lab * d, d);
+        // an update follows: count the point for its center
+        if (!last_pass && ph == PH_ITER) atomicAdd(&cnt[R.cnt_off + lab], 1);
     }
     const unsigned long long nre = __popcll(__ballot(valid && st != ST_CERTAIN));
     if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
@@ -484,21 +555,9 @@ __global__ __launch_bounds__(kAT) void k_assign_split(
 
 // ---------------------------------------------------------------------------
 // Update of the wide runs.  cnt holds per run (at cnt_off) counts[k],
-// starts[k] and cursors[k]; order holds per run (at lab_off) the run's point
-// indices grouped by label.
-__global__ __launch_bounds__(kAT) void k_wcount(const DevRun *__restrict__ runs,
-                                               const Item *__restrict__ items, int i0,
-                                               const int32_t *__restrict__ labels,
-                                               const RunState *__restrict__ rstate, int32_t *cnt) {
-    const Item itm = items[i0 + blockIdx.x];
-    const DevRun R = runs[itm.run];
-    if (rstate[itm.run].phase != PH_ITER) return;
-    const int64_t i = itm.first + threadIdx.x;
-    if (i >= R.n) return;
-    const int32_t l = labels[R.lab_off + i];
-    if ((uint32_t)l < (uint32_t)R.k) atomicAdd(&cnt[R.cnt_off + l], 1);
-}
-
+// starts[k] and cursors[k] (the counts are added by the assignment kernels);
+// order holds per run (at lab_off) the run's point indices grouped by
+// label.
 // exclusive scan of the counts of run r0 + blockIdx.x into starts and cursors
 __global__ __launch_bounds__(kAT) void k_wscan(const DevRun *__restrict__ runs, int r0,
                                               const RunState *__restrict__ rstate, int32_t *cnt) {
@@ -535,7 +594,7 @@ __global__ __launch_bounds__(kAT) void k_wscatter(const DevRun *__restrict__ run
                                                  const Item *__restrict__ items, int i0,
                                                  const int32_t *__restrict__ labels,
                                                  const RunState *__restrict__ rstate, int32_t *cnt,
-                                                 int32_t *order) {
+                                                 int32_t *order, int64_t olab_off) {
     const Item itm = items[i0 + blockIdx.x];
     const DevRun R = runs[itm.run];
     if (rstate[itm.run].phase != PH_ITER) return;
@@ -544,17 +603,122 @@ __global__ __launch_bounds__(kAT) void k_wscatter(const DevRun *__restrict__ run
     const int32_t l = labels[R.lab_off + i];
     if ((uint32_t)l >= (uint32_t)R.k) return;
     const int32_t pos = atomicAdd(&cnt[R.cnt_off + 2 * (int64_t)R.k + l], 1);
-    if ((int64_t)pos < R.n) order[R.lab_off + pos] = (int32_t)i;
+    if ((int64_t)pos < R.n) {
+        order[R.lab_off + pos] = (int32_t)i;
+        order[olab_off + R.lab_off + pos] = l;
+    }
 }
 
-// New centers of update item (run, first center c0, kcu centers): one
-// wavefront per center; lanes split the attributes (and, for narrow points,
-// several points at once).  The run's last item to finish decides.
-__global__ __launch_bounds__(kAT) void k_wsum(const float *__restrict__ P,
+// Balanced sums for runs with d <= kWalkD.  Every wavefront walks kWalkW
+// consecutive positions of the run's label-sorted order (lanes hold
+// attributes lane and lane + 64 of one point at a time) and keeps the running
+// fixed-point sum of the current center.  A center whose points all lie in
+// the window gets its new value right away; the partial sums of a center
+// that crosses a window edge go to the run's int64 sums (exact, so the order
+// of the atomic additions does not matter) and k_wfin finishes it.
+__global__ __launch_bounds__(kAT) void k_wwalk(const float *__restrict__ P,
+                                              const DevRun *__restrict__ runs,
+                                              const Item *__restrict__ items, int w0,
+                                              const int32_t *__restrict__ order, int64_t olab_off,
+                                              float *C, RunState *rstate,
+                                              const int32_t *__restrict__ cnt, long long *gsum) {
+    constexpr int kU = 16;
+    const Item itm = items[w0 + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    RunState *rs = rstate + itm.run;
+    if (rs->phase != PH_ITER || R.d > kWalkD) return;
+    const int d = R.d;
+    const int s = fix_shift_of(rs->absmax_bits);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ja = lane, jc = lane + 64;
+    const int64_t a = (int64_t)itm.first + (int64_t)wave * kWalkW;
+    const int64_t b = min(R.n, a + kWalkW);
+    const int32_t *counts = cnt + R.cnt_off;
+    const int32_t *starts = counts + R.k;
+    const float *X = P + R.x_off;
+    const int32_t *ord = order + R.lab_off;
+    const int32_t *olab = order + olab_off + R.lab_off;
+    float *Cr = C + R.c_off;
+    long long *gs = gsum + R.sum_off;
+    double wmax = 0.0;
+    int32_t cur = -1;
+    long long A0 = 0, A1 = 0;
+    auto flush = [&]() {
+        if (cur < 0) return;
+        const int32_t st = starts[cur], n_c = counts[cur];
+        if (st >= a && (int64_t)st + n_c <= b) {
+            double dv2 = 0.0;
+            if (ja < d) {
+                const float old = Cr[(int64_t)cur * d + ja];
+                const double nv = ldexp((double)A0, -s) / (double)n_c;
+                const double dv = nv - (double)old;
+                dv2 = dv * dv;
+                Cr[(int64_t)cur * d + ja] = (float)nv;
+            }
+            if (jc < d) {
+                const float old = Cr[(int64_t)cur * d + jc];
+                const double nv = ldexp((double)A1, -s) / (double)n_c;
+                const double dv = nv - (double)old;
+                dv2 = dv2 + dv * dv;
+                Cr[(int64_t)cur * d + jc] = (float)nv;
+            }
+            for (int o = 32; o > 0; o >>= 1) dv2 = dv2 + __shfl_xor(dv2, o, 64);
+            wmax = fmax(wmax, sqrt(dv2));
+        } else {
+            if (ja < d) atomicAdd((unsigned long long *)&gs[(int64_t)cur * d + ja], (unsigned long long)A0);
+            if (jc < d) atomicAdd((unsigned long long *)&gs[(int64_t)cur * d + jc], (unsigned long long)A1);
+        }
+    };
+    for (int64_t q0 = a; q0 < b; q0 += 64) {
+        const int nb = (int)min((int64_t)64, b - q0);
+        const int32_t myp = lane < nb ? ord[q0 + lane] : 0;
+        const int32_t myl = lane < nb ? olab[q0 + lane] : -1;
+        for (int ub = 0; ub < nb; ub += kU) {
+            float v0[kU], v1[kU];
+            int32_t lu[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int qq = ub + u < 64 ? ub + u : 63;
+                const int64_t p = __shfl(myp, qq, 64);
+                lu[u] = __shfl(myl, qq, 64);
+                const bool ok = ub + u < nb;
+                v0[u] = (ok && ja < d) ? X[p * d + ja] : 0.0f;
+                v1[u] = (ok && jc < d) ? X[p * d + jc] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (ub + u < nb) {  // the same for every lane
+                    if (lu[u] != cur) {
+                        flush();
+                        cur = lu[u];
+                        A0 = 0;
+                        A1 = 0;
+                    }
+                    A0 += to_fixed(v0[u], s);
+                    A1 += to_fixed(v1[u], s);
+                }
+            }
+        }
+    }
+    flush();
+    if (lane == 0 && wmax > 0.0)
+        atomicMax(&rs->shift_bits, (unsigned long long)__double_as_longlong(wmax));
+}
+
+// New centers of update item (run, first center c0, kcu centers), one
+// wavefront per center.  For d <= kWalkD only the centers that crossed a
+// walk window are left: their sums are in gsum (zeroed again here).  For
+// wider points the wavefront sums the center's points itself: lanes split
+// the attributes, two per lane and pass (narrow points: several points side
+// by side), the point indices are read 64 at a time and broadcast, and every
+// lane keeps kU rows in flight.  The run's last item decides convergence.
+__global__ __launch_bounds__(kAT) void k_wfin(const float *__restrict__ P,
                                              const DevRun *__restrict__ runs,
                                              const Item *__restrict__ items, int u0,
                                              const int32_t *__restrict__ order, float *C,
-                                             RunState *rstate, int32_t *cnt, double tol) {
+                                             RunState *rstate, int32_t *cnt, long long *gsum,
+                                             double tol) {
+    constexpr int kU = 8;
     __shared__ double s_red[kAT];
     __shared__ uint32_t s_last;
     const Item itm = items[u0 + blockIdx.x];
@@ -580,33 +744,73 @@ __global__ __launch_bounds__(kAT) void k_wsum(const float *__restrict__ P,
     float *Cr = C + R.c_off;
     const int c1 = min(R.k, itm.first + R.kcu);
     double mx = 0.0;
+    const bool walked = d <= kWalkD;
+    long long *gs = gsum + R.sum_off;
     for (int c = itm.first + wave; c < c1; c += kAT / 64) {
         const int32_t n_c = counts[c];
         const int32_t st = starts[c];
         double mv2 = 0.0;
-        if (n_c > 0) {
-            for (int jb = 0; jb < d; jb += dg) {
-                const int j = jb + j0;
-                long long a = 0;
-                if (j < d) {
-                    int m = sub;
-                    for (; m + 3 * ppw < n_c; m += 4 * ppw) {
-                        const int32_t p0 = ord[st + m], p1 = ord[st + m + ppw];
-                        const int32_t p2 = ord[st + m + 2 * ppw], p3 = ord[st + m + 3 * ppw];
-                        const float v0 = X[(int64_t)p0 * d + j], v1 = X[(int64_t)p1 * d + j];
-                        const float v2 = X[(int64_t)p2 * d + j], v3 = X[(int64_t)p3 * d + j];
-                        a += to_fixed(v0, s) + to_fixed(v1, s) + to_fixed(v2, s) + to_fixed(v3, s);
-                    }
-                    for (; m < n_c; m += ppw) a += to_fixed(X[(int64_t)ord[st + m] * d + j], s);
-                }
-                for (int o = dg; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
+        if (walked) {
+            if (n_c > 0 && st / kWalkW != (st + n_c - 1) / kWalkW) {
                 double dv2 = 0.0;
-                if (sub == 0 && j < d) {
+                for (int j = lane; j < d; j += 64) {
+                    const long long a = gs[(int64_t)c * d + j];
+                    gs[(int64_t)c * d + j] = 0;
                     const float old = Cr[(int64_t)c * d + j];
                     const double nv = ldexp((double)a, -s) / (double)n_c;
                     const double dv = nv - (double)old;
-                    dv2 = dv * dv;
+                    dv2 = dv2 + dv * dv;
                     Cr[(int64_t)c * d + j] = (float)nv;
+                }
+                for (int o = 32; o > 0; o >>= 1) dv2 = dv2 + __shfl_xor(dv2, o, 64);
+                mv2 = dv2;
+            }
+        } else if (n_c > 0) {
+            for (int jb = 0; jb < d; jb += 2 * dg) {
+                const int ja = jb + j0, jc = jb + j0 + dg;  // this lane's two attributes
+                long long a0 = 0, a1 = 0;
+                for (int m0 = 0; m0 < n_c; m0 += 64) {
+                    const int nb = min(64, n_c - m0);
+                    const int32_t myp = lane < nb ? ord[st + m0 + lane] : 0;
+                    // the trip count is the same for every lane: the
+                    // broadcasts read lanes that are all active
+                    for (int qb = 0; qb < nb; qb += kU * ppw) {
+                        float v0[kU], v1[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int qq = qb + sub + u * ppw;
+                            const int64_t p = __shfl(myp, qq < 64 ? qq : 63, 64);
+                            const bool ok = qq < nb;
+                            v0[u] = (ok && ja < d) ? X[p * d + ja] : 0.0f;
+                            v1[u] = (ok && jc < d) ? X[p * d + jc] : 0.0f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            a0 += to_fixed(v0[u], s);
+                            a1 += to_fixed(v1[u], s);
+                        }
+                    }
+                }
+                for (int o = dg; o < 64; o <<= 1) {
+                    a0 += __shfl_xor(a0, o, 64);
+                    a1 += __shfl_xor(a1, o, 64);
+                }
+                double dv2 = 0.0;
+                if (sub == 0) {
+                    if (ja < d) {
+                        const float old = Cr[(int64_t)c * d + ja];
+                        const double nv = ldexp((double)a0, -s) / (double)n_c;
+                        const double dv = nv - (double)old;
+                        dv2 = dv * dv;
+                        Cr[(int64_t)c * d + ja] = (float)nv;
+                    }
+                    if (jc < d) {
+                        const float old = Cr[(int64_t)c * d + jc];
+                        const double nv = ldexp((double)a1, -s) / (double)n_c;
+                        const double dv = nv - (double)old;
+                        dv2 = dv2 + dv * dv;
+                        Cr[(int64_t)c * d + jc] = (float)nv;
+                    }
                 }
                 // fixed-order tree over the lanes
                 for (int o = 32; o > 0; o >>= 1) dv2 = dv2 + __shfl_xor(dv2, o, 64);
@@ -638,9 +842,9 @@ template <int S>
 subkm_status launch_split(subkm_ctx *ctx, int i0, int ni, const float *P, const DevRun *runs,
                           const Item *items, const float *C, const uint4 *frags,
                           const float *cnorm, int32_t *labels, RunState *rs, double *objpart,
-                          const uint32_t *boxes, int last_pass) {
+                          const uint32_t *boxes, int last_pass, int32_t *cnt) {
     hipLaunchKernelGGL(k_assign_split<S>, dim3(ni), dim3(kAT), 0, ctx->stream, P, runs, items, i0, C,
-                       frags, cnorm, labels, rs, objpart, boxes, last_pass);
+                       frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
@@ -652,7 +856,8 @@ subkm_status wide_split_prep(subkm_ctx *ctx, int r0, int nr, int kt_max, int ste
                              uint4 *frags, float *cnorm, RunState *rs) {
     if (nr <= 0) return SUBKM_OK;
     ProfScope ps(ctx, PK_UPDATE);
-    const int64_t work = std::max<int64_t>((int64_t)kt_max * steps_max * 64, (int64_t)kt_max * 16);
+    (void)steps_max;
+    const int64_t work = (int64_t)kt_max * 64;
     const int bx = (int)std::min<int64_t>(ceil_div(work, 256), 1024);
     hipLaunchKernelGGL(k_split_prep, dim3(bx, nr), dim3(256), 0, ctx->stream, runs, r0, C, boxes,
                        frags, cnorm, rs);
@@ -664,39 +869,40 @@ subkm_status wide_assign_split(subkm_ctx *ctx, int S, int i0, int ni, const floa
                                const DevRun *runs, const Item *items, const float *C,
                                const uint4 *frags, const float *cnorm, int32_t *labels,
                                RunState *rs, double *objpart, const uint32_t *boxes,
-                               int last_pass) {
+                               int last_pass, int32_t *cnt) {
     if (ni <= 0) return SUBKM_OK;
     ProfScope ps(ctx, PK_ASSIGN);
     switch (S) {
-        case 1: return launch_split<1>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
-        case 2: return launch_split<2>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
-        case 3: return launch_split<3>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
-        case 4: return launch_split<4>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
+        case 1: return launch_split<1>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
+        case 2: return launch_split<2>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
+        case 3: return launch_split<3>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
+        case 4: return launch_split<4>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
         default: return set_err(ctx, SUBKM_EINVAL, "split path: %d attribute steps", S);
     }
 }
 
-subkm_status wide_update(subkm_ctx *ctx, int r0, int nr, int i0, int ni, int u0, int nu,
-                         const float *P, const DevRun *runs, const Item *items,
+subkm_status wide_update(subkm_ctx *ctx, int r0, int nr, int i0, int ni, int w0, int nw, int u0,
+                         int nu, const float *P, const DevRun *runs, const Item *items,
                          const int32_t *labels, float *C, RunState *rs, int32_t *cnt,
-                         int32_t *order, double tol) {
+                         int32_t *order, int64_t olab_off, long long *gsum, double tol) {
     if (nr <= 0) return SUBKM_OK;
     ProfScope ps(ctx, PK_UPDATE);
     hipStream_t s = ctx->stream;
-    if (ni > 0) {
-        hipLaunchKernelGGL(k_wcount, dim3(ni), dim3(kAT), 0, s, runs, items, i0, labels, rs, cnt);
-        SUBKM_LAUNCHED(ctx);
-    }
     hipLaunchKernelGGL(k_wscan, dim3(nr), dim3(kAT), 0, s, runs, r0, rs, cnt);
     SUBKM_LAUNCHED(ctx);
     if (ni > 0) {
         hipLaunchKernelGGL(k_wscatter, dim3(ni), dim3(kAT), 0, s, runs, items, i0, labels, rs, cnt,
-                           order);
+                           order, olab_off);
+        SUBKM_LAUNCHED(ctx);
+    }
+    if (nw > 0) {
+        hipLaunchKernelGGL(k_wwalk, dim3(nw), dim3(kAT), 0, s, P, runs, items, w0, order, olab_off, C,
+                           rs, cnt, gsum);
         SUBKM_LAUNCHED(ctx);
     }
     if (nu > 0) {
-        hipLaunchKernelGGL(k_wsum, dim3(nu), dim3(kAT), 0, s, P, runs, items, u0, order, C, rs, cnt,
-                           tol);
+        hipLaunchKernelGGL(k_wfin, dim3(nu), dim3(kAT), 0, s, P, runs, items, u0, order, C, rs, cnt,
+                           gsum, tol);
         SUBKM_LAUNCHED(ctx);
     }
     return SUBKM_OK;
