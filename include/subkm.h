@@ -221,9 +221,74 @@ subkm_status subkm_cluster_sizes(int64_t n, int64_t N, int32_t k_local,
                                  int64_t *T, int64_t *M);
 
 /* Device memory a subkm_cluster call of these sizes needs besides its
- * inputs and outputs, in bytes (host only).  Used for admission control.  */
+ * inputs and outputs, in bytes (host only): an upper bound of the scratch
+ * the call adds to a fresh context, for either precision and form.  Used
+ * for admission control.  Returns 0 for invalid sizes.                    */
 size_t subkm_cluster_footprint(int64_t n, int32_t d, int64_t N, int32_t k_local,
                                int32_t k_final);
+
+/* Device memory the context holds as scratch right now, in bytes (host
+ * only; scratch grows to the largest call and is kept until destroy).     */
+size_t subkm_device_bytes(const subkm_ctx *ctx);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: an engine on one device takes whole clustering jobs (the method
+ * of subkm_cluster) as they arrive, admits them in arrival order when one of
+ * its `slots` is idle and the device memory the job adds keeps the engine
+ * within `budget_bytes`, and runs admitted jobs concurrently on separate
+ * streams; a job's points are copied in and its results copied out by the
+ * engine (host buffers; pinned memory lets the copies overlap other jobs).
+ * The points of a job stay resident on the device while it runs.
+ *
+ * subkm_engine_submit returns at once with a job id (SUBKM_ENOMEM when the
+ * job could never fit the budget, SUBKM_EINVAL for invalid sizes).
+ * subkm_engine_wait blocks until the job is done; subkm_engine_poll does not
+ * block.  Both release the job's record once they report it done.  Results
+ * do not depend on which other jobs run at the same time.  destroy waits for
+ * running jobs and cancels the waiting ones (status SUBKM_EBUSY).  One host
+ * thread at a time per call; the engine itself is thread safe.            */
+typedef struct subkm_engine subkm_engine;
+
+typedef struct {
+    const float *X;    /* HOST n x d input, row-major, valid until the job ends */
+    int64_t n;
+    int64_t N;         /* subcluster size                                    */
+    int32_t d;
+    int32_t k_local;
+    int32_t k_final;
+    int32_t max_iter;
+    double tol;
+    int32_t precision; /* SUBKM_PREC_*                                       */
+    int32_t reserved;
+    float *centers;    /* HOST output, k_final x d (scaled space)            */
+    int32_t *labels;   /* HOST output, n; may be NULL                        */
+} subkm_job;
+
+typedef struct {
+    int32_t status;       /* subkm_status of the job                         */
+    int32_t slot;         /* slot that ran it                                */
+    double sse;           /* objective over all points (scaled space)        */
+    double t_submit;      /* seconds on the engine's clock                   */
+    double t_admit;
+    double t_start;
+    double t_done;        /* results are in the host buffers                 */
+    size_t footprint;     /* device bytes the job needs on an empty slot     */
+    size_t device_bytes;  /* device bytes the engine held when it finished   */
+    size_t slot_bytes_admitted; /* the slot's device bytes allowed for the job */
+    size_t slot_bytes_after;    /* the slot's device bytes after the job       */
+    char message[128];    /* error text when status != SUBKM_OK              */
+} subkm_job_result;
+
+subkm_status subkm_engine_create(int device, size_t budget_bytes, int32_t slots,
+                                 subkm_engine **out);
+void subkm_engine_destroy(subkm_engine *e);
+const char *subkm_engine_last_error(const subkm_engine *e);
+size_t subkm_job_footprint(const subkm_job *job);
+subkm_status subkm_engine_submit(subkm_engine *e, const subkm_job *job, int64_t *id);
+subkm_status subkm_engine_poll(subkm_engine *e, int64_t id, int32_t *done, subkm_job_result *res);
+subkm_status subkm_engine_wait(subkm_engine *e, int64_t id, subkm_job_result *res);
+subkm_status subkm_engine_stats(subkm_engine *e, int32_t *queued, int32_t *running,
+                                size_t *device_bytes);
 
 /* ---------------------------------------------------------------------- */
 /* Per-launch kernel timing (diagnostics; not part of the method).

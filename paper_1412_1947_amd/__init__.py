@@ -58,10 +58,29 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("d", ctypes.c_int32), ("k_local", ctypes.c_int32), ("k_final", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("centers", ctypes.c_void_p), ("labels", ctypes.c_void_p)]
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("sse", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("footprint", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t),
+                ("slot_bytes_admitted", ctypes.c_size_t), ("slot_bytes_after", ctypes.c_size_t),
+                ("message", ctypes.c_char * 128)]
+
+
 EXPORTS = ("subkm_create", "subkm_destroy", "subkm_last_error", "subkm_set_stream",
            "subkm_synchronize", "subkm_scale", "subkm_subcluster", "subkm_lloyd_batched",
-           "subkm_cluster", "subkm_cluster_sizes", "subkm_cluster_footprint",
-           "subkm_profile_enable", "subkm_profile_query", "subkm_profile_name")
+           "subkm_cluster", "subkm_cluster_sizes", "subkm_cluster_footprint", "subkm_device_bytes",
+           "subkm_profile_enable", "subkm_profile_query", "subkm_profile_name",
+           "subkm_engine_create", "subkm_engine_destroy", "subkm_engine_last_error",
+           "subkm_job_footprint", "subkm_engine_submit", "subkm_engine_poll", "subkm_engine_wait",
+           "subkm_engine_stats")
 
 KERNEL_CLASSES = ("assign", "update", "keys", "cand", "scatter", "scale", "lloyd_fused",
                   "subcluster")
@@ -104,6 +123,25 @@ def lib():
             L.subkm_cluster_sizes.restype = st
             L.subkm_cluster_footprint.argtypes = [i64, i32, i64, i32, i32]
             L.subkm_cluster_footprint.restype = ctypes.c_size_t
+            L.subkm_device_bytes.argtypes = [P]
+            L.subkm_device_bytes.restype = ctypes.c_size_t
+            L.subkm_engine_create.argtypes = [ctypes.c_int, ctypes.c_size_t, i32, ctypes.POINTER(P)]
+            L.subkm_engine_create.restype = st
+            L.subkm_engine_destroy.argtypes = [P]
+            L.subkm_engine_destroy.restype = None
+            L.subkm_engine_last_error.argtypes = [P]
+            L.subkm_engine_last_error.restype = ctypes.c_char_p
+            L.subkm_job_footprint.argtypes = [ctypes.POINTER(Job)]
+            L.subkm_job_footprint.restype = ctypes.c_size_t
+            L.subkm_engine_submit.argtypes = [P, ctypes.POINTER(Job), ctypes.POINTER(i64)]
+            L.subkm_engine_submit.restype = st
+            L.subkm_engine_poll.argtypes = [P, i64, ctypes.POINTER(i32), ctypes.POINTER(JobResult)]
+            L.subkm_engine_poll.restype = st
+            L.subkm_engine_wait.argtypes = [P, i64, ctypes.POINTER(JobResult)]
+            L.subkm_engine_wait.restype = st
+            L.subkm_engine_stats.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                             ctypes.POINTER(ctypes.c_size_t)]
+            L.subkm_engine_stats.restype = st
             L.subkm_profile_enable.argtypes = [P, i32]
             L.subkm_profile_enable.restype = st
             L.subkm_profile_query.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64)]
@@ -175,6 +213,10 @@ class Context:
 
     def synchronize(self):
         self._check(lib().subkm_synchronize(self._h))
+
+    def device_bytes(self) -> int:
+        """Device memory the context holds as scratch."""
+        return int(lib().subkm_device_bytes(self._h))
 
     def profile(self, on: bool = True):
         """Start (or stop) per-launch kernel timing; resets the counters."""
@@ -293,3 +335,86 @@ def lloyd_batched(P, runs, C, labels, max_iter, tol, precision=PREC_FP32, form=F
 
 def cluster(X, N, k_local, k_final, max_iter, tol, **kw):
     return context(X.device.index or 0).cluster(X, N, k_local, k_final, max_iter, tol, **kw)
+
+
+class Engine:
+    """Serving engine on one GPU (subkm_engine_*): whole clustering jobs
+    submitted from host memory, admitted in arrival order as slots and the
+    device memory budget allow, run concurrently on separate streams.
+
+    Inputs are CPU float32 tensors [n, d] (pinned memory lets the copies
+    overlap other jobs); results come back in pinned CPU tensors."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 200 << 30, slots: int = 4):
+        h = ctypes.c_void_p()
+        st = lib().subkm_engine_create(device, int(budget_bytes), int(slots), ctypes.byref(h))
+        if st != 0:
+            raise SubkmError(st, "engine creation failed")
+        self._h = h
+        self._live = {}
+        self._lock = threading.Lock()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().subkm_engine_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, X, N: int, k_local: int, k_final: int, max_iter: int, tol: float,
+               precision: int = PREC_FP32, labels: bool = True) -> int:
+        if X.device.type != "cpu" or X.dtype != torch.float32 or X.dim() != 2:
+            raise ValueError("X must be a 2-D float32 CPU tensor")
+        X = X.contiguous()
+        n, d = X.shape
+        cen = torch.empty((k_final, d), dtype=torch.float32, pin_memory=True)
+        lab = torch.empty((n,), dtype=torch.int32, pin_memory=True) if labels else None
+        job = Job(X.data_ptr(), n, int(N), d, int(k_local), int(k_final), int(max_iter), float(tol),
+                  int(precision), 0, cen.data_ptr(), lab.data_ptr() if lab is not None else None)
+        jid = ctypes.c_int64()
+        st = lib().subkm_engine_submit(self._h, ctypes.byref(job), ctypes.byref(jid))
+        if st != 0:
+            raise SubkmError(st, lib().subkm_engine_last_error(self._h).decode())
+        with self._lock:
+            self._live[jid.value] = (X, cen, lab)
+        return jid.value
+
+    def _result(self, jid, r: JobResult):
+        with self._lock:
+            X, cen, lab = self._live.pop(jid)
+        if r.status != 0:
+            raise SubkmError(r.status, r.message.decode())
+        return {"centers": cen, "labels": lab, "sse": r.sse, "slot": r.slot,
+                "t_submit": r.t_submit, "t_admit": r.t_admit, "t_start": r.t_start,
+                "t_done": r.t_done, "footprint": r.footprint, "device_bytes": r.device_bytes,
+                "slot_bytes_admitted": r.slot_bytes_admitted, "slot_bytes_after": r.slot_bytes_after}
+
+    def wait(self, jid: int):
+        r = JobResult()
+        st = lib().subkm_engine_wait(self._h, jid, ctypes.byref(r))
+        if st != 0:
+            raise SubkmError(st, "unknown job")
+        return self._result(jid, r)
+
+    def poll(self, jid: int):
+        r = JobResult()
+        done = ctypes.c_int32()
+        st = lib().subkm_engine_poll(self._h, jid, ctypes.byref(done), ctypes.byref(r))
+        if st != 0:
+            raise SubkmError(st, "unknown job")
+        return self._result(jid, r) if done.value else None
+
+    def stats(self):
+        q, r, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        lib().subkm_engine_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b))
+        return {"queued": q.value, "running": r.value, "device_bytes": b.value}
+
+
+def job_footprint(n: int, d: int, N: int, k_local: int, k_final: int) -> int:
+    job = Job(None, n, N, d, k_local, k_final, 0, 0.0, 0, 0, None, None)
+    return int(lib().subkm_job_footprint(ctypes.byref(job)))

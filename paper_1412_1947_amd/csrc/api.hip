@@ -36,7 +36,7 @@ void *ctx_scratch(subkm_ctx *ctx, int slot, size_t bytes) {
         b.ptr = nullptr;
         b.bytes = 0;
     }
-    size_t want = bytes + bytes / 8 + 4096;
+    const size_t want = scratch_reserve(bytes);
     if (hipMalloc(&b.ptr, want) != hipSuccess) {
         hipGetLastError();
         b.ptr = nullptr;
@@ -285,18 +285,69 @@ subkm_status subkm_cluster_sizes(int64_t n, int64_t N, int32_t k_local, int64_t 
     return SUBKM_OK;
 }
 
+}  // extern "C"
+
+// Scratch requests, slot by slot, of a subkm_cluster call of these sizes on
+// a fresh context, for either precision and form (each slot keeps the
+// largest request it sees).  False for invalid sizes.
+bool cluster_requests(int64_t n, int32_t d, int64_t N, int32_t k_local, int32_t k_final,
+                      size_t *req) {
+    int64_t T = 0, M = 0;
+    if (n < 1 || n >= (1ll << 31) || d < 1 || d > 4096 || N < 1 || k_local < 1 || k_local > N ||
+        k_final < 1)
+        return false;
+    if (subkm_cluster_sizes(n, N, k_local, &T, &M) != SUBKM_OK || k_final > M) return false;
+    // the requests of subkm_cluster, slot by slot, for either precision and
+    // form (each slot keeps the largest request it has seen)
+    auto need = [&](int slot, size_t b) { req[slot] = std::max(req[slot], b); };
+    const size_t pts = (size_t)n * d;
+    need(SC_CL_S, pts * 4);
+    need(SC_CL_P, pts * 4);
+    need(SC_CL_PERM, (size_t)n * 4);
+    need(SC_CL_OFFS, (size_t)(T + 1) * 8);
+    need(SC_CL_LOCAL, (size_t)M * d * 4);
+    need(SC_CL_LLAB, (size_t)n * 4);
+    need(SC_CL_LIT, (size_t)T * 4);
+    need(SC_CL_LSSE, (size_t)T * 8);
+    need(SC_CL_MINMAX, (size_t)d * 8);
+    need(SC_CL_FINAL, (size_t)M * 4 + 128);
+    need(SC_MM_PART, minmax_scratch_bytes(n, d));
+    need(SC_MM_FLAG, 256);
+    subcluster_scratch_requests(n, d, req);
+    std::vector<subkm_run> runs((size_t)T);
+    int64_t m = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        const int64_t nr = std::min<int64_t>(N, n - t * N);
+        runs[t] = subkm_run{t * N * d, nr, m * d, t * N, d, (int32_t)ceil_div(nr * (int64_t)k_local, N)};
+        m += runs[t].k;
+    }
+    const subkm_run fr{0, M, 0, 0, d, k_final}, lr{0, n, 0, 0, d, k_final};
+    const int big = 1 << 20;  // schedule bounded by the number of tiles
+    for (int prec = 0; prec <= 1; ++prec) {
+        for (int form = 0; form <= 1; ++form)
+            lloyd_scratch_requests(runs.data(), (int32_t)T, prec, form, 1, big, req);
+        lloyd_scratch_requests(&fr, 1, prec, SUBKM_FORM_BATCHED, 1, big, req);
+        lloyd_scratch_requests(&lr, 1, prec, SUBKM_FORM_BATCHED, 0, big, req);
+    }
+    return true;
+}
+
+extern "C" {
+
+
 size_t subkm_cluster_footprint(int64_t n, int32_t d, int64_t N, int32_t k_local,
                                int32_t k_final) {
-    int64_t T = 0, M = 0;
-    if (subkm_cluster_sizes(n, N, k_local, &T, &M) != SUBKM_OK || d < 1) return 0;
-    size_t pts = (size_t)n * d * sizeof(float);
+    size_t req[SC_COUNT] = {};
+    if (!cluster_requests(n, d, N, k_local, k_final, req)) return 0;
     size_t b = 0;
-    b += 2 * pts;                                  // S and P
-    b += (size_t)n * (4 + 4 + 4 + 8 + 12 + 4);     // perm, rem x2, keys, candidates, labels
-    b += (size_t)M * d * sizeof(float) + (size_t)M * 4;  // local centers + their labels
-    b += (size_t)(T + 1) * 8 + (size_t)T * 16;
-    b += (size_t)(n / 256 + M / 256 + T + 8) * 64;      // Lloyd work items and partials
-    b += (size_t)k_final * d * 4 + (size_t)d * 64 + (1 << 20);
+    for (int q = 0; q < SC_COUNT; ++q) b += scratch_reserve(req[q]);
+    return b;
+}
+
+size_t subkm_device_bytes(const subkm_ctx *ctx) {
+    if (!ctx) return 0;
+    size_t b = 0;
+    for (int q = 0; q < SC_COUNT; ++q) b += ctx->scratch[q].bytes;
     return b;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -58,6 +59,16 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 
+// Contexts that share a device inside one serving engine run their
+// cooperative (persistent) launches one after the other: each such launch
+// waits on the GPU for the previous one, so two grids never hold parts of
+// the device while they wait for their own missing blocks.
+struct CoopGate {
+    std::mutex mu;
+    hipEvent_t ev = nullptr;
+    bool armed = false;
+};
+
 struct ScratchBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -79,6 +90,7 @@ struct subkm_ctx {
     long long prof_n[PK_COUNT] = {};
     uint64_t scratch_epoch = 0;       // bumped whenever a scratch buffer moves
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    CoopGate *coop = nullptr;          // serving engine: shared gate of cooperative launches
     struct GraphCache {
         bool valid = false;
         uint64_t key[12] = {};
@@ -139,6 +151,17 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                         float *C, int32_t *labels, int32_t max_iter, double tol,
                         int32_t precision, int32_t form, int32_t *iters, double *sse,
                         int init_mode, unsigned long long *rechecks_acc = nullptr);
+
+// Scratch bytes per slot that a call of these sizes requests (maximum into
+// req[SC_COUNT]); used for admission control.
+void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision, int32_t form,
+                            int32_t max_iter, int cu_count, size_t *req);
+void subcluster_scratch_requests(int64_t n, int32_t d, size_t *req);
+size_t minmax_scratch_bytes(int64_t n, int32_t d);
+bool cluster_requests(int64_t n, int32_t d, int64_t N, int32_t k_local, int32_t k_final,
+                      size_t *req);
+// bytes ctx_scratch reserves for a request of `bytes`
+inline size_t scratch_reserve(size_t bytes) { return bytes ? bytes + bytes / 8 + 4096 : 0; }
 
 // ---------------------------------------------------------------------------
 // Small device helpers shared by the kernels.

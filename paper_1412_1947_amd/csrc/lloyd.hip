@@ -45,7 +45,7 @@ constexpr int kCF = 4608;           // floats of centers held in LDS (fused path
 constexpr int kSumW = 4096;         // int64 center sums held in LDS (fused path)
 constexpr int kMaxK = 1024;         // centers per run in the fused path
 constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path)
-constexpr long long kSpinLimit = 1ll << 24;
+constexpr long long kSpinLimit = 1ll << 26;
 constexpr int kMaxG = 16;          // blocks per run in the batched form
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
@@ -1215,14 +1215,16 @@ void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blo
 
 }  // namespace
 
-subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, int32_t R,
-                        float *C, int32_t *labels, int32_t max_iter, double tol,
-                        int32_t precision, int32_t form, int32_t *iters, double *sse,
-                        int init_mode, unsigned long long *rechecks_acc) {
-    hipStream_t s = ctx->stream;
-    std::vector<DevRun> dr(R);
+// Per-run path and the per-run parts of the scratch layout of one call
+// (shared by the call and by the bound of its scratch).
+struct PlanSizes {
     bool all_fused = true;
     int64_t sum_words = 0, box_words = 0, cnt_words = 0, order_words = 0, frag_words = 0, cn_words = 0;
+};
+
+void plan_runs(const subkm_run *runs, int32_t R, int32_t precision, std::vector<DevRun> &dr,
+               PlanSizes &z) {
+    dr.assign(R, DevRun{});
     for (int r = 0; r < R; ++r) {
         const subkm_run &u = runs[r];
         DevRun &D = dr[r];
@@ -1237,32 +1239,62 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         const bool mf_shape = (u.d == 4 || u.d == 8 || u.d == 16 || u.d == 32 || u.d == 64 || u.d == 128);
         D.mf = (mf_shape && (int64_t)u.d * (u.k + 16) <= kCF) ? 1 : 0;
         D.fused = (kd <= kSumW && kd <= kCF && u.k <= kMaxK) ? 1 : 0;
-        all_fused = all_fused && D.fused;
-        D.box_off = box_words;
-        box_words += 2 * (int64_t)u.d;
+        z.all_fused = z.all_fused && D.fused;
+        D.box_off = z.box_words;
+        z.box_words += 2 * (int64_t)u.d;
         if (D.fused) {
-            D.sum_off = sum_words;
-            sum_words += kd + u.k;
+            D.sum_off = z.sum_words;
+            z.sum_words += kd + u.k;
         } else {
             if (u.d <= kWalkD) {
                 // sums of the centers that cross a walk window
-                D.sum_off = sum_words;
-                sum_words += kd;
+                D.sum_off = z.sum_words;
+                z.sum_words += kd;
             }
             // centers stream from memory; exact update through labels
-            D.cnt_off = cnt_words;
-            cnt_words += 3 * (int64_t)u.k;
-            order_words = std::max<int64_t>(order_words, u.lab_off + u.n);
+            D.cnt_off = z.cnt_words;
+            z.cnt_words += 3 * (int64_t)u.k;
+            z.order_words = std::max<int64_t>(z.order_words, u.lab_off + u.n);
             D.split = (precision == SUBKM_PREC_BF16 && u.d >= 32 && u.d <= 128 && u.k <= 1024) ? 1 : 0;
             if (D.split) {
                 const int64_t kt = ceil_div(u.k, 16), st = ceil_div(u.d, 32);
-                D.frag_off = frag_words;
-                frag_words += kt * st * 128;
-                D.cn_off = cn_words;
-                cn_words += kt * 16;
+                D.frag_off = z.frag_words;
+                z.frag_words += kt * st * 128;
+                D.cn_off = z.cn_words;
+                z.cn_words += kt * 16;
             }
         }
     }
+}
+
+// bytes requested per scratch slot by the call's plan
+void plan_requests(int32_t R, int64_t n_items, int64_t n_tasks, int64_t n_toff, int64_t n_obj,
+                   int64_t part_words, const PlanSizes &z, size_t *req) {
+    auto need = [&](int slot, size_t b) { req[slot] = std::max(req[slot], b); };
+    need(SC_RUNS, sizeof(DevRun) * R + sizeof(Item) * n_items + sizeof(Task) * n_tasks +
+                      sizeof(int32_t) * n_toff + 64);
+    need(SC_RSTATE, sizeof(RunState) * R + 64);
+    need(SC_SSEPART, sizeof(double) * (n_obj + 1));
+    need(SC_FIXSCALE, sizeof(long long) * (z.sum_words + part_words + 1));
+    need(SC_RECHECK, 128);
+    need(SC_BOX, sizeof(uint32_t) * (z.box_words + 1));
+    need(SC_WCNT, sizeof(int32_t) * (z.cnt_words + 2));
+    need(SC_WORDER, sizeof(int32_t) * (2 * z.order_words + 1));
+    need(SC_FRAGS, sizeof(uint4) * (z.frag_words + 1));
+    need(SC_CNORM, sizeof(float) * (z.cn_words + 16));
+}
+
+subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, int32_t R,
+                        float *C, int32_t *labels, int32_t max_iter, double tol,
+                        int32_t precision, int32_t form, int32_t *iters, double *sse,
+                        int init_mode, unsigned long long *rechecks_acc) {
+    hipStream_t s = ctx->stream;
+    std::vector<DevRun> dr;
+    PlanSizes z;
+    plan_runs(runs, R, precision, dr, z);
+    const bool all_fused = z.all_fused;
+    int64_t sum_words = z.sum_words, box_words = z.box_words, cnt_words = z.cnt_words;
+    const int64_t order_words = z.order_words, frag_words = z.frag_words, cn_words = z.cn_words;
     std::vector<std::pair<int, int>> ds;  // distinct (attribute count, matrix-core path)
     for (int r = 0; r < R; ++r) ds.push_back({dr[r].d, dr[r].mf});
     std::sort(ds.begin(), ds.end());
@@ -1302,7 +1334,8 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                 D.G = G[r];
                 D.nitems = (int32_t)((D.n + kAT - 1) / kAT);
                 D.part_off = part_words;
-                if (G[r] > 1) part_words += 2ll * G[r] * ((int64_t)D.k * D.d + D.k);
+                // exchange slots only when there is an update to exchange
+                if (G[r] > 1 && max_iter > 0) part_words += 2ll * G[r] * ((int64_t)D.k * D.d + D.k);
             }
             for (int b = 0; b < blocks; ++b) {
                 for (const Task &t : pb[b]) tasks.push_back(t);
@@ -1349,18 +1382,19 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     const size_t b_runs = sizeof(DevRun) * R, b_items = sizeof(Item) * n_items;
     const size_t b_tasks = sizeof(Task) * tasks.size(), b_toff = sizeof(int32_t) * task_off.size();
     const size_t b_plan = b_runs + b_items + b_tasks + b_toff;
-    char *d_plan = (char *)ctx_scratch(ctx, SC_RUNS, b_plan + 64);
-    RunState *d_rs = (RunState *)ctx_scratch(ctx, SC_RSTATE, sizeof(RunState) * R + 64);
-    double *d_obj = (double *)ctx_scratch(ctx, SC_SSEPART, sizeof(double) * (n_obj + 1));
-    long long *d_sum =
-        (long long *)ctx_scratch(ctx, SC_FIXSCALE, sizeof(long long) * (sum_words + part_words + 1));
-    int *d_err = (int *)ctx_scratch(ctx, SC_RECHECK, 128);
-    uint32_t *d_box = (uint32_t *)ctx_scratch(ctx, SC_BOX, sizeof(uint32_t) * (box_words + 1));
-    int32_t *d_cnt = (int32_t *)ctx_scratch(ctx, SC_WCNT, sizeof(int32_t) * (cnt_words + 2));
+    size_t req[SC_COUNT] = {};
+    plan_requests(R, n_items, (int64_t)tasks.size(), (int64_t)task_off.size(), n_obj, part_words, z, req);
+    char *d_plan = (char *)ctx_scratch(ctx, SC_RUNS, req[SC_RUNS]);
+    RunState *d_rs = (RunState *)ctx_scratch(ctx, SC_RSTATE, req[SC_RSTATE]);
+    double *d_obj = (double *)ctx_scratch(ctx, SC_SSEPART, req[SC_SSEPART]);
+    long long *d_sum = (long long *)ctx_scratch(ctx, SC_FIXSCALE, req[SC_FIXSCALE]);
+    int *d_err = (int *)ctx_scratch(ctx, SC_RECHECK, req[SC_RECHECK]);
+    uint32_t *d_box = (uint32_t *)ctx_scratch(ctx, SC_BOX, req[SC_BOX]);
+    int32_t *d_cnt = (int32_t *)ctx_scratch(ctx, SC_WCNT, req[SC_WCNT]);
     // point indices grouped by label, then their labels
-    int32_t *d_order = (int32_t *)ctx_scratch(ctx, SC_WORDER, sizeof(int32_t) * (2 * order_words + 1));
-    uint4 *d_frags = (uint4 *)ctx_scratch(ctx, SC_FRAGS, sizeof(uint4) * (frag_words + 1));
-    float *d_cn = (float *)ctx_scratch(ctx, SC_CNORM, sizeof(float) * (cn_words + 16));
+    int32_t *d_order = (int32_t *)ctx_scratch(ctx, SC_WORDER, req[SC_WORDER]);
+    uint4 *d_frags = (uint4 *)ctx_scratch(ctx, SC_FRAGS, req[SC_FRAGS]);
+    float *d_cn = (float *)ctx_scratch(ctx, SC_CNORM, req[SC_CNORM]);
     if (!d_plan || !d_rs || !d_obj || !d_sum || !d_err || !d_box || !d_cnt || !d_order || !d_frags || !d_cn)
         return SUBKM_ENOMEM;
     char *h = (char *)ctx_pinned(ctx, b_plan + 64);
@@ -1455,9 +1489,18 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     };
 
     if (batched) {
+        std::unique_lock<std::mutex> gate;
+        if (ctx->coop) {
+            gate = std::unique_lock<std::mutex>(ctx->coop->mu);
+            if (ctx->coop->armed) SUBKM_HIP(ctx, hipStreamWaitEvent(s, ctx->coop->ev, 0));
+        }
         for (const Group &g : groups)
             SUBKM_TRY(persist_d(ctx, g.d, g.mf != 0, g.blocks, P, d_runs, d_tasks, d_toff + g.block0,
                                 C, labels, d_rs, parts, d_obj, d_box, max_iter, tol, d_err));
+        if (ctx->coop) {
+            SUBKM_HIP(ctx, hipEventRecord(ctx->coop->ev, s));
+            ctx->coop->armed = true;
+        }
     } else if (form == SUBKM_FORM_PLAIN) {
         // one run at a time, one launch per phase
         for (int r = 0; r < R; ++r) {
@@ -1497,4 +1540,44 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         if (*hflag) return set_err(ctx, SUBKM_EDEVICE, "persistent Lloyd barrier timed out");
     }
     return SUBKM_OK;
+}
+
+// Upper bound of the scratch one lloyd_impl call requests per slot (for
+// admission control): the same per-run plan; the batched schedule, which
+// depends on the device, is bounded by its largest possible size.
+void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision, int32_t form,
+                            int32_t max_iter, int cu_count, size_t *req) {
+    std::vector<DevRun> dr;
+    PlanSizes z;
+    plan_runs(runs, R, precision, dr, z);
+    int64_t tiles = 0, n_items = 0, n_tasks = 0, n_toff = 0, part_words = 0;
+    for (int r = 0; r < R; ++r) tiles += ceil_div(dr[r].n, kAT);
+    if (form == SUBKM_FORM_BATCHED && z.all_fused) {
+        std::vector<std::pair<int, int>> ds;
+        for (int r = 0; r < R; ++r) ds.push_back({dr[r].d, dr[r].mf});
+        std::sort(ds.begin(), ds.end());
+        ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
+        n_toff = 1;
+        for (auto dm : ds) {
+            int64_t gt = 0;
+            for (int r = 0; r < R; ++r)
+                if (dr[r].d == dm.first && dr[r].mf == dm.second) gt += ceil_div(dr[r].n, kAT);
+            const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)cu_count * 32, gt));
+            n_toff += blocks;
+        }
+        for (int r = 0; r < R; ++r) {
+            const int64_t t = ceil_div(dr[r].n, kAT);
+            const int64_t g = max_iter > 0 ? std::min<int64_t>(kMaxG, std::max<int64_t>(1, t / 2)) : t;
+            n_tasks += g;
+            if (max_iter > 0 && g > 1) part_words += 2 * g * ((int64_t)dr[r].k * dr[r].d + dr[r].k);
+        }
+    } else {
+        n_items = tiles;
+        for (int r = 0; r < R; ++r)
+            if (!dr[r].fused) {
+                n_items += ceil_div(dr[r].k, kWideCenters);
+                if (dr[r].d <= kWalkD) n_items += ceil_div(dr[r].n, kWalkB);
+            }
+    }
+    plan_requests(R, n_items, n_tasks, n_toff, tiles, part_words, z, req);
 }

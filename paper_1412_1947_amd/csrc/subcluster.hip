@@ -619,18 +619,33 @@ struct SubBufs {
 };
 
 // Scratch of one subclustering call (allocated before any capture).
-subkm_status sub_alloc(subkm_ctx *ctx, int64_t n, int32_t d, SubBufs &b) {
+void sub_requests(int64_t n, int32_t d, size_t *req) {
+    auto need = [&](int slot, size_t b) { req[slot] = std::max(req[slot], b); };
     const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
-    b.keys = (double *)ctx_scratch(ctx, SC_KEYS, sizeof(double) * n);
-    b.rem0 = (int32_t *)ctx_scratch(ctx, SC_REM0, sizeof(int32_t) * n);
-    b.rem1 = (int32_t *)ctx_scratch(ctx, SC_REM1, sizeof(int32_t) * n);
-    b.cand = (char *)ctx_scratch(ctx, SC_CAND, (sizeof(double) + sizeof(uint32_t)) * n + 64);
     const size_t sel_words = 2 * (size_t)kRep * kBins + 3 * (size_t)nb_max + 64;
-    b.sel = (char *)ctx_scratch(ctx, SC_SEL, 256 + sizeof(uint32_t) * sel_words);
-    b.land = (float *)ctx_scratch(ctx, SC_LAND, sizeof(float) * ((size_t)d * (nb_max + 1) + 64));
-    b.colmax = (float *)ctx_scratch(ctx, SC_COLMAX, sizeof(float) * d + 64);
-    b.flag = (int *)ctx_scratch(ctx, SC_MM_FLAG, 256);
-    void *mm = ctx_scratch(ctx, SC_MM_PART, minmax_scratch_bytes(n, d));
+    need(SC_KEYS, sizeof(double) * n);
+    need(SC_REM0, sizeof(int32_t) * n);
+    need(SC_REM1, sizeof(int32_t) * n);
+    need(SC_CAND, (sizeof(double) + sizeof(uint32_t)) * n + 64);
+    need(SC_SEL, 256 + sizeof(uint32_t) * sel_words);
+    need(SC_LAND, sizeof(float) * ((size_t)d * (nb_max + 1) + 64));
+    need(SC_COLMAX, sizeof(float) * d + 64);
+    need(SC_MM_FLAG, 256);
+    need(SC_MM_PART, minmax_scratch_bytes(n, d));
+}
+
+subkm_status sub_alloc(subkm_ctx *ctx, int64_t n, int32_t d, SubBufs &b) {
+    size_t req[SC_COUNT] = {};
+    sub_requests(n, d, req);
+    b.keys = (double *)ctx_scratch(ctx, SC_KEYS, req[SC_KEYS]);
+    b.rem0 = (int32_t *)ctx_scratch(ctx, SC_REM0, req[SC_REM0]);
+    b.rem1 = (int32_t *)ctx_scratch(ctx, SC_REM1, req[SC_REM1]);
+    b.cand = (char *)ctx_scratch(ctx, SC_CAND, req[SC_CAND]);
+    b.sel = (char *)ctx_scratch(ctx, SC_SEL, req[SC_SEL]);
+    b.land = (float *)ctx_scratch(ctx, SC_LAND, req[SC_LAND]);
+    b.colmax = (float *)ctx_scratch(ctx, SC_COLMAX, req[SC_COLMAX]);
+    b.flag = (int *)ctx_scratch(ctx, SC_MM_FLAG, req[SC_MM_FLAG]);
+    void *mm = ctx_scratch(ctx, SC_MM_PART, req[SC_MM_PART]);
     if (!b.keys || !b.rem0 || !b.rem1 || !b.cand || !b.sel || !b.land || !b.colmax || !b.flag || !mm)
         return SUBKM_ENOMEM;
     return SUBKM_OK;
@@ -781,3 +796,5 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
     SUBKM_HIP(ctx, hipGraphLaunch(g.exec, ctx->stream));
     return SUBKM_OK;
 }
+
+void subcluster_scratch_requests(int64_t n, int32_t d, size_t *req) { sub_requests(n, d, req); }

@@ -75,3 +75,30 @@ def test_create_without_gpu_reports(lib):
     st = lib.subkm_create(0, None, ctypes.byref(h))
     assert st == 3  # SUBKM_EDEVICE
     assert b"device" in lib.subkm_last_error(None)
+
+
+def test_engine_without_gpu_reports(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    h = ctypes.c_void_p()
+    assert lib.subkm_engine_create(0, 1 << 30, 2, ctypes.byref(h)) == 3  # SUBKM_EDEVICE
+
+
+def test_engine_argument_checks(lib):
+    h = ctypes.c_void_p()
+    assert lib.subkm_engine_create(0, 0, 2, ctypes.byref(h)) == 1      # no budget
+    assert lib.subkm_engine_create(0, 1 << 30, 0, ctypes.byref(h)) == 1  # no slot
+    assert lib.subkm_engine_submit(None, None, None) == 1
+    assert lib.subkm_engine_wait(None, 1, None) == 1
+    lib.subkm_engine_destroy(None)  # no-op
+
+
+def test_job_footprint_covers_cluster_scratch(lib):
+    import paper_1412_1947_amd as pkg
+    for (n, d, N, kl, kf) in [(10000, 4, 8192, 256, 8), (2_000_000, 64, 8192, 256, 256),
+                              (1 << 22, 128, 32768, 1024, 256), (777, 3, 100, 7, 5)]:
+        fp = pkg.cluster_footprint(n, d, N, kl, kf)
+        jf = pkg.job_footprint(n, d, N, kl, kf)
+        assert fp > 0 and jf >= fp + n * d * 4 + n * 4 + kf * d * 4
+    assert pkg.job_footprint(10, 8, 5, 6, 1) == 0

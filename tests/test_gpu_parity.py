@@ -477,3 +477,110 @@ def test_precision_workload_full_size(km, oracle):
         diff = Sr[a:a + (1 << 19)].astype(np.float64) - fin.astype(np.float64)[labels[a:a + (1 << 19)]]
         tot += float(np.sum(np.einsum("ij,ij->i", diff, diff)))
     assert abs(host(out["sse"])[0] - tot) <= TOL * tot
+
+
+# ------------------------------------------------------------ memory and serving
+@pytest.mark.parametrize("n,d,N,kl,kf,prec", [(4096, 4, 512, 32, 8, 0), (50000, 16, 8192, 256, 64, 0),
+                                               (30000, 64, 8192, 256, 100, 0), (40000, 128, 8192, 512, 64, 1),
+                                               (20000, 32, 4096, 256, 300, 1), (9000, 7, 1000, 90, 40, 0),
+                                               (45000, 128, 8192, 256, 30, 1)])
+def test_footprint_bounds_the_scratch(n, d, N, kl, kf, prec):
+    """The footprint used for admission is an upper bound of the device memory
+    a fresh context holds after the call (and not a wild over-estimate)."""
+    import paper_1412_1947_amd as subkm
+    X, _ = synth.gaussian_blobs(n, d, 20, seed=n + d, sigma=0.6)
+    ctx = subkm.Context(0)
+    try:
+        ctx.cluster(dev(X), N, kl, kf, 8, 1e-6, precision=prec)
+        torch.cuda.synchronize()
+        used = ctx.device_bytes()
+        fp = subkm.cluster_footprint(n, d, N, kl, kf)
+        assert used <= fp, (used, fp)
+        assert used >= fp // 4, (used, fp)
+    finally:
+        ctx.close()
+
+
+def _serve_jobs():
+    rng = np.random.default_rng(9)
+    jobs = []
+    for j, (n, d, kf, prec) in enumerate([(30000, 8, 40, 0), (5000, 4, 12, 0), (120000, 16, 64, 0),
+                                          (60000, 64, 100, 0), (20000, 32, 200, 1), (45000, 128, 30, 1),
+                                          (9000, 16, 8, 0), (70000, 4, 256, 0)]):
+        X, _ = synth.gaussian_blobs(n, d, kf, seed=600 + j, sigma=0.5)
+        jobs.append((torch.from_numpy(X).pin_memory(), kf, prec))
+    return jobs
+
+
+def _run_engine(eng, jobs, together):
+    out = []
+    if together:
+        ids = [eng.submit(X, 8192, 256, kf, 30, 1e-6, precision=p) for X, kf, p in jobs]
+        out = [eng.wait(i) for i in ids]
+    else:
+        for X, kf, p in jobs:
+            out.append(eng.wait(eng.submit(X, 8192, 256, kf, 30, 1e-6, precision=p)))
+    return out
+
+
+def test_engine_alone_and_in_the_mix(km):
+    """Every job gives the same result alone, in a mix of concurrent jobs, and
+    through a direct cluster() call."""
+    import paper_1412_1947_amd as subkm
+    jobs = _serve_jobs()
+    e1 = subkm.Engine(0, budget_bytes=64 << 30, slots=1)
+    try:
+        alone = _run_engine(e1, jobs, together=False)
+    finally:
+        e1.close()
+    e4 = subkm.Engine(0, budget_bytes=64 << 30, slots=4)
+    try:
+        mix = _run_engine(e4, jobs, together=True)
+    finally:
+        e4.close()
+    # the mix really overlapped: some job started before another finished
+    spans = sorted((r["t_start"], r["t_done"]) for r in mix)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    for (X, kf, p), a, b in zip(jobs, alone, mix):
+        assert a["sse"] == b["sse"]
+        assert torch.equal(a["centers"], b["centers"]) and torch.equal(a["labels"], b["labels"])
+        ref = km.cluster(dev(X.numpy()), 8192, 256, kf, 30, 1e-6, precision=p)
+        assert host(ref["sse"])[0] == a["sse"]
+        assert np.array_equal(host(ref["centers"]), a["centers"].numpy())
+        assert np.array_equal(host(ref["labels"]), a["labels"].numpy())
+
+
+def test_engine_budget_admission():
+    """Jobs are admitted only while the engine stays within its budget: with
+    room for one job of a kind at a time, such jobs run one after the other;
+    a mix never holds more than the budget; a job larger than the budget is
+    refused at submission."""
+    import paper_1412_1947_amd as subkm
+    same = []
+    for j in range(4):
+        X, _ = synth.gaussian_blobs(40000, 16, 32, seed=700 + j, sigma=0.5)
+        same.append((torch.from_numpy(X).pin_memory(), 32, 0))
+    fp = subkm.job_footprint(40000, 16, 8192, 256, 32)
+    eng = subkm.Engine(0, budget_bytes=int(fp * 1.5), slots=4)
+    try:
+        res = _run_engine(eng, same, together=True)
+        spans = sorted((r["t_start"], r["t_done"]) for r in res)
+        for i in range(len(spans) - 1):
+            assert spans[i + 1][0] >= spans[i][1], spans
+        for r in res:
+            assert r["device_bytes"] <= fp * 1.5
+    finally:
+        eng.close()
+    jobs = _serve_jobs()
+    budget = int(max(subkm.job_footprint(X.shape[0], X.shape[1], 8192, 256, kf) for X, kf, _ in jobs) * 1.2)
+    eng = subkm.Engine(0, budget_bytes=budget, slots=4)
+    try:
+        res = _run_engine(eng, jobs, together=True)
+        for r in res:
+            assert r["slot_bytes_after"] <= r["slot_bytes_admitted"], r
+            assert r["device_bytes"] <= budget
+        big = torch.zeros((400000, 64), dtype=torch.float32)
+        with pytest.raises(subkm.SubkmError):
+            eng.submit(big, 8192, 256, 64, 30, 1e-6)
+    finally:
+        eng.close()
