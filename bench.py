@@ -45,6 +45,13 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-runs", type=int, default=24, help="oracle Lloyd runs in the CPU sample")
+    ap.add_argument("--serve-jobs", type=int, default=400, help="measured jobs of the served stream")
+    ap.add_argument("--serve-warmup", type=int, default=40, help="warm-up jobs of the served stream")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served stream")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision workload")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged workload")
+    ap.add_argument("--no-error-report", action="store_true",
+                    help="skip the oracle error report of the precision workload")
     return ap.parse_args()
 
 
@@ -68,6 +75,209 @@ def cpu_baseline(job, runs: int):
         t_total += time.perf_counter() - t0
         pi += job.N * out["iters"]
     return pi / t_total, t_total, pi
+
+
+def bench_serving(subkm, synth, a):
+    """Poisson stream at 50 jobs/s through the serving engine (4 slots, 200 GB
+    budget); latency = completion - scheduled arrival; jobs take their points
+    from per-d pools in pinned host memory (the copy to the GPU is part of the
+    latency)."""
+    import threading
+    import torch
+    n_max = 2_000_000
+    pools = {d: torch.from_numpy(X).pin_memory() for d, X in synth.serving_pool(n_max=n_max).items()}
+    reqs = synth.serving_stream(a.serve_warmup + a.serve_jobs, rate_hz=50.0)
+    eng = subkm.Engine(0, budget_bytes=200 << 30, slots=4)
+    done = {}
+    ids = []
+    lock = threading.Lock()
+
+    def collect():
+        i = 0
+        while True:
+            with lock:
+                if i >= len(reqs):
+                    return
+                have = i < len(ids)
+                jid = ids[i] if have else None
+            if not have:
+                time.sleep(0.0005)
+                continue
+            done[i] = eng.wait(jid)
+            i += 1
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    late = []
+    for r in reqs:
+        wait = t0 + r.arrival_s - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        off, n = synth.pool_slice(r, n_max)
+        X = pools[r.d][off:off + n]
+        sub = time.perf_counter()
+        jid = eng.submit(X, 8192, 256, r.k_final, 30, 1e-6)
+        late.append(max(0.0, sub - (t0 + r.arrival_s)))
+        with lock:
+            ids.append(jid)
+    th.join()
+    eng.close()
+    meas = range(a.serve_warmup, len(reqs))
+    lat = np.array([(done[i]["t_done"] - done[i]["t_submit"] + late[i]) * 1e3 for i in meas])
+    qwait = np.array([(done[i]["t_admit"] - done[i]["t_submit"]) * 1e3 for i in meas])
+    first = min(done[i]["t_submit"] - late[i] for i in meas)
+    last = max(done[i]["t_done"] for i in meas)
+    pts = sum(reqs[i].n for i in meas)
+    # concurrency: largest number of jobs running at once
+    ev = sorted([(done[i]["t_start"], 1) for i in meas] + [(done[i]["t_done"], -1) for i in meas])
+    cur = peak = 0
+    for _, e in ev:
+        cur += e
+        peak = max(peak, cur)
+    return {"jobs": len(lat), "warmup_jobs": a.serve_warmup, "rate_hz": 50.0,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+            "queue_wait_p99_ms": float(np.percentile(qwait, 99)),
+            "points_per_s": pts / (last - first), "makespan_s": last - first,
+            "peak_concurrent_jobs": peak, "slots": 4, "budget_gb": 200,
+            "peak_device_gb": max(done[i]["device_bytes"] for i in meas) / 1e9,
+            "workload": "Poisson 50 jobs/s; n log-uniform [1e4, 2e6]; d in {4,8,16,32,64}; k_final U[8,256]; "
+                        "N=8192, k_local=256, <=30 moves or shift<1e-6; points from per-d blob pools"}
+
+
+def bench_precision(subkm, synth, a):
+    """Precision workload (n = 2^22, d = 128, 256 blobs, N = 32768, 1024
+    local and 256 final centers): whole method with split-bfloat16 and with
+    float32 matrix-core distances; both give the exact labels, so the results
+    must coincide.  Roofline of the split assignment against bf16 peak."""
+    import torch
+    job = synth.precision()
+    n, d = job.X.shape
+    X = torch.from_numpy(job.X).to("cuda:0")
+    km = subkm.context(0)
+    kw = dict(N=job.N, k_local=job.k_local, k_final=job.k_final, max_iter=job.max_iter, tol=job.tol)
+    out = {}
+    for name, prec in (("bf16", subkm.PREC_BF16), ("fp32", subkm.PREC_FP32)):
+        ref = km.cluster(X, precision=prec, intermediates=True, stats=True, **kw)
+        km.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            km.cluster(X, precision=prec, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        prof = km.profile_read()
+        km.profile(False)
+        st = ref["stats"]
+        T, M = st["T"], st["M"]
+        lit = ref["local_iters"].cpu().numpy()
+        assigns = int(lit.sum()) + T
+        flops = 2.0 * d * job.k_local * job.N * assigns          # local assignments
+        flops += 2.0 * d * job.k_final * M * (st["final_iters"] + 1) + 2.0 * d * job.k_final * n
+        pi = st["local_point_iters"] + st["final_point_iters"]
+        a_launch, a_ms = prof.get("assign", (0, 0.0))
+        out[name] = {"ms_per_step": ms, "point_iters_per_s": pi / (ms * 1e-3),
+                     "sse": float(ref["sse"].cpu()[0]), "phases_us": {k: st[k] for k in (
+                         "us_scale", "us_subcluster", "us_local", "us_final", "us_label")},
+                     "rechecked_fraction": st["rechecked"] / (n * 1.0 * (assigns / T) + M * (st["final_iters"] + 1)),
+                     "assign_ms_per_step": a_ms / reps,
+                     "assign_achieved_tflops": flops / (a_ms / reps * 1e-3) / 1e12}
+        out[name]["_ref"] = ref
+    b, f = out["bf16"], out["fp32"]
+    same = (b["sse"] == f["sse"] and torch.equal(b["_ref"]["centers"], f["_ref"]["centers"])
+            and torch.equal(b["_ref"]["labels"], f["_ref"]["labels"]))
+    ach = b["assign_achieved_tflops"] * 1e12
+    res = {"workload": "n=2^22 d=128, 256 blobs (sigma 1, means N(0,25 I)); N=32768 (T=128), k_local=1024, "
+                       "k_final=256, <=30 moves or shift<1e-6",
+           "bf16_ms_per_step": b["ms_per_step"], "fp32_ms_per_step": f["ms_per_step"],
+           "speedup_bf16": f["ms_per_step"] / b["ms_per_step"],
+           "bf16_point_iters_per_s": b["point_iters_per_s"],
+           "identical_results": bool(same), "sse": b["sse"],
+           "phases_us_bf16": b["phases_us"], "phases_us_fp32": f["phases_us"],
+           "rechecked_fraction_bf16": b["rechecked_fraction"], "rechecked_fraction_fp32": f["rechecked_fraction"],
+           "assign_roofline_bf16": {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_BF16 / 1e12,
+                                    "unit": "TFLOP/s", "frac": ach / PEAK_BF16,
+                                    "note": "algorithmic 2dk flops per point-assignment; the split form "
+                                            "issues three bf16 products per algorithmic one"},
+           "assign_fp32_achieved_tflops": f["assign_achieved_tflops"]}
+    if not a.no_error_report:
+        res["error_vs_oracle"] = precision_error_report(subkm, b["_ref"], job)
+    return res
+
+
+def precision_error_report(subkm, ref, job):
+    """One Lloyd move of a sampled local run, on the GPU (split-bfloat16) and
+    in the binary64 oracle from the same float32 centers: label mismatches,
+    largest center difference, relative objective difference."""
+    import torch
+    import oracle
+    S = ref["S"]
+    perm = ref["perm"].cpu().numpy()
+    loc = ref["local_centers"].cpu().numpy()
+    t, N, k = 5, job.N, job.k_local
+    idx = perm[t * N:(t + 1) * N]
+    P = S[torch.from_numpy(idx.astype(np.int64)).to(S.device)].contiguous()
+    C0 = loc[t * k:(t + 1) * k].copy()
+    Cd = torch.from_numpy(C0).to("cuda:0")
+    lab = torch.empty(N, dtype=torch.int32, device="cuda:0")
+    it, sse = subkm.lloyd_batched(P.reshape(-1), [(0, N, 0, 0, P.shape[1], k)], Cd, lab, 1, 0.0,
+                                  precision=subkm.PREC_BF16)
+    X64 = P.cpu().numpy().astype(np.float64)
+    lab0, _, _, _ = oracle.assign(X64, C0)
+    C1, _, _ = oracle.update(X64, lab0, C0.astype(np.float64))
+    lab1, sse1, _, margin = oracle.assign(X64, Cd.cpu().numpy())
+    g_lab = lab.cpu().numpy()
+    mism = int((g_lab != lab1).sum())
+    return {"run": t, "n": N, "k": k, "d": int(P.shape[1]),
+            "max_abs_center_diff": float(np.abs(Cd.cpu().numpy() - C1).max()),
+            "max_rel_center_diff": float(np.abs(Cd.cpu().numpy() - C1).max() / max(1e-30, np.abs(C1).max())),
+            "label_mismatches": mism,
+            "rel_sse_diff": float(abs(float(sse.cpu()[0]) - sse1) / sse1),
+            "near_ties_below_1e-6": int(np.sum(np.isfinite(margin) & (margin < 1e-6)))}
+
+
+def bench_ragged(subkm, synth, a):
+    """512 independent runs, sizes log-uniform in [1k, 64k], d in {8, 32},
+    k = min(ceil(n/32), 1024), each min-max scaled on its own; all runs in
+    one batched call (<= 30 moves or shift < 1e-6)."""
+    import torch
+    rs = synth.ragged()
+    km = subkm.context(0)
+    parts, specs, cinit = [], [], []
+    x_off = c_off = l_off = 0
+    for X, k in zip(rs.X, rs.k):
+        S, _, _ = km.scale(torch.from_numpy(X).to("cuda:0"))
+        n, d = S.shape
+        parts.append(S.reshape(-1))
+        cinit.append(S[:k].reshape(-1))
+        specs.append((x_off, n, c_off, l_off, d, k))
+        x_off += n * d
+        c_off += k * d
+        l_off += n
+    P = torch.cat(parts)
+    C0 = torch.cat(cinit)
+    C = C0.clone()
+    lab = torch.empty(l_off, dtype=torch.int32, device="cuda:0")
+    it, sse = km.lloyd_batched(P, specs, C, lab, rs.max_iter, rs.tol)
+    times = []
+    for _ in range(3):
+        C.copy_(C0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, sse = km.lloyd_batched(P, specs, C, lab, rs.max_iter, rs.tol)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = float(np.median(times)) * 1e3
+    its = it.cpu().numpy()
+    pi = sum(sp[1] * int(i) for sp, i in zip(specs, its))
+    flops = sum(2.0 * sp[4] * sp[5] * sp[1] * (int(i) + 1) for sp, i in zip(specs, its))
+    return {"workload": "512 runs, n log-uniform [1024, 65536], d in {8,32}, k=min(ceil(n/32),1024), "
+                        "<=30 moves or shift<1e-6, one batched call",
+            "runs": len(specs), "points": l_off, "ms_per_call": ms, "point_iters_per_s": pi / (ms * 1e-3),
+            "achieved_tflops": flops / (ms * 1e-3) / 1e12, "frac_fp32_peak": flops / (ms * 1e-3) / PEAK_FP32,
+            "iters_mean": float(its.mean())}
 
 
 def main():
@@ -170,6 +380,10 @@ def main():
                          f"d={d}, k={job.k_local}, <= {job.max_iter} moves, tol {job.tol}); "
                          f"{pi} point-iters in {secs:.1f} s"}
 
+    serving = None if a.no_serve else bench_serving(subkm, synth, a)
+    precision = None if a.no_precision else bench_precision(subkm, synth, a)
+    ragged = None if a.no_ragged else bench_ragged(subkm, synth, a)
+
     line = {
         "metric": METRIC, "value": value, "unit": "point-iters/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step,
@@ -180,13 +394,16 @@ def main():
                    "n": n, "d": d, "N": job.N, "k_local": job.k_local, "k_final": job.k_final,
                    "max_iter": job.max_iter, "tol": job.tol, "T": T, "M": M},
         "point_iters_per_step": point_iters,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "latency_ms": ({"p50": serving["p50_ms"], "p99": serving["p99_ms"], "of": "served job stream"}
+                       if serving else None),
+        "step_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phases_us": {k: st[k] for k in ("us_scale", "us_subcluster", "us_local", "us_final", "us_label")},
         "rechecked_assignments_per_step": st["rechecked"],
         "kernels_ms_per_step": {c: v[1] / a.steps for c, v in prof.items() if v[0]},
         "roofline": roof, "roofline_other": {c: v for c, v in roofs.items() if c != dom},
         "plain": plain, "cpu_baseline": cpu,
         "sse": sse_batched,
+        "serving": serving, "precision": precision, "ragged": ragged,
     }
     print(json.dumps(line))
 

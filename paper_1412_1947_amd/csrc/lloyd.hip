@@ -33,6 +33,7 @@
 #include <cmath>
 #include <cstring>
 #include <queue>
+#include <tuple>
 #include <vector>
 
 #pragma clang fp contract(off)
@@ -1025,8 +1026,8 @@ __global__ __launch_bounds__(kAT) void k_finalize(const DevRun *__restrict__ run
     for (int q = q0; q < q1; ++q) s = s + objpart[D.item0 + q];
     const double tot = block_sum_det(s, s_red);
     if (threadIdx.x == 0) {
-        sse[r] = tot;
-        if (iters) iters[r] = rstate[r].iters;
+        sse[D.orig] = tot;
+        if (iters) iters[D.orig] = rstate[r].iters;
         if (rechecks) atomicAdd(rechecks, rstate[r].rechecks);
     }
 }
@@ -1289,9 +1290,27 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                         int32_t precision, int32_t form, int32_t *iters, double *sse,
                         int init_mode, unsigned long long *rechecks_acc) {
     hipStream_t s = ctx->stream;
+    // runs of one path are launched together: order them by path (outputs go
+    // back to the caller's order through DevRun::orig)
+    std::vector<int> ord(R);
+    for (int r = 0; r < R; ++r) ord[r] = r;
+    {
+        std::vector<DevRun> probe;
+        PlanSizes pz;
+        plan_runs(runs, R, precision, probe, pz);
+        auto key = [&](int r) {
+            const DevRun &D = probe[r];
+            return std::make_tuple(D.fused, D.split, D.d, D.mf);
+        };
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) < key(b); });
+    }
+    std::vector<subkm_run> sorted_runs(R);
+    for (int r = 0; r < R; ++r) sorted_runs[r] = runs[ord[r]];
+    runs = sorted_runs.data();
     std::vector<DevRun> dr;
     PlanSizes z;
     plan_runs(runs, R, precision, dr, z);
+    for (int r = 0; r < R; ++r) dr[r].orig = ord[r];
     const bool all_fused = z.all_fused;
     int64_t sum_words = z.sum_words, box_words = z.box_words, cnt_words = z.cnt_words;
     const int64_t order_words = z.order_words, frag_words = z.frag_words, cn_words = z.cn_words;

@@ -33,7 +33,7 @@ struct DevRun {
     int64_t frag_off;         // split-bfloat16 path: center fragments (uint4 units)
     int64_t cn_off;           // split-bfloat16 path: squared norms of the centers
     int32_t split;            // assignment with split-bfloat16 products
-    int32_t pad;
+    int32_t orig;             // index of the run in the caller's array
 };
 
 struct RunState {

@@ -177,6 +177,22 @@ def serving_points(req: ServeRequest) -> np.ndarray:
     return X
 
 
+def serving_pool(dims=(4, 8, 16, 32, 64), n_max: int = 2_000_000, blobs: int = 128,
+                 seed: int | None = None) -> dict:
+    """One point pool per attribute count for a served stream: n_max points
+    of `blobs` Gaussian blobs (means U[0,10]^d, sigma 0.5).  A job of n points
+    takes n consecutive rows at a seeded offset (see :func:`pool_slice`), so
+    a long stream needs no per-job generation."""
+    seed = default_seed("serving") if seed is None else seed
+    return {d: gaussian_blobs(n_max, d, blobs, seed + 17 * d, sigma=0.5)[0] for d in dims}
+
+
+def pool_slice(req: ServeRequest, n_max: int) -> tuple:
+    """(first row, n) of a request's points inside its pool."""
+    off = int(np.random.default_rng(req.seed).integers(0, n_max - req.n + 1))
+    return off, req.n
+
+
 def paper2d(n: int, seed: int = BASE_SEED + 100, per_cluster: int = 500) -> np.ndarray:
     """2-D blobs with ``per_cluster`` points per cluster on average."""
     k = max(1, n // per_cluster)
