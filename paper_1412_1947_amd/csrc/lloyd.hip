@@ -26,7 +26,8 @@
 //   plain    one run at a time: per iteration one assign+accumulate launch
 //            over the run's tiles and one finalize launch.
 // Runs whose k*d exceeds the LDS budget use launch-per-phase kernels for all
-// runs together (the update scans the labels per chunk of centers).
+// runs together (assignment here or in lloyd_wide.hip, exact update through
+// a label sort in lloyd_wide.hip).
 #include "lloyd_dev.h"
 
 #include <algorithm>
