@@ -173,7 +173,8 @@ void subkm_destroy(subkm_ctx *ctx) {
         if (e) hipEventDestroy(e);
     prof_resolve(ctx);
     for (auto &e : ctx->prof_free) hipEventDestroy(e);
-    if (ctx->subg.exec) hipGraphExecDestroy(ctx->subg.exec);
+    for (auto &g : ctx->subg)
+        if (g.exec) hipGraphExecDestroy(g.exec);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
@@ -401,8 +402,6 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[0], s));
     SUBKM_TRY(scale_impl(ctx, X, n, d, S, mm, mm + d, true));
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[1], s));
-    SUBKM_TRY(subcluster_impl(ctx, S, n, d, N, o.landmark_mode, P, perm, offs, nullptr));
-    if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
 
     // local runs: subcluster t holds rows t*N .. of P
     std::vector<subkm_run> runs((size_t)T);
@@ -418,6 +417,8 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
         u.k = (int32_t)ceil_div(nr * (int64_t)k_local, N);
         m += u.k;
     }
+    SUBKM_TRY(subcluster_impl(ctx, S, n, d, N, o.landmark_mode, P, perm, offs, nullptr));
+    if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
     SUBKM_TRY(lloyd_impl(ctx, P, runs.data(), (int32_t)T, loc, llab, max_iter, tol, o.precision,
                          o.form, lit, lsse, 1, nrecheck));
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[3], s));

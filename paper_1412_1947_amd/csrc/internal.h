@@ -93,9 +93,10 @@ struct subkm_ctx {
     CoopGate *coop = nullptr;          // serving engine: shared gate of cooperative launches
     struct GraphCache {
         bool valid = false;
-        uint64_t key[12] = {};
+        uint64_t key[16] = {};
         hipGraphExec_t exec = nullptr;
-    } subg;                            // captured subclustering sequence
+    };
+    std::vector<GraphCache> subg;      // captured subclustering segments
 };
 
 // RAII timer of the launches issued inside its scope (no-op when off).
@@ -143,6 +144,11 @@ subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, fl
 subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
                              int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
                              float *landmarks);
+// Rounds [t0, t1) of the subclustering (segment `seg` of the caller's split;
+// the segments must be launched in order on ctx->stream).
+subkm_status subcluster_segment(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
+                                int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
+                                float *landmarks, int64_t t0, int64_t t1, int32_t seg);
 
 // Lloyd runs.  `runs` is a host array; `init_mode` 0 = centers already in C,
 // 1 = copy the first k points of every run into C first, 2 = strided start

@@ -256,11 +256,15 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
         // rows of sC are padded to k + 16 and cn holds +inf up to the next
         // multiple of 16, so these reads stay inside the arrays; values of
         // centers past k are discarded by the selects
+        // every load is unconditional (the padding keeps it in bounds) and
+        // the padding centers are masked to zero with a bit mask, so the
+        // loads are not turned into branches with a wait each
+        const uint32_t vmask = cA < k ? 0xFFFFFFFFu : 0u;
         float ca[KQ];
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
             const float cv = L.sC[(kk + 4 * q) * ldk + cA];
-            ca[q] = cA < k ? -2.0f * (cv - mq[q]) : 0.0f;
+            ca[q] = __uint_as_float(__float_as_uint(-2.0f * (cv - mq[q])) & vmask);
         }
         const float cnv = L.cn[cA];
         const float cb = kk == 0 ? cnv : 0.0f;
@@ -842,11 +846,12 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
         Rc2 = fmaxf(Rc2, (float)s_red[0]);
         for (int t0 = 0; t0 < nc; t0 += 16) {
             const int cA = t0 + col;
+            const uint32_t vmask = cA < nc ? 0xFFFFFFFFu : 0u;
             float ca[KQ];
 #pragma unroll
             for (int q = 0; q < KQ; ++q) {
                 const float cv = sC[(kk + 4 * q) * ldc + cA];
-                ca[q] = cA < nc ? -2.0f * (cv - mq[q]) : 0.0f;
+                ca[q] = __uint_as_float(__float_as_uint(-2.0f * (cv - mq[q])) & vmask);
             }
             const float cnv = cn[cA];
             const float cb = kk == 0 ? cnv : 0.0f;

@@ -654,7 +654,7 @@ subkm_status sub_alloc(subkm_ctx *ctx, int64_t n, int32_t d, SubBufs &b) {
 // Every launch of one subclustering call, in order, on ctx->stream.
 subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64_t n, int32_t d,
                          int64_t N, int32_t landmark_mode, float *P, int32_t *perm,
-                         int64_t *offsets, float *landmarks) {
+                         int64_t *offsets, float *landmarks, int64_t t0, int64_t t1) {
     const int64_t T = ceil_div(n, N);
     hipStream_t s = ctx->stream;
     const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
@@ -671,14 +671,16 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     int32_t *rem0 = b.rem0, *rem1 = b.rem1;
     const float *colmax = b.colmax;
 
-    // histogram replicas start at zero (the select kernels re-zero them)
-    const uint32_t nzero = (uint32_t)(2 * kRep * kBins);
-    hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(nzero, 256)), dim3(256), 0, s, hist1, nzero, 0u);
-    SUBKM_LAUNCHED(ctx);
-    // first landmark: attribute-wise minimum of all points; column maxima bound the keys
-    SUBKM_TRY(minmax_impl(ctx, S, n, d, L, b.colmax, b.flag));
-    hipLaunchKernelGGL(k_offsets, dim3(ceil_div(T + 1, 256)), dim3(256), 0, s, offsets, T, N, n);
-    SUBKM_LAUNCHED(ctx);
+    if (t0 == 0) {
+        // histogram replicas start at zero (the select kernels re-zero them)
+        const uint32_t nzero = (uint32_t)(2 * kRep * kBins);
+        hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(nzero, 256)), dim3(256), 0, s, hist1, nzero, 0u);
+        SUBKM_LAUNCHED(ctx);
+        // first landmark: attribute-wise minimum of all points; column maxima bound the keys
+        SUBKM_TRY(minmax_impl(ctx, S, n, d, L, b.colmax, b.flag));
+        hipLaunchKernelGGL(k_offsets, dim3(ceil_div(T + 1, 256)), dim3(256), 0, s, offsets, T, N, n);
+        SUBKM_LAUNCHED(ctx);
+    }
 
     const bool fixed = landmark_mode == 1;
     const bool vec4 = (d % 4) == 0 && ((uintptr_t)S % 16) == 0;
@@ -687,11 +689,20 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     int32_t *nxt = rem0;
     uint32_t nrem = (uint32_t)n;
     const size_t dyn_d = sizeof(float) * d;
-    for (int64_t t = 0; t < T; ++t) {
+    for (int64_t t = 0; t < t1; ++t) {
         const uint32_t need = (uint32_t)std::min<int64_t>(N, nrem);
         const uint32_t nb = (uint32_t)ceil_div(nrem, kBS);
         const bool all = need == nrem;
         float *lm_t = landmarks ? landmarks + t * d : nullptr;
+        if (t < t0) {
+            // rounds of earlier segments: only their host-side bookkeeping
+            if (!all && !cur) cur = rem1;
+            nrem -= need;
+            int32_t *written = nxt;
+            nxt = (written == rem0) ? rem1 : rem0;
+            cur = written;
+            continue;
+        }
         if (!all) {
             if (!cur) {
                 hipLaunchKernelGGL(k_iota, dim3(ceil_div(nrem, 256)), dim3(256), 0, s, rem1, nrem);
@@ -742,21 +753,26 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
 
 }  // namespace
 
-// The whole sequence (3 + about 6 T launches) is captured once into a HIP
-// graph per (inputs, outputs, sizes, scratch buffers) and replayed, which
-// removes the launch gaps between the many short kernels.  The graph holds
-// kernel nodes only.
-subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
-                             int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
-                             float *landmarks) {
+// Rounds [t0, t1) of the sequence (3 + about 6 T launches in all) are
+// captured once into a HIP graph per (segment, inputs, outputs, sizes,
+// buffers) and replayed, which removes the launch gaps between the many short
+// kernels.  The graphs hold kernel nodes only.
+subkm_status subcluster_segment(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
+                                int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
+                                float *landmarks, int64_t t0, int64_t t1, int32_t seg) {
     SubBufs b;
     SUBKM_TRY(sub_alloc(ctx, n, d, b));
-    const uint64_t key[12] = {(uint64_t)(uintptr_t)S, (uint64_t)n, (uint64_t)d, (uint64_t)N,
+    const uint64_t key[16] = {(uint64_t)(uintptr_t)S, (uint64_t)n, (uint64_t)d, (uint64_t)N,
                               (uint64_t)landmark_mode, (uint64_t)(uintptr_t)P,
                               (uint64_t)(uintptr_t)perm, (uint64_t)(uintptr_t)offsets,
-                              (uint64_t)(uintptr_t)landmarks, ctx->scratch_epoch,
-                              (uint64_t)(uintptr_t)ctx, 0x5c1ull};
-    auto &g = ctx->subg;
+                              (uint64_t)(uintptr_t)landmarks, (uint64_t)(uintptr_t)b.keys,
+                              (uint64_t)(uintptr_t)b.rem0 ^ ((uint64_t)(uintptr_t)b.rem1 << 1),
+                              (uint64_t)(uintptr_t)b.cand ^ ((uint64_t)(uintptr_t)b.sel << 1),
+                              (uint64_t)(uintptr_t)b.land ^ ((uint64_t)(uintptr_t)b.colmax << 1),
+                              (uint64_t)(uintptr_t)b.flag ^ ((uint64_t)(uintptr_t)ctx->scratch[SC_MM_PART].ptr << 1),
+                              (uint64_t)t0, (uint64_t)t1};
+    if ((int)ctx->subg.size() <= seg) ctx->subg.resize(seg + 1);
+    auto &g = ctx->subg[seg];
     if (!(g.valid && std::memcmp(g.key, key, sizeof key) == 0)) {
         if (g.exec) {
             hipGraphExecDestroy(g.exec);
@@ -773,7 +789,7 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
         subkm_status st = SUBKM_OK;
         hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed);
         if (e == hipSuccess) {
-            st = sub_enqueue(ctx, b, S, n, d, N, landmark_mode, P, perm, offsets, landmarks);
+            st = sub_enqueue(ctx, b, S, n, d, N, landmark_mode, P, perm, offsets, landmarks, t0, t1);
             e = hipStreamEndCapture(ctx->cap_stream, &graph);
         }
         ctx->stream = user;
@@ -795,6 +811,13 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
     ProfScope ps(ctx, PK_SUBCLUSTER);
     SUBKM_HIP(ctx, hipGraphLaunch(g.exec, ctx->stream));
     return SUBKM_OK;
+}
+
+subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
+                             int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
+                             float *landmarks) {
+    return subcluster_segment(ctx, S, n, d, N, landmark_mode, P, perm, offsets, landmarks, 0,
+                              ceil_div(n, N), 0);
 }
 
 void subcluster_scratch_requests(int64_t n, int32_t d, size_t *req) { sub_requests(n, d, req); }
