@@ -1,7 +1,7 @@
 // Equal sized subclustering (Sec. II, Algorithm 1 steps 2, 3 and 5), applied
 // round after round to the points left over.
 //
-// One round is six launches with no host round trip (the threshold stays in
+// One round is five launches with no host round trip (the threshold stays in
 // device memory) and no inter-block synchronisation inside a kernel:
 //
 //   k_keys     binary64 key of every remaining point (its squared distance to
@@ -19,10 +19,10 @@
 //              counts into output offsets;
 //   k_scatter  stable compaction: a point is selected iff (key, pos) <=
 //              (key*, pos*); selected rows go to P / perm in ascending index,
-//              the others to the next remaining list, and every block writes
-//              the attribute-wise minimum of the points it keeps;
-//   k_lfin     (one block) reduces those minima to the next landmark L_{t+1}
-//              (Algorithm 1 step 2 on the points left over).
+//              the others to the next remaining list, and every block folds
+//              the attribute-wise minimum of the points it keeps into the
+//              next landmark L_{t+1} (Algorithm 1 step 2 on the points left
+//              over) with integer atomic minima on order-preserving bits.
 //
 // Positions in the remaining list are in ascending original index, so the
 // index tie-break of the selection is a tie-break on positions.
@@ -96,9 +96,10 @@ __device__ uint32_t block_scan(uint32_t v, uint32_t *tmp, uint32_t *total) {
     return wbase + x - v;
 }
 
-// Sum the kRep replicas of a kBins histogram (zeroing them for the next
+// Sum the REP replicas of a kBins histogram (zeroing them for the next
 // use) and find the bin holding the need-th element (1-based).  Every
 // thread of the kST-thread block returns the same (bin, below, count).
+template <int REP>
 __device__ void merge_find_bin(uint32_t *hist, uint32_t need, uint32_t *sh, uint32_t *tmp,
                                uint32_t *bin, uint32_t *below, uint32_t *count) {
     constexpr int per = kBins / kST;
@@ -108,7 +109,8 @@ __device__ void merge_find_bin(uint32_t *hist, uint32_t need, uint32_t *sh, uint
     for (int q = 0; q < per; ++q) {
         const int b = threadIdx.x * per + q;
         uint32_t a = 0;
-        for (int r = 0; r < kRep; ++r) {
+#pragma unroll
+        for (int r = 0; r < REP; ++r) {
             a += hist[r * kBins + b];
             hist[r * kBins + b] = 0;
         }
@@ -140,6 +142,7 @@ __device__ void merge_find_bin(uint32_t *hist, uint32_t need, uint32_t *sh, uint
 __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
                                              const int32_t *__restrict__ rem, uint32_t nrem,
                                              const float *__restrict__ L,
+                                             const uint32_t *__restrict__ Lcur, uint32_t *Lnext,
                                              const float *__restrict__ colmax,
                                              double *__restrict__ keys, uint32_t *hist1,
                                              SelState *st, float *landmarks_t, int vec4) {
@@ -147,20 +150,24 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
     __shared__ uint32_t h[kBins];
     __shared__ uint32_t s_base;
     for (int i = threadIdx.x; i < kBins; i += kT) h[i] = 0;
-    for (int j = threadIdx.x; j < d; j += kT) sL[j] = L[j];
+    for (int j = threadIdx.x; j < d; j += kT) sL[j] = Lcur ? ordered_float(Lcur[j]) : L[j];
+    __syncthreads();
     if (threadIdx.x == 0) {
         // upper bound of any key of this round: sum_j (max_j - L_j)^2
         double b = 0.0;
         for (int j = 0; j < d; ++j) {
-            double q = (double)colmax[j] - (double)L[j];
+            double q = (double)colmax[j] - (double)sL[j];
             b = b + q * q;
         }
         s_base = vbase_of(b);
         if (blockIdx.x == 0) st->base = s_base;
     }
     __syncthreads();
-    if (blockIdx.x == 0 && landmarks_t)
-        for (int j = threadIdx.x; j < d; j += kT) landmarks_t[j] = sL[j];
+    if (blockIdx.x == 0)
+        for (int j = threadIdx.x; j < d; j += kT) {
+            if (landmarks_t) landmarks_t[j] = sL[j];
+            if (Lnext) Lnext[j] = 0xFFFFFFFFu;  // the round's compaction folds the next landmark here
+        }
     const uint32_t base = s_base;
     for (uint32_t p = blockIdx.x * kT + threadIdx.x; p < nrem; p += gridDim.x * kT) {
         const float *row = S + (int64_t)rem[p] * d;
@@ -193,7 +200,7 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
 __global__ __launch_bounds__(kST) void k_sel1(uint32_t *hist1, uint32_t need, SelState *st) {
     __shared__ uint32_t sh[4], tmp[kST / 64];
     uint32_t a, below, cnt;
-    merge_find_bin(hist1, need, sh, tmp, &a, &below, &cnt);
+    merge_find_bin<kRep>(hist1, need, sh, tmp, &a, &below, &cnt);
     if (threadIdx.x == 0) {
         st->astar = a;
         st->below1 = below;
@@ -258,9 +265,9 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
             ckey[b0 + i] = s_ck[i];
             cpos[b0 + i] = s_cp[i];
         }
-        uint32_t *rep = hist2 + (blockIdx.x % kRep) * kBins;
+        // one histogram: only the candidates of one bin add to it
         for (int i = threadIdx.x; i < kBins; i += kT)
-            if (h[i]) atomicAdd(&rep[i], h[i]);
+            if (h[i]) atomicAdd(&hist2[i], h[i]);
     }
 }
 
@@ -336,7 +343,7 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
     const bool lds_counts = nb <= kSegCap;
     for (uint32_t i = threadIdx.x; i < kSegCap; i += kST) csel[i] = 0;
     uint32_t b, below2, cnt2;
-    merge_find_bin(hist2, need1, sh, tmp, &b, &below2, &cnt2);
+    merge_find_bin<1>(hist2, need1, sh, tmp, &b, &below2, &cnt2);
     const uint32_t need2 = need1 - below2;
     const uint32_t vstar = (astar << 12) | b;
     double thr_key;
@@ -485,8 +492,8 @@ __device__ void scatter_rows(const float *__restrict__ S, int d, uint32_t cnt, c
 
 // ---------------------------------------------------------------------------
 // Stable compaction of one block of kBS positions.  all_sel: every remaining
-// point is selected (last round).  track_min: write the attribute-wise
-// minimum (ordered bits) of the points that stay to Lpart[block * d + j].
+// point is selected (last round).  track_min: fold the attribute-wise
+// minimum (ordered bits) of the points that stay into Lnext.
 __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int d,
                                                 const int32_t *__restrict__ rem,
                                                 const double *__restrict__ keys, uint32_t nrem,
@@ -495,7 +502,7 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
                                                 int all_sel, int track_min, float *__restrict__ P,
                                                 int32_t *__restrict__ perm, int64_t off_t,
                                                 int32_t *__restrict__ rem_next,
-                                                uint32_t *__restrict__ Lpart, int vec4) {
+                                                uint32_t *__restrict__ Lnext, int vec4) {
     __shared__ int32_t s_src[kBS];
     __shared__ int32_t s_dst[kBS];  // >= 0: P row; < 0: -(1 + slot) in rem_next
     __shared__ uint32_t tmp[kT / 64];
@@ -558,28 +565,11 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
         else scatter_rows<1>(S, d, cnt, s_src, s_dst, track_min, P, off_t, s_cmin);
     }
     if (track_min) {
+        // the next landmark: minimum over the blocks of the points that stay
         __syncthreads();
-        for (int j = threadIdx.x; j < d; j += kT) Lpart[(int64_t)blockIdx.x * d + j] = s_cmin[j];
+        for (int j = threadIdx.x; j < d; j += kT)
+            if (s_cmin[j] != 0xFFFFFFFFu) atomicMin(&Lnext[j], s_cmin[j]);
     }
-}
-
-// next landmark: minimum over the blocks' partial minima
-__global__ __launch_bounds__(kST) void k_lfin(const uint32_t *__restrict__ Lpart, uint32_t nb,
-                                              int d, float *__restrict__ L) {
-    extern __shared__ uint32_t s_m[];  // d words
-    for (int j = threadIdx.x; j < d; j += kST) s_m[j] = 0xFFFFFFFFu;
-    __syncthreads();
-    const uint32_t total = nb * (uint32_t)d;
-    const uint32_t dj = kST % d;
-    uint32_t j = threadIdx.x % d;
-    for (uint32_t e = threadIdx.x; e < total; e += kST) {
-        const uint32_t v = Lpart[e];
-        if (v != 0xFFFFFFFFu) atomicMin(&s_m[j], v);
-        j += dj;
-        if (j >= (uint32_t)d) j -= d;
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < d; j += kST) L[j] = ordered_float(s_m[j]);
 }
 
 __global__ void k_iota(int32_t *a, uint32_t n) {
@@ -590,6 +580,11 @@ __global__ void k_iota(int32_t *a, uint32_t n) {
 __global__ void k_fill_u32(uint32_t *a, uint32_t n, uint32_t v) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = v;
+}
+
+__global__ void k_bits_to_f32(float *dst, const uint32_t *src, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = ordered_float(src[i]);
 }
 
 __global__ void k_copy_f32(float *dst, const float *src, int n) {
@@ -628,7 +623,7 @@ void sub_requests(int64_t n, int32_t d, size_t *req) {
     need(SC_REM1, sizeof(int32_t) * n);
     need(SC_CAND, (sizeof(double) + sizeof(uint32_t)) * n + 64);
     need(SC_SEL, 256 + sizeof(uint32_t) * sel_words);
-    need(SC_LAND, sizeof(float) * ((size_t)d * (nb_max + 1) + 64));
+    need(SC_LAND, sizeof(float) * (3 * (size_t)d + 64));
     need(SC_COLMAX, sizeof(float) * d + 64);
     need(SC_MM_FLAG, 256);
     need(SC_MM_PART, minmax_scratch_bytes(n, d));
@@ -665,8 +660,9 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     uint32_t *blockoff = blockcnt + nb_max;
     double *ckey = (double *)b.cand;
     uint32_t *cpos = (uint32_t *)(b.cand + sizeof(double) * n);
-    float *L = b.land;
-    uint32_t *Lpart = (uint32_t *)(b.land + d);
+    float *L = b.land;                                // first landmark (floats)
+    uint32_t *Lb[2] = {(uint32_t *)(b.land + d),       // later landmarks as ordered bits,
+                       (uint32_t *)(b.land + 2 * d)};  // round t reads Lb[t & 1]
     double *keys = b.keys;
     int32_t *rem0 = b.rem0, *rem1 = b.rem1;
     const float *colmax = b.colmax;
@@ -694,6 +690,9 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
         const uint32_t nb = (uint32_t)ceil_div(nrem, kBS);
         const bool all = need == nrem;
         float *lm_t = landmarks ? landmarks + t * d : nullptr;
+        const bool track = !all && !fixed;
+        const uint32_t *Lcur = (t == 0 || fixed) ? nullptr : Lb[t & 1];
+        uint32_t *Lnext = track ? Lb[(t + 1) & 1] : nullptr;
         if (t < t0) {
             // rounds of earlier segments: only their host-side bookkeeping
             if (!all && !cur) cur = rem1;
@@ -712,8 +711,8 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
             const int64_t grid = std::min<int64_t>(ceil_div(nrem, kT), 512);
             {
                 ProfScope pk(ctx, PK_KEYS);
-                hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kT), dyn_d, s, S, d, cur, nrem, L,
-                                   colmax, keys, hist1, st, lm_t, vec4 ? 1 : 0);
+                hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kT), dyn_d, s, S, d, cur, nrem, L, Lcur,
+                                   Lnext, colmax, keys, hist1, st, lm_t, vec4 ? 1 : 0);
                 SUBKM_LAUNCHED(ctx);
             }
             hipLaunchKernelGGL(k_sel1, dim3(1), dim3(kST), 0, s, hist1, need, st);
@@ -728,19 +727,15 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
                                blockcnt, blockoff);
             SUBKM_LAUNCHED(ctx);
         } else if (lm_t) {
-            hipLaunchKernelGGL(k_copy_f32, dim3(ceil_div(d, 256)), dim3(256), 0, s, lm_t, L, d);
+            if (Lcur) hipLaunchKernelGGL(k_bits_to_f32, dim3(ceil_div(d, 256)), dim3(256), 0, s, lm_t, Lcur, d);
+            else hipLaunchKernelGGL(k_copy_f32, dim3(ceil_div(d, 256)), dim3(256), 0, s, lm_t, L, d);
             SUBKM_LAUNCHED(ctx);
         }
-        const bool track = !all && !fixed;
         {
             ProfScope psc(ctx, PK_SCATTER);
             hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kT), dyn_d, s, S, d, cur, keys, nrem, need,
-                               st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt, Lpart,
+                               st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt, Lnext,
                                vec4p ? 1 : 0);
-            SUBKM_LAUNCHED(ctx);
-        }
-        if (track) {
-            hipLaunchKernelGGL(k_lfin, dim3(1), dim3(kST), dyn_d, s, Lpart, nb, d, L);
             SUBKM_LAUNCHED(ctx);
         }
         nrem -= need;
