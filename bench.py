@@ -52,7 +52,38 @@ def parse():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged workload")
     ap.add_argument("--no-error-report", action="store_true",
                     help="skip the oracle error report of the precision workload")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a kernel of known "
+                         "traffic for calibrating HBM counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mid_hbm_traffic.md")
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1412_1947_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated by a copy of known size), per kernel class, or {}
+    when the kernels' sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return {}
+    out = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("TRAFFIC_JSON "):
+            rec = json.loads(line[len("TRAFFIC_JSON "):])
+            for cls, r in rec.items():
+                if r.get("source_hash") == source_hash(r["sources"]):
+                    out[cls] = r["bytes_per_launch"]
+    return out
 
 
 def assign_flops(n, d, k, assigns):
@@ -291,6 +322,14 @@ def main():
     import paper_1412_1947_amd as subkm
     import synth
 
+    if a.copy_calib_mib:
+        src = torch.empty(a.copy_calib_mib << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     job = synth.mid()
     n, d = job.X.shape
     X = torch.from_numpy(job.X).to("cuda:0")
@@ -355,6 +394,9 @@ def main():
                                "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
                                "traffic": None, "launches": launches, "avg_launch_us": ms * 1e3 / launches,
                                "algorithmic_bytes_per_step": sub_bytes}
+    traffic = measured_traffic()
+    for c, r in roofs.items():
+        r["traffic"] = traffic.get(c)
     dom = max(roofs, key=lambda c: prof[c][1]) if roofs else None
     roof = roofs.get(dom)
 
