@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the served stream")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision workload")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged workload")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip direct Lloyd on all points (the paper's comparison baseline)")
     ap.add_argument("--no-error-report", action="store_true",
                     help="skip the oracle error report of the precision workload")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -106,6 +108,38 @@ def cpu_baseline(job, runs: int):
         t_total += time.perf_counter() - t0
         pi += job.N * out["iters"]
     return pi / t_total, t_total, pi
+
+
+def bench_direct(subkm, km, ref, job, two_level_ms):
+    """The paper's comparison (Sec. VI, Table II): Lloyd directly on all n
+    scaled points with k_final centers (strided start, the same rule as the
+    final run), against the two-level method on the same data: SSE ratio and
+    speedup."""
+    import torch
+    S = ref["S"]
+    n, d = S.shape
+    k = job.k_final
+    C0 = S[torch.arange(k, device=S.device) * (n // k)].contiguous()
+    C = C0.clone()
+    lab = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    spec = [(0, n, 0, 0, d, k)]
+    km.lloyd_batched(S.reshape(-1), spec, C, lab, job.max_iter, job.tol)
+    times = []
+    for _ in range(3):
+        C.copy_(C0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, sse = km.lloyd_batched(S.reshape(-1), spec, C, lab, job.max_iter, job.tol)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = float(np.median(times)) * 1e3
+    sse_d = float(sse.cpu()[0])
+    sse_t = float(ref["sse"].cpu()[0])
+    iters = int(it.cpu()[0])
+    return {"what": "Lloyd on all n points, k_final centers, strided start, same stopping rule",
+            "ms": ms, "iters": iters, "point_iters_per_s": n * iters / (ms * 1e-3), "sse": sse_d,
+            "sse_two_level": sse_t, "sse_ratio_two_level_over_direct": sse_t / sse_d,
+            "speedup_two_level": ms / two_level_ms}
 
 
 def bench_serving(subkm, synth, a):
@@ -422,6 +456,7 @@ def main():
                          f"d={d}, k={job.k_local}, <= {job.max_iter} moves, tol {job.tol}); "
                          f"{pi} point-iters in {secs:.1f} s"}
 
+    direct = None if a.no_direct else bench_direct(subkm, km, ref, job, ms_per_step)
     serving = None if a.no_serve else bench_serving(subkm, synth, a)
     precision = None if a.no_precision else bench_precision(subkm, synth, a)
     ragged = None if a.no_ragged else bench_ragged(subkm, synth, a)
@@ -445,7 +480,7 @@ def main():
         "roofline": roof, "roofline_other": {c: v for c, v in roofs.items() if c != dom},
         "plain": plain, "cpu_baseline": cpu,
         "sse": sse_batched,
-        "serving": serving, "precision": precision, "ragged": ragged,
+        "direct": direct, "serving": serving, "precision": precision, "ragged": ragged,
     }
     print(json.dumps(line))
 

@@ -51,6 +51,7 @@ constexpr long long kSpinLimit = 1ll << 26;
 constexpr int kMaxG = 16;          // blocks per run in the batched form
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
+constexpr int64_t kHugeRun = 1 << 18; // points beyond which a run with moves takes the wide path
 
 // Float32 squared distances of this thread's point against centers sC[0..nc)
 // (row-major, d per row); keeps the two smallest values and the first index
@@ -1229,8 +1230,8 @@ struct PlanSizes {
     int64_t sum_words = 0, box_words = 0, cnt_words = 0, order_words = 0, frag_words = 0, cn_words = 0;
 };
 
-void plan_runs(const subkm_run *runs, int32_t R, int32_t precision, std::vector<DevRun> &dr,
-               PlanSizes &z) {
+void plan_runs(const subkm_run *runs, int32_t R, int32_t precision, int32_t max_iter,
+               std::vector<DevRun> &dr, PlanSizes &z) {
     dr.assign(R, DevRun{});
     for (int r = 0; r < R; ++r) {
         const subkm_run &u = runs[r];
@@ -1246,6 +1247,10 @@ void plan_runs(const subkm_run *runs, int32_t R, int32_t precision, std::vector<
         const bool mf_shape = (u.d == 4 || u.d == 8 || u.d == 16 || u.d == 32 || u.d == 64 || u.d == 128);
         D.mf = (mf_shape && (int64_t)u.d * (u.k + 16) <= kCF) ? 1 : 0;
         D.fused = (kd <= kSumW && kd <= kCF && u.k <= kMaxK) ? 1 : 0;
+        // a run with moves whose tiles would overload the kMaxG blocks that
+        // can share one run's partial sums takes the wide path, whose update
+        // scales with the number of points
+        if (max_iter > 0 && u.n > kHugeRun) D.fused = 0;
         z.all_fused = z.all_fused && D.fused;
         D.box_off = z.box_words;
         z.box_words += 2 * (int64_t)u.d;
@@ -1303,7 +1308,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     {
         std::vector<DevRun> probe;
         PlanSizes pz;
-        plan_runs(runs, R, precision, probe, pz);
+        plan_runs(runs, R, precision, max_iter, probe, pz);
         auto key = [&](int r) {
             const DevRun &D = probe[r];
             return std::make_tuple(D.fused, D.split, D.d, D.mf);
@@ -1315,7 +1320,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
     runs = sorted_runs.data();
     std::vector<DevRun> dr;
     PlanSizes z;
-    plan_runs(runs, R, precision, dr, z);
+    plan_runs(runs, R, precision, max_iter, dr, z);
     for (int r = 0; r < R; ++r) dr[r].orig = ord[r];
     const bool all_fused = z.all_fused;
     int64_t sum_words = z.sum_words, box_words = z.box_words, cnt_words = z.cnt_words;
@@ -1574,7 +1579,7 @@ void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision,
                             int32_t max_iter, int cu_count, size_t *req) {
     std::vector<DevRun> dr;
     PlanSizes z;
-    plan_runs(runs, R, precision, dr, z);
+    plan_runs(runs, R, precision, max_iter, dr, z);
     int64_t tiles = 0, n_items = 0, n_tasks = 0, n_toff = 0, part_words = 0;
     for (int r = 0; r < R; ++r) tiles += ceil_div(dr[r].n, kAT);
     if (form == SUBKM_FORM_BATCHED && z.all_fused) {

@@ -584,3 +584,20 @@ def test_engine_budget_admission():
             eng.submit(big, 8192, 256, 64, 30, 1e-6)
     finally:
         eng.close()
+
+
+# ------------------------------------------------- direct Lloyd (comparison baseline)
+def test_direct_lloyd_full_size(km, oracle):
+    """Lloyd on all 2^20 points of the benchmark workload at once (the
+    paper's comparison baseline): one run far beyond the blocks that can
+    share partial sums, so it takes the wide path.  One move from the
+    strided start against the oracle; the plain form gives the same bits."""
+    job = synth.mid()
+    S, _, _ = oracle.scale(job.X)
+    n, d = S.shape
+    k = job.k_final
+    C0 = S[np.arange(k) * (n // k)]
+    shadow_steps(km, oracle, S, C0, steps=1)
+    a, ia, sa = run_batch(km, [S], [k], 3, 0.0, form=0)
+    b, ib, sb = run_batch(km, [S], [k], 3, 0.0, form=1)
+    assert np.array_equal(sa, sb) and np.array_equal(a[0][0], b[0][0])
