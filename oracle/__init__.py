@@ -2,7 +2,8 @@
 
 A plain, single-threaded FP64 reference written from the paper ("A parallel
 sampling based clustering", arXiv 1412.1947): min-max scaling, equal sized
-subclustering (Sec. II, Algorithm 1), Lloyd's algorithm inside every
+subclustering (Sec. II, Algorithm 1), unequal sized subclustering (Sec. III,
+Algorithm 2), Lloyd's algorithm inside every
 subcluster and on the local centers (Sec. I, Sec. V).  The arithmetic lives
 in ``subkm_oracle.c``; this module only compiles it with gcc and marshals
 numpy arrays.  Only the test suite, the package smoke check and the
@@ -54,8 +55,10 @@ def _load():
             lib.subkm_ref_update.restype = f64
             lib.subkm_ref_lloyd.argtypes = [P, i64, i32, i32, P, i32, f64, P, P, P, P]
             lib.subkm_ref_lloyd.restype = i32
-            lib.subkm_ref_cluster.argtypes = [P, i64, i32, i64, i32, i32, i32, f64, i32,
-                                              P, P, P, P, P, P, P, P, P, P, P, P, P]
+            lib.subkm_ref_subcluster_unequal.argtypes = [P, i64, i32, i64, P, P, P, P]
+            lib.subkm_ref_subcluster_unequal.restype = i64
+            lib.subkm_ref_cluster.argtypes = [P, i64, i32, i64, i32, i32, i32, f64, i32, i32,
+                                              i64, P, P, P, P, P, P, P, P, P, P, P, P, P]
             lib.subkm_ref_cluster.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -98,6 +101,22 @@ def subcluster(S, N: int, fixed_landmark: bool = False):
     if T < 0:
         raise ValueError("invalid arguments")
     return perm, offsets[:T + 1].copy(), lms[:T].copy()
+
+
+def subcluster_unequal(S, m: int):
+    """Algorithm 2. Returns (perm int64[n], offsets int64[m+1], landmarks f64[m,d],
+    group int32[n])."""
+    S = _f32(S)
+    n, d = S.shape
+    perm = np.empty(n, np.int64)
+    offsets = np.empty(m + 1, np.int64)
+    lms = np.empty((m, d), np.float64)
+    grp = np.empty(n, np.int32)
+    T = _load().subkm_ref_subcluster_unequal(_p(S), n, d, int(m), _p(perm), _p(offsets),
+                                             _p(lms), _p(grp))
+    if T < 0:
+        raise ValueError("invalid arguments")
+    return perm, offsets, lms, grp
 
 
 def assign(X, C):
@@ -152,11 +171,13 @@ def local_k(n_r: int, k_local: int, N: int) -> int:
 
 
 def cluster(X, N: int, k_local: int, k_final: int, max_iter: int, tol: float,
-            fixed_landmark: bool = False):
-    """The whole two-level method; returns a dict of every intermediate."""
+            fixed_landmark: bool = False, scheme: int = 0, m: int = 0):
+    """The whole two-level method; returns a dict of every intermediate.
+    scheme 0 subclusters with Algorithm 1, scheme 1 with Algorithm 2 into m
+    groups (0: ceil(n / N))."""
     X = _f32(X)
     n, d = X.shape
-    T_cap = -(-n // N)
+    T_cap = -(-n // N) if scheme == 0 or m == 0 else int(m)
     S = np.empty_like(X)
     perm = np.empty(n, np.int64)
     offsets = np.empty(T_cap + 1, np.int64)
@@ -171,7 +192,8 @@ def cluster(X, N: int, k_local: int, k_final: int, max_iter: int, tol: float,
     sse = ctypes.c_double()
     fit = ctypes.c_int32()
     rc = _load().subkm_ref_cluster(_p(X), n, d, int(N), int(k_local), int(k_final), int(max_iter),
-                                   float(tol), int(fixed_landmark), _p(S), _p(perm), _p(offsets),
+                                   float(tol), int(fixed_landmark), int(scheme), int(m),
+                                   _p(S), _p(perm), _p(offsets),
                                    ctypes.byref(T), _p(loc), _p(lk), _p(lit), _p(lsse),
                                    ctypes.byref(M), _p(C), _p(lab), ctypes.byref(sse),
                                    ctypes.byref(fit))

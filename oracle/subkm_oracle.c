@@ -28,7 +28,12 @@
  *  - an empty cluster keeps its center; Lloyd stops after max_iter updates or
  *    when the largest center move (Euclidean) is strictly below tol;
  *  - the final run clusters the concatenated local centers, unweighted, from
- *    the strided start C[q] = local[q * floor(M / k_final)].
+ *    the strided start C[q] = local[q * floor(M / k_final)];
+ *  - Algorithm 2 (Sec. III) places its m landmarks evenly on the segment from
+ *    L to H, both corner points included (p_q = L + q/(m-1) (H - L)); a point
+ *    joins the nearest landmark, the lower q on a tie; groups are kept in
+ *    landmark order with members in ascending index, and an empty group gets
+ *    no local center.
  */
 #include <math.h>
 #include <stdint.h>
@@ -158,6 +163,87 @@ int64_t subkm_ref_subcluster(const float *S, int64_t n, int32_t d, int64_t N,
     offsets[t] = off;
     free(rem); free(nxt); free(kv); free(taken); free(L);
     return t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2b Unequal sized subclustering (Sec. III, Algorithm 2).                  */
+
+/* Squared Euclidean distance of a row of S to a binary64 landmark p,
+ * attributes taken in ascending order.                                     */
+static double segment_key(const float *row, const double *p, int32_t d)
+{
+    double acc = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+        double q = (double)row[j] - p[j];
+        acc = acc + q * q;
+    }
+    return acc;
+}
+
+/* Partition the n rows of S into m groups around m landmarks placed evenly
+ * on the segment between the corner points L (attribute-wise minimum, step
+ * 2) and H (attribute-wise maximum, step 3):
+ *     p_q[j] = L[j] + (q / (m - 1)) * (H[j] - L[j]),  q = 0 .. m-1,
+ * in binary64 and in that order (q / (m - 1) first, then the product, then
+ * the sum); with m = 1 the one landmark is L.  Every point joins the
+ * landmark at the least squared distance, the lower q on a tie (step 5).
+ * Groups are emitted in landmark order, members in ascending index; a group
+ * may be empty.  perm[offsets[q] .. offsets[q+1]) lists group q.
+ * landmarks (nullable) receives p, m x d binary64; group (nullable) the
+ * group of every point.  Returns m, or -1 on error.                        */
+int64_t subkm_ref_subcluster_unequal(const float *S, int64_t n, int32_t d, int64_t m,
+                                     int64_t *perm, int64_t *offsets, double *landmarks,
+                                     int32_t *group)
+{
+    if (n < 1 || d < 1 || m < 1 || m > 0x7fffffff) return -1;
+    float *L = (float *)malloc((size_t)d * sizeof(float));
+    float *H = (float *)malloc((size_t)d * sizeof(float));
+    double *p = (double *)malloc((size_t)m * d * sizeof(double));
+    int32_t *g = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int64_t *fill = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
+    if (!L || !H || !p || !g || !fill) {
+        free(L); free(H); free(p); free(g); free(fill);
+        return -1;
+    }
+    /* steps 2 and 3: the corner points */
+    for (int32_t j = 0; j < d; ++j) {
+        float lo = S[j], hi = S[j];
+        for (int64_t i = 1; i < n; ++i) {
+            float v = S[i * d + j];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+        }
+        L[j] = lo;
+        H[j] = hi;
+    }
+    /* step 4: the landmarks along the segment from L to H */
+    for (int64_t q = 0; q < m; ++q) {
+        double t = m == 1 ? 0.0 : (double)q / (double)(m - 1);
+        for (int32_t j = 0; j < d; ++j)
+            p[q * d + j] = (double)L[j] + t * ((double)H[j] - (double)L[j]);
+    }
+    if (landmarks) memcpy(landmarks, p, (size_t)m * d * sizeof(double));
+    /* step 5: every point to its nearest landmark */
+    for (int64_t i = 0; i < n; ++i) {
+        double best = segment_key(S + i * d, p, d);
+        int32_t bq = 0;
+        for (int64_t q = 1; q < m; ++q) {
+            double k = segment_key(S + i * d, p + q * d, d);
+            if (k < best) {
+                best = k;
+                bq = (int32_t)q;
+            }
+        }
+        g[i] = bq;
+    }
+    if (group) memcpy(group, g, (size_t)n * sizeof(int32_t));
+    /* the groups in landmark order, each in ascending index */
+    for (int64_t i = 0; i < n; ++i) ++fill[g[i] + 1];
+    for (int64_t q = 0; q < m; ++q) fill[q + 1] += fill[q];
+    for (int64_t q = 0; q <= m; ++q) offsets[q] = fill[q];
+    for (int64_t i = 0; i < n; ++i) perm[fill[g[i]]++] = i;
+    free(L); free(H); free(p); free(g); free(fill);
+    return m;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -291,23 +377,30 @@ int32_t subkm_ref_lloyd(const double *X, int64_t n, int32_t d, int32_t k,
 }
 
 /* ------------------------------------------------------------------------ */
-/* O4  The whole two-level method (Sec. II Algorithm 1 and Sec. V): scale,
- *     subcluster, cluster every subcluster locally, then cluster the local
- *     centers into k_final centers; finally label all n points.
+/* O4  The whole two-level method (Sec. II Algorithm 1 or Sec. III
+ *     Algorithm 2, and Sec. V): scale, subcluster, cluster every subcluster
+ *     locally, then cluster the local centers into k_final centers; finally
+ *     label all n points.
  *
- * Output capacities: S n*d; perm n; offsets ceil(n/N)+1; local_centers and
- * the local_* arrays as many entries as the sum of the local k (at most n
- * rows); centers k_final*d; labels n.  Centers are in scaled space.        */
+ * scheme 0 subclusters with Algorithm 1 into T = ceil(n/N) subclusters of N
+ * points; scheme 1 with Algorithm 2 into T = m_groups groups (m_groups = 0
+ * takes ceil(n/N)).  In both, a subcluster of n_r points gets
+ * ceil(n_r * k_local / N) local centers, so an empty group gets none.
+ * Output capacities: S n*d; perm n; offsets T+1; local_centers at most n
+ * rows; local_k, local_iters, local_sse T; centers k_final*d; labels n.
+ * Centers are in scaled space.                                            */
 int subkm_ref_cluster(const float *X, int64_t n, int32_t d, int64_t N,
                       int32_t k_local, int32_t k_final, int32_t max_iter,
-                      double tol, int32_t fixed_landmark,
+                      double tol, int32_t fixed_landmark, int32_t scheme,
+                      int64_t m_groups,
                       float *S, int64_t *perm, int64_t *offsets, int64_t *T_out,
                       double *local_centers, int32_t *local_k,
                       int32_t *local_iters, double *local_sse, int64_t *M_out,
                       double *centers, int32_t *labels, double *sse,
                       int32_t *final_iters)
 {
-    if (n < 1 || d < 1 || N < 1 || k_local < 1 || k_local > N || k_final < 1)
+    if (n < 1 || d < 1 || N < 1 || k_local < 1 || k_local > N || k_final < 1 ||
+        (scheme != 0 && scheme != 1) || m_groups < 0)
         return REF_EINVAL;
     float *mins = (float *)malloc((size_t)d * sizeof(float));
     float *maxs = (float *)malloc((size_t)d * sizeof(float));
@@ -316,18 +409,29 @@ int subkm_ref_cluster(const float *X, int64_t n, int32_t d, int64_t N,
     free(mins); free(maxs);
     if (rc) return rc;
 
-    int64_t T = subkm_ref_subcluster(S, n, d, N, fixed_landmark, perm, offsets, NULL);
+    int64_t T;
+    if (scheme == 0)
+        T = subkm_ref_subcluster(S, n, d, N, fixed_landmark, perm, offsets, NULL);
+    else
+        T = subkm_ref_subcluster_unequal(S, n, d, m_groups ? m_groups : (n + N - 1) / N,
+                                         perm, offsets, NULL, NULL);
     if (T < 0) return REF_ENOMEM;
     *T_out = T;
 
-    double *xr = (double *)malloc((size_t)N * d * sizeof(double));
-    int32_t *lab = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    double *xr = (double *)malloc((size_t)n * d * sizeof(double));
+    int32_t *lab = (int32_t *)malloc((size_t)n * sizeof(int32_t));
     if (!xr || !lab) { free(xr); free(lab); return REF_ENOMEM; }
     int64_t M = 0;
     for (int64_t t = 0; t < T; ++t) {
         int64_t nr = offsets[t + 1] - offsets[t];
         /* local centers of this subcluster: ceil(n_r * k_local / N) */
         int32_t kr = (int32_t)((nr * (int64_t)k_local + N - 1) / N);
+        if (nr == 0) {  /* an empty group of Algorithm 2 */
+            local_k[t] = 0;
+            local_iters[t] = 0;
+            local_sse[t] = 0.0;
+            continue;
+        }
         for (int64_t r = 0; r < nr; ++r)
             for (int32_t j = 0; j < d; ++j)
                 xr[r * d + j] = (double)S[perm[offsets[t] + r] * d + j];
