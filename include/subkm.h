@@ -110,6 +110,30 @@ subkm_status subkm_subcluster(subkm_ctx *ctx, const float *S, int64_t n, int32_t
                               int32_t *perm, int64_t *offsets, float *landmarks);
 
 /* ---------------------------------------------------------------------- */
+/* Unequal sized subclustering (Sec. III, Algorithm 2).
+ *
+ *   L[j] = min_i S[i][j],  H[j] = max_i S[i][j]        (steps 2 and 3);
+ *   p_q[j] = (double)L[j] + (q / (double)(m - 1)) * ((double)H[j] - (double)L[j]),
+ *            q = 0 .. m-1, binary64 in that order; p_0 = L when m = 1
+ *            (step 4: m landmarks evenly on the segment, both ends included);
+ *   group_i = argmin_q sum_j ((double)S[i][j] - p_q[j])^2, binary64, j
+ *            ascending, no fused multiply-add, the lower q on a tie (step 5).
+ * Group q is written in ascending index to perm[offsets[q] .. offsets[q+1])
+ * and its rows to the same rows of P; a group may be empty.
+ *
+ * S: n x d input (normally the output of subkm_scale), finite values.
+ * P: n x d output, P[r] = S[perm[r]].  perm: n int32 output.  offsets: m+1
+ * int64 output (offsets[0] = 0, offsets[m] = n).  landmarks: nullable,
+ * m x d binary64 output of p_q.
+ * Requires 1 <= n < 2^31, 1 <= d <= 4096, 1 <= m <= 8192.  The result is
+ * the argmin over all m landmarks bit for bit; the search visits only the
+ * few landmarks near each point's projection on the segment and proves the
+ * rest farther with a rounding-error bound.                              */
+subkm_status subkm_subcluster_unequal(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
+                                      int64_t m, float *P, int32_t *perm, int64_t *offsets,
+                                      double *landmarks);
+
+/* ---------------------------------------------------------------------- */
 /* Many independent Lloyd runs in one call (Sec. II Algorithm 1 step 4 for
  * every subcluster; Sec. V runs every subcluster on its own block of
  * threads).
@@ -163,8 +187,10 @@ subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run
                                  int32_t *iters, double *sse);
 
 /* ---------------------------------------------------------------------- */
-/* The whole two-level method (Sec. II Algorithm 1 and Sec. V): scale X,
- * subcluster it with subclusters of N points, run Lloyd in every subcluster
+/* The whole two-level method (Sec. II Algorithm 1 or Sec. III Algorithm 2,
+ * and Sec. V): scale X, subcluster it (Algorithm 1: subclusters of N points;
+ * Algorithm 2, opts->scheme = SUBKM_SCHEME_UNEQUAL: opts->m groups, or
+ * ceil(n / N) when opts->m is 0), run Lloyd in every non-empty subcluster
  * with k_r = ceil(n_r * k_local / N) centers started from the subcluster's
  * first k_r points (the compression value of Sec. VI is N / k_local), then
  * run Lloyd on the M = sum_r k_r local centers with k_final centers started
@@ -178,18 +204,26 @@ subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run
  * in scaled space.  opts: nullable.  stats: nullable HOST output; when given
  * the call synchronises and reports phase times.
  * Requires k_local <= N and k_final <= M, besides the requirements of the
- * calls above.                                                            */
+ * calls above.  With Algorithm 2, T = m and M depends on the group sizes:
+ * M <= min(n, floor(n * k_local / N) + m) (the capacity opts->local_centers
+ * needs), and k_final > M is found, and reported as SUBKM_EINVAL, only
+ * after the groups are formed; the call then synchronises once to read the
+ * group sizes.                                                            */
+#define SUBKM_SCHEME_EQUAL 0   /* Algorithm 1 (default) */
+#define SUBKM_SCHEME_UNEQUAL 1 /* Algorithm 2 */
+
 typedef struct {
     int32_t landmark_mode; /* 0: landmark recomputed each round (default)   */
     int32_t precision;     /* SUBKM_PREC_*                                   */
     int32_t form;          /* SUBKM_FORM_* of the local runs                 */
-    int32_t reserved;
+    int32_t scheme;        /* SUBKM_SCHEME_*                                 */
     /* optional device outputs of intermediates (NULL = not wanted) */
     float *S;              /* n x d scaled points                            */
     int32_t *perm;         /* n, subcluster order                            */
     float *local_centers;  /* M x d                                          */
     int32_t *local_iters;  /* T                                              */
     double *local_sse;     /* T                                              */
+    int64_t m;             /* Algorithm 2: groups (0: ceil(n / N))           */
 } subkm_opts;
 
 typedef struct {
@@ -214,16 +248,17 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
                            const subkm_opts *opts, float *centers, int32_t *labels,
                            double *sse, subkm_stats *stats);
 
-/* Sizes of the two-level problem: T = ceil(n / N) subclusters and
- * M = sum_r ceil(n_r * k_local / N) local centers (host only, no device
- * work).  Returns SUBKM_EINVAL on invalid sizes.                          */
+/* Sizes of the two-level problem with Algorithm 1: T = ceil(n / N)
+ * subclusters and M = sum_r ceil(n_r * k_local / N) local centers (host
+ * only, no device work).  Returns SUBKM_EINVAL on invalid sizes.          */
 subkm_status subkm_cluster_sizes(int64_t n, int64_t N, int32_t k_local,
                                  int64_t *T, int64_t *M);
 
 /* Device memory a subkm_cluster call of these sizes needs besides its
  * inputs and outputs, in bytes (host only): an upper bound of the scratch
- * the call adds to a fresh context, for either precision and form.  Used
- * for admission control.  Returns 0 for invalid sizes.                    */
+ * the call adds to a fresh context, for either precision and form, with
+ * Algorithm 1 (the scheme the serving engine runs).  Used for admission
+ * control.  Returns 0 for invalid sizes.                                  */
 size_t subkm_cluster_footprint(int64_t n, int32_t d, int64_t N, int32_t k_local,
                                int32_t k_final);
 

@@ -7,8 +7,9 @@ fallback: without the built library (``__graft_entry__.build()``) or without
 a GPU every call raises.
 
 The method (arXiv 1412.1947): min-max feature scaling, equal sized
-subclustering (Sec. II, Algorithm 1), Lloyd's k-means inside every
-subcluster and on the local centers (Sec. I, Sec. V).
+subclustering (Sec. II, Algorithm 1) or unequal sized subclustering (Sec.
+III, Algorithm 2), Lloyd's k-means inside every subcluster and on the local
+centers (Sec. I, Sec. V).
 """
 from __future__ import annotations
 
@@ -25,6 +26,8 @@ PREC_FP32 = 0
 PREC_BF16 = 1
 FORM_BATCHED = 0
 FORM_PLAIN = 1
+SCHEME_EQUAL = 0    # Algorithm 1
+SCHEME_UNEQUAL = 1  # Algorithm 2
 
 
 class SubkmError(RuntimeError):
@@ -40,10 +43,10 @@ class Run(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("landmark_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("S", ctypes.c_void_p), ("perm", ctypes.c_void_p),
                 ("local_centers", ctypes.c_void_p), ("local_iters", ctypes.c_void_p),
-                ("local_sse", ctypes.c_void_p)]
+                ("local_sse", ctypes.c_void_p), ("m", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -75,7 +78,8 @@ class JobResult(ctypes.Structure):
 
 
 EXPORTS = ("subkm_create", "subkm_destroy", "subkm_last_error", "subkm_set_stream",
-           "subkm_synchronize", "subkm_scale", "subkm_subcluster", "subkm_lloyd_batched",
+           "subkm_synchronize", "subkm_scale", "subkm_subcluster", "subkm_subcluster_unequal",
+           "subkm_lloyd_batched",
            "subkm_cluster", "subkm_cluster_sizes", "subkm_cluster_footprint", "subkm_device_bytes",
            "subkm_profile_enable", "subkm_profile_query", "subkm_profile_name",
            "subkm_engine_create", "subkm_engine_destroy", "subkm_engine_last_error",
@@ -113,6 +117,8 @@ def lib():
             L.subkm_scale.restype = st
             L.subkm_subcluster.argtypes = [P, P, i64, i32, i64, i32, P, P, P, P]
             L.subkm_subcluster.restype = st
+            L.subkm_subcluster_unequal.argtypes = [P, P, i64, i32, i64, P, P, P, P]
+            L.subkm_subcluster_unequal.restype = st
             L.subkm_lloyd_batched.argtypes = [P, P, ctypes.POINTER(Run), i32, P, P, i32, f64, i32,
                                               i32, P, P]
             L.subkm_lloyd_batched.restype = st
@@ -257,6 +263,20 @@ class Context:
                                            _ptr(P), _ptr(perm), _ptr(offs), _ptr(lm)))
         return (P, perm, offs, lm) if landmarks else (P, perm, offs)
 
+    def subcluster_unequal(self, S, m: int, landmarks: bool = False):
+        """Algorithm 2 into m groups. Returns (P, perm, offsets[, landmarks])."""
+        S = self._dev(S, torch.float32, "S")
+        n, d = S.shape
+        m = int(m)
+        P = self._empty((n, d), torch.float32)
+        perm = self._empty((n,), torch.int32)
+        offs = self._empty((max(m, 0) + 1,), torch.int64)
+        lm = self._empty((max(m, 0), d), torch.float64) if landmarks else None
+        self._bind_stream()
+        self._check(lib().subkm_subcluster_unequal(self._h, _ptr(S), n, d, m, _ptr(P), _ptr(perm),
+                                                   _ptr(offs), _ptr(lm)))
+        return (P, perm, offs, lm) if landmarks else (P, perm, offs)
+
     def lloyd_batched(self, P, runs, C, labels, max_iter: int, tol: float,
                       precision: int = PREC_FP32, form: int = FORM_BATCHED):
         """Lloyd runs described by `runs` (tuples x_off, n, c_off, lab_off, d, k).
@@ -276,15 +296,23 @@ class Context:
 
     def cluster(self, X, N: int, k_local: int, k_final: int, max_iter: int, tol: float,
                 landmark_mode: int = 0, precision: int = PREC_FP32, form: int = FORM_BATCHED,
-                intermediates: bool = False, stats: bool = False):
-        """The whole two-level method.  Returns a dict with centers (scaled
-        space), labels, sse and, on request, intermediates and phase stats."""
+                intermediates: bool = False, stats: bool = False, scheme: int = SCHEME_EQUAL,
+                m: int = 0):
+        """The whole two-level method (scheme SCHEME_EQUAL: Algorithm 1;
+        SCHEME_UNEQUAL: Algorithm 2 into m groups, 0 for ceil(n / N)).  Returns
+        a dict with centers (scaled space), labels, sse and, on request,
+        intermediates and phase stats.  With Algorithm 2, local_centers holds
+        room for the largest possible M; stats["M"] rows of it are used."""
         X = self._dev(X, torch.float32, "X")
         n, d = X.shape
         out = {}
-        o = Opts(landmark_mode=int(landmark_mode), precision=int(precision), form=int(form))
+        o = Opts(landmark_mode=int(landmark_mode), precision=int(precision), form=int(form),
+                 scheme=int(scheme), m=int(m))
         if intermediates:
             T, M = cluster_sizes(n, int(N), int(k_local))
+            if scheme == SCHEME_UNEQUAL:
+                T = int(m) if m else T
+                M = min(n, n * int(k_local) // int(N) + T)
             out["S"] = self._empty((n, d), torch.float32)
             out["perm"] = self._empty((n,), torch.int32)
             out["local_centers"] = self._empty((M, d), torch.float32)
@@ -326,6 +354,10 @@ def scale(X):
 
 def subcluster(S, N, landmark_mode=0, landmarks=False):
     return context(S.device.index or 0).subcluster(S, N, landmark_mode, landmarks)
+
+
+def subcluster_unequal(S, m, landmarks=False):
+    return context(S.device.index or 0).subcluster_unequal(S, m, landmarks)
 
 
 def lloyd_batched(P, runs, C, labels, max_iter, tol, precision=PREC_FP32, form=FORM_BATCHED):

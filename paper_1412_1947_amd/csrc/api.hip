@@ -253,6 +253,19 @@ subkm_status subkm_subcluster(subkm_ctx *ctx, const float *S, int64_t n, int32_t
     return subcluster_impl(ctx, S, n, d, N, landmark_mode, P, perm, offsets, landmarks);
 }
 
+subkm_status subkm_subcluster_unequal(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
+                                      int64_t m, float *P, int32_t *perm, int64_t *offsets,
+                                      double *landmarks) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
+    REQUIRE(ctx, d >= 1 && d <= 4096, "d must be in [1, 4096]");
+    REQUIRE(ctx, m >= 1 && m <= kUqMaxGroups, "m must be in [1, %lld]", (long long)kUqMaxGroups);
+    REQUIRE(ctx, S && P && perm && offsets, "NULL array argument");
+    REQUIRE(ctx, (const void *)S != (const void *)P, "P must not alias S");
+    DeviceGuard g(ctx->device);
+    return subcluster_unequal_impl(ctx, S, n, d, m, P, perm, offsets, landmarks);
+}
+
 subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run *runs,
                                  int32_t R, float *C, int32_t *labels, int32_t max_iter,
                                  double tol, int32_t precision, int32_t form, int32_t *iters,
@@ -370,8 +383,18 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
     REQUIRE(ctx, o.precision == SUBKM_PREC_FP32 || o.precision == SUBKM_PREC_BF16,
             "unknown precision");
     REQUIRE(ctx, o.form == SUBKM_FORM_BATCHED || o.form == SUBKM_FORM_PLAIN, "unknown form");
+    REQUIRE(ctx, o.scheme == SUBKM_SCHEME_EQUAL || o.scheme == SUBKM_SCHEME_UNEQUAL,
+            "unknown scheme %d", o.scheme);
+    const bool uneq = o.scheme == SUBKM_SCHEME_UNEQUAL;
     int64_t T = 0, M = 0;
     subkm_cluster_sizes(n, N, k_local, &T, &M);
+    if (uneq) {
+        REQUIRE(ctx, o.m >= 0, "m must be >= 0");
+        T = o.m ? o.m : T;
+        REQUIRE(ctx, T <= kUqMaxGroups, "m must be in [1, %lld]", (long long)kUqMaxGroups);
+        // capacity: sum_r ceil(n_r k_local / N) <= floor(n k_local / N) + T, and <= n
+        M = std::min<int64_t>(n, n * (int64_t)k_local / N + T);
+    }
     REQUIRE(ctx, k_final >= 1 && k_final <= M, "k_final must be in [1, M=%lld]", (long long)M);
     DeviceGuard g(ctx->device);
     hipStream_t s = ctx->stream;
@@ -403,24 +426,56 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
     SUBKM_TRY(scale_impl(ctx, X, n, d, S, mm, mm + d, true));
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[1], s));
 
-    // local runs: subcluster t holds rows t*N .. of P
-    std::vector<subkm_run> runs((size_t)T);
-    int64_t m = 0;
-    for (int64_t t = 0; t < T; ++t) {
-        int64_t nr = std::min<int64_t>(N, n - t * N);
-        subkm_run &u = runs[t];
-        u.x_off = t * N * d;
+    // local runs: one per non-empty subcluster, rows offsets[t] .. of P
+    std::vector<subkm_run> runs;
+    int32_t *lit_r = lit;  // moves of run r
+    double *lsse_r = lsse;
+    int32_t *gid_d = nullptr;  // Algorithm 2: group of run r
+    auto add_run = [&](int64_t off, int64_t nr, int64_t &m) {
+        subkm_run u;
+        u.x_off = off * d;
         u.n = nr;
         u.c_off = m * d;
-        u.lab_off = t * N;
+        u.lab_off = off;
         u.d = d;
         u.k = (int32_t)ceil_div(nr * (int64_t)k_local, N);
         m += u.k;
+        runs.push_back(u);
+    };
+    if (!uneq) {
+        int64_t m = 0;
+        for (int64_t t = 0; t < T; ++t) add_run(t * N, std::min<int64_t>(N, n - t * N), m);
+        SUBKM_TRY(subcluster_impl(ctx, S, n, d, N, o.landmark_mode, P, perm, offs, nullptr));
+        if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
+    } else {
+        SUBKM_TRY(subcluster_unequal_impl(ctx, S, n, d, T, P, perm, offs, nullptr));
+        if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
+        // the group sizes decide the runs: read them back
+        std::vector<int64_t> hoff((size_t)T + 1);
+        SUBKM_HIP(ctx, hipMemcpyAsync(hoff.data(), offs, (T + 1) * sizeof(int64_t),
+                                      hipMemcpyDeviceToHost, s));
+        SUBKM_HIP(ctx, hipStreamSynchronize(s));
+        std::vector<int32_t> gid;
+        int64_t m = 0;
+        for (int64_t q = 0; q < T; ++q)
+            if (hoff[q + 1] > hoff[q]) {
+                add_run(hoff[q], hoff[q + 1] - hoff[q], m);
+                gid.push_back((int32_t)q);
+            }
+        M = m;
+        REQUIRE(ctx, k_final <= M, "k_final must be in [1, M=%lld]", (long long)M);
+        const size_t R = runs.size();
+        char *lb = (char *)ctx_scratch(ctx, SC_UQ_LOCAL, R * 16 + 256);
+        if (!lb) return SUBKM_ENOMEM;
+        lsse_r = (double *)lb;
+        lit_r = (int32_t *)(lb + R * 8);
+        gid_d = (int32_t *)(lb + R * 12 + 64);
+        SUBKM_HIP(ctx, hipMemcpy(gid_d, gid.data(), R * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    SUBKM_TRY(subcluster_impl(ctx, S, n, d, N, o.landmark_mode, P, perm, offs, nullptr));
-    if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
-    SUBKM_TRY(lloyd_impl(ctx, P, runs.data(), (int32_t)T, loc, llab, max_iter, tol, o.precision,
-                         o.form, lit, lsse, 1, nrecheck));
+    const int32_t R = (int32_t)runs.size();
+    SUBKM_TRY(lloyd_impl(ctx, P, runs.data(), R, loc, llab, max_iter, tol, o.precision, o.form,
+                         lit_r, lsse_r, 1, nrecheck));
+    if (uneq) SUBKM_TRY(unequal_expand_local(ctx, gid_d, R, lit_r, lsse_r, T, lit, lsse));
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[3], s));
     // final run on the local centers, strided start
     subkm_run fr{0, M, 0, 0, d, k_final};
@@ -436,19 +491,19 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
         SUBKM_HIP(ctx, hipEventSynchronize(ev[5]));
         float ms[5];
         for (int q = 0; q < 5; ++q) SUBKM_HIP(ctx, hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
-        std::vector<int32_t> hit((size_t)T + 1);
-        SUBKM_HIP(ctx, hipMemcpy(hit.data(), lit, T * sizeof(int32_t), hipMemcpyDeviceToHost));
-        SUBKM_HIP(ctx, hipMemcpy(&hit[T], fit, sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::vector<int32_t> hit((size_t)R + 1);
+        SUBKM_HIP(ctx, hipMemcpy(hit.data(), lit_r, R * sizeof(int32_t), hipMemcpyDeviceToHost));
+        SUBKM_HIP(ctx, hipMemcpy(&hit[R], fit, sizeof(int32_t), hipMemcpyDeviceToHost));
         unsigned long long nr = 0;
         SUBKM_HIP(ctx, hipMemcpy(&nr, nrecheck, sizeof nr, hipMemcpyDeviceToHost));
         stats->rechecked = (int64_t)nr;
         stats->T = T;
         stats->M = M;
-        stats->final_iters = hit[T];
+        stats->final_iters = hit[R];
         int64_t lpi = 0;
-        for (int64_t t = 0; t < T; ++t) lpi += runs[t].n * (int64_t)hit[t];
+        for (int32_t r = 0; r < R; ++r) lpi += runs[r].n * (int64_t)hit[r];
         stats->local_point_iters = lpi;
-        stats->final_point_iters = M * (int64_t)hit[T];
+        stats->final_point_iters = M * (int64_t)hit[R];
         stats->us_scale = ms[0] * 1e3;
         stats->us_subcluster = ms[1] * 1e3;
         stats->us_local = ms[2] * 1e3;

@@ -44,6 +44,9 @@ enum ScratchSlot {
     SC_WORDER,       // wide runs: point indices grouped by label
     SC_FRAGS,        // split path: center fragments
     SC_CNORM,        // split path: squared center norms
+    SC_UQ,           // unequal subclustering: bounds, landmark basis, histograms
+    SC_UQ_GROUP,     // unequal subclustering: group of every point
+    SC_UQ_LOCAL,     // cluster() with unequal groups: run -> group map, local outputs
     SC_COUNT
 };
 
@@ -144,6 +147,23 @@ subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, fl
 subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
                              int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
                              float *landmarks);
+// Largest number of groups of the unequal subclustering (one LDS counter per
+// group in the histogram and placement kernels).
+constexpr int64_t kUqMaxGroups = 8192;
+// Unequal sized subclustering (Algorithm 2) into m groups: P, perm (n),
+// offsets (m + 1), landmarks (nullable, m x d binary64).
+subkm_status subcluster_unequal_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
+                                     int64_t m, float *P, int32_t *perm, int64_t *offsets,
+                                     double *landmarks);
+// Moves and objective of the local runs of the non-empty groups (run r is
+// group gid[r], device array) spread over all T groups, 0 for empty ones.
+subkm_status unequal_expand_local(subkm_ctx *ctx, const int32_t *gid, int R,
+                                  const int32_t *it_c, const double *sse_c, int64_t T,
+                                  int32_t *it, double *sse);
+// Column minima and maxima of an n x d array (either output may be null);
+// flag (device int) is set when a value is NaN or infinite.
+subkm_status minmax_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *mins,
+                         float *maxs, int *flag);
 // Rounds [t0, t1) of the subclustering (segment `seg` of the caller's split;
 // the segments must be launched in order on ctx->stream).
 subkm_status subcluster_segment(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
@@ -163,6 +183,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
 void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision, int32_t form,
                             int32_t max_iter, int cu_count, size_t *req);
 void subcluster_scratch_requests(int64_t n, int32_t d, size_t *req);
+void unequal_scratch_requests(int64_t n, int32_t d, int64_t m, size_t *req);
 size_t minmax_scratch_bytes(int64_t n, int32_t d);
 bool cluster_requests(int64_t n, int32_t d, int64_t N, int32_t k_local, int32_t k_final,
                       size_t *req);

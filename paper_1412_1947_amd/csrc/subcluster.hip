@@ -599,9 +599,6 @@ __global__ void k_offsets(int64_t *off, int64_t T, int64_t N, int64_t n) {
 
 }  // namespace
 
-subkm_status minmax_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *mins,
-                         float *maxs, int *flag);
-size_t minmax_scratch_bytes(int64_t n, int32_t d);
 
 namespace {
 
