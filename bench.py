@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged workload")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip direct Lloyd on all points (the paper's comparison baseline)")
+    ap.add_argument("--no-unequal", action="store_true",
+                    help="skip the Algorithm 2 measurements")
     ap.add_argument("--no-error-report", action="store_true",
                     help="skip the oracle error report of the precision workload")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -140,6 +142,54 @@ def bench_direct(subkm, km, ref, job, two_level_ms):
             "ms": ms, "iters": iters, "point_iters_per_s": n * iters / (ms * 1e-3), "sse": sse_d,
             "sse_two_level": sse_t, "sse_ratio_two_level_over_direct": sse_t / sse_d,
             "speedup_two_level": ms / two_level_ms}
+
+
+def bench_unequal(subkm, km, X, ref, job, kw, alg1_ms):
+    """Algorithm 2 (Sec. III) on the same workload: the subclustering call on
+    its own against the HBM roofline (algorithmic bytes: read S, write P and
+    perm), and the whole method with it next to Algorithm 1."""
+    import torch
+    S = ref["S"]
+    n, d = S.shape
+    m = -(-n // job.N)
+    km.subcluster_unequal(S, m)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    torch.cuda.synchronize()
+    for k in range(5):
+        ev[k].record()
+        km.subcluster_unequal(S, m)
+    ev[5].record()
+    torch.cuda.synchronize()
+    sub_ms = float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(5)]))
+    nbytes = n * d * 4 * 2 + n * 4
+    ach = nbytes / (sub_ms * 1e-3)
+    out = km.cluster(X, scheme=subkm.SCHEME_UNEQUAL, stats=True, **kw)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = km.cluster(X, scheme=subkm.SCHEME_UNEQUAL, stats=True, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    st = out["stats"]
+    ms = float(np.median(times)) * 1e3
+    sse = float(out["sse"].cpu()[0])
+    _, _, offs = km.subcluster_unequal(S, m)
+    sizes = np.diff(offs.cpu().numpy())
+    return {"what": "Algorithm 2: m landmarks on the segment from the min to the max corner, "
+                    "nearest-landmark groups", "m": m,
+            "subcluster_ms": sub_ms, "subcluster_gbps": ach / 1e9,
+            "subcluster_roofline": {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9,
+                                    "unit": "GB/s", "frac": ach / PEAK_HBM,
+                                    "algorithmic_bytes": nbytes},
+            "alg1_subcluster_ms": ref["stats"]["us_subcluster"] * 1e-3,
+            "group_sizes": {"min": int(sizes.min()), "max": int(sizes.max()),
+                            "empty": int((sizes == 0).sum())},
+            "ms_per_step": ms, "alg1_ms_per_step": alg1_ms, "M": st["M"],
+            "point_iters_per_step": int(st["local_point_iters"] + st["final_point_iters"]),
+            "phases_us": {k: st[k] for k in ("us_scale", "us_subcluster", "us_local", "us_final",
+                                            "us_label")},
+            "sse": sse, "alg1_sse": float(ref["sse"].cpu()[0])}
 
 
 def bench_serving(subkm, synth, a):
@@ -457,6 +507,7 @@ def main():
                          f"{pi} point-iters in {secs:.1f} s"}
 
     direct = None if a.no_direct else bench_direct(subkm, km, ref, job, ms_per_step)
+    unequal = None if a.no_unequal else bench_unequal(subkm, km, X, ref, job, kw, ms_per_step)
     serving = None if a.no_serve else bench_serving(subkm, synth, a)
     precision = None if a.no_precision else bench_precision(subkm, synth, a)
     ragged = None if a.no_ragged else bench_ragged(subkm, synth, a)
@@ -480,7 +531,7 @@ def main():
         "roofline": roof, "roofline_other": {c: v for c, v in roofs.items() if c != dom},
         "plain": plain, "cpu_baseline": cpu,
         "sse": sse_batched,
-        "direct": direct, "serving": serving, "precision": precision, "ragged": ragged,
+        "direct": direct, "unequal": unequal, "serving": serving, "precision": precision, "ragged": ragged,
     }
     print(json.dumps(line))
 

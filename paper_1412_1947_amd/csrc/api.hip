@@ -448,7 +448,7 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
         SUBKM_TRY(subcluster_impl(ctx, S, n, d, N, o.landmark_mode, P, perm, offs, nullptr));
         if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
     } else {
-        SUBKM_TRY(subcluster_unequal_impl(ctx, S, n, d, T, P, perm, offs, nullptr));
+        SUBKM_TRY(subcluster_unequal_impl(ctx, S, n, d, T, P, perm, offs, nullptr, mm, mm + d));
         if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
         // the group sizes decide the runs: read them back
         std::vector<int64_t> hoff((size_t)T + 1);

@@ -151,10 +151,13 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
 // group in the histogram and placement kernels).
 constexpr int64_t kUqMaxGroups = 8192;
 // Unequal sized subclustering (Algorithm 2) into m groups: P, perm (n),
-// offsets (m + 1), landmarks (nullable, m x d binary64).
+// offsets (m + 1), landmarks (nullable, m x d binary64).  xmin/xmax
+// (nullable, device): the column bounds of the data S was min-max scaled
+// from, which fix the corner points without a pass over S.
 subkm_status subcluster_unequal_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
                                      int64_t m, float *P, int32_t *perm, int64_t *offsets,
-                                     double *landmarks);
+                                     double *landmarks, const float *xmin = nullptr,
+                                     const float *xmax = nullptr);
 // Moves and objective of the local runs of the non-empty groups (run r is
 // group gid[r], device array) spread over all T groups, 0 for empty ones.
 subkm_status unequal_expand_local(subkm_ctx *ctx, const int32_t *gid, int R,

@@ -10,19 +10,23 @@
 // index; a group may be empty.
 //
 // Kernels (one HBM pass to find the groups, one to move the rows):
-//   minmax_impl     L and H (exact column minima and maxima);
+//   minmax_impl     L and H (exact column minima and maxima), unless the
+//                   caller knows them from the scaling of S;
 //   k_uq_prep       one block: L and H - L in binary64 and float32, and the
 //                   bounds used by the certified search below;
 //   k_uq_landmarks  the landmarks, only when the caller asks for them;
 //   k_uq_assign     one block per segment of consecutive points: the nearest
 //                   landmark of every point and the segment's histogram,
 //                   stored landmark-major, counts[q * nseg + s];
-//   k_uq_scan_*     exclusive scan of counts in that order: element (q, s)
-//                   becomes the first output position of group q's members
-//                   in segment s; the group offsets fall out of it;
-//   k_uq_scatter    one block per segment: stable placement of perm and of
-//                   the rows of P (wave ballots rank equal groups in index
-//                   order, waves take turns in index order).
+//   k_uq_scan_blocks exclusive scan of counts in that order, per block of
+//                   4096 cells, with the block sums;
+//   k_uq_scatter    one block per segment: the scanned block sums (every
+//                   block rescans them in LDS) complete the scan, so that
+//                   cell (q, s) is the first output position of group q's
+//                   members in segment s (segment 0's cells are the group
+//                   offsets); then stable placement of perm and of the rows
+//                   of P (wave ballots rank equal groups in index order,
+//                   waves take turns in index order).
 //
 // The nearest landmark without visiting all m.  With P(t) = L + t (H - L)
 // (exact arithmetic, the binary64 H - L), the squared distance
@@ -79,8 +83,14 @@ __device__ T block_sum_fixed(T v, T *sh) {
     return r;
 }
 
+// The landmark basis.  With xmin/xmax (the column bounds of the data S was
+// min-max scaled from) the corners are known exactly: L_j = 0 and H_j = 1
+// (0 for a constant column), since the scaling maps the minimum to 0 and the
+// maximum to 1 without rounding.
 __global__ __launch_bounds__(kUT) void k_uq_prep(const float *__restrict__ mins,
-                                                 const float *__restrict__ maxs, int d,
+                                                 const float *__restrict__ maxs,
+                                                 const float *__restrict__ xmin,
+                                                 const float *__restrict__ xmax, int d,
                                                  double *__restrict__ Ld, double *__restrict__ Dd,
                                                  float *__restrict__ Lf, float *__restrict__ Df,
                                                  UqParam *prm) {
@@ -91,12 +101,14 @@ __global__ __launch_bounds__(kUT) void k_uq_prep(const float *__restrict__ mins,
     float sf = 0.0f;
     int nz = 0;
     for (int j = threadIdx.x; j < d; j += kUT) {
-        const double l = (double)mins[j];
-        const double dd = (double)maxs[j] - (double)mins[j];
+        const float lo = xmin ? 0.0f : mins[j];
+        const float hi = xmin ? (xmax[j] > xmin[j] ? 1.0f : 0.0f) : maxs[j];
+        const double l = (double)lo;
+        const double dd = (double)hi - (double)lo;
         const float df = (float)dd;
         Ld[j] = l;
         Dd[j] = dd;
-        Lf[j] = mins[j];
+        Lf[j] = lo;
         Df[j] = df;
         const double a = fabs(l) + 2.01 * dd;
         sl = sl + a * a;
@@ -130,91 +142,115 @@ __global__ __launch_bounds__(kUT) void k_uq_landmarks(const double *__restrict__
     }
 }
 
-// binary64 squared distance of row x to the landmark at t (attributes left to
-// right; the landmark coordinate is formed exactly as in its definition).
-template <int V>
-__host__ __device__ __forceinline__ double uq_dist(const float *__restrict__ x,
-                                          const double *__restrict__ Ld,
-                                          const double *__restrict__ Dd, int d, double t) {
-    double acc = 0.0;
-    if (V == 4) {
+// A point's row as the search reads it.  each(f) calls f(value, j) for the
+// attributes in ascending j (the order every sum below needs).
+//   RowReg<R>: d = 4 * n4 floats, n4 <= R, loaded into registers at once
+//              (all loads in flight together, both passes from registers);
+//   RowVec:    d = 4 * n4 floats read from memory in float4 units;
+//   RowScalar: any d, read float by float.
+template <int R>
+struct RowReg {
+    float4 v[R];
+    int n4;
+    __host__ __device__ __forceinline__ RowReg(const float *x, int d) : n4(d >> 2) {
         const float4 *x4 = (const float4 *)x;
-        for (int j4 = 0; j4 < (d >> 2); ++j4) {
-            const float4 v = x4[j4];
-            const int j = 4 * j4;
-            double q;
-            q = (double)v.x - (Ld[j + 0] + t * Dd[j + 0]); acc = acc + q * q;
-            q = (double)v.y - (Ld[j + 1] + t * Dd[j + 1]); acc = acc + q * q;
-            q = (double)v.z - (Ld[j + 2] + t * Dd[j + 2]); acc = acc + q * q;
-            q = (double)v.w - (Ld[j + 3] + t * Dd[j + 3]); acc = acc + q * q;
-        }
-    } else {
-        for (int j = 0; j < d; ++j) {
-            const double q = (double)x[j] - (Ld[j] + t * Dd[j]);
-            acc = acc + q * q;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (k < n4) v[k] = x4[k];
+    }
+    template <class F>
+    __host__ __device__ __forceinline__ void each(F &&f) const {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (k < n4) {
+                f(v[k].x, 4 * k);
+                f(v[k].y, 4 * k + 1);
+                f(v[k].z, 4 * k + 2);
+                f(v[k].w, 4 * k + 3);
+            }
+    }
+};
+
+struct RowVec {
+    const float4 *x4;
+    int n4;
+    __host__ __device__ __forceinline__ RowVec(const float *x, int d)
+        : x4((const float4 *)x), n4(d >> 2) {}
+    template <class F>
+    __host__ __device__ __forceinline__ void each(F &&f) const {
+#pragma unroll 4
+        for (int k = 0; k < n4; ++k) {
+            const float4 v = x4[k];
+            f(v.x, 4 * k);
+            f(v.y, 4 * k + 1);
+            f(v.z, 4 * k + 2);
+            f(v.w, 4 * k + 3);
         }
     }
+};
+
+struct RowScalar {
+    const float *x;
+    int d;
+    __host__ __device__ __forceinline__ RowScalar(const float *p, int dd) : x(p), d(dd) {}
+    template <class F>
+    __host__ __device__ __forceinline__ void each(F &&f) const {
+#pragma unroll 4
+        for (int j = 0; j < d; ++j) f(x[j], j);
+    }
+};
+
+// binary64 squared distance of the row to the landmark at t (attributes left
+// to right; the landmark coordinate is formed exactly as in its definition).
+template <class Row>
+__host__ __device__ __forceinline__ double uq_dist(const Row &x, const double *__restrict__ Ld,
+                                                   const double *__restrict__ Dd, double t) {
+    double acc = 0.0;
+    x.each([&](float xv, int j) {
+        const double q = (double)xv - (Ld[j] + t * Dd[j]);
+        acc = acc + q * q;
+    });
     return acc;
 }
 
 // The same for three landmarks in one pass over the row.
-template <int V>
-__host__ __device__ __forceinline__ void uq_dist3(const float *__restrict__ x,
-                                         const double *__restrict__ Ld,
-                                         const double *__restrict__ Dd, int d, double t0,
-                                         double t1, double t2, double &f0, double &f1,
-                                         double &f2) {
+template <class Row>
+__host__ __device__ __forceinline__ void uq_dist3(const Row &x, const double *__restrict__ Ld,
+                                                  const double *__restrict__ Dd, double t0,
+                                                  double t1, double t2, double &f0, double &f1,
+                                                  double &f2) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    auto step = [&](float xv, int j) {
+    x.each([&](float xv, int j) {
         const double xd = (double)xv, l = Ld[j], dj = Dd[j];
         double q;
-        q = xd - (l + t0 * dj); a0 = a0 + q * q;
-        q = xd - (l + t1 * dj); a1 = a1 + q * q;
-        q = xd - (l + t2 * dj); a2 = a2 + q * q;
-    };
-    if (V == 4) {
-        const float4 *x4 = (const float4 *)x;
-        for (int j4 = 0; j4 < (d >> 2); ++j4) {
-            const float4 v = x4[j4];
-            step(v.x, 4 * j4 + 0);
-            step(v.y, 4 * j4 + 1);
-            step(v.z, 4 * j4 + 2);
-            step(v.w, 4 * j4 + 3);
-        }
-    } else {
-        for (int j = 0; j < d; ++j) step(x[j], j);
-    }
+        q = xd - (l + t0 * dj);
+        a0 = a0 + q * q;
+        q = xd - (l + t1 * dj);
+        a1 = a1 + q * q;
+        q = xd - (l + t2 * dj);
+        a2 = a2 + q * q;
+    });
     f0 = a0;
     f1 = a1;
     f2 = a2;
 }
 
-// Nearest landmark of row x (the lower q on ties), by the certified window
+// Nearest landmark of the row (the lower q on ties), by the certified window
 // search described at the top of this file (host-callable, so that the
-// search can be exercised on the CPU).
-template <int V>
-__host__ __device__ int uq_nearest(const float *__restrict__ x, int d, int m,
-                          const double *__restrict__ Ld, const double *__restrict__ Dd,
-                          const float *__restrict__ Lf, const float *__restrict__ Df,
-                          const UqParam &P) {
+// search can be exercised on the CPU).  x serves the guess and the first
+// window; xm, the same row, the rare widening steps (a memory-backed row, so
+// that no register copy of the row stays live through the loop).
+template <class Row, class RowM>
+__host__ __device__ int uq_nearest(const Row &x, const RowM &xm, int m,
+                                   const double *__restrict__ Ld,
+                                   const double *__restrict__ Dd, const float *__restrict__ Lf,
+                                   const float *__restrict__ Df, const UqParam &P) {
     if (m == 1 || P.flat) return 0;  // every landmark is the same point
     const int m1 = m - 1;
     const double dm1 = (double)m1;
     // the guess: float32 projection of x on the segment
     float dot = 0.0f;
-    if (V == 4) {
-        const float4 *x4 = (const float4 *)x;
-        for (int j4 = 0; j4 < (d >> 2); ++j4) {
-            const float4 v = x4[j4];
-            const int j = 4 * j4;
-            dot = fmaf(v.x - Lf[j + 0], Df[j + 0], dot);
-            dot = fmaf(v.y - Lf[j + 1], Df[j + 1], dot);
-            dot = fmaf(v.z - Lf[j + 2], Df[j + 2], dot);
-            dot = fmaf(v.w - Lf[j + 3], Df[j + 3], dot);
-        }
-    } else {
-        for (int j = 0; j < d; ++j) dot = fmaf(x[j] - Lf[j], Df[j], dot);
-    }
+    x.each([&](float xv, int j) { dot = fmaf(xv - Lf[j], Df[j], dot); });
     const float u = dot * P.inv_n2 * (float)m1;
     int q0 = 0;
     if (u > 0.0f) q0 = u < (float)m1 ? (int)rintf(u) : m1;  // NaN gives 0
@@ -225,7 +261,7 @@ __host__ __device__ int uq_nearest(const float *__restrict__ x, int d, int m,
     {
         double f0, f1, f2;
         const double t0 = (double)a / dm1, t1 = (double)(a + 1) / dm1, t2 = (double)z / dm1;
-        uq_dist3<V>(x, Ld, Dd, d, t0, t1, t2, f0, f1, f2);
+        uq_dist3(x, Ld, Dd, t0, t1, t2, f0, f1, f2);
         // window of three (a, a+1, z) or of two (a, z = a+1, f2 == f1)
         fa = f0;
         fa1 = f1;
@@ -254,7 +290,7 @@ __host__ __device__ int uq_nearest(const float *__restrict__ x, int d, int m,
             if (!(lz > hi(fz1) && (lz - eps) * cl * dn > rb)) {
                 ++z;
                 fz1 = fz;
-                fz = uq_dist<V>(x, Ld, Dd, d, (double)z / dm1);
+                fz = uq_dist(xm, Ld, Dd, (double)z / dm1);
                 if (fz < fb) {
                     fb = fz;
                     b = z;
@@ -267,7 +303,7 @@ __host__ __device__ int uq_nearest(const float *__restrict__ x, int d, int m,
             if (!(la > hi(fa1) && (la - eps) * cl * dn > rb)) {
                 --a;
                 fa1 = fa;
-                fa = uq_dist<V>(x, Ld, Dd, d, (double)a / dm1);
+                fa = uq_dist(xm, Ld, Dd, (double)a / dm1);
                 if (fa <= fb) {
                     fb = fa;
                     b = a;
@@ -280,7 +316,32 @@ __host__ __device__ int uq_nearest(const float *__restrict__ x, int d, int m,
     return b;
 }
 
-template <int V>
+// Row kinds of the assignment kernel: registers for d = 4 n4 up to 4 R, else
+// float4 or scalar reads.
+template <int K>
+struct RowOf;
+template <>
+struct RowOf<0> {
+    using T = RowScalar;
+};
+template <>
+struct RowOf<1> {
+    using T = RowVec;
+};
+template <>
+struct RowOf<8> {
+    using T = RowReg<8>;
+};
+template <>
+struct RowOf<16> {
+    using T = RowReg<16>;
+};
+template <>
+struct RowOf<32> {
+    using T = RowReg<32>;
+};
+
+template <int K>
 __global__ __launch_bounds__(kUT) void k_uq_assign(const float *__restrict__ S, int64_t n, int d,
                                                    int m, int64_t seg, int64_t nseg,
                                                    const double *__restrict__ Ld,
@@ -290,6 +351,7 @@ __global__ __launch_bounds__(kUT) void k_uq_assign(const float *__restrict__ S, 
                                                    const UqParam *__restrict__ prm,
                                                    int32_t *__restrict__ group,
                                                    uint32_t *__restrict__ counts) {
+    using Row = typename RowOf<K>::T;
     extern __shared__ uint32_t h[];  // m
     const UqParam P = *prm;
     for (int q = threadIdx.x; q < m; q += kUT) h[q] = 0;
@@ -297,7 +359,12 @@ __global__ __launch_bounds__(kUT) void k_uq_assign(const float *__restrict__ S, 
     const int64_t s = blockIdx.x;
     const int64_t i0 = s * seg, i1 = i0 + seg < n ? i0 + seg : n;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kUT) {
-        const int q = uq_nearest<V>(S + i * d, d, m, Ld, Dd, Lf, Df, P);
+        const Row x(S + i * d, d);
+        int q;
+        if (K == 0)
+            q = uq_nearest(x, x, m, Ld, Dd, Lf, Df, P);
+        else
+            q = uq_nearest(x, RowVec(S + i * d, d), m, Ld, Dd, Lf, Df, P);
         group[i] = q;
         atomicAdd(&h[q], 1u);
     }
@@ -345,30 +412,6 @@ __global__ __launch_bounds__(kUT) void k_uq_scan_blocks(uint32_t *__restrict__ v
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kScanPartsMax) void k_uq_scan_parts(uint32_t *__restrict__ part,
-                                                                int np) {
-    __shared__ uint32_t sh[kScanPartsMax / 64];
-    const uint32_t x = (int)threadIdx.x < np ? part[threadIdx.x] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(x, sh, &total);
-    if ((int)threadIdx.x < np) part[threadIdx.x] = ex;
-}
-
-// Adds the block offsets and writes the group offsets: offsets[q] is the
-// position of cell (q, segment 0); offsets[m] = n.
-__global__ __launch_bounds__(kUT) void k_uq_finish(uint32_t *__restrict__ v, int64_t E,
-                                                   const uint32_t *__restrict__ part, int64_t nseg,
-                                                   int64_t m, int64_t n,
-                                                   int64_t *__restrict__ offsets) {
-    for (int64_t e = (int64_t)blockIdx.x * kUT + threadIdx.x; e < E;
-         e += (int64_t)gridDim.x * kUT) {
-        const uint32_t x = v[e] + part[e / kScanBlock];
-        v[e] = x;
-        if (e % nseg == 0) offsets[e / nseg] = x;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) offsets[m] = n;
-}
-
 template <int V>
 struct VecOf;
 template <>
@@ -385,18 +428,50 @@ __global__ __launch_bounds__(kUT) void k_uq_scatter(const float *__restrict__ S,
                                                     int m, int nbits, int64_t seg, int64_t nseg,
                                                     const int32_t *__restrict__ group,
                                                     const uint32_t *__restrict__ pos0,
+                                                    const uint32_t *__restrict__ part, int np,
                                                     float *__restrict__ P,
-                                                    int32_t *__restrict__ perm) {
+                                                    int32_t *__restrict__ perm,
+                                                    int64_t *__restrict__ offsets) {
     using VT = typename VecOf<V>::T;
     extern __shared__ uint32_t next[];  // m: next output position of each group
+    __shared__ uint32_t s_part[kScanPartsMax];
     __shared__ uint32_t s_pos[kUT];
+    __shared__ uint32_t s_tmp[kUT / 64];
     const int64_t s = blockIdx.x;
-    for (int q = threadIdx.x; q < m; q += kUT) next[q] = pos0[(int64_t)q * nseg + s];
+    // exclusive scan of the scan blocks' sums (small: every block redoes it)
+    {
+        constexpr int per = kScanPartsMax / kUT;
+        uint32_t v[per], sum = 0;
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            const int e = threadIdx.x * per + k;
+            v[k] = e < np ? part[e] : 0u;
+            sum += v[k];
+        }
+        uint32_t total;
+        uint32_t run = block_excl_scan(sum, s_tmp, &total);
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            s_part[threadIdx.x * per + k] = run;
+            run += v[k];
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < m; q += kUT) {
+        const int64_t e = (int64_t)q * nseg + s;
+        next[q] = pos0[e] + s_part[e / kScanBlock];
+        if (s == 0) offsets[q] = next[q];  // group q starts in segment 0
+    }
+    if (s == 0 && threadIdx.x == 0) offsets[m] = n;
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t i0 = s * seg, i1 = i0 + seg < n ? i0 + seg : n;
     const int dv = d / V;
+    // row copy: rows of up to kUT vectors are spread rpp rows per pass
+    const int rpp = dv <= kUT ? kUT / dv : 0;
+    const int cr = dv <= kUT ? threadIdx.x / dv : 0;
+    const int cc = dv <= kUT ? threadIdx.x - cr * dv : 0;
     for (int64_t c0 = i0; c0 < i1; c0 += kUT) {
         const int64_t i = c0 + threadIdx.x;
         const bool valid = i < i1;
@@ -426,9 +501,14 @@ __global__ __launch_bounds__(kUT) void k_uq_scatter(const float *__restrict__ S,
         const int nrow = (int)(i1 - c0 < kUT ? i1 - c0 : kUT);
         const VT *src = (const VT *)(S + c0 * d);
         VT *dst = (VT *)P;
-        for (int e = threadIdx.x; e < nrow * dv; e += kUT) {
-            const int r = e / dv, c = e - r * dv;
-            dst[(int64_t)s_pos[r] * dv + c] = src[e];
+        if (rpp > 0) {
+            if (cr < rpp)
+                for (int r = cr; r < nrow; r += rpp)
+                    dst[(int64_t)s_pos[r] * dv + cc] = src[(int64_t)r * dv + cc];
+        } else {
+            for (int r = 0; r < nrow; ++r)
+                for (int c = threadIdx.x; c < dv; c += kUT)
+                    dst[(int64_t)s_pos[r] * dv + c] = src[(int64_t)r * dv + c];
         }
         __syncthreads();
     }
@@ -450,7 +530,10 @@ struct UqPlan {
 
 UqPlan uq_plan(int64_t n, int64_t m) {
     UqPlan p;
-    p.seg = 4096;
+    // about 2048 segments or more (8 blocks per CU), up to 16 points per thread
+    int64_t ppt = 1;
+    while (ppt < 16 && ceil_div(n, (int64_t)kUT * ppt * 2) >= 2048) ppt *= 2;
+    p.seg = kUT * ppt;
     while (m * ceil_div(n, p.seg) > kMaxCounts) p.seg *= 2;
     p.nseg = ceil_div(n, p.seg);
     p.E = m * p.nseg;
@@ -477,7 +560,7 @@ void unequal_scratch_requests(int64_t n, int32_t d, int64_t m, size_t *req) {
 
 subkm_status subcluster_unequal_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
                                      int64_t m, float *P, int32_t *perm, int64_t *offsets,
-                                     double *landmarks) {
+                                     double *landmarks, const float *xmin, const float *xmax) {
     ProfScope ps(ctx, PK_SUBCLUSTER);
     const UqPlan pl = uq_plan(n, m);
     size_t gbytes = 0;
@@ -505,9 +588,10 @@ subkm_status subcluster_unequal_impl(subkm_ctx *ctx, const float *S, int64_t n, 
     b.group = group;
     hipStream_t st = ctx->stream;
 
-    SUBKM_TRY(minmax_impl(ctx, S, n, d, b.mins, b.maxs, b.flag));
-    hipLaunchKernelGGL(k_uq_prep, dim3(1), dim3(kUT), 0, st, b.mins, b.maxs, d, b.Ld, b.Dd, b.Lf,
-                       b.Df, b.prm);
+    // the corner points: measured, or known from the scaling of S
+    if (!xmin) SUBKM_TRY(minmax_impl(ctx, S, n, d, b.mins, b.maxs, b.flag));
+    hipLaunchKernelGGL(k_uq_prep, dim3(1), dim3(kUT), 0, st, b.mins, b.maxs, xmin, xmax, d, b.Ld,
+                       b.Dd, b.Lf, b.Df, b.prm);
     SUBKM_LAUNCHED(ctx);
     if (landmarks) {
         const int64_t total = m * d;
@@ -518,33 +602,33 @@ subkm_status subcluster_unequal_impl(subkm_ctx *ctx, const float *S, int64_t n, 
     }
     const bool v4 = (d % 4) == 0 && ((uintptr_t)S % 16) == 0 && ((uintptr_t)P % 16) == 0;
     const size_t lds = (size_t)m * sizeof(uint32_t);
-    if (v4)
-        hipLaunchKernelGGL(k_uq_assign<4>, dim3((unsigned)pl.nseg), dim3(kUT), lds, st, S, n, d,
-                           (int)m, pl.seg, pl.nseg, b.Ld, b.Dd, b.Lf, b.Df, b.prm, group,
-                           b.counts);
-    else
-        hipLaunchKernelGGL(k_uq_assign<1>, dim3((unsigned)pl.nseg), dim3(kUT), lds, st, S, n, d,
-                           (int)m, pl.seg, pl.nseg, b.Ld, b.Dd, b.Lf, b.Df, b.prm, group,
-                           b.counts);
-    SUBKM_LAUNCHED(ctx);
-    hipLaunchKernelGGL(k_uq_scan_blocks, dim3(pl.np), dim3(kUT), 0, st, b.counts, pl.E, b.part);
-    SUBKM_LAUNCHED(ctx);
-    hipLaunchKernelGGL(k_uq_scan_parts, dim3(1), dim3(kScanPartsMax), 0, st, b.part, pl.np);
-    SUBKM_LAUNCHED(ctx);
     {
-        const int grid = (int)std::min<int64_t>(ceil_div(pl.E, kUT), 4096);
-        hipLaunchKernelGGL(k_uq_finish, dim3(grid), dim3(kUT), 0, st, b.counts, pl.E, b.part,
-                           pl.nseg, m, n, offsets);
+        const int kind = !v4 ? 0 : d <= 32 ? 8 : d <= 64 ? 16 : d <= 128 ? 32 : 1;
+        auto launch = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)pl.nseg), dim3(kUT), lds, st, S, n, d, (int)m,
+                               pl.seg, pl.nseg, b.Ld, b.Dd, b.Lf, b.Df, b.prm, group, b.counts);
+        };
+        switch (kind) {
+            case 0: launch(k_uq_assign<0>); break;
+            case 8: launch(k_uq_assign<8>); break;
+            case 16: launch(k_uq_assign<16>); break;
+            case 32: launch(k_uq_assign<32>); break;
+            default: launch(k_uq_assign<1>); break;
+        }
         SUBKM_LAUNCHED(ctx);
     }
+    hipLaunchKernelGGL(k_uq_scan_blocks, dim3(pl.np), dim3(kUT), 0, st, b.counts, pl.E, b.part);
+    SUBKM_LAUNCHED(ctx);
     int nbits = 0;
     while ((1ll << nbits) < m) ++nbits;
     if (v4)
         hipLaunchKernelGGL(k_uq_scatter<4>, dim3((unsigned)pl.nseg), dim3(kUT), lds, st, S, n, d,
-                           (int)m, nbits, pl.seg, pl.nseg, group, b.counts, P, perm);
+                           (int)m, nbits, pl.seg, pl.nseg, group, b.counts, b.part, pl.np, P,
+                           perm, offsets);
     else
         hipLaunchKernelGGL(k_uq_scatter<1>, dim3((unsigned)pl.nseg), dim3(kUT), lds, st, S, n, d,
-                           (int)m, nbits, pl.seg, pl.nseg, group, b.counts, P, perm);
+                           (int)m, nbits, pl.seg, pl.nseg, group, b.counts, b.part, pl.np, P,
+                           perm, offsets);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
