@@ -85,14 +85,22 @@ subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
                          float *S, float *mins, float *maxs);
 
 /* ---------------------------------------------------------------------- */
+/* Similarity to a landmark (Sec. II leaves the measure open and names the
+ * Euclidean and the Manhattan distance).  It only decides the subclusters;
+ * the clustering inside them is k-means (squared Euclidean) either way.   */
+#define SUBKM_METRIC_L2 0 /* squared Euclidean distance (ranks as Euclidean) */
+#define SUBKM_METRIC_L1 1 /* Manhattan distance                            */
+
+/* ---------------------------------------------------------------------- */
 /* Equal sized subclustering (Sec. II, Algorithm 1 steps 2, 3 and 5, applied
  * round after round to the points left over).
  *
  * Round t (t = 0 .. T-1, T = ceil(n / N)):
  *   L_t[j] = min over the remaining points of S[i][j]   (landmark_mode 0),
  *            or the first landmark L_0 in every round     (landmark_mode 1);
- *   key_i  = sum_j ((double)S[i][j] - (double)L_t[j])^2, binary64, j
- *            ascending, no fused multiply-add;
+ *   key_i  = sum_j ((double)S[i][j] - (double)L_t[j])^2     (SUBKM_METRIC_L2)
+ *         or sum_j |(double)S[i][j] - (double)L_t[j]|       (SUBKM_METRIC_L1),
+ *            binary64, j ascending, no fused multiply-add;
  *   G_t    = the min(N, remaining) remaining points with the smallest
  *            (key_i, i) in lexicographic order (ties to the lower index);
  *   G_t is written in ascending index to perm[t*N ..] and its rows to P.
@@ -106,7 +114,7 @@ subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
  * Requires 1 <= n < 2^31, 1 <= d <= 4096, N >= 1.  The selection is exact:
  * perm and P equal those of a sort by (key, index) bit for bit.          */
 subkm_status subkm_subcluster(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
-                              int64_t N, int32_t landmark_mode, float *P,
+                              int64_t N, int32_t landmark_mode, int32_t metric, float *P,
                               int32_t *perm, int64_t *offsets, float *landmarks);
 
 /* ---------------------------------------------------------------------- */
@@ -116,8 +124,10 @@ subkm_status subkm_subcluster(subkm_ctx *ctx, const float *S, int64_t n, int32_t
  *   p_q[j] = (double)L[j] + (q / (double)(m - 1)) * ((double)H[j] - (double)L[j]),
  *            q = 0 .. m-1, binary64 in that order; p_0 = L when m = 1
  *            (step 4: m landmarks evenly on the segment, both ends included);
- *   group_i = argmin_q sum_j ((double)S[i][j] - p_q[j])^2, binary64, j
- *            ascending, no fused multiply-add, the lower q on a tie (step 5).
+ *   group_i = argmin_q sum_j ((double)S[i][j] - p_q[j])^2   (SUBKM_METRIC_L2)
+ *          or argmin_q sum_j |(double)S[i][j] - p_q[j]|     (SUBKM_METRIC_L1),
+ *            binary64, j ascending, no fused multiply-add, the lower q on a
+ *            tie (step 5).
  * Group q is written in ascending index to perm[offsets[q] .. offsets[q+1])
  * and its rows to the same rows of P; a group may be empty.
  *
@@ -130,8 +140,8 @@ subkm_status subkm_subcluster(subkm_ctx *ctx, const float *S, int64_t n, int32_t
  * few landmarks near each point's projection on the segment and proves the
  * rest farther with a rounding-error bound.                              */
 subkm_status subkm_subcluster_unequal(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
-                                      int64_t m, float *P, int32_t *perm, int64_t *offsets,
-                                      double *landmarks);
+                                      int64_t m, int32_t metric, float *P, int32_t *perm,
+                                      int64_t *offsets, double *landmarks);
 
 /* ---------------------------------------------------------------------- */
 /* Many independent Lloyd runs in one call (Sec. II Algorithm 1 step 4 for
@@ -224,6 +234,8 @@ typedef struct {
     int32_t *local_iters;  /* T                                              */
     double *local_sse;     /* T                                              */
     int64_t m;             /* Algorithm 2: groups (0: ceil(n / N))           */
+    int32_t metric;        /* SUBKM_METRIC_* of the subclustering            */
+    int32_t reserved;
 } subkm_opts;
 
 typedef struct {

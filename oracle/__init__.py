@@ -47,7 +47,7 @@ def _load():
             i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
             lib.subkm_ref_scale.argtypes = [P, i64, i32, P, P, P]
             lib.subkm_ref_scale.restype = ctypes.c_int
-            lib.subkm_ref_subcluster.argtypes = [P, i64, i32, i64, i32, P, P, P]
+            lib.subkm_ref_subcluster.argtypes = [P, i64, i32, i64, i32, i32, P, P, P]
             lib.subkm_ref_subcluster.restype = i64
             lib.subkm_ref_assign.argtypes = [P, i64, i32, i32, P, P, P, P]
             lib.subkm_ref_assign.restype = f64
@@ -55,10 +55,10 @@ def _load():
             lib.subkm_ref_update.restype = f64
             lib.subkm_ref_lloyd.argtypes = [P, i64, i32, i32, P, i32, f64, P, P, P, P]
             lib.subkm_ref_lloyd.restype = i32
-            lib.subkm_ref_subcluster_unequal.argtypes = [P, i64, i32, i64, P, P, P, P]
+            lib.subkm_ref_subcluster_unequal.argtypes = [P, i64, i32, i64, i32, P, P, P, P]
             lib.subkm_ref_subcluster_unequal.restype = i64
             lib.subkm_ref_cluster.argtypes = [P, i64, i32, i64, i32, i32, i32, f64, i32, i32,
-                                              i64, P, P, P, P, P, P, P, P, P, P, P, P, P]
+                                              i64, i32, P, P, P, P, P, P, P, P, P, P, P, P, P]
             lib.subkm_ref_cluster.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -88,32 +88,33 @@ def scale(X):
     return S, mins, maxs
 
 
-def subcluster(S, N: int, fixed_landmark: bool = False):
-    """Algorithm 1. Returns (perm int64[n], offsets int64[T+1], landmarks f32[T,d])."""
+def subcluster(S, N: int, fixed_landmark: bool = False, metric: int = 0):
+    """Algorithm 1 (metric 0: squared Euclidean, 1: Manhattan similarity).
+    Returns (perm int64[n], offsets int64[T+1], landmarks f32[T,d])."""
     S = _f32(S)
     n, d = S.shape
     T_cap = -(-n // N)
     perm = np.empty(n, np.int64)
     offsets = np.empty(T_cap + 1, np.int64)
     lms = np.empty((T_cap, d), np.float32)
-    T = _load().subkm_ref_subcluster(_p(S), n, d, int(N), int(fixed_landmark),
+    T = _load().subkm_ref_subcluster(_p(S), n, d, int(N), int(fixed_landmark), int(metric),
                                      _p(perm), _p(offsets), _p(lms))
     if T < 0:
         raise ValueError("invalid arguments")
     return perm, offsets[:T + 1].copy(), lms[:T].copy()
 
 
-def subcluster_unequal(S, m: int):
-    """Algorithm 2. Returns (perm int64[n], offsets int64[m+1], landmarks f64[m,d],
-    group int32[n])."""
+def subcluster_unequal(S, m: int, metric: int = 0):
+    """Algorithm 2 (metric as for subcluster). Returns (perm int64[n],
+    offsets int64[m+1], landmarks f64[m,d], group int32[n])."""
     S = _f32(S)
     n, d = S.shape
     perm = np.empty(n, np.int64)
     offsets = np.empty(m + 1, np.int64)
     lms = np.empty((m, d), np.float64)
     grp = np.empty(n, np.int32)
-    T = _load().subkm_ref_subcluster_unequal(_p(S), n, d, int(m), _p(perm), _p(offsets),
-                                             _p(lms), _p(grp))
+    T = _load().subkm_ref_subcluster_unequal(_p(S), n, d, int(m), int(metric), _p(perm),
+                                             _p(offsets), _p(lms), _p(grp))
     if T < 0:
         raise ValueError("invalid arguments")
     return perm, offsets, lms, grp
@@ -171,7 +172,7 @@ def local_k(n_r: int, k_local: int, N: int) -> int:
 
 
 def cluster(X, N: int, k_local: int, k_final: int, max_iter: int, tol: float,
-            fixed_landmark: bool = False, scheme: int = 0, m: int = 0):
+            fixed_landmark: bool = False, scheme: int = 0, m: int = 0, metric: int = 0):
     """The whole two-level method; returns a dict of every intermediate.
     scheme 0 subclusters with Algorithm 1, scheme 1 with Algorithm 2 into m
     groups (0: ceil(n / N))."""
@@ -193,6 +194,7 @@ def cluster(X, N: int, k_local: int, k_final: int, max_iter: int, tol: float,
     fit = ctypes.c_int32()
     rc = _load().subkm_ref_cluster(_p(X), n, d, int(N), int(k_local), int(k_final), int(max_iter),
                                    float(tol), int(fixed_landmark), int(scheme), int(m),
+                                   int(metric),
                                    _p(S), _p(perm), _p(offsets),
                                    ctypes.byref(T), _p(loc), _p(lk), _p(lit), _p(lsse),
                                    ctypes.byref(M), _p(C), _p(lab), ctypes.byref(sse),

@@ -14,7 +14,9 @@
  * What the paper leaves open is fixed as follows (the "readings"):
  *  - feature scaling is min-max scaling of every attribute to [0,1]; a
  *    constant attribute maps to 0;
- *  - the similarity to the landmark is the squared Euclidean distance;
+ *  - the similarity to the landmark is the squared Euclidean distance
+ *    (metric 0, ranks like the distance) or the Manhattan distance (metric
+ *    1), the two measures Sec. II names; Lloyd is k-means, Euclidean, always;
  *  - Algorithm 1 is applied repeatedly to the points left over (Sec. II
  *    describes the recursion as "redoing the process" on the remaining points)
  *    and the landmark is recomputed over the remaining points each round;
@@ -93,14 +95,16 @@ static int cmp_keyed(const void *a, const void *b)
     return (x->idx > y->idx) - (x->idx < y->idx);
 }
 
-/* Squared Euclidean distance of row i of S to the landmark L (the similarity
- * measure of Sec. II), attributes taken in ascending order.                */
-static double landmark_key(const float *row, const float *L, int32_t d)
+/* Similarity of row i of S to the landmark L (Sec. II leaves the measure
+ * open and names the Euclidean and the Manhattan distance): metric 0 is the
+ * squared Euclidean distance, metric 1 the Manhattan distance; attributes
+ * taken in ascending order.                                                */
+static double landmark_key(const float *row, const float *L, int32_t d, int32_t metric)
 {
     double acc = 0.0;
     for (int32_t j = 0; j < d; ++j) {
         double q = (double)row[j] - (double)L[j];
-        acc = acc + q * q;
+        acc = acc + (metric ? fabs(q) : q * q);
     }
     return acc;
 }
@@ -112,10 +116,10 @@ static double landmark_key(const float *row, const float *L, int32_t d)
  * perm[offsets[t] .. offsets[t+1]) lists subcluster t in ascending index.
  * landmarks (nullable) receives L_t, T x d.  Returns T, or -1 on error.   */
 int64_t subkm_ref_subcluster(const float *S, int64_t n, int32_t d, int64_t N,
-                             int32_t fixed_landmark, int64_t *perm,
+                             int32_t fixed_landmark, int32_t metric, int64_t *perm,
                              int64_t *offsets, float *landmarks)
 {
-    if (n < 1 || d < 1 || N < 1) return -1;
+    if (n < 1 || d < 1 || N < 1 || (metric != 0 && metric != 1)) return -1;
     int64_t *rem = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     int64_t *nxt = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     ref_keyed *kv = (ref_keyed *)malloc((size_t)n * sizeof(ref_keyed));
@@ -143,7 +147,7 @@ int64_t subkm_ref_subcluster(const float *S, int64_t n, int32_t d, int64_t N,
         /* step 3: the N points closest to L */
         int64_t take = nrem < N ? nrem : N;
         for (int64_t r = 0; r < nrem; ++r) {
-            kv[r].key = landmark_key(S + rem[r] * d, L, d);
+            kv[r].key = landmark_key(S + rem[r] * d, L, d, metric);
             kv[r].idx = rem[r];
         }
         qsort(kv, (size_t)nrem, sizeof(ref_keyed), cmp_keyed);
@@ -168,14 +172,14 @@ int64_t subkm_ref_subcluster(const float *S, int64_t n, int32_t d, int64_t N,
 /* ------------------------------------------------------------------------ */
 /* O2b Unequal sized subclustering (Sec. III, Algorithm 2).                  */
 
-/* Squared Euclidean distance of a row of S to a binary64 landmark p,
- * attributes taken in ascending order.                                     */
-static double segment_key(const float *row, const double *p, int32_t d)
+/* Similarity of a row of S to a binary64 landmark p (metric as for
+ * landmark_key), attributes taken in ascending order.                      */
+static double segment_key(const float *row, const double *p, int32_t d, int32_t metric)
 {
     double acc = 0.0;
     for (int32_t j = 0; j < d; ++j) {
         double q = (double)row[j] - p[j];
-        acc = acc + q * q;
+        acc = acc + (metric ? fabs(q) : q * q);
     }
     return acc;
 }
@@ -192,10 +196,10 @@ static double segment_key(const float *row, const double *p, int32_t d)
  * landmarks (nullable) receives p, m x d binary64; group (nullable) the
  * group of every point.  Returns m, or -1 on error.                        */
 int64_t subkm_ref_subcluster_unequal(const float *S, int64_t n, int32_t d, int64_t m,
-                                     int64_t *perm, int64_t *offsets, double *landmarks,
-                                     int32_t *group)
+                                     int32_t metric, int64_t *perm, int64_t *offsets,
+                                     double *landmarks, int32_t *group)
 {
-    if (n < 1 || d < 1 || m < 1 || m > 0x7fffffff) return -1;
+    if (n < 1 || d < 1 || m < 1 || m > 0x7fffffff || (metric != 0 && metric != 1)) return -1;
     float *L = (float *)malloc((size_t)d * sizeof(float));
     float *H = (float *)malloc((size_t)d * sizeof(float));
     double *p = (double *)malloc((size_t)m * d * sizeof(double));
@@ -225,10 +229,10 @@ int64_t subkm_ref_subcluster_unequal(const float *S, int64_t n, int32_t d, int64
     if (landmarks) memcpy(landmarks, p, (size_t)m * d * sizeof(double));
     /* step 5: every point to its nearest landmark */
     for (int64_t i = 0; i < n; ++i) {
-        double best = segment_key(S + i * d, p, d);
+        double best = segment_key(S + i * d, p, d, metric);
         int32_t bq = 0;
         for (int64_t q = 1; q < m; ++q) {
-            double k = segment_key(S + i * d, p + q * d, d);
+            double k = segment_key(S + i * d, p + q * d, d, metric);
             if (k < best) {
                 best = k;
                 bq = (int32_t)q;
@@ -392,7 +396,7 @@ int32_t subkm_ref_lloyd(const double *X, int64_t n, int32_t d, int32_t k,
 int subkm_ref_cluster(const float *X, int64_t n, int32_t d, int64_t N,
                       int32_t k_local, int32_t k_final, int32_t max_iter,
                       double tol, int32_t fixed_landmark, int32_t scheme,
-                      int64_t m_groups,
+                      int64_t m_groups, int32_t metric,
                       float *S, int64_t *perm, int64_t *offsets, int64_t *T_out,
                       double *local_centers, int32_t *local_k,
                       int32_t *local_iters, double *local_sse, int64_t *M_out,
@@ -400,7 +404,7 @@ int subkm_ref_cluster(const float *X, int64_t n, int32_t d, int64_t N,
                       int32_t *final_iters)
 {
     if (n < 1 || d < 1 || N < 1 || k_local < 1 || k_local > N || k_final < 1 ||
-        (scheme != 0 && scheme != 1) || m_groups < 0)
+        (scheme != 0 && scheme != 1) || m_groups < 0 || (metric != 0 && metric != 1))
         return REF_EINVAL;
     float *mins = (float *)malloc((size_t)d * sizeof(float));
     float *maxs = (float *)malloc((size_t)d * sizeof(float));
@@ -411,10 +415,10 @@ int subkm_ref_cluster(const float *X, int64_t n, int32_t d, int64_t N,
 
     int64_t T;
     if (scheme == 0)
-        T = subkm_ref_subcluster(S, n, d, N, fixed_landmark, perm, offsets, NULL);
+        T = subkm_ref_subcluster(S, n, d, N, fixed_landmark, metric, perm, offsets, NULL);
     else
         T = subkm_ref_subcluster_unequal(S, n, d, m_groups ? m_groups : (n + N - 1) / N,
-                                         perm, offsets, NULL, NULL);
+                                         metric, perm, offsets, NULL, NULL);
     if (T < 0) return REF_ENOMEM;
     *T_out = T;
 

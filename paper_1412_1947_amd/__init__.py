@@ -28,6 +28,8 @@ FORM_BATCHED = 0
 FORM_PLAIN = 1
 SCHEME_EQUAL = 0    # Algorithm 1
 SCHEME_UNEQUAL = 1  # Algorithm 2
+METRIC_L2 = 0       # squared Euclidean similarity to the landmark
+METRIC_L1 = 1       # Manhattan similarity to the landmark
 
 
 class SubkmError(RuntimeError):
@@ -46,7 +48,8 @@ class Opts(ctypes.Structure):
                 ("form", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("S", ctypes.c_void_p), ("perm", ctypes.c_void_p),
                 ("local_centers", ctypes.c_void_p), ("local_iters", ctypes.c_void_p),
-                ("local_sse", ctypes.c_void_p), ("m", ctypes.c_int64)]
+                ("local_sse", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("metric", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -115,9 +118,9 @@ def lib():
             L.subkm_synchronize.restype = st
             L.subkm_scale.argtypes = [P, P, i64, i32, P, P, P]
             L.subkm_scale.restype = st
-            L.subkm_subcluster.argtypes = [P, P, i64, i32, i64, i32, P, P, P, P]
+            L.subkm_subcluster.argtypes = [P, P, i64, i32, i64, i32, i32, P, P, P, P]
             L.subkm_subcluster.restype = st
-            L.subkm_subcluster_unequal.argtypes = [P, P, i64, i32, i64, P, P, P, P]
+            L.subkm_subcluster_unequal.argtypes = [P, P, i64, i32, i64, i32, P, P, P, P]
             L.subkm_subcluster_unequal.restype = st
             L.subkm_lloyd_batched.argtypes = [P, P, ctypes.POINTER(Run), i32, P, P, i32, f64, i32,
                                               i32, P, P]
@@ -249,7 +252,8 @@ class Context:
         self._check(lib().subkm_scale(self._h, _ptr(X), n, d, _ptr(S), _ptr(mins), _ptr(maxs)))
         return S, mins, maxs
 
-    def subcluster(self, S, N: int, landmark_mode: int = 0, landmarks: bool = False):
+    def subcluster(self, S, N: int, landmark_mode: int = 0, landmarks: bool = False,
+                   metric: int = METRIC_L2):
         """Algorithm 1. Returns (P, perm, offsets[, landmarks])."""
         S = self._dev(S, torch.float32, "S")
         n, d = S.shape
@@ -260,10 +264,10 @@ class Context:
         lm = self._empty((T, d), torch.float32) if landmarks else None
         self._bind_stream()
         self._check(lib().subkm_subcluster(self._h, _ptr(S), n, d, int(N), int(landmark_mode),
-                                           _ptr(P), _ptr(perm), _ptr(offs), _ptr(lm)))
+                                           int(metric), _ptr(P), _ptr(perm), _ptr(offs), _ptr(lm)))
         return (P, perm, offs, lm) if landmarks else (P, perm, offs)
 
-    def subcluster_unequal(self, S, m: int, landmarks: bool = False):
+    def subcluster_unequal(self, S, m: int, landmarks: bool = False, metric: int = METRIC_L2):
         """Algorithm 2 into m groups. Returns (P, perm, offsets[, landmarks])."""
         S = self._dev(S, torch.float32, "S")
         n, d = S.shape
@@ -273,8 +277,8 @@ class Context:
         offs = self._empty((max(m, 0) + 1,), torch.int64)
         lm = self._empty((max(m, 0), d), torch.float64) if landmarks else None
         self._bind_stream()
-        self._check(lib().subkm_subcluster_unequal(self._h, _ptr(S), n, d, m, _ptr(P), _ptr(perm),
-                                                   _ptr(offs), _ptr(lm)))
+        self._check(lib().subkm_subcluster_unequal(self._h, _ptr(S), n, d, m, int(metric), _ptr(P),
+                                                   _ptr(perm), _ptr(offs), _ptr(lm)))
         return (P, perm, offs, lm) if landmarks else (P, perm, offs)
 
     def lloyd_batched(self, P, runs, C, labels, max_iter: int, tol: float,
@@ -297,7 +301,7 @@ class Context:
     def cluster(self, X, N: int, k_local: int, k_final: int, max_iter: int, tol: float,
                 landmark_mode: int = 0, precision: int = PREC_FP32, form: int = FORM_BATCHED,
                 intermediates: bool = False, stats: bool = False, scheme: int = SCHEME_EQUAL,
-                m: int = 0):
+                m: int = 0, metric: int = METRIC_L2):
         """The whole two-level method (scheme SCHEME_EQUAL: Algorithm 1;
         SCHEME_UNEQUAL: Algorithm 2 into m groups, 0 for ceil(n / N)).  Returns
         a dict with centers (scaled space), labels, sse and, on request,
@@ -307,7 +311,7 @@ class Context:
         n, d = X.shape
         out = {}
         o = Opts(landmark_mode=int(landmark_mode), precision=int(precision), form=int(form),
-                 scheme=int(scheme), m=int(m))
+                 scheme=int(scheme), m=int(m), metric=int(metric))
         if intermediates:
             T, M = cluster_sizes(n, int(N), int(k_local))
             if scheme == SCHEME_UNEQUAL:
@@ -352,12 +356,12 @@ def scale(X):
     return context(X.device.index or 0).scale(X)
 
 
-def subcluster(S, N, landmark_mode=0, landmarks=False):
-    return context(S.device.index or 0).subcluster(S, N, landmark_mode, landmarks)
+def subcluster(S, N, landmark_mode=0, landmarks=False, metric=METRIC_L2):
+    return context(S.device.index or 0).subcluster(S, N, landmark_mode, landmarks, metric)
 
 
-def subcluster_unequal(S, m, landmarks=False):
-    return context(S.device.index or 0).subcluster_unequal(S, m, landmarks)
+def subcluster_unequal(S, m, landmarks=False, metric=METRIC_L2):
+    return context(S.device.index or 0).subcluster_unequal(S, m, landmarks, metric)
 
 
 def lloyd_batched(P, runs, C, labels, max_iter, tol, precision=PREC_FP32, form=FORM_BATCHED):

@@ -240,30 +240,34 @@ subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, f
 }
 
 subkm_status subkm_subcluster(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
-                              int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
-                              float *landmarks) {
+                              int32_t landmark_mode, int32_t metric, float *P, int32_t *perm,
+                              int64_t *offsets, float *landmarks) {
     CHECK_CTX(ctx);
     REQUIRE(ctx, n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
     REQUIRE(ctx, d >= 1 && d <= 4096, "d must be in [1, 4096]");
     REQUIRE(ctx, N >= 1, "N must be >= 1");
     REQUIRE(ctx, landmark_mode == 0 || landmark_mode == 1, "landmark_mode must be 0 or 1");
+    REQUIRE(ctx, metric == SUBKM_METRIC_L2 || metric == SUBKM_METRIC_L1, "unknown metric %d",
+            metric);
     REQUIRE(ctx, S && P && perm && offsets, "NULL array argument");
     REQUIRE(ctx, (const void *)S != (const void *)P, "P must not alias S");
     DeviceGuard g(ctx->device);
-    return subcluster_impl(ctx, S, n, d, N, landmark_mode, P, perm, offsets, landmarks);
+    return subcluster_impl(ctx, S, n, d, N, landmark_mode, metric, P, perm, offsets, landmarks);
 }
 
 subkm_status subkm_subcluster_unequal(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
-                                      int64_t m, float *P, int32_t *perm, int64_t *offsets,
-                                      double *landmarks) {
+                                      int64_t m, int32_t metric, float *P, int32_t *perm,
+                                      int64_t *offsets, double *landmarks) {
     CHECK_CTX(ctx);
     REQUIRE(ctx, n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
     REQUIRE(ctx, d >= 1 && d <= 4096, "d must be in [1, 4096]");
     REQUIRE(ctx, m >= 1 && m <= kUqMaxGroups, "m must be in [1, %lld]", (long long)kUqMaxGroups);
+    REQUIRE(ctx, metric == SUBKM_METRIC_L2 || metric == SUBKM_METRIC_L1, "unknown metric %d",
+            metric);
     REQUIRE(ctx, S && P && perm && offsets, "NULL array argument");
     REQUIRE(ctx, (const void *)S != (const void *)P, "P must not alias S");
     DeviceGuard g(ctx->device);
-    return subcluster_unequal_impl(ctx, S, n, d, m, P, perm, offsets, landmarks);
+    return subcluster_unequal_impl(ctx, S, n, d, m, P, perm, offsets, landmarks, metric);
 }
 
 subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run *runs,
@@ -385,6 +389,8 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
     REQUIRE(ctx, o.form == SUBKM_FORM_BATCHED || o.form == SUBKM_FORM_PLAIN, "unknown form");
     REQUIRE(ctx, o.scheme == SUBKM_SCHEME_EQUAL || o.scheme == SUBKM_SCHEME_UNEQUAL,
             "unknown scheme %d", o.scheme);
+    REQUIRE(ctx, o.metric == SUBKM_METRIC_L2 || o.metric == SUBKM_METRIC_L1, "unknown metric %d",
+            o.metric);
     const bool uneq = o.scheme == SUBKM_SCHEME_UNEQUAL;
     int64_t T = 0, M = 0;
     subkm_cluster_sizes(n, N, k_local, &T, &M);
@@ -445,10 +451,12 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
     if (!uneq) {
         int64_t m = 0;
         for (int64_t t = 0; t < T; ++t) add_run(t * N, std::min<int64_t>(N, n - t * N), m);
-        SUBKM_TRY(subcluster_impl(ctx, S, n, d, N, o.landmark_mode, P, perm, offs, nullptr));
+        SUBKM_TRY(subcluster_impl(ctx, S, n, d, N, o.landmark_mode, o.metric, P, perm, offs,
+                                  nullptr));
         if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
     } else {
-        SUBKM_TRY(subcluster_unequal_impl(ctx, S, n, d, T, P, perm, offs, nullptr, mm, mm + d));
+        SUBKM_TRY(subcluster_unequal_impl(ctx, S, n, d, T, P, perm, offs, nullptr, o.metric, mm,
+                                          mm + d));
         if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[2], s));
         // the group sizes decide the runs: read them back
         std::vector<int64_t> hoff((size_t)T + 1);

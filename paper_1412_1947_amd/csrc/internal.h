@@ -145,8 +145,8 @@ subkm_status set_err(subkm_ctx *ctx, subkm_status st, const char *fmt, ...);
 subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
                         float *mins, float *maxs, bool check_finite);
 subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
-                             int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
-                             float *landmarks);
+                             int32_t landmark_mode, int32_t metric, float *P, int32_t *perm,
+                             int64_t *offsets, float *landmarks);
 // Largest number of groups of the unequal subclustering (one LDS counter per
 // group in the histogram and placement kernels).
 constexpr int64_t kUqMaxGroups = 8192;
@@ -156,8 +156,8 @@ constexpr int64_t kUqMaxGroups = 8192;
 // from, which fix the corner points without a pass over S.
 subkm_status subcluster_unequal_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
                                      int64_t m, float *P, int32_t *perm, int64_t *offsets,
-                                     double *landmarks, const float *xmin = nullptr,
-                                     const float *xmax = nullptr);
+                                     double *landmarks, int32_t metric,
+                                     const float *xmin = nullptr, const float *xmax = nullptr);
 // Moves and objective of the local runs of the non-empty groups (run r is
 // group gid[r], device array) spread over all T groups, 0 for empty ones.
 subkm_status unequal_expand_local(subkm_ctx *ctx, const int32_t *gid, int R,
@@ -170,8 +170,9 @@ subkm_status minmax_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, f
 // Rounds [t0, t1) of the subclustering (segment `seg` of the caller's split;
 // the segments must be launched in order on ctx->stream).
 subkm_status subcluster_segment(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
-                                int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
-                                float *landmarks, int64_t t0, int64_t t1, int32_t seg);
+                                int32_t landmark_mode, int32_t metric, float *P, int32_t *perm,
+                                int64_t *offsets, float *landmarks, int64_t t0, int64_t t1,
+                                int32_t seg);
 
 // Lloyd runs.  `runs` is a host array; `init_mode` 0 = centers already in C,
 // 1 = copy the first k points of every run into C first, 2 = strided start

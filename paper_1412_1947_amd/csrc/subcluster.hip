@@ -4,8 +4,9 @@
 // One round is five launches with no host round trip (the threshold stays in
 // device memory) and no inter-block synchronisation inside a kernel:
 //
-//   k_keys     binary64 key of every remaining point (its squared distance to
-//              the landmark, attributes left to right, no FMA) and a 4096-bin
+//   k_keys     binary64 key of every remaining point (its squared Euclidean or
+//              its Manhattan distance to the landmark, attributes left to
+//              right, no FMA) and a 4096-bin
 //              histogram of a monotone 24-bit image v(key) of the key, merged
 //              into 16 replicas so that no address sees many atomics;
 //   k_sel1     (one block) sums the replicas and finds the bin a* holding the
@@ -139,6 +140,14 @@ __device__ void merge_find_bin(uint32_t *hist, uint32_t need, uint32_t *sh, uint
 }
 
 // ---------------------------------------------------------------------------
+// The key of a point: M = 0 squared Euclidean, M = 1 Manhattan distance to the
+// landmark (binary64, attributes left to right, no FMA).
+template <int M>
+__device__ __forceinline__ double key_term(double q) {
+    return M ? fabs(q) : q * q;
+}
+
+template <int M>
 __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
                                              const int32_t *__restrict__ rem, uint32_t nrem,
                                              const float *__restrict__ L,
@@ -153,11 +162,11 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
     for (int j = threadIdx.x; j < d; j += kT) sL[j] = Lcur ? ordered_float(Lcur[j]) : L[j];
     __syncthreads();
     if (threadIdx.x == 0) {
-        // upper bound of any key of this round: sum_j (max_j - L_j)^2
+        // upper bound of any key of this round: sum_j term(max_j - L_j)
         double b = 0.0;
         for (int j = 0; j < d; ++j) {
             double q = (double)colmax[j] - (double)sL[j];
-            b = b + q * q;
+            b = b + key_term<M>(q);
         }
         s_base = vbase_of(b);
         if (blockIdx.x == 0) st->base = s_base;
@@ -177,15 +186,15 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
             for (int j4 = 0; j4 < (d >> 2); ++j4) {
                 float4 x = r4[j4];
                 double q;
-                q = (double)x.x - (double)sL[4 * j4 + 0]; key = key + q * q;
-                q = (double)x.y - (double)sL[4 * j4 + 1]; key = key + q * q;
-                q = (double)x.z - (double)sL[4 * j4 + 2]; key = key + q * q;
-                q = (double)x.w - (double)sL[4 * j4 + 3]; key = key + q * q;
+                q = (double)x.x - (double)sL[4 * j4 + 0]; key = key + key_term<M>(q);
+                q = (double)x.y - (double)sL[4 * j4 + 1]; key = key + key_term<M>(q);
+                q = (double)x.z - (double)sL[4 * j4 + 2]; key = key + key_term<M>(q);
+                q = (double)x.w - (double)sL[4 * j4 + 3]; key = key + key_term<M>(q);
             }
         } else {
             for (int j = 0; j < d; ++j) {
                 double q = (double)row[j] - (double)sL[j];
-                key = key + q * q;
+                key = key + key_term<M>(q);
             }
         }
         keys[p] = key;
@@ -645,8 +654,9 @@ subkm_status sub_alloc(subkm_ctx *ctx, int64_t n, int32_t d, SubBufs &b) {
 
 // Every launch of one subclustering call, in order, on ctx->stream.
 subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64_t n, int32_t d,
-                         int64_t N, int32_t landmark_mode, float *P, int32_t *perm,
-                         int64_t *offsets, float *landmarks, int64_t t0, int64_t t1) {
+                         int64_t N, int32_t landmark_mode, int32_t metric, float *P,
+                         int32_t *perm, int64_t *offsets, float *landmarks, int64_t t0,
+                         int64_t t1) {
     const int64_t T = ceil_div(n, N);
     hipStream_t s = ctx->stream;
     const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
@@ -708,8 +718,9 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
             const int64_t grid = std::min<int64_t>(ceil_div(nrem, kT), 512);
             {
                 ProfScope pk(ctx, PK_KEYS);
-                hipLaunchKernelGGL(k_keys, dim3(grid), dim3(kT), dyn_d, s, S, d, cur, nrem, L, Lcur,
-                                   Lnext, colmax, keys, hist1, st, lm_t, vec4 ? 1 : 0);
+                hipLaunchKernelGGL(metric ? k_keys<1> : k_keys<0>, dim3(grid), dim3(kT), dyn_d, s,
+                                   S, d, cur, nrem, L, Lcur, Lnext, colmax, keys, hist1, st, lm_t,
+                                   vec4 ? 1 : 0);
                 SUBKM_LAUNCHED(ctx);
             }
             hipLaunchKernelGGL(k_sel1, dim3(1), dim3(kST), 0, s, hist1, need, st);
@@ -750,12 +761,14 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
 // buffers) and replayed, which removes the launch gaps between the many short
 // kernels.  The graphs hold kernel nodes only.
 subkm_status subcluster_segment(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
-                                int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
-                                float *landmarks, int64_t t0, int64_t t1, int32_t seg) {
+                                int32_t landmark_mode, int32_t metric, float *P, int32_t *perm,
+                                int64_t *offsets, float *landmarks, int64_t t0, int64_t t1,
+                                int32_t seg) {
     SubBufs b;
     SUBKM_TRY(sub_alloc(ctx, n, d, b));
     const uint64_t key[16] = {(uint64_t)(uintptr_t)S, (uint64_t)n, (uint64_t)d, (uint64_t)N,
-                              (uint64_t)landmark_mode, (uint64_t)(uintptr_t)P,
+                              (uint64_t)landmark_mode | ((uint64_t)metric << 8),
+                              (uint64_t)(uintptr_t)P,
                               (uint64_t)(uintptr_t)perm, (uint64_t)(uintptr_t)offsets,
                               (uint64_t)(uintptr_t)landmarks, (uint64_t)(uintptr_t)b.keys,
                               (uint64_t)(uintptr_t)b.rem0 ^ ((uint64_t)(uintptr_t)b.rem1 << 1),
@@ -781,7 +794,8 @@ subkm_status subcluster_segment(subkm_ctx *ctx, const float *S, int64_t n, int32
         subkm_status st = SUBKM_OK;
         hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed);
         if (e == hipSuccess) {
-            st = sub_enqueue(ctx, b, S, n, d, N, landmark_mode, P, perm, offsets, landmarks, t0, t1);
+            st = sub_enqueue(ctx, b, S, n, d, N, landmark_mode, metric, P, perm, offsets,
+                             landmarks, t0, t1);
             e = hipStreamEndCapture(ctx->cap_stream, &graph);
         }
         ctx->stream = user;
@@ -806,10 +820,10 @@ subkm_status subcluster_segment(subkm_ctx *ctx, const float *S, int64_t n, int32
 }
 
 subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
-                             int32_t landmark_mode, float *P, int32_t *perm, int64_t *offsets,
-                             float *landmarks) {
-    return subcluster_segment(ctx, S, n, d, N, landmark_mode, P, perm, offsets, landmarks, 0,
-                              ceil_div(n, N), 0);
+                             int32_t landmark_mode, int32_t metric, float *P, int32_t *perm,
+                             int64_t *offsets, float *landmarks) {
+    return subcluster_segment(ctx, S, n, d, N, landmark_mode, metric, P, perm, offsets,
+                              landmarks, 0, ceil_div(n, N), 0);
 }
 
 void subcluster_scratch_requests(int64_t n, int32_t d, size_t *req) { sub_requests(n, d, req); }

@@ -46,6 +46,12 @@
 // f(b), so the window's argmin (lower q on ties) is the argmin over all m,
 // bit for bit.  The bounds carry a factor 2 and a few ulps of slack for the
 // rounding of their own evaluation.
+//
+// With the Manhattan distance the same search holds with the distance itself
+// in place of its square root: ||x - P(t)||_1 is convex in t (a sum of
+// convex functions), the landmark rounding moves it by at most
+// eps = u sum_j (|L_j| + 2.01 |H_j - L_j|), and the evaluated sum of d
+// non-negative rounded terms is within the same relative bound.
 #include "internal.h"
 
 #include <algorithm>
@@ -93,11 +99,11 @@ __global__ __launch_bounds__(kUT) void k_uq_prep(const float *__restrict__ mins,
                                                  const float *__restrict__ xmax, int d,
                                                  double *__restrict__ Ld, double *__restrict__ Dd,
                                                  float *__restrict__ Lf, float *__restrict__ Df,
-                                                 UqParam *prm) {
+                                                 int metric, UqParam *prm) {
     __shared__ double shd[kUT];
     __shared__ float shf[kUT];
     __shared__ int shi[kUT];
-    double sl = 0.0;
+    double sl = 0.0, sa = 0.0;
     float sf = 0.0f;
     int nz = 0;
     for (int j = threadIdx.x; j < d; j += kUT) {
@@ -112,15 +118,18 @@ __global__ __launch_bounds__(kUT) void k_uq_prep(const float *__restrict__ mins,
         Df[j] = df;
         const double a = fabs(l) + 2.01 * dd;
         sl = sl + a * a;
+        sa = sa + a;
         sf = sf + df * df;
         nz |= dd != 0.0;
     }
     const double SL = block_sum_fixed(sl, shd);
+    const double SA = block_sum_fixed(sa, shd);
     const float SF = block_sum_fixed(sf, shf);
     const int NZ = block_sum_fixed(nz, shi);
     if (threadIdx.x == 0) {
         UqParam p;
-        p.eps = 2.0 * kU * sqrt(SL) * (1.0 + 8.0 * kU);
+        // squared Euclidean: the bound of ||e||_2; Manhattan: of ||e||_1
+        p.eps = 2.0 * kU * (metric ? SA : sqrt(SL)) * (1.0 + 8.0 * kU);
         const double du = (double)(d + 2) * kU;
         p.gam = 2.0 * du / (1.0 - du) + 16.0 * kU;
         p.inv_n2 = SF > 0.0f ? 1.0f / SF : 0.0f;
@@ -200,21 +209,27 @@ struct RowScalar {
     }
 };
 
-// binary64 squared distance of the row to the landmark at t (attributes left
-// to right; the landmark coordinate is formed exactly as in its definition).
-template <class Row>
+// binary64 distance of the row to the landmark at t: M = 0 squared
+// Euclidean, M = 1 Manhattan (attributes left to right; the landmark
+// coordinate is formed exactly as in its definition).
+template <int M>
+__host__ __device__ __forceinline__ double uq_term(double q) {
+    return M ? fabs(q) : q * q;
+}
+
+template <int M, class Row>
 __host__ __device__ __forceinline__ double uq_dist(const Row &x, const double *__restrict__ Ld,
                                                    const double *__restrict__ Dd, double t) {
     double acc = 0.0;
     x.each([&](float xv, int j) {
         const double q = (double)xv - (Ld[j] + t * Dd[j]);
-        acc = acc + q * q;
+        acc = acc + uq_term<M>(q);
     });
     return acc;
 }
 
 // The same for three landmarks in one pass over the row.
-template <class Row>
+template <int M, class Row>
 __host__ __device__ __forceinline__ void uq_dist3(const Row &x, const double *__restrict__ Ld,
                                                   const double *__restrict__ Dd, double t0,
                                                   double t1, double t2, double &f0, double &f1,
@@ -224,11 +239,11 @@ __host__ __device__ __forceinline__ void uq_dist3(const Row &x, const double *__
         const double xd = (double)xv, l = Ld[j], dj = Dd[j];
         double q;
         q = xd - (l + t0 * dj);
-        a0 = a0 + q * q;
+        a0 = a0 + uq_term<M>(q);
         q = xd - (l + t1 * dj);
-        a1 = a1 + q * q;
+        a1 = a1 + uq_term<M>(q);
         q = xd - (l + t2 * dj);
-        a2 = a2 + q * q;
+        a2 = a2 + uq_term<M>(q);
     });
     f0 = a0;
     f1 = a1;
@@ -240,7 +255,7 @@ __host__ __device__ __forceinline__ void uq_dist3(const Row &x, const double *__
 // search can be exercised on the CPU).  x serves the guess and the first
 // window; xm, the same row, the rare widening steps (a memory-backed row, so
 // that no register copy of the row stays live through the loop).
-template <class Row, class RowM>
+template <int M, class Row, class RowM>
 __host__ __device__ int uq_nearest(const Row &x, const RowM &xm, int m,
                                    const double *__restrict__ Ld,
                                    const double *__restrict__ Dd, const float *__restrict__ Lf,
@@ -261,7 +276,7 @@ __host__ __device__ int uq_nearest(const Row &x, const RowM &xm, int m,
     {
         double f0, f1, f2;
         const double t0 = (double)a / dm1, t1 = (double)(a + 1) / dm1, t2 = (double)z / dm1;
-        uq_dist3(x, Ld, Dd, t0, t1, t2, f0, f1, f2);
+        uq_dist3<M>(x, Ld, Dd, t0, t1, t2, f0, f1, f2);
         // window of three (a, a+1, z) or of two (a, z = a+1, f2 == f1)
         fa = f0;
         fa1 = f1;
@@ -281,16 +296,19 @@ __host__ __device__ int uq_nearest(const Row &x, const RowM &xm, int m,
     const double cl = 1.0 - P.gam, ch = 1.0 + P.gam;
     const double dn = 1.0 - 4.0 * kU, up = 1.0 + 4.0 * kU;
     const double eps = P.eps;
-    auto lo = [&](double f) { return fmax(0.0, (sqrt(f) * cl - eps) * dn); };
-    auto hi = [&](double f) { return (sqrt(f) * ch + eps) * up; };
+    // bounds of the exact distance to the ideal landmark: of its square root
+    // for the squared Euclidean distance, of itself for the Manhattan one
+    auto root = [](double f) { return M ? f : sqrt(f); };
+    auto lo = [&](double f) { return fmax(0.0, (root(f) * cl - eps) * dn); };
+    auto hi = [&](double f) { return (root(f) * ch + eps) * up; };
     for (;;) {
-        const double rb = sqrt(fb) * ch * up;
+        const double rb = root(fb) * ch * up;
         if (z < m1) {
             const double lz = lo(fz);
             if (!(lz > hi(fz1) && (lz - eps) * cl * dn > rb)) {
                 ++z;
                 fz1 = fz;
-                fz = uq_dist(xm, Ld, Dd, (double)z / dm1);
+                fz = uq_dist<M>(xm, Ld, Dd, (double)z / dm1);
                 if (fz < fb) {
                     fb = fz;
                     b = z;
@@ -303,7 +321,7 @@ __host__ __device__ int uq_nearest(const Row &x, const RowM &xm, int m,
             if (!(la > hi(fa1) && (la - eps) * cl * dn > rb)) {
                 --a;
                 fa1 = fa;
-                fa = uq_dist(xm, Ld, Dd, (double)a / dm1);
+                fa = uq_dist<M>(xm, Ld, Dd, (double)a / dm1);
                 if (fa <= fb) {
                     fb = fa;
                     b = a;
@@ -341,7 +359,7 @@ struct RowOf<32> {
     using T = RowReg<32>;
 };
 
-template <int K>
+template <int K, int M>
 __global__ __launch_bounds__(kUT) void k_uq_assign(const float *__restrict__ S, int64_t n, int d,
                                                    int m, int64_t seg, int64_t nseg,
                                                    const double *__restrict__ Ld,
@@ -362,9 +380,9 @@ __global__ __launch_bounds__(kUT) void k_uq_assign(const float *__restrict__ S, 
         const Row x(S + i * d, d);
         int q;
         if (K == 0)
-            q = uq_nearest(x, x, m, Ld, Dd, Lf, Df, P);
+            q = uq_nearest<M>(x, x, m, Ld, Dd, Lf, Df, P);
         else
-            q = uq_nearest(x, RowVec(S + i * d, d), m, Ld, Dd, Lf, Df, P);
+            q = uq_nearest<M>(x, RowVec(S + i * d, d), m, Ld, Dd, Lf, Df, P);
         group[i] = q;
         atomicAdd(&h[q], 1u);
     }
@@ -560,7 +578,8 @@ void unequal_scratch_requests(int64_t n, int32_t d, int64_t m, size_t *req) {
 
 subkm_status subcluster_unequal_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d,
                                      int64_t m, float *P, int32_t *perm, int64_t *offsets,
-                                     double *landmarks, const float *xmin, const float *xmax) {
+                                     double *landmarks, int32_t metric, const float *xmin,
+                                     const float *xmax) {
     ProfScope ps(ctx, PK_SUBCLUSTER);
     const UqPlan pl = uq_plan(n, m);
     size_t gbytes = 0;
@@ -591,7 +610,7 @@ subkm_status subcluster_unequal_impl(subkm_ctx *ctx, const float *S, int64_t n, 
     // the corner points: measured, or known from the scaling of S
     if (!xmin) SUBKM_TRY(minmax_impl(ctx, S, n, d, b.mins, b.maxs, b.flag));
     hipLaunchKernelGGL(k_uq_prep, dim3(1), dim3(kUT), 0, st, b.mins, b.maxs, xmin, xmax, d, b.Ld,
-                       b.Dd, b.Lf, b.Df, b.prm);
+                       b.Dd, b.Lf, b.Df, (int)metric, b.prm);
     SUBKM_LAUNCHED(ctx);
     if (landmarks) {
         const int64_t total = m * d;
@@ -608,13 +627,20 @@ subkm_status subcluster_unequal_impl(subkm_ctx *ctx, const float *S, int64_t n, 
             hipLaunchKernelGGL(kern, dim3((unsigned)pl.nseg), dim3(kUT), lds, st, S, n, d, (int)m,
                                pl.seg, pl.nseg, b.Ld, b.Dd, b.Lf, b.Df, b.prm, group, b.counts);
         };
-        switch (kind) {
-            case 0: launch(k_uq_assign<0>); break;
-            case 8: launch(k_uq_assign<8>); break;
-            case 16: launch(k_uq_assign<16>); break;
-            case 32: launch(k_uq_assign<32>); break;
-            default: launch(k_uq_assign<1>); break;
-        }
+        if (metric == 0) switch (kind) {
+                case 0: launch(k_uq_assign<0, 0>); break;
+                case 8: launch(k_uq_assign<8, 0>); break;
+                case 16: launch(k_uq_assign<16, 0>); break;
+                case 32: launch(k_uq_assign<32, 0>); break;
+                default: launch(k_uq_assign<1, 0>); break;
+            }
+        else switch (kind) {
+                case 0: launch(k_uq_assign<0, 1>); break;
+                case 8: launch(k_uq_assign<8, 1>); break;
+                case 16: launch(k_uq_assign<16, 1>); break;
+                case 32: launch(k_uq_assign<32, 1>); break;
+                default: launch(k_uq_assign<1, 1>); break;
+            }
         SUBKM_LAUNCHED(ctx);
     }
     hipLaunchKernelGGL(k_uq_scan_blocks, dim3(pl.np), dim3(kUT), 0, st, b.counts, pl.E, b.part);

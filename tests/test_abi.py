@@ -61,7 +61,8 @@ def test_footprint_monotone(lib):
 def test_null_context_is_einval(lib):
     P = ctypes.c_void_p
     assert lib.subkm_scale(None, None, 1, 1, None, None, None) == 1
-    assert lib.subkm_subcluster(None, None, 1, 1, 1, 0, None, None, None, None) == 1
+    assert lib.subkm_subcluster(None, None, 1, 1, 1, 0, 0, None, None, None, None) == 1
+    assert lib.subkm_subcluster_unequal(None, None, 1, 1, 1, 0, None, None, None, None) == 1
     assert lib.subkm_cluster(None, None, 1, 1, 1, 1, 1, 1, 0.0, None, None, None, None, None) == 1
     assert lib.subkm_synchronize(None) == 1
     lib.subkm_destroy(None)  # no-op
