@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged workload")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip direct Lloyd on all points (the paper's comparison baseline)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the paper-shaped 2-D sweep")
     ap.add_argument("--no-unequal", action="store_true",
                     help="skip the Algorithm 2 measurements")
     ap.add_argument("--no-error-report", action="store_true",
@@ -190,6 +192,69 @@ def bench_unequal(subkm, km, X, ref, job, kw, alg1_ms):
             "phases_us": {k: st[k] for k in ("us_scale", "us_subcluster", "us_local", "us_final",
                                             "us_label")},
             "sse": sse, "alg1_sse": float(ref["sse"].cpu()[0])}
+
+
+# Sec. VI Tables II and III (seconds on a Tesla C2075 with a Xeon E5-1410 host):
+# traditional / parallel k-means at 100k, 250k, 500k points, and the parallel
+# time at compression values 5, 10, 15 (the cell for 20 is empty)
+PAPER_TABLE2 = {100_000: (2.328, 2.78), 250_000: (25.6, 4.96), 500_000: (156.8, 6.2)}
+PAPER_TABLE3 = {5: 6.2, 10: 5.76, 15: 4.83, 20: None}
+
+
+def bench_paper_sweep(subkm, km, synth):
+    """The shape of the paper's timing experiment: 2-D blobs with 500 points
+    per cluster (k_final = n / 500), Lloyd on all points against the
+    two-level method (Algorithm 1, subclusters of N = 10000 points, compression
+    c = N / k_local), at n = 100k, 250k, 500k with c = 5, and c = 5..20 at
+    500k.  Both use <= 30 moves or a move below 1e-6."""
+    import torch
+    N, max_iter, tol = 10_000, 30, 1e-6
+
+    def timed(fn, reps=2):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) * 1e3, out
+
+    rows, sweep = [], []
+    for n in (100_000, 250_000, 500_000):
+        X = torch.from_numpy(synth.paper2d(n)).to("cuda:0")
+        k = n // 500
+        S = km.scale(X)[0]
+        C0 = S[torch.arange(k, device=S.device) * (n // k)].contiguous()
+        C = C0.clone()
+        lab = torch.empty(n, dtype=torch.int32, device="cuda:0")
+
+        def direct():
+            C.copy_(C0)
+            return km.lloyd_batched(S.reshape(-1), [(0, n, 0, 0, 2, k)], C, lab, max_iter, tol)
+
+        ms_d, (it_d, sse_d) = timed(direct)
+        cs = (5, 10, 15, 20) if n == 500_000 else (5,)
+        for c in cs:
+            def two_level():
+                return km.cluster(X, N=N, k_local=N // c, k_final=k, max_iter=max_iter, tol=tol)
+            ms_t, out = timed(two_level)
+            sse_t = float(out["sse"].cpu()[0])
+            rec = {"n": n, "k_final": k, "c": c, "N": N, "k_local": N // c, "two_level_ms": ms_t,
+                   "sse": sse_t}
+            if c == 5:
+                rows.append(dict(rec, direct_ms=ms_d, direct_iters=int(it_d.cpu()[0]),
+                                 direct_sse=float(sse_d.cpu()[0]), speedup=ms_d / ms_t,
+                                 sse_ratio=sse_t / float(sse_d.cpu()[0]),
+                                 paper_s={"traditional": PAPER_TABLE2[n][0],
+                                          "parallel": PAPER_TABLE2[n][1]}))
+            if n == 500_000:
+                sweep.append(dict(rec, speedup_over_direct=ms_d / ms_t, paper_s=PAPER_TABLE3[c]))
+        del X, S, C, C0, lab
+    return {"what": "2-D blobs, 500 points per cluster; direct Lloyd vs the two-level method "
+                    "(paper numbers: seconds on a Tesla C2075, context only)",
+            "table2": rows, "table3": sweep}
 
 
 def bench_serving(subkm, synth, a):
@@ -508,6 +573,7 @@ def main():
 
     direct = None if a.no_direct else bench_direct(subkm, km, ref, job, ms_per_step)
     unequal = None if a.no_unequal else bench_unequal(subkm, km, X, ref, job, kw, ms_per_step)
+    sweep = None if a.no_sweep else bench_paper_sweep(subkm, km, synth)
     serving = None if a.no_serve else bench_serving(subkm, synth, a)
     precision = None if a.no_precision else bench_precision(subkm, synth, a)
     ragged = None if a.no_ragged else bench_ragged(subkm, synth, a)
@@ -531,7 +597,7 @@ def main():
         "roofline": roof, "roofline_other": {c: v for c, v in roofs.items() if c != dom},
         "plain": plain, "cpu_baseline": cpu,
         "sse": sse_batched,
-        "direct": direct, "unequal": unequal, "serving": serving, "precision": precision, "ragged": ragged,
+        "direct": direct, "unequal": unequal, "paper_sweep": sweep, "serving": serving, "precision": precision, "ragged": ragged,
     }
     print(json.dumps(line))
 

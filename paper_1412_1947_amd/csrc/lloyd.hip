@@ -51,7 +51,7 @@ constexpr long long kSpinLimit = 1ll << 26;
 constexpr int kMaxG = 16;          // blocks per run in the batched form
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
-constexpr int64_t kHugeRun = 1 << 18; // points beyond which a run with moves takes the wide path
+constexpr int64_t kHugeRun = 1 << 15; // points beyond which a run with moves takes the wide path
 
 // Float32 squared distances of this thread's point against centers sC[0..nc)
 // (row-major, d per row); keeps the two smallest values and the first index
@@ -741,9 +741,9 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
     if (valid) {
         labels[R.lab_off + i] = i1;
         if (want_obj) obj = dist64(xg, Cr + (int64_t)i1 * d, d);
-        // an update follows: count the point for its center
-        if (!last_pass && ph == PH_ITER) atomicAdd(&cnt[R.cnt_off + i1], 1);
     }
+    // an update follows: count the points for their centers
+    if (cnt && !last_pass && ph == PH_ITER) wave_count_add(cnt + R.cnt_off, valid, i1, label_bits(k));
     if (threadIdx.x == 0 && nl) atomicAdd(&rstate[itm.run].rechecks, (unsigned long long)nl);
     if (want_obj) {
         const double tot = block_sum_det(obj, s_red);
@@ -917,8 +917,8 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
     if (valid) {
         labels[R.lab_off + i] = lab;
         if (want_obj) obj = dist64(xg, Cr + (int64_t)lab * D, D);
-        if (!last_pass && ph == PH_ITER) atomicAdd(&cnt[R.cnt_off + lab], 1);
     }
+    if (cnt && !last_pass && ph == PH_ITER) wave_count_add(cnt + R.cnt_off, valid, lab, label_bits(k));
     if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
     if (want_obj) {
         const double tot = block_sum_det(obj, s_red);
@@ -1494,10 +1494,11 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
             const int S = (int)ceil_div(D0.d, 32);
             SUBKM_TRY(wide_split_prep(ctx, r0, r1 - r0, kt, S, d_runs, C, d_box, d_frags, d_cn, d_rs));
             return wide_assign_split(ctx, S, i0, ni, P, d_runs, d_items, C, d_frags, d_cn, labels, d_rs,
-                                     d_obj, d_box, last, d_cnt);
+                                     d_obj, d_box, last, nullptr);
         }
+        // the update counts the labels itself (k_wcount)
         return assign_big_d(ctx, D0.d, ni, i0, P, d_runs, d_items, C, labels, d_rs, d_obj, d_box, last,
-                            d_cnt);
+                            nullptr);
     };
     // one update for runs [r0, r1), all on-chip or all wide
     auto update_seg = [&](int r0, int r1) -> subkm_status {

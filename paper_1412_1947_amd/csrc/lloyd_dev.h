@@ -95,6 +95,32 @@ __device__ __forceinline__ int32_t wave_argmin64(const float *x, const float *C,
     return bi;
 }
 
+// Label bits of a run with k centers (ballot rounds of wave_count_add).
+__device__ __forceinline__ int label_bits(int k) { return k > 1 ? 32 - __clz(k - 1) : 0; }
+
+// counter[l] += 1 for every active lane with label l, with one atomic per
+// distinct label of the wavefront: lanes with equal labels are matched by
+// ballots over the nbits label bits, and the lowest lane of each group adds
+// the group's size.  Returns to every active lane the counter's value before
+// its group's addition plus the lane's rank in the group, i.e. its slot when
+// the counter is a cursor.  Every lane of the wavefront must make the call.
+__device__ __forceinline__ int32_t wave_count_add(int32_t *counter, bool active, int32_t l,
+                                                  int nbits) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long same = __ballot(active);
+    for (int bit = 0; bit < nbits; ++bit) {
+        const bool on = (l >> bit) & 1;
+        const unsigned long long bb = __ballot(on);
+        same &= on ? bb : ~bb;
+    }
+    const int rank = __popcll(same & ((1ull << lane) - 1ull));
+    int32_t base = 0;
+    if (active && rank == 0) base = atomicAdd(&counter[l], (int32_t)__popcll(same));
+    const int leader = active ? __ffsll((unsigned long long)same) - 1 : lane;
+    base = __shfl(base, leader, 64);
+    return base + rank;
+}
+
 // Deterministic sum of one double per thread of a kAT block (fixed tree).
 __device__ __forceinline__ double block_sum_det(double v, double *sh) {
     sh[threadIdx.x] = v;

@@ -542,9 +542,9 @@ __global__ __launch_bounds__(kAT, 2) void k_assign_split(
     if (valid) {
         labels[R.lab_off + i] = lab;
         if (want_obj && !have_obj) obj = dist64(xg, Cr + (int64_t)lab * d, d);
-        // an update follows: count the point for its center
-        if (!last_pass && ph == PH_ITER) atomicAdd(&cnt[R.cnt_off + lab], 1);
     }
+    // an update follows: count the points for their centers
+    if (cnt && !last_pass && ph == PH_ITER) wave_count_add(cnt + R.cnt_off, valid, lab, label_bits(k));
     const unsigned long long nre = __popcll(__ballot(valid && st != ST_CERTAIN));
     if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
     if (want_obj) {
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(kAT, 2) void k_assign_split(
 
 // ---------------------------------------------------------------------------
 // Update of the wide runs.  cnt holds per run (at cnt_off) counts[k],
-// starts[k] and cursors[k] (the counts are added by the assignment kernels);
+// starts[k] and cursors[k] (the counts are added by k_wcount);
 // order holds per run (at lab_off) the run's point indices grouped by
 // label.
 // exclusive scan of the counts of run r0 + blockIdx.x into starts and cursors
@@ -590,23 +590,102 @@ __global__ __launch_bounds__(kAT) void k_wscan(const DevRun *__restrict__ runs, 
     }
 }
 
+// Counting and placement by label work on chunks of up to kChunkItems
+// assignment items (consecutive points; a chunk is cut where the run
+// changes).  Runs with k <= kHistK aggregate in an LDS histogram and touch
+// each global counter once per chunk; larger runs aggregate per wavefront.
+constexpr int kChunkItems = 16;
+constexpr int kHistK = 4096;
+
+// Visits the same-run segments of block blockIdx.x's chunk of items
+// [i0, i0 + ni): f(R, run, first item, end item) for runs still iterating.
+template <class F>
+__device__ __forceinline__ void for_chunk_segments(const DevRun *__restrict__ runs,
+                                                   const Item *__restrict__ items, int i0, int ni,
+                                                   const RunState *__restrict__ rstate, F &&f) {
+    const int a = i0 + blockIdx.x * kChunkItems;
+    const int b = min(i0 + ni, a + kChunkItems);
+    for (int it = a; it < b;) {
+        const int run = items[it].run;
+        const DevRun R = runs[run];
+        const int e = min(b, R.item0 + R.nitems);
+        if (rstate[run].phase == PH_ITER) f(R, run, it, e);
+        it = e;
+    }
+}
+
+// counts[c] = points labelled c (k_wfin zeroes them after the update)
+__global__ __launch_bounds__(kAT) void k_wcount(const DevRun *__restrict__ runs,
+                                               const Item *__restrict__ items, int i0, int ni,
+                                               const int32_t *__restrict__ labels,
+                                               const RunState *__restrict__ rstate,
+                                               int32_t *cnt) {
+    __shared__ int32_t h[kHistK];
+    for_chunk_segments(runs, items, i0, ni, rstate, [&](const DevRun &R, int, int a, int e) {
+        int32_t *counts = cnt + R.cnt_off;
+        const bool lds = R.k <= kHistK;
+        if (lds) {
+            for (int c = threadIdx.x; c < R.k; c += kAT) h[c] = 0;
+            __syncthreads();
+        }
+        for (int it = a; it < e; ++it) {
+            const int64_t i = items[it].first + threadIdx.x;
+            const int32_t l = i < R.n ? labels[R.lab_off + i] : -1;
+            const bool valid = (uint32_t)l < (uint32_t)R.k;
+            if (lds) {
+                if (valid) atomicAdd(&h[l], 1);
+            } else {
+                wave_count_add(counts, valid, l, label_bits(R.k));
+            }
+        }
+        if (lds) {
+            __syncthreads();
+            for (int c = threadIdx.x; c < R.k; c += kAT)
+                if (h[c]) atomicAdd(&counts[c], h[c]);
+            __syncthreads();
+        }
+    });
+}
+
+// order[starts[c] ..) = the points labelled c (any order inside a center:
+// the sums over them are exact integers), and their labels at olab_off
 __global__ __launch_bounds__(kAT) void k_wscatter(const DevRun *__restrict__ runs,
-                                                 const Item *__restrict__ items, int i0,
+                                                 const Item *__restrict__ items, int i0, int ni,
                                                  const int32_t *__restrict__ labels,
                                                  const RunState *__restrict__ rstate, int32_t *cnt,
                                                  int32_t *order, int64_t olab_off) {
-    const Item itm = items[i0 + blockIdx.x];
-    const DevRun R = runs[itm.run];
-    if (rstate[itm.run].phase != PH_ITER) return;
-    const int64_t i = itm.first + threadIdx.x;
-    if (i >= R.n) return;
-    const int32_t l = labels[R.lab_off + i];
-    if ((uint32_t)l >= (uint32_t)R.k) return;
-    const int32_t pos = atomicAdd(&cnt[R.cnt_off + 2 * (int64_t)R.k + l], 1);
-    if ((int64_t)pos < R.n) {
-        order[R.lab_off + pos] = (int32_t)i;
-        order[olab_off + R.lab_off + pos] = l;
-    }
+    __shared__ int32_t h[kHistK];
+    for_chunk_segments(runs, items, i0, ni, rstate, [&](const DevRun &R, int, int a, int e) {
+        int32_t *cursor = cnt + R.cnt_off + 2 * (int64_t)R.k;
+        const bool lds = R.k <= kHistK;
+        if (lds) {
+            // the segment's count per label, then one range per label
+            for (int c = threadIdx.x; c < R.k; c += kAT) h[c] = 0;
+            __syncthreads();
+            for (int it = a; it < e; ++it) {
+                const int64_t i = items[it].first + threadIdx.x;
+                const int32_t l = i < R.n ? labels[R.lab_off + i] : -1;
+                if ((uint32_t)l < (uint32_t)R.k) atomicAdd(&h[l], 1);
+            }
+            __syncthreads();
+            for (int c = threadIdx.x; c < R.k; c += kAT)
+                if (h[c]) h[c] = atomicAdd(&cursor[c], h[c]);
+            __syncthreads();
+        }
+        for (int it = a; it < e; ++it) {
+            const int64_t i = items[it].first + threadIdx.x;
+            const int32_t l = i < R.n ? labels[R.lab_off + i] : -1;
+            const bool valid = (uint32_t)l < (uint32_t)R.k;
+            int32_t pos;
+            if (lds) pos = valid ? atomicAdd(&h[l], 1) : 0;
+            else pos = wave_count_add(cursor, valid, l, label_bits(R.k));
+            if (valid && (int64_t)pos < R.n) {
+                order[R.lab_off + pos] = (int32_t)i;
+                order[olab_off + R.lab_off + pos] = l;
+            }
+        }
+        if (lds) __syncthreads();
+    });
 }
 
 // Balanced sums for runs with d <= kWalkD.  Every wavefront walks kWalkW
@@ -888,11 +967,17 @@ subkm_status wide_update(subkm_ctx *ctx, int r0, int nr, int i0, int ni, int w0,
     if (nr <= 0) return SUBKM_OK;
     ProfScope ps(ctx, PK_UPDATE);
     hipStream_t s = ctx->stream;
+    const int nchunks = (int)ceil_div(ni, kChunkItems);
+    if (ni > 0) {
+        hipLaunchKernelGGL(k_wcount, dim3(nchunks), dim3(kAT), 0, s, runs, items, i0, ni, labels,
+                           rs, cnt);
+        SUBKM_LAUNCHED(ctx);
+    }
     hipLaunchKernelGGL(k_wscan, dim3(nr), dim3(kAT), 0, s, runs, r0, rs, cnt);
     SUBKM_LAUNCHED(ctx);
     if (ni > 0) {
-        hipLaunchKernelGGL(k_wscatter, dim3(ni), dim3(kAT), 0, s, runs, items, i0, labels, rs, cnt,
-                           order, olab_off);
+        hipLaunchKernelGGL(k_wscatter, dim3(nchunks), dim3(kAT), 0, s, runs, items, i0, ni, labels,
+                           rs, cnt, order, olab_off);
         SUBKM_LAUNCHED(ctx);
     }
     if (nw > 0) {

@@ -601,3 +601,32 @@ def test_direct_lloyd_full_size(km, oracle):
     a, ia, sa = run_batch(km, [S], [k], 3, 0.0, form=0)
     b, ib, sb = run_batch(km, [S], [k], 3, 0.0, form=1)
     assert np.array_equal(sa, sb) and np.array_equal(a[0][0], b[0][0])
+
+
+# ------------------------------------------------- the paper's 2-D workload shape
+@pytest.mark.timeout(600)
+def test_paper2d_direct_full_size(km, oracle):
+    """Lloyd on all 500,000 points of the 2-D, 500-points-per-cluster
+    workload with 1000 centers (the traditional side of the timing
+    experiment): one move from the strided start against the oracle."""
+    X = synth.paper2d(500_000)
+    S, _, _ = oracle.scale(X)
+    k = 1000
+    shadow_steps(km, oracle, S, S[np.arange(k) * (len(S) // k)], steps=1)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_paper2d_two_level_scaled_down(km, oracle, scheme):
+    """The two-level method at the sweep's shape, scaled down so that the
+    oracle finishes: 2-D blobs, 500 points per cluster, compression 5."""
+    import paper_1412_1947_amd as pkg
+    X = synth.paper2d(20_000)
+    N, c, kf = 2000, 5, 40
+    out = km.cluster(dev(X), N, N // c, kf, 30, 1e-6, intermediates=True, stats=True,
+                     scheme=scheme)
+    ref = oracle.cluster(X, N, N // c, kf, 30, 1e-6, scheme=scheme)
+    assert out["stats"]["M"] == ref["M"]
+    assert np.array_equal(host(out["perm"]), ref["perm"])
+    assert rel_err(host(out["local_centers"])[:ref["M"]], ref["local_centers"]) <= TOL
+    assert rel_err(host(out["centers"]), ref["centers"]) <= TOL
+    assert abs(host(out["sse"])[0] - ref["sse"]) <= TOL * ref["sse"]
