@@ -97,10 +97,10 @@ __device__ uint32_t block_scan(uint32_t v, uint32_t *tmp, uint32_t *total) {
     return wbase + x - v;
 }
 
-// Sum the REP replicas of a kBins histogram (zeroing them for the next
-// use) and find the bin holding the need-th element (1-based).  Every
+// Sum the REP replicas of a kBins histogram (zeroing them for the next use
+// when ZERO) and find the bin holding the need-th element (1-based).  Every
 // thread of the kST-thread block returns the same (bin, below, count).
-template <int REP>
+template <int REP, bool ZERO>
 __device__ void merge_find_bin(uint32_t *hist, uint32_t need, uint32_t *sh, uint32_t *tmp,
                                uint32_t *bin, uint32_t *below, uint32_t *count) {
     constexpr int per = kBins / kST;
@@ -113,7 +113,7 @@ __device__ void merge_find_bin(uint32_t *hist, uint32_t need, uint32_t *sh, uint
 #pragma unroll
         for (int r = 0; r < REP; ++r) {
             a += hist[r * kBins + b];
-            hist[r * kBins + b] = 0;
+            if (ZERO) hist[r * kBins + b] = 0;
         }
         h[q] = a;
         s += a;
@@ -209,7 +209,8 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
 __global__ __launch_bounds__(kST) void k_sel1(uint32_t *hist1, uint32_t need, SelState *st) {
     __shared__ uint32_t sh[4], tmp[kST / 64];
     uint32_t a, below, cnt;
-    merge_find_bin<kRep>(hist1, need, sh, tmp, &a, &below, &cnt);
+    // (k_cand zeroes the replicas, spread over its blocks)
+    merge_find_bin<kRep, false>(hist1, need, sh, tmp, &a, &below, &cnt);
     if (threadIdx.x == 0) {
         st->astar = a;
         st->below1 = below;
@@ -220,8 +221,16 @@ __global__ __launch_bounds__(kST) void k_sel1(uint32_t *hist1, uint32_t need, Se
 
 __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, uint32_t nrem,
                                              SelState *st, double *__restrict__ ckey,
-                                             uint32_t *__restrict__ cpos, uint32_t *hist2,
-                                             uint32_t *__restrict__ blockcnt) {
+                                             uint32_t *__restrict__ cpos, uint32_t *hist1,
+                                             uint32_t *hist2, uint32_t *__restrict__ blockcnt) {
+    {
+        // the level-1 replicas were read by k_sel1: clear them for the next
+        // round, a slice per block
+        constexpr uint32_t words = kRep * kBins;
+        const uint32_t per = (words + gridDim.x - 1) / gridDim.x;
+        const uint32_t z0 = blockIdx.x * per, z1 = min(words, z0 + per);
+        for (uint32_t i = z0 + threadIdx.x; i < z1; i += kT) hist1[i] = 0;
+    }
     __shared__ uint32_t h[kBins];
     __shared__ double s_ck[kBS];
     __shared__ uint32_t s_cp[kBS];
@@ -233,10 +242,18 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
     const int lane = threadIdx.x & 63;
     uint32_t below = 0;
     const uint32_t p0 = blockIdx.x * kBS;
-    for (uint32_t q = threadIdx.x; q < kBS; q += kT) {
-        const uint32_t p = p0 + q;
+    constexpr int kPer = kBS / kT;
+    double kb[kPer];  // all of the thread's keys in flight at once
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const uint32_t p = p0 + u * kT + threadIdx.x;
+        kb[u] = p < nrem ? keys[p] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const uint32_t p = p0 + u * kT + threadIdx.x;
         const bool in = p < nrem;
-        const double k = in ? keys[p] : 0.0;
+        const double k = kb[u];
         const uint32_t v = in ? vmap(k, base) : 0u;
         const uint32_t a = v >> 12;
         below += (in && a < astar) ? 1u : 0u;
@@ -335,6 +352,7 @@ __device__ void slow_select(const double *ckey, const uint32_t *cpos, uint32_t n
 }
 
 constexpr uint32_t kSegCap = 4096;  // compaction blocks counted in LDS by k_sel2
+constexpr int kBatch = 8;           // candidate loads in flight per thread in k_sel2
 
 __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
                                               const double *__restrict__ ckey,
@@ -352,25 +370,49 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
     const bool lds_counts = nb <= kSegCap;
     for (uint32_t i = threadIdx.x; i < kSegCap; i += kST) csel[i] = 0;
     uint32_t b, below2, cnt2;
-    merge_find_bin<1>(hist2, need1, sh, tmp, &b, &below2, &cnt2);
+    merge_find_bin<1, true>(hist2, need1, sh, tmp, &b, &below2, &cnt2);
     const uint32_t need2 = need1 - below2;
     const uint32_t vstar = (astar << 12) | b;
-    double thr_key;
-    uint32_t thr_pos;
-    if (cnt2 <= (uint32_t)kRankCap) {
-        if (threadIdx.x == 0) s_n = 0;
-        __syncthreads();
-        for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
-            const double k = ckey[c];
-            if (vmap(k, base) == vstar) {
+    // A candidate's bucket decides it unless it is the boundary bucket vstar
+    // (the bucket map is monotone in the key): below, it is selected, and
+    // joins its compaction block's count now; above, it stays.
+    auto count_sel = [&](uint32_t pc) {
+        if (lds_counts) atomicAdd(&csel[pc / kBS], 1u);
+        else atomicAdd(&blockcnt[pc / kBS], 1u);
+    };
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < ncand; c0 += kST * kBatch) {
+        // the candidate list is thousands long: kBatch loads in flight per thread
+        double kk[kBatch];
+        uint32_t pp[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const uint32_t c = c0 + u * kST + threadIdx.x;
+            kk[u] = c < ncand ? ckey[c] : 0.0;
+            pp[u] = c < ncand ? cpos[c] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const uint32_t c = c0 + u * kST + threadIdx.x;
+            if (c >= ncand) continue;
+            const uint32_t v = vmap(kk[u], base);
+            if (v < vstar) {
+                count_sel(pp[u]);
+            } else if (v == vstar) {
                 const uint32_t q = atomicAdd(&s_n, 1u);
                 if (q < (uint32_t)kRankCap) {
-                    rk[q] = k;
-                    rp[q] = cpos[c];
+                    rk[q] = kk[u];
+                    rp[q] = pp[u];
                 }
             }
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    double thr_key;
+    uint32_t thr_pos;
+    if (cnt2 <= (uint32_t)kRankCap) {
+        // exact rank of the few pairs in the boundary bucket
         for (uint32_t i = threadIdx.x; i < cnt2; i += kST) {
             const double ki = rk[i];
             const uint32_t pi = rp[i];
@@ -381,18 +423,15 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
         __syncthreads();
         thr_key = rk[sh[3]];
         thr_pos = rp[sh[3]];
-        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt2; i += kST)
+            if (pair_le(rk[i], rp[i], thr_key, thr_pos)) count_sel(rp[i]);
     } else {
         slow_select(ckey, cpos, ncand, vstar, base, need2, h256, sh, &thr_key, &thr_pos);
         if (threadIdx.x == 0) st->fallback += 1;
-    }
-    // the candidates at or below the threshold join their block's count;
-    // then block counts become block offsets of the selected rows
-    for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
-        const uint32_t pc = cpos[c];
-        if (pair_le(ckey[c], pc, thr_key, thr_pos)) {
-            if (lds_counts) atomicAdd(&csel[pc / kBS], 1u);
-            else atomicAdd(&blockcnt[pc / kBS], 1u);
+        for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
+            const double k = ckey[c];
+            const uint32_t pc = cpos[c];
+            if (vmap(k, base) == vstar && pair_le(k, pc, thr_key, thr_pos)) count_sel(pc);
         }
     }
     if (!lds_counts) __threadfence_block();
@@ -727,7 +766,7 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
             SUBKM_LAUNCHED(ctx);
             {
                 ProfScope pc(ctx, PK_CAND);
-                hipLaunchKernelGGL(k_cand, dim3(nb), dim3(kT), 0, s, keys, nrem, st, ckey, cpos,
+                hipLaunchKernelGGL(k_cand, dim3(nb), dim3(kT), 0, s, keys, nrem, st, ckey, cpos, hist1,
                                    hist2, blockcnt);
                 SUBKM_LAUNCHED(ctx);
             }
