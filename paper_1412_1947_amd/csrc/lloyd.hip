@@ -48,7 +48,8 @@ constexpr int kSumW = 4096;         // int64 center sums held in LDS (fused path
 constexpr int kMaxK = 1024;         // centers per run in the fused path
 constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path)
 constexpr long long kSpinLimit = 1ll << 26;
-constexpr int kMaxG = 16;          // blocks per run in the batched form
+constexpr int kMaxG = 64;          // blocks per run in the batched form
+constexpr int kExB = 16;           // exchange loads in flight per element
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
 constexpr int64_t kHugeRun = 1 << 15; // points beyond which a run with moves takes the wide path
@@ -576,17 +577,19 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
                 }
                 __syncthreads();
                 const long long *base = parts + R.part_off + (int64_t)(it & 1) * G * (kd + k);
-                // all G loads of an element are issued before any is used
+                // kExB loads of an element are issued before any is used
                 for (int e = threadIdx.x; e < kd + k; e += kAT) {
-                    long long v[kMaxG];
-#pragma unroll
-                    for (int q = 0; q < kMaxG; ++q)
-                        v[q] = q < G ? __hip_atomic_load(&base[(int64_t)q * (kd + k) + e], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT)
-                                     : 0ll;
                     long long a = 0;
+                    for (int q0 = 0; q0 < G; q0 += kExB) {
+                        long long v[kExB];
 #pragma unroll
-                    for (int q = 0; q < kMaxG; ++q) a += v[q];
+                        for (int q = 0; q < kExB; ++q)
+                            v[q] = q0 + q < G ? __hip_atomic_load(&base[(int64_t)(q0 + q) * (kd + k) + e],
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                              : 0ll;
+#pragma unroll
+                        for (int q = 0; q < kExB; ++q) a += v[q];
+                    }
                     if (e < kd) L.s_sum[e] = a;
                     else L.s_cnt[e - kd] = (unsigned int)a;
                 }
