@@ -6,8 +6,9 @@
 // Thread -> element mapping.  Narrow rows (d < 64): a flat grid-stride loop
 // whose stride is a multiple of d, so every thread keeps one fixed column and
 // consecutive lanes read consecutive floats.  Wide rows (d >= 64): a block
-// owns a range of rows and its lanes sweep the columns of each row, again
-// contiguous across lanes.
+// owns a range of rows; its threads split into row groups whose lanes cover
+// the (float4) columns of a row, contiguous across lanes, each walking its
+// group's rows with several rows in flight.
 #include "internal.h"
 
 #include <algorithm>
@@ -55,24 +56,104 @@ __global__ __launch_bounds__(kThreads) void k_minmax_narrow(const float *__restr
     }
 }
 
+// Wide rows: a block owns rows [r0, r1).  Its threads form row groups of
+// `span` threads, one thread per W-float column vector (a block handles up
+// to kThreads vectors of a row at a time); each thread walks its group's
+// rows with kRU rows in flight, and the row groups meet in LDS.
+template <int W>
+struct VecW;
+template <>
+struct VecW<1> {
+    using T = float;
+    static __device__ __forceinline__ float get(const float &v, int) { return v; }
+    static __device__ __forceinline__ void set(float &v, int, float x) { v = x; }
+};
+template <>
+struct VecW<4> {
+    using T = float4;
+    static __device__ __forceinline__ float get(const float4 &v, int c) {
+        return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+    }
+    static __device__ __forceinline__ void set(float4 &v, int c, float x) {
+        if (c == 0) v.x = x;
+        else if (c == 1) v.y = x;
+        else if (c == 2) v.z = x;
+        else v.w = x;
+    }
+};
+
+constexpr int kRU = 4;  // rows in flight per thread
+
+template <int W>
 __global__ __launch_bounds__(kThreads) void k_minmax_wide(const float *__restrict__ X, int64_t n,
                                                           int d, int64_t rows_per_block,
                                                           float *__restrict__ pmin,
                                                           float *__restrict__ pmax,
                                                           int *__restrict__ flag) {
+    using V = typename VecW<W>::T;
+    __shared__ float smn[kThreads * W], smx[kThreads * W];
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = min(n, r0 + rows_per_block);
+    const int dv = d / W;
+    const V *Xv = (const V *)X;
     bool bad = false;
-    for (int c = threadIdx.x; c < d; c += kThreads) {
-        float mn = INFINITY, mx = -INFINITY;
-        for (int64_t r = r0; r < r1; ++r) {
-            float v = __builtin_nontemporal_load(X + r * d + c);
-            bad |= !isfinite(v);
-            mn = fminf(mn, v);
-            mx = fmaxf(mx, v);
+    for (int cb = 0; cb < dv; cb += kThreads) {
+        const int span = min(kThreads, dv - cb);
+        const int rp = kThreads / span;
+        const int rg = threadIdx.x / span, cv = cb + threadIdx.x % span;
+        float mn[W], mx[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            mn[w] = INFINITY;
+            mx[w] = -INFINITY;
         }
-        pmin[(int64_t)blockIdx.x * d + c] = mn;
-        pmax[(int64_t)blockIdx.x * d + c] = mx;
+        if (rg < rp) {
+            int64_t r = r0 + rg;
+            for (; r + (int64_t)(kRU - 1) * rp < r1; r += (int64_t)kRU * rp) {
+                V v[kRU];
+#pragma unroll
+                for (int u = 0; u < kRU; ++u) v[u] = Xv[(r + (int64_t)u * rp) * dv + cv];
+#pragma unroll
+                for (int u = 0; u < kRU; ++u)
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const float x = VecW<W>::get(v[u], w);
+                        bad |= !isfinite(x);
+                        mn[w] = fminf(mn[w], x);
+                        mx[w] = fmaxf(mx[w], x);
+                    }
+            }
+            for (; r < r1; r += rp) {
+                const V v = Xv[r * dv + cv];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const float x = VecW<W>::get(v, w);
+                    bad |= !isfinite(x);
+                    mn[w] = fminf(mn[w], x);
+                    mx[w] = fmaxf(mx[w], x);
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            smn[threadIdx.x * W + w] = mn[w];
+            smx[threadIdx.x * W + w] = mx[w];
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < span) {
+            for (int g = 1; g < rp; ++g)
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    mn[w] = fminf(mn[w], smn[(g * span + threadIdx.x) * W + w]);
+                    mx[w] = fmaxf(mx[w], smx[(g * span + threadIdx.x) * W + w]);
+                }
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                pmin[(int64_t)blockIdx.x * d + cv * W + w] = mn[w];
+                pmax[(int64_t)blockIdx.x * d + cv * W + w] = mx[w];
+            }
+        }
+        __syncthreads();
     }
     if (bad) atomicOr(flag, 1);
 }
@@ -125,16 +206,49 @@ __global__ __launch_bounds__(kThreads) void k_apply_narrow(const float *X, int64
     for (int64_t e = e0; e < total; e += stride) S[e] = scale_one(X[e], mn, mx);
 }
 
+template <int W>
 __global__ __launch_bounds__(kThreads) void k_apply_wide(const float *X, int64_t n, int d,
                                                          int64_t rows_per_block,
                                                          const float *__restrict__ mins,
                                                          const float *__restrict__ maxs,
                                                          float *S) {
+    using V = typename VecW<W>::T;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = min(n, r0 + rows_per_block);
-    for (int c = threadIdx.x; c < d; c += kThreads) {
-        const float mn = mins[c], mx = maxs[c];
-        for (int64_t r = r0; r < r1; ++r) S[r * d + c] = scale_one(X[r * d + c], mn, mx);
+    const int dv = d / W;
+    const V *Xv = (const V *)X;
+    V *Sv = (V *)S;
+    for (int cb = 0; cb < dv; cb += kThreads) {
+        const int span = min(kThreads, dv - cb);
+        const int rp = kThreads / span;
+        const int rg = threadIdx.x / span, cv = cb + threadIdx.x % span;
+        if (rg >= rp) continue;
+        float mn[W], mx[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            mn[w] = mins[cv * W + w];
+            mx[w] = maxs[cv * W + w];
+        }
+        int64_t r = r0 + rg;
+        for (; r + (int64_t)(kRU - 1) * rp < r1; r += (int64_t)kRU * rp) {
+            V v[kRU];
+#pragma unroll
+            for (int u = 0; u < kRU; ++u) v[u] = Xv[(r + (int64_t)u * rp) * dv + cv];
+#pragma unroll
+            for (int u = 0; u < kRU; ++u) {
+                V o;
+#pragma unroll
+                for (int w = 0; w < W; ++w) VecW<W>::set(o, w, scale_one(VecW<W>::get(v[u], w), mn[w], mx[w]));
+                Sv[(r + (int64_t)u * rp) * dv + cv] = o;
+            }
+        }
+        for (; r < r1; r += rp) {
+            const V v = Xv[r * dv + cv];
+            V o;
+#pragma unroll
+            for (int w = 0; w < W; ++w) VecW<W>::set(o, w, scale_one(VecW<W>::get(v, w), mn[w], mx[w]));
+            Sv[r * dv + cv] = o;
+        }
     }
 }
 
@@ -183,8 +297,11 @@ subkm_status minmax_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, f
     if (p.narrow)
         hipLaunchKernelGGL(k_minmax_narrow, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X,
                            n * d, d, p.stride, pmin, pmax, flag);
+    else if (d % 4 == 0 && (uintptr_t)X % 16 == 0)
+        hipLaunchKernelGGL(k_minmax_wide<4>, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n,
+                           d, p.rows_per_block, pmin, pmax, flag);
     else
-        hipLaunchKernelGGL(k_minmax_wide, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n,
+        hipLaunchKernelGGL(k_minmax_wide<1>, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n,
                            d, p.rows_per_block, pmin, pmax, flag);
     SUBKM_LAUNCHED(ctx);
     hipLaunchKernelGGL(k_minmax_final, dim3(d), dim3(256), 0, ctx->stream, pmin,
@@ -211,8 +328,11 @@ subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, fl
     if (p.narrow)
         hipLaunchKernelGGL(k_apply_narrow, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X,
                            n * d, d, p.stride, mins, maxs, S);
+    else if (d % 4 == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)S % 16 == 0)
+        hipLaunchKernelGGL(k_apply_wide<4>, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n, d,
+                           p.rows_per_block, mins, maxs, S);
     else
-        hipLaunchKernelGGL(k_apply_wide, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n, d,
+        hipLaunchKernelGGL(k_apply_wide<1>, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n, d,
                            p.rows_per_block, mins, maxs, S);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;

@@ -40,7 +40,7 @@ def rel_err(a, b):
 
 # ----------------------------------------------------------------------------- scale
 @pytest.mark.parametrize("n,d", [(1, 1), (7, 3), (4096, 4), (5000, 7), (3001, 64), (1000, 100),
-                                 (257, 300)])
+                                 (257, 300), (500, 65), (700, 130), (9, 1030), (40000, 128)])
 def test_scale_bit_exact(km, oracle, n, d):
     rng = np.random.default_rng(n * 31 + d)
     X = (rng.standard_normal((n, d)) * rng.uniform(0.01, 100, d) + rng.uniform(-9, 9, d)).astype(np.float32)
