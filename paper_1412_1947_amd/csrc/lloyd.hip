@@ -188,7 +188,7 @@ __device__ void center_norms(FusedLds &L, const uint32_t *box, int k, int ldk) {
 // 16 centers (rows) with 16 points (columns): lane l sees point l % 16 of a
 // group and centers 4 * (l / 16) + r, r = 0..3, of the tile.  Both sides are
 // centered on m; v = ||c - m||^2 - 2 (x - m).(c - m) ranks the centers like
-// ||x - c||^2.  Every lane keeps the two smallest v of its centers; four
+// ||x - c||^2 (the accumulator starts at ||c - m||^2).  Every lane keeps the two smallest v of its centers; four
 // lanes share a point and merge at the end.  The gap of the two smallest is
 // certain when it exceeds twice the error bound
 //     E = 2 (d + 5) u (||x - m|| + max_c ||c - m||)^2,   u = 2^-24,
@@ -249,10 +249,9 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
         b2[g] = INFINITY;
         i1[g] = 0;
     }
-    // the bias ||c - m||^2 enters the product as one more K-step: lanes of
-    // K-slot 0 carry (||c - m||^2, 1), the others (0, 0); the centers are
-    // scaled by -2 (exact), so the accumulator is v itself
-    const float bb = kk == 0 ? 1.0f : 0.0f;
+    // the bias ||c - m||^2 of the lane's four output rows (centers
+    // c0 + 4 kk + r) starts the accumulator; the centers are scaled by -2
+    // (exact), so the accumulator ends as v itself
     for (int c0 = 0; c0 < k; c0 += 16) {
         const int cA = c0 + col;
         // rows of sC are padded to k + 16 and cn holds +inf up to the next
@@ -268,15 +267,14 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
             const float cv = L.sC[(kk + 4 * q) * ldk + cA];
             ca[q] = __uint_as_float(__float_as_uint(-2.0f * (cv - mq[q])) & vmask);
         }
-        const float cnv = L.cn[cA];
-        const float cb = kk == 0 ? cnv : 0.0f;
+        const floatx4 cinit = {L.cn[c0 + 4 * kk], L.cn[c0 + 4 * kk + 1], L.cn[c0 + 4 * kk + 2],
+                               L.cn[c0 + 4 * kk + 3]};
         int32_t ci[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) ci[r] = c0 + 4 * kk + r;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cb, bb, acc, 0, 0, 0);
+            floatx4 acc = cinit;
 #pragma unroll
             for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[q], xb[g][q], acc, 0, 0, 0);
 #pragma unroll
@@ -818,7 +816,6 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
         i1[g] = 0;
     }
     float Rc2 = 0.0f;  // max_c ||c - m||^2 over the chunks seen
-    const float bb = kk == 0 ? 1.0f : 0.0f;
     for (int c0 = 0; c0 < k; c0 += kc) {
         const int nc = kc < k - c0 ? kc : k - c0;
         __syncthreads();
@@ -857,15 +854,15 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
                 const float cv = sC[(kk + 4 * q) * ldc + cA];
                 ca[q] = __uint_as_float(__float_as_uint(-2.0f * (cv - mq[q])) & vmask);
             }
-            const float cnv = cn[cA];
-            const float cb = kk == 0 ? cnv : 0.0f;
+            // the bias of the lane's four output rows starts the accumulator
+            const floatx4 cinit = {cn[t0 + 4 * kk], cn[t0 + 4 * kk + 1], cn[t0 + 4 * kk + 2],
+                                   cn[t0 + 4 * kk + 3]};
             int32_t ci[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) ci[r] = c0 + t0 + 4 * kk + r;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cb, bb, acc, 0, 0, 0);
+                floatx4 acc = cinit;
 #pragma unroll
                 for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[q], xb[g][q], acc, 0, 0, 0);
 #pragma unroll
