@@ -84,6 +84,14 @@ subkm_status subkm_synchronize(subkm_ctx *ctx);
 subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
                          float *S, float *mins, float *maxs);
 
+/* Min-max scaling of a column-major X (Sec. V flattens the data row by row
+ * or column by column; this is the column-major input): attribute j of point
+ * i at X[j * n + i].  S, mins, maxs and the arithmetic are those of
+ * subkm_scale (S row-major n x d), so both layouts give the same bits.
+ * S must not alias X.                                                      */
+subkm_status subkm_scale_colmajor(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
+                                  float *S, float *mins, float *maxs);
+
 /* ---------------------------------------------------------------------- */
 /* Similarity to a landmark (Sec. II leaves the measure open and names the
  * Euclidean and the Manhattan distance).  It only decides the subclusters;
@@ -207,7 +215,8 @@ subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run
  * from local center q * floor(M / k_final) for q = 0 .. k_final-1, and label
  * every point.
  *
- * X: n x d input (not modified).  centers: k_final x d output, in scaled
+ * X: n x d input (not modified), row-major, or column-major with
+ * opts->layout = SUBKM_LAYOUT_COL.  centers: k_final x d output, in scaled
  * space (unscale with the mins/maxs of subkm_scale).  labels: n int32
  * output, the final center of every point in input order.  sse: 1 double
  * output, sum over all points of the squared distance to its final center,
@@ -219,6 +228,8 @@ subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run
  * needs), and k_final > M is found, and reported as SUBKM_EINVAL, only
  * after the groups are formed; the call then synchronises once to read the
  * group sizes.                                                            */
+#define SUBKM_LAYOUT_ROW 0     /* X row-major, n x d (default)               */
+#define SUBKM_LAYOUT_COL 1     /* X column-major: X[j * n + i]               */
 #define SUBKM_SCHEME_EQUAL 0   /* Algorithm 1 (default) */
 #define SUBKM_SCHEME_UNEQUAL 1 /* Algorithm 2 */
 
@@ -235,7 +246,7 @@ typedef struct {
     double *local_sse;     /* T                                              */
     int64_t m;             /* Algorithm 2: groups (0: ceil(n / N))           */
     int32_t metric;        /* SUBKM_METRIC_* of the subclustering            */
-    int32_t reserved;
+    int32_t layout;        /* SUBKM_LAYOUT_* of X                            */
 } subkm_opts;
 
 typedef struct {

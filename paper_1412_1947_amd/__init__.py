@@ -30,6 +30,8 @@ SCHEME_EQUAL = 0    # Algorithm 1
 SCHEME_UNEQUAL = 1  # Algorithm 2
 METRIC_L2 = 0       # squared Euclidean similarity to the landmark
 METRIC_L1 = 1       # Manhattan similarity to the landmark
+LAYOUT_ROW = 0      # X is n x d, row-major
+LAYOUT_COL = 1      # X is d x n (column-major points)
 
 
 class SubkmError(RuntimeError):
@@ -49,7 +51,7 @@ class Opts(ctypes.Structure):
                 ("S", ctypes.c_void_p), ("perm", ctypes.c_void_p),
                 ("local_centers", ctypes.c_void_p), ("local_iters", ctypes.c_void_p),
                 ("local_sse", ctypes.c_void_p), ("m", ctypes.c_int64),
-                ("metric", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("metric", ctypes.c_int32), ("layout", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -81,7 +83,8 @@ class JobResult(ctypes.Structure):
 
 
 EXPORTS = ("subkm_create", "subkm_destroy", "subkm_last_error", "subkm_set_stream",
-           "subkm_synchronize", "subkm_scale", "subkm_subcluster", "subkm_subcluster_unequal",
+           "subkm_synchronize", "subkm_scale", "subkm_scale_colmajor", "subkm_subcluster",
+           "subkm_subcluster_unequal",
            "subkm_lloyd_batched",
            "subkm_cluster", "subkm_cluster_sizes", "subkm_cluster_footprint", "subkm_device_bytes",
            "subkm_profile_enable", "subkm_profile_query", "subkm_profile_name",
@@ -118,6 +121,8 @@ def lib():
             L.subkm_synchronize.restype = st
             L.subkm_scale.argtypes = [P, P, i64, i32, P, P, P]
             L.subkm_scale.restype = st
+            L.subkm_scale_colmajor.argtypes = [P, P, i64, i32, P, P, P]
+            L.subkm_scale_colmajor.restype = st
             L.subkm_subcluster.argtypes = [P, P, i64, i32, i64, i32, i32, P, P, P, P]
             L.subkm_subcluster.restype = st
             L.subkm_subcluster_unequal.argtypes = [P, P, i64, i32, i64, i32, P, P, P, P]
@@ -241,15 +246,21 @@ class Context:
         return out
 
     # -- the C ABI -------------------------------------------------------------
-    def scale(self, X, out=None):
-        """Min-max scaling. Returns (S, mins, maxs)."""
+    def scale(self, X, out=None, layout: int = LAYOUT_ROW):
+        """Min-max scaling. X is n x d (LAYOUT_ROW) or d x n (LAYOUT_COL, the
+        column-major layout of the points); S is n x d either way.  Returns
+        (S, mins, maxs)."""
         X = self._dev(X, torch.float32, "X")
-        n, d = X.shape
+        if layout == LAYOUT_COL:
+            d, n = X.shape
+        else:
+            n, d = X.shape
         S = self._empty((n, d), torch.float32) if out is None else self._dev(out, torch.float32, "out")
         mins = self._empty((d,), torch.float32)
         maxs = self._empty((d,), torch.float32)
         self._bind_stream()
-        self._check(lib().subkm_scale(self._h, _ptr(X), n, d, _ptr(S), _ptr(mins), _ptr(maxs)))
+        fn = lib().subkm_scale_colmajor if layout == LAYOUT_COL else lib().subkm_scale
+        self._check(fn(self._h, _ptr(X), n, d, _ptr(S), _ptr(mins), _ptr(maxs)))
         return S, mins, maxs
 
     def subcluster(self, S, N: int, landmark_mode: int = 0, landmarks: bool = False,
@@ -301,17 +312,20 @@ class Context:
     def cluster(self, X, N: int, k_local: int, k_final: int, max_iter: int, tol: float,
                 landmark_mode: int = 0, precision: int = PREC_FP32, form: int = FORM_BATCHED,
                 intermediates: bool = False, stats: bool = False, scheme: int = SCHEME_EQUAL,
-                m: int = 0, metric: int = METRIC_L2):
+                m: int = 0, metric: int = METRIC_L2, layout: int = LAYOUT_ROW):
         """The whole two-level method (scheme SCHEME_EQUAL: Algorithm 1;
         SCHEME_UNEQUAL: Algorithm 2 into m groups, 0 for ceil(n / N)).  Returns
         a dict with centers (scaled space), labels, sse and, on request,
         intermediates and phase stats.  With Algorithm 2, local_centers holds
         room for the largest possible M; stats["M"] rows of it are used."""
         X = self._dev(X, torch.float32, "X")
-        n, d = X.shape
+        if layout == LAYOUT_COL:
+            d, n = X.shape
+        else:
+            n, d = X.shape
         out = {}
         o = Opts(landmark_mode=int(landmark_mode), precision=int(precision), form=int(form),
-                 scheme=int(scheme), m=int(m), metric=int(metric))
+                 scheme=int(scheme), m=int(m), metric=int(metric), layout=int(layout))
         if intermediates:
             T, M = cluster_sizes(n, int(N), int(k_local))
             if scheme == SCHEME_UNEQUAL:
@@ -352,8 +366,8 @@ def context(device: int = 0) -> Context:
     return c
 
 
-def scale(X):
-    return context(X.device.index or 0).scale(X)
+def scale(X, layout=LAYOUT_ROW):
+    return context(X.device.index or 0).scale(X, layout=layout)
 
 
 def subcluster(S, N, landmark_mode=0, landmarks=False, metric=METRIC_L2):

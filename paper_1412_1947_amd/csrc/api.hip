@@ -239,6 +239,17 @@ subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, f
     return scale_impl(ctx, X, n, d, S, mins, maxs, true);
 }
 
+subkm_status subkm_scale_colmajor(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
+                                  float *S, float *mins, float *maxs) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
+    REQUIRE(ctx, d >= 1 && d <= 4096, "d must be in [1, 4096]");
+    REQUIRE(ctx, X && S && mins && maxs, "NULL array argument");
+    REQUIRE(ctx, (const void *)X != (const void *)S, "S must not alias X");
+    DeviceGuard g(ctx->device);
+    return scale_cm_impl(ctx, X, n, d, S, mins, maxs, true);
+}
+
 subkm_status subkm_subcluster(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
                               int32_t landmark_mode, int32_t metric, float *P, int32_t *perm,
                               int64_t *offsets, float *landmarks) {
@@ -391,6 +402,10 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
             "unknown scheme %d", o.scheme);
     REQUIRE(ctx, o.metric == SUBKM_METRIC_L2 || o.metric == SUBKM_METRIC_L1, "unknown metric %d",
             o.metric);
+    REQUIRE(ctx, o.layout == SUBKM_LAYOUT_ROW || o.layout == SUBKM_LAYOUT_COL, "unknown layout %d",
+            o.layout);
+    REQUIRE(ctx, o.layout == SUBKM_LAYOUT_ROW || (const void *)X != (const void *)o.S,
+            "opts->S must not alias a column-major X");
     const bool uneq = o.scheme == SUBKM_SCHEME_UNEQUAL;
     int64_t T = 0, M = 0;
     subkm_cluster_sizes(n, N, k_local, &T, &M);
@@ -429,7 +444,8 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
 
     hipEvent_t *ev = ctx->ev;
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[0], s));
-    SUBKM_TRY(scale_impl(ctx, X, n, d, S, mm, mm + d, true));
+    if (o.layout == SUBKM_LAYOUT_COL) SUBKM_TRY(scale_cm_impl(ctx, X, n, d, S, mm, mm + d, true));
+    else SUBKM_TRY(scale_impl(ctx, X, n, d, S, mm, mm + d, true));
     if (stats) SUBKM_HIP(ctx, hipEventRecord(ev[1], s));
 
     // local runs: one per non-empty subcluster, rows offsets[t] .. of P

@@ -144,6 +144,9 @@ subkm_status set_err(subkm_ctx *ctx, subkm_status st, const char *fmt, ...);
 // Stage entry points used by subkm_cluster (already validated arguments).
 subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
                         float *mins, float *maxs, bool check_finite);
+// The same for a column-major X (X[j n + i]); S is row-major.
+subkm_status scale_cm_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
+                           float *mins, float *maxs, bool check_finite);
 subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
                              int32_t landmark_mode, int32_t metric, float *P, int32_t *perm,
                              int64_t *offsets, float *landmarks);

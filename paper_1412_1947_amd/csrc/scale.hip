@@ -252,6 +252,84 @@ __global__ __launch_bounds__(kThreads) void k_apply_wide(const float *X, int64_t
     }
 }
 
+// Column-major input (attribute j of point i at X[j n + i], the paper's
+// column-major flattening).  Minima/maxima: block (chunk, column) reduces a
+// contiguous stretch of one column with float4 loads; the partials use the
+// row-major layout of k_minmax_final.
+constexpr int kCmChunk = 16384;  // points per partial
+
+__global__ __launch_bounds__(kThreads) void k_minmax_cm(const float *__restrict__ X, int64_t n,
+                                                        int d, int vec4,
+                                                        float *__restrict__ pmin,
+                                                        float *__restrict__ pmax,
+                                                        int *__restrict__ flag) {
+    __shared__ float sa[kThreads], sb[kThreads];
+    const int j = blockIdx.y;
+    const int64_t i0 = (int64_t)blockIdx.x * kCmChunk;
+    const int64_t i1 = min(n, i0 + kCmChunk);
+    const float *col = X + (int64_t)j * n;
+    float mn = INFINITY, mx = -INFINITY;
+    bool bad = false;
+    auto take = [&](float x) {
+        bad |= !isfinite(x);
+        mn = fminf(mn, x);
+        mx = fmaxf(mx, x);
+    };
+    if (vec4) {
+        const float4 *c4 = (const float4 *)(col + i0);
+        const int64_t nv = (i1 - i0) >> 2;
+        for (int64_t v = threadIdx.x; v < nv; v += kThreads) {
+            const float4 q = c4[v];
+            take(q.x);
+            take(q.y);
+            take(q.z);
+            take(q.w);
+        }
+        for (int64_t i = i0 + 4 * nv + threadIdx.x; i < i1; i += kThreads) take(col[i]);
+    } else {
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) take(col[i]);
+    }
+    sa[threadIdx.x] = mn;
+    sb[threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = kThreads / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sa[threadIdx.x] = fminf(sa[threadIdx.x], sa[threadIdx.x + st]);
+            sb[threadIdx.x] = fmaxf(sb[threadIdx.x], sb[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pmin[(int64_t)blockIdx.x * d + j] = sa[0];
+        pmax[(int64_t)blockIdx.x * d + j] = sb[0];
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+// Scaling with the transpose to row-major S: a block moves a tile of 64
+// points x 64 attributes through LDS, reading along points (contiguous in X)
+// and writing along attributes (contiguous in S).
+__global__ __launch_bounds__(kThreads) void k_apply_cm(const float *__restrict__ X, int64_t n, int d,
+                                                       const float *__restrict__ mins,
+                                                       const float *__restrict__ maxs,
+                                                       float *__restrict__ S) {
+    __shared__ float tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 64;
+    const int ti = threadIdx.x & 63, tq = threadIdx.x >> 6;
+    for (int jj = tq; jj < 64; jj += kThreads / 64) {
+        const int j = j0 + jj;
+        const int64_t i = i0 + ti;
+        tile[jj][ti] = (j < d && i < n) ? X[(int64_t)j * n + i] : 0.0f;
+    }
+    __syncthreads();
+    for (int ii = tq; ii < 64; ii += kThreads / 64) {
+        const int64_t i = i0 + ii;
+        const int j = j0 + ti;
+        if (i < n && j < d) S[i * d + j] = scale_one(tile[ti][ii], mins[j], maxs[j]);
+    }
+}
+
 struct Plan {
     bool narrow;
     int64_t blocks;
@@ -277,6 +355,45 @@ Plan plan_for(int64_t n, int d) {
 }
 
 }  // namespace
+
+size_t minmax_cm_scratch_bytes(int64_t n, int32_t d) {
+    return sizeof(float) * 2 * (size_t)ceil_div(n, kCmChunk) * d;
+}
+
+// Scaling of a column-major X into row-major S (Sec. V's column-major
+// flattening as an input layout); the same arithmetic as scale_impl.
+subkm_status scale_cm_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
+                           float *mins, float *maxs, bool check_finite) {
+    int *flag = (int *)ctx_scratch(ctx, SC_MM_FLAG, 256);
+    if (!flag) return SUBKM_ENOMEM;
+    SUBKM_HIP(ctx, hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+    const int64_t parts = ceil_div(n, kCmChunk);
+    float *part = (float *)ctx_scratch(ctx, SC_MM_PART, minmax_cm_scratch_bytes(n, d));
+    if (!part) return SUBKM_ENOMEM;
+    float *pmin = part, *pmax = part + parts * d;
+    {
+        ProfScope ps(ctx, PK_SCALE);
+        const int vec4 = ((uintptr_t)X % 16 == 0 && n % 4 == 0) ? 1 : 0;
+        hipLaunchKernelGGL(k_minmax_cm, dim3((unsigned)parts, (unsigned)d), dim3(kThreads), 0,
+                           ctx->stream, X, n, d, vec4, pmin, pmax, flag);
+        SUBKM_LAUNCHED(ctx);
+        hipLaunchKernelGGL(k_minmax_final, dim3(d), dim3(256), 0, ctx->stream, pmin, pmax,
+                           (int)parts, d, mins, maxs);
+        SUBKM_LAUNCHED(ctx);
+    }
+    if (check_finite) {
+        int *h = (int *)ctx_pinned(ctx, sizeof(int));
+        if (!h) return SUBKM_ENOMEM;
+        SUBKM_HIP(ctx, hipMemcpyAsync(h, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        SUBKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (*h) return set_err(ctx, SUBKM_EINVAL, "input contains NaN or infinite values");
+    }
+    ProfScope ps(ctx, PK_SCALE);
+    hipLaunchKernelGGL(k_apply_cm, dim3((unsigned)ceil_div(n, 64), (unsigned)ceil_div(d, 64)),
+                       dim3(kThreads), 0, ctx->stream, X, n, d, mins, maxs, S);
+    SUBKM_LAUNCHED(ctx);
+    return SUBKM_OK;
+}
 
 // scratch bytes minmax_impl asks for (callers that capture graphs allocate first)
 size_t minmax_scratch_bytes(int64_t n, int32_t d) {
