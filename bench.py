@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged workload")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip direct Lloyd on all points (the paper's comparison baseline)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default schedules (no tuning during the warm-up)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the paper-shaped 2-D sweep")
     ap.add_argument("--no-unequal", action="store_true",
@@ -485,9 +487,14 @@ def main():
     km = subkm.context(0)
     kw = dict(N=job.N, k_local=job.k_local, k_final=job.k_final, max_iter=job.max_iter, tol=job.tol)
 
+    # the schedule tuner picks the batched form's schedules during the warm-up
+    # (never inside the timed region; results do not depend on it)
+    tune = a.warmup > 0 and not a.no_tune
+    km.tune(tune)
     for _ in range(a.warmup):
         km.cluster(X, **kw)
     torch.cuda.synchronize()
+    km.tune(False)
 
     # work of one step (deterministic: every step does exactly the same)
     ref = km.cluster(X, intermediates=True, stats=True, **kw)
@@ -593,6 +600,7 @@ def main():
         "step_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phases_us": {k: st[k] for k in ("us_scale", "us_subcluster", "us_local", "us_final", "us_label")},
         "rechecked_assignments_per_step": st["rechecked"],
+        "tuned_shapes": km.tuned(),
         "kernels_ms_per_step": {c: v[1] / a.steps for c, v in prof.items() if v[0]},
         "roofline": roof, "roofline_other": {c: v for c, v in roofs.items() if c != dom},
         "plain": plain, "cpu_baseline": cpu,

@@ -205,6 +205,26 @@ subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run
                                  int32_t *iters, double *sse);
 
 /* ---------------------------------------------------------------------- */
+/* Schedule tuner of the batched form (Sec. V runs the subclusters in
+ * parallel; how the runs of a call share the device is this library's
+ * choice).  The schedule is the persistent kernel's grid and the largest
+ * number of blocks that split one run; it changes no result (sums are exact
+ * integers, labels exact), only the time.  With tuning on, the first
+ * batched call with moves of a new shape (number of runs, points, smallest
+ * and largest d and k, precision) runs itself under each candidate schedule
+ * on the caller's data, restarting from the caller's centers, keeps the
+ * fastest for the shape, and returns the result of one more run with it.
+ * Tuned schedules are used whether tuning is on or off.
+ *   subkm_tune_enable: on = 1 tunes unseen shapes, 0 stops (default 0).
+ *   subkm_tune_count: number of tuned shapes.
+ *   subkm_tune_save / _load: the tuned schedules as a text file (load adds
+ *   to the context's schedules; SUBKM_EINVAL on a malformed file).       */
+subkm_status subkm_tune_enable(subkm_ctx *ctx, int32_t on);
+subkm_status subkm_tune_count(subkm_ctx *ctx, int32_t *entries);
+subkm_status subkm_tune_save(subkm_ctx *ctx, const char *path);
+subkm_status subkm_tune_load(subkm_ctx *ctx, const char *path);
+
+/* ---------------------------------------------------------------------- */
 /* The whole two-level method (Sec. II Algorithm 1 or Sec. III Algorithm 2,
  * and Sec. V): scale X, subcluster it (Algorithm 1: subclusters of N points;
  * Algorithm 2, opts->scheme = SUBKM_SCHEME_UNEQUAL: opts->m groups, or

@@ -90,7 +90,8 @@ EXPORTS = ("subkm_create", "subkm_destroy", "subkm_last_error", "subkm_set_strea
            "subkm_profile_enable", "subkm_profile_query", "subkm_profile_name",
            "subkm_engine_create", "subkm_engine_destroy", "subkm_engine_last_error",
            "subkm_job_footprint", "subkm_engine_submit", "subkm_engine_poll", "subkm_engine_wait",
-           "subkm_engine_stats")
+           "subkm_engine_stats", "subkm_tune_enable", "subkm_tune_count", "subkm_tune_save",
+           "subkm_tune_load")
 
 KERNEL_CLASSES = ("assign", "update", "keys", "cand", "scatter", "scale", "lloyd_fused",
                   "subcluster")
@@ -156,6 +157,14 @@ def lib():
             L.subkm_engine_stats.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                              ctypes.POINTER(ctypes.c_size_t)]
             L.subkm_engine_stats.restype = st
+            L.subkm_tune_enable.argtypes = [P, i32]
+            L.subkm_tune_enable.restype = st
+            L.subkm_tune_count.argtypes = [P, ctypes.POINTER(i32)]
+            L.subkm_tune_count.restype = st
+            L.subkm_tune_save.argtypes = [P, ctypes.c_char_p]
+            L.subkm_tune_save.restype = st
+            L.subkm_tune_load.argtypes = [P, ctypes.c_char_p]
+            L.subkm_tune_load.restype = st
             L.subkm_profile_enable.argtypes = [P, i32]
             L.subkm_profile_enable.restype = st
             L.subkm_profile_query.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64)]
@@ -231,6 +240,22 @@ class Context:
     def device_bytes(self) -> int:
         """Device memory the context holds as scratch."""
         return int(lib().subkm_device_bytes(self._h))
+
+    def tune(self, on: bool = True):
+        """Schedule tuner of the batched form (results do not depend on it)."""
+        self._check(lib().subkm_tune_enable(self._h, 1 if on else 0))
+
+    def tuned(self) -> int:
+        """Number of shapes with a tuned schedule."""
+        n = ctypes.c_int32()
+        self._check(lib().subkm_tune_count(self._h, ctypes.byref(n)))
+        return n.value
+
+    def tune_save(self, path: str):
+        self._check(lib().subkm_tune_save(self._h, os.fsencode(path)))
+
+    def tune_load(self, path: str):
+        self._check(lib().subkm_tune_load(self._h, os.fsencode(path)))
 
     def profile(self, on: bool = True):
         """Start (or stop) per-launch kernel timing; resets the counters."""

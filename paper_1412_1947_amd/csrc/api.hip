@@ -200,6 +200,67 @@ subkm_status subkm_synchronize(subkm_ctx *ctx) {
     return SUBKM_OK;
 }
 
+subkm_status subkm_tune_enable(subkm_ctx *ctx, int32_t on) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, on == 0 || on == 1, "on must be 0 or 1");
+    ctx->tune_on = on != 0;
+    return SUBKM_OK;
+}
+
+subkm_status subkm_tune_count(subkm_ctx *ctx, int32_t *entries) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, entries, "NULL array argument");
+    *entries = (int32_t)ctx->tune.size();
+    return SUBKM_OK;
+}
+
+static const char kTuneMagic[] = "subkm-tune 1";
+
+subkm_status subkm_tune_save(subkm_ctx *ctx, const char *path) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, path, "NULL path");
+    FILE *f = std::fopen(path, "w");
+    if (!f) return set_err(ctx, SUBKM_EINVAL, "cannot open %s for writing", path);
+    std::fprintf(f, "%s\n", kTuneMagic);
+    for (const auto &e : ctx->tune) {
+        for (int i = 0; i < 5; ++i) std::fprintf(f, "%llx ", (unsigned long long)e.first.v[i]);
+        std::fprintf(f, "%d %d %.6f\n", e.second.sched.gcap, e.second.sched.bdiv, e.second.ms);
+    }
+    const bool ok = std::fclose(f) == 0;
+    return ok ? SUBKM_OK : set_err(ctx, SUBKM_EINVAL, "cannot write %s", path);
+}
+
+subkm_status subkm_tune_load(subkm_ctx *ctx, const char *path) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, path, "NULL path");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return set_err(ctx, SUBKM_EINVAL, "cannot open %s", path);
+    char head[64] = {};
+    if (!std::fgets(head, sizeof head, f) || std::strncmp(head, kTuneMagic, sizeof kTuneMagic - 1) != 0) {
+        std::fclose(f);
+        return set_err(ctx, SUBKM_EINVAL, "%s is not a schedule file", path);
+    }
+    std::map<TuneKey, TuneEntry> got;
+    for (;;) {
+        unsigned long long v[5];
+        int gcap = 0, bdiv = 0;
+        double ms = 0.0;
+        const int nf = std::fscanf(f, "%llx %llx %llx %llx %llx %d %d %lf", &v[0], &v[1], &v[2], &v[3],
+                                   &v[4], &gcap, &bdiv, &ms);
+        if (nf == EOF) break;
+        if (nf != 8 || gcap < 1 || bdiv < 1 || bdiv > 64) {
+            std::fclose(f);
+            return set_err(ctx, SUBKM_EINVAL, "%s: malformed entry", path);
+        }
+        TuneKey k;
+        for (int i = 0; i < 5; ++i) k.v[i] = v[i];
+        got[k] = TuneEntry{LloydSched{gcap, bdiv}, ms};
+    }
+    std::fclose(f);
+    for (const auto &e : got) ctx->tune[e.first] = e.second;
+    return SUBKM_OK;
+}
+
 subkm_status subkm_profile_enable(subkm_ctx *ctx, int32_t on) {
     CHECK_CTX(ctx);
     DeviceGuard g(ctx->device);

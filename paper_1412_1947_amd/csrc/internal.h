@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -47,6 +48,7 @@ enum ScratchSlot {
     SC_UQ,           // unequal subclustering: bounds, landmark basis, histograms
     SC_UQ_GROUP,     // unequal subclustering: group of every point
     SC_UQ_LOCAL,     // cluster() with unequal groups: run -> group map, local outputs
+    SC_TUNE,         // schedule tuner: the caller's starting centers
     SC_COUNT
 };
 
@@ -70,6 +72,25 @@ struct CoopGate {
     std::mutex mu;
     hipEvent_t ev = nullptr;
     bool armed = false;
+};
+
+// Schedule of the batched Lloyd form (results do not depend on it): the
+// largest number of blocks per run and the divisor of the co-resident grid.
+struct LloydSched {
+    int32_t gcap;
+    int32_t bdiv;
+};
+struct TuneKey {
+    uint64_t v[5];
+    bool operator<(const TuneKey &o) const {
+        for (int i = 0; i < 5; ++i)
+            if (v[i] != o.v[i]) return v[i] < o.v[i];
+        return false;
+    }
+};
+struct TuneEntry {
+    LloydSched sched;
+    double ms;
 };
 
 struct ScratchBuf {
@@ -100,6 +121,8 @@ struct subkm_ctx {
         hipGraphExec_t exec = nullptr;
     };
     std::vector<GraphCache> subg;      // captured subclustering segments
+    bool tune_on = false;              // tune the schedules of unseen shapes
+    std::map<TuneKey, TuneEntry> tune; // tuned schedule per shape
 };
 
 // RAII timer of the launches issued inside its scope (no-op when off).

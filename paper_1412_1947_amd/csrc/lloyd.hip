@@ -1187,7 +1187,8 @@ subkm_status persist_d(subkm_ctx *ctx, int d, bool mf, int blocks, const float *
 // blocks are free.  Every block's task list follows the global assignment
 // order, so the per-run barriers cannot wait on each other in a cycle.
 void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blocks,
-              bool exchange, std::vector<int32_t> &G, std::vector<std::vector<Task>> &per_block) {
+              bool exchange, int gcap, std::vector<int32_t> &G,
+              std::vector<std::vector<Task>> &per_block) {
     std::vector<int> order(rr);
     auto work = [&](int r) { return (double)dr[r].n * dr[r].k * dr[r].d; };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
@@ -1203,7 +1204,8 @@ void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blo
         int64_t g = std::llround(work(r) / std::max(target, 1.0));
         // with a per-iteration exchange, every block reads the G partial sums:
         // keep G small and at least two tiles per block
-        const int64_t gmax = exchange ? std::min<int64_t>(kMaxG, std::max<int64_t>(1, tiles / 2)) : tiles;
+        const int64_t gmax =
+            exchange ? std::min<int64_t>(std::min(gcap, kMaxG), std::max<int64_t>(1, tiles / 2)) : tiles;
         g = std::max<int64_t>(1, std::min<int64_t>({g, gmax, (int64_t)blocks}));
         G[r] = (int32_t)g;
         std::vector<Slot> take;
@@ -1296,10 +1298,12 @@ void plan_requests(int32_t R, int64_t n_items, int64_t n_tasks, int64_t n_toff, 
     need(SC_CNORM, sizeof(float) * (z.cn_words + 16));
 }
 
-subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, int32_t R,
-                        float *C, int32_t *labels, int32_t max_iter, double tol,
-                        int32_t precision, int32_t form, int32_t *iters, double *sse,
-                        int init_mode, unsigned long long *rechecks_acc) {
+// One call with a given schedule of the batched form (the schedule changes
+// no result: sums are exact integers and labels exact).
+subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, int32_t R,
+                       float *C, int32_t *labels, int32_t max_iter, double tol,
+                       int32_t precision, int32_t form, int32_t *iters, double *sse,
+                       int init_mode, unsigned long long *rechecks_acc, const LloydSched &sc) {
     hipStream_t s = ctx->stream;
     // runs of one path are launched together: order them by path (outputs go
     // back to the caller's order through DevRun::orig)
@@ -1355,10 +1359,11 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
                     tiles += (dr[r].n + kAT - 1) / kAT;
                 }
             const int occ = std::max(1, persist_occupancy_d(dv, mv != 0));
-            const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->cu_count * occ, tiles));
+            const int64_t cap = std::max<int64_t>(1, (int64_t)ctx->cu_count * occ / std::max(1, sc.bdiv));
+            const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cap, tiles));
             std::vector<int32_t> G(R, 1);
             std::vector<std::vector<Task>> pb;
-            schedule(rr, dr, blocks, max_iter > 0, G, pb);
+            schedule(rr, dr, blocks, max_iter > 0, sc.gcap, G, pb);
             for (int r : rr) {
                 DevRun &D = dr[r];
                 D.G = G[r];
@@ -1571,6 +1576,82 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
         if (*hflag) return set_err(ctx, SUBKM_EDEVICE, "persistent Lloyd barrier timed out");
     }
     return SUBKM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Schedule tuner of the batched form.  A shape is (runs, points, smallest
+// and largest d and k, precision, moves or not); on the first call of a new
+// shape with tuning on, every candidate schedule runs the call itself on the
+// caller's data (restarting from the same centers), the fastest is kept for
+// the shape, and the call is made once more with it.  Results are identical
+// under every schedule, so tuning only changes the time.
+namespace {
+const LloydSched kCandidates[] = {{64, 1}, {32, 1}, {16, 1}, {64, 2}, {32, 2}, {16, 2}};
+
+TuneKey shape_key(const subkm_run *runs, int32_t R, int32_t precision, int32_t max_iter) {
+    int64_t npts = 0;
+    int32_t dmin = INT32_MAX, dmax = 0, kmin = INT32_MAX, kmax = 0;
+    for (int r = 0; r < R; ++r) {
+        npts += runs[r].n;
+        dmin = std::min(dmin, runs[r].d);
+        dmax = std::max(dmax, runs[r].d);
+        kmin = std::min(kmin, runs[r].k);
+        kmax = std::max(kmax, runs[r].k);
+    }
+    TuneKey k;
+    k.v[0] = (uint64_t)R;
+    k.v[1] = (uint64_t)npts;
+    k.v[2] = ((uint64_t)(uint32_t)dmin << 32) | (uint32_t)dmax;
+    k.v[3] = ((uint64_t)(uint32_t)kmin << 32) | (uint32_t)kmax;
+    k.v[4] = ((uint64_t)(uint32_t)precision << 1) | (max_iter > 0 ? 1u : 0u);
+    return k;
+}
+}  // namespace
+
+subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, int32_t R,
+                        float *C, int32_t *labels, int32_t max_iter, double tol,
+                        int32_t precision, int32_t form, int32_t *iters, double *sse,
+                        int init_mode, unsigned long long *rechecks_acc) {
+    const LloydSched def = kCandidates[0];
+    if (form != SUBKM_FORM_BATCHED || max_iter <= 0 || (!ctx->tune_on && ctx->tune.empty()))
+        return lloyd_run(ctx, P, runs, R, C, labels, max_iter, tol, precision, form, iters, sse,
+                         init_mode, rechecks_acc, def);
+    const TuneKey key = shape_key(runs, R, precision, max_iter);
+    auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end())
+        return lloyd_run(ctx, P, runs, R, C, labels, max_iter, tol, precision, form, iters, sse,
+                         init_mode, rechecks_acc, it->second.sched);
+    if (!ctx->tune_on)
+        return lloyd_run(ctx, P, runs, R, C, labels, max_iter, tol, precision, form, iters, sse,
+                         init_mode, rechecks_acc, def);
+    hipStream_t s = ctx->stream;
+    // the caller's starting centers, restored before every candidate
+    size_t cfloats = 0;
+    for (int r = 0; r < R; ++r)
+        cfloats = std::max<size_t>(cfloats, (size_t)runs[r].c_off + (size_t)runs[r].k * runs[r].d);
+    float *saved = nullptr;
+    if (init_mode == 0) {
+        saved = (float *)ctx_scratch(ctx, SC_TUNE, cfloats * sizeof(float));
+        if (!saved) return SUBKM_ENOMEM;
+        SUBKM_HIP(ctx, hipMemcpyAsync(saved, C, cfloats * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    TuneEntry best{def, 1e300};
+    for (const LloydSched &sc : kCandidates) {
+        if (saved)
+            SUBKM_HIP(ctx, hipMemcpyAsync(C, saved, cfloats * sizeof(float), hipMemcpyDeviceToDevice, s));
+        SUBKM_HIP(ctx, hipEventRecord(ctx->ev[6], s));
+        SUBKM_TRY(lloyd_run(ctx, P, runs, R, C, labels, max_iter, tol, precision, form, iters, sse,
+                            init_mode, nullptr, sc));
+        SUBKM_HIP(ctx, hipEventRecord(ctx->ev[7], s));
+        SUBKM_HIP(ctx, hipEventSynchronize(ctx->ev[7]));
+        float ms = 0.0f;
+        SUBKM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]));
+        if (ms < best.ms) best = TuneEntry{sc, (double)ms};
+    }
+    ctx->tune[key] = best;
+    if (saved) SUBKM_HIP(ctx, hipMemcpyAsync(C, saved, cfloats * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return lloyd_run(ctx, P, runs, R, C, labels, max_iter, tol, precision, form, iters, sse, init_mode,
+                     rechecks_acc, best.sched);
 }
 
 // Upper bound of the scratch one lloyd_impl call requests per slot (for

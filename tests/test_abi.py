@@ -65,6 +65,10 @@ def test_null_context_is_einval(lib):
     assert lib.subkm_subcluster_unequal(None, None, 1, 1, 1, 0, None, None, None, None) == 1
     assert lib.subkm_cluster(None, None, 1, 1, 1, 1, 1, 1, 0.0, None, None, None, None, None) == 1
     assert lib.subkm_synchronize(None) == 1
+    assert lib.subkm_tune_enable(None, 1) == 1
+    assert lib.subkm_tune_count(None, None) == 1
+    assert lib.subkm_tune_save(None, b"x") == 1
+    assert lib.subkm_tune_load(None, b"x") == 1
     lib.subkm_destroy(None)  # no-op
 
 
