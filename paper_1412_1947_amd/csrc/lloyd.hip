@@ -696,8 +696,7 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
                                                 const DevRun *__restrict__ runs,
                                                 const Item *__restrict__ items, int item_base,
                                                 const float *__restrict__ C, int32_t *labels,
-                                                RunState *rstate, double *objpart, int last_pass,
-                                                int32_t *cnt) {
+                                                RunState *rstate, double *objpart, int last_pass) {
     __shared__ float sC[kLdsFloats];
     __shared__ int32_t s_list[kAT];
     __shared__ int32_t s_newlab[kAT];
@@ -744,7 +743,6 @@ __global__ __launch_bounds__(kAT) void k_assign(const float *__restrict__ P,
         if (want_obj) obj = dist64(xg, Cr + (int64_t)i1 * d, d);
     }
     // an update follows: count the points for their centers
-    if (cnt && !last_pass && ph == PH_ITER) wave_count_add(cnt + R.cnt_off, valid, i1, label_bits(k));
     if (threadIdx.x == 0 && nl) atomicAdd(&rstate[itm.run].rechecks, (unsigned long long)nl);
     if (want_obj) {
         const double tot = block_sum_det(obj, s_red);
@@ -765,7 +763,7 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
                                                     const float *__restrict__ C, int32_t *labels,
                                                     RunState *rstate, double *objpart,
                                                     const uint32_t *__restrict__ boxes,
-                                                    int last_pass, int32_t *cnt) {
+                                                    int last_pass) {
     constexpr int KQ = D / 4;
     constexpr int ldc = (kChunkF / D) < 1040 ? (kChunkF / D) : 1040;  // pitch of a staged chunk
     constexpr int kc = ((ldc - 16) / 16) * 16;                         // centers per chunk
@@ -918,7 +916,6 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
         labels[R.lab_off + i] = lab;
         if (want_obj) obj = dist64(xg, Cr + (int64_t)lab * D, D);
     }
-    if (cnt && !last_pass && ph == PH_ITER) wave_count_add(cnt + R.cnt_off, valid, lab, label_bits(k));
     if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
     if (want_obj) {
         const double tot = block_sum_det(obj, s_red);
@@ -1080,10 +1077,10 @@ subkm_status launch_assign_acc(subkm_ctx *ctx, bool mf, int nitems, int item_bas
 template <int D>
 subkm_status launch_assign(subkm_ctx *ctx, int nitems, int item_base, const float *P,
                            const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                           RunState *rs, double *objpart, int last_pass, int32_t *cnt) {
+                           RunState *rs, double *objpart, int last_pass) {
     ProfScope ps(ctx, PK_ASSIGN);
     hipLaunchKernelGGL(k_assign<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
-                       item_base, C, labels, rs, objpart, last_pass, cnt);
+                       item_base, C, labels, rs, objpart, last_pass);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
@@ -1150,27 +1147,26 @@ template <int D>
 subkm_status launch_assign_big(subkm_ctx *ctx, int nitems, int item_base, const float *P,
                                const DevRun *runs, const Item *items, const float *C,
                                int32_t *labels, RunState *rs, double *objpart,
-                               const uint32_t *boxes, int last_pass, int32_t *cnt) {
+                               const uint32_t *boxes, int last_pass) {
     if constexpr (kHasMF<D>) {
         ProfScope ps(ctx, PK_ASSIGN);
         hipLaunchKernelGGL(k_assign_big<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
-                           item_base, C, labels, rs, objpart, boxes, last_pass, cnt);
+                           item_base, C, labels, rs, objpart, boxes, last_pass);
         SUBKM_LAUNCHED(ctx);
         return SUBKM_OK;
     } else {
         return launch_assign<D>(ctx, nitems, item_base, P, runs, items, C, labels, rs, objpart,
-                                last_pass, cnt);
+                                last_pass);
     }
 }
 
 // assignment of runs beyond the LDS budget: matrix cores when d allows
 subkm_status assign_big_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
                           const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                          RunState *rs, double *objpart, const uint32_t *boxes, int last_pass,
-                          int32_t *cnt) {
+                          RunState *rs, double *objpart, const uint32_t *boxes, int last_pass) {
     if (nitems <= 0) return SUBKM_OK;
     SUBKM_DISPATCH_D(d, launch_assign_big, ctx, nitems, item_base, P, runs, items, C, labels, rs,
-                     objpart, boxes, last_pass, cnt);
+                     objpart, boxes, last_pass);
 }
 
 subkm_status persist_d(subkm_ctx *ctx, int d, bool mf, int blocks, const float *P,
@@ -1499,11 +1495,9 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
             const int S = (int)ceil_div(D0.d, 32);
             SUBKM_TRY(wide_split_prep(ctx, r0, r1 - r0, kt, S, d_runs, C, d_box, d_frags, d_cn, d_rs));
             return wide_assign_split(ctx, S, i0, ni, P, d_runs, d_items, C, d_frags, d_cn, labels, d_rs,
-                                     d_obj, d_box, last, nullptr);
+                                     d_obj, d_box, last);
         }
-        // the update counts the labels itself (k_wcount)
-        return assign_big_d(ctx, D0.d, ni, i0, P, d_runs, d_items, C, labels, d_rs, d_obj, d_box, last,
-                            nullptr);
+        return assign_big_d(ctx, D0.d, ni, i0, P, d_runs, d_items, C, labels, d_rs, d_obj, d_box, last);
     };
     // one update for runs [r0, r1), all on-chip or all wide
     auto update_seg = [&](int r0, int r1) -> subkm_status {

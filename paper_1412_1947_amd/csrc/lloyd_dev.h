@@ -192,7 +192,7 @@ subkm_status wide_assign_split(subkm_ctx *ctx, int S, int i0, int ni, const floa
                                const DevRun *runs, const Item *items, const float *C,
                                const uint4 *frags, const float *cnorm, int32_t *labels,
                                RunState *rs, double *objpart, const uint32_t *boxes,
-                               int last_pass, int32_t *cnt);
+                               int last_pass);
 
 // Exact center update of the wide runs from their labels (counted per
 // center by the assignment): starts, points ordered by label, then

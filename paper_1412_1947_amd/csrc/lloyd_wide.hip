@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kAT, 2) void k_assign_split(
     const float *__restrict__ P, const DevRun *__restrict__ runs, const Item *__restrict__ items,
     int item_base, const float *__restrict__ C, const uint4 *__restrict__ frags,
     const float *__restrict__ cnorm, int32_t *labels, RunState *rstate, double *objpart,
-    const uint32_t *__restrict__ boxes, int last_pass, int32_t *cnt) {
+    const uint32_t *__restrict__ boxes, int last_pass) {
     __shared__ int32_t s_c1[kAT], s_c2[kAT], s_st[kAT], s_lab[kAT];
     __shared__ float s_thr[kAT];
     __shared__ int32_t s_pool[kAT];
@@ -543,8 +543,6 @@ __global__ __launch_bounds__(kAT, 2) void k_assign_split(
         labels[R.lab_off + i] = lab;
         if (want_obj && !have_obj) obj = dist64(xg, Cr + (int64_t)lab * d, d);
     }
-    // an update follows: count the points for their centers
-    if (cnt && !last_pass && ph == PH_ITER) wave_count_add(cnt + R.cnt_off, valid, lab, label_bits(k));
     const unsigned long long nre = __popcll(__ballot(valid && st != ST_CERTAIN));
     if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
     if (want_obj) {
@@ -921,9 +919,9 @@ template <int S>
 subkm_status launch_split(subkm_ctx *ctx, int i0, int ni, const float *P, const DevRun *runs,
                           const Item *items, const float *C, const uint4 *frags,
                           const float *cnorm, int32_t *labels, RunState *rs, double *objpart,
-                          const uint32_t *boxes, int last_pass, int32_t *cnt) {
+                          const uint32_t *boxes, int last_pass) {
     hipLaunchKernelGGL(k_assign_split<S>, dim3(ni), dim3(kAT), 0, ctx->stream, P, runs, items, i0, C,
-                       frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
+                       frags, cnorm, labels, rs, objpart, boxes, last_pass);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
@@ -948,14 +946,14 @@ subkm_status wide_assign_split(subkm_ctx *ctx, int S, int i0, int ni, const floa
                                const DevRun *runs, const Item *items, const float *C,
                                const uint4 *frags, const float *cnorm, int32_t *labels,
                                RunState *rs, double *objpart, const uint32_t *boxes,
-                               int last_pass, int32_t *cnt) {
+                               int last_pass) {
     if (ni <= 0) return SUBKM_OK;
     ProfScope ps(ctx, PK_ASSIGN);
     switch (S) {
-        case 1: return launch_split<1>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
-        case 2: return launch_split<2>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
-        case 3: return launch_split<3>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
-        case 4: return launch_split<4>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass, cnt);
+        case 1: return launch_split<1>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
+        case 2: return launch_split<2>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
+        case 3: return launch_split<3>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
+        case 4: return launch_split<4>(ctx, i0, ni, P, runs, items, C, frags, cnorm, labels, rs, objpart, boxes, last_pass);
         default: return set_err(ctx, SUBKM_EINVAL, "split path: %d attribute steps", S);
     }
 }
