@@ -51,22 +51,37 @@ struct SelState {
     uint32_t thr_pos;
     uint32_t fallback;  // rounds that needed the slow exact path
     uint32_t ncand;     // length of the flat candidate list
-    uint32_t pad;
+    uint32_t vshift;    // low float bits the v-map drops this round
     double thr_key;
 };
 
 // Monotone non-decreasing map of a non-negative key to [0, 2^24): float32
-// rounding (monotone), its bit pattern without the 4 lowest bits, offset so
-// that the largest possible key lands in the top bin, clamped at both ends.
-__device__ __forceinline__ uint32_t vmap(double key, uint32_t base) {
-    uint32_t u = __float_as_uint((float)key) >> 4;
+// rounding (monotone), its bit pattern without the `sh` lowest bits, offset by
+// `base`, clamped at both ends.  Any base and shift give an exact selection;
+// they only decide how many keys share the boundary bins.
+__device__ __forceinline__ uint32_t vmap(double key, uint32_t base, uint32_t sh) {
+    uint32_t u = __float_as_uint((float)key) >> sh;
     uint32_t v = u > base ? u - base : 0u;
     return v > kVMax ? kVMax : v;
 }
 
-__device__ __forceinline__ uint32_t vbase_of(double bound) {
-    uint32_t top = __float_as_uint((float)bound) >> 4;
-    return top > kVMax ? top - kVMax : 0u;
+// The round's map.  Without a previous threshold: 4 bits dropped (the 2^24
+// values span 32 binades) and the largest possible key in the top bin.
+// Otherwise the threshold moves little from one round to the next, so the map
+// is centred on the previous one with 2 bits dropped (8 binades, a quarter of
+// them below it): a boundary bin then holds about a quarter of the keys it
+// would hold under the bound-based map.
+__device__ __forceinline__ void vmap_params(double bound, double prev_thr, bool have_prev,
+                                            uint32_t *base, uint32_t *sh) {
+    if (have_prev && prev_thr > 0.0) {
+        const uint32_t c = __float_as_uint((float)prev_thr) >> 2;
+        *sh = 2;
+        *base = c > kVMax / 4 ? c - kVMax / 4 : 0u;
+    } else {
+        const uint32_t top = __float_as_uint((float)bound) >> 4;
+        *sh = 4;
+        *base = top > kVMax ? top - kVMax : 0u;
+    }
 }
 
 __device__ __forceinline__ bool pair_le(double ka, uint32_t pa, double kb, uint32_t pb) {
@@ -154,22 +169,38 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
                                              const uint32_t *__restrict__ Lcur, uint32_t *Lnext,
                                              const float *__restrict__ colmax,
                                              double *__restrict__ keys, uint32_t *hist1,
-                                             SelState *st, float *landmarks_t, int vec4) {
+                                             SelState *st, float *landmarks_t, int vec4,
+                                             int have_prev) {
     extern __shared__ float sL[];  // d floats
     __shared__ uint32_t h[kBins];
-    __shared__ uint32_t s_base;
+    __shared__ double s_term[kT];  // bound terms of the first kT attributes
+    __shared__ uint32_t s_base, s_sh;
     for (int i = threadIdx.x; i < kBins; i += kT) h[i] = 0;
-    for (int j = threadIdx.x; j < d; j += kT) sL[j] = Lcur ? ordered_float(Lcur[j]) : L[j];
+    for (int j = threadIdx.x; j < d; j += kT) {
+        const float l = Lcur ? ordered_float(Lcur[j]) : L[j];
+        sL[j] = l;
+        if (j < kT) s_term[j] = key_term<M>((double)colmax[j] - (double)l);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        // upper bound of any key of this round: sum_j term(max_j - L_j)
+        // upper bound of any key of this round: sum_j term(max_j - L_j),
+        // added left to right like the keys (the terms were formed in
+        // parallel above)
         double b = 0.0;
         for (int j = 0; j < d; ++j) {
-            double q = (double)colmax[j] - (double)sL[j];
-            b = b + key_term<M>(q);
+            const double t = j < kT ? s_term[j] : key_term<M>((double)colmax[j] - (double)sL[j]);
+            b = b + t;
         }
-        s_base = vbase_of(b);
-        if (blockIdx.x == 0) st->base = s_base;
+        // (every block forms the same map; the previous round's threshold is
+        // read before any block of this round can change it)
+        uint32_t vb, vs;
+        vmap_params(b, have_prev ? st->thr_key : 0.0, have_prev != 0, &vb, &vs);
+        s_base = vb;
+        s_sh = vs;
+        if (blockIdx.x == 0) {
+            st->base = vb;
+            st->vshift = vs;
+        }
     }
     __syncthreads();
     if (blockIdx.x == 0)
@@ -177,7 +208,7 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
             if (landmarks_t) landmarks_t[j] = sL[j];
             if (Lnext) Lnext[j] = 0xFFFFFFFFu;  // the round's compaction folds the next landmark here
         }
-    const uint32_t base = s_base;
+    const uint32_t base = s_base, vsh = s_sh;
     for (uint32_t p = blockIdx.x * kT + threadIdx.x; p < nrem; p += gridDim.x * kT) {
         const float *row = S + (int64_t)rem[p] * d;
         double key = 0.0;
@@ -198,7 +229,7 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
             }
         }
         keys[p] = key;
-        atomicAdd(&h[vmap(key, base) >> 12], 1u);
+        atomicAdd(&h[vmap(key, base, vsh) >> 12], 1u);
     }
     __syncthreads();
     uint32_t *rep = hist1 + (blockIdx.x % kRep) * kBins;
@@ -238,7 +269,7 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
     for (int i = threadIdx.x; i < kBins; i += kT) h[i] = 0;
     if (threadIdx.x == 0) s_nc = 0;
     __syncthreads();
-    const uint32_t astar = st->astar, base = st->base;
+    const uint32_t astar = st->astar, base = st->base, vsh = st->vshift;
     const int lane = threadIdx.x & 63;
     uint32_t below = 0;
     const uint32_t p0 = blockIdx.x * kBS;
@@ -254,7 +285,7 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
         const uint32_t p = p0 + u * kT + threadIdx.x;
         const bool in = p < nrem;
         const double k = kb[u];
-        const uint32_t v = in ? vmap(k, base) : 0u;
+        const uint32_t v = in ? vmap(k, base, vsh) : 0u;
         const uint32_t a = v >> 12;
         below += (in && a < astar) ? 1u : 0u;
         const bool c = in && a == astar;
@@ -301,7 +332,7 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
 // whose v equals vstar, when there are too many to rank in LDS: a
 // most-significant-digit radix select over the 96-bit pair, 8 bits a pass.
 __device__ void slow_select(const double *ckey, const uint32_t *cpos, uint32_t ncand,
-                            uint32_t vstar, uint32_t base, uint32_t need,
+                            uint32_t vstar, uint32_t base, uint32_t vsh, uint32_t need,
                             uint32_t *hist256, uint32_t *sh, double *thr_key, uint32_t *thr_pos) {
     uint64_t kpre = 0;
     uint32_t ppre = 0;
@@ -311,7 +342,7 @@ __device__ void slow_select(const double *ckey, const uint32_t *cpos, uint32_t n
         {
             for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
                 const double k = ckey[c];
-                if (vmap(k, base) != vstar) continue;
+                if (vmap(k, base, vsh) != vstar) continue;
                 const uint64_t kb = (uint64_t)__double_as_longlong(k);
                 const uint32_t p = cpos[c];
                 bool match;
@@ -364,7 +395,7 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
     __shared__ uint32_t rp[kRankCap];
     __shared__ uint32_t h256[256];
     __shared__ uint32_t csel[kSegCap];
-    const uint32_t astar = st->astar, base = st->base;
+    const uint32_t astar = st->astar, base = st->base, vsh = st->vshift;
     const uint32_t need1 = need - st->below1;
     const uint32_t ncand = st->ncand;
     const bool lds_counts = nb <= kSegCap;
@@ -396,7 +427,7 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
         for (int u = 0; u < kBatch; ++u) {
             const uint32_t c = c0 + u * kST + threadIdx.x;
             if (c >= ncand) continue;
-            const uint32_t v = vmap(kk[u], base);
+            const uint32_t v = vmap(kk[u], base, vsh);
             if (v < vstar) {
                 count_sel(pp[u]);
             } else if (v == vstar) {
@@ -426,12 +457,12 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
         for (uint32_t i = threadIdx.x; i < cnt2; i += kST)
             if (pair_le(rk[i], rp[i], thr_key, thr_pos)) count_sel(rp[i]);
     } else {
-        slow_select(ckey, cpos, ncand, vstar, base, need2, h256, sh, &thr_key, &thr_pos);
+        slow_select(ckey, cpos, ncand, vstar, base, vsh, need2, h256, sh, &thr_key, &thr_pos);
         if (threadIdx.x == 0) st->fallback += 1;
         for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
             const double k = ckey[c];
             const uint32_t pc = cpos[c];
-            if (vmap(k, base) == vstar && pair_le(k, pc, thr_key, thr_pos)) count_sel(pc);
+            if (vmap(k, base, vsh) == vstar && pair_le(k, pc, thr_key, thr_pos)) count_sel(pc);
         }
     }
     if (!lds_counts) __threadfence_block();
@@ -620,6 +651,144 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
     }
 }
 
+// The same compaction for rows of d = W * DQ attributes with DQ dividing kT
+// (a thread keeps one attribute group j for all its vectors).  The rows a
+// block touches are its own span of positions whatever the selection decides,
+// so the row index of every vector is read straight from the remaining list
+// and every row is requested before the keys are compared and scanned; the
+// selection then only decides where each row goes.  Every load address is
+// clamped into the block's span, so the loads are unconditional and go out
+// together: two dependent memory round trips per block instead of one per
+// key, index and row batch.  Results are those of k_scatter.
+template <int W, int DQ>
+__global__ __launch_bounds__(kT) void k_scatter_fast(
+    const float *__restrict__ S, const int32_t *__restrict__ rem,
+    const double *__restrict__ keys, uint32_t nrem, uint32_t need,
+    const SelState *__restrict__ st, const uint32_t *__restrict__ blockoff, int all_sel,
+    int track_min, float *__restrict__ P, int32_t *__restrict__ perm, int64_t off_t,
+    int32_t *__restrict__ rem_next, uint32_t *__restrict__ Lnext) {
+    typedef typename VecT<W>::type V;
+    constexpr int D = W * DQ;
+    constexpr int per = kBS / kT;   // positions per thread in the selection
+    constexpr int RS = kT / DQ;     // rows per sweep of the block
+    constexpr int NV = kBS / RS;    // row vectors per thread
+    static_assert(kT % DQ == 0 && kBS % RS == 0, "attribute groups must tile the block");
+    __shared__ int32_t s_dst[kBS];  // >= 0: P row; < 0: -(1 + slot) in rem_next
+    __shared__ uint32_t tmp[kT / 64];
+    __shared__ uint32_t s_cmin[D];
+    const uint32_t p0 = blockIdx.x * kBS;
+    const uint32_t cnt = min(kBS, nrem - p0);
+    const uint32_t last = p0 + cnt - 1;
+    const int j = threadIdx.x % DQ;
+    const uint32_t r0 = threadIdx.x / DQ;
+    int32_t ridx[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const uint32_t p = min(p0 + r0 + u * RS, last);
+        ridx[u] = rem ? rem[p] : (int32_t)p;
+    }
+    double kq[per];
+    int32_t iq[per];
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+        const uint32_t p = min(p0 + threadIdx.x * per + q, last);
+        kq[q] = all_sel ? 0.0 : keys[p];
+        iq[q] = rem ? rem[p] : (int32_t)p;
+    }
+    double thr_key = 0.0;
+    uint32_t thr_pos = 0, sel_base = p0;
+    if (!all_sel) {
+        thr_key = st->thr_key;
+        thr_pos = st->thr_pos;
+        sel_base = blockoff[blockIdx.x];
+    }
+    V v[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) v[u] = ((const V *)(S + (int64_t)ridx[u] * D))[j];
+
+    bool sel[per];
+    uint32_t nsel = 0;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+        const uint32_t lp = threadIdx.x * per + q;
+        sel[q] = lp < cnt && (all_sel || pair_le(kq[q], p0 + lp, thr_key, thr_pos));
+        nsel += sel[q] ? 1u : 0u;
+    }
+    uint32_t tot;
+    const uint32_t pre = block_scan<kT>(nsel, tmp, &tot);
+    const uint32_t stay_base = p0 - sel_base;
+    uint32_t si = pre, ti = threadIdx.x * per - pre;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+        const uint32_t lp = threadIdx.x * per + q;
+        if (lp < cnt) {
+            // the guards only matter if the selection counts were inconsistent
+            if (sel[q]) {
+                const uint32_t row = sel_base + si++;
+                const bool ok = row < need;
+                s_dst[lp] = ok ? (int32_t)row : INT32_MIN;
+                if (ok) perm[off_t + row] = iq[q];
+            } else {
+                const uint32_t slot = stay_base + ti++;
+                const bool ok = slot < nrem - need;
+                s_dst[lp] = ok ? -1 - (int32_t)slot : INT32_MIN;
+                if (ok) rem_next[slot] = iq[q];
+            }
+        }
+    }
+    if (track_min && threadIdx.x < D) s_cmin[threadIdx.x] = 0xFFFFFFFFu;
+    __syncthreads();
+    uint32_t mymin[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) mymin[c] = 0xFFFFFFFFu;
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const uint32_t r = r0 + u * RS;
+        if (r < cnt) {
+            const int32_t dst = s_dst[r];
+            if (dst >= 0) {
+                ((V *)(P + (off_t + dst) * D))[j] = v[u];
+            } else if (dst != INT32_MIN) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) mymin[c] = min(mymin[c], ordered_bits(vget(v[u], c)));
+            }
+        }
+    }
+    if (track_min) {
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+            if (mymin[c] != 0xFFFFFFFFu) atomicMin(&s_cmin[j * W + c], mymin[c]);
+        // the next landmark: minimum over the blocks of the points that stay
+        __syncthreads();
+        if (threadIdx.x < D && s_cmin[threadIdx.x] != 0xFFFFFFFFu)
+            atomicMin(&Lnext[threadIdx.x], s_cmin[threadIdx.x]);
+    }
+}
+
+typedef void (*ScatterFastFn)(const float *, const int32_t *, const double *, uint32_t, uint32_t,
+                              const SelState *, const uint32_t *, int, int, float *, int32_t *,
+                              int64_t, int32_t *, uint32_t *);
+
+// The early-load compaction for this row width and alignment, or null.
+ScatterFastFn scatter_fast_for(int d, bool vec4) {
+    if (vec4) {
+        switch (d) {
+            case 4: return k_scatter_fast<4, 1>;
+            case 8: return k_scatter_fast<4, 2>;
+            case 16: return k_scatter_fast<4, 4>;
+            case 32: return k_scatter_fast<4, 8>;
+            default: return nullptr;
+        }
+    }
+    switch (d) {
+        case 1: return k_scatter_fast<1, 1>;
+        case 2: return k_scatter_fast<1, 2>;
+        case 4: return k_scatter_fast<1, 4>;
+        case 8: return k_scatter_fast<1, 8>;
+        default: return nullptr;
+    }
+}
+
 __global__ void k_iota(int32_t *a, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = (int32_t)i;
@@ -727,6 +896,7 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     const bool fixed = landmark_mode == 1;
     const bool vec4 = (d % 4) == 0 && ((uintptr_t)S % 16) == 0;
     const bool vec4p = vec4 && ((uintptr_t)P % 16) == 0;
+    const ScatterFastFn scat_fast = scatter_fast_for(d, vec4p);
     int32_t *cur = nullptr;  // round 0 reads the points through the identity
     int32_t *nxt = rem0;
     uint32_t nrem = (uint32_t)n;
@@ -759,7 +929,7 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
                 ProfScope pk(ctx, PK_KEYS);
                 hipLaunchKernelGGL(metric ? k_keys<1> : k_keys<0>, dim3(grid), dim3(kT), dyn_d, s,
                                    S, d, cur, nrem, L, Lcur, Lnext, colmax, keys, hist1, st, lm_t,
-                                   vec4 ? 1 : 0);
+                                   vec4 ? 1 : 0, t > 0 ? 1 : 0);
                 SUBKM_LAUNCHED(ctx);
             }
             hipLaunchKernelGGL(k_sel1, dim3(1), dim3(kST), 0, s, hist1, need, st);
@@ -780,9 +950,14 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
         }
         {
             ProfScope psc(ctx, PK_SCATTER);
-            hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kT), dyn_d, s, S, d, cur, keys, nrem, need,
-                               st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt, Lnext,
-                               vec4p ? 1 : 0);
+            if (scat_fast)
+                hipLaunchKernelGGL(scat_fast, dim3(nb), dim3(kT), 0, s, S, cur, keys, nrem, need,
+                                   st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt,
+                                   Lnext);
+            else
+                hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kT), dyn_d, s, S, d, cur, keys, nrem,
+                                   need, st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N,
+                                   nxt, Lnext, vec4p ? 1 : 0);
             SUBKM_LAUNCHED(ctx);
         }
         nrem -= need;

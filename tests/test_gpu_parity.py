@@ -94,6 +94,49 @@ def test_subcluster_shapes(km, oracle, n, d, N):
     check_subcluster(km, oracle, S, N)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 8, 12, 16, 32, 33])
+@pytest.mark.parametrize("aligned", [True, False])
+def test_subcluster_row_widths(km, oracle, d, aligned):
+    # the compaction has a specialised form per row width and alignment
+    # (float4 rows for d = 4, 8, 16, 32 on 16-byte boundaries, single words
+    # for d = 1, 2, 4, 8 otherwise) and a general one; several blocks of
+    # 2048 positions, a ragged last block, the last round taking everything
+    n, N = 9001, 1100
+    rng = np.random.default_rng(70 + d)
+    X = rng.standard_normal((n, d)).astype(np.float32) + rng.integers(0, 4, (n, 1)).astype(np.float32)
+    S, _, _ = oracle.scale(X)
+    buf = torch.zeros(n * d + 1, dtype=torch.float32, device="cuda:0")
+    Sd = buf[(0 if aligned else 1):][:n * d].view(n, d)
+    Sd.copy_(dev(S))
+    assert (Sd.data_ptr() % 16 == 0) == aligned
+    for mode in (0, 1):
+        P, perm, offs, lm = km.subcluster(Sd, N, landmark_mode=mode, landmarks=True)
+        permr, offr, lmr = oracle.subcluster(S, N, fixed_landmark=bool(mode))
+        perm = host(perm)
+        assert np.array_equal(host(offs), offr)
+        assert np.array_equal(host(lm), lmr)
+        assert np.array_equal(perm, permr)
+        assert np.array_equal(host(P), S[perm])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_subcluster_threshold_jumps(km, oracle, mode):
+    # the selection histogram of a round is centred on the previous round's
+    # threshold; thresholds that jump by many binades from one round to the
+    # next (up: a tight cluster at the corner, then a wide cloud; down: a
+    # sparse cloud, then near-duplicates) land in its clamped end bins, where
+    # the exact path must still hold
+    rng = np.random.default_rng(44)
+    tight = rng.normal(0.0, 1e-5, (3000, 3))
+    wide = rng.uniform(0.5, 3.0, (4000, 3))
+    S = np.concatenate([wide[:2000], tight, wide[2000:]]).astype(np.float32)
+    check_subcluster(km, oracle, S, 1000, mode)
+    sparse = rng.uniform(0.0, 1.0, (2500, 4))
+    dup = np.repeat(rng.uniform(0.9, 0.9001, (30, 4)), 100, axis=0) + rng.normal(0, 1e-7, (3000, 4))
+    S2 = np.concatenate([dup[:1500], sparse, dup[1500:]]).astype(np.float32)
+    check_subcluster(km, oracle, S2, 700, mode)
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_subcluster_ties_and_duplicates(km, oracle, mode):
     rng = np.random.default_rng(3)
