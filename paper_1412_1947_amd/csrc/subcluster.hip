@@ -88,6 +88,23 @@ __device__ __forceinline__ bool pair_le(double ka, uint32_t pa, double kb, uint3
     return ka < kb || (ka == kb && pa <= pb);
 }
 
+// Rows as float4 vectors (W = 4) or single floats (W = 1).
+template <int W>
+struct VecT;
+template <>
+struct VecT<1> {
+    typedef float type;
+};
+template <>
+struct VecT<4> {
+    typedef float4 type;
+};
+
+__device__ __forceinline__ float vget(const float &v, int) { return v; }
+__device__ __forceinline__ float vget(const float4 &v, int c) {
+    return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+}
+
 // Exclusive scan of one value per thread over an NT-thread block.  Returns
 // the prefix; *total receives the block sum.  `tmp` holds NT/64 words.
 template <int NT>
@@ -235,6 +252,128 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
     uint32_t *rep = hist1 + (blockIdx.x % kRep) * kBins;
     for (int i = threadIdx.x; i < kBins; i += kT)
         if (h[i]) atomicAdd(&rep[i], h[i]);
+}
+
+// The same keys for rows of a compile-time width D (float4 vectors when V4),
+// PP points per thread at the grid stride.  The index and the whole row of
+// every point of the thread are requested before the landmark and the map of
+// the round are set up (those wait on their own loads and two barriers), so
+// a thread makes two dependent memory round trips in all instead of two per
+// point.  Keys and histograms are those of k_keys.
+template <int M, int D, bool V4, int PP>
+__global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
+                                                  const int32_t *__restrict__ rem, uint32_t nrem,
+                                                  const float *__restrict__ L,
+                                                  const uint32_t *__restrict__ Lcur,
+                                                  uint32_t *Lnext, const float *__restrict__ colmax,
+                                                  double *__restrict__ keys, uint32_t *hist1,
+                                                  SelState *st, float *landmarks_t,
+                                                  int have_prev) {
+    constexpr int W = V4 ? 4 : 1;
+    constexpr int NV = D / W;  // loads per row
+    static_assert(D % W == 0 && D <= kT, "row width");
+    typedef typename VecT<W>::type V;
+    __shared__ float sL[D];
+    __shared__ double s_term[D];
+    __shared__ uint32_t h[kBins];
+    __shared__ uint32_t s_base, s_sh;
+    const uint32_t stride = gridDim.x * kT;
+    const uint32_t p0 = blockIdx.x * kT + threadIdx.x;
+    int32_t idx[PP];
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+        const uint32_t p = min(p0 + u * stride, nrem - 1);
+        idx[u] = rem ? rem[p] : (int32_t)p;
+    }
+    // unconditional loads (one pointer chosen for the whole grid, no branch)
+    const int jl = threadIdx.x < D ? (int)threadIdx.x : D - 1;
+    const uint32_t lraw = (Lcur ? Lcur : (const uint32_t *)L)[jl];
+    const float cm = colmax[jl];
+    const float lj = Lcur ? ordered_float(lraw) : __uint_as_float(lraw);
+    const double prev = have_prev ? st->thr_key : 0.0;
+    V x[PP][NV];
+#pragma unroll
+    for (int u = 0; u < PP; ++u)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) x[u][q] = ((const V *)(S + (int64_t)idx[u] * D))[q];
+
+    for (int i = threadIdx.x; i < kBins; i += kT) h[i] = 0;
+    if (threadIdx.x < D) {
+        sL[threadIdx.x] = lj;
+        s_term[threadIdx.x] = key_term<M>((double)cm - (double)lj);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // the key bound, added left to right like the keys
+        double b = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) b = b + s_term[j];
+        uint32_t vb, vs;
+        vmap_params(b, prev, have_prev != 0, &vb, &vs);
+        s_base = vb;
+        s_sh = vs;
+        if (blockIdx.x == 0) {
+            st->base = vb;
+            st->vshift = vs;
+        }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x < D) {
+        if (landmarks_t) landmarks_t[threadIdx.x] = sL[threadIdx.x];
+        if (Lnext) Lnext[threadIdx.x] = 0xFFFFFFFFu;  // the round's compaction folds the next landmark here
+    }
+    const uint32_t base = s_base, vsh = s_sh;
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+        const uint32_t p = p0 + u * stride;
+        double key = 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                const double t = (double)vget(x[u][q], c) - (double)sL[q * W + c];
+                key = key + key_term<M>(t);
+            }
+        if (p < nrem) {
+            keys[p] = key;
+            atomicAdd(&h[vmap(key, base, vsh) >> 12], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t *rep = hist1 + (blockIdx.x % kRep) * kBins;
+    for (int i = threadIdx.x; i < kBins; i += kT)
+        if (h[i]) atomicAdd(&rep[i], h[i]);
+}
+
+typedef void (*KeysFastFn)(const float *, const int32_t *, uint32_t, const float *,
+                           const uint32_t *, uint32_t *, const float *, double *, uint32_t *,
+                           SelState *, float *, int);
+
+template <int M, int D, bool V4>
+KeysFastFn keys_fast_pp(int pp) {
+    return pp >= 4 ? k_keys_fast<M, D, V4, 4> : pp == 2 ? k_keys_fast<M, D, V4, 2>
+                                                         : k_keys_fast<M, D, V4, 1>;
+}
+
+template <int M>
+KeysFastFn keys_fast_m(int d, bool vec4, int pp) {
+    switch (d) {
+        case 1: return keys_fast_pp<M, 1, false>(pp);
+        case 2: return keys_fast_pp<M, 2, false>(pp);
+        case 4: return vec4 ? keys_fast_pp<M, 4, true>(pp) : nullptr;
+        case 8: return vec4 ? keys_fast_pp<M, 8, true>(pp) : nullptr;
+        case 16: return vec4 ? keys_fast_pp<M, 16, true>(pp) : nullptr;
+        case 32: return vec4 ? keys_fast_pp<M, 32, true>(pp) : nullptr;
+        default: return nullptr;
+    }
+}
+
+// Points per thread of the early-load keys pass for nrem remaining points.
+int keys_fast_pp_of(uint32_t nrem) { return nrem > (1u << 19) ? 4 : nrem > (1u << 18) ? 2 : 1; }
+
+// The early-load keys pass for this metric, row width and alignment, or null.
+KeysFastFn keys_fast_for(int metric, int d, bool vec4, int pp) {
+    return metric ? keys_fast_m<1>(d, vec4, pp) : keys_fast_m<0>(d, vec4, pp);
 }
 
 __global__ __launch_bounds__(kST) void k_sel1(uint32_t *hist1, uint32_t need, SelState *st) {
@@ -487,21 +626,6 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
     }
 }
 
-template <int W>
-struct VecT;
-template <>
-struct VecT<1> {
-    typedef float type;
-};
-template <>
-struct VecT<4> {
-    typedef float4 type;
-};
-
-__device__ __forceinline__ float vget(const float &v, int) { return v; }
-__device__ __forceinline__ float vget(const float4 &v, int c) {
-    return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
-}
 
 template <int W>
 __device__ void scatter_rows(const float *__restrict__ S, int d, uint32_t cnt, const int32_t *s_src,
@@ -924,12 +1048,20 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
                 SUBKM_LAUNCHED(ctx);
                 cur = rem1;
             }
-            const int64_t grid = std::min<int64_t>(ceil_div(nrem, kT), 512);
             {
                 ProfScope pk(ctx, PK_KEYS);
-                hipLaunchKernelGGL(metric ? k_keys<1> : k_keys<0>, dim3(grid), dim3(kT), dyn_d, s,
-                                   S, d, cur, nrem, L, Lcur, Lnext, colmax, keys, hist1, st, lm_t,
-                                   vec4 ? 1 : 0, t > 0 ? 1 : 0);
+                const int pp = keys_fast_pp_of(nrem);
+                const KeysFastFn kf = keys_fast_for(metric, d, vec4, pp);
+                if (kf) {
+                    hipLaunchKernelGGL(kf, dim3(ceil_div(nrem, (int64_t)kT * pp)), dim3(kT), 0, s,
+                                       S, cur, nrem, L, Lcur, Lnext, colmax, keys, hist1, st, lm_t,
+                                       t > 0 ? 1 : 0);
+                } else {
+                    const int64_t grid = std::min<int64_t>(ceil_div(nrem, kT), 512);
+                    hipLaunchKernelGGL(metric ? k_keys<1> : k_keys<0>, dim3(grid), dim3(kT), dyn_d,
+                                       s, S, d, cur, nrem, L, Lcur, Lnext, colmax, keys, hist1, st,
+                                       lm_t, vec4 ? 1 : 0, t > 0 ? 1 : 0);
+                }
                 SUBKM_LAUNCHED(ctx);
             }
             hipLaunchKernelGGL(k_sel1, dim3(1), dim3(kST), 0, s, hist1, need, st);

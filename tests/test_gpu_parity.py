@@ -157,6 +157,22 @@ def test_subcluster_mid_workload(km, oracle):
     check_subcluster(km, oracle, S, job.N)
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n,d,metric", [(600_001, 2, 0), (300_000, 8, 0), (600_000, 32, 0),
+                                        (300_001, 1, 0), (600_000, 16, 1), (530_000, 4, 1)])
+def test_subcluster_many_points_per_thread(km, oracle, n, d, metric):
+    # above 2^18 and 2^19 remaining points the keys pass gives each thread 2
+    # or 4 points; every row width of that form, both measures
+    X, _ = synth.gaussian_blobs(n, d, 20, seed=n + d, sigma=0.4)
+    S, _, _ = oracle.scale(X)
+    N = 8192
+    P, perm, offs, lm = km.subcluster(dev(S), N, landmarks=True, metric=metric)
+    permr, offr, lmr = oracle.subcluster(S, N, metric=metric)
+    assert np.array_equal(host(lm), lmr)
+    assert np.array_equal(host(perm), permr)
+    assert np.array_equal(host(P), S[permr])
+
+
 # ----------------------------------------------------------------------------- Lloyd
 def shadow_steps(km, oracle, X, C0, steps, precision=0):
     """Run `steps` single GPU iterations, each checked against one oracle
