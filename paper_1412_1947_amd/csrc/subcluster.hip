@@ -260,6 +260,16 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
 // the round are set up (those wait on their own loads and two barriers), so
 // a thread makes two dependent memory round trips in all instead of two per
 // point.  Keys and histograms are those of k_keys.
+//
+// Keys carried over: the compaction of the previous round wrote the key of
+// every point that stayed, in the new order, to `keys`.  A key depends only on
+// the row and the landmark, so when the landmark of this round equals the
+// previous one bit for bit (reuse = 1; Lprev holds the previous landmark), or
+// never moves (reuse = 2, fixed landmark), those keys are this round's and no
+// row is read.  Removing a subcluster leaves the attribute-wise minimum
+// unchanged whenever no removed point held a minimum, which is most rounds.
+// Lsave (first round only) receives the landmark as ordered bits for the
+// next round's comparison.
 template <int M, int D, bool V4, int PP>
 __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
                                                   const int32_t *__restrict__ rem, uint32_t nrem,
@@ -268,7 +278,9 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
                                                   uint32_t *Lnext, const float *__restrict__ colmax,
                                                   double *__restrict__ keys, uint32_t *hist1,
                                                   SelState *st, float *landmarks_t,
-                                                  int have_prev) {
+                                                  int have_prev, int reuse,
+                                                  const uint32_t *__restrict__ Lprev,
+                                                  uint32_t *__restrict__ Lsave) {
     constexpr int W = V4 ? 4 : 1;
     constexpr int NV = D / W;  // loads per row
     static_assert(D % W == 0 && D <= kT, "row width");
@@ -279,11 +291,30 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
     __shared__ uint32_t s_base, s_sh;
     const uint32_t stride = gridDim.x * kT;
     const uint32_t p0 = blockIdx.x * kT + threadIdx.x;
-    int32_t idx[PP];
+    // the landmark test reads the same words in every thread (scalar loads):
+    // every block takes the same branch
+    bool same = reuse == 2;
+    if (reuse == 1) {
+        uint32_t diff = 0;
 #pragma unroll
-    for (int u = 0; u < PP; ++u) {
-        const uint32_t p = min(p0 + u * stride, nrem - 1);
-        idx[u] = rem ? rem[p] : (int32_t)p;
+        for (int j = 0; j < D; ++j) diff |= Lcur[j] ^ Lprev[j];
+        same = diff == 0;
+    }
+    int32_t idx[PP];
+    double kold[PP];
+    if (same) {
+#pragma unroll
+        for (int u = 0; u < PP; ++u) {
+            kold[u] = keys[min(p0 + u * stride, nrem - 1)];
+            idx[u] = 0;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < PP; ++u) {
+            const uint32_t p = min(p0 + u * stride, nrem - 1);
+            idx[u] = rem ? rem[p] : (int32_t)p;
+            kold[u] = 0.0;
+        }
     }
     // unconditional loads (one pointer chosen for the whole grid, no branch)
     const int jl = threadIdx.x < D ? (int)threadIdx.x : D - 1;
@@ -292,10 +323,12 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
     const float lj = Lcur ? ordered_float(lraw) : __uint_as_float(lraw);
     const double prev = have_prev ? st->thr_key : 0.0;
     V x[PP][NV];
+    if (!same) {
 #pragma unroll
-    for (int u = 0; u < PP; ++u)
+        for (int u = 0; u < PP; ++u)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) x[u][q] = ((const V *)(S + (int64_t)idx[u] * D))[q];
+            for (int q = 0; q < NV; ++q) x[u][q] = ((const V *)(S + (int64_t)idx[u] * D))[q];
+    }
 
     for (int i = threadIdx.x; i < kBins; i += kT) h[i] = 0;
     if (threadIdx.x < D) {
@@ -321,21 +354,25 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
     if (blockIdx.x == 0 && threadIdx.x < D) {
         if (landmarks_t) landmarks_t[threadIdx.x] = sL[threadIdx.x];
         if (Lnext) Lnext[threadIdx.x] = 0xFFFFFFFFu;  // the round's compaction folds the next landmark here
+        if (Lsave) Lsave[threadIdx.x] = ordered_bits(sL[threadIdx.x]);
     }
     const uint32_t base = s_base, vsh = s_sh;
 #pragma unroll
     for (int u = 0; u < PP; ++u) {
         const uint32_t p = p0 + u * stride;
-        double key = 0.0;
+        double key = kold[u];
+        if (!same) {
+            key = 0.0;
 #pragma unroll
-        for (int q = 0; q < NV; ++q)
+            for (int q = 0; q < NV; ++q)
 #pragma unroll
-            for (int c = 0; c < W; ++c) {
-                const double t = (double)vget(x[u][q], c) - (double)sL[q * W + c];
-                key = key + key_term<M>(t);
-            }
+                for (int c = 0; c < W; ++c) {
+                    const double t = (double)vget(x[u][q], c) - (double)sL[q * W + c];
+                    key = key + key_term<M>(t);
+                }
+        }
         if (p < nrem) {
-            keys[p] = key;
+            if (!same) keys[p] = key;
             atomicAdd(&h[vmap(key, base, vsh) >> 12], 1u);
         }
     }
@@ -347,7 +384,7 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
 
 typedef void (*KeysFastFn)(const float *, const int32_t *, uint32_t, const float *,
                            const uint32_t *, uint32_t *, const float *, double *, uint32_t *,
-                           SelState *, float *, int);
+                           SelState *, float *, int, int, const uint32_t *, uint32_t *);
 
 template <int M, int D, bool V4>
 KeysFastFn keys_fast_pp(int pp) {
@@ -790,7 +827,8 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
     const double *__restrict__ keys, uint32_t nrem, uint32_t need,
     const SelState *__restrict__ st, const uint32_t *__restrict__ blockoff, int all_sel,
     int track_min, float *__restrict__ P, int32_t *__restrict__ perm, int64_t off_t,
-    int32_t *__restrict__ rem_next, uint32_t *__restrict__ Lnext) {
+    int32_t *__restrict__ rem_next, uint32_t *__restrict__ Lnext,
+    double *__restrict__ keys_next) {
     typedef typename VecT<W>::type V;
     constexpr int D = W * DQ;
     constexpr int per = kBS / kT;   // positions per thread in the selection
@@ -856,7 +894,11 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
                 const uint32_t slot = stay_base + ti++;
                 const bool ok = slot < nrem - need;
                 s_dst[lp] = ok ? -1 - (int32_t)slot : INT32_MIN;
-                if (ok) rem_next[slot] = iq[q];
+                if (ok) {
+                    rem_next[slot] = iq[q];
+                    // the next round's keys pass may take it as is
+                    if (keys_next) keys_next[slot] = kq[q];
+                }
             }
         }
     }
@@ -891,7 +933,7 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
 
 typedef void (*ScatterFastFn)(const float *, const int32_t *, const double *, uint32_t, uint32_t,
                               const SelState *, const uint32_t *, int, int, float *, int32_t *,
-                              int64_t, int32_t *, uint32_t *);
+                              int64_t, int32_t *, uint32_t *, double *);
 
 // The early-load compaction for this row width and alignment, or null.
 ScatterFastFn scatter_fast_for(int d, bool vec4) {
@@ -956,12 +998,12 @@ void sub_requests(int64_t n, int32_t d, size_t *req) {
     auto need = [&](int slot, size_t b) { req[slot] = std::max(req[slot], b); };
     const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
     const size_t sel_words = 2 * (size_t)kRep * kBins + 3 * (size_t)nb_max + 64;
-    need(SC_KEYS, sizeof(double) * n);
+    need(SC_KEYS, 2 * sizeof(double) * n);  // this round's keys and the carried ones
     need(SC_REM0, sizeof(int32_t) * n);
     need(SC_REM1, sizeof(int32_t) * n);
     need(SC_CAND, (sizeof(double) + sizeof(uint32_t)) * n + 64);
     need(SC_SEL, 256 + sizeof(uint32_t) * sel_words);
-    need(SC_LAND, sizeof(float) * (3 * (size_t)d + 64));
+    need(SC_LAND, sizeof(float) * (4 * (size_t)d + 64));
     need(SC_COLMAX, sizeof(float) * d + 64);
     need(SC_MM_FLAG, 256);
     need(SC_MM_PART, minmax_scratch_bytes(n, d));
@@ -999,10 +1041,15 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     uint32_t *blockoff = blockcnt + nb_max;
     double *ckey = (double *)b.cand;
     uint32_t *cpos = (uint32_t *)(b.cand + sizeof(double) * n);
-    float *L = b.land;                                // first landmark (floats)
-    uint32_t *Lb[2] = {(uint32_t *)(b.land + d),       // later landmarks as ordered bits,
-                       (uint32_t *)(b.land + 2 * d)};  // round t reads Lb[t & 1]
-    double *keys = b.keys;
+    float *L = b.land;  // first landmark (floats)
+    // landmarks as ordered bits: round t >= 1 reads Lb[t % 3], folds the next
+    // one into Lb[(t + 1) % 3] and compares with the previous one in
+    // Lb[(t - 1) % 3] (round 0 saves its own there)
+    uint32_t *Lb[3] = {(uint32_t *)(b.land + d), (uint32_t *)(b.land + 2 * d),
+                       (uint32_t *)(b.land + 3 * d)};
+    // keys of round t in Kb[t & 1]; the compaction carries the keys of the
+    // points that stay into Kb[(t + 1) & 1]
+    double *Kb[2] = {b.keys, b.keys + n};
     int32_t *rem0 = b.rem0, *rem1 = b.rem1;
     const float *colmax = b.colmax;
 
@@ -1021,6 +1068,8 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     const bool vec4 = (d % 4) == 0 && ((uintptr_t)S % 16) == 0;
     const bool vec4p = vec4 && ((uintptr_t)P % 16) == 0;
     const ScatterFastFn scat_fast = scatter_fast_for(d, vec4p);
+    // keys are carried from round to round when both early-load kernels run
+    const bool carry = scat_fast && keys_fast_for(metric, d, vec4, 1);
     int32_t *cur = nullptr;  // round 0 reads the points through the identity
     int32_t *nxt = rem0;
     uint32_t nrem = (uint32_t)n;
@@ -1031,8 +1080,13 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
         const bool all = need == nrem;
         float *lm_t = landmarks ? landmarks + t * d : nullptr;
         const bool track = !all && !fixed;
-        const uint32_t *Lcur = (t == 0 || fixed) ? nullptr : Lb[t & 1];
-        uint32_t *Lnext = track ? Lb[(t + 1) & 1] : nullptr;
+        const uint32_t *Lcur = (t == 0 || fixed) ? nullptr : Lb[t % 3];
+        uint32_t *Lnext = track ? Lb[(t + 1) % 3] : nullptr;
+        double *keys = Kb[t & 1];
+        double *keys_next = carry && !all ? Kb[(t + 1) & 1] : nullptr;
+        const int reuse = (!carry || t == 0) ? 0 : fixed ? 2 : 1;
+        const uint32_t *Lprev = reuse == 1 ? Lb[(t + 2) % 3] : nullptr;
+        uint32_t *Lsave = (carry && t == 0 && !fixed) ? Lb[0] : nullptr;
         if (t < t0) {
             // rounds of earlier segments: only their host-side bookkeeping
             if (!all && !cur) cur = rem1;
@@ -1055,7 +1109,7 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
                 if (kf) {
                     hipLaunchKernelGGL(kf, dim3(ceil_div(nrem, (int64_t)kT * pp)), dim3(kT), 0, s,
                                        S, cur, nrem, L, Lcur, Lnext, colmax, keys, hist1, st, lm_t,
-                                       t > 0 ? 1 : 0);
+                                       t > 0 ? 1 : 0, reuse, Lprev, Lsave);
                 } else {
                     const int64_t grid = std::min<int64_t>(ceil_div(nrem, kT), 512);
                     hipLaunchKernelGGL(metric ? k_keys<1> : k_keys<0>, dim3(grid), dim3(kT), dyn_d,
@@ -1085,7 +1139,7 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
             if (scat_fast)
                 hipLaunchKernelGGL(scat_fast, dim3(nb), dim3(kT), 0, s, S, cur, keys, nrem, need,
                                    st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt,
-                                   Lnext);
+                                   Lnext, keys_next);
             else
                 hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kT), dyn_d, s, S, d, cur, keys, nrem,
                                    need, st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N,
