@@ -115,12 +115,16 @@ struct subkm_ctx {
     uint64_t scratch_epoch = 0;       // bumped whenever a scratch buffer moves
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     CoopGate *coop = nullptr;          // serving engine: shared gate of cooperative launches
+    static constexpr int kGraphKeyWords = 21;
+    static constexpr size_t kGraphCacheMax = 8;
     struct GraphCache {
         bool valid = false;
-        uint64_t key[16] = {};
+        uint64_t key[kGraphKeyWords] = {};
+        uint64_t stamp = 0;            // last use (least recently used is replaced)
         hipGraphExec_t exec = nullptr;
     };
-    std::vector<GraphCache> subg;      // captured subclustering segments
+    std::vector<GraphCache> subg;      // captured subclustering sequences
+    uint64_t subg_clock = 0;
     bool tune_on = false;              // tune the schedules of unseen shapes
     std::map<TuneKey, TuneEntry> tune; // tuned schedule per shape
 };

@@ -1166,20 +1166,38 @@ subkm_status subcluster_segment(subkm_ctx *ctx, const float *S, int64_t n, int32
                                 int32_t seg) {
     SubBufs b;
     SUBKM_TRY(sub_alloc(ctx, n, d, b));
-    const uint64_t key[16] = {(uint64_t)(uintptr_t)S, (uint64_t)n, (uint64_t)d, (uint64_t)N,
-                              (uint64_t)landmark_mode | ((uint64_t)metric << 8),
-                              (uint64_t)(uintptr_t)P,
-                              (uint64_t)(uintptr_t)perm, (uint64_t)(uintptr_t)offsets,
-                              (uint64_t)(uintptr_t)landmarks, (uint64_t)(uintptr_t)b.keys,
-                              (uint64_t)(uintptr_t)b.rem0 ^ ((uint64_t)(uintptr_t)b.rem1 << 1),
-                              (uint64_t)(uintptr_t)b.cand ^ ((uint64_t)(uintptr_t)b.sel << 1),
-                              (uint64_t)(uintptr_t)b.land ^ ((uint64_t)(uintptr_t)b.colmax << 1),
-                              (uint64_t)(uintptr_t)b.flag ^ ((uint64_t)(uintptr_t)ctx->scratch[SC_MM_PART].ptr << 1),
-                              (uint64_t)t0, (uint64_t)t1};
-    if ((int)ctx->subg.size() <= seg) ctx->subg.resize(seg + 1);
-    auto &g = ctx->subg[seg];
+    // every input of the captured sequence, one word each
+    const uint64_t key[subkm_ctx::kGraphKeyWords] = {
+        (uint64_t)(uintptr_t)S, (uint64_t)n, (uint64_t)d, (uint64_t)N,
+        (uint64_t)landmark_mode | ((uint64_t)metric << 8) | ((uint64_t)seg << 16),
+        (uint64_t)(uintptr_t)P, (uint64_t)(uintptr_t)perm, (uint64_t)(uintptr_t)offsets,
+        (uint64_t)(uintptr_t)landmarks, (uint64_t)(uintptr_t)b.keys, (uint64_t)(uintptr_t)b.rem0,
+        (uint64_t)(uintptr_t)b.rem1, (uint64_t)(uintptr_t)b.cand, (uint64_t)(uintptr_t)b.sel,
+        (uint64_t)(uintptr_t)b.land, (uint64_t)(uintptr_t)b.colmax, (uint64_t)(uintptr_t)b.flag,
+        (uint64_t)(uintptr_t)ctx->scratch[SC_MM_PART].ptr, (uint64_t)t0, (uint64_t)t1, 0};
+    subkm_ctx::GraphCache *gp = nullptr;
+    for (auto &e : ctx->subg)
+        if (e.valid && std::memcmp(e.key, key, sizeof key) == 0) {
+            gp = &e;
+            break;
+        }
+    if (!gp) {
+        // a free entry, else the least recently used one
+        if (ctx->subg.size() < subkm_ctx::kGraphCacheMax) {
+            ctx->subg.emplace_back();
+            gp = &ctx->subg.back();
+        } else {
+            gp = &ctx->subg[0];
+            for (auto &e : ctx->subg)
+                if (e.stamp < gp->stamp) gp = &e;
+        }
+    }
+    auto &g = *gp;
+    g.stamp = ++ctx->subg_clock;
     if (!(g.valid && std::memcmp(g.key, key, sizeof key) == 0)) {
         if (g.exec) {
+            // an earlier launch of it may still be running
+            SUBKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
             hipGraphExecDestroy(g.exec);
             g.exec = nullptr;
         }

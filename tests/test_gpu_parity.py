@@ -119,6 +119,24 @@ def test_subcluster_row_widths(km, oracle, d, aligned):
         assert np.array_equal(host(P), S[perm])
 
 
+def test_subcluster_graph_cache(km, oracle):
+    # the captured subclustering sequences are cached per configuration (8
+    # at most, least recently used replaced): ten configurations on the same
+    # buffers, cycled twice, hit and evict entries; every result must be the
+    # oracle's
+    S, _, _ = oracle.scale(synth.tiny().X)
+    Sd = dev(S)
+    Ns = [100, 150, 200, 300, 450, 512, 700, 1000, 1500, 2048]
+    refs = {N: oracle.subcluster(S, N) for N in Ns}
+    for rep in range(2):
+        for N in Ns + Ns[::-1][:3]:
+            P, perm, offs = km.subcluster(Sd, N)
+            permr, offr, _ = refs[N]
+            assert np.array_equal(host(perm), permr)
+            assert np.array_equal(host(offs), offr)
+            assert np.array_equal(host(P), S[permr])
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_subcluster_threshold_jumps(km, oracle, mode):
     # the selection histogram of a round is centred on the previous round's
