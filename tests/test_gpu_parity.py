@@ -94,13 +94,14 @@ def test_subcluster_shapes(km, oracle, n, d, N):
     check_subcluster(km, oracle, S, N)
 
 
-@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 8, 12, 16, 32, 33])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 8, 12, 16, 32, 33, 64, 128])
 @pytest.mark.parametrize("aligned", [True, False])
 def test_subcluster_row_widths(km, oracle, d, aligned):
-    # the compaction has a specialised form per row width and alignment
-    # (float4 rows for d = 4, 8, 16, 32 on 16-byte boundaries, single words
-    # for d = 1, 2, 4, 8 otherwise) and a general one; several blocks of
-    # 2048 positions, a ragged last block, the last round taking everything
+    # the keys pass and the compaction have specialised forms per row width
+    # and alignment (float4 rows for d = 4, 8, 16, 32 on 16-byte boundaries,
+    # single words for d = 1, 2, 4, 8 otherwise) and general ones (the other
+    # widths, 64 and 128 among them); several blocks of 2048 positions, a
+    # ragged last block, the last round taking everything
     n, N = 9001, 1100
     rng = np.random.default_rng(70 + d)
     X = rng.standard_normal((n, d)).astype(np.float32) + rng.integers(0, 4, (n, 1)).astype(np.float32)
