@@ -81,7 +81,8 @@ def source_hash(files):
 def measured_traffic():
     """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE, calibrated by a copy of known size), per kernel class, or {}
-    when the kernels' sources changed since the counters were taken."""
+    when the kernels' sources (or the build script with its compiler flags)
+    changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return {}
     out = {}
