@@ -468,8 +468,8 @@ def bench_ragged(subkm, synth, a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the method on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py measures one GPU only: the method runs on a single MI355X; sharding "
+              "across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
 
