@@ -307,6 +307,27 @@ def test_plain_equals_batched_and_deterministic(km, oracle):
         assert np.array_equal(ca, cc) and np.array_equal(la, lc)
 
 
+@pytest.mark.parametrize("n,k,d", [(32768, 64, 16), (12000, 64, 16), (20000, 100, 8),
+                                   (30001, 16, 4), (9000, 64, 32)])
+def test_forms_agree_on_long_runs(km, oracle, n, k, d):
+    # runs long enough to be split over many blocks of the persistent kernel
+    # (16 or more reduce-scatter their partial sums, in slices that need not
+    # divide the sums evenly); the plain form sums through global integer
+    # atomics instead, so equal bits show the exchange is exact; the batched
+    # result alone and next to short runs in the same call
+    X, _ = synth.gaussian_blobs(n, d, 2 * k, seed=n + k, sigma=0.4)
+    S = oracle.scale(X)[0]
+    a, ia, sa = run_batch(km, [S], [k], 8, 0.0, form=0)
+    b, ib, sb = run_batch(km, [S], [k], 8, 0.0, form=1)
+    assert np.array_equal(ia, ib) and np.array_equal(sa, sb)
+    assert np.array_equal(a[0][0], b[0][0]) and np.array_equal(a[0][1], b[0][1])
+    short = [oracle.scale(synth.gaussian_blobs(700, d, 5, seed=j, sigma=0.5)[0])[0] for j in range(3)]
+    c, ic, sc = run_batch(km, short + [S], [20, 20, 20, k], 8, 0.0, form=0)
+    assert np.array_equal(c[3][0], a[0][0]) and np.array_equal(c[3][1], a[0][1]) and sc[3] == sa[0]
+    # moves one at a time against the oracle (each goes through the exchange)
+    shadow_steps(km, oracle, S, S[:k], steps=2)
+
+
 # --------------------------------------------------------------------------- cluster
 def check_cluster(km, oracle, job, fixed=False):
     X = dev(job.X)
