@@ -50,7 +50,7 @@ constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path
 constexpr long long kSpinLimit = 1ll << 26;
 constexpr int kMaxG = 64;          // blocks per run in the batched form
 constexpr int kExB = 16;           // exchange loads in flight per element
-constexpr int kRsMin = 16;         // runs split over this many blocks reduce-scatter their sums
+constexpr int kRsMin = 2;          // runs split over this many blocks or more reduce-scatter their sums
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
 constexpr int64_t kHugeRun = 1 << 15; // points beyond which a run with moves takes the wide path

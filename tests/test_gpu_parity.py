@@ -311,7 +311,7 @@ def test_plain_equals_batched_and_deterministic(km, oracle):
                                    (30001, 16, 4), (9000, 64, 32)])
 def test_forms_agree_on_long_runs(km, oracle, n, k, d):
     # runs long enough to be split over many blocks of the persistent kernel
-    # (16 or more reduce-scatter their partial sums, in slices that need not
+    # (they reduce-scatter their partial sums, in slices that need not
     # divide the sums evenly); the plain form sums through global integer
     # atomics instead, so equal bits show the exchange is exact; the batched
     # result alone and next to short runs in the same call
