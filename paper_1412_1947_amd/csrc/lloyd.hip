@@ -49,8 +49,7 @@ constexpr int kMaxK = 1024;         // centers per run in the fused path
 constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path)
 constexpr long long kSpinLimit = 1ll << 26;
 constexpr int kMaxG = 64;          // blocks per run in the batched form
-constexpr int kExB = 16;           // exchange loads in flight per element
-constexpr int kRsMin = 2;          // runs split over this many blocks or more reduce-scatter their sums
+constexpr int kExB = 16;           // exchange loads in flight per thread
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
 constexpr int64_t kHugeRun = 1 << 15; // points beyond which a run with moves takes the wide path
@@ -548,8 +547,9 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
             __syncthreads();
             if (G > 1) {
                 // Publish this block's sums, wait for the run's other blocks,
-                // then add all parts in block order (exact integer sums).  The
-                // parts are written and read with agent-scope atomic stores
+                // then sum the parts (exact integer sums: any order gives the
+                // same bits), reduce-scattered as below.  The parts and
+                // their sums are written and read with agent-scope atomic stores
                 // and loads, which the hardware performs at the device's
                 // coherence point; every thread waits for its own stores to
                 // complete before the block arrives, so a block that sees
@@ -579,73 +579,52 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
                     __syncthreads();
                 };
                 const long long *base = parts + R.part_off + (int64_t)(it & 1) * G * ne;
-                if (G >= kRsMin) {
-                    // Reduce-scatter: block g sums slice g of the G parts
-                    // and publishes it; after a second arrival every block
-                    // reads the summed vector (2 ne words per block instead
-                    // of G ne).  Parts and sums alternate by iteration
-                    // parity like the parts alone: a buffer is written again
-                    // two iterations later, after every block has passed the
-                    // first arrival of the iteration in between.
-                    arrive_wait((uint32_t)G * (uint32_t)(2 * it + 1));
-                    long long *tot = parts + R.part_off + 2ll * G * ne + (int64_t)(it & 1) * ne;
-                    const int S = (ne + G - 1) / G;
-                    const int e0 = min(ne, tk.g * S), ns = min(ne, e0 + S) - e0;
-                    for (int i = threadIdx.x; i < ns; i += kAT) L.s_sum[i] = 0;
-                    __syncthreads();
-                    // (element, part) pairs element-fastest: neighbouring
-                    // threads read neighbouring words of one part
-                    const int np = ns * G;
-                    for (int p0 = 0; p0 < np; p0 += kAT * kExB) {
-                        long long v[kExB];
+                // Reduce-scatter: block g sums slice g of the G parts
+                // and publishes it; after a second arrival every block
+                // reads the summed vector (2 ne words per block instead
+                // of G ne).  Parts and sums alternate by iteration
+                // parity like the parts alone: a buffer is written again
+                // two iterations later, after every block has passed the
+                // first arrival of the iteration in between.
+                arrive_wait((uint32_t)G * (uint32_t)(2 * it + 1));
+                long long *tot = parts + R.part_off + 2ll * G * ne + (int64_t)(it & 1) * ne;
+                const int S = (ne + G - 1) / G;
+                const int e0 = min(ne, tk.g * S), ns = min(ne, e0 + S) - e0;
+                for (int i = threadIdx.x; i < ns; i += kAT) L.s_sum[i] = 0;
+                __syncthreads();
+                // (element, part) pairs element-fastest: neighbouring
+                // threads read neighbouring words of one part
+                const int np = ns * G;
+                for (int p0 = 0; p0 < np; p0 += kAT * kExB) {
+                    long long v[kExB];
 #pragma unroll
-                        for (int u = 0; u < kExB; ++u) {
-                            const int p = min(p0 + u * kAT + (int)threadIdx.x, np - 1);
-                            const int q = p / ns, e = p - q * ns;
-                            v[u] = __hip_atomic_load(&base[(int64_t)q * ne + e0 + e], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                        }
+                    for (int u = 0; u < kExB; ++u) {
+                        const int p = min(p0 + u * kAT + (int)threadIdx.x, np - 1);
+                        const int q = p / ns, e = p - q * ns;
+                        v[u] = __hip_atomic_load(&base[(int64_t)q * ne + e0 + e], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+                    }
 #pragma unroll
-                        for (int u = 0; u < kExB; ++u) {
-                            const int p = p0 + u * kAT + (int)threadIdx.x;
-                            if (p < np) {
-                                const int e = p % ns;
-                                atomicAdd((unsigned long long *)&L.s_sum[e], (unsigned long long)v[u]);
-                            }
+                    for (int u = 0; u < kExB; ++u) {
+                        const int p = p0 + u * kAT + (int)threadIdx.x;
+                        if (p < np) {
+                            const int e = p % ns;
+                            atomicAdd((unsigned long long *)&L.s_sum[e], (unsigned long long)v[u]);
                         }
                     }
-                    __syncthreads();
-                    for (int i = threadIdx.x; i < ns; i += kAT)
-                        __hip_atomic_store(&tot[e0 + i], L.s_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __syncthreads();
-                    arrive_wait((uint32_t)G * (uint32_t)(2 * it + 2));
-                    for (int e = threadIdx.x; e < ne; e += kAT) {
-                        const long long a = __hip_atomic_load(&tot[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (e < kd) L.s_sum[e] = a;
-                        else L.s_cnt[e - kd] = (unsigned int)a;
-                    }
-                    __syncthreads();
-                } else {
-                    arrive_wait((uint32_t)G * (uint32_t)(it + 1));
-                    // kExB loads of an element are issued before any is used
-                    for (int e = threadIdx.x; e < ne; e += kAT) {
-                        long long a = 0;
-                        for (int q0 = 0; q0 < G; q0 += kExB) {
-                            long long v[kExB];
-#pragma unroll
-                            for (int q = 0; q < kExB; ++q)
-                                v[q] = q0 + q < G ? __hip_atomic_load(&base[(int64_t)(q0 + q) * ne + e],
-                                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                                  : 0ll;
-#pragma unroll
-                            for (int q = 0; q < kExB; ++q) a += v[q];
-                        }
-                        if (e < kd) L.s_sum[e] = a;
-                        else L.s_cnt[e - kd] = (unsigned int)a;
-                    }
-                    __syncthreads();
                 }
+                __syncthreads();
+                for (int i = threadIdx.x; i < ns; i += kAT)
+                    __hip_atomic_store(&tot[e0 + i], L.s_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                arrive_wait((uint32_t)G * (uint32_t)(2 * it + 2));
+                for (int e = threadIdx.x; e < ne; e += kAT) {
+                    const long long a = __hip_atomic_load(&tot[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (e < kd) L.s_sum[e] = a;
+                    else L.s_cnt[e - kd] = (unsigned int)a;
+                }
+                __syncthreads();
             }
             const double shift_max = centers_from_sums<MF>(L, d, k, ldk, shift, tk.g == 0 ? Cr : nullptr);
             if constexpr (MF) center_norms<D>(L, box, k, ldk);
@@ -1421,7 +1400,7 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
                 D.part_off = part_words;
                 // exchange slots only when there is an update to exchange
                 if (G[r] > 1 && max_iter > 0)
-                    part_words += (2ll * G[r] + (G[r] >= kRsMin ? 2 : 0)) * ((int64_t)D.k * D.d + D.k);
+                    part_words += (2ll * G[r] + 2) * ((int64_t)D.k * D.d + D.k);  // parts, sums
             }
             for (int b = 0; b < blocks; ++b) {
                 for (const Task &t : pb[b]) tasks.push_back(t);
@@ -1731,7 +1710,7 @@ void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision,
             const int64_t g = max_iter > 0 ? std::min<int64_t>(kMaxG, std::max<int64_t>(1, t / 2)) : t;
             n_tasks += g;
             if (max_iter > 0 && g > 1)
-                part_words += (2 * g + (g >= kRsMin ? 2 : 0)) * ((int64_t)dr[r].k * dr[r].d + dr[r].k);
+                part_words += (2 * g + 2) * ((int64_t)dr[r].k * dr[r].d + dr[r].k);
         }
     } else {
         n_items = tiles;
