@@ -669,7 +669,7 @@ __device__ void scatter_rows(const float *__restrict__ S, int d, uint32_t cnt, c
                              const int32_t *s_dst, int track_min, float *__restrict__ P,
                              int64_t off_t, uint32_t *s_cmin) {
     typedef typename VecT<W>::type V;
-    constexpr int U = 4;
+    constexpr int U = 8;
     const uint32_t dq = (uint32_t)d / W;
     const uint32_t total = cnt * dq;
     const uint32_t dr = kT / dq, dj = kT % dq;
@@ -687,21 +687,16 @@ __device__ void scatter_rows(const float *__restrict__ S, int d, uint32_t cnt, c
         uint32_t jj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            kind[u] = 0;
-            prow[u] = 0;
+            // every load is unconditional (past the block's rows the row
+            // index is clamped to its last row, whose value is not used), so
+            // the U loads are in flight together
+            const uint32_t rc = min(r, cnt - 1);
+            const int32_t dst = s_dst[rc];
+            v[u] = ((const V *)(S + (int64_t)s_src[rc] * d))[j];
+            const bool use = e + u * kT < total && dst != INT32_MIN;
+            kind[u] = !use ? 0 : dst >= 0 ? 1 : 2;
+            prow[u] = dst;
             jj[u] = j;
-            if (e + u * kT < total) {
-                const int32_t dst = s_dst[r];
-                if (dst != INT32_MIN) {
-                    v[u] = ((const V *)(S + (int64_t)s_src[r] * d))[j];
-                    if (dst >= 0) {
-                        kind[u] = 1;
-                        prow[u] = dst;
-                    } else {
-                        kind[u] = 2;
-                    }
-                }
-            }
             r += dr;
             j += dj;
             if (j >= dq) {
@@ -757,14 +752,22 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
         thr_key = st->thr_key;
         thr_pos = st->thr_pos;
     }
-    // flags of this thread's `per` consecutive positions
+    // flags of this thread's `per` consecutive positions (unconditional
+    // loads, clamped to the block's last position)
+    double kq[per];
+    int32_t iq[per];
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+        const uint32_t pc = p0 + min(threadIdx.x * per + q, cnt - 1);
+        kq[q] = all_sel ? 0.0 : keys[pc];
+        iq[q] = rem ? rem[pc] : (int32_t)pc;
+    }
     bool sel[per];
     uint32_t nsel = 0;
 #pragma unroll
     for (int q = 0; q < per; ++q) {
         const uint32_t lp = threadIdx.x * per + q;
-        bool s = false;
-        if (lp < cnt) s = all_sel || pair_le(keys[p0 + lp], p0 + lp, thr_key, thr_pos);
+        const bool s = lp < cnt && (all_sel || pair_le(kq[q], p0 + lp, thr_key, thr_pos));
         sel[q] = s;
         nsel += s ? 1u : 0u;
     }
@@ -777,7 +780,7 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
     for (int q = 0; q < per; ++q) {
         const uint32_t lp = threadIdx.x * per + q;
         if (lp < cnt) {
-            const int32_t idx = rem ? rem[p0 + lp] : (int32_t)(p0 + lp);
+            const int32_t idx = iq[q];
             s_src[lp] = idx;
             // the guards only matter if the selection counts were inconsistent
             if (sel[q]) {
