@@ -1,19 +1,20 @@
 // Equal sized subclustering (Sec. II, Algorithm 1 steps 2, 3 and 5), applied
 // round after round to the points left over.
 //
-// One round is five launches with no host round trip (the threshold stays in
+// One round is four launches with no host round trip (the threshold stays in
 // device memory) and no inter-block synchronisation inside a kernel:
 //
 //   k_keys     binary64 key of every remaining point (its squared Euclidean or
 //              its Manhattan distance to the landmark, attributes left to
 //              right, no FMA) and a 4096-bin
 //              histogram of a monotone 24-bit image v(key) of the key, merged
-//              into 16 replicas so that no address sees many atomics;
-//   k_sel1     (one block) sums the replicas and finds the bin a* holding the
-//              N-th smallest key;
-//   k_cand     per block of 2048 positions: counts the points surely selected
-//              (bin < a*) and compacts the points of bin a* (candidates) into
-//              the block's own segment, with a histogram of their low 12 bits;
+//              into 16 replicas so that no address sees many atomics, with
+//              the counts of its 64-bin groups beside them;
+//   k_cand     per block of 2048 positions: finds the bin a* holding the N-th
+//              smallest key (group counts first, then the bins of that group),
+//              counts the points surely selected (bin < a*) and compacts the
+//              points of bin a* (candidates) into the block's own segment,
+//              with a histogram of their low 12 bits;
 //   k_sel2     (one block) finds the sub-bin, ranks the few candidates whose v
 //              equals the boundary value exactly by (key, position), which
 //              gives the threshold pair (key*, pos*), and turns the per-block
@@ -23,7 +24,8 @@
 //              the others to the next remaining list, and every block folds
 //              the attribute-wise minimum of the points it keeps into the
 //              next landmark L_{t+1} (Algorithm 1 step 2 on the points left
-//              over) with integer atomic minima on order-preserving bits.
+//              over) with integer atomic minima on order-preserving bits,
+//              and clears the level-1 histograms for the next round.
 //
 // Positions in the remaining list are in ascending original index, so the
 // index tie-break of the selection is a tie-break on positions.
@@ -40,6 +42,7 @@ constexpr int kT = 512;           // threads of the wide kernels
 constexpr int kST = 1024;         // threads of the single-block kernels
 constexpr int kBins = 4096;       // histogram bins per level
 constexpr int kRep = 16;          // histogram replicas (spread the atomics)
+constexpr int kGroups = kBins / 64;  // 64-bin groups of the level-1 bins
 constexpr uint32_t kBS = 2048;    // positions per compaction block
 constexpr int kRankCap = 2048;    // boundary candidates ranked in LDS
 constexpr uint32_t kVMax = 0xFFFFFFu;
@@ -179,6 +182,23 @@ __device__ __forceinline__ double key_term(double q) {
     return M ? fabs(q) : q * q;
 }
 
+// Add a block's histogram h to replica (block % kRep) of the level-1 bins and
+// of their 64-bin group counts (those follow the bin replicas).  With kT a
+// multiple of 64 and kBins of kT, each wave holds exactly one group per pass.
+__device__ __forceinline__ void flush_hist(const uint32_t *h, uint32_t *hist1) {
+    static_assert(kT % 64 == 0 && kBins % kT == 0, "a wave covers one group per pass");
+    const uint32_t r = blockIdx.x % kRep;
+    uint32_t *rep = hist1 + r * kBins;
+    uint32_t *grp = hist1 + kRep * kBins + r * kGroups;
+    for (int i = threadIdx.x; i < kBins; i += kT) {
+        const uint32_t c = h[i];
+        if (c) atomicAdd(&rep[i], c);
+        uint32_t g = c;
+        for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o, 64);
+        if ((threadIdx.x & 63) == 0 && g) atomicAdd(&grp[i >> 6], g);
+    }
+}
+
 template <int M>
 __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
                                              const int32_t *__restrict__ rem, uint32_t nrem,
@@ -217,6 +237,7 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
         if (blockIdx.x == 0) {
             st->base = vb;
             st->vshift = vs;
+            st->ncand = 0;  // the candidate pass appends to it
         }
     }
     __syncthreads();
@@ -249,9 +270,7 @@ __global__ __launch_bounds__(kT) void k_keys(const float *__restrict__ S, int d,
         atomicAdd(&h[vmap(key, base, vsh) >> 12], 1u);
     }
     __syncthreads();
-    uint32_t *rep = hist1 + (blockIdx.x % kRep) * kBins;
-    for (int i = threadIdx.x; i < kBins; i += kT)
-        if (h[i]) atomicAdd(&rep[i], h[i]);
+    flush_hist(h, hist1);
 }
 
 // The same keys for rows of a compile-time width D (float4 vectors when V4),
@@ -348,6 +367,7 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
         if (blockIdx.x == 0) {
             st->base = vb;
             st->vshift = vs;
+            st->ncand = 0;  // the candidate pass appends to it
         }
     }
     __syncthreads();
@@ -377,9 +397,7 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
         }
     }
     __syncthreads();
-    uint32_t *rep = hist1 + (blockIdx.x % kRep) * kBins;
-    for (int i = threadIdx.x; i < kBins; i += kT)
-        if (h[i]) atomicAdd(&rep[i], h[i]);
+    flush_hist(h, hist1);
 }
 
 typedef void (*KeysFastFn)(const float *, const int32_t *, uint32_t, const float *,
@@ -413,39 +431,61 @@ KeysFastFn keys_fast_for(int metric, int d, bool vec4, int pp) {
     return metric ? keys_fast_m<1>(d, vec4, pp) : keys_fast_m<0>(d, vec4, pp);
 }
 
-__global__ __launch_bounds__(kST) void k_sel1(uint32_t *hist1, uint32_t need, SelState *st) {
-    __shared__ uint32_t sh[4], tmp[kST / 64];
-    uint32_t a, below, cnt;
-    // (k_cand zeroes the replicas, spread over its blocks)
-    merge_find_bin<kRep, false>(hist1, need, sh, tmp, &a, &below, &cnt);
-    if (threadIdx.x == 0) {
-        st->astar = a;
-        st->below1 = below;
-        st->cnt1 = cnt;
-        st->ncand = 0;
+// The level-1 bin a* holding the need-th smallest v (1-based) and the counts
+// below and in it, from the kRep replicas written by the keys pass: first the
+// 64-bin group from the group counts, then the bin inside that group (two
+// reads of kRep x 64 words).  s_part: kT words of LDS.  Every thread of the
+// kT-thread block returns the same values.
+__device__ void find_bin1(const uint32_t *hist1, uint32_t need, uint32_t *s_part,
+                          uint32_t *s_res, uint32_t *bin, uint32_t *below, uint32_t *count) {
+    static_assert(kT == 8 * 64 && kRep == 16 && kGroups == 64, "two replicas per thread");
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_res[0] = s_res[1] = s_res[2] = 0;
+    uint32_t at = 0, under = 0;
+#pragma unroll
+    for (int lev = 0; lev < 2; ++lev) {
+        // lev 0: the group counts; lev 1: the 64 bins of group `at`
+        const uint32_t *src = lev == 0 ? hist1 + kRep * kBins + lane : hist1 + at * 64 + lane;
+        const uint32_t stride = lev == 0 ? kGroups : kBins;
+        s_part[threadIdx.x] = src[w * stride] + src[(w + 8) * stride];
+        __syncthreads();
+        if (w == 0) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c += s_part[q * 64 + lane];
+            uint32_t inc = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += y;
+            }
+            const uint32_t ex = under + inc - c;
+            if (ex < need && need <= ex + c) {
+                s_res[0] = lane;
+                s_res[1] = ex;
+                s_res[2] = c;
+            }
+        }
+        __syncthreads();
+        at = at * 64 + s_res[0];
+        under = s_res[1];
     }
+    *bin = at;
+    *below = under;
+    *count = s_res[2];
 }
 
 __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, uint32_t nrem,
-                                             SelState *st, double *__restrict__ ckey,
-                                             uint32_t *__restrict__ cpos, uint32_t *hist1,
-                                             uint32_t *hist2, uint32_t *__restrict__ blockcnt) {
-    {
-        // the level-1 replicas were read by k_sel1: clear them for the next
-        // round, a slice per block
-        constexpr uint32_t words = kRep * kBins;
-        const uint32_t per = (words + gridDim.x - 1) / gridDim.x;
-        const uint32_t z0 = blockIdx.x * per, z1 = min(words, z0 + per);
-        for (uint32_t i = z0 + threadIdx.x; i < z1; i += kT) hist1[i] = 0;
-    }
+                                             uint32_t need, SelState *st,
+                                             double *__restrict__ ckey,
+                                             uint32_t *__restrict__ cpos,
+                                             const uint32_t *hist1, uint32_t *hist2,
+                                             uint32_t *__restrict__ blockcnt) {
     __shared__ uint32_t h[kBins];
     __shared__ double s_ck[kBS];
     __shared__ uint32_t s_cp[kBS];
-    __shared__ uint32_t s_red[kT / 64], s_nc, s_base;
-    for (int i = threadIdx.x; i < kBins; i += kT) h[i] = 0;
-    if (threadIdx.x == 0) s_nc = 0;
-    __syncthreads();
-    const uint32_t astar = st->astar, base = st->base, vsh = st->vshift;
+    __shared__ uint32_t s_red[kT / 64], s_nc, s_base, s_res[3];
+    const uint32_t base = st->base, vsh = st->vshift;
     const int lane = threadIdx.x & 63;
     uint32_t below = 0;
     const uint32_t p0 = blockIdx.x * kBS;
@@ -456,6 +496,17 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
         const uint32_t p = p0 + u * kT + threadIdx.x;
         kb[u] = p < nrem ? keys[p] : 0.0;
     }
+    // every block finds the boundary bin itself (h serves as scratch)
+    uint32_t astar, below1, cnt1;
+    find_bin1(hist1, need, h, s_res, &astar, &below1, &cnt1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->astar = astar;
+        st->below1 = below1;
+        st->cnt1 = cnt1;
+    }
+    for (int i = threadIdx.x; i < kBins; i += kT) h[i] = 0;
+    if (threadIdx.x == 0) s_nc = 0;
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const uint32_t p = p0 + u * kT + threadIdx.x;
@@ -737,7 +788,8 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
                                                 int all_sel, int track_min, float *__restrict__ P,
                                                 int32_t *__restrict__ perm, int64_t off_t,
                                                 int32_t *__restrict__ rem_next,
-                                                uint32_t *__restrict__ Lnext, int vec4) {
+                                                uint32_t *__restrict__ Lnext, int vec4,
+                                                uint32_t *__restrict__ hclear) {
     __shared__ int32_t s_src[kBS];
     __shared__ int32_t s_dst[kBS];  // >= 0: P row; < 0: -(1 + slot) in rem_next
     __shared__ uint32_t tmp[kT / 64];
@@ -813,6 +865,14 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
         for (int j = threadIdx.x; j < d; j += kT)
             if (s_cmin[j] != 0xFFFFFFFFu) atomicMin(&Lnext[j], s_cmin[j]);
     }
+    // the level-1 replicas and group counts were last read by the candidate
+    // pass: clear them for the next round, a slice per block
+    {
+        constexpr uint32_t words = kRep * (kBins + kGroups);
+        const uint32_t zs = (words + gridDim.x - 1) / gridDim.x;
+        const uint32_t z0 = blockIdx.x * zs, z1 = min(words, z0 + zs);
+        for (uint32_t i = z0 + threadIdx.x; i < z1; i += kT) hclear[i] = 0;
+    }
 }
 
 // The same compaction for rows of d = W * DQ attributes with DQ dividing kT
@@ -831,7 +891,7 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
     const SelState *__restrict__ st, const uint32_t *__restrict__ blockoff, int all_sel,
     int track_min, float *__restrict__ P, int32_t *__restrict__ perm, int64_t off_t,
     int32_t *__restrict__ rem_next, uint32_t *__restrict__ Lnext,
-    double *__restrict__ keys_next) {
+    double *__restrict__ keys_next, uint32_t *__restrict__ hclear) {
     typedef typename VecT<W>::type V;
     constexpr int D = W * DQ;
     constexpr int per = kBS / kT;   // positions per thread in the selection
@@ -932,11 +992,19 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
         if (threadIdx.x < D && s_cmin[threadIdx.x] != 0xFFFFFFFFu)
             atomicMin(&Lnext[threadIdx.x], s_cmin[threadIdx.x]);
     }
+    // the level-1 replicas and group counts were last read by the candidate
+    // pass: clear them for the next round, a slice per block
+    {
+        constexpr uint32_t words = kRep * (kBins + kGroups);
+        const uint32_t zs = (words + gridDim.x - 1) / gridDim.x;
+        const uint32_t z0 = blockIdx.x * zs, z1 = min(words, z0 + zs);
+        for (uint32_t i = z0 + threadIdx.x; i < z1; i += kT) hclear[i] = 0;
+    }
 }
 
 typedef void (*ScatterFastFn)(const float *, const int32_t *, const double *, uint32_t, uint32_t,
                               const SelState *, const uint32_t *, int, int, float *, int32_t *,
-                              int64_t, int32_t *, uint32_t *, double *);
+                              int64_t, int32_t *, uint32_t *, double *, uint32_t *);
 
 // The early-load compaction for this row width and alignment, or null.
 ScatterFastFn scatter_fast_for(int d, bool vec4) {
@@ -1038,9 +1106,10 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     hipStream_t s = ctx->stream;
     const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
     SelState *st = (SelState *)b.sel;
+    // level-1 bin replicas, their group counts, then the level-2 bins
     uint32_t *hist1 = (uint32_t *)(b.sel + 256);
-    uint32_t *hist2 = hist1 + kRep * kBins;
-    uint32_t *blockcnt = hist2 + kRep * kBins;
+    uint32_t *hist2 = hist1 + kRep * (kBins + kGroups);
+    uint32_t *blockcnt = hist1 + 2 * kRep * kBins;
     uint32_t *blockoff = blockcnt + nb_max;
     double *ckey = (double *)b.cand;
     uint32_t *cpos = (uint32_t *)(b.cand + sizeof(double) * n);
@@ -1057,7 +1126,7 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     const float *colmax = b.colmax;
 
     if (t0 == 0) {
-        // histogram replicas start at zero (the select kernels re-zero them)
+        // histograms start at zero (the compaction and k_sel2 re-zero them)
         const uint32_t nzero = (uint32_t)(2 * kRep * kBins);
         hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(nzero, 256)), dim3(256), 0, s, hist1, nzero, 0u);
         SUBKM_LAUNCHED(ctx);
@@ -1121,12 +1190,10 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
                 }
                 SUBKM_LAUNCHED(ctx);
             }
-            hipLaunchKernelGGL(k_sel1, dim3(1), dim3(kST), 0, s, hist1, need, st);
-            SUBKM_LAUNCHED(ctx);
             {
                 ProfScope pc(ctx, PK_CAND);
-                hipLaunchKernelGGL(k_cand, dim3(nb), dim3(kT), 0, s, keys, nrem, st, ckey, cpos, hist1,
-                                   hist2, blockcnt);
+                hipLaunchKernelGGL(k_cand, dim3(nb), dim3(kT), 0, s, keys, nrem, need, st, ckey,
+                                   cpos, hist1, hist2, blockcnt);
                 SUBKM_LAUNCHED(ctx);
             }
             hipLaunchKernelGGL(k_sel2, dim3(1), dim3(kST), 0, s, need, st, ckey, cpos, nb, hist2,
@@ -1142,11 +1209,11 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
             if (scat_fast)
                 hipLaunchKernelGGL(scat_fast, dim3(nb), dim3(kT), 0, s, S, cur, keys, nrem, need,
                                    st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt,
-                                   Lnext, keys_next);
+                                   Lnext, keys_next, hist1);
             else
                 hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kT), dyn_d, s, S, d, cur, keys, nrem,
                                    need, st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N,
-                                   nxt, Lnext, vec4p ? 1 : 0);
+                                   nxt, Lnext, vec4p ? 1 : 0, hist1);
             SUBKM_LAUNCHED(ctx);
         }
         nrem -= need;
@@ -1159,7 +1226,7 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
 
 }  // namespace
 
-// Rounds [t0, t1) of the sequence (3 + about 6 T launches in all) are
+// Rounds [t0, t1) of the sequence (3 + about 4 T launches in all) are
 // captured once into a HIP graph per (segment, inputs, outputs, sizes,
 // buffers) and replayed, which removes the launch gaps between the many short
 // kernels.  The graphs hold kernel nodes only.
