@@ -46,6 +46,9 @@ constexpr int kGroups = kBins / 64;  // 64-bin groups of the level-1 bins
 constexpr uint32_t kBS = 2048;    // positions per compaction block
 constexpr int kRankCap = 2048;    // boundary candidates ranked in LDS
 constexpr uint32_t kVMax = 0xFFFFFFu;
+// remaining points from which the compaction reads only the selected rows in
+// rounds whose landmark surely stays
+constexpr uint32_t kSkipMin = 1u << 16;
 
 struct SelState {
     uint32_t base;     // v-map offset of this round
@@ -55,6 +58,7 @@ struct SelState {
     uint32_t fallback;  // rounds that needed the slow exact path
     uint32_t ncand;     // length of the flat candidate list
     uint32_t vshift;    // low float bits the v-map drops this round
+    uint32_t lchange;   // 0: no point holding an attribute minimum can be removed
     double thr_key;
 };
 
@@ -299,7 +303,9 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
                                                   SelState *st, float *landmarks_t,
                                                   int have_prev, int reuse,
                                                   const uint32_t *__restrict__ Lprev,
-                                                  uint32_t *__restrict__ Lsave) {
+                                                  uint32_t *__restrict__ Lsave,
+                                                  unsigned long long *__restrict__ mk,
+                                                  const unsigned long long *__restrict__ mk_prev) {
     constexpr int W = V4 ? 4 : 1;
     constexpr int NV = D / W;  // loads per row
     static_assert(D % W == 0 && D <= kT, "row width");
@@ -375,6 +381,8 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
         if (landmarks_t) landmarks_t[threadIdx.x] = sL[threadIdx.x];
         if (Lnext) Lnext[threadIdx.x] = 0xFFFFFFFFu;  // the round's compaction folds the next landmark here
         if (Lsave) Lsave[threadIdx.x] = ordered_bits(sL[threadIdx.x]);
+        // same landmark, same keys: the holders' largest keys carry over
+        if (mk && same) mk[threadIdx.x] = mk_prev[threadIdx.x];
     }
     const uint32_t base = s_base, vsh = s_sh;
 #pragma unroll
@@ -394,6 +402,22 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
         if (p < nrem) {
             if (!same) keys[p] = key;
             atomicAdd(&h[vmap(key, base, vsh) >> 12], 1u);
+            if (mk && !same) {
+                // attributes in which this point holds the landmark (the
+                // minimum): its key raises their holders' largest key
+                uint32_t hold = 0;
+#pragma unroll
+                for (int q = 0; q < NV; ++q)
+#pragma unroll
+                    for (int c = 0; c < W; ++c)
+                        hold |= (__float_as_uint(vget(x[u][q], c)) == __float_as_uint(sL[q * W + c])
+                                     ? 1u : 0u) << (q * W + c);
+                if (hold) {
+                    const unsigned long long kb = (unsigned long long)__double_as_longlong(key);
+                    for (int j = 0; j < D; ++j)
+                        if ((hold >> j) & 1u) atomicMax(&mk[j], kb);
+                }
+            }
         }
     }
     __syncthreads();
@@ -402,7 +426,8 @@ __global__ __launch_bounds__(kT) void k_keys_fast(const float *__restrict__ S,
 
 typedef void (*KeysFastFn)(const float *, const int32_t *, uint32_t, const float *,
                            const uint32_t *, uint32_t *, const float *, double *, uint32_t *,
-                           SelState *, float *, int, int, const uint32_t *, uint32_t *);
+                           SelState *, float *, int, int, const uint32_t *, uint32_t *,
+                           unsigned long long *, const unsigned long long *);
 
 template <int M, int D, bool V4>
 KeysFastFn keys_fast_pp(int pp) {
@@ -616,8 +641,9 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
                                               const double *__restrict__ ckey,
                                               const uint32_t *__restrict__ cpos, uint32_t nb,
                                               uint32_t *hist2, uint32_t *blockcnt,
-                                              uint32_t *blockoff) {
-    __shared__ uint32_t sh[4], tmp[kST / 64], s_n;
+                                              uint32_t *blockoff,
+                                              const unsigned long long *__restrict__ mk, int d) {
+    __shared__ uint32_t sh[4], tmp[kST / 64], s_n, s_lch;
     __shared__ double rk[kRankCap];
     __shared__ uint32_t rp[kRankCap];
     __shared__ uint32_t h256[256];
@@ -692,8 +718,15 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
             if (vmap(k, base, vsh) == vstar && pair_le(k, pc, thr_key, thr_pos)) count_sel(pc);
         }
     }
+    // The landmark can move only if every point holding some attribute's
+    // minimum is removed, which needs that attribute's largest holder key to
+    // be <= key* (an equal key is counted as removed: a conservative test)
+    if (threadIdx.x == 0) s_lch = mk ? 0u : 1u;
     if (!lds_counts) __threadfence_block();
     __syncthreads();
+    if (mk && (int)threadIdx.x < d &&
+        mk[threadIdx.x] <= (unsigned long long)__double_as_longlong(thr_key))
+        s_lch = 1u;
     uint32_t carry = 0;
     for (uint32_t c0 = 0; c0 < nb; c0 += kST) {
         const uint32_t sg = c0 + threadIdx.x;
@@ -712,6 +745,8 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
         st->thr_key = thr_key;
         st->thr_pos = thr_pos;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) st->lchange = s_lch;
 }
 
 
@@ -891,7 +926,9 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
     const SelState *__restrict__ st, const uint32_t *__restrict__ blockoff, int all_sel,
     int track_min, float *__restrict__ P, int32_t *__restrict__ perm, int64_t off_t,
     int32_t *__restrict__ rem_next, uint32_t *__restrict__ Lnext,
-    double *__restrict__ keys_next, uint32_t *__restrict__ hclear) {
+    double *__restrict__ keys_next, uint32_t *__restrict__ hclear, int lm_skip,
+    const uint32_t *__restrict__ Lcur, const float *__restrict__ L,
+    unsigned long long *__restrict__ mk_clear) {
     typedef typename VecT<W>::type V;
     constexpr int D = W * DQ;
     constexpr int per = kBS / kT;   // positions per thread in the selection
@@ -921,15 +958,23 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
         iq[q] = rem ? rem[p] : (int32_t)p;
     }
     double thr_key = 0.0;
-    uint32_t thr_pos = 0, sel_base = p0;
+    uint32_t thr_pos = 0, sel_base = p0, lch = 1;
     if (!all_sel) {
         thr_key = st->thr_key;
         thr_pos = st->thr_pos;
         sel_base = blockoff[blockIdx.x];
+        lch = st->lchange;
     }
+    // Rows are needed for the selected points, and for the others only when
+    // the next landmark has to be folded from them.  When the landmark
+    // surely stays (or is fixed), only selected rows are read, after the
+    // selection; otherwise every row is requested now (one uniform branch).
+    const bool full = !(lm_skip && !all_sel && (!track_min || lch == 0));
     V v[NV];
+    if (full) {
 #pragma unroll
-    for (int u = 0; u < NV; ++u) v[u] = ((const V *)(S + (int64_t)ridx[u] * D))[j];
+        for (int u = 0; u < NV; ++u) v[u] = ((const V *)(S + (int64_t)ridx[u] * D))[j];
+    }
 
     bool sel[per];
     uint32_t nsel = 0;
@@ -967,6 +1012,17 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
     }
     if (track_min && threadIdx.x < D) s_cmin[threadIdx.x] = 0xFFFFFFFFu;
     __syncthreads();
+    if (!full) {
+        // every thread loads; a row that is not selected reads row 0 instead
+        // (one line for the whole grid), so the loads go out together
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const uint32_t rc = min(r0 + u * RS, cnt - 1);
+            const int32_t row = s_dst[rc] >= 0 ? ridx[u] : 0;
+            v[u] = ((const V *)(S + (int64_t)row * D))[j];
+        }
+    }
+    const bool fold = track_min && full;
     uint32_t mymin[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) mymin[c] = 0xFFFFFFFFu;
@@ -977,13 +1033,13 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
             const int32_t dst = s_dst[r];
             if (dst >= 0) {
                 ((V *)(P + (off_t + dst) * D))[j] = v[u];
-            } else if (dst != INT32_MIN) {
+            } else if (fold && dst != INT32_MIN) {
 #pragma unroll
                 for (int c = 0; c < W; ++c) mymin[c] = min(mymin[c], ordered_bits(vget(v[u], c)));
             }
         }
     }
-    if (track_min) {
+    if (fold) {
 #pragma unroll
         for (int c = 0; c < W; ++c)
             if (mymin[c] != 0xFFFFFFFFu) atomicMin(&s_cmin[j * W + c], mymin[c]);
@@ -991,7 +1047,12 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
         __syncthreads();
         if (threadIdx.x < D && s_cmin[threadIdx.x] != 0xFFFFFFFFu)
             atomicMin(&Lnext[threadIdx.x], s_cmin[threadIdx.x]);
+    } else if (track_min && blockIdx.x == 0 && threadIdx.x < D) {
+        // the landmark stays (every block takes this branch)
+        Lnext[threadIdx.x] = Lcur ? Lcur[threadIdx.x] : ordered_bits(L[threadIdx.x]);
     }
+    // the next round's holder keys start from zero
+    if (mk_clear && blockIdx.x == 0 && threadIdx.x < D) mk_clear[threadIdx.x] = 0ull;
     // the level-1 replicas and group counts were last read by the candidate
     // pass: clear them for the next round, a slice per block
     {
@@ -1004,7 +1065,8 @@ __global__ __launch_bounds__(kT) void k_scatter_fast(
 
 typedef void (*ScatterFastFn)(const float *, const int32_t *, const double *, uint32_t, uint32_t,
                               const SelState *, const uint32_t *, int, int, float *, int32_t *,
-                              int64_t, int32_t *, uint32_t *, double *, uint32_t *);
+                              int64_t, int32_t *, uint32_t *, double *, uint32_t *, int,
+                              const uint32_t *, const float *, unsigned long long *);
 
 // The early-load compaction for this row width and alignment, or null.
 ScatterFastFn scatter_fast_for(int d, bool vec4) {
@@ -1074,7 +1136,7 @@ void sub_requests(int64_t n, int32_t d, size_t *req) {
     need(SC_REM1, sizeof(int32_t) * n);
     need(SC_CAND, (sizeof(double) + sizeof(uint32_t)) * n + 64);
     need(SC_SEL, 256 + sizeof(uint32_t) * sel_words);
-    need(SC_LAND, sizeof(float) * (4 * (size_t)d + 64));
+    need(SC_LAND, sizeof(float) * (8 * (size_t)d + 64));
     need(SC_COLMAX, sizeof(float) * d + 64);
     need(SC_MM_FLAG, 256);
     need(SC_MM_PART, minmax_scratch_bytes(n, d));
@@ -1122,6 +1184,10 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     // keys of round t in Kb[t & 1]; the compaction carries the keys of the
     // points that stay into Kb[(t + 1) & 1]
     double *Kb[2] = {b.keys, b.keys + n};
+    // per attribute, the largest key among the points holding the landmark
+    // value (binary64 bits): round t in MK[t & 1]
+    unsigned long long *MK[2] = {(unsigned long long *)(b.land + 4 * d),
+                                 (unsigned long long *)(b.land + 4 * d) + d};
     int32_t *rem0 = b.rem0, *rem1 = b.rem1;
     const float *colmax = b.colmax;
 
@@ -1129,6 +1195,9 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
         // histograms start at zero (the compaction and k_sel2 re-zero them)
         const uint32_t nzero = (uint32_t)(2 * kRep * kBins);
         hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(nzero, 256)), dim3(256), 0, s, hist1, nzero, 0u);
+        SUBKM_LAUNCHED(ctx);
+        hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(4 * d, 256)), dim3(256), 0, s,
+                           (uint32_t *)MK[0], (uint32_t)(4 * d), 0u);
         SUBKM_LAUNCHED(ctx);
         // first landmark: attribute-wise minimum of all points; column maxima bound the keys
         SUBKM_TRY(minmax_impl(ctx, S, n, d, L, b.colmax, b.flag));
@@ -1142,6 +1211,9 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
     const ScatterFastFn scat_fast = scatter_fast_for(d, vec4p);
     // keys are carried from round to round when both early-load kernels run
     const bool carry = scat_fast && keys_fast_for(metric, d, vec4, 1);
+    // the keys pass records the holder keys; the compaction then skips the
+    // rows that stay in rounds whose landmark surely stays
+    const bool lm_track = carry && !fixed;
     int32_t *cur = nullptr;  // round 0 reads the points through the identity
     int32_t *nxt = rem0;
     uint32_t nrem = (uint32_t)n;
@@ -1159,6 +1231,8 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
         const int reuse = (!carry || t == 0) ? 0 : fixed ? 2 : 1;
         const uint32_t *Lprev = reuse == 1 ? Lb[(t + 2) % 3] : nullptr;
         uint32_t *Lsave = (carry && t == 0 && !fixed) ? Lb[0] : nullptr;
+        unsigned long long *mk = lm_track ? MK[t & 1] : nullptr;
+        unsigned long long *mk_other = lm_track ? MK[(t + 1) & 1] : nullptr;
         if (t < t0) {
             // rounds of earlier segments: only their host-side bookkeeping
             if (!all && !cur) cur = rem1;
@@ -1181,7 +1255,7 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
                 if (kf) {
                     hipLaunchKernelGGL(kf, dim3(ceil_div(nrem, (int64_t)kT * pp)), dim3(kT), 0, s,
                                        S, cur, nrem, L, Lcur, Lnext, colmax, keys, hist1, st, lm_t,
-                                       t > 0 ? 1 : 0, reuse, Lprev, Lsave);
+                                       t > 0 ? 1 : 0, reuse, Lprev, Lsave, mk, mk_other);
                 } else {
                     const int64_t grid = std::min<int64_t>(ceil_div(nrem, kT), 512);
                     hipLaunchKernelGGL(metric ? k_keys<1> : k_keys<0>, dim3(grid), dim3(kT), dyn_d,
@@ -1197,7 +1271,7 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
                 SUBKM_LAUNCHED(ctx);
             }
             hipLaunchKernelGGL(k_sel2, dim3(1), dim3(kST), 0, s, need, st, ckey, cpos, nb, hist2,
-                               blockcnt, blockoff);
+                               blockcnt, blockoff, mk, d);
             SUBKM_LAUNCHED(ctx);
         } else if (lm_t) {
             if (Lcur) hipLaunchKernelGGL(k_bits_to_f32, dim3(ceil_div(d, 256)), dim3(256), 0, s, lm_t, Lcur, d);
@@ -1209,7 +1283,8 @@ subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64
             if (scat_fast)
                 hipLaunchKernelGGL(scat_fast, dim3(nb), dim3(kT), 0, s, S, cur, keys, nrem, need,
                                    st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N, nxt,
-                                   Lnext, keys_next, hist1);
+                                   Lnext, keys_next, hist1, nrem >= kSkipMin ? 1 : 0, Lcur, L,
+                                   all ? nullptr : mk_other);
             else
                 hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kT), dyn_d, s, S, d, cur, keys, nrem,
                                    need, st, blockoff, all ? 1 : 0, track ? 1 : 0, P, perm, t * N,
