@@ -920,7 +920,7 @@ __global__ __launch_bounds__(kT) void k_scatter(const float *__restrict__ S, int
 // together: two dependent memory round trips per block instead of one per
 // key, index and row batch.  Results are those of k_scatter.
 template <int W, int DQ>
-__global__ __launch_bounds__(kT) void k_scatter_fast(
+__global__ __launch_bounds__(kT, W * DQ <= 16 ? 4 : 1) void k_scatter_fast(
     const float *__restrict__ S, const int32_t *__restrict__ rem,
     const double *__restrict__ keys, uint32_t nrem, uint32_t need,
     const SelState *__restrict__ st, const uint32_t *__restrict__ blockoff, int all_sel,

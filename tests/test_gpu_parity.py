@@ -192,6 +192,30 @@ def test_subcluster_many_points_per_thread(km, oracle, n, d, metric):
     assert np.array_equal(host(P), S[permr])
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n,d,metric,mode", [(300_000, 16, 0, 0), (200_000, 8, 1, 0),
+                                             (250_000, 16, 0, 1)])
+def test_subcluster_tied_minimum_holders(km, oracle, n, d, metric, mode):
+    # values on a 1/8 grid (many keys tie), and below it, per attribute, five
+    # levels held by two random points each: rounds where some holder of
+    # the current minimum stays (the compaction reads only the selected
+    # rows) alternate with rounds where the last ones leave and the landmark
+    # moves (a third of the rounds here); with a fixed landmark no row that
+    # stays is read at all
+    rng = np.random.default_rng(n + d + mode)
+    X = (np.floor(rng.beta(2.0, 5.0, (n, d)) * 8.0) / 8.0).astype(np.float32)
+    for j in range(d):
+        for level in range(1, 6):
+            X[rng.integers(0, n, 2), j] = -level / 8.0
+    S, _, _ = oracle.scale(X)
+    N = 4096
+    P, perm, offs, lm = km.subcluster(dev(S), N, landmark_mode=mode, landmarks=True, metric=metric)
+    permr, offr, lmr = oracle.subcluster(S, N, fixed_landmark=bool(mode), metric=metric)
+    assert np.array_equal(host(lm), lmr)
+    assert np.array_equal(host(perm), permr)
+    assert np.array_equal(host(P), S[permr])
+
+
 # ----------------------------------------------------------------------------- Lloyd
 def shadow_steps(km, oracle, X, C0, steps, precision=0):
     """Run `steps` single GPU iterations, each checked against one oracle
