@@ -22,7 +22,7 @@ enum ScratchSlot {
     SC_REM1,         // (pong)
     SC_CAND,         // selection candidates (key, position)
     SC_SEL,          // selection state + histograms + block counts
-    SC_LAND,         // landmark (float) + running minima (ordered uint)
+    SC_LAND,         // landmark (float), running minima (ordered uint), minimum-holder keys
     SC_COLMAX,       // column maxima of S for the key bound
     SC_RUNS,         // device copy of run descriptors
     SC_ITEMS,        // work items of the Lloyd kernels

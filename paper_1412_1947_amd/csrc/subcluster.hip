@@ -25,7 +25,11 @@
 //              the attribute-wise minimum of the points it keeps into the
 //              next landmark L_{t+1} (Algorithm 1 step 2 on the points left
 //              over) with integer atomic minima on order-preserving bits,
-//              and clears the level-1 histograms for the next round.
+//              and clears the level-1 histograms for the next round.  In
+//              rounds where some point holding each attribute's minimum
+//              surely stays (k_sel2 decides it from the largest key among
+//              those holders), L_{t+1} = L_t and the early-load form reads
+//              only the selected rows.
 //
 // Positions in the remaining list are in ascending original index, so the
 // index tie-break of the selection is a tie-break on positions.
