@@ -65,7 +65,11 @@ const char *subkm_last_error(const subkm_ctx *ctx);
 /* Replace the stream of a context (hipStream_t, NULL = null stream).        */
 subkm_status subkm_set_stream(subkm_ctx *ctx, void *stream);
 
-/* Block the host until all work issued on the context's stream is done.    */
+/* Block the host until all work issued on the context's stream is done.
+ * Returns SUBKM_EDEVICE when a persistent Lloyd launch issued since the
+ * last such report gave up waiting at one of its barriers (a bounded spin
+ * that a device running the whole cooperative grid never exhausts); the
+ * results of that subkm_lloyd_batched or subkm_cluster call are invalid.  */
 subkm_status subkm_synchronize(subkm_ctx *ctx);
 
 /* ---------------------------------------------------------------------- */
@@ -184,7 +188,14 @@ subkm_status subkm_subcluster_unequal(subkm_ctx *ctx, const float *S, int64_t n,
  *            with one launch per phase and run (the reference form).  Both
  *            give identical results.
  * Requires R >= 1, n >= 1, 1 <= d <= 4096, 1 <= k <= n per run,
- * max_iter >= 0, tol >= 0.                                               */
+ * max_iter >= 0, tol >= 0.
+ *
+ * The call never synchronises the stream (with tuning on, the first call
+ * of a new shape does; see below).  The run descriptors are staged through
+ * a ring of pinned host buffers, so `runs` may be reused as soon as the
+ * call returns; a call waits only when the copy issued from the same ring
+ * slot four calls earlier has not run yet.  A persistent launch that gives
+ * up at a barrier is reported by the next subkm_synchronize.              */
 typedef struct {
     int64_t x_off;   /* offset of the run's first point in P, in floats      */
     int64_t n;       /* number of points                                     */
@@ -213,7 +224,8 @@ subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run
  * batched call with moves of a new shape (number of runs, points, smallest
  * and largest d and k, precision) runs itself under each candidate schedule
  * on the caller's data, restarting from the caller's centers, keeps the
- * fastest for the shape, and returns the result of one more run with it.
+ * fastest for the shape, and returns the result of one more run with it
+ * (such a tuning call synchronises the stream after every candidate).
  * Tuned schedules are used whether tuning is on or off.
  *   subkm_tune_enable: on = 1 tunes unseen shapes, 0 stops (default 0).
  *   subkm_tune_count: number of tuned shapes.
@@ -241,7 +253,12 @@ subkm_status subkm_tune_load(subkm_ctx *ctx, const char *path);
  * output, the final center of every point in input order.  sse: 1 double
  * output, sum over all points of the squared distance to its final center,
  * in scaled space.  opts: nullable.  stats: nullable HOST output; when given
- * the call synchronises and reports phase times.
+ * the call synchronises at its end, reports phase times, and reports a
+ * persistent Lloyd barrier that gave up as subkm_synchronize does.
+ * Host round trips: the call synchronises the stream once after the
+ * min/max pass (the non-finite check of subkm_scale), once more at the end
+ * when stats is given, and with Algorithm 2 once to read the group sizes;
+ * it makes no other.
  * Requires k_local <= N and k_final <= M, besides the requirements of the
  * calls above.  With Algorithm 2, T = m and M depends on the group sizes:
  * M <= min(n, floor(n * k_local / N) + m) (the capacity opts->local_centers
@@ -321,10 +338,12 @@ size_t subkm_device_bytes(const subkm_ctx *ctx);
  * subkm_engine_submit returns at once with a job id (SUBKM_ENOMEM when the
  * job could never fit the budget, SUBKM_EINVAL for invalid sizes).
  * subkm_engine_wait blocks until the job is done; subkm_engine_poll does not
- * block.  Both release the job's record once they report it done.  Results
- * do not depend on which other jobs run at the same time.  destroy waits for
- * running jobs and cancels the waiting ones (status SUBKM_EBUSY).  One host
- * thread at a time per call; the engine itself is thread safe.            */
+ * block.  Both release the job's record once they report it done; a wait
+ * whose record another thread released meanwhile returns SUBKM_EINVAL.
+ * Results do not depend on which other jobs run at the same time.  destroy
+ * waits for running jobs, cancels the waiting ones (status SUBKM_EBUSY),
+ * wakes every thread blocked in subkm_engine_wait and returns only after
+ * they have left it.  The engine itself is thread safe.                  */
 typedef struct subkm_engine subkm_engine;
 
 typedef struct {

@@ -13,9 +13,12 @@ centers (Sec. I, Sec. V).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
 import threading
+import weakref
 
 import torch
 
@@ -203,6 +206,7 @@ class Context:
         if st != 0:
             raise SubkmError(st, lib().subkm_last_error(None).decode())
         self._h = h
+        _live_handles.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -210,6 +214,12 @@ class Context:
             self._h = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime (and a profiler
+        # attached to it) may already be torn down: contexts still open then
+        # were closed by the exit handler below, or are left to the process
+        # exit
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -381,6 +391,20 @@ class Context:
 
 
 _contexts: dict = {}
+# every open context and engine, closed at interpreter exit while the HIP
+# runtime is still whole (engines first: they own contexts of their own)
+_live_handles: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    live = list(_live_handles)
+    for h in [x for x in live if isinstance(x, Engine)] + [x for x in live if isinstance(x, Context)]:
+        try:
+            h.close()
+        except Exception:
+            pass
+    _contexts.clear()
 
 
 def context(device: int = 0) -> Context:
@@ -428,6 +452,7 @@ class Engine:
         self._h = h
         self._live = {}
         self._lock = threading.Lock()
+        _live_handles.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -436,6 +461,8 @@ class Engine:
             self._live.clear()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -67,6 +67,49 @@ void *ctx_pinned(subkm_ctx *ctx, size_t bytes) {
     return ctx->pinned;
 }
 
+void *ctx_stage(subkm_ctx *ctx, size_t bytes, int *slot) {
+    const int q = ctx->stage_next;
+    subkm_ctx::Stage &g = ctx->stage[q];
+    if (!g.ev && hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess) {
+        hipGetLastError();
+        g.ev = nullptr;
+        set_err(ctx, SUBKM_EDEVICE, "hipEventCreate failed");
+        return nullptr;
+    }
+    if (g.pending) {
+        // the copy issued from this slot kStageSlots calls ago
+        if (hipEventSynchronize(g.ev) != hipSuccess) {
+            hipGetLastError();
+            set_err(ctx, SUBKM_EDEVICE, "waiting for a plan copy failed");
+            return nullptr;
+        }
+        g.pending = false;
+    }
+    if (g.bytes < bytes) {
+        if (g.h) hipHostFree(g.h);
+        g.h = nullptr;
+        g.bytes = 0;
+        const size_t want = std::max<size_t>(bytes, 1 << 16);
+        if (hipHostMalloc(&g.h, want, hipHostMallocDefault) != hipSuccess) {
+            hipGetLastError();
+            g.h = nullptr;
+            set_err(ctx, SUBKM_ENOMEM, "pinned host allocation of %zu bytes failed", want);
+            return nullptr;
+        }
+        g.bytes = want;
+    }
+    *slot = q;
+    ctx->stage_next = (q + 1) % subkm_ctx::kStageSlots;
+    return g.h;
+}
+
+subkm_status ctx_stage_issued(subkm_ctx *ctx, int slot) {
+    subkm_ctx::Stage &g = ctx->stage[slot];
+    SUBKM_HIP(ctx, hipEventRecord(g.ev, ctx->stream));
+    g.pending = true;
+    return SUBKM_OK;
+}
+
 static hipEvent_t prof_event(subkm_ctx *ctx) {
     if (!ctx->prof_free.empty()) {
         hipEvent_t e = ctx->prof_free.back();
@@ -106,6 +149,20 @@ static void prof_resolve(subkm_ctx *ctx) {
         ctx->prof_free.push_back(r.b);
     }
     ctx->prof_pending.clear();
+}
+
+// Report (and clear) what a finished launch flagged in the sticky words;
+// the context's stream must be idle.
+static subkm_status check_sticky(subkm_ctx *ctx) {
+    int h = 0;
+    SUBKM_HIP(ctx, hipMemcpy(&h, ctx->sticky, sizeof h, hipMemcpyDeviceToHost));
+    if (h) {
+        SUBKM_HIP(ctx, hipMemset(ctx->sticky, 0, sizeof h));
+        return set_err(ctx, SUBKM_EDEVICE,
+                       "a persistent Lloyd launch on this context gave up waiting at a barrier; "
+                       "the results of that batched call are invalid");
+    }
+    return SUBKM_OK;
 }
 
 // RAII: make the context's device current for the duration of a call
@@ -154,9 +211,14 @@ subkm_status subkm_create(int device, void *stream, subkm_ctx **out) {
     for (auto &e : c->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
             hipGetLastError();
-            delete c;
+            subkm_destroy(c);
             return set_err(nullptr, SUBKM_EDEVICE, "hipEventCreate failed");
         }
+    }
+    if (hipMalloc(&c->sticky, 256) != hipSuccess || hipMemset(c->sticky, 0, 256) != hipSuccess) {
+        hipGetLastError();
+        subkm_destroy(c);
+        return set_err(nullptr, SUBKM_ENOMEM, "device allocation of the context's flags failed");
     }
     *out = c;
     return SUBKM_OK;
@@ -169,6 +231,11 @@ void subkm_destroy(subkm_ctx *ctx) {
     for (auto &b : ctx->scratch)
         if (b.ptr) hipFree(b.ptr);
     if (ctx->pinned) hipHostFree(ctx->pinned);
+    for (auto &g : ctx->stage) {
+        if (g.h) hipHostFree(g.h);
+        if (g.ev) hipEventDestroy(g.ev);
+    }
+    if (ctx->sticky) hipFree(ctx->sticky);
     for (auto &e : ctx->ev)
         if (e) hipEventDestroy(e);
     prof_resolve(ctx);
@@ -197,7 +264,7 @@ subkm_status subkm_synchronize(subkm_ctx *ctx) {
     CHECK_CTX(ctx);
     DeviceGuard g(ctx->device);
     SUBKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return SUBKM_OK;
+    return check_sticky(ctx);
 }
 
 subkm_status subkm_tune_enable(subkm_ctx *ctx, int32_t on) {
@@ -581,6 +648,7 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
         SUBKM_HIP(ctx, hipMemcpy(&hit[R], fit, sizeof(int32_t), hipMemcpyDeviceToHost));
         unsigned long long nr = 0;
         SUBKM_HIP(ctx, hipMemcpy(&nr, nrecheck, sizeof nr, hipMemcpyDeviceToHost));
+        SUBKM_TRY(check_sticky(ctx));
         stats->rechecked = (int64_t)nr;
         stats->T = T;
         stats->M = M;

@@ -63,6 +63,8 @@ struct subkm_engine {
     std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv_done;
+    std::condition_variable cv_left;  // a waiter left subkm_engine_wait
+    int waiters = 0;                  // threads inside subkm_engine_wait
     std::deque<int64_t> queue;
     std::unordered_map<int64_t, JobRec> jobs;
     int64_t next_id = 1;
@@ -282,9 +284,17 @@ void subkm_engine_destroy(subkm_engine *e) {
         }
         e->queue.clear();
         for (Slot &s : e->slots) s.cv.notify_all();
+        e->cv_done.notify_all();
     }
     for (Slot &s : e->slots)
         if (s.th.joinable()) s.th.join();
+    {
+        // every job is done now; threads still waiting on one leave before
+        // the engine goes away
+        std::unique_lock<std::mutex> lk(e->mu);
+        e->cv_done.notify_all();
+        e->cv_left.wait(lk, [&] { return e->waiters == 0; });
+    }
     for (Slot &s : e->slots) {
         for (DevBuf &x : s.buf)
             if (x.ptr) hipFree(x.ptr);
@@ -367,8 +377,16 @@ subkm_status subkm_engine_wait(subkm_engine *e, int64_t id, subkm_job_result *re
     std::unique_lock<std::mutex> lk(e->mu);
     auto it = e->jobs.find(id);
     if (it == e->jobs.end()) return SUBKM_EINVAL;
-    e->cv_done.wait(lk, [&] { return e->jobs[id].done; });
+    e->waiters += 1;
+    // the record may be taken by another thread's poll or wait meanwhile
+    e->cv_done.wait(lk, [&] {
+        auto f = e->jobs.find(id);
+        return f == e->jobs.end() || f->second.done;
+    });
+    e->waiters -= 1;
+    if (e->waiters == 0) e->cv_left.notify_all();
     it = e->jobs.find(id);
+    if (it == e->jobs.end()) return SUBKM_EINVAL;
     if (res) *res = it->second.res;
     e->jobs.erase(it);
     return SUBKM_OK;

@@ -104,8 +104,25 @@ struct subkm_ctx {
     int cu_count = 256;
     std::string err;
     ScratchBuf scratch[SC_COUNT];
-    void *pinned = nullptr;  // small pinned host staging area
+    void *pinned = nullptr;  // small pinned host area (flags read back after a sync)
     size_t pinned_bytes = 0;
+    // Pinned staging of the Lloyd plans, a ring: a call writes its plan into
+    // the next slot and records an event after the slot's host-to-device
+    // copy, so it waits (rarely) only for the copy issued kStageSlots calls
+    // earlier, never for the stream to drain.
+    static constexpr int kStageSlots = 4;
+    struct Stage {
+        void *h = nullptr;
+        size_t bytes = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    Stage stage[kStageSlots];
+    int stage_next = 0;
+    // Sticky device flags (zeroed at creation): word 0 is set by a
+    // persistent Lloyd launch whose barrier gave up; subkm_synchronize
+    // reports and clears it.
+    int *sticky = nullptr;
     hipEvent_t ev[8] = {};
     bool prof_on = false;
     std::vector<ProfRec> prof_pending;
@@ -142,6 +159,11 @@ struct ProfScope {
 // Returns nullptr and sets ctx->err when allocation fails.
 void *ctx_scratch(subkm_ctx *ctx, int slot, size_t bytes);
 void *ctx_pinned(subkm_ctx *ctx, size_t bytes);
+// Next slot of the plan staging ring with at least `bytes` bytes; *slot
+// receives its index for ctx_stage_issued (nullptr and ctx->err on failure).
+void *ctx_stage(subkm_ctx *ctx, size_t bytes, int *slot);
+// The copy out of staging slot `slot` has been issued on the context's stream.
+subkm_status ctx_stage_issued(subkm_ctx *ctx, int slot);
 
 subkm_status set_err(subkm_ctx *ctx, subkm_status st, const char *fmt, ...);
 

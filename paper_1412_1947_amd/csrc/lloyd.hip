@@ -1355,7 +1355,6 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
     PlanSizes z;
     plan_runs(runs, R, precision, max_iter, dr, z);
     for (int r = 0; r < R; ++r) dr[r].orig = ord[r];
-    const bool all_fused = z.all_fused;
     int64_t sum_words = z.sum_words, box_words = z.box_words, cnt_words = z.cnt_words;
     const int64_t order_words = z.order_words, frag_words = z.frag_words, cn_words = z.cn_words;
     std::vector<std::pair<int, int>> ds;  // distinct (attribute count, matrix-core path)
@@ -1363,9 +1362,17 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
     std::sort(ds.begin(), ds.end());
     ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
 
-    const bool batched = form == SUBKM_FORM_BATCHED && all_fused;
+    // Batched form: the runs whose centers and sums fit on chip go to one
+    // persistent launch per (d, matrix-core) group; the others (sorted
+    // first) take the per-phase path, in the same call.  Plain form: every
+    // run on its own, one launch per phase.
+    const bool batched = form == SUBKM_FORM_BATCHED;
+    int nwide = 0;
+    while (nwide < R && !dr[nwide].fused) ++nwide;
+    const bool persist_any = batched && nwide < R;
+    const int nplain = batched ? nwide : R;  // runs that take per-phase launches
     std::vector<Item> items;
-    std::vector<int> walk0, nwalk;
+    std::vector<int> walk0(R, 0), nwalk(R, 0);
     std::vector<Task> tasks;
     std::vector<int32_t> task_off;
     struct Group {
@@ -1374,15 +1381,43 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
     std::vector<Group> groups;
     int64_t part_words = 0;
     int n_obj = 0;
-    if (batched) {
+    // per-phase runs: assignment items (tiles) first, so that an item's index
+    // is also its objective slot; then update and walk items of wide runs
+    for (int r = 0; r < nplain; ++r) {
+        DevRun &D = dr[r];
+        D.item0 = (int)items.size();
+        for (int64_t f = 0; f < D.n; f += kAT) items.push_back(Item{r, (int32_t)f, 0, 0});
+        D.nitems = (int)items.size() - D.item0;
+    }
+    n_obj = (int)items.size();
+    for (int r = 0; r < nplain; ++r) {
+        DevRun &D = dr[r];
+        D.uitem0 = (int)items.size();
+        if (!D.fused) {
+            D.kcu = kWideCenters;
+            for (int c = 0; c < D.k; c += kWideCenters) items.push_back(Item{r, c, 0, 0});
+        }
+        D.nuitems = (int)items.size() - D.uitem0;
+    }
+    for (int r = 0; r < nplain; ++r) {
+        walk0[r] = (int)items.size();
+        if (!dr[r].fused && dr[r].d <= kWalkD)
+            for (int64_t f = 0; f < dr[r].n; f += kWalkB) items.push_back(Item{r, (int32_t)f, 0, 0});
+        nwalk[r] = (int)items.size() - walk0[r];
+    }
+    if (persist_any) {
         // one persistent launch per attribute count, at most the co-resident capacity
+        std::vector<std::pair<int, int>> dsf;
+        for (int r = nwide; r < R; ++r) dsf.push_back({dr[r].d, dr[r].mf});
+        std::sort(dsf.begin(), dsf.end());
+        dsf.erase(std::unique(dsf.begin(), dsf.end()), dsf.end());
         int block_base = 0;
         task_off.push_back(0);
-        for (auto dm : ds) {
+        for (auto dm : dsf) {
             const int dv = dm.first, mv = dm.second;
             std::vector<int> rr;
             int64_t tiles = 0;
-            for (int r = 0; r < R; ++r)
+            for (int r = nwide; r < R; ++r)
                 if (dr[r].d == dv && dr[r].mf == mv) {
                     rr.push_back(r);
                     tiles += (dr[r].n + kAT - 1) / kAT;
@@ -1409,36 +1444,10 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
             groups.push_back(Group{dv, mv, block_base, blocks});
             block_base += blocks;
         }
-        for (int r = 0; r < R; ++r) {
+        // objective slots of the persistent runs follow the per-phase items
+        for (int r = nwide; r < R; ++r) {
             dr[r].item0 = n_obj;
             n_obj += dr[r].nitems;
-        }
-    } else {
-        for (int r = 0; r < R; ++r) {
-            DevRun &D = dr[r];
-            D.item0 = (int)items.size();
-            for (int64_t f = 0; f < D.n; f += kAT) items.push_back(Item{r, (int32_t)f, 0, 0});
-            D.nitems = (int)items.size() - D.item0;
-        }
-        n_obj = (int)items.size();
-        // update items of the wide runs: chunks of kWideCenters centers
-        for (int r = 0; r < R; ++r) {
-            DevRun &D = dr[r];
-            D.uitem0 = (int)items.size();
-            if (!D.fused) {
-                D.kcu = kWideCenters;
-                for (int c = 0; c < D.k; c += kWideCenters) items.push_back(Item{r, c, 0, 0});
-            }
-            D.nuitems = (int)items.size() - D.uitem0;
-        }
-        // walk items of the wide runs: kWalkB label-sorted positions each
-        walk0.assign(R, 0);
-        nwalk.assign(R, 0);
-        for (int r = 0; r < R; ++r) {
-            walk0[r] = (int)items.size();
-            if (!dr[r].fused && dr[r].d <= kWalkD)
-                for (int64_t f = 0; f < dr[r].n; f += kWalkB) items.push_back(Item{r, (int32_t)f, 0, 0});
-            nwalk[r] = (int)items.size() - walk0[r];
         }
     }
     const int n_items = (int)items.size();
@@ -1462,19 +1471,21 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
     float *d_cn = (float *)ctx_scratch(ctx, SC_CNORM, req[SC_CNORM]);
     if (!d_plan || !d_rs || !d_obj || !d_sum || !d_err || !d_box || !d_cnt || !d_order || !d_frags || !d_cn)
         return SUBKM_ENOMEM;
-    char *h = (char *)ctx_pinned(ctx, b_plan + 64);
-    if (!h) return SUBKM_ENOMEM;
+    int stage = 0;
+    char *h = (char *)ctx_stage(ctx, b_plan + 64, &stage);
+    if (!h) return ctx->err.empty() ? SUBKM_ENOMEM : SUBKM_EDEVICE;
     DevRun *d_runs = (DevRun *)d_plan;
     Item *d_items = (Item *)(d_plan + b_runs);
     Task *d_tasks = (Task *)(d_plan + b_runs + b_items);
     int32_t *d_toff = (int32_t *)(d_plan + b_runs + b_items + b_tasks);
-    // the pinned staging area is shared by calls: wait for its previous copy
-    SUBKM_HIP(ctx, hipStreamSynchronize(s));
+    // the plan goes through a slot of the staging ring (no wait for the
+    // stream: only the copy issued from the same slot calls ago must be done)
     std::memcpy(h, dr.data(), b_runs);
     if (b_items) std::memcpy(h + b_runs, items.data(), b_items);
     if (b_tasks) std::memcpy(h + b_runs + b_items, tasks.data(), b_tasks);
     if (b_toff) std::memcpy(h + b_runs + b_items + b_tasks, task_off.data(), b_toff);
     SUBKM_HIP(ctx, hipMemcpyAsync(d_plan, h, b_plan, hipMemcpyHostToDevice, s));
+    SUBKM_TRY(ctx_stage_issued(ctx, stage));
 
     hipLaunchKernelGGL(k_state_init, dim3(ceil_div(R, 256)), dim3(256), 0, s, d_rs, R);
     SUBKM_LAUNCHED(ctx);
@@ -1552,20 +1563,23 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
                dr[a].split == dr[b].split;
     };
 
-    if (batched) {
+    if (persist_any) {
         std::unique_lock<std::mutex> gate;
         if (ctx->coop) {
             gate = std::unique_lock<std::mutex>(ctx->coop->mu);
             if (ctx->coop->armed) SUBKM_HIP(ctx, hipStreamWaitEvent(s, ctx->coop->ev, 0));
         }
+        // a barrier that gives up sets the context's sticky flag, which
+        // subkm_synchronize reports
         for (const Group &g : groups)
             SUBKM_TRY(persist_d(ctx, g.d, g.mf != 0, g.blocks, P, d_runs, d_tasks, d_toff + g.block0,
-                                C, labels, d_rs, parts, d_obj, d_box, max_iter, tol, d_err));
+                                C, labels, d_rs, parts, d_obj, d_box, max_iter, tol, ctx->sticky));
         if (ctx->coop) {
             SUBKM_HIP(ctx, hipEventRecord(ctx->coop->ev, s));
             ctx->coop->armed = true;
         }
-    } else if (form == SUBKM_FORM_PLAIN) {
+    }
+    if (form == SUBKM_FORM_PLAIN) {
         // one run at a time, one launch per phase
         for (int r = 0; r < R; ++r) {
             for (int a = 0; a <= max_iter; ++a) {
@@ -1574,35 +1588,23 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
                 SUBKM_TRY(update_seg(r, r + 1));
             }
         }
-    } else {
-        // batched request with runs beyond the on-chip budget: every phase is
+    } else if (nwide > 0) {
+        // the batched form's runs beyond the on-chip budget: every phase is
         // one launch per group of consecutive runs of the same path
         for (int a = 0; a <= max_iter; ++a) {
-            for (int r0 = 0; r0 < R;) {
+            for (int r0 = 0; r0 < nwide;) {
                 int r1 = r0 + 1;
-                while (r1 < R && same_assign(r0, r1)) ++r1;
+                while (r1 < nwide && same_assign(r0, r1)) ++r1;
                 SUBKM_TRY(assign_seg(r0, r1, a));
                 r0 = r1;
             }
             if (a == max_iter) break;
-            for (int r0 = 0; r0 < R;) {
-                int r1 = r0 + 1;
-                while (r1 < R && dr[r1].fused == dr[r0].fused) ++r1;
-                SUBKM_TRY(update_seg(r0, r1));
-                r0 = r1;
-            }
+            SUBKM_TRY(update_seg(0, nwide));
         }
     }
     hipLaunchKernelGGL(k_finalize, dim3(R), dim3(kAT), 0, s, d_runs, d_rs, d_obj, iters, sse,
                        rechecks_acc ? rechecks_acc : d_rechecks);
     SUBKM_LAUNCHED(ctx);
-    if (batched) {
-        // a barrier that gave up would leave wrong results: report it
-        int *hflag = (int *)h;
-        SUBKM_HIP(ctx, hipMemcpyAsync(hflag, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
-        SUBKM_HIP(ctx, hipStreamSynchronize(s));
-        if (*hflag) return set_err(ctx, SUBKM_EDEVICE, "persistent Lloyd barrier timed out");
-    }
     return SUBKM_OK;
 }
 
@@ -1692,33 +1694,36 @@ void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision,
     plan_runs(runs, R, precision, max_iter, dr, z);
     int64_t tiles = 0, n_items = 0, n_tasks = 0, n_toff = 0, part_words = 0;
     for (int r = 0; r < R; ++r) tiles += ceil_div(dr[r].n, kAT);
-    if (form == SUBKM_FORM_BATCHED && z.all_fused) {
-        std::vector<std::pair<int, int>> ds;
-        for (int r = 0; r < R; ++r) ds.push_back({dr[r].d, dr[r].mf});
-        std::sort(ds.begin(), ds.end());
-        ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
-        n_toff = 1;
-        for (auto dm : ds) {
-            int64_t gt = 0;
-            for (int r = 0; r < R; ++r)
-                if (dr[r].d == dm.first && dr[r].mf == dm.second) gt += ceil_div(dr[r].n, kAT);
-            const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)cu_count * 32, gt));
-            n_toff += blocks;
-        }
-        for (int r = 0; r < R; ++r) {
-            const int64_t t = ceil_div(dr[r].n, kAT);
+    const bool batched = form == SUBKM_FORM_BATCHED;
+    // runs of the persistent launch (batched form, on-chip runs): tasks and
+    // exchange slots; every other run: per-phase items
+    std::vector<std::pair<int, int>> ds;
+    for (int r = 0; r < R; ++r) {
+        const int64_t t = ceil_div(dr[r].n, kAT);
+        if (batched && dr[r].fused) {
+            ds.push_back({dr[r].d, dr[r].mf});
             const int64_t g = max_iter > 0 ? std::min<int64_t>(kMaxG, std::max<int64_t>(1, t / 2)) : t;
             n_tasks += g;
             if (max_iter > 0 && g > 1)
                 part_words += (2 * g + 2) * ((int64_t)dr[r].k * dr[r].d + dr[r].k);
-        }
-    } else {
-        n_items = tiles;
-        for (int r = 0; r < R; ++r)
+        } else {
+            n_items += t;
             if (!dr[r].fused) {
                 n_items += ceil_div(dr[r].k, kWideCenters);
                 if (dr[r].d <= kWalkD) n_items += ceil_div(dr[r].n, kWalkB);
             }
+        }
+    }
+    std::sort(ds.begin(), ds.end());
+    ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
+    if (!ds.empty()) {
+        n_toff = 1;
+        for (auto dm : ds) {
+            int64_t gt = 0;
+            for (int r = 0; r < R; ++r)
+                if (dr[r].fused && dr[r].d == dm.first && dr[r].mf == dm.second) gt += ceil_div(dr[r].n, kAT);
+            n_toff += std::max<int64_t>(1, std::min<int64_t>((int64_t)cu_count * 32, gt));
+        }
     }
     plan_requests(R, n_items, n_tasks, n_toff, tiles, part_words, z, req);
 }

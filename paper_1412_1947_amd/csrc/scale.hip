@@ -337,7 +337,9 @@ struct Plan {
     int64_t rows_per_block;  // wide
 };
 
-Plan plan_for(int64_t n, int d) {
+// max_blocks caps the wide form's grid (its partials take 2 d floats per
+// block); the narrow form has at most 2048 + 62 blocks.
+Plan plan_for(int64_t n, int d, int64_t max_blocks = 2048) {
     Plan p{};
     const int64_t total = n * d;
     if (d < 64) {
@@ -348,10 +350,41 @@ Plan plan_for(int64_t n, int d) {
         p.stride = p.blocks * kThreads;
     } else {
         p.narrow = false;
-        p.rows_per_block = std::max<int64_t>(8, ceil_div(n, 2048));
+        p.rows_per_block = std::max<int64_t>(8, ceil_div(n, std::min<int64_t>(2048, max_blocks)));
         p.blocks = ceil_div(n, p.rows_per_block);
     }
     return p;
+}
+
+// Column minima/maxima (partials into pmin/pmax, then the final reduction)
+// and the transform, for a plan; shared by the entry points that take their
+// partials from the context's scratch and from the static scratch below.
+void launch_minmax(hipStream_t s, const Plan &p, const float *X, int64_t n, int d, float *pmin,
+                   float *pmax, int *flag, float *mins, float *maxs) {
+    if (p.narrow)
+        hipLaunchKernelGGL(k_minmax_narrow, dim3(p.blocks), dim3(kThreads), 0, s, X, n * d, d,
+                           p.stride, pmin, pmax, flag);
+    else if (d % 4 == 0 && (uintptr_t)X % 16 == 0)
+        hipLaunchKernelGGL(k_minmax_wide<4>, dim3(p.blocks), dim3(kThreads), 0, s, X, n, d,
+                           p.rows_per_block, pmin, pmax, flag);
+    else
+        hipLaunchKernelGGL(k_minmax_wide<1>, dim3(p.blocks), dim3(kThreads), 0, s, X, n, d,
+                           p.rows_per_block, pmin, pmax, flag);
+    hipLaunchKernelGGL(k_minmax_final, dim3(d), dim3(256), 0, s, pmin, pmax, (int)p.blocks, d, mins,
+                       maxs);
+}
+
+void launch_apply(hipStream_t s, const Plan &p, const float *X, int64_t n, int d,
+                  const float *mins, const float *maxs, float *S) {
+    if (p.narrow)
+        hipLaunchKernelGGL(k_apply_narrow, dim3(p.blocks), dim3(kThreads), 0, s, X, n * d, d,
+                           p.stride, mins, maxs, S);
+    else if (d % 4 == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)S % 16 == 0)
+        hipLaunchKernelGGL(k_apply_wide<4>, dim3(p.blocks), dim3(kThreads), 0, s, X, n, d,
+                           p.rows_per_block, mins, maxs, S);
+    else
+        hipLaunchKernelGGL(k_apply_wide<1>, dim3(p.blocks), dim3(kThreads), 0, s, X, n, d,
+                           p.rows_per_block, mins, maxs, S);
 }
 
 }  // namespace
@@ -410,19 +443,7 @@ subkm_status minmax_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, f
     Plan p = plan_for(n, d);
     float *part = (float *)ctx_scratch(ctx, SC_MM_PART, sizeof(float) * 2 * p.blocks * d);
     if (!part) return SUBKM_ENOMEM;
-    float *pmin = part, *pmax = part + p.blocks * d;
-    if (p.narrow)
-        hipLaunchKernelGGL(k_minmax_narrow, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X,
-                           n * d, d, p.stride, pmin, pmax, flag);
-    else if (d % 4 == 0 && (uintptr_t)X % 16 == 0)
-        hipLaunchKernelGGL(k_minmax_wide<4>, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n,
-                           d, p.rows_per_block, pmin, pmax, flag);
-    else
-        hipLaunchKernelGGL(k_minmax_wide<1>, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n,
-                           d, p.rows_per_block, pmin, pmax, flag);
-    SUBKM_LAUNCHED(ctx);
-    hipLaunchKernelGGL(k_minmax_final, dim3(d), dim3(256), 0, ctx->stream, pmin,
-                       pmax, (int)p.blocks, d, mins, maxs);
+    launch_minmax(ctx->stream, p, X, n, d, part, part + p.blocks * d, flag, mins, maxs);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
@@ -440,17 +461,8 @@ subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, fl
         SUBKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
         if (*h) return set_err(ctx, SUBKM_EINVAL, "input contains NaN or infinite values");
     }
-    Plan p = plan_for(n, d);
     ProfScope ps(ctx, PK_SCALE);
-    if (p.narrow)
-        hipLaunchKernelGGL(k_apply_narrow, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X,
-                           n * d, d, p.stride, mins, maxs, S);
-    else if (d % 4 == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)S % 16 == 0)
-        hipLaunchKernelGGL(k_apply_wide<4>, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n, d,
-                           p.rows_per_block, mins, maxs, S);
-    else
-        hipLaunchKernelGGL(k_apply_wide<1>, dim3(p.blocks), dim3(kThreads), 0, ctx->stream, X, n, d,
-                           p.rows_per_block, mins, maxs, S);
+    launch_apply(ctx->stream, plan_for(n, d), X, n, d, mins, maxs, S);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
