@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-runs", type=int, default=24, help="oracle Lloyd runs in the CPU sample")
+    ap.add_argument("--cpu-runs", type=int, default=4,
+                    help="oracle Lloyd runs per CPU thread in the CPU sample")
     ap.add_argument("--serve-jobs", type=int, default=400, help="measured jobs of the served stream")
     ap.add_argument("--serve-warmup", type=int, default=40, help="warm-up jobs of the served stream")
     ap.add_argument("--no-serve", action="store_true", help="skip the served stream")
@@ -59,7 +60,7 @@ def parse():
     ap.add_argument("--no-unequal", action="store_true",
                     help="skip the Algorithm 2 measurements")
     ap.add_argument("--no-error-report", action="store_true",
-                    help="skip the oracle error report of the precision workload")
+                    help="skip the oracle error reports (mid and precision workloads)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of known "
                          "traffic for calibrating HBM counters)")
@@ -100,21 +101,121 @@ def assign_flops(n, d, k, assigns):
     return 2.0 * d * k * n * assigns
 
 
-def cpu_baseline(job, runs: int):
-    """The oracle (single-threaded FP64 C) on `runs` local Lloyd runs of the
-    workload's shape: n_r = N scaled points, k_local centers from the first
-    k points, the same iteration limit and tolerance.  Returns the Lloyd
-    point-iterations per second it achieved."""
+def host_cpu():
+    """Host CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def cpu_baseline(job, runs_per_thread: int):
+    """The oracle (single-threaded FP64 C, as it stands) on local Lloyd runs
+    of the workload's shape: n_r = N scaled points, k_local centers from the
+    first k points, the same iteration limit and tolerance.  Timed twice:
+    one run after another on one core, and P concurrent threads (P = the
+    cores this process may use, at most 16) each working through its own
+    runs (the oracle's C calls release the interpreter lock; the runs are
+    independent, as on the GPU).  Returns both rates in Lloyd
+    point-iterations per second."""
+    import concurrent.futures as cf
     import oracle
-    S, _, _ = oracle.scale(job.X[: runs * job.N])
-    t_total, pi = 0.0, 0
-    for r in range(runs):
-        X = S[r * job.N:(r + 1) * job.N].astype(np.float64)
-        t0 = time.perf_counter()
-        out = oracle.lloyd(X, X[: job.k_local], job.max_iter, job.tol)
-        t_total += time.perf_counter() - t0
-        pi += job.N * out["iters"]
-    return pi / t_total, t_total, pi
+    model, avail = host_cpu()
+    P = max(1, min(16, avail))
+    total = P * runs_per_thread
+    S, _, _ = oracle.scale(job.X[: total * job.N])
+    runs = [S[r * job.N:(r + 1) * job.N].astype(np.float64) for r in range(total)]
+
+    def one(X):
+        return job.N * oracle.lloyd(X, X[: job.k_local], job.max_iter, job.tol)["iters"]
+
+    t0 = time.perf_counter()
+    pi1 = sum(one(X) for X in runs[:runs_per_thread])
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(P) as ex:
+        piP = sum(ex.map(one, runs))
+    tP = time.perf_counter() - t0
+    return {"value": piP / tP, "unit": "point-iters/s", "cores": P, "kind": "oracle",
+            "single_core_value": pi1 / t1, "cpu_model": model, "cpus_available": avail,
+            "sample": f"{total} local Lloyd runs of the workload's shape (n_r={job.N} scaled points, "
+                      f"d={job.X.shape[1]}, k={job.k_local}, <= {job.max_iter} moves, tol {job.tol}) on "
+                      f"{P} threads: {piP} point-iters in {tP:.2f} s wall; single core: "
+                      f"{runs_per_thread} of them, {pi1} point-iters in {t1:.2f} s"}
+
+
+def mid_error_report(ref, job):
+    """Error of the benchmarked results against the binary64 oracle: 8
+    sampled local runs (the oracle's own run from the same start; per run the
+    largest relative center difference, the relative objective difference,
+    the move counts and the smallest top-2 margin on the oracle's path), the
+    final run (the oracle's final stage from the GPU's local centers) and the
+    objective of all points against the final centers.  A check beside the
+    benchmark, outside its timed region."""
+    import concurrent.futures as cf
+    import oracle
+    S = ref["S"].cpu().numpy()
+    perm = ref["perm"].cpu().numpy()
+    loc = ref["local_centers"].cpu().numpy()
+    lit = ref["local_iters"].cpu().numpy()
+    lsse = ref["local_sse"].cpu().numpy()
+    fin = ref["centers"].cpu().numpy()
+    N, k, T = job.N, job.k_local, len(lit)
+    P_ = max(1, min(16, host_cpu()[1]))
+
+    def traj(X, C0):
+        C = np.array(C0, np.float64)
+        it, conv, mm = 0, False, np.inf
+        while True:
+            lab, sse, _, margin = oracle.assign(X, C)
+            f = margin[np.isfinite(margin)]
+            mm = min(mm, float(f.min()) if f.size else np.inf)
+            if it == job.max_iter or conv:
+                return C, float(sse), it, mm
+            C, shift, _ = oracle.update(X, lab, C)
+            it += 1
+            conv = shift < job.tol
+
+    def rel(a, b):
+        return float(np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b))))
+
+    sample = [int(t) for t in np.linspace(0, T - 1, 8).round()]
+
+    def local(t):
+        X = S[perm[t * N:(t + 1) * N]].astype(np.float64)
+        C, sse, it, mm = traj(X, X[:k])
+        return {"run": t, "max_rel_center_diff": rel(loc[t * k:(t + 1) * k], C),
+                "rel_sse_diff": abs(float(lsse[t]) - sse) / sse, "moves": int(lit[t]),
+                "oracle_moves": it, "oracle_min_margin": mm}
+
+    with cf.ThreadPoolExecutor(P_) as ex:
+        locs = list(ex.map(local, sample))
+        M = loc.shape[0]
+        Cf, _, fit, fmm = traj(loc.astype(np.float64), loc[::M // job.k_final][:job.k_final])
+        chunks = [(a, min(a + (1 << 16), S.shape[0])) for a in range(0, S.shape[0], 1 << 16)]
+        parts = list(ex.map(lambda ab: oracle.assign(S[ab[0]:ab[1]].astype(np.float64), fin)[:2],
+                            chunks))
+    labs = np.concatenate([p[0] for p in parts])
+    obj = float(sum(p[1] for p in parts))
+    return {"what": "binary64 oracle; local runs: the oracle's own runs from the same start; final run: "
+                    "the oracle's final stage from the GPU's local centers; objective: oracle labels of all "
+                    "points against the GPU's final centers",
+            "local_sample": locs,
+            "local_max_rel_center_diff": max(r["max_rel_center_diff"] for r in locs),
+            "local_max_rel_sse_diff": max(r["rel_sse_diff"] for r in locs),
+            "final_max_rel_center_diff": rel(fin, Cf), "final_moves_oracle": fit,
+            "final_oracle_min_margin": fmm,
+            "sse_rel_diff": abs(float(ref["sse"].cpu()[0]) - obj) / obj,
+            "label_mismatches": int((ref["labels"].cpu().numpy() != labs).sum())}
 
 
 def bench_direct(subkm, km, ref, job, two_level_ms):
@@ -393,34 +494,61 @@ def bench_precision(subkm, synth, a):
 
 
 def precision_error_report(subkm, ref, job):
-    """One Lloyd move of a sampled local run, on the GPU (split-bfloat16) and
-    in the binary64 oracle from the same float32 centers: label mismatches,
-    largest center difference, relative objective difference."""
+    """Error of the precision workload's results against the binary64
+    oracle, one Lloyd move from the same float32 centers (a whole oracle run
+    at k = 1024, d = 128 is about 10^11 operations per run): 4 sampled local
+    runs (from the GPU's returned local centers) and the final run (from the
+    GPU's final centers, on the GPU's local centers), each on the GPU
+    (split-bfloat16) and in the oracle: label mismatches, largest center
+    difference, relative objective difference; and the objective of all
+    points against the final centers.  A check beside the benchmark."""
+    import concurrent.futures as cf
     import torch
     import oracle
     S = ref["S"]
     perm = ref["perm"].cpu().numpy()
     loc = ref["local_centers"].cpu().numpy()
-    t, N, k = 5, job.N, job.k_local
-    idx = perm[t * N:(t + 1) * N]
-    P = S[torch.from_numpy(idx.astype(np.int64)).to(S.device)].contiguous()
-    C0 = loc[t * k:(t + 1) * k].copy()
-    Cd = torch.from_numpy(C0).to("cuda:0")
-    lab = torch.empty(N, dtype=torch.int32, device="cuda:0")
-    it, sse = subkm.lloyd_batched(P.reshape(-1), [(0, N, 0, 0, P.shape[1], k)], Cd, lab, 1, 0.0,
-                                  precision=subkm.PREC_BF16)
-    X64 = P.cpu().numpy().astype(np.float64)
-    lab0, _, _, _ = oracle.assign(X64, C0)
-    C1, _, _ = oracle.update(X64, lab0, C0.astype(np.float64))
-    lab1, sse1, _, margin = oracle.assign(X64, Cd.cpu().numpy())
-    g_lab = lab.cpu().numpy()
-    mism = int((g_lab != lab1).sum())
-    return {"run": t, "n": N, "k": k, "d": int(P.shape[1]),
-            "max_abs_center_diff": float(np.abs(Cd.cpu().numpy() - C1).max()),
-            "max_rel_center_diff": float(np.abs(Cd.cpu().numpy() - C1).max() / max(1e-30, np.abs(C1).max())),
-            "label_mismatches": mism,
-            "rel_sse_diff": float(abs(float(sse.cpu()[0]) - sse1) / sse1),
-            "near_ties_below_1e-6": int(np.sum(np.isfinite(margin) & (margin < 1e-6)))}
+    fin = ref["centers"].cpu().numpy()
+    N, k, d = job.N, job.k_local, int(S.shape[1])
+    T = perm.shape[0] // N
+    P_ = max(1, min(16, host_cpu()[1]))
+
+    def one_move(X32, C0):
+        n, kk = X32.shape[0], C0.shape[0]
+        Cd = torch.from_numpy(C0.copy()).to("cuda:0")
+        lab = torch.empty(n, dtype=torch.int32, device="cuda:0")
+        _, sse = subkm.lloyd_batched(torch.from_numpy(X32).to("cuda:0").reshape(-1),
+                                     [(0, n, 0, 0, d, kk)], Cd, lab, 1, 0.0, precision=subkm.PREC_BF16)
+        Cg, lg, sg = Cd.cpu().numpy(), lab.cpu().numpy(), float(sse.cpu()[0])
+        X64 = X32.astype(np.float64)
+        lab0, _, _, _ = oracle.assign(X64, C0)
+        C1, _, _ = oracle.update(X64, lab0, C0.astype(np.float64))
+        lab1, sse1, _, margin = oracle.assign(X64, Cg)
+        return {"n": n, "k": kk,
+                "max_abs_center_diff": float(np.abs(Cg - C1).max()),
+                "max_rel_center_diff": float(np.max(np.abs(Cg - C1) / np.maximum(1.0, np.abs(C1)))),
+                "label_mismatches": int((lg != lab1).sum()),
+                "rel_sse_diff": float(abs(sg - sse1) / sse1),
+                "near_ties_below_1e-6": int(np.sum(np.isfinite(margin) & (margin < 1e-6)))}
+
+    S_h = S.cpu().numpy()
+    sample = [0, T // 3, 2 * T // 3, T - 1]
+    locs = []
+    for t in sample:
+        X32 = np.ascontiguousarray(S_h[perm[t * N:(t + 1) * N]])
+        locs.append(dict(one_move(X32, loc[t * k:(t + 1) * k].copy()), run=t))
+    final = one_move(loc, fin.copy())
+    chunks = [(a, min(a + (1 << 16), S_h.shape[0])) for a in range(0, S_h.shape[0], 1 << 16)]
+    with cf.ThreadPoolExecutor(P_) as ex:
+        parts = list(ex.map(lambda ab: oracle.assign(S_h[ab[0]:ab[1]].astype(np.float64), fin)[:2],
+                            chunks))
+    labs = np.concatenate([p[0] for p in parts])
+    obj = float(sum(p[1] for p in parts))
+    return {"what": "one move from the same float32 centers on the GPU (split-bfloat16) and in the binary64 "
+                    "oracle; objective: oracle labels of all points against the GPU's final centers",
+            "d": d, "local_sample": locs, "final": final,
+            "sse_rel_diff": abs(float(ref["sse"].cpu()[0]) - obj) / obj,
+            "label_mismatches": int((ref["labels"].cpu().numpy() != labs).sum())}
 
 
 def bench_ragged(subkm, synth, a):
@@ -563,27 +691,27 @@ def main():
     dom = max(roofs, key=lambda c: prof[c][1]) if roofs else None
     roof = roofs.get(dom)
 
-    # ---- plain form at matched SSE ----
+    # ---- plain form at matched SSE: one untimed call, then the median of 3 ----
     plain = None
     if not a.no_plain:
-        torch.cuda.synchronize()
-        p0 = time.perf_counter()
-        outp = km.cluster(X, form=subkm.FORM_PLAIN, **kw)
-        torch.cuda.synchronize()
-        pw = time.perf_counter() - p0
+        km.cluster(X, form=subkm.FORM_PLAIN, **kw)
+        pts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            p0 = time.perf_counter()
+            outp = km.cluster(X, form=subkm.FORM_PLAIN, **kw)
+            torch.cuda.synchronize()
+            pts.append(time.perf_counter() - p0)
+        pw = float(np.median(pts))
         sse_plain = float(outp["sse"].cpu()[0])
-        plain = {"value": point_iters / pw, "ms_per_step": pw * 1e3, "speedup_batched": pw / (wall / a.steps),
+        plain = {"value": point_iters / pw, "ms_per_step": pw * 1e3,
+                 "ms_samples": [t * 1e3 for t in pts], "speedup_batched": pw / (wall / a.steps),
                  "sse": sse_plain, "sse_batched": sse_batched,
                  "sse_rel_diff": abs(sse_plain - sse_batched) / sse_batched,
                  "matched": abs(sse_plain - sse_batched) <= 1e-4 * sse_batched}
 
-    cpu = None
-    if not a.no_cpu:
-        rate, secs, pi = cpu_baseline(job, a.cpu_runs)
-        cpu = {"value": rate, "unit": "point-iters/s", "cores": 1, "kind": "oracle",
-               "sample": f"{a.cpu_runs} local Lloyd runs of the workload's shape (n_r={job.N} scaled points, "
-                         f"d={d}, k={job.k_local}, <= {job.max_iter} moves, tol {job.tol}); "
-                         f"{pi} point-iters in {secs:.1f} s"}
+    cpu = None if a.no_cpu else cpu_baseline(job, a.cpu_runs)
+    err = None if a.no_error_report else mid_error_report(ref, job)
 
     direct = None if a.no_direct else bench_direct(subkm, km, ref, job, ms_per_step)
     unequal = None if a.no_unequal else bench_unequal(subkm, km, X, ref, st_warm, job, kw, ms_per_step)
@@ -612,7 +740,7 @@ def main():
         "kernels_ms_per_step": {c: v[1] / a.steps for c, v in prof.items() if v[0]},
         "roofline": roof, "roofline_other": {c: v for c, v in roofs.items() if c != dom},
         "plain": plain, "cpu_baseline": cpu,
-        "sse": sse_batched,
+        "sse": sse_batched, "error_vs_oracle": err,
         "direct": direct, "unequal": unequal, "paper_sweep": sweep, "serving": serving, "precision": precision, "ragged": ragged,
     }
     print(json.dumps(line))
