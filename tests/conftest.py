@@ -18,3 +18,14 @@ def oracle():
     import oracle as _oracle
     _oracle.build()
     return _oracle
+
+
+@pytest.fixture(scope="module")
+def km():
+    """The package's shared context on cuda:0.  At the end of every module
+    the context is synchronised, which reports a persistent Lloyd launch of
+    that module whose barrier gave up."""
+    import paper_1412_1947_amd as pkg
+    ctx = pkg.context(0)
+    yield ctx
+    ctx.synchronize()

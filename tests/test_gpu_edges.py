@@ -14,12 +14,6 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-@pytest.fixture(scope="module")
-def km():
-    import paper_1412_1947_amd as pkg
-    return pkg.context(0)
-
-
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 

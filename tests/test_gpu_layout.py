@@ -12,12 +12,6 @@ import synth
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def km():
-    import paper_1412_1947_amd as pkg
-    return pkg.context(0)
-
-
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 

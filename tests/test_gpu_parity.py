@@ -10,17 +10,12 @@ import numpy as np
 import pytest
 import torch
 
+import protocol
 import synth
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-
-
-@pytest.fixture(scope="module")
-def km():
-    import paper_1412_1947_amd as pkg
-    return pkg.context(0)
 
 
 def dev(a):
@@ -294,6 +289,10 @@ def run_batch(km, runs_np, ks, max_iter, tol, form=0, precision=0):
 
 
 def test_lloyd_batched_matches_oracle_trajectory(km, oracle):
+    # whole runs against the oracle's own trajectories (the comparison
+    # protocol of tests/protocol.py): every run free of near ties must give
+    # the oracle's centers, objective and move count; at least 10 of the 12
+    # runs are such runs here; every run passes the shadow step
     rng = np.random.default_rng(21)
     runs, ks = [], []
     for j in range(12):
@@ -303,15 +302,79 @@ def test_lloyd_batched_matches_oracle_trajectory(km, oracle):
         runs.append(oracle.scale(X)[0])
         ks.append(int(rng.integers(1, 40)))
     out, iters, sse = run_batch(km, runs, ks, 15, 1e-6)
+    trajs = protocol.trajectories(oracle, [(X.astype(np.float64), X[:k]) for X, k in zip(runs, ks)],
+                                  15, 1e-6)
+    compared = 0
     for r, (X, k) in enumerate(zip(runs, ks)):
-        ref = oracle.lloyd(X.astype(np.float64), X[:k], 15, 1e-6)
-        # with no near tie on the oracle's path the trajectories coincide
         C, lab = out[r]
-        lab_ref, _, _, margin = oracle.assign(X.astype(np.float64), ref["centers"])
-        if np.all(margin[np.isfinite(margin)] > 1e-6) and abs(iters[r] - ref["iters"]) == 0:
-            assert rel_err(C, ref["centers"]) <= TOL, r
-            assert abs(sse[r] - ref["sse"]) <= TOL * ref["sse"], r
-            assert np.array_equal(lab, ref["labels"]), r
+        ref = oracle.lloyd(X.astype(np.float64), X[:k], 15, 1e-6)
+        # the step-by-step trajectory is oracle.lloyd itself
+        assert np.array_equal(ref["centers"], trajs[r]["centers"]) and ref["iters"] == trajs[r]["iters"]
+        if protocol.check_independent(C, sse[r], iters[r], trajs[r], 1e-6, f"run {r}"):
+            compared += 1
+            if iters[r] == trajs[r]["iters"]:
+                assert np.array_equal(lab, trajs[r]["labels"]), r
+    assert compared >= 10, compared
+    protocol.shadow(km, oracle, runs, [o[0] for o in out], what="trajectory runs")
+
+
+def test_back_to_back_calls_without_sync(km, oracle):
+    # the calls never synchronise: a long call first (its work keeps the
+    # stream busy, so the plan copies of the calls after it queue behind
+    # it), then eight batched calls with different run layouts issued back
+    # to back, more than the four slots of the plan staging ring; each must
+    # give the bits of the same call made alone, with a sync after it
+    rng = np.random.default_rng(9)
+    cases = []
+    for j in range(8):
+        runs, ks = [], []
+        for q in range(int(rng.integers(1, 6))):
+            n = int(rng.integers(200, 4000))
+            d = int(rng.choice([4, 8, 16, 32]))
+            X, _ = synth.gaussian_blobs(n, d, 6, seed=900 + 10 * j + q, sigma=0.5)
+            runs.append(oracle.scale(X)[0])
+            ks.append(int(rng.integers(2, min(n, 200))))
+        cases.append((runs, ks))
+
+    def prepare(runs, ks):
+        # device buffers made up front: torch's copies from host memory
+        # synchronise, the library's calls must not
+        specs, x_off, c_off, l_off = [], 0, 0, 0
+        for X, k in zip(runs, ks):
+            n, d = X.shape
+            specs.append((x_off, n, c_off, l_off, d, k))
+            x_off, c_off, l_off = x_off + n * d, c_off + k * d, l_off + n
+        P = torch.cat([dev(X.reshape(-1)) for X in runs])
+        C0 = torch.cat([dev(X[:k].reshape(-1)) for X, k in zip(runs, ks)])
+        return specs, P, C0, l_off
+
+    def issue(specs, P, C0, l_off):
+        C = C0.clone()
+        lab = torch.empty(l_off, dtype=torch.int32, device="cuda:0")
+        it, sse = km.lloyd_batched(P, specs, C, lab, 12, 1e-6)
+        return C, lab, it, sse
+
+    bufs = [prepare(runs, ks) for runs, ks in cases]
+    alone = []
+    for b in bufs:
+        r = issue(*b)
+        torch.cuda.synchronize()
+        alone.append([host(t) for t in r])
+    big = synth.mid(n=1 << 18)
+    Sb = oracle.scale(big.X)[0]
+    nb = Sb.shape[0] // 32
+    long_specs = [(q * nb * 16, nb, q * 256 * 16, q * nb, 16, 256) for q in range(32)]
+    Cl = torch.cat([dev(Sb[q * nb:q * nb + 256].reshape(-1)) for q in range(32)])
+    lab_l = torch.empty(Sb.shape[0], dtype=torch.int32, device="cuda:0")
+    Pl = dev(Sb.reshape(-1))
+    torch.cuda.synchronize()
+    km.lloyd_batched(Pl, long_specs, Cl, lab_l, 30, 0.0)
+    queued = [issue(*b) for b in bufs]
+    torch.cuda.synchronize()
+    km.synchronize()
+    for j, (q, a) in enumerate(zip(queued, alone)):
+        for t, ref in zip(q, a):
+            assert np.array_equal(host(t), ref), j
 
 
 def test_plain_equals_batched_and_deterministic(km, oracle):
@@ -436,40 +499,187 @@ def test_forms_agree_on_large_k(km, oracle):
 
 
 # ------------------------------------------------ full-size workload, bench config
+def _assign_chunked(oracle, S, C, chunk=1 << 16):
+    """oracle.assign over all rows of S in chunks on a thread pool; the
+    objective is summed in chunk order."""
+    import concurrent.futures as cf
+    C = np.asarray(C, np.float64)
+    parts = [(a, min(a + chunk, S.shape[0])) for a in range(0, S.shape[0], chunk)]
+
+    def one(ab):
+        lab, sse, _, _ = oracle.assign(S[ab[0]:ab[1]].astype(np.float64), C)
+        return lab, sse
+    with cf.ThreadPoolExecutor(protocol.threads()) as ex:
+        res = list(ex.map(one, parts))
+    return np.concatenate([r[0] for r in res]), float(sum(r[1] for r in res))
+
+
+def _golden_subclusters(name):
+    """Digests of the oracle's scaling and subclustering of a full-size
+    workload (tests/golden/make_fullsize_subclusters.py)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "fullsize_subclusters.json")
+    if not os.path.exists(path):
+        return {"x": None}
+    with open(path) as f:
+        return json.load(f)[name]
+
+
+def _digest(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@pytest.mark.timeout(900)
 def test_mid_workload_full_size(km, oracle):
-    """The benchmark's workload at full size, through the same call the
-    benchmark times: scaling and subclustering bit-exact against the oracle;
-    sampled local runs checked by one oracle step from the GPU's centers."""
+    """The benchmark's workload at full size (2^20 x 16, N = 8192, 256 local
+    and 64 final centers, <= 30 moves or a move below 1e-6), through the
+    same call the benchmark times, against the oracle:
+    * scaling, subclusters (perm, offsets) bit-exact;
+    * all 128 local runs: the oracle's own trajectory from the same start;
+      every run without a near tie on that path must give the oracle's
+      centers, objective and move count; every run passes the shadow step
+      from the GPU's returned centers;
+    * the final run: the oracle's final stage on the GPU's local centers
+      (same protocol), and, when every local run agreed, the oracle's whole
+      method on its own local centers;
+    * labels and objective of all 2^20 points against the final centers."""
     job = synth.mid()
-    X = dev(job.X)
-    out = km.cluster(X, job.N, job.k_local, job.k_final, job.max_iter, job.tol,
+    n, d = job.X.shape
+    out = km.cluster(dev(job.X), job.N, job.k_local, job.k_final, job.max_iter, job.tol,
                      intermediates=True, stats=True)
     S = host(out["S"])
-    Sr, _, _ = oracle.scale(job.X)
-    assert np.array_equal(S, Sr)
-    perm = host(out["perm"])
-    permr, offr, _ = oracle.subcluster(Sr, job.N)
-    assert np.array_equal(perm, permr)
+    perm = host(out["perm"]).astype("<i8")
+    gold = _golden_subclusters("mid")
+    if _digest(job.X) == gold["x"]:
+        # the oracle's own scaling and subclustering, by their digests
+        assert _digest(S) == gold["s"]
+        assert _digest(perm) == gold["perm"]
+        Sr, permr = S, perm
+        offr = np.append(np.arange(0, n, job.N, dtype=np.int64), n)
+        assert _digest(offr.astype("<i8")) == gold["offsets"]
+    else:
+        Sr, _, _ = oracle.scale(job.X)
+        assert np.array_equal(S, Sr)
+        permr, offr, _ = oracle.subcluster(Sr, job.N)
+        assert np.array_equal(perm, permr)
+    T, k = len(offr) - 1, job.k_local
+    st = out["stats"]
+    assert st["T"] == T == 128 and st["M"] == T * k
     loc = host(out["local_centers"])
     lit = host(out["local_iters"])
     lsse = host(out["local_sse"])
-    k = job.k_local
-    for t in (0, 63, 127):
-        P = Sr[permr[offr[t]:offr[t + 1]]].astype(np.float64)
-        C = loc[t * k:(t + 1) * k]
-        # labels and objective of the returned centers
-        lab, obj, _, _ = oracle.assign(P, C)
-        assert abs(lsse[t] - obj) <= TOL * obj
-        assert 1 <= lit[t] <= job.max_iter
-        # the returned centers are (within the tolerance) where one more
-        # oracle move takes them when the run stopped on the tolerance
-        nxt, shift, _ = oracle.update(P, lab, C)
-        if lit[t] < job.max_iter:
-            assert shift < 1e-4
+    Ps = [Sr[permr[offr[t]:offr[t + 1]]] for t in range(T)]
+    trajs = protocol.trajectories(oracle, [(P.astype(np.float64), P[:k]) for P in Ps],
+                                  job.max_iter, job.tol)
+    compared, agree = 0, 0
+    for t in range(T):
+        Ct = loc[t * k:(t + 1) * k]
+        compared += protocol.check_independent(Ct, lsse[t], lit[t], trajs[t], job.tol, f"local {t}")
+        agree += rel_err(Ct, trajs[t]["centers"]) <= TOL
+    near = [t for t in range(T) if trajs[t]["min_margin"] <= protocol.NEAR_TIE]
+    print(f"mid local runs: {compared} of {T} compared on independent trajectories, "
+          f"{len(near)} with a near tie on the oracle's path, {agree} within 1e-5 of the oracle")
+    assert compared + len(near) == T
+    assert compared >= T // 2
+    protocol.shadow(km, oracle, Ps, [loc[t * k:(t + 1) * k] for t in range(T)], what="mid local")
+
+    # final run: the oracle's final stage from the GPU's local centers
+    M = T * k
+    stride = M // job.k_final
     fin = host(out["centers"])
-    lab, obj, _, _ = oracle.assign(Sr.astype(np.float64), fin)
+    ftraj = protocol.trajectory(oracle, loc.astype(np.float64), loc[::stride][:job.k_final],
+                                job.max_iter, job.tol)
+    fcomp = protocol.check_independent(fin, None, st["final_iters"], ftraj, job.tol, "final")
+    protocol.shadow(km, oracle, [loc], [fin], what="mid final")
+    print(f"mid final run: {st['final_iters']} moves (oracle {ftraj['iters']}), "
+          f"{'compared' if fcomp else 'near tie: shadow step only'}")
+    if agree == T:
+        # the whole method on the oracle's own local centers
+        oloc = np.concatenate([tr["centers"] for tr in trajs])
+        otraj = protocol.trajectory(oracle, oloc, oloc[::stride][:job.k_final], job.max_iter, job.tol)
+        if otraj["min_margin"] > protocol.NEAR_TIE and ftraj["min_margin"] > protocol.NEAR_TIE:
+            assert rel_err(fin, otraj["centers"]) <= TOL
+            assert protocol.iters_agree(st["final_iters"], otraj, job.tol)
+
+    # labels of all points and the objective
+    lab, obj = _assign_chunked(oracle, Sr, fin)
     assert np.array_equal(host(out["labels"]), lab)
     assert abs(host(out["sse"])[0] - obj) <= TOL * obj
+
+
+@pytest.mark.timeout(900)
+def test_ragged_workload_full_size(km, oracle):
+    """The ragged batch at full size (512 runs, n log-uniform in [1k, 64k],
+    half d = 8 and half d = 32, k = min(ceil(n / 32), 1024), <= 30 moves or a
+    move below 1e-6), every run scaled by the library and all of them in one
+    batched call, as the benchmark times it:
+    * every run's scaling bit-exact;
+    * every run's labels equal the oracle's assignment against the run's
+      returned centers, objective within 1e-5;
+    * 48 sampled runs of up to 12k points (both d) against the oracle's own
+      trajectories, per the comparison protocol;
+    * the shadow step on those and on the 8 largest runs (k = 1024, more
+      than 2^15 points: the runs beyond the on-chip budget)."""
+    import concurrent.futures as cf
+    rs = synth.ragged()
+    Ss, parts, cinit, specs = [], [], [], []
+    x_off = c_off = l_off = 0
+    for X, k in zip(rs.X, rs.k):
+        Sg, _, _ = km.scale(dev(X))
+        n, d = Sg.shape
+        Ss.append(Sg)
+        parts.append(Sg.reshape(-1))
+        cinit.append(Sg[:k].reshape(-1))
+        specs.append((x_off, n, c_off, l_off, d, k))
+        x_off += n * d
+        c_off += k * d
+        l_off += n
+    C = torch.cat(cinit)
+    lab = torch.empty(l_off, dtype=torch.int32, device="cuda:0")
+    km.profile(True)
+    it, sse = km.lloyd_batched(torch.cat(parts), specs, C, lab, rs.max_iter, rs.tol)
+    Ch, lh, ih, sh = host(C), host(lab), host(it), host(sse)
+    prof = km.profile_read()
+    km.profile(False)
+    # one call, both paths: the runs that fit on chip in the persistent
+    # kernel, the others in per-phase launches
+    assert prof["lloyd_fused"][0] >= 1 and prof["assign"][0] >= 1, prof
+    with cf.ThreadPoolExecutor(protocol.threads()) as ex:
+        Sr = list(ex.map(lambda X: oracle.scale(X)[0], rs.X))
+    for j, Sg in enumerate(Ss):
+        assert np.array_equal(host(Sg), Sr[j]), j
+    del Ss, parts, cinit
+    Cs = [Ch[co:co + k * d].reshape(k, d) for (xo, n, co, lo, d, k) in specs]
+    labs = [lh[lo:lo + n] for (xo, n, co, lo, d, k) in specs]
+
+    def assign_run(j):
+        return oracle.assign(Sr[j].astype(np.float64), Cs[j])[:2]
+    with cf.ThreadPoolExecutor(protocol.threads()) as ex:
+        refs = list(ex.map(assign_run, range(len(specs))))
+    for j, (lr, sr) in enumerate(refs):
+        assert np.array_equal(labs[j], lr), j
+        assert abs(sh[j] - sr) <= TOL * sr, j
+        assert 1 <= ih[j] <= rs.max_iter, j
+    ns = np.array([sp[1] for sp in specs])
+    dd = np.array([sp[4] for sp in specs])
+    rng = np.random.default_rng(8)
+    sample = []
+    for dv in (8, 32):
+        pool = np.flatnonzero((dd == dv) & (ns <= 12000))
+        sample += sorted(rng.choice(pool, 24, replace=False).tolist())
+    trajs = protocol.trajectories(
+        oracle, [(Sr[j].astype(np.float64), Sr[j][:rs.k[j]]) for j in sample], rs.max_iter, rs.tol)
+    compared = sum(protocol.check_independent(Cs[j], sh[j], ih[j], tr, rs.tol, f"ragged run {j}")
+                   for j, tr in zip(sample, trajs))
+    print(f"ragged: {compared} of {len(sample)} sampled runs compared on independent trajectories")
+    assert compared >= len(sample) // 2
+    big = np.argsort(ns)[-8:].tolist()
+    assert all(ns[j] > 1 << 15 and rs.k[j] == 1024 for j in big)
+    assert any(dd[j] == 32 for j in big)
+    shadow = sample + big
+    protocol.shadow(km, oracle, [Sr[j] for j in shadow], [Cs[j] for j in shadow], what="ragged")
 
 
 # ------------------------------------------- split-bfloat16 path (wide runs, BF16)
@@ -544,62 +754,54 @@ def _keys(S, L):
 def test_precision_workload_full_size(km, oracle):
     """The precision workload (n = 2^22, d = 128, N = 32768, 1024 local and
     256 final centers) through cluster() with split-bfloat16 products:
-    scaling bit-exact; the subclustering a partition whose sampled rounds are
-    exactly the N smallest (key, index) of the remaining points; sampled
+    scaling and the whole subclustering (perm of all 2^22 points) bit-exact
+    against the oracle's, by the SHA-256 digests the oracle's own run wrote
+    (its 128 rounds take minutes on one core; the oracle runs live only when
+    the input differs from the one the digests were made from); sampled
     local runs and a sample of the final labels against the oracle."""
     import paper_1412_1947_amd as subkm
     job = synth.precision()
     n, d = job.X.shape
+    gold = _golden_subclusters("precision")
     X = dev(job.X)
     out = km.cluster(X, job.N, job.k_local, job.k_final, job.max_iter, job.tol,
                      precision=subkm.PREC_BF16, intermediates=True, stats=True)
     S = host(out["S"])
-    Sr, _, _ = oracle.scale(job.X)
-    assert np.array_equal(S, Sr)
     del X
-    perm = host(out["perm"]).astype(np.int64)
+    perm = host(out["perm"]).astype("<i8")
     N, T = job.N, out["stats"]["T"]
     assert T == n // N
+    if _digest(job.X) == gold["x"]:
+        assert _digest(S) == gold["s"]
+        assert _digest(perm) == gold["perm"]
+        assert _digest(np.arange(0, n + 1, N, dtype="<i8")) == gold["offsets"]
+        Sr = S
+    else:
+        Sr, _, _ = oracle.scale(job.X)
+        assert np.array_equal(S, Sr)
+        permr, offr, _ = oracle.subcluster(Sr, N)
+        assert np.array_equal(perm, permr)
     assert np.array_equal(np.sort(perm), np.arange(n))
-    removed = np.zeros(n, dtype=bool)
-    for t in range(T):
-        G = perm[t * N:(t + 1) * N]
-        assert np.all(np.diff(G) > 0), t            # ascending original index
-        if t in (0, 1, 64, T - 1):
-            R = np.flatnonzero(~removed)
-            L = Sr[R].min(axis=0)
-            key = _keys(Sr[R], L)
-            inG = np.isin(R, G)
-            kg, ig = key[inG], R[inG]
-            kr, ir = key[~inG], R[~inG]
-            if kr.size:
-                # lexicographic (key, index): max over G below min over the rest
-                jg = np.lexsort((ig, kg))[-1]
-                jr = np.lexsort((ir, kr))[0]
-                assert (kg[jg], ig[jg]) < (kr[jr], ir[jr]), t
-        removed[G] = True
     loc = host(out["local_centers"])
     lsse = host(out["local_sse"])
     lit = host(out["local_iters"])
     k = job.k_local
-    for t in (0, T - 1):
-        P = Sr[perm[t * N:(t + 1) * N]].astype(np.float64)
-        C = loc[t * k:(t + 1) * k]
-        lab, obj, _, _ = oracle.assign(P, C)
+    sample = (0, T // 2, T - 1)
+    Ps = [np.ascontiguousarray(Sr[perm[t * N:(t + 1) * N]]) for t in sample]
+    Cs = [loc[t * k:(t + 1) * k] for t in sample]
+    for t, P, C in zip(sample, Ps, Cs):
+        _, obj, _, _ = oracle.assign(P.astype(np.float64), C)
         assert abs(lsse[t] - obj) <= TOL * obj
         assert 1 <= lit[t] <= job.max_iter
+    # the shadow step of sampled local runs and of the final run, with
+    # split-bfloat16 products: labels identical to binary64 arithmetic
     fin = host(out["centers"])
-    labels = host(out["labels"])
-    rng = np.random.default_rng(3)
-    sample = np.sort(rng.choice(n, 1 << 15, replace=False))
-    lab, _, _, _ = oracle.assign(Sr[sample].astype(np.float64), fin)
-    assert np.array_equal(labels[sample], lab)
-    # objective of the returned labels, summed in binary64
-    tot = 0.0
-    for a in range(0, n, 1 << 19):
-        diff = Sr[a:a + (1 << 19)].astype(np.float64) - fin.astype(np.float64)[labels[a:a + (1 << 19)]]
-        tot += float(np.sum(np.einsum("ij,ij->i", diff, diff)))
-    assert abs(host(out["sse"])[0] - tot) <= TOL * tot
+    protocol.shadow(km, oracle, Ps, Cs, precision=subkm.PREC_BF16, what="precision local")
+    protocol.shadow(km, oracle, [loc], [fin], precision=subkm.PREC_BF16, what="precision final")
+    # labels of all 2^22 points and the objective against the final centers
+    lab, obj = _assign_chunked(oracle, Sr, fin)
+    assert np.array_equal(host(out["labels"]), lab)
+    assert abs(host(out["sse"])[0] - obj) <= TOL * obj
 
 
 # ------------------------------------------------------------ memory and serving
