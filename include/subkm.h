@@ -88,6 +88,26 @@ subkm_status subkm_synchronize(subkm_ctx *ctx);
 subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
                          float *S, float *mins, float *maxs);
 
+/* subkm_scale without any allocation, for callers that cannot allocate
+ * memory: code inside HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, arithmetic, bits and errors as
+ * subkm_scale; it calls no hipMalloc, hipFree or other allocating routine
+ * and leaves the context's scratch untouched (subkm_device_bytes does not
+ * change).  Its scratch -- the non-finite flag and the per-block min/max
+ * partials -- is one static device array of 4 MiB that every GPU the
+ * library runs on holds from the library's first use there until the
+ * process ends; its per-device address is looked up when a context is
+ * created.  The grid of the min/max pass is capped so that its partials
+ * always fit (2 d floats per block), so every n and d that subkm_scale
+ * accepts fits; a shape that did not would be refused with SUBKM_EINVAL.
+ * The array is shared by all calls on one GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (two contexts or streams of the
+ * same device) race and must be serialised by the caller.  Like subkm_scale
+ * it synchronises the stream once (the non-finite check), so it cannot be
+ * captured into a graph itself.                                          */
+subkm_status subkm_scale_noalloc(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
+                                 float *S, float *mins, float *maxs);
+
 /* Min-max scaling of a column-major X (Sec. V flattens the data row by row
  * or column by column; this is the column-major input): attribute j of point
  * i at X[j * n + i].  S, mins, maxs and the arithmetic are those of

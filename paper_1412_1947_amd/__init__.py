@@ -86,7 +86,8 @@ class JobResult(ctypes.Structure):
 
 
 EXPORTS = ("subkm_create", "subkm_destroy", "subkm_last_error", "subkm_set_stream",
-           "subkm_synchronize", "subkm_scale", "subkm_scale_colmajor", "subkm_subcluster",
+           "subkm_synchronize", "subkm_scale", "subkm_scale_noalloc", "subkm_scale_colmajor",
+           "subkm_subcluster",
            "subkm_subcluster_unequal",
            "subkm_lloyd_batched",
            "subkm_cluster", "subkm_cluster_sizes", "subkm_cluster_footprint", "subkm_device_bytes",
@@ -125,6 +126,8 @@ def lib():
             L.subkm_synchronize.restype = st
             L.subkm_scale.argtypes = [P, P, i64, i32, P, P, P]
             L.subkm_scale.restype = st
+            L.subkm_scale_noalloc.argtypes = [P, P, i64, i32, P, P, P]
+            L.subkm_scale_noalloc.restype = st
             L.subkm_scale_colmajor.argtypes = [P, P, i64, i32, P, P, P]
             L.subkm_scale_colmajor.restype = st
             L.subkm_subcluster.argtypes = [P, P, i64, i32, i64, i32, i32, P, P, P, P]
@@ -296,6 +299,20 @@ class Context:
         self._bind_stream()
         fn = lib().subkm_scale_colmajor if layout == LAYOUT_COL else lib().subkm_scale
         self._check(fn(self._h, _ptr(X), n, d, _ptr(S), _ptr(mins), _ptr(maxs)))
+        return S, mins, maxs
+
+    def scale_noalloc(self, X, S, mins, maxs):
+        """Min-max scaling through the allocation-free entry point: the
+        caller passes every output (S n x d, mins and maxs d, float32)."""
+        X = self._dev(X, torch.float32, "X")
+        n, d = X.shape
+        S = self._dev(S, torch.float32, "S")
+        mins = self._dev(mins, torch.float32, "mins")
+        maxs = self._dev(maxs, torch.float32, "maxs")
+        if tuple(S.shape) != (n, d) or mins.numel() != d or maxs.numel() != d:
+            raise ValueError("S must be n x d and mins, maxs of d values")
+        self._bind_stream()
+        self._check(lib().subkm_scale_noalloc(self._h, _ptr(X), n, d, _ptr(S), _ptr(mins), _ptr(maxs)))
         return S, mins, maxs
 
     def subcluster(self, S, N: int, landmark_mode: int = 0, landmarks: bool = False,

@@ -220,6 +220,7 @@ subkm_status subkm_create(int device, void *stream, subkm_ctx **out) {
         subkm_destroy(c);
         return set_err(nullptr, SUBKM_ENOMEM, "device allocation of the context's flags failed");
     }
+    noalloc_scratch_init(c);
     *out = c;
     return SUBKM_OK;
 }
@@ -365,6 +366,16 @@ subkm_status subkm_scale(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, f
     REQUIRE(ctx, X && S && mins && maxs, "NULL array argument");
     DeviceGuard g(ctx->device);
     return scale_impl(ctx, X, n, d, S, mins, maxs, true);
+}
+
+subkm_status subkm_scale_noalloc(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
+                                 float *mins, float *maxs) {
+    CHECK_CTX(ctx);
+    REQUIRE(ctx, n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
+    REQUIRE(ctx, d >= 1 && d <= 4096, "d must be in [1, 4096]");
+    REQUIRE(ctx, X && S && mins && maxs, "NULL array argument");
+    DeviceGuard g(ctx->device);
+    return scale_noalloc_impl(ctx, X, n, d, S, mins, maxs);
 }
 
 subkm_status subkm_scale_colmajor(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,

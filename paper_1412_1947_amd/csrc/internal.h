@@ -123,6 +123,10 @@ struct subkm_ctx {
     // persistent Lloyd launch whose barrier gave up; subkm_synchronize
     // reports and clears it.
     int *sticky = nullptr;
+    // device address of the static scratch of subkm_scale_noalloc on this
+    // context's device (nullptr when the lookup failed, with its error)
+    void *noalloc_scratch = nullptr;
+    hipError_t noalloc_err = hipSuccess;
     hipEvent_t ev[8] = {};
     bool prof_on = false;
     std::vector<ProfRec> prof_pending;
@@ -241,6 +245,12 @@ void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision,
 void subcluster_scratch_requests(int64_t n, int32_t d, size_t *req);
 void unequal_scratch_requests(int64_t n, int32_t d, int64_t m, size_t *req);
 size_t minmax_scratch_bytes(int64_t n, int32_t d);
+// Look up this device's address of the static scratch of the
+// allocation-free scaling (ctx->device current); sets ctx->noalloc_scratch.
+void noalloc_scratch_init(subkm_ctx *ctx);
+// Scaling with the static scratch: no allocation of any kind.
+subkm_status scale_noalloc_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
+                                float *mins, float *maxs);
 bool cluster_requests(int64_t n, int32_t d, int64_t N, int32_t k_local, int32_t k_final,
                       size_t *req);
 // bytes ctx_scratch reserves for a request of `bytes`

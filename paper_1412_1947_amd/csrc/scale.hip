@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 
 #pragma clang fp contract(off)
@@ -387,6 +388,8 @@ void launch_apply(hipStream_t s, const Plan &p, const float *X, int64_t n, int d
                            p.rows_per_block, mins, maxs, S);
 }
 
+__global__ void k_clear_word(int *w) { *w = 0; }
+
 }  // namespace
 
 size_t minmax_cm_scratch_bytes(int64_t n, int32_t d) {
@@ -463,6 +466,76 @@ subkm_status scale_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, fl
     }
     ProfScope ps(ctx, PK_SCALE);
     launch_apply(ctx->stream, plan_for(n, d), X, n, d, mins, maxs, S);
+    SUBKM_LAUNCHED(ctx);
+    return SUBKM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free scaling (subkm_scale_noalloc).  Its scratch -- the
+// non-finite flag in the first 256 bytes, then the min/max partials -- is
+// this file-scope device array, which every GPU the library runs on holds
+// once, at its own address, until the process ends.  In host code the
+// array's name is not a device address: the address is looked up per
+// device with hipGetSymbolAddress when a context is created, and only that
+// address is handed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+constexpr size_t kNoAllocFlagBytes = 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocDevices] = {};
+hipError_t g_noalloc_err[kNoAllocDevices] = {};
+bool g_noalloc_done[kNoAllocDevices] = {};
+}  // namespace
+
+void noalloc_scratch_init(subkm_ctx *ctx) {
+    // the caller has made ctx->device current
+    const int dev = ctx->device;
+    ctx->noalloc_scratch = nullptr;
+    if (dev < 0 || dev >= kNoAllocDevices) return;
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (!g_noalloc_done[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            hipGetLastError();
+            p = nullptr;
+        }
+        g_noalloc_ptr[dev] = p;
+        g_noalloc_err[dev] = e;
+        g_noalloc_done[dev] = true;
+    }
+    ctx->noalloc_scratch = g_noalloc_ptr[dev];
+    ctx->noalloc_err = g_noalloc_err[dev];
+}
+
+subkm_status scale_noalloc_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d, float *S,
+                                float *mins, float *maxs) {
+    if (!ctx->noalloc_scratch)
+        return set_err(ctx, SUBKM_EDEVICE, "the static scratch of device %d has no address: %s",
+                       ctx->device, hipGetErrorString(ctx->noalloc_err));
+    // the wide form's grid is capped so that its partials fit; the narrow
+    // form needs at most 2 * 2110 * 63 floats
+    const int64_t cap = (int64_t)((kNoAllocScratchBytes - kNoAllocFlagBytes) / (2 * sizeof(float) * d));
+    const Plan p = plan_for(n, d, std::max<int64_t>(1, cap));
+    const size_t need = kNoAllocFlagBytes + sizeof(float) * 2 * (size_t)p.blocks * d;
+    if (need > kNoAllocScratchBytes)
+        return set_err(ctx, SUBKM_EINVAL, "n = %lld, d = %d needs %zu bytes of scratch; the static "
+                       "scratch holds %zu", (long long)n, d, need, kNoAllocScratchBytes);
+    hipStream_t s = ctx->stream;
+    int *flag = (int *)ctx->noalloc_scratch;
+    float *part = (float *)((unsigned char *)ctx->noalloc_scratch + kNoAllocFlagBytes);
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(1), 0, s, flag);
+    SUBKM_LAUNCHED(ctx);
+    launch_minmax(s, p, X, n, d, part, part + p.blocks * d, flag, mins, maxs);
+    SUBKM_LAUNCHED(ctx);
+    int h = 0;
+    SUBKM_HIP(ctx, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    SUBKM_HIP(ctx, hipStreamSynchronize(s));
+    if (h) return set_err(ctx, SUBKM_EINVAL, "input contains NaN or infinite values");
+    launch_apply(s, p, X, n, d, mins, maxs, S);
     SUBKM_LAUNCHED(ctx);
     return SUBKM_OK;
 }
