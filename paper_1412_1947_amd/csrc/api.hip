@@ -282,7 +282,8 @@ subkm_status subkm_tune_count(subkm_ctx *ctx, int32_t *entries) {
     return SUBKM_OK;
 }
 
-static const char kTuneMagic[] = "subkm-tune 1";
+static const char kTuneMagic[] = "subkm-tune 2";
+static const char kTuneMagic1[] = "subkm-tune 1";  // no tiles-per-block field (2 then)
 
 subkm_status subkm_tune_save(subkm_ctx *ctx, const char *path) {
     CHECK_CTX(ctx);
@@ -292,7 +293,8 @@ subkm_status subkm_tune_save(subkm_ctx *ctx, const char *path) {
     std::fprintf(f, "%s\n", kTuneMagic);
     for (const auto &e : ctx->tune) {
         for (int i = 0; i < 5; ++i) std::fprintf(f, "%llx ", (unsigned long long)e.first.v[i]);
-        std::fprintf(f, "%d %d %.6f\n", e.second.sched.gcap, e.second.sched.bdiv, e.second.ms);
+        std::fprintf(f, "%d %d %d %.6f\n", e.second.sched.gcap, e.second.sched.bdiv, e.second.sched.tpb,
+                     e.second.ms);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? SUBKM_OK : set_err(ctx, SUBKM_EINVAL, "cannot write %s", path);
@@ -304,25 +306,30 @@ subkm_status subkm_tune_load(subkm_ctx *ctx, const char *path) {
     FILE *f = std::fopen(path, "r");
     if (!f) return set_err(ctx, SUBKM_EINVAL, "cannot open %s", path);
     char head[64] = {};
-    if (!std::fgets(head, sizeof head, f) || std::strncmp(head, kTuneMagic, sizeof kTuneMagic - 1) != 0) {
+    const bool read = std::fgets(head, sizeof head, f) != nullptr;
+    const bool v2 = read && std::strncmp(head, kTuneMagic, sizeof kTuneMagic - 1) == 0;
+    const bool v1 = read && std::strncmp(head, kTuneMagic1, sizeof kTuneMagic1 - 1) == 0;
+    if (!v1 && !v2) {
         std::fclose(f);
         return set_err(ctx, SUBKM_EINVAL, "%s is not a schedule file", path);
     }
     std::map<TuneKey, TuneEntry> got;
     for (;;) {
         unsigned long long v[5];
-        int gcap = 0, bdiv = 0;
+        int gcap = 0, bdiv = 0, tpb = 2;
         double ms = 0.0;
-        const int nf = std::fscanf(f, "%llx %llx %llx %llx %llx %d %d %lf", &v[0], &v[1], &v[2], &v[3],
-                                   &v[4], &gcap, &bdiv, &ms);
+        const int nf = v2 ? std::fscanf(f, "%llx %llx %llx %llx %llx %d %d %d %lf", &v[0], &v[1], &v[2],
+                                        &v[3], &v[4], &gcap, &bdiv, &tpb, &ms)
+                          : std::fscanf(f, "%llx %llx %llx %llx %llx %d %d %lf", &v[0], &v[1], &v[2],
+                                        &v[3], &v[4], &gcap, &bdiv, &ms);
         if (nf == EOF) break;
-        if (nf != 8 || gcap < 1 || bdiv < 1 || bdiv > 64) {
+        if (nf != (v2 ? 9 : 8) || gcap < 1 || bdiv < 1 || bdiv > 64 || tpb < 1 || tpb > 64) {
             std::fclose(f);
             return set_err(ctx, SUBKM_EINVAL, "%s: malformed entry", path);
         }
         TuneKey k;
         for (int i = 0; i < 5; ++i) k.v[i] = v[i];
-        got[k] = TuneEntry{LloydSched{gcap, bdiv}, ms};
+        got[k] = TuneEntry{LloydSched{gcap, bdiv, tpb}, ms};
     }
     std::fclose(f);
     for (const auto &e : got) ctx->tune[e.first] = e.second;
@@ -481,7 +488,7 @@ bool cluster_requests(int64_t n, int32_t d, int64_t N, int32_t k_local, int32_t 
     need(SC_CL_FINAL, (size_t)M * 4 + 128);
     need(SC_MM_PART, minmax_scratch_bytes(n, d));
     need(SC_MM_FLAG, 256);
-    subcluster_scratch_requests(n, d, req);
+    subcluster_scratch_requests(n, d, N, req);
     std::vector<subkm_run> runs((size_t)T);
     int64_t m = 0;
     for (int64_t t = 0; t < T; ++t) {

@@ -75,10 +75,12 @@ struct CoopGate {
 };
 
 // Schedule of the batched Lloyd form (results do not depend on it): the
-// largest number of blocks per run and the divisor of the co-resident grid.
+// largest number of blocks per run, the divisor of the co-resident grid, and
+// the fewest 256-point tiles a block of a split run takes per move.
 struct LloydSched {
     int32_t gcap;
     int32_t bdiv;
+    int32_t tpb;
 };
 struct TuneKey {
     uint64_t v[5];
@@ -242,7 +244,7 @@ subkm_status lloyd_impl(subkm_ctx *ctx, const float *P, const subkm_run *runs, i
 // req[SC_COUNT]); used for admission control.
 void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision, int32_t form,
                             int32_t max_iter, int cu_count, size_t *req);
-void subcluster_scratch_requests(int64_t n, int32_t d, size_t *req);
+void subcluster_scratch_requests(int64_t n, int32_t d, int64_t N, size_t *req);
 void unequal_scratch_requests(int64_t n, int32_t d, int64_t m, size_t *req);
 size_t minmax_scratch_bytes(int64_t n, int32_t d);
 // Look up this device's address of the static scratch of the

@@ -48,7 +48,7 @@ constexpr int kSumW = 4096;         // int64 center sums held in LDS (fused path
 constexpr int kMaxK = 1024;         // centers per run in the fused path
 constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path)
 constexpr long long kSpinLimit = 1ll << 26;
-constexpr int kMaxG = 64;          // blocks per run in the batched form
+constexpr int kMaxG = 128;         // blocks per run in the batched form
 constexpr int kExB = 16;           // exchange loads in flight per thread
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
@@ -249,17 +249,15 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
         b2[g] = INFINITY;
         i1[g] = 0;
     }
-    // the bias ||c - m||^2 of the lane's four output rows (centers
-    // c0 + 4 kk + r) starts the accumulator; the centers are scaled by -2
-    // (exact), so the accumulator ends as v itself
-    for (int c0 = 0; c0 < k; c0 += 16) {
+    // The products of a block of 16 centers: the bias ||c - m||^2 of the
+    // lane's four output rows (centers c0 + 4 kk + r) starts the
+    // accumulator; the centers are scaled by -2 (exact), so the accumulator
+    // ends as v itself.  Rows of sC are padded to k + 16 and cn holds +inf
+    // up to the next multiple of 16, so every read stays inside the arrays;
+    // centers past k are zeroed by a bit mask (the loads stay unconditional,
+    // with no branch and wait each) and their values are never selected.
+    auto products = [&](int c0, floatx4 (&acc)[4]) {
         const int cA = c0 + col;
-        // rows of sC are padded to k + 16 and cn holds +inf up to the next
-        // multiple of 16, so these reads stay inside the arrays; values of
-        // centers past k are discarded by the selects
-        // every load is unconditional (the padding keeps it in bounds) and
-        // the padding centers are masked to zero with a bit mask, so the
-        // loads are not turned into branches with a wait each
         const uint32_t vmask = cA < k ? 0xFFFFFFFFu : 0u;
         float ca[KQ];
 #pragma unroll
@@ -269,24 +267,32 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
         }
         const floatx4 cinit = {L.cn[c0 + 4 * kk], L.cn[c0 + 4 * kk + 1], L.cn[c0 + 4 * kk + 2],
                                L.cn[c0 + 4 * kk + 3]};
-        int32_t ci[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) ci[r] = c0 + 4 * kk + r;
+        for (int g = 0; g < 4; ++g) acc[g] = cinit;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            floatx4 acc = cinit;
+        for (int q = 0; q < KQ; ++q)
 #pragma unroll
-            for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[q], xb[g][q], acc, 0, 0, 0);
+            for (int g = 0; g < 4; ++g) acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[q], xb[g][q], acc[g], 0, 0, 0);
+    };
+    // The two smallest values of each point's four lanes and the first
+    // index of the smallest, centers in ascending order (strict <).
+    auto select = [&](int c0, const floatx4 (&acc)[4]) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float v = acc[r];
+                const float v = acc[g][r];
                 // b1 <= b2 always holds, so the new second-smallest is the median
                 b2[g] = __builtin_amdgcn_fmed3f(v, b1[g], b2[g]);
                 const bool lt = v < b1[g];
                 b1[g] = lt ? v : b1[g];
-                i1[g] = lt ? ci[r] : i1[g];
+                i1[g] = lt ? c0 + 4 * kk + r : i1[g];
             }
-        }
+    };
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        floatx4 acc[4];
+        products(c0, acc);
+        select(c0, acc);
     }
     const float Rc = L.s_R;
     const float Ku = 2.0f * (float)(D + 5) * 5.9604645e-8f;
@@ -1216,7 +1222,7 @@ subkm_status persist_d(subkm_ctx *ctx, int d, bool mf, int blocks, const float *
 // blocks are free.  Every block's task list follows the global assignment
 // order, so the per-run barriers cannot wait on each other in a cycle.
 void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blocks,
-              bool exchange, int gcap, std::vector<int32_t> &G,
+              bool exchange, int gcap, int tpb, std::vector<int32_t> &G,
               std::vector<std::vector<Task>> &per_block) {
     std::vector<int> order(rr);
     auto work = [&](int r) { return (double)dr[r].n * dr[r].k * dr[r].d; };
@@ -1231,10 +1237,11 @@ void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blo
     for (int r : order) {
         const int64_t tiles = (dr[r].n + kAT - 1) / kAT;
         int64_t g = std::llround(work(r) / std::max(target, 1.0));
-        // with a per-iteration exchange, every block reads the G partial sums:
-        // keep G small and at least two tiles per block
+        // with a per-iteration exchange every move ends in two barriers of
+        // the run's G blocks: keep G at most gcap and at least tpb tiles per block
         const int64_t gmax =
-            exchange ? std::min<int64_t>(std::min(gcap, kMaxG), std::max<int64_t>(1, tiles / 2)) : tiles;
+            exchange ? std::min<int64_t>(std::min(gcap, kMaxG), std::max<int64_t>(1, tiles / std::max(1, tpb)))
+                     : tiles;
         g = std::max<int64_t>(1, std::min<int64_t>({g, gmax, (int64_t)blocks}));
         G[r] = (int32_t)g;
         std::vector<Slot> take;
@@ -1427,7 +1434,7 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
             const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cap, tiles));
             std::vector<int32_t> G(R, 1);
             std::vector<std::vector<Task>> pb;
-            schedule(rr, dr, blocks, max_iter > 0, sc.gcap, G, pb);
+            schedule(rr, dr, blocks, max_iter > 0, sc.gcap, sc.tpb, G, pb);
             for (int r : rr) {
                 DevRun &D = dr[r];
                 D.G = G[r];
@@ -1616,7 +1623,8 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
 // the shape, and the call is made once more with it.  Results are identical
 // under every schedule, so tuning only changes the time.
 namespace {
-const LloydSched kCandidates[] = {{64, 1}, {32, 1}, {16, 1}, {64, 2}, {32, 2}, {16, 2}};
+const LloydSched kCandidates[] = {{64, 1, 2}, {32, 1, 2}, {16, 1, 2}, {64, 2, 2},
+                                  {32, 2, 2}, {16, 2, 2}, {128, 1, 1}, {64, 1, 1}};
 
 TuneKey shape_key(const subkm_run *runs, int32_t R, int32_t precision, int32_t max_iter) {
     int64_t npts = 0;
@@ -1702,7 +1710,7 @@ void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision,
         const int64_t t = ceil_div(dr[r].n, kAT);
         if (batched && dr[r].fused) {
             ds.push_back({dr[r].d, dr[r].mf});
-            const int64_t g = max_iter > 0 ? std::min<int64_t>(kMaxG, std::max<int64_t>(1, t / 2)) : t;
+            const int64_t g = max_iter > 0 ? std::min<int64_t>(kMaxG, std::max<int64_t>(1, t)) : t;
             n_tasks += g;
             if (max_iter > 0 && g > 1)
                 part_words += (2 * g + 2) * ((int64_t)dr[r].k * dr[r].d + dr[r].k);

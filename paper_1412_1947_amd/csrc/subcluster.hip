@@ -1117,6 +1117,899 @@ __global__ void k_offsets(int64_t *off, int64_t T, int64_t N, int64_t n) {
     if (t <= T) off[t] = t < T ? t * N : n;
 }
 
+// ---------------------------------------------------------------------------
+// Batches of rounds that share a landmark.
+//
+// Removing a subcluster leaves the landmark (the attribute-wise minimum of
+// the remaining points) unchanged while, for every attribute, some point
+// holding its minimum stays.  While the landmark stays, so do the keys, and
+// the subclusters of rounds t, t+1, ..., t+q-1 are the consecutive N-blocks
+// of one (key, position) order of the points remaining at round t.  The
+// keys pass records, per attribute, the largest key among the points that
+// hold the minimum (mk); every point with a smaller key ranks below that
+// holder, so with c = #{keys < min_j mk_j} the landmark surely stays for
+// rounds t+1 .. t + floor(c / N).  One batch therefore selects the ranks N,
+// 2N, ..., qN at once (q <= kQMax, q - 1 <= floor(c / N), and the last round
+// always left to a slot of its own), sorts the points into q subclusters
+// and the rest in one compaction, and the rounds t+1 .. t+q-1 have nothing
+// left to do.  With a fixed landmark every batch takes the largest q.
+//
+// The launch sequence stays static (it is captured once into a HIP graph):
+// every round t keeps its four launches, and act[t] says whether round t
+// starts a batch (the number of batches before it, which also selects the
+// ping-pong buffers) or lies inside an earlier one (kNoRound: every block
+// returns at once).  A batch at round t writes act[t + q]; nothing else
+// writes act during the sequence, so no launch reads a word another one of
+// the same launch writes.
+constexpr int kQMax = 9;                   // subclusters one batch emits at most
+constexpr uint32_t kNoRound = 0xFFFFFFFFu;  // act[t]: round t lies inside a batch
+constexpr uint32_t kCselCap = 8192;        // (class, block) counts k_sel2m keeps in LDS
+
+struct BatchPlan {
+    uint32_t q;                 // subclusters of the active batch
+    uint32_t lchange;           // 0: the landmark surely stays after the batch
+    uint32_t bin[kQMax];        // level-1 bin of rank (i + 1) N
+    uint32_t below[kQMax];      // points in bins below bin[i]
+    uint32_t cnt[kQMax];        // points in bin[i]
+    uint32_t thr_pos[kQMax];    // threshold of group i: (thr_key[i], thr_pos[i])
+    double thr_key[kQMax];
+};
+
+// Buffers of the batched sequence (kernel arguments by value).
+struct RoundBufs {
+    const float *S;
+    float *P;
+    int32_t *perm;
+    float *landmarks;            // nullable, T x d
+    int32_t *rem[2];             // remaining positions -> index, by batch parity
+    double *keys[2];             // keys of the remaining points, by batch parity
+    uint32_t *Lb;                // 3 x d landmarks as ordered bits (batch count mod 3)
+    unsigned long long *mk;      // 2 x d largest holder keys (nullptr: fixed landmark)
+    const float *L0;             // first landmark
+    const float *colmax;
+    SelState *st;
+    BatchPlan *bp;
+    uint32_t *act;               // T + 1 words
+    uint32_t *hist1;             // level-1 replicas and group counts (the keys pass)
+    uint32_t *hist2;             // kQMax level-2 histograms
+    uint32_t *blockcnt;          // (kQMax + 1) x nbs
+    uint32_t *blockoff;          // (kQMax + 1) x nbs
+    double *ckey;
+    uint32_t *cpos;
+    uint32_t nbs;                // stride of the per-class block arrays
+    int32_t d;
+};
+
+// The keys pass of a batch (k_keys_fast with the buffers of batch act[t]).
+template <int M, int D, bool V4, int PP>
+__global__ __launch_bounds__(kT) void k_keys_b(RoundBufs B, uint32_t t, uint32_t nrem, int fixed) {
+    constexpr int W = V4 ? 4 : 1;
+    constexpr int NV = D / W;
+    static_assert(D % W == 0 && D <= kT, "row width");
+    typedef typename VecT<W>::type V;
+    const uint32_t a = B.act[t];
+    if (a == kNoRound) return;
+    __shared__ float sL[D];
+    __shared__ double s_term[D];
+    __shared__ uint32_t h[kBins];
+    __shared__ uint32_t s_base, s_sh;
+    const int32_t *rem = t == 0 ? nullptr : B.rem[a & 1];
+    double *keys = B.keys[a & 1];
+    const uint32_t *Lcur = (t == 0 || fixed) ? nullptr : B.Lb + (a % 3) * D;
+    uint32_t *Lnext = fixed ? nullptr : B.Lb + ((a + 1) % 3) * D;
+    const uint32_t *Lprev = (t > 0 && !fixed) ? B.Lb + ((a + 2) % 3) * D : nullptr;
+    uint32_t *Lsave = (t == 0 && !fixed) ? B.Lb + (a % 3) * D : nullptr;
+    unsigned long long *mk = B.mk ? B.mk + (a & 1) * D : nullptr;
+    const unsigned long long *mk_prev = B.mk ? B.mk + ((a + 1) & 1) * D : nullptr;
+    const int reuse = t == 0 ? 0 : fixed ? 2 : 1;
+    const uint32_t stride = gridDim.x * kT;
+    const uint32_t p0 = blockIdx.x * kT + threadIdx.x;
+    bool same = reuse == 2;
+    if (reuse == 1) {
+        uint32_t diff = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) diff |= Lcur[j] ^ Lprev[j];
+        same = diff == 0;
+    }
+    int32_t idx[PP];
+    double kold[PP];
+    if (same) {
+#pragma unroll
+        for (int u = 0; u < PP; ++u) {
+            kold[u] = keys[min(p0 + u * stride, nrem - 1)];
+            idx[u] = 0;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < PP; ++u) {
+            const uint32_t p = min(p0 + u * stride, nrem - 1);
+            idx[u] = rem ? rem[p] : (int32_t)p;
+            kold[u] = 0.0;
+        }
+    }
+    const int jl = threadIdx.x < D ? (int)threadIdx.x : D - 1;
+    const uint32_t lraw = (Lcur ? Lcur : (const uint32_t *)B.L0)[jl];
+    const float cm = B.colmax[jl];
+    const float lj = Lcur ? ordered_float(lraw) : __uint_as_float(lraw);
+    const double prev = t > 0 ? B.st->thr_key : 0.0;
+    V x[PP][NV];
+    if (!same) {
+#pragma unroll
+        for (int u = 0; u < PP; ++u)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) x[u][q] = ((const V *)(B.S + (int64_t)idx[u] * D))[q];
+    }
+    for (int i = threadIdx.x; i < kBins; i += kT) h[i] = 0;
+    if (threadIdx.x < D) {
+        sL[threadIdx.x] = lj;
+        s_term[threadIdx.x] = key_term<M>((double)cm - (double)lj);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) b = b + s_term[j];
+        uint32_t vb, vs;
+        vmap_params(b, prev, t > 0, &vb, &vs);
+        s_base = vb;
+        s_sh = vs;
+        if (blockIdx.x == 0) {
+            B.st->base = vb;
+            B.st->vshift = vs;
+            B.st->ncand = 0;
+        }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x < D) {
+        if (B.landmarks) B.landmarks[(int64_t)t * D + threadIdx.x] = sL[threadIdx.x];
+        if (Lnext) Lnext[threadIdx.x] = 0xFFFFFFFFu;
+        if (Lsave) Lsave[threadIdx.x] = ordered_bits(sL[threadIdx.x]);
+        if (mk && same) mk[threadIdx.x] = mk_prev[threadIdx.x];
+    }
+    const uint32_t base = s_base, vsh = s_sh;
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+        const uint32_t p = p0 + u * stride;
+        double key = kold[u];
+        if (!same) {
+            key = 0.0;
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+#pragma unroll
+                for (int c = 0; c < W; ++c) {
+                    const double dlt = (double)vget(x[u][q], c) - (double)sL[q * W + c];
+                    key = key + key_term<M>(dlt);
+                }
+        }
+        if (p < nrem) {
+            if (!same) keys[p] = key;
+            atomicAdd(&h[vmap(key, base, vsh) >> 12], 1u);
+            if (mk && !same) {
+                uint32_t hold = 0;
+#pragma unroll
+                for (int q = 0; q < NV; ++q)
+#pragma unroll
+                    for (int c = 0; c < W; ++c)
+                        hold |= (__float_as_uint(vget(x[u][q], c)) == __float_as_uint(sL[q * W + c])
+                                     ? 1u : 0u) << (q * W + c);
+                if (hold) {
+                    const unsigned long long kb = (unsigned long long)__double_as_longlong(key);
+                    for (int j = 0; j < D; ++j)
+                        if ((hold >> j) & 1u) atomicMax(&mk[j], kb);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    flush_hist(h, B.hist1);
+}
+
+typedef void (*KeysBFn)(RoundBufs, uint32_t, uint32_t, int);
+
+template <int M, int D, bool V4>
+KeysBFn keys_b_pp(int pp) {
+    return pp >= 4 ? k_keys_b<M, D, V4, 4> : pp == 2 ? k_keys_b<M, D, V4, 2> : k_keys_b<M, D, V4, 1>;
+}
+
+template <int M>
+KeysBFn keys_b_m(int d, bool vec4, int pp) {
+    switch (d) {
+        case 1: return keys_b_pp<M, 1, false>(pp);
+        case 2: return keys_b_pp<M, 2, false>(pp);
+        case 4: return vec4 ? keys_b_pp<M, 4, true>(pp) : nullptr;
+        case 8: return vec4 ? keys_b_pp<M, 8, true>(pp) : nullptr;
+        case 16: return vec4 ? keys_b_pp<M, 16, true>(pp) : nullptr;
+        case 32: return vec4 ? keys_b_pp<M, 32, true>(pp) : nullptr;
+        default: return nullptr;
+    }
+}
+
+KeysBFn keys_b_for(int metric, int d, bool vec4, int pp) {
+    return metric ? keys_b_m<1>(d, vec4, pp) : keys_b_m<0>(d, vec4, pp);
+}
+
+// Plan of a batch, computed by every block of k_candm alike from the
+// level-1 histogram: the number of subclusters q, and for every target rank
+// (i + 1) N the level-1 bin holding it with the counts below and in it.
+// The group counts (64 bins a group) first; then one wave per target (and
+// one for the holder key) finds its group with a ballot, reads that group's
+// 64 bins and finds its bin with a scan and a ballot.
+struct PlanLds {
+    uint32_t part[kT];
+    uint32_t gpre[kGroups + 1];      // exclusive prefix of the group totals
+    uint32_t tbin[kQMax], tbelow[kQMax], tcnt[kQMax];
+    uint32_t hkbelow;                // points in bins below the holder key's bin
+    unsigned long long hk;           // smallest of the largest holder keys
+    uint32_t q;
+};
+
+__device__ void batch_plan(const RoundBufs &B, uint32_t a, uint32_t t, uint32_t T, uint32_t N,
+                           uint32_t base, uint32_t vsh, PlanLds &Lp) {
+    static_assert(kT == 8 * 64 && kRep == 16 && kGroups == 64, "two replicas per thread");
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t *grp = B.hist1 + kRep * kBins;
+    Lp.part[threadIdx.x] = grp[w * kGroups + lane] + grp[(w + 8) * kGroups + lane];
+    if (threadIdx.x == 0) {
+        unsigned long long hk = ~0ull;
+        if (B.mk) {
+            const unsigned long long *mk = B.mk + (a & 1) * B.d;
+            for (int j = 0; j < B.d; ++j) hk = min(hk, mk[j]);
+        }
+        Lp.hk = hk;
+        Lp.hkbelow = 0;
+    }
+    __syncthreads();
+    if (w == 0) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) c += Lp.part[r * 64 + lane];
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        Lp.gpre[lane] = inc - c;
+        if (lane == 63) Lp.gpre[64] = inc;
+    }
+    __syncthreads();
+    const uint32_t qcap = min((uint32_t)kQMax, T - 1 - t);
+    // item i < qcap: target rank (i + 1) N; item kQMax: the holder key
+    for (uint32_t i = w; i <= (uint32_t)kQMax; i += kT / 64) {
+        const bool target = i < qcap;
+        const bool holder = i == (uint32_t)kQMax && B.mk != nullptr;
+        if (!target && !holder) continue;
+        uint32_t g, hb = 0;
+        const uint32_t rank = target ? (i + 1) * N : 0u;
+        if (target) {
+            const uint64_t m = __ballot(Lp.gpre[lane] < rank && rank <= Lp.gpre[lane + 1]);
+            g = m ? (uint32_t)(__ffsll((unsigned long long)m) - 1) : 0u;
+        } else {
+            hb = vmap(__longlong_as_double((long long)Lp.hk), base, vsh) >> 12;
+            g = hb >> 6;
+        }
+        uint32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < kRep; ++r) c += B.hist1[r * kBins + g * 64 + lane];
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        const uint32_t lo = Lp.gpre[g] + inc - c;  // points below bin g * 64 + lane
+        if (target) {
+            const uint64_t m = __ballot(lo < rank && rank <= lo + c);
+            const int b = m ? __ffsll((unsigned long long)m) - 1 : 0;
+            if (lane == b) {
+                Lp.tbin[i] = g * 64 + b;
+                Lp.tbelow[i] = lo;
+                Lp.tcnt[i] = c;
+            }
+        } else if (lane == (int)(hb & 63)) {
+            Lp.hkbelow = lo;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t q = qcap;
+        // every key in a bin below the holder key's bin is below it
+        if (B.mk) q = min(q, 1 + Lp.hkbelow / N);
+        Lp.q = max(q, 1u);
+    }
+    __syncthreads();
+}
+
+// Candidate pass of a batch: the plan, then per block of kBS positions the
+// points surely in each class (bin strictly between the boundary bins) and
+// the candidates (a boundary bin) with their level-2 histograms, one per
+// distinct boundary bin (the slot of its first target).
+__global__ __launch_bounds__(kT) void k_candm(RoundBufs B, uint32_t t, uint32_t T, uint32_t nrem,
+                                              uint32_t N) {
+    const uint32_t a = B.act[t];
+    if (a == kNoRound) return;
+    __shared__ PlanLds Lp;
+    __shared__ double s_ck[kBS];
+    __shared__ uint32_t s_cp[kBS];
+    __shared__ uint32_t s_cc[kQMax + 1];
+    __shared__ uint32_t s_nc, s_base;
+    const double *keys = B.keys[a & 1];
+    const uint32_t base = B.st->base, vsh = B.st->vshift;
+    const int lane = threadIdx.x & 63;
+    const uint32_t p0 = blockIdx.x * kBS;
+    constexpr int kPer = kBS / kT;
+    double kb[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const uint32_t p = p0 + u * kT + threadIdx.x;
+        kb[u] = p < nrem ? keys[p] : 0.0;
+    }
+    if (threadIdx.x <= (uint32_t)kQMax) s_cc[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_nc = 0;
+    batch_plan(B, a, t, T, N, base, vsh, Lp);
+    const uint32_t q = Lp.q;
+    if (blockIdx.x == 0 && threadIdx.x < q) {
+        B.bp->bin[threadIdx.x] = Lp.tbin[threadIdx.x];
+        B.bp->below[threadIdx.x] = Lp.tbelow[threadIdx.x];
+        B.bp->cnt[threadIdx.x] = Lp.tcnt[threadIdx.x];
+        if (threadIdx.x == 0) B.bp->q = q;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const uint32_t p = p0 + u * kT + threadIdx.x;
+        const bool in = p < nrem;
+        const uint32_t v = in ? vmap(kb[u], base, vsh) : 0u;
+        const uint32_t b = v >> 12;
+        uint32_t lo = 0, hi = 0;
+        for (uint32_t i = 0; i < q; ++i) {
+            lo += Lp.tbin[i] < b ? 1u : 0u;
+            hi += Lp.tbin[i] <= b ? 1u : 0u;
+        }
+        const bool sure = in && lo == hi;
+        // sure points: one ballot per class present in the wave
+        uint64_t rest = __ballot(sure);
+        while (rest) {
+            const int l0 = __ffsll((unsigned long long)rest) - 1;
+            const uint32_t c0 = __shfl(lo, l0, 64);
+            const uint64_t m = __ballot(sure && lo == c0);
+            if (lane == l0) atomicAdd(&s_cc[c0], (uint32_t)__popcll(m));
+            rest &= ~m;
+        }
+        const bool c = in && lo != hi;
+        const uint64_t m = __ballot(c);
+        if (m) {
+            const uint32_t cnt = (uint32_t)__popcll(m);
+            const uint32_t first = (uint32_t)__ffsll((unsigned long long)m) - 1;
+            uint32_t slot0 = 0;
+            if (lane == (int)first) slot0 = atomicAdd(&s_nc, cnt);
+            slot0 = __shfl(slot0, first, 64);
+            if (c) {
+                const uint32_t slot = slot0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                s_ck[slot] = kb[u];
+                s_cp[slot] = p;
+                atomicAdd(&B.hist2[lo * kBins + (v & 0xFFFu)], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t nc = s_nc;
+    if (threadIdx.x <= q) B.blockcnt[threadIdx.x * B.nbs + blockIdx.x] = s_cc[threadIdx.x];
+    if (threadIdx.x == 0) s_base = nc ? atomicAdd(&B.st->ncand, nc) : 0u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nc; i += kT) {
+        B.ckey[s_base + i] = s_ck[i];
+        B.cpos[s_base + i] = s_cp[i];
+    }
+}
+
+// Thresholds of a batch (one block).  (1) For every distinct boundary bin,
+// one wave scans its level-2 histogram (and clears it) and gives every target
+// in it the level-2 bin of its rank.  (2) One pass over the candidate list:
+// a candidate whose level-2 value differs from every target's is below or
+// above each threshold by that value alone, so its class is known and it
+// joins its compaction block's count at once; the others (the few sharing a
+// target's level-2 bin) are gathered into that target's segment of LDS.
+// (3) Exact ranks by (key, position) inside every segment give the
+// thresholds, then the segment members get their classes.  A target whose
+// level-2 bin holds too many candidates for LDS takes a radix select over
+// the list, and then one more pass classifies the members of such bins.
+// (4) Per class, one wave turns the block counts into offsets.  Then:
+// whether the landmark may move after the batch, the round of the next
+// batch, the landmarks of the rounds inside this one.
+__global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t N, uint32_t nb,
+                                               int fixed) {
+    const uint32_t a = B.act[t];
+    if (a == kNoRound) return;
+    __shared__ uint32_t sh[4], s_lch, s_anyslow;
+    __shared__ double rk[kRankCap];
+    __shared__ uint32_t rp[kRankCap];
+    __shared__ uint32_t h256[256];
+    __shared__ uint32_t csel[kCselCap];
+    __shared__ double s_tk[kQMax];
+    __shared__ uint32_t s_tp[kQMax], s_bin[kQMax], s_below[kQMax];
+    __shared__ uint32_t s_vstar[kQMax], s_need2[kQMax], s_cnt2[kQMax], s_seg[kQMax], s_fill[kQMax];
+    __shared__ uint32_t s_fast[kQMax];
+    const BatchPlan *bp = B.bp;
+    const uint32_t q = bp->q;
+    const uint32_t base = B.st->base, vsh = B.st->vshift;
+    const uint32_t ncand = B.st->ncand;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool lds_counts = (q + 1) * nb <= kCselCap;
+    for (uint32_t i = threadIdx.x; i < kCselCap; i += kST) csel[i] = 0;
+    if (threadIdx.x < q) {
+        s_bin[threadIdx.x] = bp->bin[threadIdx.x];
+        s_below[threadIdx.x] = bp->below[threadIdx.x];
+        s_fill[threadIdx.x] = 0;
+        // (found below; these values only stand if the counts were inconsistent)
+        s_vstar[threadIdx.x] = 0xFFFFFFFFu;
+        s_need2[threadIdx.x] = 1;
+        s_cnt2[threadIdx.x] = 0;
+        s_tk[threadIdx.x] = 0.0;
+        s_tp[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    auto count_cls = [&](uint32_t cls, uint32_t p) {
+        if (lds_counts) atomicAdd(&csel[cls * nb + p / kBS], 1u);
+        else atomicAdd(&B.blockcnt[cls * B.nbs + p / kBS], 1u);
+    };
+    // (1) level-2 bins: one wave per distinct boundary bin (slot = its first
+    // target); lane l holds bins 64 l .. 64 l + 63
+    for (uint32_t i0 = wv; i0 < q; i0 += kST / 64) {
+        if (i0 > 0 && s_bin[i0] == s_bin[i0 - 1]) continue;  // the same histogram
+        uint32_t *hist = B.hist2 + i0 * kBins + lane * 64;
+        constexpr int kC = 16;  // bins loaded at a time
+        uint32_t sum = 0;
+#pragma unroll
+        for (int x0 = 0; x0 < 64; x0 += kC) {
+            uint32_t h[kC];
+#pragma unroll
+            for (int x = 0; x < kC; ++x) h[x] = hist[x0 + x];
+#pragma unroll
+            for (int x = 0; x < kC; ++x) sum += h[x];
+        }
+        uint32_t inc = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        const uint32_t pre = inc - sum;
+        for (uint32_t i = i0; i < q && s_bin[i] == s_bin[i0]; ++i) {
+            const uint32_t need1 = (i + 1) * N - s_below[i];
+            if (pre < need1 && need1 <= pre + sum) {
+                uint32_t cum = pre;
+                for (int x0 = 0; x0 < 64; x0 += kC) {
+                    uint32_t h[kC];
+#pragma unroll
+                    for (int x = 0; x < kC; ++x) h[x] = hist[x0 + x];
+#pragma unroll
+                    for (int x = 0; x < kC; ++x) {
+                        if (cum < need1 && need1 <= cum + h[x]) {
+                            s_vstar[i] = (s_bin[i] << 12) | (uint32_t)(lane * 64 + x0 + x);
+                            s_need2[i] = need1 - cum;
+                            s_cnt2[i] = h[x];
+                        }
+                        cum += h[x];
+                    }
+                }
+            }
+        }
+        // cleared for the next batch (every read of this slot is above)
+#pragma unroll
+        for (int x = 0; x < 64; ++x) hist[x] = 0;
+    }
+    __syncthreads();
+    // segments: every target whose level-2 bin fits gets its own stretch of
+    // rk/rp (targets that share a level-2 bin share its members' counts:
+    // only the first of them counts them)
+    if (threadIdx.x == 0) {
+        uint32_t off = 0, slow = 0;
+        for (uint32_t i = 0; i < q; ++i) {
+            const bool fits = off + s_cnt2[i] <= (uint32_t)kRankCap;
+            s_fast[i] = fits ? 1u : 0u;
+            s_seg[i] = off;
+            if (fits) off += s_cnt2[i];
+            else slow = 1u;
+        }
+        s_anyslow = slow;
+    }
+    __syncthreads();
+    // (2) one pass over the candidates
+    for (uint32_t c0 = 0; c0 < ncand; c0 += kST * kBatch) {
+        double kk[kBatch];
+        uint32_t pp[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const uint32_t c = c0 + u * kST + threadIdx.x;
+            kk[u] = c < ncand ? B.ckey[c] : 0.0;
+            pp[u] = c < ncand ? B.cpos[c] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const uint32_t c = c0 + u * kST + threadIdx.x;
+            const bool in = c < ncand;
+            const uint32_t v = vmap(kk[u], base, vsh);
+            uint32_t cls = 0;
+            bool member = false;
+            for (uint32_t i = 0; i < q; ++i) {
+                if (v > s_vstar[i]) cls = i + 1;
+                if (in && v == s_vstar[i]) {
+                    member = true;
+                    if (s_fast[i]) {
+                        const uint32_t r = atomicAdd(&s_fill[i], 1u);
+                        if (r < s_cnt2[i]) {
+                            rk[s_seg[i] + r] = kk[u];
+                            rp[s_seg[i] + r] = pp[u];
+                        }
+                    }
+                }
+            }
+            // the value alone decides every threshold (bins are monotone in
+            // the key); neighbouring candidates come from one compaction
+            // block and mostly share a class, so the wave adds them up by
+            // (class, block) first: one atomic per distinct pair
+            const bool cnt_it = in && !member;
+            const uint32_t key = cls * nb + pp[u] / kBS;
+            uint64_t rest = __ballot(cnt_it);
+            while (rest) {
+                const int l0 = __ffsll((unsigned long long)rest) - 1;
+                const uint32_t k0 = __shfl(key, l0, 64);
+                const uint64_t m = __ballot(cnt_it && key == k0);
+                if (lane == l0) {
+                    if (lds_counts) atomicAdd(&csel[k0], (uint32_t)__popcll(m));
+                    else atomicAdd(&B.blockcnt[(k0 / nb) * B.nbs + k0 % nb], (uint32_t)__popcll(m));
+                }
+                rest &= ~m;
+            }
+        }
+    }
+    __syncthreads();
+    // (3) exact ranks inside every segment (threads over all (target, member) pairs)
+    uint32_t tot = 0;
+    for (uint32_t i = 0; i < q; ++i) tot += s_fast[i] ? s_cnt2[i] : 0u;
+    for (uint32_t x = threadIdx.x; x < tot; x += kST) {
+        uint32_t i = 0;
+        while (!(s_fast[i] && x >= s_seg[i] && x < s_seg[i] + s_cnt2[i])) ++i;
+        const double kx = rk[x];
+        const uint32_t px = rp[x];
+        uint32_t r = 0;
+        for (uint32_t y = s_seg[i]; y < s_seg[i] + s_cnt2[i]; ++y)
+            r += (rk[y] < kx || (rk[y] == kx && rp[y] < px)) ? 1u : 0u;
+        if (r == s_need2[i] - 1) {
+            s_tk[i] = kx;
+            s_tp[i] = px;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = 0; i < q; ++i) {
+        if (s_fast[i]) continue;
+        double thr_key;
+        uint32_t thr_pos;
+        slow_select(B.ckey, B.cpos, ncand, s_vstar[i], base, vsh, s_need2[i], h256, sh, &thr_key, &thr_pos);
+        if (threadIdx.x == 0) {
+            s_tk[i] = thr_key;
+            s_tp[i] = thr_pos;
+            B.st->fallback += 1;
+        }
+        __syncthreads();
+    }
+    auto exact_cls = [&](double k, uint32_t p) {
+        uint32_t cls = 0;
+        while (cls < q && !pair_le(k, p, s_tk[cls], s_tp[cls])) ++cls;
+        return cls;
+    };
+    if (!s_anyslow) {
+        // members of the fast segments, each counted once (by the first
+        // target of its level-2 bin)
+        for (uint32_t x = threadIdx.x; x < tot; x += kST) {
+            uint32_t i = 0;
+            while (!(s_fast[i] && x >= s_seg[i] && x < s_seg[i] + s_cnt2[i])) ++i;
+            if (i == 0 || s_vstar[i - 1] != s_vstar[i]) count_cls(exact_cls(rk[x], rp[x]), rp[x]);
+        }
+    } else {
+        // some level-2 bin was too large for LDS: its members (and all
+        // others sharing a target's bin) are classified by one more pass
+        for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
+            const double k = B.ckey[c];
+            const uint32_t p = B.cpos[c];
+            const uint32_t v = vmap(k, base, vsh);
+            bool member = false;
+            for (uint32_t i = 0; i < q; ++i) member = member || v == s_vstar[i];
+            if (member) count_cls(exact_cls(k, p), p);
+        }
+    }
+    // the landmark may move after the batch only if some attribute's
+    // largest holder key is <= the last threshold's key (equality counted
+    // as a move: a conservative test)
+    if (threadIdx.x == 0) s_lch = (B.mk && !fixed) ? 0u : 1u;
+    if (!lds_counts) __threadfence_block();
+    __syncthreads();
+    if (B.mk && !fixed && (int)threadIdx.x < B.d &&
+        B.mk[(a & 1) * B.d + threadIdx.x] <= (unsigned long long)__double_as_longlong(s_tk[q - 1]))
+        s_lch = 1u;
+    // (4) per class, one wave scans the block counts
+    for (uint32_t cls = wv; cls <= q; cls += kST / 64) {
+        uint32_t carry = 0;
+        for (uint32_t c0 = 0; c0 < nb; c0 += 64) {
+            const uint32_t sg = c0 + lane;
+            uint32_t v = 0;
+            if (sg < nb)
+                v = (lds_counts ? csel[cls * nb + sg] : 0u) +
+                    __hip_atomic_load(&B.blockcnt[cls * B.nbs + sg], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t inc = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += y;
+            }
+            if (sg < nb) B.blockoff[cls * B.nbs + sg] = carry + inc - v;
+            carry += __shfl(inc, 63, 64);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < q) {
+        B.bp->thr_key[threadIdx.x] = s_tk[threadIdx.x];
+        B.bp->thr_pos[threadIdx.x] = s_tp[threadIdx.x];
+    }
+    if (threadIdx.x == 0) {
+        B.bp->lchange = s_lch;
+        B.st->thr_key = s_tk[q - 1];  // centre of the next batch's key map
+        B.act[t + q] = a + 1;
+    }
+    // the rounds inside the batch share its landmark
+    if (B.landmarks)
+        for (uint32_t x = threadIdx.x; x < (q - 1) * (uint32_t)B.d; x += kST)
+            B.landmarks[((int64_t)t + 1) * B.d + x] = B.landmarks[(int64_t)t * B.d + x % B.d];
+}
+
+// Compaction of a batch (the rows of d = W * DQ attributes, early loads as in
+// k_scatter_fast): every point's class is the first group whose threshold
+// bounds it, or the rest; class c < q goes to subcluster t + c in ascending
+// index, the rest to the next remaining list with its key; the minimum of
+// the rest is folded into the next landmark when it may move.  all_sel:
+// the last round, every remaining point to subcluster t.  FULL: every row of
+// the block is requested before the classes are known (the landmark may
+// move, so the rows that stay are needed too); otherwise only the rows that
+// go to a subcluster are read, once their destinations are known.  The two
+// forms are separate instantiations so that neither holds the other's
+// registers.
+struct ScatterLds {
+    int32_t dst[kBS];  // >= 0: row within its subcluster; < 0: -(1 + slot) in rem_next
+    uint8_t cls[kBS];
+    unsigned long long wsum[kT / 64][2];
+    double tk[kQMax];
+    uint32_t tp[kQMax], off[kQMax + 1];
+    uint32_t cmin[32];
+};
+
+template <int W, int DQ, bool FULL>
+__device__ __forceinline__ void scatterm_body(const RoundBufs &B, ScatterLds &sm, uint32_t a,
+                                              uint32_t t, uint32_t nrem, uint32_t N, int all_sel,
+                                              int track_min, int fixed, uint32_t qn) {
+    typedef typename VecT<W>::type V;
+    constexpr int D = W * DQ;
+    constexpr int per = kBS / kT;
+    constexpr int RS = kT / DQ;
+    constexpr int NV = kBS / RS;
+    const int32_t *rem = t == 0 ? nullptr : B.rem[a & 1];
+    int32_t *rem_next = B.rem[(a + 1) & 1];
+    const double *keys = B.keys[a & 1];
+    double *keys_next = B.keys[(a + 1) & 1];
+    const uint32_t *Lcur = (t == 0 || fixed) ? nullptr : B.Lb + (a % 3) * D;
+    uint32_t *Lnext = fixed ? nullptr : B.Lb + ((a + 1) % 3) * D;
+    const uint32_t p0 = blockIdx.x * kBS;
+    const uint32_t cnt = min(kBS, nrem - p0);
+    const uint32_t last = p0 + cnt - 1;
+    const int j = threadIdx.x % DQ;
+    const uint32_t r0 = threadIdx.x / DQ;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t ridx[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const uint32_t p = min(p0 + r0 + u * RS, last);
+        ridx[u] = rem ? rem[p] : (int32_t)p;
+    }
+    double kq[per];
+    int32_t iq[per];
+#pragma unroll
+    for (int x = 0; x < per; ++x) {
+        const uint32_t p = min(p0 + threadIdx.x * per + x, last);
+        kq[x] = all_sel ? 0.0 : keys[p];
+        iq[x] = rem ? rem[p] : (int32_t)p;
+    }
+    V v[NV];
+    if (FULL) {
+#pragma unroll
+        for (int u = 0; u < NV; ++u) v[u] = ((const V *)(B.S + (int64_t)ridx[u] * D))[j];
+    }
+    // classes of the thread's positions, 4 bits each
+    uint32_t clsw = 0;
+#pragma unroll
+    for (int x = 0; x < per; ++x) {
+        const uint32_t lp = threadIdx.x * per + x;
+        uint32_t c = 0;
+        if (!all_sel)
+            while (c < qn && !pair_le(kq[x], p0 + lp, sm.tk[c], sm.tp[c])) ++c;
+        clsw |= (lp < cnt ? c : 15u) << (4 * x);
+    }
+    // per-class counts packed 12 bits a field, 5 fields a word (class c in
+    // word c / 5); an exclusive scan of the two words over the block gives
+    // every position its rank among the block's positions of its class
+    auto packed = [&](int w) {
+        unsigned long long pv = 0;
+#pragma unroll
+        for (int x = 0; x < per; ++x) {
+            const uint32_t c = (clsw >> (4 * x)) & 15u;
+            if (c != 15u && (int)(c / 5) == w) pv += 1ull << (12 * (c % 5));
+        }
+        return pv;
+    };
+    unsigned long long ex[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        unsigned long long xx = packed(w);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(xx, o, 64);
+            if (lane >= o) xx += y;
+        }
+        if (lane == 63) sm.wsum[wv][w] = xx;
+        ex[w] = xx;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        unsigned long long b0 = 0;
+        for (int q = 0; q < wv; ++q) b0 += sm.wsum[q][w];
+        ex[w] = b0 + ex[w] - packed(w);
+    }
+    const uint32_t stay_cap = nrem - (all_sel ? nrem : qn * N);
+    const uint32_t sel_cap = all_sel ? nrem : N;
+#pragma unroll
+    for (int x = 0; x < per; ++x) {
+        const uint32_t lp = threadIdx.x * per + x;
+        if (lp < cnt) {
+            const uint32_t c = (clsw >> (4 * x)) & 15u;
+            uint32_t rk = 0;
+#pragma unroll
+            for (int w = 0; w < 2; ++w)
+                if ((uint32_t)w == c / 5) {
+                    rk = (uint32_t)(ex[w] >> (12 * (c % 5))) & 0xFFFu;
+                    ex[w] += 1ull << (12 * (c % 5));
+                }
+            sm.cls[lp] = (uint8_t)c;
+            if (c < qn) {
+                // the guards only matter if the counts were inconsistent
+                const uint32_t row = sm.off[c] + rk;
+                const bool ok = row < sel_cap;
+                sm.dst[lp] = ok ? (int32_t)row : INT32_MIN;
+                if (ok) B.perm[((int64_t)t + c) * N + row] = iq[x];
+            } else {
+                const uint32_t slot = sm.off[qn] + rk;
+                const bool ok = slot < stay_cap;
+                sm.dst[lp] = ok ? -1 - (int32_t)slot : INT32_MIN;
+                if (ok) {
+                    rem_next[slot] = iq[x];
+                    keys_next[slot] = kq[x];
+                }
+            }
+        }
+    }
+    if (track_min && threadIdx.x < D) sm.cmin[threadIdx.x] = 0xFFFFFFFFu;
+    __syncthreads();
+    if (!FULL) {
+        // every thread loads; a row that goes to no subcluster reads row 0
+        // instead (one line for the whole grid), so the loads go out together
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const uint32_t rc = min(r0 + u * RS, cnt - 1);
+            const int32_t row = sm.dst[rc] >= 0 ? ridx[u] : 0;
+            v[u] = ((const V *)(B.S + (int64_t)row * D))[j];
+        }
+    }
+    const bool fold = FULL && track_min;
+    uint32_t mymin[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) mymin[c] = 0xFFFFFFFFu;
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const uint32_t r = r0 + u * RS;
+        if (r < cnt) {
+            const int32_t dst = sm.dst[r];
+            if (dst >= 0) {
+                const int64_t prow = ((int64_t)t + sm.cls[r]) * N + dst;
+                ((V *)(B.P + prow * D))[j] = v[u];
+            } else if (fold && dst != INT32_MIN) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) mymin[c] = min(mymin[c], ordered_bits(vget(v[u], c)));
+            }
+        }
+    }
+    if (fold) {
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+            if (mymin[c] != 0xFFFFFFFFu) atomicMin(&sm.cmin[j * W + c], mymin[c]);
+        __syncthreads();
+        if (threadIdx.x < D && sm.cmin[threadIdx.x] != 0xFFFFFFFFu)
+            atomicMin(&Lnext[threadIdx.x], sm.cmin[threadIdx.x]);
+    } else if (track_min && blockIdx.x == 0 && threadIdx.x < D) {
+        // the landmark stays (every block takes this branch)
+        Lnext[threadIdx.x] = Lcur ? Lcur[threadIdx.x] : ordered_bits(B.L0[threadIdx.x]);
+    }
+}
+
+template <int W, int DQ>
+__global__ __launch_bounds__(kT, W * DQ <= 16 ? 4 : 1) void k_scatterm(
+    RoundBufs B, uint32_t t, uint32_t nrem, uint32_t N, int all_sel, int track_min, int lm_skip,
+    int fixed) {
+    constexpr int D = W * DQ;
+    static_assert(kT % DQ == 0 && kBS % (kT / DQ) == 0, "attribute groups must tile the block");
+    static_assert(kBS / kT <= 4 && kQMax + 1 <= 10, "class counts packed 5 x 12 bits per word, 2 words");
+    static_assert(D <= 32, "row width of the early-load forms");
+    const uint32_t a = B.act[t];
+    if (a == kNoRound) return;
+    __shared__ ScatterLds sm;
+    const uint32_t qn = all_sel ? 1u : B.bp->q;
+    const uint32_t lch = all_sel ? 1u : B.bp->lchange;
+    if (!all_sel && threadIdx.x < qn) {
+        sm.tk[threadIdx.x] = B.bp->thr_key[threadIdx.x];
+        sm.tp[threadIdx.x] = B.bp->thr_pos[threadIdx.x];
+    }
+    if (threadIdx.x <= qn)
+        sm.off[threadIdx.x] = all_sel ? (threadIdx.x == 0 ? blockIdx.x * kBS : 0u)
+                                      : B.blockoff[threadIdx.x * B.nbs + blockIdx.x];
+    __syncthreads();
+    // rows that stay are read only when the next landmark may move
+    const bool full = !(lm_skip && !all_sel && (!track_min || lch == 0));
+    if (full) scatterm_body<W, DQ, true>(B, sm, a, t, nrem, N, all_sel, track_min, fixed, qn);
+    else scatterm_body<W, DQ, false>(B, sm, a, t, nrem, N, all_sel, track_min, fixed, qn);
+    if (B.mk && !all_sel && blockIdx.x == 0 && threadIdx.x < D) B.mk[((a + 1) & 1) * D + threadIdx.x] = 0ull;
+    if (!all_sel) {
+        // the level-1 replicas and group counts were last read by the
+        // candidate pass: clear them for the next batch, a slice per block
+        constexpr uint32_t words = kRep * (kBins + kGroups);
+        const uint32_t zs = (words + gridDim.x - 1) / gridDim.x;
+        const uint32_t z0 = blockIdx.x * zs, z1 = min(words, z0 + zs);
+        for (uint32_t i = z0 + threadIdx.x; i < z1; i += kT) B.hist1[i] = 0;
+    }
+}
+
+typedef void (*ScatterMFn)(RoundBufs, uint32_t, uint32_t, uint32_t, int, int, int, int);
+
+ScatterMFn scatterm_for(int d, bool vec4) {
+    if (vec4) {
+        switch (d) {
+            case 4: return k_scatterm<4, 1>;
+            case 8: return k_scatterm<4, 2>;
+            case 16: return k_scatterm<4, 4>;
+            case 32: return k_scatterm<4, 8>;
+            default: return nullptr;
+        }
+    }
+    switch (d) {
+        case 1: return k_scatterm<1, 1>;
+        case 2: return k_scatterm<1, 2>;
+        case 4: return k_scatterm<1, 4>;
+        case 8: return k_scatterm<1, 8>;
+        default: return nullptr;
+    }
+}
+
+// the landmark of the last round (a slot of its own) into the landmarks output
+__global__ void k_land_last(RoundBufs B, uint32_t t, int fixed) {
+    const uint32_t a = B.act[t];
+    if (a == kNoRound) return;
+    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= B.d) return;
+    B.landmarks[(int64_t)t * B.d + jj] =
+        (t == 0 || fixed) ? B.L0[jj] : ordered_float(B.Lb[(a % 3) * B.d + jj]);
+}
+
+__global__ void k_act_init(uint32_t *act, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) act[i] = i == 0 ? 0u : kNoRound;
+}
+
 }  // namespace
 
 
@@ -1130,25 +2023,38 @@ struct SubBufs {
     int *flag;
 };
 
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Layout of SC_SEL: the single-round state (SelState, level-1 replicas and
+// group counts, level-2 bins, block counts and offsets), then the batch
+// region (BatchPlan, act[T + 1], kQMax level-2 histograms, per-class block
+// counts and offsets).
+size_t sel_round_bytes(uint32_t nb_max) {
+    return align256(256 + sizeof(uint32_t) * (2 * (size_t)kRep * kBins + 3 * (size_t)nb_max + 64));
+}
+size_t sel_batch_bytes(int64_t T, uint32_t nb_max) {
+    return align256(sizeof(BatchPlan)) + align256(sizeof(uint32_t) * (size_t)(T + 1)) +
+           sizeof(uint32_t) * ((size_t)kQMax * kBins + 2 * (size_t)(kQMax + 1) * nb_max) + 256;
+}
+
 // Scratch of one subclustering call (allocated before any capture).
-void sub_requests(int64_t n, int32_t d, size_t *req) {
+void sub_requests(int64_t n, int32_t d, int64_t N, size_t *req) {
     auto need = [&](int slot, size_t b) { req[slot] = std::max(req[slot], b); };
     const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
-    const size_t sel_words = 2 * (size_t)kRep * kBins + 3 * (size_t)nb_max + 64;
     need(SC_KEYS, 2 * sizeof(double) * n);  // this round's keys and the carried ones
     need(SC_REM0, sizeof(int32_t) * n);
     need(SC_REM1, sizeof(int32_t) * n);
     need(SC_CAND, (sizeof(double) + sizeof(uint32_t)) * n + 64);
-    need(SC_SEL, 256 + sizeof(uint32_t) * sel_words);
+    need(SC_SEL, sel_round_bytes(nb_max) + sel_batch_bytes(ceil_div(n, std::max<int64_t>(N, 1)), nb_max));
     need(SC_LAND, sizeof(float) * (8 * (size_t)d + 64));
     need(SC_COLMAX, sizeof(float) * d + 64);
     need(SC_MM_FLAG, 256);
     need(SC_MM_PART, minmax_scratch_bytes(n, d));
 }
 
-subkm_status sub_alloc(subkm_ctx *ctx, int64_t n, int32_t d, SubBufs &b) {
+subkm_status sub_alloc(subkm_ctx *ctx, int64_t n, int32_t d, int64_t N, SubBufs &b) {
     size_t req[SC_COUNT] = {};
-    sub_requests(n, d, req);
+    sub_requests(n, d, N, req);
     b.keys = (double *)ctx_scratch(ctx, SC_KEYS, req[SC_KEYS]);
     b.rem0 = (int32_t *)ctx_scratch(ctx, SC_REM0, req[SC_REM0]);
     b.rem1 = (int32_t *)ctx_scratch(ctx, SC_REM1, req[SC_REM1]);
@@ -1163,11 +2069,116 @@ subkm_status sub_alloc(subkm_ctx *ctx, int64_t n, int32_t d, SubBufs &b) {
     return SUBKM_OK;
 }
 
+// Every launch of one subclustering call in batches of rounds (row widths
+// with the early-load kernels), in order, on ctx->stream.  The sequence is
+// the same whatever the data: T round slots, each starting a batch or
+// returning at once (act).
+subkm_status sub_enqueue_batched(subkm_ctx *ctx, const SubBufs &b, const float *S, int64_t n,
+                                 int32_t d, int64_t N, int32_t landmark_mode, int32_t metric,
+                                 float *P, int32_t *perm, int64_t *offsets, float *landmarks) {
+    const int64_t T = ceil_div(n, N);
+    hipStream_t s = ctx->stream;
+    const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
+    const bool fixed = landmark_mode == 1;
+    const bool vec4 = (d % 4) == 0 && ((uintptr_t)S % 16) == 0;
+    const bool vec4p = vec4 && ((uintptr_t)P % 16) == 0;
+    const ScatterMFn scat = scatterm_for(d, vec4p);
+    RoundBufs B;
+    std::memset(&B, 0, sizeof B);
+    B.S = S;
+    B.P = P;
+    B.perm = perm;
+    B.landmarks = landmarks;
+    B.rem[0] = b.rem0;
+    B.rem[1] = b.rem1;
+    B.keys[0] = b.keys;
+    B.keys[1] = b.keys + n;
+    B.L0 = b.land;
+    B.Lb = (uint32_t *)(b.land + d);
+    B.mk = fixed ? nullptr : (unsigned long long *)(b.land + 4 * d);
+    B.colmax = b.colmax;
+    B.st = (SelState *)b.sel;
+    uint32_t *hist1 = (uint32_t *)(b.sel + 256);
+    B.hist1 = hist1;
+    char *breg = b.sel + sel_round_bytes(nb_max);
+    B.bp = (BatchPlan *)breg;
+    B.act = (uint32_t *)(breg + align256(sizeof(BatchPlan)));
+    B.hist2 = B.act + (align256(sizeof(uint32_t) * (size_t)(T + 1)) / sizeof(uint32_t));
+    B.blockcnt = B.hist2 + (size_t)kQMax * kBins;
+    B.blockoff = B.blockcnt + (size_t)(kQMax + 1) * nb_max;
+    B.ckey = (double *)b.cand;
+    B.cpos = (uint32_t *)(b.cand + sizeof(double) * n);
+    B.nbs = nb_max;
+    B.d = d;
+    {
+        const uint32_t nz1 = (uint32_t)(2 * kRep * kBins);
+        hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(nz1, 256)), dim3(256), 0, s, hist1, nz1, 0u);
+        SUBKM_LAUNCHED(ctx);
+        const uint32_t nz2 = (uint32_t)(kQMax * kBins);
+        hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(nz2, 256)), dim3(256), 0, s, B.hist2, nz2, 0u);
+        SUBKM_LAUNCHED(ctx);
+        hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(4 * d, 256)), dim3(256), 0, s,
+                           (uint32_t *)(b.land + 4 * d), (uint32_t)(4 * d), 0u);
+        SUBKM_LAUNCHED(ctx);
+        hipLaunchKernelGGL(k_act_init, dim3(ceil_div(T + 1, 256)), dim3(256), 0, s, B.act,
+                           (uint32_t)(T + 1));
+        SUBKM_LAUNCHED(ctx);
+        SUBKM_TRY(minmax_impl(ctx, S, n, d, b.land, b.colmax, b.flag));
+        hipLaunchKernelGGL(k_offsets, dim3(ceil_div(T + 1, 256)), dim3(256), 0, s, offsets, T, N, n);
+        SUBKM_LAUNCHED(ctx);
+    }
+    uint32_t nrem = (uint32_t)n;
+    for (int64_t t = 0; t < T; ++t) {
+        const uint32_t need = (uint32_t)std::min<int64_t>(N, nrem);
+        const uint32_t nb = (uint32_t)ceil_div(nrem, kBS);
+        const bool all = need == nrem;
+        const bool track = !all && !fixed;
+        if (!all) {
+            {
+                ProfScope pk(ctx, PK_KEYS);
+                const int pp = keys_fast_pp_of(nrem);
+                const KeysBFn kf = keys_b_for(metric, d, vec4, pp);
+                hipLaunchKernelGGL(kf, dim3(ceil_div(nrem, (int64_t)kT * pp)), dim3(kT), 0, s, B,
+                                   (uint32_t)t, nrem, fixed ? 1 : 0);
+                SUBKM_LAUNCHED(ctx);
+            }
+            {
+                ProfScope pc(ctx, PK_CAND);
+                hipLaunchKernelGGL(k_candm, dim3(nb), dim3(kT), 0, s, B, (uint32_t)t, (uint32_t)T,
+                                   nrem, (uint32_t)N);
+                SUBKM_LAUNCHED(ctx);
+            }
+            hipLaunchKernelGGL(k_sel2m, dim3(1), dim3(kST), 0, s, B, (uint32_t)t, (uint32_t)N, nb,
+                               fixed ? 1 : 0);
+            SUBKM_LAUNCHED(ctx);
+        } else if (landmarks) {
+            hipLaunchKernelGGL(k_land_last, dim3(ceil_div(d, 256)), dim3(256), 0, s, B, (uint32_t)t,
+                               fixed ? 1 : 0);
+            SUBKM_LAUNCHED(ctx);
+        }
+        {
+            ProfScope psc(ctx, PK_SCATTER);
+            hipLaunchKernelGGL(scat, dim3(nb), dim3(kT), 0, s, B, (uint32_t)t, nrem, (uint32_t)N,
+                               all ? 1 : 0, track ? 1 : 0, nrem >= kSkipMin ? 1 : 0, fixed ? 1 : 0);
+            SUBKM_LAUNCHED(ctx);
+        }
+        nrem -= need;
+    }
+    return SUBKM_OK;
+}
+
 // Every launch of one subclustering call, in order, on ctx->stream.
 subkm_status sub_enqueue(subkm_ctx *ctx, const SubBufs &b, const float *S, int64_t n, int32_t d,
                          int64_t N, int32_t landmark_mode, int32_t metric, float *P,
                          int32_t *perm, int64_t *offsets, float *landmarks, int64_t t0,
                          int64_t t1) {
+    {
+        const bool v4 = (d % 4) == 0 && ((uintptr_t)S % 16) == 0;
+        const bool v4p = v4 && ((uintptr_t)P % 16) == 0;
+        if (t0 == 0 && t1 == ceil_div(n, N) && scatterm_for(d, v4p) && keys_b_for(metric, d, v4, 1))
+            return sub_enqueue_batched(ctx, b, S, n, d, N, landmark_mode, metric, P, perm, offsets,
+                                       landmarks);
+    }
     const int64_t T = ceil_div(n, N);
     hipStream_t s = ctx->stream;
     const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
@@ -1314,7 +2325,7 @@ subkm_status subcluster_segment(subkm_ctx *ctx, const float *S, int64_t n, int32
                                 int64_t *offsets, float *landmarks, int64_t t0, int64_t t1,
                                 int32_t seg) {
     SubBufs b;
-    SUBKM_TRY(sub_alloc(ctx, n, d, b));
+    SUBKM_TRY(sub_alloc(ctx, n, d, N, b));
     // every input of the captured sequence, one word each
     const uint64_t key[subkm_ctx::kGraphKeyWords] = {
         (uint64_t)(uintptr_t)S, (uint64_t)n, (uint64_t)d, (uint64_t)N,
@@ -1393,4 +2404,6 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
                               landmarks, 0, ceil_div(n, N), 0);
 }
 
-void subcluster_scratch_requests(int64_t n, int32_t d, size_t *req) { sub_requests(n, d, req); }
+void subcluster_scratch_requests(int64_t n, int32_t d, int64_t N, size_t *req) {
+    sub_requests(n, d, N, req);
+}

@@ -94,4 +94,17 @@ def test_tune_load_rejects_malformed(tmp_path):
         f.write("subkm-tune 1\n1 2 3 4 5 0 1 0.5\n")  # block cap 0
     with pytest.raises(pkg.SubkmError):
         ctx.tune_load(path)
+    with open(path, "w") as f:
+        f.write("subkm-tune 2\n1 2 3 4 5 64 1 0 0.5\n")  # no tiles per block
+    with pytest.raises(pkg.SubkmError):
+        ctx.tune_load(path)
+    with open(path, "w") as f:
+        f.write("subkm-tune 2\n1 2 3 4 5 64 1 0.5\n")  # a field missing
+    with pytest.raises(pkg.SubkmError):
+        ctx.tune_load(path)
+    # the first format (no tiles field) still loads
+    with open(path, "w") as f:
+        f.write("subkm-tune 1\n1 2 3 4 5 64 1 0.5\n")
+    ctx.tune_load(path)
+    assert ctx.tuned() == 1
     ctx.close()
