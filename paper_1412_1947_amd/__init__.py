@@ -216,12 +216,13 @@ class Context:
             lib().subkm_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # during interpreter shutdown the HIP runtime (and a profiler
         # attached to it) may already be torn down: contexts still open then
         # were closed by the exit handler below, or are left to the process
-        # exit
-        if sys.is_finalizing():
+        # exit (the check is bound at definition: module globals may already
+        # be cleared when this runs)
+        if _finalizing():
             return
         try:
             self.close()
@@ -477,8 +478,8 @@ class Engine:
             self._h = None
             self._live.clear()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

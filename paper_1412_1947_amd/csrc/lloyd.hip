@@ -35,6 +35,7 @@
 #include <cstring>
 #include <queue>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #pragma clang fp contract(off)
@@ -53,6 +54,7 @@ constexpr int kExB = 16;           // exchange loads in flight per thread
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
 constexpr int64_t kHugeRun = 1 << 15; // points beyond which a run with moves takes the wide path
+constexpr int kUList = 256;         // deferred uncertain points per block and pass (split path)
 
 // Float32 squared distances of this thread's point against centers sC[0..nc)
 // (row-major, d per row); keeps the two smallest values and the first index
@@ -109,22 +111,46 @@ __device__ void recheck_tile(const float *X, int64_t first, const float *Csrc, i
 // LDS of the fused kernels.  Centers are held row-major (c * d + j) for the
 // vector path and dim-major with a padded pitch (j * (k + 16) + c) for the
 // matrix-core path, whose operand reads are then free of bank conflicts.
-struct FusedLds {
+// NT is the block size: the matrix-core persistent kernel of narrow points
+// runs 512 threads (two 256-point tiles at a time) so that four wavefronts
+// share each SIMD within the LDS of two blocks per CU.
+template <int NT>
+struct FusedLdsT {
+    static constexpr int kThreads = NT;
     float sC[kCF];
     float cn[kMaxK + 16];  // matrix-core path: ||c - m||^2, +inf past k
     long long s_sum[kSumW];
     unsigned int s_cnt[kMaxK];
-    int32_t s_list[kAT];
+    int32_t s_list[kAT];   // vector path (256-thread blocks only)
     int32_t s_newlab[kAT];
-    int32_t s_lab[kAT];    // stage-1 label, bit 31 set when uncertain
-    double s_red[kAT];
+    int32_t s_lab[NT];     // stage-1 label, bit 31 set when uncertain
+    double s_red[NT];
     float s_R;             // matrix-core path: max_c ||c - m||
     uint32_t s_nlist;
 };
+using FusedLds = FusedLdsT<kAT>;
 
 template <bool MF>
 __device__ __forceinline__ int cidx(int c, int j, int d, int ldk) {
     return MF ? j * ldk + c : c * d + j;
+}
+
+// Index of the sum of attribute j of center c in s_sum.  On the matrix-core
+// path (D a power of two) the attributes of row c are permuted by an XOR with
+// bits of c: the 64 LDS banks take 32 int64 per pass, and without the
+// permutation the points of one wavefront that add attribute j to different
+// centers would all land on the few banks of column j.  Every reader and
+// writer of s_sum goes through this index (or works elementwise on the whole
+// array), so the permutation is invisible outside the LDS.
+template <int D, bool MF>
+__device__ __forceinline__ int sum_idx(int c, int j, int d) {
+    if constexpr (MF && D >= 4) {
+        constexpr int R = D >= 32 ? 1 : 32 / D;   // rows per pass over the banks
+        constexpr int M = (D >= 32 ? 32 : D) - 1;
+        return c * D + (j ^ ((c / R) & M));
+    } else {
+        return c * d + j;
+    }
 }
 
 // binary64 distance of a point (global memory) to center c held in LDS
@@ -161,11 +187,86 @@ __device__ int32_t wave_argmin64_lds(const float *x, const float *sC, int d, int
     return bi;
 }
 
-// Matrix-core path: squared norms of the centered centers and their maximum.
+// Exact nearest center of one point x (a row in global memory) among the k
+// centers held dim-major in LDS, by the whole wavefront (lanes over
+// centers): the result of the binary64 argmin over all centers (attributes
+// left to right, lowest index on ties), found in two steps.  Float32
+// distances, each within gam = 2 (D + 2) u of the exact one (twice the
+// bound of D + 2 roundings of nonnegative terms), give the minimum m; every
+// center at the exact minimum distance has a float32 distance at most
+// m (1 + 2 gam) (plus a margin for results in the subnormal range), and
+// every center above that bound is farther than the minimum by more than
+// the binary64 rounding can bridge.  Only the centers under the bound
+// (usually one or two) get binary64 distances.
 template <int D>
-__device__ void center_norms(FusedLds &L, const uint32_t *box, int k, int ldk) {
+__device__ __forceinline__ int32_t wave_argmin_exact(const float *x, const float *sC, int k,
+                                                  int ldk) {
+    constexpr int KL = ((kCF / D - 16) + 63) / 64;  // centers per lane at most
+    const int lane = threadIdx.x & 63;
+    // narrow points are held in registers, wide ones read again (cached)
+    constexpr bool kHold = D <= 16;
+    float xs[kHold ? D : 1];
+    if constexpr (kHold) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) xs[j] = x[j];
+    }
+    auto xj = [&](int j) { return kHold ? xs[kHold ? j : 0] : x[j]; };
+    float d32[KL];
+    float m = INFINITY;
+#pragma unroll
+    for (int u = 0; u < KL; ++u) {
+        const int c = lane + 64 * u;
+        float a = INFINITY;
+        if (c < k) {
+            a = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const float t = xj(j) - sC[j * ldk + c];
+                a = __builtin_fmaf(t, t, a);
+            }
+        }
+        d32[u] = a;
+        m = fminf(m, a);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
+    const float gam = 2.0f * (float)(D + 2) * 5.9604645e-8f;
+    const float thr = m * (1.0f + 2.0f * gam) + (float)(4 * D + 4) * 2.8025969e-45f;
+    double best = INFINITY;
+    int32_t bi = 0x7fffffff;
+#pragma unroll
+    for (int u = 0; u < KL; ++u) {
+        if (d32[u] <= thr) {  // false past k (+inf)
+            const int c = lane + 64 * u;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const double q = (double)xj(j) - (double)sC[j * ldk + c];
+                acc = acc + q * q;
+            }
+            if (acc < best) {  // this lane's centers ascend: the first of equals stays
+                best = acc;
+                bi = c;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int32_t oi = __shfl_xor(bi, o, 64);
+        if (ob < best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    return bi;
+}
+
+// Matrix-core path: squared norms of the centered centers and their maximum.
+template <int D, class LT>
+__device__ void center_norms(LT &L, const uint32_t *box, int k, int ldk) {
     float mx = 0.0f;
-    for (int c = threadIdx.x; c < kMaxK + 16 && c < ((k + 15) & ~15); c += kAT) {
+    for (int c = threadIdx.x; c < kMaxK + 16 && c < ((k + 15) & ~15); c += LT::kThreads) {
         float a = INFINITY;
         if (c < k) {
             a = 0.0f;
@@ -178,7 +279,7 @@ __device__ void center_norms(FusedLds &L, const uint32_t *box, int k, int ldk) {
         }
         L.cn[c] = a;
     }
-    const double r = block_max((double)mx, L.s_red);
+    const double r = block_max<LT::kThreads>((double)mx, L.s_red);
     if (threadIdx.x == 0) L.s_R = sqrtf((float)r);
     __syncthreads();
 }
@@ -215,18 +316,19 @@ __device__ __forceinline__ void load_tile(const float *X, int64_t first_w, int64
     }
 }
 
+// The tile centered on the box midpoint m (points past n become 0) and the
+// norms ||x - m|| of its points, as the matrix-core lanes hold them.  The raw
+// registers are free afterwards (the next tile can be loaded into them).
 template <int D>
-__device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t first_w, int64_t n,
-                            int k, int ldk, const uint32_t *box, int32_t *lab_out, bool accumulate,
-                            int shift, int32_t *wlab) {
+__device__ __forceinline__ void center_tile(const float (&xr)[4][D / 4], const uint32_t *box,
+                                            int64_t first_w, int64_t n, float (&xb)[4][D / 4],
+                                            float (&xn)[4]) {
     constexpr int KQ = D / 4;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kk = lane >> 4;
     float mq[KQ];
 #pragma unroll
     for (int q = 0; q < KQ; ++q) mq[q] = box_mid(box, D, kk + 4 * q);
-    float xb[4][KQ];
-    float xn[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const bool ok = first_w + g * 16 + col < n;
@@ -241,6 +343,23 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
         s2 += __shfl_xor(s2, 32, 64);
         xn[g] = sqrtf(s2);
     }
+}
+
+// Stage 1 of a centered tile (xb, xn from center_tile).  Certain points are
+// added to the sums from their raw coordinates, read again from X (the tile
+// was just loaded, so the reads hit the caches), which keeps the raw tile out
+// of the registers while the products run.
+template <int D, class LT>
+__device__ void stage1_mfma(LT &L, const float (&xb)[4][D / 4], const float (&xn)[4],
+                            const float *X, int64_t first_w, int64_t n, int k, int ldk,
+                            const uint32_t *box, int32_t *lab_out, bool accumulate, int shift,
+                            int32_t *wlab) {
+    constexpr int KQ = D / 4;
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kk = lane >> 4;
+    float mq[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) mq[q] = box_mid(box, D, kk + 4 * q);
     float b1[4], b2[4];
     int32_t i1[4];
 #pragma unroll
@@ -296,6 +415,20 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
     }
     const float Rc = L.s_R;
     const float Ku = 2.0f * (float)(D + 5) * 5.9604645e-8f;
+    // raw attributes for the sums, loaded before the merge (rows past n
+    // clamped) for narrow points; wide ones load at the addition
+    constexpr bool kEarly = D <= 16;
+    float xv[4][KQ];
+    if (kEarly && accumulate) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            int64_t p = first_w + g * 16 + col;
+            p = p < n ? p : n - 1;
+            const float *xp = X + p * D + kk;
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) xv[g][q] = xp[4 * q];
+        }
+    }
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
 #pragma unroll
@@ -304,7 +437,7 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
             const float ob2 = __shfl_xor(b2[g], o, 64);
             const int32_t oi = __shfl_xor(i1[g], o, 64);
             const float nb2 = fminf(fminf(b2[g], ob2), fmaxf(b1[g], ob1));
-            const bool take = ob1 < b1[g] || (ob1 == b1[g] && oi < i1[g]);
+            const bool take = (ob1 < b1[g]) | ((ob1 == b1[g]) & (oi < i1[g]));  // no branch
             b1[g] = take ? ob1 : b1[g];
             i1[g] = take ? oi : i1[g];
             b2[g] = nb2;
@@ -320,11 +453,15 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
             if (kk == 0) lab_out[p] = i1[g];
             if (accumulate) {
                 if (kk == 0) atomicAdd(&L.s_cnt[i1[g]], 1u);
-                long long *row = L.s_sum + i1[g] * D;
+                if constexpr (!kEarly) {
+                    const float *xp = X + p * D + kk;
+#pragma unroll
+                    for (int q = 0; q < KQ; ++q) xv[g][q] = xp[4 * q];
+                }
 #pragma unroll
                 for (int q = 0; q < KQ; ++q)
-                    atomicAdd((unsigned long long *)&row[kk + 4 * q],
-                              (unsigned long long)to_fixed(xr[g][q], shift));
+                    atomicAdd((unsigned long long *)&L.s_sum[sum_idx<D, true>(i1[g], kk + 4 * q, D)],
+                              (unsigned long long)to_fixed(xv[g][q], shift));
             }
         }
         if (kk == 0) wlab[g * 16 + col] = i1[g] | (certain ? 0 : (int32_t)0x80000000);
@@ -338,17 +475,19 @@ __device__ void stage1_mfma(FusedLds &L, const float (&xr)[4][D / 4], int64_t fi
 // lane.  No block barrier: only the wavefront's own LDS slice is exchanged.
 // On the final pass (no accumulation) every lane returns the binary64
 // objective of its point.
-template <int D>
-__device__ double wave_tile_mf(FusedLds &L, const float (&xr)[4][D / 4], const float *X,
-                               int64_t first_w, int64_t n, int k, int ldk, const uint32_t *box,
-                               int32_t *lab_out, bool accumulate, int shift,
-                               unsigned long long &nrecheck) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int32_t *wlab = L.s_lab + wave * 64;
+// Second half of a matrix-core tile, after stage 1 has filled wlab.
+// With DEFER, on a pass with an update, the uncertain points go to the
+// block's list (resolve_deferred takes them before the exchange) as long as
+// it has room; the others, and all of them on the last pass (whose per-tile
+// objective needs the labels now), are re-assigned here.
+template <int D, bool DEFER = false, class LT>
+__device__ double wave_tile_finish(LT &L, const float *X, int64_t first_w, int64_t n, int k, int ldk,
+                                   int32_t *lab_out, bool accumulate, int shift,
+                                   unsigned long long &nrecheck, const int32_t *wlab) {
+    const int lane = threadIdx.x & 63;
     const int64_t i = first_w + lane;
     const bool valid = i < n;
     const float *xg = X + (valid ? i : 0) * D;
-    stage1_mfma<D>(L, xr, first_w, n, k, ldk, box, lab_out, accumulate, shift, wlab);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -356,18 +495,29 @@ __device__ double wave_tile_mf(FusedLds &L, const float (&xr)[4][D / 4], const f
     int32_t i1 = sl & 0x7fffffff;
     unsigned long long todo = __ballot(valid && sl < 0);
     nrecheck += (unsigned long long)__popcll(todo);
+    if constexpr (DEFER) {
+        if (accumulate && todo) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&L.s_nu, (uint32_t)__popcll(todo));
+            base = __shfl(base, 0, 64);
+            const bool mine = (todo >> lane) & 1ull;
+            const uint32_t slot = base + (uint32_t)__popcll(todo & ((1ull << lane) - 1ull));
+            if (mine && slot < (uint32_t)kUList) L.s_ulist[slot] = (int32_t)i;
+            todo = __ballot(mine && slot >= (uint32_t)kUList);
+        }
+    }
     while (todo) {
         const int t = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;
-        const int32_t w = wave_argmin64_lds<true>(X + (first_w + t) * D, L.sC, D, k, ldk);
+        const int32_t w = wave_argmin_exact<D>(X + (first_w + t) * D, L.sC, k, ldk);
         if (lane == t) {
             i1 = w;
             lab_out[i] = w;
             if (accumulate) {
                 atomicAdd(&L.s_cnt[w], 1u);
-                long long *row = L.s_sum + w * D;
                 for (int j = 0; j < D; ++j)
-                    atomicAdd((unsigned long long *)&row[j], (unsigned long long)to_fixed(xg[j], shift));
+                    atomicAdd((unsigned long long *)&L.s_sum[sum_idx<D, true>(w, j, D)],
+                              (unsigned long long)to_fixed(xg[j], shift));
             }
         }
     }
@@ -376,11 +526,377 @@ __device__ double wave_tile_mf(FusedLds &L, const float (&xr)[4][D / 4], const f
     return obj;
 }
 
+template <int D, class LT>
+__device__ double wave_tile_mf(LT &L, const float (&xb)[4][D / 4], const float (&xn)[4],
+                               const float *X, int64_t first_w, int64_t n, int k, int ldk,
+                               const uint32_t *box, int32_t *lab_out, bool accumulate, int shift,
+                               unsigned long long &nrecheck) {
+    int32_t *wlab = L.s_lab + (threadIdx.x >> 6) * 64;
+    stage1_mfma<D>(L, xb, xn, X, first_w, n, k, ldk, box, lab_out, accumulate, shift, wlab);
+    return wave_tile_finish<D>(L, X, first_w, n, k, ldk, lab_out, accumulate, shift, nrecheck, wlab);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core path on split bfloat16 (D = 8, 16, 32).  The float32 matrix
+// instruction (16x16x4) keeps the SIMD busy for 32 cycles and does not overlap
+// the selection that follows on the same SIMD, so stage 1 runs on
+// v_mfma_f32_16x16x32_bf16 instead: both centered operands are split into two
+// bfloat16 parts (round to nearest), a = ah + al and -2 c = ch + cl, and the
+// four products ch ah, cl ah, ch al, cl al, each exact in float32, are summed
+// by the instruction with K laid out as four terms of D attributes
+// (kappa = term * D + j).  Error bound of one value v, s = ||x - m|| + R:
+//   centering and norms    (D + 3) u s^2                       u = 2^-24
+//   split residuals        4 * 2^-16 sum_j |a_j| |c_j|  <=  2^-16 s^2
+//   accumulation           (4 D + 1) additions that may each round toward
+//                          zero: 2 (4 D + 1) u (1.03 s^2)
+// so E = (2^-16 + (D + 3 + 2.06 (4 D + 1)) u) s^2 + 1e-30, and the gap of the
+// two smallest values is certain when it exceeds 2 E.  Uncertain points are
+// re-assigned in binary64 like on the other paths, so labels are unchanged.
+template <int D>
+constexpr bool kBF = D == 8 || D == 16 || D == 32;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBfMaxK = kCF / 8 - 16;  // centers of a split-path run (D >= 8)
+
+template <int NT>
+struct BfLdsT {
+    static constexpr int kThreads = NT;
+    float sC[kCF];           // centers, dim-major with pitch k + 16 (as the float32 path)
+    bf16x8 sA[kCF / 4];      // split -2 (c - m): per center D/4 chunks of 8 (ch chunks, then cl)
+    float cn[kBfMaxK + 16];  // ||c - m||^2, +inf past k
+    long long s_sum[kSumW];
+    unsigned int s_cnt[kBfMaxK];
+    int32_t s_lab[NT];
+    double s_red[NT];
+    int32_t s_ulist[kUList];  // uncertain points of this pass, resolved before the exchange
+    uint32_t s_nu;
+    float s_R;
+};
+
+// Chunk q of center c in sA.  A wavefront reads chunk q of 16 consecutive
+// centers in one instruction; chunk q of center c sits at position q ^ f(c)
+// of its row so that those 16 reads cover the 64 banks once.
+template <int D>
+__device__ __forceinline__ int sa_idx(int c, int q) {
+    constexpr int NQ = D / 4;   // chunks per center
+    constexpr int RP = 64 / D;  // centers per 256 bytes
+    return c * NQ + (q ^ ((c / RP) & (NQ - 1)));
+}
+
+// Norms, maximum norm and split operands of the run's centers (after every
+// update).  Centers k .. 16 ceil(k / 16) - 1 get zero operands and an
+// infinite norm, so their values are +inf and never selected.
+template <int D, class LT>
+__device__ void center_prep_bf(LT &L, const uint32_t *box, int k, int ldk) {
+    float mx = 0.0f;
+    const int kr = (k + 15) & ~15;
+    for (int c = threadIdx.x; c < kr; c += LT::kThreads) {
+        float a = INFINITY;
+        if (c < k) {
+            a = 0.0f;
+#pragma unroll
+            for (int q = 0; q < D / 8; ++q) {
+                bf16x8 hi, lo;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int j = 8 * q + e;
+                    const float t = L.sC[j * ldk + c] - box_mid(box, D, j);
+                    a = __builtin_fmaf(t, t, a);
+                    const float v = -2.0f * t;
+                    const __bf16 h = (__bf16)v;
+                    hi[e] = h;
+                    lo[e] = (__bf16)(v - (float)h);
+                }
+                L.sA[sa_idx<D>(c, q)] = hi;
+                L.sA[sa_idx<D>(c, D / 8 + q)] = lo;
+            }
+            mx = fmaxf(mx, a);
+        } else {
+            const bf16x8 z = {};
+#pragma unroll
+            for (int q = 0; q < D / 4; ++q) L.sA[sa_idx<D>(c, q)] = z;
+        }
+        L.cn[c] = a;
+    }
+    const double r = block_max<LT::kThreads>((double)mx, L.s_red);
+    if (threadIdx.x == 0) L.s_R = sqrtf((float)r);
+    __syncthreads();
+}
+
+// Raw attributes of a tile as the split path's lanes use them: lane
+// (col = l % 16, kg = l / 16) holds attributes j0 .. j0 + 7, j0 = 8 kg mod D,
+// of point col of each 16-point group (rows past n clamped to the last).
+template <int D>
+__device__ __forceinline__ void load_tile_bf(const float *X, int64_t first_w, int64_t n,
+                                             float (&xr)[4][8]) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kg = lane >> 4;
+    const int j0 = (8 * kg) % D;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        int64_t p = first_w + g * 16 + col;
+        p = p < n ? p : n - 1;
+        const float4 *src = reinterpret_cast<const float4 *>(X + p * D + j0);
+        const float4 u = src[0], w = src[1];
+        xr[g][0] = u.x; xr[g][1] = u.y; xr[g][2] = u.z; xr[g][3] = u.w;
+        xr[g][4] = w.x; xr[g][5] = w.y; xr[g][6] = w.z; xr[g][7] = w.w;
+    }
+}
+
+// Centered and split tile (points past n become 0) and the norms ||x - m||.
+template <int D>
+__device__ __forceinline__ void split_tile_bf(const float (&xr)[4][8], const uint32_t *box,
+                                              int64_t first_w, int64_t n, bf16x8 (&ah)[4],
+                                              bf16x8 (&al)[4], float (&xn)[4]) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kg = lane >> 4;
+    const int j0 = (8 * kg) % D;
+    float mq[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) mq[e] = box_mid(box, D, j0 + e);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const bool ok = first_w + g * 16 + col < n;
+        float s2 = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float a = ok ? xr[g][e] - mq[e] : 0.0f;
+            s2 = __builtin_fmaf(a, a, s2);
+            const __bf16 h = (__bf16)a;
+            ah[g][e] = h;
+            al[g][e] = (__bf16)(a - (float)h);
+        }
+        // the lanes that hold the point's other attributes
+        if constexpr (D >= 16) s2 += __shfl_xor(s2, 16, 64);
+        if constexpr (D >= 32) s2 += __shfl_xor(s2, 32, 64);
+        xn[g] = sqrtf(s2);
+    }
+}
+
+// Stage 1 of a split tile: labels and (if asked) sums of the certain points,
+// stage-1 labels with the uncertain flag in wlab, as stage1_mfma.  The lanes
+// that hold the same 8 raw attributes of a point (xr, from load_tile_bf)
+// share its sums: each adds D/4 of them, from its registers.  Once the
+// products are done, the next tile's raw attributes are requested into xq
+// (next_w < 0: none), so that their loads overlap the rest of the tile.
+template <int D, class LT>
+__device__ void stage1_bf(LT &L, const bf16x8 (&ah)[4], const bf16x8 (&al)[4], const float (&xn)[4],
+                          const float (&xr)[4][8], float (&xq)[4][8], int64_t next_w, const float *X,
+                          int64_t first_w, int64_t n, int k, int32_t *lab_out, bool accumulate,
+                          int shift, int32_t *wlab) {
+    constexpr int S = D / 8;                 // instructions per group and center block
+    constexpr int NA = D >= 16 ? D / 16 : 1;  // distinct A operands per lane
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kg = lane >> 4;
+    // A operand of instruction s: chunk (t & 1) D/8 + j0/8 of the center,
+    // t = (32 s + 8 kg) / D the term; terms 2 and 3 repeat the chunks of 0 and 1
+    int qa[NA];
+#pragma unroll
+    for (int s = 0; s < NA; ++s) {
+        const int t = (32 * s + 8 * kg) / D, j0 = (32 * s + 8 * kg) % D;
+        qa[s] = (t & 1) * (D / 8) + j0 / 8;
+    }
+    // B operand: al for terms 2 and 3 (a lane-dependent choice only for D = 8)
+    bf16x8 b8[4];
+    if constexpr (D == 8) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) b8[g] = kg >= 2 ? al[g] : ah[g];
+    }
+    float b1[4], b2[4];
+    int32_t i1[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        b1[g] = INFINITY;
+        b2[g] = INFINITY;
+        i1[g] = 0;
+    }
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        bf16x8 A[NA];
+#pragma unroll
+        for (int s = 0; s < NA; ++s) A[s] = L.sA[sa_idx<D>(c0 + col, qa[s])];
+        const floatx4 cinit = {L.cn[c0 + 4 * kg], L.cn[c0 + 4 * kg + 1], L.cn[c0 + 4 * kg + 2],
+                               L.cn[c0 + 4 * kg + 3]};
+        floatx4 acc[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            acc[g] = cinit;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const bf16x8 B = D == 8 ? b8[g] : ((32 * s) / D >= 2 ? al[g] : ah[g]);
+                acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s % NA], B, acc[g], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float v = acc[g][r];
+                b2[g] = __builtin_amdgcn_fmed3f(v, b1[g], b2[g]);
+                const bool lt = v < b1[g];
+                b1[g] = lt ? v : b1[g];
+                i1[g] = lt ? c0 + 4 * kg + r : i1[g];
+            }
+    }
+    if (next_w >= 0) load_tile_bf<D>(X, next_w, n, xq);
+    const float Rc = L.s_R;
+    constexpr float Kb = 1.52587890625e-05f + (float)(D + 3 + 2.06 * (4 * D + 1)) * 5.9604645e-8f;
+    // this lane's share of its 8 attributes: the 32 / D lanes that hold
+    // them take QA = D / 4 each, lane kg the part (8 kg / D)
+    constexpr int QA = D / 4;
+    const int part = (8 * kg) / D;
+    const int j0 = (8 * kg) % D;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            const float ob1 = __shfl_xor(b1[g], o, 64);
+            const float ob2 = __shfl_xor(b2[g], o, 64);
+            const int32_t oi = __shfl_xor(i1[g], o, 64);
+            const float nb2 = fminf(fminf(b2[g], ob2), fmaxf(b1[g], ob1));
+            const bool take = (ob1 < b1[g]) | ((ob1 == b1[g]) & (oi < i1[g]));  // no branch
+            b1[g] = take ? ob1 : b1[g];
+            i1[g] = take ? oi : i1[g];
+            b2[g] = nb2;
+        }
+        const int64_t p = first_w + g * 16 + col;
+        const float sx = xn[g] + Rc;
+        const float E = Kb * sx * sx + 1e-30f;
+        const bool certain = k == 1 || (b2[g] - b1[g]) > 2.0f * E;
+        if (p < n && certain) {
+            if (kg == 0) lab_out[p] = i1[g];
+            if (accumulate) {
+                if (kg == 0) atomicAdd(&L.s_cnt[i1[g]], 1u);
+#pragma unroll
+                for (int q = 0; q < QA; ++q) {
+                    // element part * QA + q of xr[g], chosen without indexing registers
+                    float v = xr[g][q];
+#pragma unroll
+                    for (int pp = 1; pp < 8 / QA; ++pp) v = part == pp ? xr[g][pp * QA + q] : v;
+                    atomicAdd((unsigned long long *)&L.s_sum[sum_idx<D, true>(i1[g], j0 + part * QA + q, D)],
+                              (unsigned long long)to_fixed(v, shift));
+                }
+            }
+        }
+        if (kg == 0) wlab[g * 16 + col] = i1[g] | (certain ? 0 : (int32_t)0x80000000);
+    }
+}
+
+// Split-path tile of one wavefront: stage 1 on split bfloat16, then the
+// binary64 re-assignment of the uncertain points and the objective.
+template <int D, class LT>
+__device__ double wave_tile_bf(LT &L, const bf16x8 (&ah)[4], const bf16x8 (&al)[4],
+                               const float (&xn)[4], const float (&xr)[4][8], float (&xq)[4][8],
+                               int64_t next_w, const float *X, int64_t first_w, int64_t n, int k,
+                               int ldk, int32_t *lab_out, bool accumulate, int shift,
+                               unsigned long long &nrecheck) {
+    int32_t *wlab = L.s_lab + (threadIdx.x >> 6) * 64;
+    stage1_bf<D>(L, ah, al, xn, xr, xq, next_w, X, first_w, n, k, lab_out, accumulate, shift, wlab);
+    return wave_tile_finish<D, true>(L, X, first_w, n, k, ldk, lab_out, accumulate, shift, nrecheck, wlab);
+}
+
+// The deferred uncertain points of a pass, 16 per wavefront at a time, on
+// the float32 matrix cores (the products of stage1_mfma for one 16-point
+// group, bound 2 (D + 5) u s^2: about a tenth of the split path's).  The
+// certain ones are labelled and added to the sums; the others get the exact
+// argmin.  Every thread of the block calls this after the pass's tiles.
+template <int D, class LT>
+__device__ void resolve_deferred(LT &L, const float *X, int k, int ldk, const uint32_t *box,
+                                 int32_t *lab_out, int shift) {
+    constexpr int KQ = D / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kk = lane >> 4;
+    const int nu = min((int)L.s_nu, kUList);
+    float mq[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) mq[q] = box_mid(box, D, kk + 4 * q);
+    const float Rc = L.s_R;
+    const float Ku = 2.0f * (float)(D + 5) * 5.9604645e-8f;
+    for (int g0 = wave * 16; g0 < nu; g0 += (LT::kThreads / 64) * 16) {
+        const bool ok = g0 + col < nu;
+        const int32_t p = L.s_ulist[ok ? g0 + col : g0];  // a listed row either way
+        float xr[KQ], xb[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) xr[q] = X[(int64_t)p * D + kk + 4 * q];
+        float s2 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            xb[q] = xr[q] - mq[q];
+            s2 = __builtin_fmaf(xb[q], xb[q], s2);
+        }
+        s2 += __shfl_xor(s2, 16, 64);
+        s2 += __shfl_xor(s2, 32, 64);
+        const float xn = sqrtf(s2);
+        float b1 = INFINITY, b2 = INFINITY;
+        int32_t i1 = 0;
+        for (int c0 = 0; c0 < k; c0 += 16) {
+            const int cA = c0 + col;
+            const uint32_t vmask = cA < k ? 0xFFFFFFFFu : 0u;
+            float ca[KQ];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                const float cv = L.sC[(kk + 4 * q) * ldk + cA];
+                ca[q] = __uint_as_float(__float_as_uint(-2.0f * (cv - mq[q])) & vmask);
+            }
+            floatx4 acc = {L.cn[c0 + 4 * kk], L.cn[c0 + 4 * kk + 1], L.cn[c0 + 4 * kk + 2],
+                           L.cn[c0 + 4 * kk + 3]};
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[q], xb[q], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float v = acc[r];
+                b2 = __builtin_amdgcn_fmed3f(v, b1, b2);
+                const bool lt = v < b1;
+                b1 = lt ? v : b1;
+                i1 = lt ? c0 + 4 * kk + r : i1;
+            }
+        }
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            const float ob1 = __shfl_xor(b1, o, 64);
+            const float ob2 = __shfl_xor(b2, o, 64);
+            const int32_t oi = __shfl_xor(i1, o, 64);
+            const float nb2 = fminf(fminf(b2, ob2), fmaxf(b1, ob1));
+            const bool take = (ob1 < b1) | ((ob1 == b1) & (oi < i1));
+            b1 = take ? ob1 : b1;
+            i1 = take ? oi : i1;
+            b2 = nb2;
+        }
+        const float sx = xn + Rc;
+        const float E = Ku * sx * sx + 1e-30f;
+        const bool certain = k == 1 || (b2 - b1) > 2.0f * E;
+        if (ok && certain) {
+            if (kk == 0) {
+                lab_out[p] = i1;
+                atomicAdd(&L.s_cnt[i1], 1u);
+            }
+#pragma unroll
+            for (int q = 0; q < KQ; ++q)
+                atomicAdd((unsigned long long *)&L.s_sum[sum_idx<D, true>(i1, kk + 4 * q, D)],
+                          (unsigned long long)to_fixed(xr[q], shift));
+        }
+        unsigned long long todo = __ballot(ok && !certain && kk == 0);
+        while (todo) {
+            const int t = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int32_t pt = L.s_ulist[g0 + t];
+            const int32_t w = wave_argmin_exact<D>(X + (int64_t)pt * D, L.sC, k, ldk);
+            if (lane == 0) {
+                lab_out[pt] = w;
+                atomicAdd(&L.s_cnt[w], 1u);
+            }
+            for (int j = lane; j < D; j += 64)
+                atomicAdd((unsigned long long *)&L.s_sum[sum_idx<D, true>(w, j, D)],
+                          (unsigned long long)to_fixed(X[(int64_t)pt * D + j], shift));
+        }
+    }
+}
+
 // Assign one tile of up to 256 points of a run against all k centers held in
 // LDS; optionally add the points to the fixed-point sums.  Returns the
 // binary64 objective contribution of this thread's point (0 if none).
 template <int D, bool MF>
-__device__ double fused_tile(FusedLds &L, const float *X, int64_t first, int64_t n, int d, int k,
+__device__ __forceinline__ double fused_tile(FusedLds &L, const float *X, int64_t first, int64_t n, int d, int k,
                              int ldk, const uint32_t *box, int32_t *lab_out, bool accumulate,
                              int shift, unsigned long long *rechecks) {
     const int64_t i = first + threadIdx.x;
@@ -437,17 +953,18 @@ __device__ double fused_tile(FusedLds &L, const float *X, int64_t first, int64_t
 
 // New centers from the sums in L.s_sum / L.s_cnt: writes L.sC (and Cglob,
 // row-major, if non-null) and returns the largest binary64 center move.
-template <bool MF>
-__device__ double centers_from_sums(FusedLds &L, int d, int k, int ldk, int shift, float *Cglob) {
+template <int D, bool MF, class LT>
+__device__ double centers_from_sums(LT &L, int d, int k, int ldk, int shift, float *Cglob) {
     double mx = 0.0;
-    for (int c = threadIdx.x; c < k; c += kAT) {
+    for (int c = threadIdx.x; c < k; c += LT::kThreads) {
         const unsigned int cnt = L.s_cnt[c];
         double mv2 = 0.0;
         int j = c % d;  // rotated start: neighbouring lanes read different banks
         for (int q = 0; q < d; ++q, j = j + 1 == d ? 0 : j + 1) {
             const int e = cidx<MF>(c, j, d, ldk);
             const float old = L.sC[e];
-            const double nv = cnt ? ldexp((double)L.s_sum[c * d + j], -shift) / (double)cnt : (double)old;
+            const double nv =
+                cnt ? ldexp((double)L.s_sum[sum_idx<D, MF>(c, j, d)], -shift) / (double)cnt : (double)old;
             const double dv = nv - (double)old;
             mv2 = mv2 + dv * dv;
             const float f = (float)nv;
@@ -456,13 +973,13 @@ __device__ double centers_from_sums(FusedLds &L, int d, int k, int ldk, int shif
         }
         mx = fmax(mx, sqrt(mv2));
     }
-    return block_max(mx, L.s_red);
+    return block_max<LT::kThreads>(mx, L.s_red);
 }
 
 // load the run's centers (row-major in global memory) into LDS
-template <bool MF>
-__device__ void load_centers(FusedLds &L, const float *Cr, int d, int k, int ldk) {
-    for (int e = threadIdx.x; e < k * d; e += kAT) {
+template <bool MF, class LT>
+__device__ void load_centers(LT &L, const float *Cr, int d, int k, int ldk) {
+    for (int e = threadIdx.x; e < k * d; e += LT::kThreads) {
         const int c = e / d, j = e - c * d;
         L.sC[cidx<MF>(c, j, d, ldk)] = Cr[e];
     }
@@ -471,13 +988,18 @@ __device__ void load_centers(FusedLds &L, const float *Cr, int d, int k, int ldk
 // ---------------------------------------------------------------------------
 // Batched form: persistent, cooperative.  Block b works through its tasks
 // task_off[b] .. task_off[b+1]-1 in order; every task is one part of a run.
-template <int D, bool MF>
-__global__ __launch_bounds__(kAT) void k_lloyd_persist(
+// A block of NT threads takes NT / 256 tiles of 256 points at a time, one
+// per 256-thread part.
+template <int D, bool MF, bool BF, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > kAT ? 4 : (D > 0 && D <= 32 ? 2 : 1)))) void k_lloyd_persist(
     const float *__restrict__ P, const DevRun *__restrict__ runs, const Task *__restrict__ tasks,
     const int32_t *__restrict__ task_off, float *C, int32_t *labels, RunState *rstate,
     long long *parts, double *objpart, const uint32_t *__restrict__ boxes, int max_iter,
     double tol, int *err) {
-    __shared__ FusedLds L;
+    static_assert(MF || NT == kAT, "the vector path runs 256-thread blocks");
+    static_assert(!BF || (MF && kBF<D>), "split path: matrix cores, D = 8, 16 or 32");
+    using LT = std::conditional_t<BF, BfLdsT<NT>, FusedLdsT<NT>>;
+    __shared__ LT L;
     for (int ti = task_off[blockIdx.x]; ti < task_off[blockIdx.x + 1]; ++ti) {
         const Task tk = tasks[ti];
         const DevRun R = runs[tk.run];
@@ -498,41 +1020,72 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
         __syncthreads();
         load_centers<MF>(L, Cr, d, k, ldk);
         __syncthreads();
-        if constexpr (MF) center_norms<D>(L, box, k, ldk);
         int it = 0;
         bool converged = false;
         for (;;) {
             const bool last = it == max_iter || converged;
-            for (int e = threadIdx.x; e < kd; e += kAT) L.s_sum[e] = 0;
-            for (int c = threadIdx.x; c < k; c += kAT) L.s_cnt[c] = 0;
-            if constexpr (MF) {
-                // the next tile's points are loaded while this one computes
-                // (for narrow points; wide ones would need too many registers)
-                constexpr bool kPrefetch = D <= 32;
+            // operands of the matrix-core paths from this pass's centers
+            if constexpr (BF) center_prep_bf<D>(L, box, k, ldk);
+            else if constexpr (MF) center_norms<D>(L, box, k, ldk);
+            for (int e = threadIdx.x; e < kd; e += NT) L.s_sum[e] = 0;
+            for (int c = threadIdx.x; c < k; c += NT) L.s_cnt[c] = 0;
+            if constexpr (BF) {
+                // split path: the next tile's raw points load while this one
+                // finishes (requested after its products)
                 const int64_t wofs = (threadIdx.x >> 6) * 64;
-                float xr[4][D / 4], xq[4][D / 4];
+                float xr[4][8], xq[4][8];
                 unsigned long long nre = 0;
-                if (t0 < t1) load_tile<D>(X, t0 * kAT + wofs, R.n, xr);
-                __syncthreads();  // sums and counts are zeroed
+                if (t0 < t1) load_tile_bf<D>(X, t0 * kAT + wofs, R.n, xr);
+                if (threadIdx.x == 0) L.s_nu = 0;
+                __syncthreads();  // sums, counts and the list are cleared
                 for (int64_t t = t0; t < t1; ++t) {
-                    if constexpr (kPrefetch) {
-                        if (t + 1 < t1) load_tile<D>(X, (t + 1) * kAT + wofs, R.n, xq);
-                    } else {
-                        if (t > t0) load_tile<D>(X, t * kAT + wofs, R.n, xr);
-                    }
-                    const double obj = wave_tile_mf<D>(L, xr, X, t * kAT + wofs, R.n, k, ldk, box, lab,
-                                                       !last, shift, nre);
+                    bf16x8 ah[4], al[4];
+                    float xn[4];
+                    split_tile_bf<D>(xr, box, t * kAT + wofs, R.n, ah, al, xn);
+                    const int64_t next_w = t + 1 < t1 ? (t + 1) * kAT + wofs : -1;
+                    const double obj = wave_tile_bf<D>(L, ah, al, xn, xr, xq, next_w, X, t * kAT + wofs,
+                                                       R.n, k, ldk, lab, !last, shift, nre);
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) xr[g][e] = xq[g][e];
                     if (last) {
-                        // objective per tile, summed over tiles in order by the
-                        // finalize kernel: the same rounding as the plain form
                         const double tot = block_sum_det(obj, L.s_red);
                         if (threadIdx.x == 0) objpart[R.item0 + t] = tot;
                     }
-                    if constexpr (kPrefetch) {
-#pragma unroll
-                        for (int g = 0; g < 4; ++g)
-#pragma unroll
-                            for (int q = 0; q < D / 4; ++q) xr[g][q] = xq[g][q];
+                }
+                if (!last) {
+                    __syncthreads();  // the list is complete
+                    resolve_deferred<D>(L, X, k, ldk, box, lab, shift);
+                }
+                if ((threadIdx.x & 63) == 0 && nre) atomicAdd(&rs->rechecks, nre);
+            } else if constexpr (MF) {
+                // the next tile's points are loaded while this one computes
+                // (for narrow points; wide ones would need too many registers)
+                constexpr bool kPrefetch = D <= 32 && NT == kAT;
+                constexpr int TB = NT / kAT;
+                const int part = (int)threadIdx.x / kAT;
+                const int64_t wofs = ((threadIdx.x & (kAT - 1)) >> 6) * 64;
+                float xr[4][D / 4];
+                unsigned long long nre = 0;
+                if (kPrefetch && t0 + part < t1) load_tile<D>(X, (t0 + part) * kAT + wofs, R.n, xr);
+                __syncthreads();  // sums and counts are zeroed
+                for (int64_t tb = t0; tb < t1; tb += TB) {
+                    const int64_t t = tb + part;  // this part's tile (uniform per wavefront)
+                    double obj = 0.0;
+                    if (t < t1) {
+                        if (!kPrefetch) load_tile<D>(X, t * kAT + wofs, R.n, xr);
+                        float xb[4][D / 4], xn[4];
+                        center_tile<D>(xr, box, t * kAT + wofs, R.n, xb, xn);
+                        if (kPrefetch && t + TB < t1) load_tile<D>(X, (t + TB) * kAT + wofs, R.n, xr);
+                        obj = wave_tile_mf<D>(L, xb, xn, X, t * kAT + wofs, R.n, k, ldk, box, lab,
+                                              !last, shift, nre);
+                    }
+                    if (last) {
+                        // objective per tile, summed over tiles in order by the
+                        // finalize kernel: the same rounding as the plain form
+                        const double tot = block_sum_det<NT>(obj, L.s_red);
+                        if ((threadIdx.x & (kAT - 1)) == 0 && t < t1) objpart[R.item0 + t] = tot;
                     }
                 }
                 if ((threadIdx.x & 63) == 0 && nre) atomicAdd(&rs->rechecks, nre);
@@ -562,9 +1115,9 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
                 // all arrivals also sees all parts.  No cache-wide fence.
                 const int ne = kd + k;
                 long long *slot = parts + R.part_off + ((int64_t)(it & 1) * G + tk.g) * ne;
-                for (int e = threadIdx.x; e < kd; e += kAT)
+                for (int e = threadIdx.x; e < kd; e += NT)
                     __hip_atomic_store(&slot[e], L.s_sum[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                for (int c = threadIdx.x; c < k; c += kAT)
+                for (int c = threadIdx.x; c < k; c += NT)
                     __hip_atomic_store(&slot[kd + c], (long long)L.s_cnt[c], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_s_waitcnt(0);
@@ -596,23 +1149,23 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
                 long long *tot = parts + R.part_off + 2ll * G * ne + (int64_t)(it & 1) * ne;
                 const int S = (ne + G - 1) / G;
                 const int e0 = min(ne, tk.g * S), ns = min(ne, e0 + S) - e0;
-                for (int i = threadIdx.x; i < ns; i += kAT) L.s_sum[i] = 0;
+                for (int i = threadIdx.x; i < ns; i += NT) L.s_sum[i] = 0;
                 __syncthreads();
                 // (element, part) pairs element-fastest: neighbouring
                 // threads read neighbouring words of one part
                 const int np = ns * G;
-                for (int p0 = 0; p0 < np; p0 += kAT * kExB) {
+                for (int p0 = 0; p0 < np; p0 += NT * kExB) {
                     long long v[kExB];
 #pragma unroll
                     for (int u = 0; u < kExB; ++u) {
-                        const int p = min(p0 + u * kAT + (int)threadIdx.x, np - 1);
+                        const int p = min(p0 + u * NT + (int)threadIdx.x, np - 1);
                         const int q = p / ns, e = p - q * ns;
                         v[u] = __hip_atomic_load(&base[(int64_t)q * ne + e0 + e], __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
                     }
 #pragma unroll
                     for (int u = 0; u < kExB; ++u) {
-                        const int p = p0 + u * kAT + (int)threadIdx.x;
+                        const int p = p0 + u * NT + (int)threadIdx.x;
                         if (p < np) {
                             const int e = p % ns;
                             atomicAdd((unsigned long long *)&L.s_sum[e], (unsigned long long)v[u]);
@@ -620,20 +1173,19 @@ __global__ __launch_bounds__(kAT) void k_lloyd_persist(
                     }
                 }
                 __syncthreads();
-                for (int i = threadIdx.x; i < ns; i += kAT)
+                for (int i = threadIdx.x; i < ns; i += NT)
                     __hip_atomic_store(&tot[e0 + i], L.s_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
                 arrive_wait((uint32_t)G * (uint32_t)(2 * it + 2));
-                for (int e = threadIdx.x; e < ne; e += kAT) {
+                for (int e = threadIdx.x; e < ne; e += NT) {
                     const long long a = __hip_atomic_load(&tot[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (e < kd) L.s_sum[e] = a;
                     else L.s_cnt[e - kd] = (unsigned int)a;
                 }
                 __syncthreads();
             }
-            const double shift_max = centers_from_sums<MF>(L, d, k, ldk, shift, tk.g == 0 ? Cr : nullptr);
-            if constexpr (MF) center_norms<D>(L, box, k, ldk);
+            const double shift_max = centers_from_sums<D, MF>(L, d, k, ldk, shift, tk.g == 0 ? Cr : nullptr);
             ++it;
             converged = shift_max < tol;
         }
@@ -671,11 +1223,12 @@ __global__ __launch_bounds__(kAT) void k_assign_acc(const float *__restrict__ P,
     double obj;
     if constexpr (MF) {
         const int64_t first_w = itm.first + (threadIdx.x >> 6) * 64;
-        float xr[4][D / 4];
+        float xr[4][D / 4], xb[4][D / 4], xn[4];
         unsigned long long nre = 0;
         load_tile<D>(P + R.x_off, first_w, R.n, xr);
-        obj = wave_tile_mf<D>(L, xr, P + R.x_off, first_w, R.n, k, ldk, box, labels + R.lab_off, acc,
-                              shift, nre);
+        center_tile<D>(xr, box, first_w, R.n, xb, xn);
+        obj = wave_tile_mf<D>(L, xb, xn, P + R.x_off, first_w, R.n, k, ldk, box, labels + R.lab_off,
+                              acc, shift, nre);
         if ((threadIdx.x & 63) == 0 && nre) atomicAdd(&rs->rechecks, nre);
     } else {
         obj = fused_tile<D, MF>(L, P + R.x_off, itm.first, R.n, d, k, ldk, box, labels + R.lab_off,
@@ -687,8 +1240,11 @@ __global__ __launch_bounds__(kAT) void k_assign_acc(const float *__restrict__ P,
     long long *gs = gsum + R.sum_off;
     for (int c = threadIdx.x; c < k; c += kAT)
         if (L.s_cnt[c]) atomicAdd((unsigned long long *)&gs[kd + c], (unsigned long long)L.s_cnt[c]);
-    for (int e = threadIdx.x; e < kd; e += kAT)
-        if (L.s_cnt[e / d]) atomicAdd((unsigned long long *)&gs[e], (unsigned long long)L.s_sum[e]);
+    for (int e = threadIdx.x; e < kd; e += kAT) {
+        const int c = e / d;
+        if (L.s_cnt[c])
+            atomicAdd((unsigned long long *)&gs[e], (unsigned long long)L.s_sum[sum_idx<D, MF>(c, e - c * d, d)]);
+    }
 }
 
 // Fused path, per iteration: new centers of run run0 + blockIdx.x from its
@@ -720,7 +1276,7 @@ __global__ __launch_bounds__(kAT) void k_update_fin(const DevRun *__restrict__ r
         gs[kd + c] = 0;
     }
     __syncthreads();
-    const double mx = centers_from_sums<false>(L, d, k, 0, shift, C + R.c_off);
+    const double mx = centers_from_sums<0, false>(L, d, k, 0, shift, C + R.c_off);
     if (threadIdx.x == 0) {
         rs->iters += 1;
         rs->phase = mx < tol ? PH_FINAL : PH_ITER;
@@ -924,7 +1480,7 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
             const float ob2 = __shfl_xor(b2[g], o, 64);
             const int32_t oi = __shfl_xor(i1[g], o, 64);
             const float nb2 = fminf(fminf(b2[g], ob2), fmaxf(b1[g], ob1));
-            const bool take = ob1 < b1[g] || (ob1 == b1[g] && oi < i1[g]);
+            const bool take = (ob1 < b1[g]) | ((ob1 == b1[g]) & (oi < i1[g]));  // no branch
             b1[g] = take ? ob1 : b1[g];
             i1[g] = take ? oi : i1[g];
             b2[g] = nb2;
@@ -1124,7 +1680,16 @@ subkm_status launch_assign(subkm_ctx *ctx, int nitems, int item_base, const floa
     return SUBKM_OK;
 }
 
-template <int D, bool MF>
+// Threads per block of the persistent kernel (every path: 256; the kernel
+// also takes 512-thread blocks, two 256-point tiles at a time, which gave no
+// gain where registers allowed four wavefronts per SIMD).
+template <int D, bool MF, bool BF>
+constexpr int persist_nt() {
+    return kAT;
+}
+
+// mf: 0 vector path, 1 float32 matrix cores, 2 split bfloat16 matrix cores
+template <int D, bool MF, bool BF>
 subkm_status launch_persist_k(subkm_ctx *ctx, int blocks, const float *P, const DevRun *runs,
                               const Task *tasks, const int32_t *task_off, float *C,
                               int32_t *labels, RunState *rs, long long *parts, double *objpart,
@@ -1134,44 +1699,67 @@ subkm_status launch_persist_k(subkm_ctx *ctx, int blocks, const float *P, const 
                     (void *)&C,       (void *)&labels, (void *)&rs,    (void *)&parts,
                     (void *)&objpart, (void *)&boxes,  (void *)&max_iter, (void *)&tol,
                     (void *)&err};
-    SUBKM_HIP(ctx, hipLaunchCooperativeKernel((const void *)k_lloyd_persist<D, MF>, dim3(blocks),
-                                              dim3(kAT), args, 0, ctx->stream));
+    constexpr int NT = persist_nt<D, MF, BF>();
+    SUBKM_HIP(ctx, hipLaunchCooperativeKernel((const void *)k_lloyd_persist<D, MF, BF, NT>, dim3(blocks),
+                                              dim3(NT), args, 0, ctx->stream));
     return SUBKM_OK;
 }
 
 template <int D>
-subkm_status launch_persist(subkm_ctx *ctx, bool mf, int blocks, const float *P,
+subkm_status launch_persist(subkm_ctx *ctx, int mf, int blocks, const float *P,
                             const DevRun *runs, const Task *tasks, const int32_t *task_off,
                             float *C, int32_t *labels, RunState *rs, long long *parts,
                             double *objpart, const uint32_t *boxes, int max_iter, double tol,
                             int *err) {
+    if constexpr (kBF<D>) {
+        if (mf == 2)
+            return launch_persist_k<D, true, true>(ctx, blocks, P, runs, tasks, task_off, C, labels, rs,
+                                                   parts, objpart, boxes, max_iter, tol, err);
+    }
     if constexpr (kHasMF<D>) {
         if (mf)
-            return launch_persist_k<D, true>(ctx, blocks, P, runs, tasks, task_off, C, labels, rs,
-                                             parts, objpart, boxes, max_iter, tol, err);
+            return launch_persist_k<D, true, false>(ctx, blocks, P, runs, tasks, task_off, C, labels, rs,
+                                                    parts, objpart, boxes, max_iter, tol, err);
     }
-    return launch_persist_k<D, false>(ctx, blocks, P, runs, tasks, task_off, C, labels, rs, parts,
-                                      objpart, boxes, max_iter, tol, err);
+    return launch_persist_k<D, false, false>(ctx, blocks, P, runs, tasks, task_off, C, labels, rs, parts,
+                                             objpart, boxes, max_iter, tol, err);
 }
 
-template <int D>
-int persist_occupancy(bool mf) {
+template <int D, bool MF, bool BF>
+int persist_occupancy_k() {
+    constexpr int NT = persist_nt<D, MF, BF>();
     int nb = 0;
-    hipError_t e;
-    if constexpr (kHasMF<D>) {
-        if (mf) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lloyd_persist<D, true>, kAT, 0);
-        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lloyd_persist<D, false>, kAT, 0);
-    } else {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lloyd_persist<D, false>, kAT, 0);
-    }
-    if (e != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lloyd_persist<D, MF, BF, NT>, NT, 0) !=
+        hipSuccess) {
         hipGetLastError();
         return 0;
     }
     return nb;
 }
 
-int persist_occupancy_d(int d, bool mf) { SUBKM_DISPATCH_D(d, persist_occupancy, mf); }
+template <int D>
+int persist_occupancy(int mf) {
+    if constexpr (kBF<D>) {
+        if (mf == 2) return persist_occupancy_k<D, true, true>();
+    }
+    if constexpr (kHasMF<D>) {
+        if (mf) return persist_occupancy_k<D, true, false>();
+    }
+    return persist_occupancy_k<D, false, false>();
+}
+
+int persist_occupancy_d(int d, int mf) { SUBKM_DISPATCH_D(d, persist_occupancy, mf); }
+
+template <int D>
+int persist_tiles_per_step(int mf) {
+    if constexpr (kHasMF<D>) {
+        if (mf == 1) return persist_nt<D, true, false>() / kAT;
+    }
+    return 1;
+}
+
+// 256-point tiles a persistent block of this path takes at a time
+int persist_tiles_per_step_d(int d, int mf) { SUBKM_DISPATCH_D(d, persist_tiles_per_step, mf); }
 
 subkm_status assign_acc_d(subkm_ctx *ctx, int d, bool mf, int nitems, int item_base,
                           const float *P, const DevRun *runs, const Item *items, const float *C,
@@ -1208,7 +1796,7 @@ subkm_status assign_big_d(subkm_ctx *ctx, int d, int nitems, int item_base, cons
                      objpart, boxes, last_pass);
 }
 
-subkm_status persist_d(subkm_ctx *ctx, int d, bool mf, int blocks, const float *P,
+subkm_status persist_d(subkm_ctx *ctx, int d, int mf, int blocks, const float *P,
                        const DevRun *runs, const Task *tasks, const int32_t *task_off, float *C,
                        int32_t *labels, RunState *rs, long long *parts, double *objpart,
                        const uint32_t *boxes, int max_iter, double tol, int *err) {
@@ -1222,7 +1810,7 @@ subkm_status persist_d(subkm_ctx *ctx, int d, bool mf, int blocks, const float *
 // blocks are free.  Every block's task list follows the global assignment
 // order, so the per-run barriers cannot wait on each other in a cycle.
 void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blocks,
-              bool exchange, int gcap, int tpb, std::vector<int32_t> &G,
+              bool exchange, int gcap, int tpb, int step, std::vector<int32_t> &G,
               std::vector<std::vector<Task>> &per_block) {
     std::vector<int> order(rr);
     auto work = [&](int r) { return (double)dr[r].n * dr[r].k * dr[r].d; };
@@ -1238,10 +1826,12 @@ void schedule(const std::vector<int> &rr, const std::vector<DevRun> &dr, int blo
         const int64_t tiles = (dr[r].n + kAT - 1) / kAT;
         int64_t g = std::llround(work(r) / std::max(target, 1.0));
         // with a per-iteration exchange every move ends in two barriers of
-        // the run's G blocks: keep G at most gcap and at least tpb tiles per block
+        // the run's G blocks: keep G at most gcap and at least tpb tiles per
+        // block; never fewer tiles per block than a block takes at a time
+        const int64_t per = std::max(std::max(1, tpb), step);
         const int64_t gmax =
-            exchange ? std::min<int64_t>(std::min(gcap, kMaxG), std::max<int64_t>(1, tiles / std::max(1, tpb)))
-                     : tiles;
+            exchange ? std::min<int64_t>(std::min(gcap, kMaxG), std::max<int64_t>(1, tiles / per))
+                     : (tiles + step - 1) / step;
         g = std::max<int64_t>(1, std::min<int64_t>({g, gmax, (int64_t)blocks}));
         G[r] = (int32_t)g;
         std::vector<Slot> take;
@@ -1284,6 +1874,9 @@ void plan_runs(const subkm_run *runs, int32_t R, int32_t precision, int32_t max_
         const int64_t kd = (int64_t)u.k * u.d;
         const bool mf_shape = (u.d == 4 || u.d == 8 || u.d == 16 || u.d == 32 || u.d == 64 || u.d == 128);
         D.mf = (mf_shape && (int64_t)u.d * (u.k + 16) <= kCF) ? 1 : 0;
+        // split bfloat16 matrix cores where D allows (16-byte row loads: the
+        // caller's pointer alignment is checked per call, see lloyd_run)
+        if (D.mf && (u.d == 8 || u.d == 16 || u.d == 32)) D.mf = 2;
         D.fused = (kd <= kSumW && kd <= kCF && u.k <= kMaxK) ? 1 : 0;
         // a run with moves whose tiles would overload the kMaxG blocks that
         // can share one run's partial sums takes the wide path, whose update
@@ -1362,6 +1955,16 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
     PlanSizes z;
     plan_runs(runs, R, precision, max_iter, dr, z);
     for (int r = 0; r < R; ++r) dr[r].orig = ord[r];
+    {
+        // the split path loads 16-byte row pieces: with any run's rows not
+        // 16-byte aligned, every such run takes the float32 matrix cores
+        bool aligned = true;
+        for (int r = 0; r < R; ++r)
+            if (dr[r].mf == 2 && ((uintptr_t)(P + dr[r].x_off) & 15u)) aligned = false;
+        if (!aligned)
+            for (int r = 0; r < R; ++r)
+                if (dr[r].mf == 2) dr[r].mf = 1;
+    }
     int64_t sum_words = z.sum_words, box_words = z.box_words, cnt_words = z.cnt_words;
     const int64_t order_words = z.order_words, frag_words = z.frag_words, cn_words = z.cn_words;
     std::vector<std::pair<int, int>> ds;  // distinct (attribute count, matrix-core path)
@@ -1429,12 +2032,13 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
                     rr.push_back(r);
                     tiles += (dr[r].n + kAT - 1) / kAT;
                 }
-            const int occ = std::max(1, persist_occupancy_d(dv, mv != 0));
+            const int occ = std::max(1, persist_occupancy_d(dv, mv));
+            const int step = persist_tiles_per_step_d(dv, mv);
             const int64_t cap = std::max<int64_t>(1, (int64_t)ctx->cu_count * occ / std::max(1, sc.bdiv));
-            const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cap, tiles));
+            const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cap, (tiles + step - 1) / step));
             std::vector<int32_t> G(R, 1);
             std::vector<std::vector<Task>> pb;
-            schedule(rr, dr, blocks, max_iter > 0, sc.gcap, sc.tpb, G, pb);
+            schedule(rr, dr, blocks, max_iter > 0, sc.gcap, sc.tpb, step, G, pb);
             for (int r : rr) {
                 DevRun &D = dr[r];
                 D.G = G[r];
@@ -1579,7 +2183,7 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
         // a barrier that gives up sets the context's sticky flag, which
         // subkm_synchronize reports
         for (const Group &g : groups)
-            SUBKM_TRY(persist_d(ctx, g.d, g.mf != 0, g.blocks, P, d_runs, d_tasks, d_toff + g.block0,
+            SUBKM_TRY(persist_d(ctx, g.d, g.mf, g.blocks, P, d_runs, d_tasks, d_toff + g.block0,
                                 C, labels, d_rs, parts, d_obj, d_box, max_iter, tol, ctx->sticky));
         if (ctx->coop) {
             SUBKM_HIP(ctx, hipEventRecord(ctx->coop->ev, s));

@@ -121,25 +121,32 @@ __device__ __forceinline__ int32_t wave_count_add(int32_t *counter, bool active,
     return base + rank;
 }
 
-// Deterministic sum of one double per thread of a kAT block (fixed tree).
+// Deterministic sum of one double per thread over each kAT-thread part of an
+// NT-thread block (fixed tree, the same for every part and every NT); every
+// thread gets its part's sum.
+template <int NT = kAT>
 __device__ __forceinline__ double block_sum_det(double v, double *sh) {
+    static_assert(NT % kAT == 0, "block of whole parts");
     sh[threadIdx.x] = v;
     __syncthreads();
+    const int b = NT == kAT ? 0 : (int)(threadIdx.x & ~(kAT - 1));
+    const int i = NT == kAT ? (int)threadIdx.x : (int)(threadIdx.x & (kAT - 1));
 #pragma unroll
     for (int s = kAT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
+        if (i < s) sh[b + i] = sh[b + i] + sh[b + i + s];
         __syncthreads();
     }
-    double r = sh[0];
+    double r = sh[b];
     __syncthreads();
     return r;
 }
 
+template <int NT = kAT>
 __device__ __forceinline__ double block_max(double v, double *sh) {
     sh[threadIdx.x] = v;
     __syncthreads();
 #pragma unroll
-    for (int s = kAT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
