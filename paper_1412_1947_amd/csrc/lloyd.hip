@@ -130,6 +130,16 @@ struct FusedLdsT {
 };
 using FusedLds = FusedLdsT<kAT>;
 
+// This thread's index, opaque to the optimizer: loops of the persistent
+// kernel that start at it would otherwise have their per-thread index
+// arithmetic hoisted out of the pass and task loops and kept live (then
+// spilled) through the whole kernel.
+__device__ __forceinline__ int opaque_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 template <bool MF>
 __device__ __forceinline__ int cidx(int c, int j, int d, int ldk) {
     return MF ? j * ldk + c : c * d + j;
@@ -571,6 +581,8 @@ struct BfLdsT {
     double s_red[NT];
     int32_t s_ulist[kUList];  // uncertain points of this pass, resolved before the exchange
     uint32_t s_nu;
+    float s_mid[32];          // the run's box midpoint m (read here, not held in registers)
+    float s_Q;                // offset that makes every value positive (see stage1_bf)
     float s_R;
 };
 
@@ -591,7 +603,7 @@ template <int D, class LT>
 __device__ void center_prep_bf(LT &L, const uint32_t *box, int k, int ldk) {
     float mx = 0.0f;
     const int kr = (k + 15) & ~15;
-    for (int c = threadIdx.x; c < kr; c += LT::kThreads) {
+    for (int c = opaque_tid(); c < kr; c += LT::kThreads) {
         float a = INFINITY;
         if (c < k) {
             a = 0.0f;
@@ -601,7 +613,7 @@ __device__ void center_prep_bf(LT &L, const uint32_t *box, int k, int ldk) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int j = 8 * q + e;
-                    const float t = L.sC[j * ldk + c] - box_mid(box, D, j);
+                    const float t = L.sC[j * ldk + c] - L.s_mid[j];
                     a = __builtin_fmaf(t, t, a);
                     const float v = -2.0f * t;
                     const __bf16 h = (__bf16)v;
@@ -617,7 +629,7 @@ __device__ void center_prep_bf(LT &L, const uint32_t *box, int k, int ldk) {
 #pragma unroll
             for (int q = 0; q < D / 4; ++q) L.sA[sa_idx<D>(c, q)] = z;
         }
-        L.cn[c] = a;
+        L.cn[c] = a + L.s_Q;  // +inf past k
     }
     const double r = block_max<LT::kThreads>((double)mx, L.s_red);
     if (threadIdx.x == 0) L.s_R = sqrtf((float)r);
@@ -644,17 +656,21 @@ __device__ __forceinline__ void load_tile_bf(const float *X, int64_t first_w, in
     }
 }
 
-// Centered and split tile (points past n become 0) and the norms ||x - m||.
+// Centered and split tile (points past n become 0), the norms ||x - m||, and
+// the raw attributes this lane adds to the sums (xa): the 32 / D lanes that
+// hold the same 8 attributes of a point take D / 4 of them each, lane kg the
+// part (8 kg / D), so that only those stay in registers through stage 1.
 template <int D>
-__device__ __forceinline__ void split_tile_bf(const float (&xr)[4][8], const uint32_t *box,
+__device__ __forceinline__ void split_tile_bf(const float (&xr)[4][8], const float *s_mid,
                                               int64_t first_w, int64_t n, bf16x8 (&ah)[4],
-                                              bf16x8 (&al)[4], float (&xn)[4]) {
+                                              bf16x8 (&al)[4], float (&xn)[4],
+                                              float (&xa)[4][D / 4]) {
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kg = lane >> 4;
     const int j0 = (8 * kg) % D;
     float mq[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) mq[e] = box_mid(box, D, j0 + e);
+    for (int e = 0; e < 8; ++e) mq[e] = s_mid[j0 + e];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const bool ok = first_w + g * 16 + col < n;
@@ -671,18 +687,27 @@ __device__ __forceinline__ void split_tile_bf(const float (&xr)[4][8], const uin
         if constexpr (D >= 16) s2 += __shfl_xor(s2, 16, 64);
         if constexpr (D >= 32) s2 += __shfl_xor(s2, 32, 64);
         xn[g] = sqrtf(s2);
+        constexpr int QA = D / 4;
+        const int part = (8 * kg) / D;
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            // element part * QA + q, chosen without indexing registers
+            float v = xr[g][q];
+#pragma unroll
+            for (int pp = 1; pp < 8 / QA; ++pp) v = part == pp ? xr[g][pp * QA + q] : v;
+            xa[g][q] = v;
+        }
     }
 }
 
 // Stage 1 of a split tile: labels and (if asked) sums of the certain points,
-// stage-1 labels with the uncertain flag in wlab, as stage1_mfma.  The lanes
-// that hold the same 8 raw attributes of a point (xr, from load_tile_bf)
-// share its sums: each adds D/4 of them, from its registers.  Once the
-// products are done, the next tile's raw attributes are requested into xq
-// (next_w < 0: none), so that their loads overlap the rest of the tile.
+// stage-1 labels with the uncertain flag in wlab, as stage1_mfma.  Each lane
+// adds its share xa of its point's attributes (from split_tile_bf).  Once
+// the products are done, the next tile's raw attributes are requested into
+// xq (next_w < 0: none), so that their loads overlap the rest of the tile.
 template <int D, class LT>
 __device__ void stage1_bf(LT &L, const bf16x8 (&ah)[4], const bf16x8 (&al)[4], const float (&xn)[4],
-                          const float (&xr)[4][8], float (&xq)[4][8], int64_t next_w, const float *X,
+                          const float (&xa)[4][D / 4], float (&xq)[4][8], int64_t next_w, const float *X,
                           int64_t first_w, int64_t n, int k, int32_t *lab_out, bool accumulate,
                           int shift, int32_t *wlab) {
     constexpr int S = D / 8;                 // instructions per group and center block
@@ -703,13 +728,21 @@ __device__ void stage1_bf(LT &L, const bf16x8 (&ah)[4], const bf16x8 (&al)[4], c
 #pragma unroll
         for (int g = 0; g < 4; ++g) b8[g] = kg >= 2 ? al[g] : ah[g];
     }
-    float b1[4], b2[4];
-    int32_t i1[4];
+    // Selection on keys: every value is positive (the accumulator starts at
+    // ||c - m||^2 + Q, Q >= max ||x - m||^2, and the error bound is far below
+    // Q / 256), so its bits order like the value as unsigned integers.  The
+    // low IB bits are replaced by the lane's candidate number (c0 / 4 + r),
+    // which makes one minimum and one median per value keep the two smallest
+    // keys and the first one's center; the bits dropped are covered in the
+    // certainty test below.
+    const int nlocal = 4 * ((k + 15) >> 4);         // candidates per lane
+    const int IB = 32 - __builtin_clz((unsigned)(nlocal - 1));
+    const uint32_t kmask = (1u << IB) - 1u;
+    uint32_t k1[4], k2[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        b1[g] = INFINITY;
-        b2[g] = INFINITY;
-        i1[g] = 0;
+        k1[g] = 0xFFFFFFFFu;
+        k2[g] = 0xFFFFFFFFu;
     }
     for (int c0 = 0; c0 < k; c0 += 16) {
         bf16x8 A[NA];
@@ -727,22 +760,39 @@ __device__ void stage1_bf(LT &L, const bf16x8 (&ah)[4], const bf16x8 (&al)[4], c
                 acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s % NA], B, acc[g], 0, 0, 0);
             }
         }
+        const uint32_t base = (uint32_t)(c0 >> 2);
 #pragma unroll
         for (int g = 0; g < 4; ++g)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float v = acc[g][r];
-                b2[g] = __builtin_amdgcn_fmed3f(v, b1[g], b2[g]);
-                const bool lt = v < b1[g];
-                b1[g] = lt ? v : b1[g];
-                i1[g] = lt ? c0 + 4 * kg + r : i1[g];
+                const uint32_t bits = __float_as_uint(acc[g][r]);
+                const uint32_t key = bits ^ ((bits ^ (base + (uint32_t)r)) & kmask);
+                // the median of (key, k1, k2) is the new second key (k1 <= k2)
+                k2[g] = max(min(key, k1[g]), min(max(key, k1[g]), k2[g]));
+                k1[g] = min(k1[g], key);
             }
     }
     if (next_w >= 0) load_tile_bf<D>(X, next_w, n, xq);
-    const float Rc = L.s_R;
-    constexpr float Kb = 1.52587890625e-05f + (float)(D + 3 + 2.06 * (4 * D + 1)) * 5.9604645e-8f;
-    // this lane's share of its 8 attributes: the 32 / D lanes that hold
-    // them take QA = D / 4 each, lane kg the part (8 kg / D)
+    // back to values (low bits cleared: at most 2^IB ulp below the value)
+    // and center numbers
+    float b1[4], b2[4];
+    int32_t i1[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        b1[g] = __uint_as_float(k1[g] & ~kmask);
+        b2[g] = __uint_as_float(k2[g] & ~kmask);
+        const uint32_t l = k1[g] & kmask;
+        i1[g] = (int32_t)(16 * (l >> 2) + 4 * (uint32_t)kg + (l & 3u));
+    }
+    const float Rc = L.s_R, Qc = L.s_Q;
+    // E = Ks s^2 + Ka (s^2 + Q): the split residuals, and the centering,
+    // norms and accumulation, whose terms now reach s^2 + Q
+    constexpr float Ks = 1.52587890625e-05f;
+    constexpr float Ka = (float)(D + 3 + 2.06 * (4 * D + 1)) * 5.9604645e-8f;
+    // the dropped low bits: the smallest key's value lies at most 2^IB ulp
+    // above its decoded value b1 <= b2, i.e. below 2^(IB - 23) b2 (taken twice)
+    const float Kt = __uint_as_float((uint32_t)(127 + IB - 22) << 23);
+    // this lane's share of its 8 attributes (see split_tile_bf)
     constexpr int QA = D / 4;
     const int part = (8 * kg) / D;
     const int j0 = (8 * kg) % D;
@@ -761,21 +811,17 @@ __device__ void stage1_bf(LT &L, const bf16x8 (&ah)[4], const bf16x8 (&al)[4], c
         }
         const int64_t p = first_w + g * 16 + col;
         const float sx = xn[g] + Rc;
-        const float E = Kb * sx * sx + 1e-30f;
-        const bool certain = k == 1 || (b2[g] - b1[g]) > 2.0f * E;
+        const float s2 = sx * sx, s2q = s2 + Qc;
+        const float E = Ks * s2 + Ka * s2q + 1e-30f;
+        const bool certain = k == 1 || (b2[g] - b1[g]) > 2.0f * E + Kt * b2[g];
         if (p < n && certain) {
             if (kg == 0) lab_out[p] = i1[g];
             if (accumulate) {
                 if (kg == 0) atomicAdd(&L.s_cnt[i1[g]], 1u);
 #pragma unroll
-                for (int q = 0; q < QA; ++q) {
-                    // element part * QA + q of xr[g], chosen without indexing registers
-                    float v = xr[g][q];
-#pragma unroll
-                    for (int pp = 1; pp < 8 / QA; ++pp) v = part == pp ? xr[g][pp * QA + q] : v;
+                for (int q = 0; q < QA; ++q)
                     atomicAdd((unsigned long long *)&L.s_sum[sum_idx<D, true>(i1[g], j0 + part * QA + q, D)],
-                              (unsigned long long)to_fixed(v, shift));
-                }
+                              (unsigned long long)to_fixed(xa[g][q], shift));
             }
         }
         if (kg == 0) wlab[g * 16 + col] = i1[g] | (certain ? 0 : (int32_t)0x80000000);
@@ -786,12 +832,12 @@ __device__ void stage1_bf(LT &L, const bf16x8 (&ah)[4], const bf16x8 (&al)[4], c
 // binary64 re-assignment of the uncertain points and the objective.
 template <int D, class LT>
 __device__ double wave_tile_bf(LT &L, const bf16x8 (&ah)[4], const bf16x8 (&al)[4],
-                               const float (&xn)[4], const float (&xr)[4][8], float (&xq)[4][8],
+                               const float (&xn)[4], const float (&xa)[4][D / 4], float (&xq)[4][8],
                                int64_t next_w, const float *X, int64_t first_w, int64_t n, int k,
                                int ldk, int32_t *lab_out, bool accumulate, int shift,
                                unsigned long long &nrecheck) {
     int32_t *wlab = L.s_lab + (threadIdx.x >> 6) * 64;
-    stage1_bf<D>(L, ah, al, xn, xr, xq, next_w, X, first_w, n, k, lab_out, accumulate, shift, wlab);
+    stage1_bf<D>(L, ah, al, xn, xa, xq, next_w, X, first_w, n, k, lab_out, accumulate, shift, wlab);
     return wave_tile_finish<D, true>(L, X, first_w, n, k, ldk, lab_out, accumulate, shift, nrecheck, wlab);
 }
 
@@ -809,7 +855,7 @@ __device__ void resolve_deferred(LT &L, const float *X, int k, int ldk, const ui
     const int nu = min((int)L.s_nu, kUList);
     float mq[KQ];
 #pragma unroll
-    for (int q = 0; q < KQ; ++q) mq[q] = box_mid(box, D, kk + 4 * q);
+    for (int q = 0; q < KQ; ++q) mq[q] = L.s_mid[kk + 4 * q];
     const float Rc = L.s_R;
     const float Ku = 2.0f * (float)(D + 5) * 5.9604645e-8f;
     for (int g0 = wave * 16; g0 < nu; g0 += (LT::kThreads / 64) * 16) {
@@ -863,7 +909,7 @@ __device__ void resolve_deferred(LT &L, const float *X, int k, int ldk, const ui
             b2 = nb2;
         }
         const float sx = xn + Rc;
-        const float E = Ku * sx * sx + 1e-30f;
+        const float E = Ku * (sx * sx + L.s_Q) + 1e-30f;  // values carry the offset Q
         const bool certain = k == 1 || (b2 - b1) > 2.0f * E;
         if (ok && certain) {
             if (kk == 0) {
@@ -956,7 +1002,7 @@ __device__ __forceinline__ double fused_tile(FusedLds &L, const float *X, int64_
 template <int D, bool MF, class LT>
 __device__ double centers_from_sums(LT &L, int d, int k, int ldk, int shift, float *Cglob) {
     double mx = 0.0;
-    for (int c = threadIdx.x; c < k; c += LT::kThreads) {
+    for (int c = opaque_tid(); c < k; c += LT::kThreads) {
         const unsigned int cnt = L.s_cnt[c];
         double mv2 = 0.0;
         int j = c % d;  // rotated start: neighbouring lanes read different banks
@@ -1019,6 +1065,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > kAT ? 4
         float *Cr = C + R.c_off;
         __syncthreads();
         load_centers<MF>(L, Cr, d, k, ldk);
+        if constexpr (BF) {
+            for (int j = threadIdx.x; j < D; j += NT) L.s_mid[j] = box_mid(box, D, j);
+            if (threadIdx.x == 0) {
+                // Q >= max ||x - m||^2 over the box, with margins: every |x_j - m_j|
+                // is at most max(hi_j - m_j, m_j - lo_j), and the centered values
+                // round up by a relative 2^-24 at most
+                float q = 0.0f;
+                for (int j = 0; j < D; ++j) {
+                    const float lo = ordered_float(box[j]), hi = ordered_float(box[D + j]);
+                    const float m = box_mid(box, D, j);
+                    const float a = fmaxf(hi - m, m - lo) * (1.0f + 0x1p-20f);
+                    q = __builtin_fmaf(a, a, q);
+                }
+                L.s_Q = q * (1.0f + 0x1p-8f) + 0x1p-100f;
+            }
+        }
         __syncthreads();
         int it = 0;
         bool converged = false;
@@ -1040,10 +1102,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > kAT ? 4
                 __syncthreads();  // sums, counts and the list are cleared
                 for (int64_t t = t0; t < t1; ++t) {
                     bf16x8 ah[4], al[4];
-                    float xn[4];
-                    split_tile_bf<D>(xr, box, t * kAT + wofs, R.n, ah, al, xn);
+                    float xn[4], xa[4][D / 4];
+                    split_tile_bf<D>(xr, L.s_mid, t * kAT + wofs, R.n, ah, al, xn, xa);
                     const int64_t next_w = t + 1 < t1 ? (t + 1) * kAT + wofs : -1;
-                    const double obj = wave_tile_bf<D>(L, ah, al, xn, xr, xq, next_w, X, t * kAT + wofs,
+                    const double obj = wave_tile_bf<D>(L, ah, al, xn, xa, xq, next_w, X, t * kAT + wofs,
                                                        R.n, k, ldk, lab, !last, shift, nre);
 #pragma unroll
                     for (int g = 0; g < 4; ++g)
@@ -1178,10 +1240,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > kAT ? 4
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
                 arrive_wait((uint32_t)G * (uint32_t)(2 * it + 2));
-                for (int e = threadIdx.x; e < ne; e += NT) {
-                    const long long a = __hip_atomic_load(&tot[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (e < kd) L.s_sum[e] = a;
-                    else L.s_cnt[e - kd] = (unsigned int)a;
+                // kExB loads in flight per thread (one at a time, each would
+                // wait out the full latency of the coherence point)
+                for (int e0 = 0; e0 < ne; e0 += NT * kExB) {
+                    long long v[kExB];
+#pragma unroll
+                    for (int u = 0; u < kExB; ++u)
+                        v[u] = __hip_atomic_load(&tot[min(e0 + u * NT + (int)threadIdx.x, ne - 1)],
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                    for (int u = 0; u < kExB; ++u) {
+                        const int e = e0 + u * NT + (int)threadIdx.x;
+                        if (e < kd) L.s_sum[e] = v[u];
+                        else if (e < ne) L.s_cnt[e - kd] = (unsigned int)v[u];
+                    }
                 }
                 __syncthreads();
             }
