@@ -581,6 +581,7 @@ struct BfLdsT {
     double s_red[NT];
     int32_t s_ulist[kUList];  // uncertain points of this pass, resolved before the exchange
     uint32_t s_nu;
+    uint32_t s_next;          // next 64-point piece of the block's tiles (passes with an update)
     float s_mid[32];          // the run's box midpoint m (read here, not held in registers)
     float s_Q;                // offset that makes every value positive (see stage1_bf)
     float s_R;
@@ -1092,29 +1093,51 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > kAT ? 4
             for (int e = threadIdx.x; e < kd; e += NT) L.s_sum[e] = 0;
             for (int c = threadIdx.x; c < k; c += NT) L.s_cnt[c] = 0;
             if constexpr (BF) {
-                // split path: the next tile's raw points load while this one
-                // finishes (requested after its products)
-                const int64_t wofs = (threadIdx.x >> 6) * 64;
+                // split path: the next piece's raw points load while this one
+                // finishes (requested after its products).  On a pass with
+                // an update every wavefront takes the block's 64-point pieces
+                // from a counter, so that a wavefront that finishes early
+                // takes more; the last pass keeps them in place (piece
+                // 4 i + wave), since its objective is summed per tile in the
+                // fixed order of the plain form.
+                const int wave = (int)(threadIdx.x >> 6);
+                const uint32_t npc = (uint32_t)(t1 - t0) * 4u;  // pieces of this block
+                auto take = [&]() -> uint32_t {
+                    uint32_t w = 0;
+                    if ((threadIdx.x & 63) == 0) w = atomicAdd(&L.s_next, 1u);
+                    return __shfl(w, 0, 64);
+                };
+                auto piece_first = [&](uint32_t w) -> int64_t {
+                    return (t0 + (int64_t)(w >> 2)) * kAT + (int64_t)(w & 3u) * 64;
+                };
                 float xr[4][8], xq[4][8];
                 unsigned long long nre = 0;
-                if (t0 < t1) load_tile_bf<D>(X, t0 * kAT + wofs, R.n, xr);
-                if (threadIdx.x == 0) L.s_nu = 0;
-                __syncthreads();  // sums, counts and the list are cleared
-                for (int64_t t = t0; t < t1; ++t) {
+                if (threadIdx.x == 0) {
+                    L.s_nu = 0;
+                    L.s_next = 4;  // pieces 0..3 go to waves 0..3 below
+                }
+                uint32_t w = (uint32_t)wave;
+                if (w < npc) load_tile_bf<D>(X, piece_first(w), R.n, xr);
+                __syncthreads();  // sums, counts, list and counter are set
+                while (w < npc) {
                     bf16x8 ah[4], al[4];
                     float xn[4], xa[4][D / 4];
-                    split_tile_bf<D>(xr, L.s_mid, t * kAT + wofs, R.n, ah, al, xn, xa);
-                    const int64_t next_w = t + 1 < t1 ? (t + 1) * kAT + wofs : -1;
-                    const double obj = wave_tile_bf<D>(L, ah, al, xn, xa, xq, next_w, X, t * kAT + wofs,
-                                                       R.n, k, ldk, lab, !last, shift, nre);
+                    const int64_t fw = piece_first(w);
+                    split_tile_bf<D>(xr, L.s_mid, fw, R.n, ah, al, xn, xa);
+                    const uint32_t wn = last ? w + 4u : take();
+                    const int64_t next_w = wn < npc ? piece_first(wn) : -1;
+                    const double obj = wave_tile_bf<D>(L, ah, al, xn, xa, xq, next_w, X, fw, R.n, k, ldk,
+                                                       lab, !last, shift, nre);
 #pragma unroll
                     for (int g = 0; g < 4; ++g)
 #pragma unroll
                         for (int e = 0; e < 8; ++e) xr[g][e] = xq[g][e];
                     if (last) {
+                        // every wavefront is at piece w of tile w / 4 (in place)
                         const double tot = block_sum_det(obj, L.s_red);
-                        if (threadIdx.x == 0) objpart[R.item0 + t] = tot;
+                        if (threadIdx.x == 0) objpart[R.item0 + t0 + (w >> 2)] = tot;
                     }
+                    w = wn;
                 }
                 if (!last) {
                     __syncthreads();  // the list is complete
@@ -1211,32 +1234,64 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > kAT ? 4
                 long long *tot = parts + R.part_off + 2ll * G * ne + (int64_t)(it & 1) * ne;
                 const int S = (ne + G - 1) / G;
                 const int e0 = min(ne, tk.g * S), ns = min(ne, e0 + S) - e0;
-                for (int i = threadIdx.x; i < ns; i += NT) L.s_sum[i] = 0;
-                __syncthreads();
-                // (element, part) pairs element-fastest: neighbouring
-                // threads read neighbouring words of one part
-                const int np = ns * G;
-                for (int p0 = 0; p0 < np; p0 += NT * kExB) {
-                    long long v[kExB];
+                if (G <= 8) {
+                    // few parts: every thread sums its elements of the slice
+                    // over the G parts in registers, kSumEl elements a round
+                    // (loads clamped to valid words, values masked)
+                    constexpr int kSumEl = 8;
+                    for (int i0 = 0; i0 < ns; i0 += NT * kSumEl) {
+                        if (i0 + (int)threadIdx.x >= ns) break;  // no element of this thread
+                        long long acc[kSumEl];
 #pragma unroll
-                    for (int u = 0; u < kExB; ++u) {
-                        const int p = min(p0 + u * NT + (int)threadIdx.x, np - 1);
-                        const int q = p / ns, e = p - q * ns;
-                        v[u] = __hip_atomic_load(&base[(int64_t)q * ne + e0 + e], __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-                    }
+                        for (int u = 0; u < kSumEl; ++u) acc[u] = 0;
+                        for (int q0 = 0; q0 < G; q0 += 2) {
+                            long long v[2][kSumEl];
 #pragma unroll
-                    for (int u = 0; u < kExB; ++u) {
-                        const int p = p0 + u * NT + (int)threadIdx.x;
-                        if (p < np) {
-                            const int e = p % ns;
-                            atomicAdd((unsigned long long *)&L.s_sum[e], (unsigned long long)v[u]);
+                            for (int pq = 0; pq < 2; ++pq)
+#pragma unroll
+                                for (int u = 0; u < kSumEl; ++u) {
+                                    const int q = min(q0 + pq, G - 1);
+                                    const int e = min(i0 + u * NT + (int)threadIdx.x, ns - 1);
+                                    v[pq][u] = __hip_atomic_load(&base[(int64_t)q * ne + e0 + e], __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                                }
+#pragma unroll
+                            for (int pq = 0; pq < 2; ++pq)
+#pragma unroll
+                                for (int u = 0; u < kSumEl; ++u) acc[u] += q0 + pq < G ? v[pq][u] : 0ll;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kSumEl; ++u) {
+                            const int e = i0 + u * NT + (int)threadIdx.x;
+                            if (e < ns) __hip_atomic_store(&tot[e0 + e], acc[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         }
                     }
+                } else {
+                    // many parts (short slices): (element, part) pairs
+                    // element-fastest over all threads, kExB loads in flight
+                    // each, summed by LDS atomics
+                    for (int i = threadIdx.x; i < ns; i += NT) L.s_sum[i] = 0;
+                    __syncthreads();
+                    const int np = ns * G;
+                    for (int p0 = 0; p0 < np; p0 += NT * kExB) {
+                        long long v[kExB];
+#pragma unroll
+                        for (int u = 0; u < kExB; ++u) {
+                            const int p = min(p0 + u * NT + (int)threadIdx.x, np - 1);
+                            const int q = p / ns, e = p - q * ns;
+                            v[u] = __hip_atomic_load(&base[(int64_t)q * ne + e0 + e], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                        }
+#pragma unroll
+                        for (int u = 0; u < kExB; ++u) {
+                            const int p = p0 + u * NT + (int)threadIdx.x;
+                            if (p < np) atomicAdd((unsigned long long *)&L.s_sum[p % ns], (unsigned long long)v[u]);
+                        }
+                    }
+                    __syncthreads();
+                    for (int i = threadIdx.x; i < ns; i += NT)
+                        __hip_atomic_store(&tot[e0 + i], L.s_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                __syncthreads();
-                for (int i = threadIdx.x; i < ns; i += NT)
-                    __hip_atomic_store(&tot[e0 + i], L.s_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
                 arrive_wait((uint32_t)G * (uint32_t)(2 * it + 2));
@@ -2299,8 +2354,11 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
 // the shape, and the call is made once more with it.  Results are identical
 // under every schedule, so tuning only changes the time.
 namespace {
+// (a few blocks per run suit calls of one or few runs, whose time is the
+// per-move exchange among their blocks)
 const LloydSched kCandidates[] = {{64, 1, 2}, {32, 1, 2}, {16, 1, 2}, {64, 2, 2},
-                                  {32, 2, 2}, {16, 2, 2}, {128, 1, 1}, {64, 1, 1}};
+                                  {32, 2, 2}, {16, 2, 2}, {128, 1, 1}, {64, 1, 1},
+                                  {8, 1, 2},  {4, 1, 2}};
 
 TuneKey shape_key(const subkm_run *runs, int32_t R, int32_t precision, int32_t max_iter) {
     int64_t npts = 0;
