@@ -313,7 +313,11 @@ typedef struct {
     int64_t T;               /* subclusters                                   */
     int64_t M;               /* local centers                                 */
     int32_t final_iters;     /* moves of the final run                        */
-    int32_t reserved;
+    int32_t sub_selections;  /* Algorithm 1: selection passes of the
+                                subclustering, T - 1 when every round selects
+                                on its own, fewer when consecutive rounds
+                                share a landmark and one pass selects all
+                                their subclusters; 0 with Algorithm 2        */
     int64_t local_point_iters; /* sum over local runs of n_r * iters_r        */
     int64_t final_point_iters; /* M * final_iters                             */
     double us_scale;         /* phase times, microseconds (device events)     */

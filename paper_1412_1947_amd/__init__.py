@@ -59,7 +59,7 @@ class Opts(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int64), ("M", ctypes.c_int64), ("final_iters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("local_point_iters", ctypes.c_int64),
+                ("sub_selections", ctypes.c_int32), ("local_point_iters", ctypes.c_int64),
                 ("final_point_iters", ctypes.c_int64), ("us_scale", ctypes.c_double),
                 ("us_subcluster", ctypes.c_double), ("us_local", ctypes.c_double),
                 ("us_final", ctypes.c_double), ("us_label", ctypes.c_double),

@@ -668,6 +668,9 @@ subkm_status subkm_cluster(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
         SUBKM_HIP(ctx, hipMemcpy(&nr, nrecheck, sizeof nr, hipMemcpyDeviceToHost));
         SUBKM_TRY(check_sticky(ctx));
         stats->rechecked = (int64_t)nr;
+        int64_t nsel = 0;
+        if (!uneq) SUBKM_TRY(subcluster_selections(ctx, S, P, n, d, N, o.metric, &nsel));
+        stats->sub_selections = (int32_t)nsel;
         stats->T = T;
         stats->M = M;
         stats->final_iters = hit[R];

@@ -205,6 +205,8 @@ subkm_status scale_cm_impl(subkm_ctx *ctx, const float *X, int64_t n, int32_t d,
 subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t d, int64_t N,
                              int32_t landmark_mode, int32_t metric, float *P, int32_t *perm,
                              int64_t *offsets, float *landmarks);
+subkm_status subcluster_selections(subkm_ctx *ctx, const float *S, const float *P, int64_t n,
+                                   int32_t d, int64_t N, int32_t metric, int64_t *out);
 // Largest number of groups of the unequal subclustering (one LDS counter per
 // group in the histogram and placement kernels).
 constexpr int64_t kUqMaxGroups = 8192;

@@ -509,7 +509,7 @@ __device__ double wave_tile_finish(LT &L, const float *X, int64_t first_w, int64
         if (accumulate && todo) {
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(&L.s_nu, (uint32_t)__popcll(todo));
-            base = __shfl(base, 0, 64);
+            base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
             const bool mine = (todo >> lane) & 1ull;
             const uint32_t slot = base + (uint32_t)__popcll(todo & ((1ull << lane) - 1ull));
             if (mine && slot < (uint32_t)kUList) L.s_ulist[slot] = (int32_t)i;
@@ -554,14 +554,20 @@ __device__ double wave_tile_mf(LT &L, const float (&xb)[4][D / 4], const float (
 // bfloat16 parts (round to nearest), a = ah + al and -2 c = ch + cl, and the
 // four products ch ah, cl ah, ch al, cl al, each exact in float32, are summed
 // by the instruction with K laid out as four terms of D attributes
-// (kappa = term * D + j).  Error bound of one value v, s = ||x - m|| + R:
-//   centering and norms    (D + 3) u s^2                       u = 2^-24
+// (kappa = term * D + j).  The accumulator starts at ||c - m||^2 + Q, with Q
+// at least the largest ||x - m||^2 of the run's box, so every value is
+// positive.  Error bound of one value v, s = ||x - m|| + R, u = 2^-24:
 //   split residuals        4 * 2^-16 sum_j |a_j| |c_j|  <=  2^-16 s^2
+//   centering and norms    (D + 3) u (s^2 + Q)
 //   accumulation           (4 D + 1) additions that may each round toward
-//                          zero: 2 (4 D + 1) u (1.03 s^2)
-// so E = (2^-16 + (D + 3 + 2.06 (4 D + 1)) u) s^2 + 1e-30, and the gap of the
-// two smallest values is certain when it exceeds 2 E.  Uncertain points are
-// re-assigned in binary64 like on the other paths, so labels are unchanged.
+//                          zero, on partial sums below 1.03 (s^2 + Q):
+//                          2 (4 D + 1) u (1.03 (s^2 + Q))
+// so E = 2^-16 s^2 + (D + 3 + 2.06 (4 D + 1)) u (s^2 + Q) + 1e-30, and the
+// gap of the two smallest values is certain when it exceeds 2 E (plus the
+// bits the selection keys drop, see stage1_bf).  Uncertain points are
+// checked again on float32 matrix cores and, if still close, in binary64
+// (resolve_deferred, wave_argmin_exact), so labels are those of the other
+// paths.
 template <int D>
 constexpr bool kBF = D == 8 || D == 16 || D == 32;
 
@@ -1105,7 +1111,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > kAT ? 4
                 auto take = [&]() -> uint32_t {
                     uint32_t w = 0;
                     if ((threadIdx.x & 63) == 0) w = atomicAdd(&L.s_next, 1u);
-                    return __shfl(w, 0, 64);
+                    return (uint32_t)__builtin_amdgcn_readlane((int)w, 0);
                 };
                 auto piece_first = [&](uint32_t w) -> int64_t {
                     return (t0 + (int64_t)(w >> 2)) * kAT + (int64_t)(w & 3u) * 64;

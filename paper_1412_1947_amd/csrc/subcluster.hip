@@ -116,17 +116,43 @@ __device__ __forceinline__ float vget(const float4 &v, int c) {
     return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront in registers (DPP
+// row shifts within each row of 16 lanes, then the row broadcasts of lanes
+// 15 and 31), with no LDS round trip.  Every lane must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+// The same for 64-bit values (each step moves both halves, then adds with carry).
+__device__ __forceinline__ unsigned long long wave_incl_scan64(unsigned long long x) {
+#define SUBKM_SCAN64_STEP(ctrl, rmask)                                                              \
+    {                                                                                              \
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, ctrl, rmask, 0xf, false); \
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), ctrl, rmask, 0xf, false); \
+        x += ((unsigned long long)hi << 32) | lo;                                                  \
+    }
+    SUBKM_SCAN64_STEP(0x111, 0xf)
+    SUBKM_SCAN64_STEP(0x112, 0xf)
+    SUBKM_SCAN64_STEP(0x114, 0xf)
+    SUBKM_SCAN64_STEP(0x118, 0xf)
+    SUBKM_SCAN64_STEP(0x142, 0xa)
+    SUBKM_SCAN64_STEP(0x143, 0xc)
+#undef SUBKM_SCAN64_STEP
+    return x;
+}
+
 // Exclusive scan of one value per thread over an NT-thread block.  Returns
 // the prefix; *total receives the block sum.  `tmp` holds NT/64 words.
 template <int NT>
 __device__ uint32_t block_scan(uint32_t v, uint32_t *tmp, uint32_t *total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    const uint32_t x = wave_incl_scan(v);
     if (lane == 63) tmp[wave] = x;
     __syncthreads();
     uint32_t wbase = 0, tot = 0;
@@ -482,12 +508,7 @@ __device__ void find_bin1(const uint32_t *hist1, uint32_t need, uint32_t *s_part
             uint32_t c = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) c += s_part[q * 64 + lane];
-            uint32_t inc = c;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(inc, o, 64);
-                if (lane >= o) inc += y;
-            }
+            const uint32_t inc = wave_incl_scan(c);
             const uint32_t ex = under + inc - c;
             if (ex < need && need <= ex + c) {
                 s_res[0] = lane;
@@ -523,7 +544,7 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const uint32_t p = p0 + u * kT + threadIdx.x;
-        kb[u] = p < nrem ? keys[p] : 0.0;
+        kb[u] = keys[min(p, nrem - 1)];  // clamped, unconditional
     }
     // every block finds the boundary bin itself (h serves as scratch)
     uint32_t astar, below1, cnt1;
@@ -551,7 +572,7 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
             const uint32_t first = (uint32_t)__ffsll((unsigned long long)m) - 1;
             uint32_t slot0 = 0;
             if (lane == (int)first) slot0 = atomicAdd(&s_nc, cnt);
-            slot0 = __shfl(slot0, first, 64);
+            slot0 = (uint32_t)__builtin_amdgcn_readlane((int)slot0, (int)first);
             if (c) {
                 const uint32_t slot = slot0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
                 s_ck[slot] = k;
@@ -677,8 +698,9 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const uint32_t c = c0 + u * kST + threadIdx.x;
-            kk[u] = c < ncand ? ckey[c] : 0.0;
-            pp[u] = c < ncand ? cpos[c] : 0u;
+            const uint32_t cc = min(c, ncand - 1);  // clamped, unconditional
+            kk[u] = ckey[cc];
+            pp[u] = cpos[cc];
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -1363,12 +1385,7 @@ __device__ void batch_plan(const RoundBufs &B, uint32_t a, uint32_t t, uint32_t 
         uint32_t c = 0;
 #pragma unroll
         for (int r = 0; r < 8; ++r) c += Lp.part[r * 64 + lane];
-        uint32_t inc = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
-        }
+        const uint32_t inc = wave_incl_scan(c);
         Lp.gpre[lane] = inc - c;
         if (lane == 63) Lp.gpre[64] = inc;
     }
@@ -1391,12 +1408,7 @@ __device__ void batch_plan(const RoundBufs &B, uint32_t a, uint32_t t, uint32_t 
         uint32_t c = 0;
 #pragma unroll
         for (int r = 0; r < kRep; ++r) c += B.hist1[r * kBins + g * 64 + lane];
-        uint32_t inc = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
-        }
+        const uint32_t inc = wave_incl_scan(c);
         const uint32_t lo = Lp.gpre[g] + inc - c;  // points below bin g * 64 + lane
         if (target) {
             const uint64_t m = __ballot(lo < rank && rank <= lo + c);
@@ -1442,7 +1454,7 @@ __global__ __launch_bounds__(kT) void k_candm(RoundBufs B, uint32_t t, uint32_t 
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const uint32_t p = p0 + u * kT + threadIdx.x;
-        kb[u] = p < nrem ? keys[p] : 0.0;
+        kb[u] = keys[min(p, nrem - 1)];  // clamped, unconditional
     }
     if (threadIdx.x <= (uint32_t)kQMax) s_cc[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_nc = 0;
@@ -1454,6 +1466,10 @@ __global__ __launch_bounds__(kT) void k_candm(RoundBufs B, uint32_t t, uint32_t 
         B.bp->cnt[threadIdx.x] = Lp.tcnt[threadIdx.x];
         if (threadIdx.x == 0) B.bp->q = q;
     }
+    // the targets' level-1 bins in registers (padding above every bin)
+    uint32_t tb[kQMax];
+#pragma unroll
+    for (int i = 0; i < kQMax; ++i) tb[i] = (uint32_t)i < q ? Lp.tbin[i] : 0xFFFFFFFFu;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const uint32_t p = p0 + u * kT + threadIdx.x;
@@ -1461,16 +1477,17 @@ __global__ __launch_bounds__(kT) void k_candm(RoundBufs B, uint32_t t, uint32_t 
         const uint32_t v = in ? vmap(kb[u], base, vsh) : 0u;
         const uint32_t b = v >> 12;
         uint32_t lo = 0, hi = 0;
-        for (uint32_t i = 0; i < q; ++i) {
-            lo += Lp.tbin[i] < b ? 1u : 0u;
-            hi += Lp.tbin[i] <= b ? 1u : 0u;
+#pragma unroll
+        for (int i = 0; i < kQMax; ++i) {
+            lo += tb[i] < b ? 1u : 0u;
+            hi += tb[i] <= b ? 1u : 0u;
         }
         const bool sure = in && lo == hi;
         // sure points: one ballot per class present in the wave
         uint64_t rest = __ballot(sure);
         while (rest) {
             const int l0 = __ffsll((unsigned long long)rest) - 1;
-            const uint32_t c0 = __shfl(lo, l0, 64);
+            const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)lo, l0);
             const uint64_t m = __ballot(sure && lo == c0);
             if (lane == l0) atomicAdd(&s_cc[c0], (uint32_t)__popcll(m));
             rest &= ~m;
@@ -1482,7 +1499,7 @@ __global__ __launch_bounds__(kT) void k_candm(RoundBufs B, uint32_t t, uint32_t 
             const uint32_t first = (uint32_t)__ffsll((unsigned long long)m) - 1;
             uint32_t slot0 = 0;
             if (lane == (int)first) slot0 = atomicAdd(&s_nc, cnt);
-            slot0 = __shfl(slot0, first, 64);
+            slot0 = (uint32_t)__builtin_amdgcn_readlane((int)slot0, (int)first);
             if (c) {
                 const uint32_t slot = slot0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
                 s_ck[slot] = kb[u];
@@ -1567,12 +1584,7 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
 #pragma unroll
             for (int x = 0; x < kC; ++x) sum += h[x];
         }
-        uint32_t inc = sum;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
-        }
+        const uint32_t inc = wave_incl_scan(sum);
         const uint32_t pre = inc - sum;
         for (uint32_t i = i0; i < q && s_bin[i] == s_bin[i0]; ++i) {
             const uint32_t need1 = (i + 1) * N - s_below[i];
@@ -1614,35 +1626,47 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
         s_anyslow = slow;
     }
     __syncthreads();
-    // (2) one pass over the candidates
+    // (2) one pass over the candidates; the targets' level-2 values are
+    // held in registers (a loop over LDS values would wait for an LDS read
+    // per target and candidate), padded with values no candidate has
+    uint32_t vst[kQMax];
+#pragma unroll
+    for (int i = 0; i < kQMax; ++i) vst[i] = (uint32_t)i < q ? s_vstar[i] : 0xFFFFFFFFu;
     for (uint32_t c0 = 0; c0 < ncand; c0 += kST * kBatch) {
         double kk[kBatch];
         uint32_t pp[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const uint32_t c = c0 + u * kST + threadIdx.x;
-            kk[u] = c < ncand ? B.ckey[c] : 0.0;
-            pp[u] = c < ncand ? B.cpos[c] : 0u;
+            // clamped, unconditional: the loads go out together
+            const uint32_t cc = min(c, ncand - 1);
+            kk[u] = B.ckey[cc];
+            pp[u] = B.cpos[cc];
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const uint32_t c = c0 + u * kST + threadIdx.x;
             const bool in = c < ncand;
             const uint32_t v = vmap(kk[u], base, vsh);
+            // class: one past the last target whose level-2 value lies below
+            // v (padding is never below; v < 2^24)
             uint32_t cls = 0;
             bool member = false;
-            for (uint32_t i = 0; i < q; ++i) {
-                if (v > s_vstar[i]) cls = i + 1;
-                if (in && v == s_vstar[i]) {
-                    member = true;
-                    if (s_fast[i]) {
+#pragma unroll
+            for (int i = 0; i < kQMax; ++i) {
+                cls = v > vst[i] ? (uint32_t)i + 1u : cls;
+                member |= v == vst[i];
+            }
+            member = member && in;
+            if (member) {
+                for (uint32_t i = 0; i < q; ++i)
+                    if (v == s_vstar[i] && s_fast[i]) {
                         const uint32_t r = atomicAdd(&s_fill[i], 1u);
                         if (r < s_cnt2[i]) {
                             rk[s_seg[i] + r] = kk[u];
                             rp[s_seg[i] + r] = pp[u];
                         }
                     }
-                }
             }
             // the value alone decides every threshold (bins are monotone in
             // the key); neighbouring candidates come from one compaction
@@ -1653,7 +1677,7 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
             uint64_t rest = __ballot(cnt_it);
             while (rest) {
                 const int l0 = __ffsll((unsigned long long)rest) - 1;
-                const uint32_t k0 = __shfl(key, l0, 64);
+                const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, l0);
                 const uint64_t m = __ballot(cnt_it && key == k0);
                 if (lane == l0) {
                     if (lds_counts) atomicAdd(&csel[k0], (uint32_t)__popcll(m));
@@ -1727,23 +1751,26 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
     if (B.mk && !fixed && (int)threadIdx.x < B.d &&
         B.mk[(a & 1) * B.d + threadIdx.x] <= (unsigned long long)__double_as_longlong(s_tk[q - 1]))
         s_lch = 1u;
-    // (4) per class, one wave scans the block counts
+    // (4) per class, one wave scans the block counts, 8 chunks of 64 loaded
+    // at a time (clamped, unconditional loads)
     for (uint32_t cls = wv; cls <= q; cls += kST / 64) {
         uint32_t carry = 0;
-        for (uint32_t c0 = 0; c0 < nb; c0 += 64) {
-            const uint32_t sg = c0 + lane;
-            uint32_t v = 0;
-            if (sg < nb)
-                v = (lds_counts ? csel[cls * nb + sg] : 0u) +
-                    __hip_atomic_load(&B.blockcnt[cls * B.nbs + sg], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t inc = v;
+        for (uint32_t c0 = 0; c0 < nb; c0 += 64 * 8) {
+            uint32_t v[8];
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(inc, o, 64);
-                if (lane >= o) inc += y;
+            for (int x = 0; x < 8; ++x) {
+                const uint32_t sg = min(c0 + 64 * x + lane, nb - 1);
+                v[x] = __hip_atomic_load(&B.blockcnt[cls * B.nbs + sg], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (sg < nb) B.blockoff[cls * B.nbs + sg] = carry + inc - v;
-            carry += __shfl(inc, 63, 64);
+#pragma unroll
+            for (int x = 0; x < 8; ++x) {
+                const uint32_t sg = c0 + 64 * x + lane;
+                if (lds_counts) v[x] += csel[cls * nb + min(sg, nb - 1)];
+                if (sg >= nb) v[x] = 0;
+                const uint32_t inc = wave_incl_scan(v[x]);
+                if (sg < nb) B.blockoff[cls * B.nbs + sg] = carry + inc - v[x];
+                carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+            }
         }
     }
     __syncthreads();
@@ -1822,14 +1849,21 @@ __device__ __forceinline__ void scatterm_body(const RoundBufs &B, ScatterLds &sm
 #pragma unroll
         for (int u = 0; u < NV; ++u) v[u] = ((const V *)(B.S + (int64_t)ridx[u] * D))[j];
     }
-    // classes of the thread's positions, 4 bits each
+    // classes of the thread's positions, 4 bits each.  Most points stay:
+    // one comparison with the last threshold (held in registers) settles
+    // them, the others search the thresholds in order.
     uint32_t clsw = 0;
+    const double tk_last = all_sel ? 0.0 : sm.tk[qn - 1];
+    const uint32_t tp_last = all_sel ? 0u : sm.tp[qn - 1];
 #pragma unroll
     for (int x = 0; x < per; ++x) {
         const uint32_t lp = threadIdx.x * per + x;
         uint32_t c = 0;
-        if (!all_sel)
-            while (c < qn && !pair_le(kq[x], p0 + lp, sm.tk[c], sm.tp[c])) ++c;
+        if (!all_sel) {
+            if (!pair_le(kq[x], p0 + lp, tk_last, tp_last)) c = qn;
+            else
+                while (c + 1 < qn && !pair_le(kq[x], p0 + lp, sm.tk[c], sm.tp[c])) ++c;
+        }
         clsw |= (lp < cnt ? c : 15u) << (4 * x);
     }
     // per-class counts packed 12 bits a field, 5 fields a word (class c in
@@ -1847,12 +1881,7 @@ __device__ __forceinline__ void scatterm_body(const RoundBufs &B, ScatterLds &sm
     unsigned long long ex[2];
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
-        unsigned long long xx = packed(w);
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned long long y = __shfl_up(xx, o, 64);
-            if (lane >= o) xx += y;
-        }
+        const unsigned long long xx = wave_incl_scan64(packed(w));
         if (lane == 63) sm.wsum[wv][w] = xx;
         ex[w] = xx;
     }
@@ -2402,6 +2431,31 @@ subkm_status subcluster_impl(subkm_ctx *ctx, const float *S, int64_t n, int32_t 
                              int64_t *offsets, float *landmarks) {
     return subcluster_segment(ctx, S, n, d, N, landmark_mode, metric, P, perm, offsets,
                               landmarks, 0, ceil_div(n, N), 0);
+}
+
+// Selection passes of the last subclustering call with these arguments on
+// ctx (reads its scratch once the stream has drained): a pass serves one
+// round, or a batch of rounds that share a landmark; the last round takes
+// every point left and needs none.  Without the batched kernels every round
+// but the last selects on its own.
+subkm_status subcluster_selections(subkm_ctx *ctx, const float *S, const float *P, int64_t n,
+                                   int32_t d, int64_t N, int32_t metric, int64_t *out) {
+    const int64_t T = ceil_div(n, N);
+    *out = T > 1 ? T - 1 : 0;
+    const bool v4 = (d % 4) == 0 && ((uintptr_t)S % 16) == 0;
+    const bool v4p = v4 && ((uintptr_t)P % 16) == 0;
+    if (T <= 1 || !scatterm_for(d, v4p) || !keys_b_for(metric, d, v4, 1)) return SUBKM_OK;
+    SubBufs b;
+    SUBKM_TRY(sub_alloc(ctx, n, d, N, b));
+    const uint32_t nb_max = (uint32_t)ceil_div(n, kBS);
+    // act[T - 1]: batches before the last round, which always has a slot of its own
+    const uint32_t *act =
+        (const uint32_t *)(b.sel + sel_round_bytes(nb_max) + align256(sizeof(BatchPlan)));
+    uint32_t a = 0;
+    SUBKM_HIP(ctx, hipMemcpyAsync(&a, act + (T - 1), sizeof a, hipMemcpyDeviceToHost, ctx->stream));
+    SUBKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *out = a;
+    return SUBKM_OK;
 }
 
 void subcluster_scratch_requests(int64_t n, int32_t d, int64_t N, size_t *req) {

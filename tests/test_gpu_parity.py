@@ -211,6 +211,29 @@ def test_subcluster_tied_minimum_holders(km, oracle, n, d, metric, mode):
     assert np.array_equal(host(P), S[permr])
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_subcluster_batched_rounds(km, oracle, mode):
+    # consecutive rounds that share a landmark are selected in one pass (at
+    # most 9 rounds, the last round on its own): with a fixed landmark every
+    # pass but the last takes 9; with the attribute-wise minimum, rounds
+    # join while some point holding each attribute's minimum surely stays.
+    # The subclusters stay those of the oracle, bit for bit.
+    job = synth.mid(n=1 << 17)
+    N = 1024
+    out = km.cluster(dev(job.X), N=N, k_local=8, k_final=4, max_iter=1, tol=0.0, landmark_mode=mode,
+                     intermediates=True, stats=True)
+    T = out["stats"]["T"]
+    S, _, _ = oracle.scale(job.X)
+    assert np.array_equal(host(out["S"]), S)
+    permr, _, _ = oracle.subcluster(S, N, fixed_landmark=bool(mode))
+    assert np.array_equal(host(out["perm"]), permr)
+    nsel = out["stats"]["sub_selections"]
+    if mode == 1:
+        assert nsel == -(-(T - 1) // 9)
+    else:
+        assert -(-(T - 1) // 9) <= nsel < T - 1
+
+
 # ----------------------------------------------------------------------------- Lloyd
 def shadow_steps(km, oracle, X, C0, steps, precision=0):
     """Run `steps` single GPU iterations, each checked against one oracle
