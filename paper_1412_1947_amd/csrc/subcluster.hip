@@ -1669,20 +1669,23 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
                     }
             }
             // the value alone decides every threshold (bins are monotone in
-            // the key); neighbouring candidates come from one compaction
-            // block and mostly share a class, so the wave adds them up by
-            // (class, block) first: one atomic per distinct pair
+            // the key).  In LDS every lane adds its own candidate (one
+            // instruction; lanes on one counter are serialised by the LDS
+            // unit, cheaper than a wave loop over the distinct counters);
+            // in global memory the wave adds up each (class, block) pair
+            // first: one atomic per distinct pair
             const bool cnt_it = in && !member;
             const uint32_t key = cls * nb + pp[u] / kBS;
+            if (lds_counts) {
+                if (cnt_it) atomicAdd(&csel[key], 1u);
+                continue;
+            }
             uint64_t rest = __ballot(cnt_it);
             while (rest) {
                 const int l0 = __ffsll((unsigned long long)rest) - 1;
                 const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, l0);
                 const uint64_t m = __ballot(cnt_it && key == k0);
-                if (lane == l0) {
-                    if (lds_counts) atomicAdd(&csel[k0], (uint32_t)__popcll(m));
-                    else atomicAdd(&B.blockcnt[(k0 / nb) * B.nbs + k0 % nb], (uint32_t)__popcll(m));
-                }
+                if (lane == l0) atomicAdd(&B.blockcnt[(k0 / nb) * B.nbs + k0 % nb], (uint32_t)__popcll(m));
                 rest &= ~m;
             }
         }
