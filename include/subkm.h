@@ -195,14 +195,21 @@ subkm_status subkm_subcluster_unequal(subkm_ctx *ctx, const float *S, int64_t n,
  * every run at the given offsets (runs must not overlap in C or labels).
  * iters (R int32) and sse (R double): device outputs.
  *
- * precision: SUBKM_PREC_FP32 computes distances in float32;
- *            SUBKM_PREC_BF16 computes them with bfloat16 matrix cores and
- *            float32 accumulation.  In both, every point whose two nearest
- *            centers are closer than the error bound of that arithmetic is
- *            re-assigned with binary64 distances, so the labels are those of
- *            exact arithmetic on the float32 inputs.  Center sums are exact
- *            (64-bit fixed point), so results do not depend on the order of
- *            the work.
+ * precision: the arithmetic of the first distance pass.
+ *            SUBKM_PREC_FP32: float32 products, except in runs whose
+ *            centers fit on chip with 8, 16 or 32 attributes, where each
+ *            product is the sum of the four products of split bfloat16
+ *            pairs (x = x_hi + x_lo, both operands), accumulated in float32
+ *            on the matrix cores (relative error about 2^-16);
+ *            SUBKM_PREC_BF16: additionally the split bfloat16 form for runs
+ *            of 32 to 128 attributes whose centers do not fit on chip
+ *            (three products per pair, the smallest dropped).  In both,
+ *            every point whose two nearest centers are closer than the
+ *            error bound of the arithmetic used is re-assigned (float32,
+ *            then binary64 distances), so the labels are those of exact
+ *            arithmetic on the float32 inputs and both settings give the
+ *            same results.  Center sums are exact (64-bit fixed point), so
+ *            results do not depend on the order of the work.
  * form:      SUBKM_FORM_BATCHED runs every run together (one launch per
  *            phase for all runs); SUBKM_FORM_PLAIN runs one run at a time
  *            with one launch per phase and run (the reference form).  Both
