@@ -189,14 +189,17 @@ def test_subcluster_many_points_per_thread(km, oracle, n, d, metric):
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("n,d,metric,mode", [(300_000, 16, 0, 0), (200_000, 8, 1, 0),
-                                             (250_000, 16, 0, 1)])
+                                             (250_000, 16, 0, 1), (150_000, 64, 0, 0),
+                                             (70_000, 128, 1, 0), (90_000, 100, 0, 0)])
 def test_subcluster_tied_minimum_holders(km, oracle, n, d, metric, mode):
     # values on a 1/8 grid (many keys tie), and below it, per attribute, five
     # levels held by two random points each: rounds where some holder of
     # the current minimum stays (the compaction reads only the selected
     # rows) alternate with rounds where the last ones leave and the landmark
     # moves (a third of the rounds here); with a fixed landmark no row that
-    # stays is read at all
+    # stays is read at all.  Rows of 64 to 128 attributes take the staged
+    # keys pass, which folds the rows above the previous round's bound into
+    # the next landmark (several tiles per block at these sizes)
     rng = np.random.default_rng(n + d + mode)
     X = (np.floor(rng.beta(2.0, 5.0, (n, d)) * 8.0) / 8.0).astype(np.float32)
     for j in range(d):
