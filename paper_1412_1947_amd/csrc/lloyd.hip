@@ -349,8 +349,8 @@ __device__ __forceinline__ void center_tile(const float (&xr)[4][D / 4], const u
             xb[g][q] = v;
             s2 = __builtin_fmaf(v, v, s2);
         }
-        s2 += __shfl_xor(s2, 16, 64);
-        s2 += __shfl_xor(s2, 32, 64);
+        s2 += lane_xor16(s2);
+        s2 += lane_xor32(s2);
         xn[g] = sqrtf(s2);
     }
 }
@@ -443,9 +443,9 @@ __device__ void stage1_mfma(LT &L, const float (&xb)[4][D / 4], const float (&xn
     for (int g = 0; g < 4; ++g) {
 #pragma unroll
         for (int o = 16; o <= 32; o <<= 1) {
-            const float ob1 = __shfl_xor(b1[g], o, 64);
-            const float ob2 = __shfl_xor(b2[g], o, 64);
-            const int32_t oi = __shfl_xor(i1[g], o, 64);
+            const float ob1 = o == 16 ? lane_xor16(b1[g]) : lane_xor32(b1[g]);
+            const float ob2 = o == 16 ? lane_xor16(b2[g]) : lane_xor32(b2[g]);
+            const int32_t oi = o == 16 ? lane_xor16(i1[g]) : lane_xor32(i1[g]);
             const float nb2 = fminf(fminf(b2[g], ob2), fmaxf(b1[g], ob1));
             const bool take = (ob1 < b1[g]) | ((ob1 == b1[g]) & (oi < i1[g]));  // no branch
             b1[g] = take ? ob1 : b1[g];
@@ -691,8 +691,8 @@ __device__ __forceinline__ void split_tile_bf(const float (&xr)[4][8], const flo
             al[g][e] = (__bf16)(a - (float)h);
         }
         // the lanes that hold the point's other attributes
-        if constexpr (D >= 16) s2 += __shfl_xor(s2, 16, 64);
-        if constexpr (D >= 32) s2 += __shfl_xor(s2, 32, 64);
+        if constexpr (D >= 16) s2 += lane_xor16(s2);
+        if constexpr (D >= 32) s2 += lane_xor32(s2);
         xn[g] = sqrtf(s2);
         constexpr int QA = D / 4;
         const int part = (8 * kg) / D;
@@ -807,9 +807,9 @@ __device__ void stage1_bf(LT &L, const bf16x8 (&ah)[4], const bf16x8 (&al)[4], c
     for (int g = 0; g < 4; ++g) {
 #pragma unroll
         for (int o = 16; o <= 32; o <<= 1) {
-            const float ob1 = __shfl_xor(b1[g], o, 64);
-            const float ob2 = __shfl_xor(b2[g], o, 64);
-            const int32_t oi = __shfl_xor(i1[g], o, 64);
+            const float ob1 = o == 16 ? lane_xor16(b1[g]) : lane_xor32(b1[g]);
+            const float ob2 = o == 16 ? lane_xor16(b2[g]) : lane_xor32(b2[g]);
+            const int32_t oi = o == 16 ? lane_xor16(i1[g]) : lane_xor32(i1[g]);
             const float nb2 = fminf(fminf(b2[g], ob2), fmaxf(b1[g], ob1));
             const bool take = (ob1 < b1[g]) | ((ob1 == b1[g]) & (oi < i1[g]));  // no branch
             b1[g] = take ? ob1 : b1[g];
@@ -877,8 +877,8 @@ __device__ void resolve_deferred(LT &L, const float *X, int k, int ldk, const ui
             xb[q] = xr[q] - mq[q];
             s2 = __builtin_fmaf(xb[q], xb[q], s2);
         }
-        s2 += __shfl_xor(s2, 16, 64);
-        s2 += __shfl_xor(s2, 32, 64);
+        s2 += lane_xor16(s2);
+        s2 += lane_xor32(s2);
         const float xn = sqrtf(s2);
         float b1 = INFINITY, b2 = INFINITY;
         int32_t i1 = 0;
@@ -906,9 +906,9 @@ __device__ void resolve_deferred(LT &L, const float *X, int k, int ldk, const ui
         }
 #pragma unroll
         for (int o = 16; o <= 32; o <<= 1) {
-            const float ob1 = __shfl_xor(b1, o, 64);
-            const float ob2 = __shfl_xor(b2, o, 64);
-            const int32_t oi = __shfl_xor(i1, o, 64);
+            const float ob1 = o == 16 ? lane_xor16(b1) : lane_xor32(b1);
+            const float ob2 = o == 16 ? lane_xor16(b2) : lane_xor32(b2);
+            const int32_t oi = o == 16 ? lane_xor16(i1) : lane_xor32(i1);
             const float nb2 = fminf(fminf(b2, ob2), fmaxf(b1, ob1));
             const bool take = (ob1 < b1) | ((ob1 == b1) & (oi < i1));
             b1 = take ? ob1 : b1;
@@ -1529,8 +1529,8 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
             xb[g][q] = v;
             s2 = __builtin_fmaf(v, v, s2);
         }
-        s2 += __shfl_xor(s2, 16, 64);
-        s2 += __shfl_xor(s2, 32, 64);
+        s2 += lane_xor16(s2);
+        s2 += lane_xor32(s2);
         xn[g] = sqrtf(s2);
     }
     float b1[4], b2[4];
@@ -1609,9 +1609,9 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
     for (int g = 0; g < 4; ++g) {
 #pragma unroll
         for (int o = 16; o <= 32; o <<= 1) {
-            const float ob1 = __shfl_xor(b1[g], o, 64);
-            const float ob2 = __shfl_xor(b2[g], o, 64);
-            const int32_t oi = __shfl_xor(i1[g], o, 64);
+            const float ob1 = o == 16 ? lane_xor16(b1[g]) : lane_xor32(b1[g]);
+            const float ob2 = o == 16 ? lane_xor16(b2[g]) : lane_xor32(b2[g]);
+            const int32_t oi = o == 16 ? lane_xor16(i1[g]) : lane_xor32(i1[g]);
             const float nb2 = fminf(fminf(b2[g], ob2), fmaxf(b1[g], ob1));
             const bool take = (ob1 < b1[g]) | ((ob1 == b1[g]) & (oi < i1[g]));  // no branch
             b1[g] = take ? ob1 : b1[g];

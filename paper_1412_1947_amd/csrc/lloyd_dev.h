@@ -60,6 +60,24 @@ struct Task {
     int32_t g;  // part g of the run's G blocks
 };
 
+// The value of lane l ^ 16 (lane_xor16) or l ^ 32 (lane_xor32) of the
+// wavefront, from the gfx950 row swaps: permlane16_swap(x, x) returns
+// (rows 0, 0, 2, 2) and (rows 1, 1, 3, 3) of x, permlane32_swap(x, x) the
+// lower and the upper half twice; each lane takes the copy of its partner.
+// No LDS round trip, unlike a general shuffle.  Every lane must be active.
+__device__ __forceinline__ uint32_t lane_xor16(uint32_t x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return ((threadIdx.x >> 4) & 1u) ? r[0] : r[1];
+}
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return ((threadIdx.x >> 5) & 1u) ? r[0] : r[1];
+}
+__device__ __forceinline__ float lane_xor16(float x) { return __uint_as_float(lane_xor16(__float_as_uint(x))); }
+__device__ __forceinline__ float lane_xor32(float x) { return __uint_as_float(lane_xor32(__float_as_uint(x))); }
+__device__ __forceinline__ int32_t lane_xor16(int32_t x) { return (int32_t)lane_xor16((uint32_t)x); }
+__device__ __forceinline__ int32_t lane_xor32(int32_t x) { return (int32_t)lane_xor32((uint32_t)x); }
+
 // Exact binary64 distance of a float32 point to a float32 center, attributes
 // left to right, separate multiply and add: the arithmetic of the objective.
 __device__ __forceinline__ double dist64(const float *x, const float *c, int d) {
