@@ -63,6 +63,7 @@ struct SelState {
     uint32_t ncand;     // length of the flat candidate list
     uint32_t vshift;    // low float bits the v-map drops this round
     uint32_t lchange;   // 0: no point holding an attribute minimum can be removed
+    uint32_t sel_done;  // batched rounds: the threshold step of this pass is published
     double thr_key;
 };
 
@@ -608,16 +609,17 @@ __global__ __launch_bounds__(kT) void k_cand(const double *__restrict__ keys, ui
 // Exact selection of the need2-th smallest (key, pos) among the candidates
 // whose v equals vstar, when there are too many to rank in LDS: a
 // most-significant-digit radix select over the 96-bit pair, 8 bits a pass.
+template <int NT>
 __device__ void slow_select(const double *ckey, const uint32_t *cpos, uint32_t ncand,
                             uint32_t vstar, uint32_t base, uint32_t vsh, uint32_t need,
                             uint32_t *hist256, uint32_t *sh, double *thr_key, uint32_t *thr_pos) {
     uint64_t kpre = 0;
     uint32_t ppre = 0;
     for (int pass = 0; pass < 12; ++pass) {
-        for (int i = threadIdx.x; i < 256; i += kST) hist256[i] = 0;
+        for (int i = threadIdx.x; i < 256; i += NT) hist256[i] = 0;
         __syncthreads();
         {
-            for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
+            for (uint32_t c = threadIdx.x; c < ncand; c += NT) {
                 const double k = ckey[c];
                 if (vmap(k, base, vsh) != vstar) continue;
                 const uint64_t kb = (uint64_t)__double_as_longlong(k);
@@ -736,7 +738,7 @@ __global__ __launch_bounds__(kST) void k_sel2(uint32_t need, SelState *st,
         for (uint32_t i = threadIdx.x; i < cnt2; i += kST)
             if (pair_le(rk[i], rp[i], thr_key, thr_pos)) count_sel(rp[i]);
     } else {
-        slow_select(ckey, cpos, ncand, vstar, base, vsh, need2, h256, sh, &thr_key, &thr_pos);
+        slow_select<kST>(ckey, cpos, ncand, vstar, base, vsh, need2, h256, sh, &thr_key, &thr_pos);
         if (threadIdx.x == 0) st->fallback += 1;
         for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
             const double k = ckey[c];
@@ -1157,7 +1159,8 @@ __global__ void k_offsets(int64_t *off, int64_t T, int64_t N, int64_t n) {
 // left to do.  With a fixed landmark every batch takes the largest q.
 //
 // The launch sequence stays static (it is captured once into a HIP graph):
-// every round t keeps its four launches, and act[t] says whether round t
+// every round t keeps its three launches (keys pass, candidate pass, and the
+// compaction whose block 0 first runs the threshold step), and act[t] says whether round t
 // starts a batch (the number of batches before it, which also selects the
 // ping-pong buffers) or lies inside an earlier one (kNoRound: every block
 // returns at once).  A batch at round t writes act[t + q]; nothing else
@@ -1165,7 +1168,7 @@ __global__ void k_offsets(int64_t *off, int64_t T, int64_t N, int64_t n) {
 // the same launch writes.
 constexpr int kQMax = 9;                   // subclusters one batch emits at most
 constexpr uint32_t kNoRound = 0xFFFFFFFFu;  // act[t]: round t lies inside a batch
-constexpr uint32_t kCselCap = 8192;        // (class, block) counts k_sel2m keeps in LDS
+constexpr uint32_t kCselCap = 8192;        // (class, block) counts the threshold step keeps in LDS
 
 struct BatchPlan {
     uint32_t q;                 // subclusters of the active batch
@@ -1200,6 +1203,7 @@ struct RoundBufs {
     uint32_t *cpos;
     uint32_t nbs;                // stride of the per-class block arrays
     int32_t d;
+    int *err;                    // sticky device flag: a bounded wait gave up
 };
 
 // The keys pass of a batch (k_keys_fast with the buffers of batch act[t]).
@@ -1464,7 +1468,10 @@ __global__ __launch_bounds__(kT) void k_candm(RoundBufs B, uint32_t t, uint32_t 
         B.bp->bin[threadIdx.x] = Lp.tbin[threadIdx.x];
         B.bp->below[threadIdx.x] = Lp.tbelow[threadIdx.x];
         B.bp->cnt[threadIdx.x] = Lp.tcnt[threadIdx.x];
-        if (threadIdx.x == 0) B.bp->q = q;
+        if (threadIdx.x == 0) {
+            B.bp->q = q;
+            B.st->sel_done = 0;  // the compaction launch publishes this pass's thresholds
+        }
     }
     // the targets' level-1 bins in registers (padding above every bin)
     uint32_t tb[kQMax];
@@ -1519,7 +1526,8 @@ __global__ __launch_bounds__(kT) void k_candm(RoundBufs B, uint32_t t, uint32_t 
     }
 }
 
-// Thresholds of a batch (one block).  (1) For every distinct boundary bin,
+// Thresholds of a batch (one block: block 0 of the batch's compaction launch,
+// the other blocks of which wait for it).  (1) For every distinct boundary bin,
 // one wave scans its level-2 histogram (and clears it) and gives every target
 // in it the level-2 bin of its rank.  (2) One pass over the candidate list:
 // a candidate whose level-2 value differs from every target's is below or
@@ -1533,26 +1541,36 @@ __global__ __launch_bounds__(kT) void k_candm(RoundBufs B, uint32_t t, uint32_t 
 // (4) Per class, one wave turns the block counts into offsets.  Then:
 // whether the landmark may move after the batch, the round of the next
 // batch, the landmarks of the rounds inside this one.
-__global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t N, uint32_t nb,
-                                               int fixed) {
-    const uint32_t a = B.act[t];
-    if (a == kNoRound) return;
-    __shared__ uint32_t sh[4], s_lch, s_anyslow;
-    __shared__ double rk[kRankCap];
-    __shared__ uint32_t rp[kRankCap];
-    __shared__ uint32_t h256[256];
-    __shared__ uint32_t csel[kCselCap];
-    __shared__ double s_tk[kQMax];
-    __shared__ uint32_t s_tp[kQMax], s_bin[kQMax], s_below[kQMax];
-    __shared__ uint32_t s_vstar[kQMax], s_need2[kQMax], s_cnt2[kQMax], s_seg[kQMax], s_fill[kQMax];
-    __shared__ uint32_t s_fast[kQMax];
+struct Sel2Lds {
+    uint32_t sh[4], s_lch, s_anyslow;
+    double rk[kRankCap];
+    uint32_t rp[kRankCap];
+    uint32_t h256[256];
+    uint32_t csel[kCselCap];
+    double s_tk[kQMax];
+    uint32_t s_tp[kQMax], s_bin[kQMax], s_below[kQMax];
+    uint32_t s_vstar[kQMax], s_need2[kQMax], s_cnt2[kQMax], s_seg[kQMax], s_fill[kQMax];
+    uint32_t s_fast[kQMax];
+};
+
+template <int NT>
+__device__ void sel2m_body(const RoundBufs &B, uint32_t t, uint32_t N, uint32_t nb, int fixed,
+                           uint32_t a, Sel2Lds &S2) {
+    uint32_t *sh = S2.sh;
+    uint32_t &s_lch = S2.s_lch, &s_anyslow = S2.s_anyslow;
+    double *rk = S2.rk;
+    uint32_t *rp = S2.rp, *h256 = S2.h256, *csel = S2.csel;
+    double *s_tk = S2.s_tk;
+    uint32_t *s_tp = S2.s_tp, *s_bin = S2.s_bin, *s_below = S2.s_below, *s_vstar = S2.s_vstar;
+    uint32_t *s_need2 = S2.s_need2, *s_cnt2 = S2.s_cnt2, *s_seg = S2.s_seg, *s_fill = S2.s_fill;
+    uint32_t *s_fast = S2.s_fast;
     const BatchPlan *bp = B.bp;
     const uint32_t q = bp->q;
     const uint32_t base = B.st->base, vsh = B.st->vshift;
     const uint32_t ncand = B.st->ncand;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool lds_counts = (q + 1) * nb <= kCselCap;
-    for (uint32_t i = threadIdx.x; i < kCselCap; i += kST) csel[i] = 0;
+    for (uint32_t i = threadIdx.x; i < kCselCap; i += NT) csel[i] = 0;
     if (threadIdx.x < q) {
         s_bin[threadIdx.x] = bp->bin[threadIdx.x];
         s_below[threadIdx.x] = bp->below[threadIdx.x];
@@ -1571,7 +1589,7 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
     };
     // (1) level-2 bins: one wave per distinct boundary bin (slot = its first
     // target); lane l holds bins 64 l .. 64 l + 63
-    for (uint32_t i0 = wv; i0 < q; i0 += kST / 64) {
+    for (uint32_t i0 = wv; i0 < q; i0 += NT / 64) {
         if (i0 > 0 && s_bin[i0] == s_bin[i0 - 1]) continue;  // the same histogram
         uint32_t *hist = B.hist2 + i0 * kBins + lane * 64;
         constexpr int kC = 16;  // bins loaded at a time
@@ -1632,12 +1650,12 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
     uint32_t vst[kQMax];
 #pragma unroll
     for (int i = 0; i < kQMax; ++i) vst[i] = (uint32_t)i < q ? s_vstar[i] : 0xFFFFFFFFu;
-    for (uint32_t c0 = 0; c0 < ncand; c0 += kST * kBatch) {
+    for (uint32_t c0 = 0; c0 < ncand; c0 += NT * kBatch) {
         double kk[kBatch];
         uint32_t pp[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const uint32_t c = c0 + u * kST + threadIdx.x;
+            const uint32_t c = c0 + u * NT + threadIdx.x;
             // clamped, unconditional: the loads go out together
             const uint32_t cc = min(c, ncand - 1);
             kk[u] = B.ckey[cc];
@@ -1645,7 +1663,7 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const uint32_t c = c0 + u * kST + threadIdx.x;
+            const uint32_t c = c0 + u * NT + threadIdx.x;
             const bool in = c < ncand;
             const uint32_t v = vmap(kk[u], base, vsh);
             // class: one past the last target whose level-2 value lies below
@@ -1694,7 +1712,7 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
     // (3) exact ranks inside every segment (threads over all (target, member) pairs)
     uint32_t tot = 0;
     for (uint32_t i = 0; i < q; ++i) tot += s_fast[i] ? s_cnt2[i] : 0u;
-    for (uint32_t x = threadIdx.x; x < tot; x += kST) {
+    for (uint32_t x = threadIdx.x; x < tot; x += NT) {
         uint32_t i = 0;
         while (!(s_fast[i] && x >= s_seg[i] && x < s_seg[i] + s_cnt2[i])) ++i;
         const double kx = rk[x];
@@ -1712,7 +1730,7 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
         if (s_fast[i]) continue;
         double thr_key;
         uint32_t thr_pos;
-        slow_select(B.ckey, B.cpos, ncand, s_vstar[i], base, vsh, s_need2[i], h256, sh, &thr_key, &thr_pos);
+        slow_select<NT>(B.ckey, B.cpos, ncand, s_vstar[i], base, vsh, s_need2[i], h256, sh, &thr_key, &thr_pos);
         if (threadIdx.x == 0) {
             s_tk[i] = thr_key;
             s_tp[i] = thr_pos;
@@ -1728,7 +1746,7 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
     if (!s_anyslow) {
         // members of the fast segments, each counted once (by the first
         // target of its level-2 bin)
-        for (uint32_t x = threadIdx.x; x < tot; x += kST) {
+        for (uint32_t x = threadIdx.x; x < tot; x += NT) {
             uint32_t i = 0;
             while (!(s_fast[i] && x >= s_seg[i] && x < s_seg[i] + s_cnt2[i])) ++i;
             if (i == 0 || s_vstar[i - 1] != s_vstar[i]) count_cls(exact_cls(rk[x], rp[x]), rp[x]);
@@ -1736,7 +1754,7 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
     } else {
         // some level-2 bin was too large for LDS: its members (and all
         // others sharing a target's bin) are classified by one more pass
-        for (uint32_t c = threadIdx.x; c < ncand; c += kST) {
+        for (uint32_t c = threadIdx.x; c < ncand; c += NT) {
             const double k = B.ckey[c];
             const uint32_t p = B.cpos[c];
             const uint32_t v = vmap(k, base, vsh);
@@ -1756,7 +1774,7 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
         s_lch = 1u;
     // (4) per class, one wave scans the block counts, 8 chunks of 64 loaded
     // at a time (clamped, unconditional loads)
-    for (uint32_t cls = wv; cls <= q; cls += kST / 64) {
+    for (uint32_t cls = wv; cls <= q; cls += NT / 64) {
         uint32_t carry = 0;
         for (uint32_t c0 = 0; c0 < nb; c0 += 64 * 8) {
             uint32_t v[8];
@@ -1771,24 +1789,30 @@ __global__ __launch_bounds__(kST) void k_sel2m(RoundBufs B, uint32_t t, uint32_t
                 if (lds_counts) v[x] += csel[cls * nb + min(sg, nb - 1)];
                 if (sg >= nb) v[x] = 0;
                 const uint32_t inc = wave_incl_scan(v[x]);
-                if (sg < nb) B.blockoff[cls * B.nbs + sg] = carry + inc - v[x];
+                // read by the compaction blocks of this launch: stored at the
+                // device's coherence point
+                if (sg < nb)
+                    __hip_atomic_store(&B.blockoff[cls * B.nbs + sg], carry + inc - v[x], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
             }
         }
     }
     __syncthreads();
     if (threadIdx.x < q) {
-        B.bp->thr_key[threadIdx.x] = s_tk[threadIdx.x];
-        B.bp->thr_pos[threadIdx.x] = s_tp[threadIdx.x];
+        __hip_atomic_store(&B.bp->thr_key[threadIdx.x], s_tk[threadIdx.x], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&B.bp->thr_pos[threadIdx.x], s_tp[threadIdx.x], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
     if (threadIdx.x == 0) {
-        B.bp->lchange = s_lch;
+        __hip_atomic_store(&B.bp->lchange, s_lch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         B.st->thr_key = s_tk[q - 1];  // centre of the next batch's key map
         B.act[t + q] = a + 1;
     }
     // the rounds inside the batch share its landmark
     if (B.landmarks)
-        for (uint32_t x = threadIdx.x; x < (q - 1) * (uint32_t)B.d; x += kST)
+        for (uint32_t x = threadIdx.x; x < (q - 1) * (uint32_t)B.d; x += NT)
             B.landmarks[((int64_t)t + 1) * B.d + x] = B.landmarks[(int64_t)t * B.d + x % B.d];
 }
 
@@ -1980,16 +2004,49 @@ __global__ __launch_bounds__(kT, W * DQ <= 16 ? 4 : 1) void k_scatterm(
     static_assert(D <= 32, "row width of the early-load forms");
     const uint32_t a = B.act[t];
     if (a == kNoRound) return;
-    __shared__ ScatterLds sm;
+    __shared__ union {
+        ScatterLds sc;
+        Sel2Lds s2;
+    } U;
+    ScatterLds &sm = U.sc;
+    if (!all_sel) {
+        // The threshold step of the pass runs in block 0 of this launch (one
+        // launch per pass fewer); the other blocks wait for its flag.  What
+        // they read of it (thresholds, landmark flag, block offsets) is
+        // stored and loaded at the device's coherence point; block 0 was
+        // dispatched first, so the wait always ends (bounded all the same).
+        if (blockIdx.x == 0) {
+            sel2m_body<kT>(B, t, N, gridDim.x, fixed, a, U.s2);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_store(&B.st->sel_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (threadIdx.x == 0) {
+            long long spins = 0;
+            while (__hip_atomic_load(&B.st->sel_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1ll << 24)) {
+                    atomicOr(B.err, 1);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+    }
     const uint32_t qn = all_sel ? 1u : B.bp->q;
-    const uint32_t lch = all_sel ? 1u : B.bp->lchange;
+    const uint32_t lch =
+        all_sel ? 1u : __hip_atomic_load(&B.bp->lchange, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!all_sel && threadIdx.x < qn) {
-        sm.tk[threadIdx.x] = B.bp->thr_key[threadIdx.x];
-        sm.tp[threadIdx.x] = B.bp->thr_pos[threadIdx.x];
+        sm.tk[threadIdx.x] = __hip_atomic_load(&B.bp->thr_key[threadIdx.x], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        sm.tp[threadIdx.x] = __hip_atomic_load(&B.bp->thr_pos[threadIdx.x], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
     }
     if (threadIdx.x <= qn)
-        sm.off[threadIdx.x] = all_sel ? (threadIdx.x == 0 ? blockIdx.x * kBS : 0u)
-                                      : B.blockoff[threadIdx.x * B.nbs + blockIdx.x];
+        sm.off[threadIdx.x] =
+            all_sel ? (threadIdx.x == 0 ? blockIdx.x * kBS : 0u)
+                    : __hip_atomic_load(&B.blockoff[threadIdx.x * B.nbs + blockIdx.x], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     // rows that stay are read only when the next landmark may move
     const bool full = !(lm_skip && !all_sel && (!track_min || lch == 0));
@@ -2142,6 +2199,7 @@ subkm_status sub_enqueue_batched(subkm_ctx *ctx, const SubBufs &b, const float *
     B.cpos = (uint32_t *)(b.cand + sizeof(double) * n);
     B.nbs = nb_max;
     B.d = d;
+    B.err = ctx->sticky;
     {
         const uint32_t nz1 = (uint32_t)(2 * kRep * kBins);
         hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(nz1, 256)), dim3(256), 0, s, hist1, nz1, 0u);
@@ -2180,9 +2238,7 @@ subkm_status sub_enqueue_batched(subkm_ctx *ctx, const SubBufs &b, const float *
                                    nrem, (uint32_t)N);
                 SUBKM_LAUNCHED(ctx);
             }
-            hipLaunchKernelGGL(k_sel2m, dim3(1), dim3(kST), 0, s, B, (uint32_t)t, (uint32_t)N, nb,
-                               fixed ? 1 : 0);
-            SUBKM_LAUNCHED(ctx);
+
         } else if (landmarks) {
             hipLaunchKernelGGL(k_land_last, dim3(ceil_div(d, 256)), dim3(256), 0, s, B, (uint32_t)t,
                                fixed ? 1 : 0);
