@@ -246,9 +246,12 @@ subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run
 /* Schedule tuner of the batched form (Sec. V runs the subclusters in
  * parallel; how the runs of a call share the device is this library's
  * choice).  The schedule is the persistent kernel's grid, the largest
- * number of blocks that split one run (up to 128), and the fewest 256-point
+ * number of blocks that split one run (up to 128), the fewest 256-point
  * tiles such a block takes per move (1 or 2: more blocks per run shorten a
- * move's tiles, fewer shorten its barriers); it changes no result (sums are
+ * move's tiles, fewer shorten its barriers), and how such blocks combine
+ * their sums every move (each publishes its part and sums a slice of all
+ * parts, two barriers; or each adds its part into shared totals with
+ * integer atomics, one barrier); it changes no result (sums are
  * exact integers, labels exact), only the time.  With tuning on, the first
  * batched call with moves of a new shape (number of runs, points, smallest
  * and largest d and k, precision) runs itself under each candidate schedule
@@ -260,7 +263,8 @@ subkm_status subkm_lloyd_batched(subkm_ctx *ctx, const float *P, const subkm_run
  *   subkm_tune_count: number of tuned shapes.
  *   subkm_tune_save / _load: the tuned schedules as a text file (load adds
  *   to the context's schedules; SUBKM_EINVAL on a malformed file; files of
- *   the first format, without the tiles field, load with 2 tiles).       */
+ *   the earlier formats load: without the exchange field with published
+ *   parts, without the tiles field also with 2 tiles).                  */
 subkm_status subkm_tune_enable(subkm_ctx *ctx, int32_t on);
 subkm_status subkm_tune_count(subkm_ctx *ctx, int32_t *entries);
 subkm_status subkm_tune_save(subkm_ctx *ctx, const char *path);

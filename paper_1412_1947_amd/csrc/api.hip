@@ -282,8 +282,9 @@ subkm_status subkm_tune_count(subkm_ctx *ctx, int32_t *entries) {
     return SUBKM_OK;
 }
 
-static const char kTuneMagic[] = "subkm-tune 2";
-static const char kTuneMagic1[] = "subkm-tune 1";  // no tiles-per-block field (2 then)
+static const char kTuneMagic[] = "subkm-tune 3";
+static const char kTuneMagic2[] = "subkm-tune 2";  // no exchange field (0 then)
+static const char kTuneMagic1[] = "subkm-tune 1";  // nor a tiles-per-block field (2 then)
 
 subkm_status subkm_tune_save(subkm_ctx *ctx, const char *path) {
     CHECK_CTX(ctx);
@@ -293,8 +294,8 @@ subkm_status subkm_tune_save(subkm_ctx *ctx, const char *path) {
     std::fprintf(f, "%s\n", kTuneMagic);
     for (const auto &e : ctx->tune) {
         for (int i = 0; i < 5; ++i) std::fprintf(f, "%llx ", (unsigned long long)e.first.v[i]);
-        std::fprintf(f, "%d %d %d %.6f\n", e.second.sched.gcap, e.second.sched.bdiv, e.second.sched.tpb,
-                     e.second.ms);
+        std::fprintf(f, "%d %d %d %d %.6f\n", e.second.sched.gcap, e.second.sched.bdiv, e.second.sched.tpb,
+                     e.second.sched.xmode, e.second.ms);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? SUBKM_OK : set_err(ctx, SUBKM_EINVAL, "cannot write %s", path);
@@ -307,29 +308,63 @@ subkm_status subkm_tune_load(subkm_ctx *ctx, const char *path) {
     if (!f) return set_err(ctx, SUBKM_EINVAL, "cannot open %s", path);
     char head[64] = {};
     const bool read = std::fgets(head, sizeof head, f) != nullptr;
-    const bool v2 = read && std::strncmp(head, kTuneMagic, sizeof kTuneMagic - 1) == 0;
+    const bool v3 = read && std::strncmp(head, kTuneMagic, sizeof kTuneMagic - 1) == 0;
+    const bool v2 = read && std::strncmp(head, kTuneMagic2, sizeof kTuneMagic2 - 1) == 0;
     const bool v1 = read && std::strncmp(head, kTuneMagic1, sizeof kTuneMagic1 - 1) == 0;
-    if (!v1 && !v2) {
+    if (!v1 && !v2 && !v3) {
         std::fclose(f);
         return set_err(ctx, SUBKM_EINVAL, "%s is not a schedule file", path);
     }
+    // one entry per line: five hex key words, the integer fields of the
+    // format (block cap, grid divisor[, tiles per block[, exchange]]) and the
+    // time; every token must parse whole
     std::map<TuneKey, TuneEntry> got;
-    for (;;) {
-        unsigned long long v[5];
-        int gcap = 0, bdiv = 0, tpb = 2;
-        double ms = 0.0;
-        const int nf = v2 ? std::fscanf(f, "%llx %llx %llx %llx %llx %d %d %d %lf", &v[0], &v[1], &v[2],
-                                        &v[3], &v[4], &gcap, &bdiv, &tpb, &ms)
-                          : std::fscanf(f, "%llx %llx %llx %llx %llx %d %d %lf", &v[0], &v[1], &v[2],
-                                        &v[3], &v[4], &gcap, &bdiv, &ms);
-        if (nf == EOF) break;
-        if (nf != (v2 ? 9 : 8) || gcap < 1 || bdiv < 1 || bdiv > 64 || tpb < 1 || tpb > 64) {
-            std::fclose(f);
-            return set_err(ctx, SUBKM_EINVAL, "%s: malformed entry", path);
+    const int nint = v3 ? 4 : v2 ? 3 : 2;
+    char line[512];
+    bool bad = false;
+    while (!bad && std::fgets(line, sizeof line, f)) {
+        char *tok[16];
+        int nt = 0;
+        char *save = nullptr;
+        for (char *t = strtok_r(line, " \t\r\n", &save); t; t = strtok_r(nullptr, " \t\r\n", &save)) {
+            if (nt == 16) {
+                bad = true;
+                break;
+            }
+            tok[nt++] = t;
+        }
+        if (bad || nt == 0) continue;  // blank lines are allowed
+        if (nt != 5 + nint + 1) {
+            bad = true;
+            continue;
         }
         TuneKey k;
-        for (int i = 0; i < 5; ++i) k.v[i] = v[i];
-        got[k] = TuneEntry{LloydSched{gcap, bdiv, tpb}, ms};
+        char *end = nullptr;
+        for (int i = 0; i < 5 && !bad; ++i) {
+            k.v[i] = std::strtoull(tok[i], &end, 16);
+            bad = *end != '\0';
+        }
+        long iv[4] = {0, 0, 2, 0};
+        for (int i = 0; i < nint && !bad; ++i) {
+            iv[i] = std::strtol(tok[5 + i], &end, 10);
+            bad = *end != '\0';
+        }
+        double ms = 0.0;
+        if (!bad) {
+            ms = std::strtod(tok[5 + nint], &end);
+            bad = *end != '\0';
+        }
+        const long gcap = iv[0], bdiv = iv[1], tpb = iv[2], xmode = iv[3];
+        if (bad || gcap < 1 || gcap > 1024 || bdiv < 1 || bdiv > 64 || tpb < 1 || tpb > 64 || xmode < 0 ||
+            xmode > 1) {
+            bad = true;
+            continue;
+        }
+        got[k] = TuneEntry{LloydSched{(int32_t)gcap, (int32_t)bdiv, (int32_t)tpb, (int32_t)xmode}, ms};
+    }
+    if (bad) {
+        std::fclose(f);
+        return set_err(ctx, SUBKM_EINVAL, "%s: malformed entry", path);
     }
     std::fclose(f);
     for (const auto &e : got) ctx->tune[e.first] = e.second;

@@ -75,12 +75,16 @@ struct CoopGate {
 };
 
 // Schedule of the batched Lloyd form (results do not depend on it): the
-// largest number of blocks per run, the divisor of the co-resident grid, and
-// the fewest 256-point tiles a block of a split run takes per move.
+// largest number of blocks per run, the divisor of the co-resident grid,
+// the fewest 256-point tiles a block of a split run takes per move, and how
+// the blocks of a run combine their sums every move (0: every block
+// publishes its part, then each sums a slice of the parts, two arrivals;
+// 1: every block adds its part into shared totals, one arrival).
 struct LloydSched {
     int32_t gcap;
     int32_t bdiv;
     int32_t tpb;
+    int32_t xmode;
 };
 struct TuneKey {
     uint64_t v[5];

@@ -50,6 +50,7 @@ constexpr int kMaxK = 1024;         // centers per run in the fused path
 constexpr int kLdsFloats = 8192;    // centers staged per pass (scan-update path)
 constexpr long long kSpinLimit = 1ll << 26;
 constexpr int kMaxG = 128;         // blocks per run in the batched form
+constexpr int64_t kXAtomMax = 1 << 18;  // shared-totals exchange: most atomics per move
 constexpr int kExB = 16;           // exchange loads in flight per thread
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
@@ -1195,7 +1196,66 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > kAT ? 4
                 break;
             }
             __syncthreads();
-            if (G > 1) {
+            if (G > 1 && R.xatom) {
+                // Shared totals: every block adds its sums into the move's
+                // totals with agent-scope integer atomics (performed at the
+                // device's coherence point; exact, so any order gives the same
+                // bits), waits for them to complete, arrives once, and reads
+                // the totals back with agent-scope loads.  Totals rotate over
+                // three buffers by move: during move it each block also clears
+                // its slice of the buffer of move it + 1, last read as the
+                // totals of move it - 2 by blocks that have all since arrived
+                // at move it - 1 (this block passed that arrival), and written
+                // again only after this move's arrival, which follows the
+                // clearing.  The buffer of move 0 is cleared before the launch.
+                const int ne = kd + k;
+                long long *tb = parts + R.part_off;
+                long long *acc = tb + (int64_t)(it % 3) * ne;
+                long long *nxt = tb + (int64_t)((it + 1) % 3) * ne;
+                for (int e = threadIdx.x; e < kd; e += NT) {
+                    const long long v = L.s_sum[e];
+                    if (v != 0) __hip_atomic_fetch_add(&acc[e], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                for (int c = threadIdx.x; c < k; c += NT) {
+                    const long long v = (long long)L.s_cnt[c];
+                    if (v != 0) __hip_atomic_fetch_add(&acc[kd + c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                {
+                    const int S = (ne + G - 1) / G;
+                    const int e0 = min(ne, tk.g * S), e1 = min(ne, e0 + S);
+                    for (int e = e0 + (int)threadIdx.x; e < e1; e += NT)
+                        __hip_atomic_exchange(&nxt[e], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    const uint32_t target = (uint32_t)G * (uint32_t)(it + 1);
+                    __hip_atomic_fetch_add(&rs->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    long long spins = 0;
+                    while (__hip_atomic_load(&rs->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++spins > kSpinLimit) {
+                            atomicOr(err, 1);
+                            break;
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int e0 = 0; e0 < ne; e0 += NT * kExB) {
+                    long long v[kExB];
+#pragma unroll
+                    for (int u = 0; u < kExB; ++u)
+                        v[u] = __hip_atomic_load(&acc[min(e0 + u * NT + (int)threadIdx.x, ne - 1)],
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                    for (int u = 0; u < kExB; ++u) {
+                        const int e = e0 + u * NT + (int)threadIdx.x;
+                        if (e < kd) L.s_sum[e] = v[u];
+                        else if (e < ne) L.s_cnt[e - kd] = (unsigned int)v[u];
+                    }
+                }
+                __syncthreads();
+            } else if (G > 1) {
                 // Publish this block's sums, wait for the run's other blocks,
                 // then sum the parts (exact integer sums: any order gives the
                 // same bits), reduce-scattered as below.  The parts and
@@ -1662,10 +1722,13 @@ __global__ void k_state_init(RunState *rstate, int R) {
 
 // Attribute-wise minimum and maximum of every run as ordered bits (box[j],
 // box[d + j]) and the largest |x| of the run (grid: chunks x runs).
-__global__ void k_box_init(const DevRun *__restrict__ runs, uint32_t *boxes) {
+__global__ void k_box_init(const DevRun *__restrict__ runs, uint32_t *boxes, long long *parts) {
     const DevRun R = runs[blockIdx.x];
     for (int j = threadIdx.x; j < 2 * R.d; j += blockDim.x)
         boxes[R.box_off + j] = j < R.d ? 0xFFFFFFFFu : 0u;
+    // batched form with shared totals: the totals of the first move start at zero
+    if (R.xatom)
+        for (int64_t j = threadIdx.x; j < (int64_t)R.k * R.d + R.k; j += blockDim.x) parts[R.part_off + j] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_runbox(const float *__restrict__ P,
@@ -2172,14 +2235,25 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
             std::vector<int32_t> G(R, 1);
             std::vector<std::vector<Task>> pb;
             schedule(rr, dr, blocks, max_iter > 0, sc.gcap, sc.tpb, step, G, pb);
+            // shared totals only while the atomics of one move stay few (a
+            // single split run: the final run of the mid workload adds 139k
+            // words per move and saves a barrier and the slice sums); with
+            // millions per move (the 128 local runs: 2.2M) they gained nothing
+            // measurable over the published parts, which such calls keep
+            int64_t xvol = 0;
+            for (int r : rr)
+                if (G[r] > 1) xvol += (int64_t)G[r] * ((int64_t)dr[r].k * dr[r].d + dr[r].k);
+            const bool xat = sc.xmode == 1 && max_iter > 0 && xvol <= kXAtomMax;
             for (int r : rr) {
                 DevRun &D = dr[r];
                 D.G = G[r];
                 D.nitems = (int32_t)((D.n + kAT - 1) / kAT);
                 D.part_off = part_words;
-                // exchange slots only when there is an update to exchange
+                // exchange slots only when there is an update to exchange:
+                // published parts and slice sums, or three rotating totals
+                D.xatom = (G[r] > 1 && xat) ? 1 : 0;
                 if (G[r] > 1 && max_iter > 0)
-                    part_words += (2ll * G[r] + 2) * ((int64_t)D.k * D.d + D.k);  // parts, sums
+                    part_words += (D.xatom ? 3ll : 2ll * G[r] + 2) * ((int64_t)D.k * D.d + D.k);
             }
             for (int b = 0; b < blocks; ++b) {
                 for (const Task &t : pb[b]) tasks.push_back(t);
@@ -2253,7 +2327,7 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
             nmax = std::max<int64_t>(nmax, dr[r].n);
             dmax = std::max(dmax, dr[r].d);
         }
-        hipLaunchKernelGGL(k_box_init, dim3(R), dim3(256), 0, s, d_runs, d_box);
+        hipLaunchKernelGGL(k_box_init, dim3(R), dim3(256), 0, s, d_runs, d_box, d_sum + sum_words);
         SUBKM_LAUNCHED(ctx);
         hipLaunchKernelGGL(k_runbox, dim3(std::min<int64_t>(ceil_div(nmax, 2048), 1024), R), dim3(256),
                            2 * sizeof(uint32_t) * dmax, s, P, d_runs, d_box, d_rs);
@@ -2362,9 +2436,10 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
 namespace {
 // (a few blocks per run suit calls of one or few runs, whose time is the
 // per-move exchange among their blocks)
-const LloydSched kCandidates[] = {{64, 1, 2}, {32, 1, 2}, {16, 1, 2}, {64, 2, 2},
-                                  {32, 2, 2}, {16, 2, 2}, {128, 1, 1}, {64, 1, 1},
-                                  {8, 1, 2},  {4, 1, 2}};
+const LloydSched kCandidates[] = {{64, 1, 2, 0}, {32, 1, 2, 0},  {16, 1, 2, 0}, {64, 2, 2, 0},
+                                  {32, 2, 2, 0}, {16, 2, 2, 0},  {128, 1, 1, 0}, {64, 1, 1, 0},
+                                  {8, 1, 2, 0},  {4, 1, 2, 0},   {128, 1, 1, 1}, {64, 1, 2, 1},
+                                  {32, 1, 2, 1}, {16, 1, 2, 1}};
 
 TuneKey shape_key(const subkm_run *runs, int32_t R, int32_t precision, int32_t max_iter) {
     int64_t npts = 0;

@@ -34,6 +34,8 @@ struct DevRun {
     int64_t cn_off;           // split-bfloat16 path: squared norms of the centers
     int32_t split;            // assignment with split-bfloat16 products
     int32_t orig;             // index of the run in the caller's array
+    int32_t xatom;            // batched on-chip form: partial sums added into shared totals
+    int32_t pad;
 };
 
 struct RunState {

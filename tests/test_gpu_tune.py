@@ -102,9 +102,88 @@ def test_tune_load_rejects_malformed(tmp_path):
         f.write("subkm-tune 2\n1 2 3 4 5 64 1 0.5\n")  # a field missing
     with pytest.raises(pkg.SubkmError):
         ctx.tune_load(path)
-    # the first format (no tiles field) still loads
+    with open(path, "w") as f:
+        f.write("subkm-tune 3\n1 2 3 4 5 64 1 2 0.5\n")  # no exchange field
+    with pytest.raises(pkg.SubkmError):
+        ctx.tune_load(path)
+    with open(path, "w") as f:
+        f.write("subkm-tune 3\n1 2 3 4 5 64 1 2 2 0.5\n")  # unknown exchange
+    with pytest.raises(pkg.SubkmError):
+        ctx.tune_load(path)
+    # the earlier formats (no exchange field; nor a tiles field) still load
     with open(path, "w") as f:
         f.write("subkm-tune 1\n1 2 3 4 5 64 1 0.5\n")
     ctx.tune_load(path)
     assert ctx.tuned() == 1
+    with open(path, "w") as f:
+        f.write("subkm-tune 2\n1 2 3 4 5 64 1 2 0.5\n2 2 3 4 5 64 1 1 0.5\n")
+    ctx.tune_load(path)
+    assert ctx.tuned() == 2
+    with open(path, "w") as f:
+        f.write("subkm-tune 3\n3 2 3 4 5 64 1 2 1 0.5\n")
+    ctx.tune_load(path)
+    assert ctx.tuned() == 3
     ctx.close()
+
+
+def _shape_line(runs, precision, sched):
+    """A schedule-file entry for the shape of `runs` (see the tuner's key:
+    runs, points, smallest and largest d and k, precision and moves)."""
+    n = sum(r[1] for r in runs)
+    ds = [r[4] for r in runs]
+    ks = [r[5] for r in runs]
+    v = [len(runs), n, (min(ds) << 32) | max(ds), (min(ks) << 32) | max(ks), (precision << 1) | 1]
+    return " ".join("%x" % x for x in v) + " %d %d %d %d 1.0\n" % sched
+
+
+@pytest.mark.parametrize("shape", ["one_run", "many_runs"])
+def test_every_exchange_mode_same_bits(tmp_path, shape):
+    """Forced schedules, both per-move exchanges (published parts with slice
+    sums; shared totals with integer atomics) and several blocks-per-run
+    caps, give the bits of the default schedule: centers, labels, moves and
+    objectives."""
+    import paper_1412_1947_amd as pkg
+    rng = np.random.default_rng(21)
+    if shape == "one_run":
+        # one run of a final stage's shape: many blocks share every move
+        specs = [(32768, 16, 64)]
+    else:
+        specs = [(6000 + 700 * r, 16, 48 + 16 * (r % 3)) for r in range(12)]
+    runs, Xs, C0, off, coff = [], [], [], 0, 0
+    for n, d, k in specs:
+        means = rng.normal(0, 3, (k, d))
+        X = (means[rng.integers(0, k, n)] + rng.normal(0, 1, (n, d))).astype(np.float32)
+        X = (X - X.min(0)) / (X.max(0) - X.min(0))
+        Xs.append(X.astype(np.float32))
+        C0.append(X[rng.choice(n, k, replace=False)])
+        runs.append((off * d, n, coff * d, off, d, k))
+        off += n
+        coff += k
+    P = dev(np.concatenate(Xs))
+    Cs = np.concatenate(C0)
+    # k_final-sized runs reach the split path in FP32 at d = 16
+    prec = pkg.PREC_FP32
+
+    def run(ctx):
+        C = dev(Cs)
+        lab = torch.empty(off, dtype=torch.int32, device="cuda:0")
+        it, sse = ctx.lloyd_batched(P.reshape(-1), runs, C, lab, 20, 0.0, prec)
+        return host(C), host(lab), host(it), host(sse)
+
+    base = pkg.Context(0)
+    ref = run(base)
+    base.close()
+    assert int(ref[2].min()) >= 2  # every run moves: the exchange runs
+    for sched in [(128, 1, 1, 0), (128, 1, 1, 1), (64, 1, 2, 1), (16, 1, 2, 1), (4, 1, 2, 1),
+                  (2, 1, 1, 1)]:
+        path = os.path.join(tmp_path, "s.txt")
+        with open(path, "w") as f:
+            f.write("subkm-tune 3\n" + _shape_line(runs, prec, sched))
+        ctx = pkg.Context(0)
+        ctx.tune_load(path)
+        assert ctx.tuned() == 1
+        got = run(ctx)
+        assert ctx.tuned() == 1  # the loaded schedule served the call
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), sched
+        ctx.close()
