@@ -282,6 +282,12 @@ def bench_unequal(subkm, km, X, ref, alg1_stats, job, kw, alg1_ms):
     sse = float(out["sse"].cpu()[0])
     _, _, offs = km.subcluster_unequal(S, m)
     sizes = np.diff(offs.cpu().numpy())
+    # a group of n_g points gets ceil(n_g k_local / N) local centers, so one
+    # move of the local runs costs sum_g 2 d n_g k_g flops: it grows with the
+    # square of the group sizes, against 2 d n k_local for N-point groups
+    kg = -(-sizes * job.k_local // job.N)
+    gflop_move = float((2.0 * d * sizes * kg).sum()) / 1e9
+    gflop_move_alg1 = 2.0 * d * n * job.k_local / 1e9
     return {"what": "Algorithm 2: m landmarks on the segment from the min to the max corner, "
                     "nearest-landmark groups", "m": m,
             "subcluster_ms": sub_ms, "subcluster_gbps": ach / 1e9,
@@ -291,6 +297,7 @@ def bench_unequal(subkm, km, X, ref, alg1_stats, job, kw, alg1_ms):
             "alg1_subcluster_ms": alg1_stats["us_subcluster"] * 1e-3,
             "group_sizes": {"min": int(sizes.min()), "max": int(sizes.max()),
                             "empty": int((sizes == 0).sum())},
+            "local_gflop_per_move": gflop_move, "alg1_local_gflop_per_move": gflop_move_alg1,
             "ms_per_step": ms, "alg1_ms_per_step": alg1_ms, "M": st["M"],
             "point_iters_per_step": int(st["local_point_iters"] + st["final_point_iters"]),
             "phases_us": {k: st[k] for k in ("us_scale", "us_subcluster", "us_local", "us_final",

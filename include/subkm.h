@@ -200,10 +200,12 @@ subkm_status subkm_subcluster_unequal(subkm_ctx *ctx, const float *S, int64_t n,
  *            centers fit on chip with 8, 16 or 32 attributes, where each
  *            product is the sum of the four products of split bfloat16
  *            pairs (x = x_hi + x_lo, both operands), accumulated in float32
- *            on the matrix cores (relative error about 2^-16);
- *            SUBKM_PREC_BF16: additionally the split bfloat16 form for runs
- *            of 32 to 128 attributes whose centers do not fit on chip
- *            (three products per pair, the smallest dropped).  In both,
+ *            on the matrix cores (relative error about 2^-16), and in runs
+ *            of 32 attributes and at most 1024 centers whose centers do not
+ *            fit on chip, which take the split form with three products per
+ *            pair (the smallest dropped);
+ *            SUBKM_PREC_BF16: additionally that three-product split form
+ *            for such runs of 33 to 128 attributes.  In both,
  *            every point whose two nearest centers are closer than the
  *            error bound of the arithmetic used is re-assigned (float32,
  *            then binary64 distances), so the labels are those of exact

@@ -2094,7 +2094,11 @@ void plan_runs(const subkm_run *runs, int32_t R, int32_t precision, int32_t max_
             D.cnt_off = z.cnt_words;
             z.cnt_words += 3 * (int64_t)u.k;
             z.order_words = std::max<int64_t>(z.order_words, u.lab_off + u.n);
-            D.split = (precision == SUBKM_PREC_BF16 && u.d >= 32 && u.d <= 128 && u.k <= 1024) ? 1 : 0;
+            // split bfloat16 for 32 attributes under either setting (one
+            // matrix-core step covers the row; same labels as float32),
+            // and for up to 128 attributes under SUBKM_PREC_BF16
+            D.split = ((u.d == 32 || (precision == SUBKM_PREC_BF16 && u.d >= 32 && u.d <= 128)) &&
+                       u.k <= 1024) ? 1 : 0;
             if (D.split) {
                 const int64_t kt = ceil_div(u.k, 16), st = ceil_div(u.d, 32);
                 D.frag_off = z.frag_words;
