@@ -2204,15 +2204,15 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
         DevRun &D = dr[r];
         D.uitem0 = (int)items.size();
         if (!D.fused) {
-            D.kcu = kWideCenters;
-            for (int c = 0; c < D.k; c += kWideCenters) items.push_back(Item{r, c, 0, 0});
+            D.kcu = D.d <= kWalkD ? kWalkCenters : kWideCenters;
+            for (int c = 0; c < D.k; c += D.kcu) items.push_back(Item{r, c, 0, 0});
         }
         D.nuitems = (int)items.size() - D.uitem0;
     }
     for (int r = 0; r < nplain; ++r) {
         walk0[r] = (int)items.size();
         if (!dr[r].fused && dr[r].d <= kWalkD)
-            for (int64_t f = 0; f < dr[r].n; f += kWalkB) items.push_back(Item{r, (int32_t)f, 0, 0});
+            for (int64_t f = 0; f < dr[r].n; f += walk_span(dr[r].d)) items.push_back(Item{r, (int32_t)f, 0, 0});
         nwalk[r] = (int)items.size() - walk0[r];
     }
     if (persist_any) {
@@ -2536,8 +2536,8 @@ void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision,
         } else {
             n_items += t;
             if (!dr[r].fused) {
-                n_items += ceil_div(dr[r].k, kWideCenters);
-                if (dr[r].d <= kWalkD) n_items += ceil_div(dr[r].n, kWalkB);
+                n_items += ceil_div(dr[r].k, dr[r].d <= kWalkD ? kWalkCenters : kWideCenters);
+                if (dr[r].d <= kWalkD) n_items += ceil_div(dr[r].n, walk_span(dr[r].d));
             }
         }
     }

@@ -12,7 +12,19 @@ namespace subkm_lloyd {
 constexpr int kAT = 256;  // threads per block = points per assignment tile
 constexpr int kWalkD = 128;            // widest points of the balanced update walk
 constexpr int kWalkW = 256;            // positions per wavefront in the walk
-constexpr int kWalkB = 4 * kWalkW;     // positions per walk item (block)
+constexpr int kWalkB = 4 * kWalkW;     // positions per walk item (block), 64-lane groups
+constexpr int kWalkCenters = 256;      // centers per update item of a walked run
+
+// Lanes that hold one point in the walk: the next power of two >= d, at most
+// 64 (wider points take two attributes per lane).  A wavefront holds
+// 64 / walk_lanes(d) points side by side, each lane group walking its own
+// window of kWalkW positions, so a walk item spans kWalkB * 64 / walk_lanes(d).
+__host__ __device__ inline int walk_lanes(int d) {
+    int g = 1;
+    while (g < d && g < 64) g <<= 1;
+    return g;
+}
+__host__ __device__ inline int64_t walk_span(int d) { return (int64_t)kWalkB * (64 / walk_lanes(d)); }
 
 enum : int32_t { PH_ITER = 0, PH_FINAL = 1, PH_DONE = 2 };
 
@@ -227,7 +239,7 @@ subkm_status wide_assign_split(subkm_ctx *ctx, int S, int i0, int ni, const floa
 // order holds the point indices grouped by label at lab_off and their
 // labels at olab_off + lab_off; gsum the int64 sums of the wide runs with
 // d <= kWalkD (at sum_off, zero between calls).  Walk items [w0, w0 + nw)
-// cover kWalkB positions each.
+// cover walk_span(d) positions each.
 subkm_status wide_update(subkm_ctx *ctx, int r0, int nr, int i0, int ni, int w0, int nw, int u0,
                          int nu, const float *P, const DevRun *runs, const Item *items,
                          const int32_t *labels, float *C, RunState *rs, int32_t *cnt,

@@ -686,20 +686,22 @@ __global__ __launch_bounds__(kAT) void k_wscatter(const DevRun *__restrict__ run
     });
 }
 
-// Balanced sums for runs with d <= kWalkD.  Every wavefront walks kWalkW
-// consecutive positions of the run's label-sorted order (lanes hold
-// attributes lane and lane + 64 of one point at a time) and keeps the running
-// fixed-point sum of the current center.  A center whose points all lie in
-// the window gets its new value right away; the partial sums of a center
-// that crosses a window edge go to the run's int64 sums (exact, so the order
-// of the atomic additions does not matter) and k_wfin finishes it.
+// Balanced sums for runs with d <= kWalkD.  A wavefront holds 64 / g points
+// side by side (g = walk_lanes(d) lanes per point, lane j0 of a group holding
+// attributes j0 and j0 + g); each lane group walks its own window of kWalkW
+// consecutive positions of the run's label-sorted order and keeps the running
+// fixed-point sum of the current center.  Windows are aligned to kWalkW
+// positions whatever g is.  A center whose points all lie in one window gets
+// its new value right away; the partial sums of a center that crosses a
+// window edge go to the run's int64 sums (exact, so the order of the atomic
+// additions does not matter) and k_wfin finishes it.
 __global__ __launch_bounds__(kAT) void k_wwalk(const float *__restrict__ P,
                                               const DevRun *__restrict__ runs,
                                               const Item *__restrict__ items, int w0,
                                               const int32_t *__restrict__ order, int64_t olab_off,
                                               float *C, RunState *rstate,
                                               const int32_t *__restrict__ cnt, long long *gsum) {
-    constexpr int kU = 16;
+    constexpr int kU = 8;
     const Item itm = items[w0 + blockIdx.x];
     const DevRun R = runs[itm.run];
     RunState *rs = rstate + itm.run;
@@ -707,9 +709,11 @@ __global__ __launch_bounds__(kAT) void k_wwalk(const float *__restrict__ P,
     const int d = R.d;
     const int s = fix_shift_of(rs->absmax_bits);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ja = lane, jc = lane + 64;
-    const int64_t a = (int64_t)itm.first + (int64_t)wave * kWalkW;
+    const int g = walk_lanes(d), ppw = 64 / g, sub = lane / g, j0 = lane % g;
+    const int ja = j0, jc = j0 + g;
+    const int64_t a = (int64_t)itm.first + ((int64_t)wave * ppw + sub) * kWalkW;
     const int64_t b = min(R.n, a + kWalkW);
+    const int nb = (int)max((int64_t)0, b - a);  // positions of this lane's group
     const int32_t *counts = cnt + R.cnt_off;
     const int32_t *starts = counts + R.k;
     const float *X = P + R.x_off;
@@ -720,6 +724,8 @@ __global__ __launch_bounds__(kAT) void k_wwalk(const float *__restrict__ P,
     double wmax = 0.0;
     int32_t cur = -1;
     long long A0 = 0, A1 = 0;
+    // every lane of a group takes the same branches (cur is the group's):
+    // the exchanges below stay inside the group
     auto flush = [&]() {
         if (cur < 0) return;
         const int32_t st = starts[cur], n_c = counts[cur];
@@ -739,32 +745,36 @@ __global__ __launch_bounds__(kAT) void k_wwalk(const float *__restrict__ P,
                 dv2 = dv2 + dv * dv;
                 Cr[(int64_t)cur * d + jc] = (float)nv;
             }
-            for (int o = 32; o > 0; o >>= 1) dv2 = dv2 + __shfl_xor(dv2, o, 64);
+            for (int o = g >> 1; o > 0; o >>= 1) dv2 = dv2 + __shfl_xor(dv2, o, 64);
             wmax = fmax(wmax, sqrt(dv2));
         } else {
             if (ja < d) atomicAdd((unsigned long long *)&gs[(int64_t)cur * d + ja], (unsigned long long)A0);
             if (jc < d) atomicAdd((unsigned long long *)&gs[(int64_t)cur * d + jc], (unsigned long long)A1);
         }
     };
-    for (int64_t q0 = a; q0 < b; q0 += 64) {
-        const int nb = (int)min((int64_t)64, b - q0);
-        const int32_t myp = lane < nb ? ord[q0 + lane] : 0;
-        const int32_t myl = lane < nb ? olab[q0 + lane] : -1;
-        for (int ub = 0; ub < nb; ub += kU) {
+    // positions are read g at a time per group (lane j0 reads position
+    // q0 + j0) and broadcast inside the group, kU rows in flight per lane;
+    // the trip counts are the same for every lane of the wavefront
+    for (int q0 = 0; q0 < kWalkW; q0 += g) {
+        const bool okp = q0 + j0 < nb;
+        const int32_t myp = okp ? ord[a + q0 + j0] : 0;
+        const int32_t myl = okp ? olab[a + q0 + j0] : -1;
+        for (int ub = 0; ub < g; ub += kU) {
             float v0[kU], v1[kU];
             int32_t lu[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int qq = ub + u < 64 ? ub + u : 63;
-                const int64_t p = __shfl(myp, qq, 64);
-                lu[u] = __shfl(myl, qq, 64);
-                const bool ok = ub + u < nb;
+                const int qq = ub + u < g ? ub + u : g - 1;
+                const int64_t p = __shfl(myp, sub * g + qq, 64);
+                lu[u] = __shfl(myl, sub * g + qq, 64);
+                const bool ok = ub + u < g && q0 + ub + u < nb;
                 v0[u] = (ok && ja < d) ? X[p * d + ja] : 0.0f;
                 v1[u] = (ok && jc < d) ? X[p * d + jc] : 0.0f;
+                if (!ok) lu[u] = -1;
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                if (ub + u < nb) {  // the same for every lane
+                if (lu[u] >= 0) {  // the same for every lane of the group
                     if (lu[u] != cur) {
                         flush();
                         cur = lu[u];
@@ -778,6 +788,7 @@ __global__ __launch_bounds__(kAT) void k_wwalk(const float *__restrict__ P,
         }
     }
     flush();
+    for (int o = 32; o > 0; o >>= 1) wmax = fmax(wmax, __shfl_xor(wmax, o, 64));
     if (lane == 0 && wmax > 0.0)
         atomicMax(&rs->shift_bits, (unsigned long long)__double_as_longlong(wmax));
 }
@@ -823,26 +834,41 @@ __global__ __launch_bounds__(kAT) void k_wfin(const float *__restrict__ P,
     double mx = 0.0;
     const bool walked = d <= kWalkD;
     long long *gs = gsum + R.sum_off;
-    for (int c = itm.first + wave; c < c1; c += kAT / 64) {
+    if (walked) {
+        // one center per lane: the counts are read (and cleared) 64 at a
+        // time; the centers that crossed a walk window are finished one
+        // after the other by the whole wavefront
+        for (int cb = itm.first + wave * 64; cb < c1; cb += kAT) {
+            const int c = cb + lane;
+            const int32_t n_c = c < c1 ? counts[c] : 0;
+            const int32_t st = c < c1 ? starts[c] : 0;
+            if (c < c1) counts[c] = 0;
+            unsigned long long todo = __ballot(n_c > 0 && st / kWalkW != (st + n_c - 1) / kWalkW);
+            while (todo) {
+                const int t = __ffsll(todo) - 1;
+                todo &= todo - 1;
+                const int ct = cb + t;
+                const int32_t nt = __shfl(n_c, t, 64);
+                double dv2 = 0.0;
+                for (int j = lane; j < d; j += 64) {
+                    const long long a = gs[(int64_t)ct * d + j];
+                    gs[(int64_t)ct * d + j] = 0;
+                    const float old = Cr[(int64_t)ct * d + j];
+                    const double nv = ldexp((double)a, -s) / (double)nt;
+                    const double dv = nv - (double)old;
+                    dv2 = dv2 + dv * dv;
+                    Cr[(int64_t)ct * d + j] = (float)nv;
+                }
+                for (int o = 32; o > 0; o >>= 1) dv2 = dv2 + __shfl_xor(dv2, o, 64);
+                mx = fmax(mx, sqrt(dv2));
+            }
+        }
+    }
+    for (int c = itm.first + wave; !walked && c < c1; c += kAT / 64) {
         const int32_t n_c = counts[c];
         const int32_t st = starts[c];
         double mv2 = 0.0;
-        if (walked) {
-            if (n_c > 0 && st / kWalkW != (st + n_c - 1) / kWalkW) {
-                double dv2 = 0.0;
-                for (int j = lane; j < d; j += 64) {
-                    const long long a = gs[(int64_t)c * d + j];
-                    gs[(int64_t)c * d + j] = 0;
-                    const float old = Cr[(int64_t)c * d + j];
-                    const double nv = ldexp((double)a, -s) / (double)n_c;
-                    const double dv = nv - (double)old;
-                    dv2 = dv2 + dv * dv;
-                    Cr[(int64_t)c * d + j] = (float)nv;
-                }
-                for (int o = 32; o > 0; o >>= 1) dv2 = dv2 + __shfl_xor(dv2, o, 64);
-                mv2 = dv2;
-            }
-        } else if (n_c > 0) {
+        if (n_c > 0) {
             for (int jb = 0; jb < d; jb += 2 * dg) {
                 const int ja = jb + j0, jc = jb + j0 + dg;  // this lane's two attributes
                 long long a0 = 0, a1 = 0;
