@@ -54,6 +54,7 @@ constexpr int64_t kXAtomMax = 1 << 18;  // shared-totals exchange: most atomics 
 constexpr int kExB = 16;           // exchange loads in flight per thread
 constexpr int kChunkF = 8192;       // center floats staged per chunk (chunked path)
 constexpr int kWideCenters = 16;    // centers per update item (wide runs)
+constexpr int64_t kWalkMinBlocks = 512;  // blocks a walk launch keeps when narrow points share wavefronts
 constexpr int64_t kHugeRun = 1 << 15; // points beyond which a run with moves takes the wide path
 constexpr int kUList = 256;         // deferred uncertain points per block and pass (split path)
 
@@ -1711,6 +1712,187 @@ __global__ __launch_bounds__(kAT) void k_assign_big(const float *__restrict__ P,
     }
 }
 
+// Chunked path on split bfloat16 (D = 8 or 16, rows 16-byte aligned): the
+// run's centers stream through LDS in chunks of kBigBfC, each block splitting
+// -2 (c - m) into bfloat16 parts as it stages them; stage 1 is the split
+// product of stage1_bf (four terms of D attributes in one K = 32 step per
+// 8 attributes, accumulator started at ||c - m||^2) with the float32 top-2
+// tracking of k_assign_big.  Without the offset Q every partial sum stays
+// below 1.03 s^2, s = ||x - m|| + max_c ||c - m||, so the bound of stage1_bf
+// holds with Q = 0: E = 2^-16 s^2 + (D + 3 + 2.06 (4 D + 1)) u s^2.  Points
+// whose two smallest values are not 2 E apart are re-assigned in binary64
+// against the centers in global memory.
+constexpr int kBigBfC = 512;  // centers per staged chunk
+
+template <int D>
+__global__ __launch_bounds__(kAT) void k_assign_big_bf(const float *__restrict__ P,
+                                                       const DevRun *__restrict__ runs,
+                                                       const Item *__restrict__ items, int item_base,
+                                                       const float *__restrict__ C, int32_t *labels,
+                                                       RunState *rstate, double *objpart,
+                                                       const uint32_t *__restrict__ boxes,
+                                                       int last_pass) {
+    static_assert(D == 8 || D == 16, "split chunked path: D = 8 or 16");
+    constexpr int S = D / 8;                 // instructions per group and center tile
+    constexpr int NA = D >= 16 ? D / 16 : 1;  // distinct A operands per lane
+    __shared__ bf16x8 sA[kBigBfC * (D / 4)];
+    __shared__ float cn[kBigBfC];
+    __shared__ float s_mid[D];
+    __shared__ int32_t s_lab[kAT];
+    __shared__ double s_red[kAT];
+    const Item itm = items[item_base + blockIdx.x];
+    const DevRun R = runs[itm.run];
+    RunState *rs = rstate + itm.run;
+    const int32_t ph = rs->phase;
+    if (ph == PH_DONE) return;
+    const bool want_obj = last_pass || ph == PH_FINAL;
+    const int k = R.k;
+    const float *X = P + R.x_off;
+    const float *Cr = C + R.c_off;
+    const uint32_t *box = boxes + R.box_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kg = lane >> 4;
+    const int64_t first_w = itm.first + wave * 64;
+    if (threadIdx.x < D) s_mid[threadIdx.x] = box_mid(box, D, threadIdx.x);
+    __syncthreads();
+    float xr[4][8];
+    load_tile_bf<D>(X, first_w, R.n, xr);
+    bf16x8 ah[4], al[4];
+    float xn[4], xa[4][D / 4];
+    split_tile_bf<D>(xr, s_mid, first_w, R.n, ah, al, xn, xa);
+    int qa[NA];
+#pragma unroll
+    for (int s = 0; s < NA; ++s) {
+        const int t = (32 * s + 8 * kg) / D, j0 = (32 * s + 8 * kg) % D;
+        qa[s] = (t & 1) * (D / 8) + j0 / 8;
+    }
+    bf16x8 b8[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) b8[g] = (D == 8 && kg >= 2) ? al[g] : ah[g];
+    float b1[4], b2[4];
+    int32_t i1[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        b1[g] = INFINITY;
+        b2[g] = INFINITY;
+        i1[g] = 0;
+    }
+    float mx = 0.0f;  // this thread's largest ||c - m||^2 over the centers it staged
+    for (int c0 = 0; c0 < k; c0 += kBigBfC) {
+        const int nc = kBigBfC < k - c0 ? kBigBfC : k - c0;
+        const int ncr = (nc + 15) & ~15;
+        __syncthreads();  // nobody still reads the previous chunk
+        for (int c = threadIdx.x; c < ncr; c += kAT) {
+            float a = INFINITY;
+            if (c < nc) {
+                a = 0.0f;
+                const float *cr = Cr + (int64_t)(c0 + c) * D;
+#pragma unroll
+                for (int q = 0; q < D / 8; ++q) {
+                    bf16x8 hi, lo;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int j = 8 * q + e;
+                        const float t = cr[j] - s_mid[j];
+                        a = __builtin_fmaf(t, t, a);
+                        const float v = -2.0f * t;
+                        const __bf16 h = (__bf16)v;
+                        hi[e] = h;
+                        lo[e] = (__bf16)(v - (float)h);
+                    }
+                    sA[sa_idx<D>(c, q)] = hi;
+                    sA[sa_idx<D>(c, D / 8 + q)] = lo;
+                }
+                mx = fmaxf(mx, a);
+            } else {
+                const bf16x8 z = {};
+#pragma unroll
+                for (int q = 0; q < D / 4; ++q) sA[sa_idx<D>(c, q)] = z;
+            }
+            cn[c] = a;  // +inf past the run's centers: never selected
+        }
+        __syncthreads();
+        for (int t0 = 0; t0 < ncr; t0 += 16) {
+            bf16x8 A[NA];
+#pragma unroll
+            for (int s = 0; s < NA; ++s) A[s] = sA[sa_idx<D>(t0 + col, qa[s])];
+            const floatx4 cinit = {cn[t0 + 4 * kg], cn[t0 + 4 * kg + 1], cn[t0 + 4 * kg + 2],
+                                   cn[t0 + 4 * kg + 3]};
+            floatx4 acc[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                acc[g] = cinit;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const bf16x8 B = D == 8 ? b8[g] : ((32 * s) / D >= 2 ? al[g] : ah[g]);
+                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s % NA], B, acc[g], 0, 0, 0);
+                }
+            }
+            const int32_t cb = c0 + t0 + 4 * kg;
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float v = acc[g][r];
+                    b2[g] = __builtin_amdgcn_fmed3f(v, b1[g], b2[g]);
+                    const bool lt = v < b1[g];
+                    b1[g] = lt ? v : b1[g];
+                    i1[g] = lt ? cb + r : i1[g];
+                }
+        }
+    }
+    const double rmax = block_max<kAT>((double)mx, s_red);
+    const float Rc = sqrtf((float)rmax);
+    constexpr float Ks = 1.52587890625e-05f;
+    constexpr float Ka = (float)(D + 3 + 2.06 * (4 * D + 1)) * 5.9604645e-8f;
+    int32_t *wlab = s_lab + wave * 64;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            const float ob1 = o == 16 ? lane_xor16(b1[g]) : lane_xor32(b1[g]);
+            const float ob2 = o == 16 ? lane_xor16(b2[g]) : lane_xor32(b2[g]);
+            const int32_t oi = o == 16 ? lane_xor16(i1[g]) : lane_xor32(i1[g]);
+            const float nb2 = fminf(fminf(b2[g], ob2), fmaxf(b1[g], ob1));
+            const bool take = (ob1 < b1[g]) | ((ob1 == b1[g]) & (oi < i1[g]));  // no branch
+            b1[g] = take ? ob1 : b1[g];
+            i1[g] = take ? oi : i1[g];
+            b2[g] = nb2;
+        }
+        const float sx = xn[g] + Rc;
+        const float s2 = sx * sx;
+        const float E = (Ks + Ka) * s2 + 1e-30f;
+        const bool certain = k == 1 || (b2[g] - b1[g]) > 2.0f * E;
+        if (kg == 0) wlab[g * 16 + col] = i1[g] | (certain ? 0 : (int32_t)0x80000000);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t i = first_w + lane;
+    const bool valid = i < R.n;
+    const float *xg = X + (valid ? i : 0) * D;
+    const int32_t sl = wlab[lane];
+    int32_t lab = sl & 0x7fffffff;
+    unsigned long long todo = __ballot(valid && sl < 0);
+    const unsigned long long nre = (unsigned long long)__popcll(todo);
+    while (todo) {
+        const int t = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int32_t w = wave_argmin64(X + (first_w + t) * D, Cr, D, k);
+        if (lane == t) lab = w;
+    }
+    double obj = 0.0;
+    if (valid) {
+        labels[R.lab_off + i] = lab;
+        if (want_obj) obj = dist64(xg, Cr + (int64_t)lab * D, D);
+    }
+    if (lane == 0 && nre) atomicAdd(&rs->rechecks, nre);
+    if (want_obj) {
+        const double tot = block_sum_det(obj, s_red);
+        if (threadIdx.x == 0) objpart[item_base + blockIdx.x] = tot;
+    }
+}
+
 // ---------------------------------------------------------------------------
 __global__ void k_state_init(RunState *rstate, int R) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1970,7 +2152,16 @@ template <int D>
 subkm_status launch_assign_big(subkm_ctx *ctx, int nitems, int item_base, const float *P,
                                const DevRun *runs, const Item *items, const float *C,
                                int32_t *labels, RunState *rs, double *objpart,
-                               const uint32_t *boxes, int last_pass) {
+                               const uint32_t *boxes, int last_pass, int bf) {
+    if constexpr (D == 8 || D == 16) {
+        if (bf) {
+            ProfScope ps(ctx, PK_ASSIGN);
+            hipLaunchKernelGGL(k_assign_big_bf<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs,
+                               items, item_base, C, labels, rs, objpart, boxes, last_pass);
+            SUBKM_LAUNCHED(ctx);
+            return SUBKM_OK;
+        }
+    }
     if constexpr (kHasMF<D>) {
         ProfScope ps(ctx, PK_ASSIGN);
         hipLaunchKernelGGL(k_assign_big<D>, dim3(nitems), dim3(kAT), 0, ctx->stream, P, runs, items,
@@ -1986,10 +2177,11 @@ subkm_status launch_assign_big(subkm_ctx *ctx, int nitems, int item_base, const 
 // assignment of runs beyond the LDS budget: matrix cores when d allows
 subkm_status assign_big_d(subkm_ctx *ctx, int d, int nitems, int item_base, const float *P,
                           const DevRun *runs, const Item *items, const float *C, int32_t *labels,
-                          RunState *rs, double *objpart, const uint32_t *boxes, int last_pass) {
+                          RunState *rs, double *objpart, const uint32_t *boxes, int last_pass,
+                          int bf) {
     if (nitems <= 0) return SUBKM_OK;
     SUBKM_DISPATCH_D(d, launch_assign_big, ctx, nitems, item_base, P, runs, items, C, labels, rs,
-                     objpart, boxes, last_pass);
+                     objpart, boxes, last_pass, bf);
 }
 
 subkm_status persist_d(subkm_ctx *ctx, int d, int mf, int blocks, const float *P,
@@ -2204,15 +2396,35 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
         DevRun &D = dr[r];
         D.uitem0 = (int)items.size();
         if (!D.fused) {
-            D.kcu = D.d <= kWalkD ? kWalkCenters : kWideCenters;
+            // walked runs whose centers average under a quarter window
+            // (few cross a window edge) read 256 centers per block
+            D.kcu = (D.d <= kWalkD && D.n < (int64_t)D.k * (kWalkW / 4)) ? kWalkCenters : kWideCenters;
             for (int c = 0; c < D.k; c += D.kcu) items.push_back(Item{r, c, 0, 0});
         }
         D.nuitems = (int)items.size() - D.uitem0;
     }
+    // Points per wavefront in the update walk: narrow points share a
+    // wavefront (fewer idle lanes), as long as the walk launch keeps about
+    // kWalkMinBlocks blocks; the batched form launches the walks of all its
+    // wide runs together, the plain form one run at a time.
+    {
+        int64_t walked = 0;
+        for (int r = 0; r < nplain; ++r)
+            if (!dr[r].fused && dr[r].d <= kWalkD) walked += dr[r].n;
+        for (int r = 0; r < nplain; ++r) {
+            DevRun &D = dr[r];
+            D.wpp = 1;
+            if (D.fused || D.d > kWalkD) continue;
+            const int64_t tot = batched ? walked : D.n;
+            const int cap = 64 / walk_lanes(D.d);
+            while (2 * D.wpp <= cap && tot >= (int64_t)kWalkB * 2 * D.wpp * kWalkMinBlocks) D.wpp *= 2;
+        }
+    }
     for (int r = 0; r < nplain; ++r) {
         walk0[r] = (int)items.size();
         if (!dr[r].fused && dr[r].d <= kWalkD)
-            for (int64_t f = 0; f < dr[r].n; f += walk_span(dr[r].d)) items.push_back(Item{r, (int32_t)f, 0, 0});
+            for (int64_t f = 0; f < dr[r].n; f += (int64_t)kWalkB * dr[r].wpp)
+                items.push_back(Item{r, (int32_t)f, 0, 0});
         nwalk[r] = (int)items.size() - walk0[r];
     }
     if (persist_any) {
@@ -2364,7 +2576,12 @@ subkm_status lloyd_run(subkm_ctx *ctx, const float *P, const subkm_run *runs, in
             return wide_assign_split(ctx, S, i0, ni, P, d_runs, d_items, C, d_frags, d_cn, labels, d_rs,
                                      d_obj, d_box, last);
         }
-        return assign_big_d(ctx, D0.d, ni, i0, P, d_runs, d_items, C, labels, d_rs, d_obj, d_box, last);
+        // 8 or 16 attributes with 16-byte aligned rows: split bfloat16 stage 1
+        bool bf = D0.d == 8 || D0.d == 16;
+        for (int r = r0; bf && r < r1; ++r)
+            if ((uintptr_t)(P + dr[r].x_off) & 15u) bf = false;
+        return assign_big_d(ctx, D0.d, ni, i0, P, d_runs, d_items, C, labels, d_rs, d_obj, d_box, last,
+                            bf ? 1 : 0);
     };
     // one update for runs [r0, r1), all on-chip or all wide
     auto update_seg = [&](int r0, int r1) -> subkm_status {
@@ -2536,8 +2753,8 @@ void lloyd_scratch_requests(const subkm_run *runs, int32_t R, int32_t precision,
         } else {
             n_items += t;
             if (!dr[r].fused) {
-                n_items += ceil_div(dr[r].k, dr[r].d <= kWalkD ? kWalkCenters : kWideCenters);
-                if (dr[r].d <= kWalkD) n_items += ceil_div(dr[r].n, walk_span(dr[r].d));
+                n_items += ceil_div(dr[r].k, kWideCenters);  // at most
+                if (dr[r].d <= kWalkD) n_items += ceil_div(dr[r].n, kWalkB);  // at most
             }
         }
     }

@@ -15,16 +15,16 @@ constexpr int kWalkW = 256;            // positions per wavefront in the walk
 constexpr int kWalkB = 4 * kWalkW;     // positions per walk item (block), 64-lane groups
 constexpr int kWalkCenters = 256;      // centers per update item of a walked run
 
-// Lanes that hold one point in the walk: the next power of two >= d, at most
-// 64 (wider points take two attributes per lane).  A wavefront holds
-// 64 / walk_lanes(d) points side by side, each lane group walking its own
-// window of kWalkW positions, so a walk item spans kWalkB * 64 / walk_lanes(d).
+// Fewest lanes that hold one point in the walk: the next power of two >= d,
+// at most 64 (wider points take two attributes per lane).  A wavefront holds
+// DevRun::wpp points side by side (at most 64 / walk_lanes(d)), each group of
+// 64 / wpp lanes walking its own window of kWalkW positions, so a walk item
+// spans kWalkB * wpp positions.
 __host__ __device__ inline int walk_lanes(int d) {
     int g = 1;
     while (g < d && g < 64) g <<= 1;
     return g;
 }
-__host__ __device__ inline int64_t walk_span(int d) { return (int64_t)kWalkB * (64 / walk_lanes(d)); }
 
 enum : int32_t { PH_ITER = 0, PH_FINAL = 1, PH_DONE = 2 };
 
@@ -47,6 +47,7 @@ struct DevRun {
     int32_t split;            // assignment with split-bfloat16 products
     int32_t orig;             // index of the run in the caller's array
     int32_t xatom;            // batched on-chip form: partial sums added into shared totals
+    int32_t wpp;              // wide path, d <= kWalkD: points per wavefront in the update walk
     int32_t pad;
 };
 
@@ -239,7 +240,7 @@ subkm_status wide_assign_split(subkm_ctx *ctx, int S, int i0, int ni, const floa
 // order holds the point indices grouped by label at lab_off and their
 // labels at olab_off + lab_off; gsum the int64 sums of the wide runs with
 // d <= kWalkD (at sum_off, zero between calls).  Walk items [w0, w0 + nw)
-// cover walk_span(d) positions each.
+// cover kWalkB * DevRun::wpp positions each.
 subkm_status wide_update(subkm_ctx *ctx, int r0, int nr, int i0, int ni, int w0, int nw, int u0,
                          int nu, const float *P, const DevRun *runs, const Item *items,
                          const int32_t *labels, float *C, RunState *rs, int32_t *cnt,

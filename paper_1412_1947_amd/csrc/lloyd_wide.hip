@@ -686,8 +686,8 @@ __global__ __launch_bounds__(kAT) void k_wscatter(const DevRun *__restrict__ run
     });
 }
 
-// Balanced sums for runs with d <= kWalkD.  A wavefront holds 64 / g points
-// side by side (g = walk_lanes(d) lanes per point, lane j0 of a group holding
+// Balanced sums for runs with d <= kWalkD.  A wavefront holds R.wpp points
+// side by side (g = 64 / R.wpp lanes per point, lane j0 of a group holding
 // attributes j0 and j0 + g); each lane group walks its own window of kWalkW
 // consecutive positions of the run's label-sorted order and keeps the running
 // fixed-point sum of the current center.  Windows are aligned to kWalkW
@@ -709,7 +709,7 @@ __global__ __launch_bounds__(kAT) void k_wwalk(const float *__restrict__ P,
     const int d = R.d;
     const int s = fix_shift_of(rs->absmax_bits);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = walk_lanes(d), ppw = 64 / g, sub = lane / g, j0 = lane % g;
+    const int ppw = R.wpp, g = 64 / ppw, sub = lane / g, j0 = lane % g;
     const int ja = j0, jc = j0 + g;
     const int64_t a = (int64_t)itm.first + ((int64_t)wave * ppw + sub) * kWalkW;
     const int64_t b = min(R.n, a + kWalkW);
@@ -834,7 +834,7 @@ __global__ __launch_bounds__(kAT) void k_wfin(const float *__restrict__ P,
     double mx = 0.0;
     const bool walked = d <= kWalkD;
     long long *gs = gsum + R.sum_off;
-    if (walked) {
+    if (walked && R.kcu == kWalkCenters) {
         // one center per lane: the counts are read (and cleared) 64 at a
         // time; the centers that crossed a walk window are finished one
         // after the other by the whole wavefront
@@ -864,11 +864,28 @@ __global__ __launch_bounds__(kAT) void k_wfin(const float *__restrict__ P,
             }
         }
     }
-    for (int c = itm.first + wave; !walked && c < c1; c += kAT / 64) {
+    for (int c = itm.first + wave; R.kcu != kWalkCenters && c < c1; c += kAT / 64) {
         const int32_t n_c = counts[c];
         const int32_t st = starts[c];
         double mv2 = 0.0;
-        if (n_c > 0) {
+        if (walked) {
+            // one wavefront per center; only centers that crossed a walk
+            // window are left to finish
+            if (n_c > 0 && st / kWalkW != (st + n_c - 1) / kWalkW) {
+                double dv2 = 0.0;
+                for (int j = lane; j < d; j += 64) {
+                    const long long a = gs[(int64_t)c * d + j];
+                    gs[(int64_t)c * d + j] = 0;
+                    const float old = Cr[(int64_t)c * d + j];
+                    const double nv = ldexp((double)a, -s) / (double)n_c;
+                    const double dv = nv - (double)old;
+                    dv2 = dv2 + dv * dv;
+                    Cr[(int64_t)c * d + j] = (float)nv;
+                }
+                for (int o = 32; o > 0; o >>= 1) dv2 = dv2 + __shfl_xor(dv2, o, 64);
+                mv2 = dv2;
+            }
+        } else if (n_c > 0) {
             for (int jb = 0; jb < d; jb += 2 * dg) {
                 const int ja = jb + j0, jc = jb + j0 + dg;  // this lane's two attributes
                 long long a0 = 0, a1 = 0;

@@ -293,9 +293,10 @@ def test_lloyd_k1_and_k_equals_n(km, oracle):
     shadow_steps(km, oracle, S[:50], S[:50], steps=1)
 
 
-def run_batch(km, runs_np, ks, max_iter, tol, form=0, precision=0):
-    """Many runs in one call; returns per-run centers, labels, iters, sse."""
-    xs, specs, x_off, c_off, l_off = [], [], 0, 0, 0
+def run_batch(km, runs_np, ks, max_iter, tol, form=0, precision=0, pad=0):
+    """Many runs in one call (the points start `pad` floats into the buffer);
+    returns per-run centers, labels, iters, sse."""
+    xs, specs, x_off, c_off, l_off = [np.zeros(pad, np.float32)], [], pad, 0, 0
     for X, k in zip(runs_np, ks):
         n, d = X.shape
         specs.append((x_off, n, c_off, l_off, d, k))
@@ -506,6 +507,36 @@ def test_ragged_large_k_runs(km, oracle):
     # shadow step on the largest run at full k
     X, k = runs[2], ks[2]
     assert k * X.shape[1] > 4096
+    shadow_steps(km, oracle, X, X[:k], steps=2)
+
+
+@pytest.mark.parametrize("d", [8, 16])
+def test_wide_narrow_rows_split_and_float32(km, oracle, d):
+    """Runs of 8 or 16 attributes whose centers stream in chunks (k d > 4096,
+    k up to 1500, not a multiple of 16): with 16-byte aligned rows the first
+    distance pass runs on split bfloat16 matrix cores, with rows off that
+    alignment on float32 ones.  Both give the same results bit for bit, every
+    final label is the oracle's nearest center of the returned centers, and
+    single moves of the largest run match the oracle's moves."""
+    rng = np.random.default_rng(40 + d)
+    runs, ks = [], []
+    for j, n in enumerate([5000, 12000, 40000, 3001]):
+        X, _ = synth.gaussian_blobs(n, d, int(rng.integers(4, 33)), seed=500 + 10 * d + j,
+                                    sigma=(0.2, 1.5))
+        runs.append(oracle.scale(X)[0])
+        ks.append(int(min(-(-n // 4), 1500)) - 3 * j)
+    assert all(k * d > 4096 for k in ks)
+    out_a, it_a, sse_a = run_batch(km, runs, ks, 4, 0.0)
+    out_m, it_m, sse_m = run_batch(km, runs, ks, 4, 0.0, pad=1)
+    assert np.array_equal(it_a, it_m) and np.array_equal(sse_a, sse_m)
+    for r, (X, k) in enumerate(zip(runs, ks)):
+        assert np.array_equal(out_a[r][0], out_m[r][0]), r
+        assert np.array_equal(out_a[r][1], out_m[r][1]), r
+        lab_ref, sse_ref, _, _ = oracle.assign(X.astype(np.float64), out_a[r][0])
+        assert np.array_equal(out_a[r][1], lab_ref), r
+        assert abs(sse_a[r] - sse_ref) <= TOL * sse_ref, r
+        assert it_a[r] == 4
+    X, k = runs[1], ks[1]
     shadow_steps(km, oracle, X, X[:k], steps=2)
 
 
